@@ -1,0 +1,229 @@
+/*
+ * lsd.h -- C ABI of the MI355X (gfx950) batched-verification library for
+ * Langevin Speculative Dynamics (LSD).
+ *
+ * Paper: A. Kosmala, S. Guennemann, M. Gao, B. Wood, "Speculative Sampling
+ * For Faster Molecular Dynamics", arXiv 2606.02455.
+ *
+ * What the library computes (one GPU, R independent replicas batched):
+ *   - lsd_draft_steps     : the draft_step procedure of Alg. 2, K times in a
+ *                           row: A half step, draft forces, the (BOB)
+ *                           Gaussian draw of Eq. bob, A half step (Eq. aboba).
+ *   - lsd_verify_window   : verify_step of Alg. 2 for all K drafted frames in
+ *                           ONE launch: target forces at every midpoint, the
+ *                           target mean of Eq. bob, and the log density ratio
+ *                           of Eq. reflectionVerify reduced in binary64.
+ *   - lsd_accept_rollback : accept/reject of Eq. reflectionVerify with
+ *                           u ~ U(0,1], first rejection of the window (Alg. 1),
+ *                           reflection of the rejected momentum, map g of
+ *                           Thm. 1, and commit of the kept prefix; everything
+ *                           after the first rejection is discarded (rollback).
+ *   In LSD_MODE_PLAIN the same kernels run plain target Langevin (ABOBA with
+ *   target forces): verify is a no-op and every drafted step is committed.
+ *
+ * Conventions
+ *   - All array arguments are DEVICE pointers unless marked "host".  Device
+ *     memory is owned by the caller (e.g. PyTorch tensors); after
+ *     lsd_init_system the library allocates no device memory: its scratch
+ *     lives in the caller's workspace of lsd_workspace_size() bytes.
+ *   - Positions, momenta, forces: binary32, structure-of-arrays [3][N]
+ *     (x of all atoms, then y, then z).  Atoms of replica r are the index
+ *     range [atom_offsets[r], atom_offsets[r+1]).
+ *   - Cubic periodic boxes; positions are kept wrapped in [0, L_r) with
+ *     int32 image counters.  Box edges must be binary32-representable and
+ *     larger than (target cutoff + skin).
+ *   - Units: force_unit converts force*time to momentum and energy to
+ *     mass*length^2/time^2 (1.0 in Lennard-Jones reduced units;
+ *     9.648533212331e-3 for eV, Angstrom, amu, fs).
+ *   - Random numbers: Philox4x32-10 keyed by seed and counter (local atom
+ *     index, simulation step n, replica, tag).  Step n (the step being
+ *     produced) keys both the noise xi of Eq. aboba and the uniform u of
+ *     Eq. reflectionVerify, so a window of any length K commits the same
+ *     trajectory.  Tests may replace the stream by replay arrays.
+ *   - Every call is asynchronous on the given stream (a hipStream_t; NULL is
+ *     the default stream) unless it says it synchronises.
+ *   - Errors: every call returns an lsd_status; nothing is thrown across the
+ *     ABI.  lsd_last_error() describes the last failure of the calling
+ *     thread.  Device-side capacity overflows are latched in a status word
+ *     read by lsd_get_status().
+ */
+#ifndef LSD_H
+#define LSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define LSD_API __attribute__((visibility("default")))
+#else
+#define LSD_API
+#endif
+
+typedef struct lsd_system lsd_system; /* opaque, host-side handle */
+typedef void *lsd_stream;             /* hipStream_t */
+
+typedef enum {
+  LSD_OK = 0,
+  LSD_ERR_INVALID_ARG = -1, /* bad size, pointer or parameter */
+  LSD_ERR_BAD_STATE = -2,   /* calls out of order (draft -> verify -> accept) */
+  LSD_ERR_HIP = -3,         /* a HIP runtime call failed */
+  LSD_ERR_CAPACITY = -4,    /* workspace too small / neighbour list overflow */
+  LSD_ERR_UNSUPPORTED = -5  /* valid request this build does not implement */
+} lsd_status;
+
+typedef enum { LSD_MODE_LSD = 0, LSD_MODE_PLAIN = 1 } lsd_mode;
+
+typedef enum {
+  LSD_POT_LJ = 1,       /* truncated, energy-shifted Lennard-Jones */
+  LSD_POT_HARMONIC = 2  /* tether U = k/2 |q - anchor|^2 (minimum image) */
+} lsd_pot_kind;
+
+/* A potential: the target force field of verify_step or the draft force
+ * field of draft_step (Alg. 2).  Forces are -dU/dq (Sec. 2.1). */
+typedef struct {
+  int32_t kind;              /* lsd_pot_kind */
+  double cutoff;             /* LJ cutoff r_c (0 for the tether) */
+  double epsilon, sigma;     /* LJ parameters */
+  double k_spring;           /* tether stiffness */
+  const float *anchor;       /* tether anchors, device [3][N] (kept by pointer) */
+  const float *force_offset; /* optional constant force field added to the
+                                forces, device [3][N] or NULL (test drafts) */
+} lsd_potential;
+
+typedef struct {
+  int32_t n_atoms;             /* N, all replicas */
+  int32_t n_replicas;          /* R >= 1 */
+  const int32_t *atom_offsets; /* host [R+1], offsets[0] = 0, offsets[R] = N */
+  const double *box;           /* host [R] cubic box edges (binary32 values) */
+  const int32_t *species;      /* host [N] species index, or NULL for all 0 */
+  const double *species_mass;  /* host [n_species] masses, > 0 */
+  int32_t n_species;           /* 1 .. 8 */
+  double dt, gamma, kT;        /* time step, friction (> 0), k_B T (> 0) */
+  double force_unit;           /* see Conventions; > 0 */
+  double skin;                 /* Verlet skin added to both cutoffs, > 0 */
+  int32_t k_max;               /* largest window, 1 .. 64 */
+  int32_t mode;                /* lsd_mode */
+  uint64_t seed;               /* Philox key */
+  lsd_potential target;        /* verify_step force field */
+  lsd_potential draft;         /* draft_step force field (ignored in PLAIN) */
+  int32_t max_neighbors_target;/* neighbour-list width; 0 = automatic */
+  int32_t max_neighbors_draft; /* 0 = automatic */
+} lsd_config;
+
+typedef struct {
+  float *q;              /* committed positions [3][N], in/out */
+  float *p;              /* committed momenta [3][N], in/out */
+  int32_t *img;          /* committed image counters [3][N], in/out */
+  int64_t *step;         /* committed step per replica [R], in/out */
+  void *workspace;       /* lsd_workspace_size() bytes, 256-byte aligned */
+  size_t workspace_bytes;
+  double *log_ratio;     /* out [R][k_max]: log N(p~;<p>,S)/N(p~;<p~>,S) */
+  double *energy;        /* out [R][k_max]: target potential energy per frame */
+  uint8_t *accepted;     /* out [R][k_max]: decision of every verified frame,
+                            1 accepted, 0 rejected; 2 not verified (frames
+                            from K_eff on, and every frame in PLAIN mode).
+                            Only frames 1..n_committed are committed. */
+  int32_t *n_committed;  /* out [R]: steps committed by the last window */
+  const double *replay_u;  /* optional [R][k_max] uniforms in (0,1] for the
+                              frames of the next window; NULL = Philox */
+  const double *replay_xi; /* optional [k_max][N][3] normals, frame-major,
+                              atom-major within a frame; NULL = Philox */
+} lsd_buffers;
+
+/* Workspace bytes needed for cfg (host only; no GPU access). */
+LSD_API lsd_status lsd_workspace_size(const lsd_config *cfg, size_t *bytes);
+
+/* Validates cfg, lays out the workspace, uploads the static tables (species,
+ * replicas, tiles, cell grids) and returns a handle.  Synchronises `stream`
+ * once.  The buffers struct is copied; its pointers must stay valid until
+ * lsd_destroy.  Errors: INVALID_ARG (gamma, kT, dt, masses or skin <= 0,
+ * k_max outside 1..64, box edge not binary32 or <= cutoff + skin, more than
+ * 2^27 atoms), CAPACITY (workspace too small), HIP. */
+LSD_API lsd_status lsd_init_system(const lsd_config *cfg, const lsd_buffers *buf,
+                           lsd_stream stream, lsd_system **out);
+
+/* draft_step of Alg. 2, K times (1 <= K <= k_max), from the committed
+ * state: builds the cell and neighbour lists at the first midpoint, then for
+ * each k: draft forces at the midpoint, p~_k = <p~_k> + Sigma^{1/2} xi (Eq.
+ * bob, xi keyed by step s + k), position half steps.  Frames whose atoms
+ * moved more than skin/2 from the list positions are marked invalid and end
+ * the window early (K_eff < K).  Needs state READY or COMMITTED; leaves
+ * DRAFTED.  In PLAIN mode the target force field steps the system. */
+LSD_API lsd_status lsd_draft_steps(lsd_system *sys, int32_t K, lsd_stream stream);
+
+/* Declares that the caller has written K frames into the window arrays of
+ * lsd_window_layout (midpoints, draft momenta 0..K, draft forces) instead of
+ * drafting them; builds the neighbour lists at frame 0 and the validity of
+ * every frame.  Leaves DRAFTED.  For external drafts and tests. */
+LSD_API lsd_status lsd_mark_drafted(lsd_system *sys, int32_t K, lsd_stream stream);
+
+/* verify_step of Alg. 2 for all valid drafted frames of all replicas in one
+ * kernel launch: target energy and forces, <p> of Eq. bob, and the binary64
+ * sums S1 = delta.z, S2 = delta.delta with z = Sigma^{-1/2}(p~ - <p~>) and
+ * delta = Sigma^{-1/2}(<p~> - <p>) (Eq. reflectionVerify).  DRAFTED ->
+ * VERIFIED.  No-op in PLAIN mode. */
+LSD_API lsd_status lsd_verify_window(lsd_system *sys, lsd_stream stream);
+
+/* Decision and commit: log r_k = -S1 - S2/2, accept frame k iff
+ * log u_{s+k} <= log r_k; j = first rejected frame (else K_eff).  Frames
+ * 1..j are committed; a rejected frame j takes the reflected momentum
+ * <p> + Sigma^{1/2}(I - 2 delta delta^T / delta^T delta) z and map g.  Fills
+ * log_ratio, energy, accepted, n_committed and advances step[r] by j.
+ * If n_host is not NULL, synchronises and copies n_committed to host [R].
+ * VERIFIED (LSD) or DRAFTED (PLAIN) -> COMMITTED. */
+LSD_API lsd_status lsd_accept_rollback(lsd_system *sys, int32_t *n_host,
+                               lsd_stream stream);
+
+/* Enqueues n_windows x (draft K, verify, accept) without synchronising. */
+LSD_API lsd_status lsd_run_windows(lsd_system *sys, int32_t n_windows, int32_t K,
+                           lsd_stream stream);
+
+/* Byte offsets into the workspace of the window and list arrays (host). */
+typedef struct {
+  size_t q_mid;      /* float4 [k_max][N]: x, y, z, packed image deltas */
+  size_t p_draft;    /* float [k_max+1][3][N]: committed p, then p~_1..p~_K */
+  size_t f_draft;    /* float [k_max][3][N] */
+  size_t f_target;   /* float [k_max][3][N] */
+  size_t frame_invalid; /* int32 [R][k_max] */
+  size_t nbr_target; /* uint32 [max_neighbors_target][N]: j << 5 | image code */
+  size_t cnt_target; /* int32 [N] */
+  size_t nbr_draft;  /* uint32 [max_neighbors_draft][N] */
+  size_t cnt_draft;  /* int32 [N] */
+  int32_t max_neighbors_target, max_neighbors_draft;
+  int32_t n_atoms, k_max;
+} lsd_window_layout;
+LSD_API lsd_status lsd_get_window_layout(const lsd_system *sys, lsd_window_layout *out);
+
+/* Synchronises `stream` and returns the device status word: bit 0 target
+ * list overflow, bit 1 draft list overflow, bit 2 cell overflow. */
+LSD_API lsd_status lsd_get_status(lsd_system *sys, int32_t *flags, lsd_stream stream);
+
+/* Kernel timing of the verification launch with HIP events on `stream`.
+ * enable != 0 starts recording; lsd_get_verify_timing synchronises and
+ * returns the summed milliseconds and launch count since enabling. */
+LSD_API lsd_status lsd_set_verify_timing(lsd_system *sys, int32_t enable);
+LSD_API lsd_status lsd_get_verify_timing(lsd_system *sys, double *total_ms,
+                                 int64_t *launches);
+
+/* The library's random stream, for parity checks: out[n][3] normals of step
+ * `step` (device buffer), and out[count] uniforms of steps step0+1 ..
+ * step0+count (device buffer). */
+LSD_API lsd_status lsd_rng_normals(uint64_t seed, int32_t replica, int64_t step,
+                           int32_t n, double *out, lsd_stream stream);
+LSD_API lsd_status lsd_rng_uniforms(uint64_t seed, int32_t replica, int64_t step0,
+                            int32_t count, double *out, lsd_stream stream);
+
+/* Releases the handle and its HIP events (no device memory is freed). */
+LSD_API lsd_status lsd_destroy(lsd_system *sys);
+
+/* Thread-local text of the last error ("" if none). */
+LSD_API const char *lsd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSD_H */

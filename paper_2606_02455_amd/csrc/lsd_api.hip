@@ -1,0 +1,595 @@
+// lsd_api.hip -- host implementation of the C ABI in include/lsd.h.
+//
+// Owns no device memory: every device array lives in the caller's workspace
+// (laid out here) or in the caller's state/output buffers.  Enforces the
+// call order draft -> verify -> accept of one synchronous window (Alg. 1
+// with lookahead K, per-step maps of Alg. 2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lsd.h"
+#include "lsd_launch.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+lsd_status fail(lsd_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(LSD_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LSD_TRY(expr)                 \
+  do {                                \
+    lsd_status s_ = (expr);           \
+    if (s_ != LSD_OK) return s_;      \
+  } while (0)
+
+enum State { ST_READY = 0, ST_DRAFTED = 1, ST_VERIFIED = 2, ST_COMMITTED = 3 };
+
+constexpr size_t kAlign = 256;
+constexpr int kTimingRing = 512;
+
+struct Layout {
+  size_t total = 0;
+  // static tables
+  size_t atom_rep, species, rep_off, box, rep_nc, rep_cell_off;
+  size_t tile_start, tile_count, tile_rep, rep_tile_off;
+  // cells and lists
+  size_t cell_count, cell_start, cell_cursor, cell_atoms, atom_cell;
+  size_t nbr_t, cnt_t, nbr_d, cnt_d;
+  // window
+  size_t qmid, p, fd, ft, invalid, partial, commit_frame, reflected, coef, status;
+  int mt = 0, md = 0, n_cells = 0, n_tiles = 0;
+  double rl_t = 0, rl_d = 0, band_L = 0;
+  std::vector<int> atom_rep_h, rep_nc_h, rep_cell_off_h, tile_start_h, tile_count_h, tile_rep_h,
+      rep_tile_off_h;
+};
+
+size_t bump(size_t* off, size_t bytes) {
+  size_t o = (*off + kAlign - 1) / kAlign * kAlign;
+  *off = o + bytes;
+  return o;
+}
+
+bool is_binary32(double v) { return (double)(float)v == v; }
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+double pot_reach(const lsd_potential& P) { return P.kind == LSD_POT_LJ ? P.cutoff : 0.0; }
+
+lsd_status check_potential(const lsd_potential& P, const char* what) {
+  if (P.kind == LSD_POT_LJ) {
+    if (!(P.cutoff > 0.0) || !(P.sigma > 0.0) || !std::isfinite(P.epsilon))
+      return fail(LSD_ERR_INVALID_ARG, "%s: Lennard-Jones needs cutoff > 0, sigma > 0", what);
+  } else if (P.kind == LSD_POT_HARMONIC) {
+    if (!P.anchor || !(P.k_spring >= 0.0))
+      return fail(LSD_ERR_INVALID_ARG, "%s: tether needs anchors and k >= 0", what);
+  } else {
+    return fail(LSD_ERR_UNSUPPORTED, "%s: potential kind %d not supported", what, P.kind);
+  }
+  return LSD_OK;
+}
+
+// Validates the configuration and computes the workspace layout.
+lsd_status plan(const lsd_config* c, Layout* L) {
+  if (!c) return fail(LSD_ERR_INVALID_ARG, "null config");
+  const int N = c->n_atoms, R = c->n_replicas;
+  if (N < 1 || N > (1 << 27)) return fail(LSD_ERR_INVALID_ARG, "n_atoms %d outside 1..2^27", N);
+  if (R < 1 || R > (1 << 23)) return fail(LSD_ERR_INVALID_ARG, "n_replicas %d invalid", R);
+  if (!c->atom_offsets || !c->box || !c->species_mass)
+    return fail(LSD_ERR_INVALID_ARG, "atom_offsets, box and species_mass are required");
+  if (c->atom_offsets[0] != 0 || c->atom_offsets[R] != N)
+    return fail(LSD_ERR_INVALID_ARG, "atom_offsets must start at 0 and end at n_atoms");
+  if (c->n_species < 1 || c->n_species > LSD_MAX_SPECIES)
+    return fail(LSD_ERR_INVALID_ARG, "n_species must be 1..%d", LSD_MAX_SPECIES);
+  for (int s = 0; s < c->n_species; ++s)
+    if (!(c->species_mass[s] > 0.0)) return fail(LSD_ERR_INVALID_ARG, "mass of species %d <= 0", s);
+  if (c->species)
+    for (int i = 0; i < N; ++i)
+      if (c->species[i] < 0 || c->species[i] >= c->n_species)
+        return fail(LSD_ERR_INVALID_ARG, "species[%d] out of range", i);
+  if (!(c->dt > 0.0) || !(c->gamma > 0.0) || !(c->kT > 0.0) || !(c->force_unit > 0.0))
+    return fail(LSD_ERR_INVALID_ARG, "dt, gamma, kT and force_unit must be > 0");
+  if (!(c->skin > 0.0)) return fail(LSD_ERR_INVALID_ARG, "skin must be > 0");
+  if (c->k_max < 1 || c->k_max > LSD_MAX_K)
+    return fail(LSD_ERR_INVALID_ARG, "k_max %d outside 1..%d", c->k_max, LSD_MAX_K);
+  if (c->mode != LSD_MODE_LSD && c->mode != LSD_MODE_PLAIN)
+    return fail(LSD_ERR_INVALID_ARG, "mode %d invalid", c->mode);
+  LSD_TRY(check_potential(c->target, "target"));
+  if (c->mode == LSD_MODE_LSD) LSD_TRY(check_potential(c->draft, "draft"));
+
+  L->rl_t = pot_reach(c->target) + c->skin;
+  L->rl_d = (c->mode == LSD_MODE_LSD ? pot_reach(c->draft) : 0.0) + c->skin;
+  const double r_cell = std::max(L->rl_t, L->rl_d);
+
+  L->atom_rep_h.resize(N);
+  L->rep_nc_h.resize(R);
+  L->rep_cell_off_h.resize(R);
+  L->rep_tile_off_h.assign(R + 1, 0);
+  L->tile_start_h.clear();
+  L->tile_count_h.clear();
+  L->tile_rep_h.clear();
+  double rho_max = 0.0;
+  long long cells = 0;
+  L->band_L = 0.0;
+  for (int r = 0; r < R; ++r) {
+    const int a0 = c->atom_offsets[r], a1 = c->atom_offsets[r + 1];
+    if (a1 <= a0) return fail(LSD_ERR_INVALID_ARG, "replica %d has no atoms", r);
+    const double Lr = c->box[r];
+    if (!(Lr > 0.0) || !is_binary32(Lr))
+      return fail(LSD_ERR_INVALID_ARG, "box[%d] = %.17g must be > 0 and binary32", r, Lr);
+    if (!(Lr > r_cell))
+      return fail(LSD_ERR_INVALID_ARG, "box[%d] = %g must exceed cutoff + skin = %g", r, Lr, r_cell);
+    L->band_L = std::max(L->band_L, Lr);
+    const int n_r = a1 - a0;
+    rho_max = std::max(rho_max, n_r / (Lr * Lr * Lr));
+    int nc = (int)std::floor(Lr / (r_cell * (1.0 + 1e-6)));
+    int cap = std::max(1, (int)std::cbrt((double)n_r));
+    nc = std::min(nc, cap);
+    if (nc < 3) nc = 1;
+    L->rep_nc_h[r] = nc;
+    L->rep_cell_off_h[r] = (int)cells;
+    cells += (long long)nc * nc * nc;
+    for (int i = a0; i < a1; ++i) L->atom_rep_h[i] = r;
+    L->rep_tile_off_h[r] = (int)L->tile_start_h.size();
+    for (int t = a0; t < a1; t += LSD_TILE) {
+      L->tile_start_h.push_back(t);
+      L->tile_count_h.push_back(std::min(LSD_TILE, a1 - t));
+      L->tile_rep_h.push_back(r);
+    }
+  }
+  L->rep_tile_off_h[R] = (int)L->tile_start_h.size();
+  if (cells > (1ll << 30)) return fail(LSD_ERR_INVALID_ARG, "too many cells");
+  L->n_cells = (int)cells;
+  L->n_tiles = (int)L->tile_start_h.size();
+
+  auto auto_width = [&](double rl) {
+    const double expect = rho_max * 4.0 / 3.0 * M_PI * rl * rl * rl;
+    return round_up((int)std::ceil(1.3 * expect + 32.0), 32);
+  };
+  L->mt = c->max_neighbors_target > 0 ? c->max_neighbors_target : auto_width(L->rl_t);
+  L->md = c->max_neighbors_draft > 0 ? c->max_neighbors_draft : auto_width(L->rl_d);
+  if (L->mt > 640) return fail(LSD_ERR_CAPACITY, "target neighbour width %d > 640", L->mt);
+  if (L->md > 4096) return fail(LSD_ERR_CAPACITY, "draft neighbour width %d > 4096", L->md);
+
+  const size_t n = (size_t)N, K = (size_t)c->k_max, T = (size_t)L->n_tiles;
+  size_t off = 0;
+  L->atom_rep = bump(&off, n * 4);
+  L->species = bump(&off, n * 4);
+  L->rep_off = bump(&off, (R + 1) * 4);
+  L->box = bump(&off, R * 8);
+  L->rep_nc = bump(&off, R * 4);
+  L->rep_cell_off = bump(&off, R * 4);
+  L->tile_start = bump(&off, T * 4);
+  L->tile_count = bump(&off, T * 4);
+  L->tile_rep = bump(&off, T * 4);
+  L->rep_tile_off = bump(&off, (R + 1) * 4);
+  L->cell_count = bump(&off, (size_t)L->n_cells * 4);
+  L->cell_start = bump(&off, ((size_t)L->n_cells + 1) * 4);
+  L->cell_cursor = bump(&off, (size_t)L->n_cells * 4);
+  L->cell_atoms = bump(&off, n * 4);
+  L->atom_cell = bump(&off, n * 4);
+  L->nbr_t = bump(&off, (size_t)L->mt * n * 4);
+  L->cnt_t = bump(&off, n * 4);
+  L->nbr_d = bump(&off, (size_t)L->md * n * 4);
+  L->cnt_d = bump(&off, n * 4);
+  L->qmid = bump(&off, K * n * 16);
+  L->p = bump(&off, (K + 1) * 3 * n * 4);
+  L->fd = bump(&off, K * 3 * n * 4);
+  L->ft = bump(&off, K * 3 * n * 4);
+  L->invalid = bump(&off, (size_t)R * K * 4);
+  L->partial = bump(&off, K * T * 4 * 8);
+  L->commit_frame = bump(&off, R * 4);
+  L->reflected = bump(&off, R * 4);
+  L->coef = bump(&off, R * 8);
+  L->status = bump(&off, 4 * 4);
+  L->total = (off + kAlign - 1) / kAlign * kAlign;
+  return LSD_OK;
+}
+
+PotDev make_pot(const lsd_potential& P, const Layout& L) {
+  PotDev d;
+  memset(&d, 0, sizeof(d));
+  d.kind = P.kind;
+  d.offset = P.force_offset;
+  if (P.kind == LSD_POT_LJ) {
+    const double rc = P.cutoff, rc2 = rc * rc;
+    // bound on |r2_binary32 - r2_exact| near the cutoff for coordinates in
+    // [0, L): |d_binary32 - d| <= u (2 L + r_list) per component, u = 2^-23
+    const double u = std::ldexp(1.0, -23);
+    const double band =
+        4.0 * std::sqrt(3.0) * rc * u * (2.0 * L.band_L + L.rl_t + L.rl_d) + 10.0 * u * rc2;
+    d.rc2_d = rc2;
+    d.rc2 = (float)rc2;
+    d.rc2_lo = (float)(rc2 - band);
+    d.rc2_hi = (float)(rc2 + band);
+    d.eps4 = (float)(4.0 * P.epsilon);
+    d.eps24 = (float)(24.0 * P.epsilon);
+    d.sig2 = (float)(P.sigma * P.sigma);
+    const double src = P.sigma / rc;
+    const double src6 = src * src * src * src * src * src;
+    d.eshift = (float)(4.0 * P.epsilon * (src6 * src6 - src6));
+  } else if (P.kind == LSD_POT_HARMONIC) {
+    d.kspring = (float)P.k_spring;
+    d.anchor = P.anchor;
+  }
+  return d;
+}
+
+struct TimingRing {
+  hipEvent_t start[kTimingRing], stop[kTimingRing];
+  int head = 0, used = 0;
+  bool created = false;
+};
+
+}  // namespace
+
+struct lsd_system {
+  lsd_config cfg;
+  lsd_buffers buf;
+  Layout lay;
+  SysDev S;
+  ListDev Lst;
+  WinDev W;
+  TileDev T;
+  OutDev O;
+  PotDev Pt, Pd;
+  int state = ST_READY;
+  int fpb = 8;
+  bool timing = false;
+  TimingRing ring;
+  double t_sum = 0.0;
+  int64_t t_count = 0;
+};
+
+namespace {
+
+template <typename T>
+T* ws(const lsd_system* s, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(s->buf.workspace) + off);
+}
+
+lsd_status upload_ints(const std::vector<int>& v, int* dst, hipStream_t st) {
+  if (v.empty()) return LSD_OK;
+  HIP_TRY(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  return LSD_OK;
+}
+
+lsd_status timing_drain_one(lsd_system* s) {
+  TimingRing& R = s->ring;
+  HIP_TRY(hipEventSynchronize(R.stop[R.head]));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, R.start[R.head], R.stop[R.head]));
+  s->t_sum += ms;
+  s->t_count += 1;
+  R.head = (R.head + 1) % kTimingRing;
+  R.used -= 1;
+  return LSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lsd_last_error(void) { return g_err.c_str(); }
+
+lsd_status lsd_workspace_size(const lsd_config* cfg, size_t* bytes) {
+  if (!bytes) return fail(LSD_ERR_INVALID_ARG, "null bytes");
+  Layout L;
+  LSD_TRY(plan(cfg, &L));
+  *bytes = L.total;
+  return LSD_OK;
+}
+
+lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_stream stream,
+                           lsd_system** out) {
+  if (!out || !buf) return fail(LSD_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  Layout L;
+  LSD_TRY(plan(cfg, &L));
+  if (!buf->q || !buf->p || !buf->img || !buf->step || !buf->workspace || !buf->log_ratio ||
+      !buf->energy || !buf->accepted || !buf->n_committed)
+    return fail(LSD_ERR_INVALID_ARG, "all state, output and workspace pointers are required");
+  if (reinterpret_cast<uintptr_t>(buf->workspace) % kAlign)
+    return fail(LSD_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
+  if (buf->workspace_bytes < L.total)
+    return fail(LSD_ERR_CAPACITY, "workspace %zu bytes < required %zu", buf->workspace_bytes, L.total);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  lsd_system* s = new lsd_system();
+  s->cfg = *cfg;
+  s->cfg.atom_offsets = nullptr;  // host arrays are not kept
+  s->cfg.box = nullptr;
+  s->cfg.species = nullptr;
+  s->cfg.species_mass = nullptr;
+  s->buf = *buf;
+  s->lay = L;
+  const int N = cfg->n_atoms, R = cfg->n_replicas;
+
+  // --- static tables
+  std::vector<int> species_h(N, 0), rep_off_h(R + 1);
+  if (cfg->species)
+    for (int i = 0; i < N; ++i) species_h[i] = cfg->species[i];
+  for (int r = 0; r <= R; ++r) rep_off_h[r] = cfg->atom_offsets[r];
+  std::vector<double> box_h(cfg->box, cfg->box + R);
+  lsd_status st_ok = LSD_OK;
+  auto up = [&](const std::vector<int>& v, size_t off) {
+    if (st_ok == LSD_OK) st_ok = upload_ints(v, ws<int>(s, off), st);
+  };
+  up(L.atom_rep_h, L.atom_rep);
+  up(species_h, L.species);
+  up(rep_off_h, L.rep_off);
+  up(L.rep_nc_h, L.rep_nc);
+  up(L.rep_cell_off_h, L.rep_cell_off);
+  up(L.tile_start_h, L.tile_start);
+  up(L.tile_count_h, L.tile_count);
+  up(L.tile_rep_h, L.tile_rep);
+  up(L.rep_tile_off_h, L.rep_tile_off);
+  if (st_ok != LSD_OK) { delete s; return st_ok; }
+  hipError_t e = hipMemcpyAsync(ws<double>(s, L.box), box_h.data(), R * sizeof(double),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cell_count), 0, L.n_cells, st);
+  if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cell_cursor), 0, L.n_cells, st);
+  if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.status), 0, 4, st);
+  if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.invalid), 0, R * cfg->k_max, st);
+  if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_t), 0, N, st);
+  if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_d), 0, N, st);
+  if (e == hipSuccess) e = prepare_verify(L.mt);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(LSD_ERR_HIP, "init upload: %s", hipGetErrorString(e));
+  }
+
+  // --- device descriptors
+  SysDev& S = s->S;
+  memset(&S, 0, sizeof(S));
+  S.n = N;
+  S.R = R;
+  S.n_tiles = L.n_tiles;
+  S.kmax = cfg->k_max;
+  S.atom_rep = ws<int>(s, L.atom_rep);
+  S.species = cfg->n_species > 1 ? ws<int>(s, L.species) : nullptr;
+  S.rep_off = ws<int>(s, L.rep_off);
+  S.box = ws<double>(s, L.box);
+  S.a = std::exp(-cfg->gamma * cfg->dt);
+  S.c1fu = (1.0 + S.a) * (0.5 * cfg->dt) * cfg->force_unit;
+  for (int sp = 0; sp < LSD_MAX_SPECIES; ++sp) {
+    const double m = cfg->species_mass[sp < cfg->n_species ? sp : 0];
+    S.hdt_m[sp] = (0.5 * cfg->dt) / m;
+    S.sig[sp] = std::sqrt(m * cfg->kT * cfg->force_unit * (1.0 - std::exp(-2.0 * cfg->gamma * cfg->dt)));
+  }
+  const double hs = 0.5 * cfg->skin * (1.0 - 1e-4);
+  S.half_skin2 = (float)(hs * hs);
+  S.seed = cfg->seed;
+  S.replay_u = buf->replay_u;
+  S.replay_xi = buf->replay_xi;
+  S.step = buf->step;
+
+  ListDev& Ls = s->Lst;
+  memset(&Ls, 0, sizeof(Ls));
+  Ls.rep_nc = ws<int>(s, L.rep_nc);
+  Ls.rep_cell_off = ws<int>(s, L.rep_cell_off);
+  Ls.cell_count = ws<int>(s, L.cell_count);
+  Ls.cell_start = ws<int>(s, L.cell_start);
+  Ls.cell_cursor = ws<int>(s, L.cell_cursor);
+  Ls.cell_atoms = ws<int>(s, L.cell_atoms);
+  Ls.atom_cell = ws<int>(s, L.atom_cell);
+  Ls.n_cells = L.n_cells;
+  Ls.nbr_t = ws<uint32_t>(s, L.nbr_t);
+  Ls.cnt_t = ws<int>(s, L.cnt_t);
+  Ls.mt = L.mt;
+  Ls.nbr_d = ws<uint32_t>(s, L.nbr_d);
+  Ls.cnt_d = ws<int>(s, L.cnt_d);
+  Ls.md = L.md;
+  Ls.rl2_t = L.rl_t * L.rl_t;
+  Ls.rl2_d = L.rl_d * L.rl_d;
+  Ls.status = ws<int>(s, L.status);
+
+  WinDev& W = s->W;
+  memset(&W, 0, sizeof(W));
+  W.qmid = ws<float4>(s, L.qmid);
+  W.p = ws<float>(s, L.p);
+  W.fd = ws<float>(s, L.fd);
+  W.ft = ws<float>(s, L.ft);
+  W.invalid = ws<int>(s, L.invalid);
+  W.partial = ws<double>(s, L.partial);
+  W.commit_frame = ws<int>(s, L.commit_frame);
+  W.reflected = ws<int>(s, L.reflected);
+  W.coef = ws<double>(s, L.coef);
+  W.K = 0;
+
+  TileDev& T = s->T;
+  T.start = ws<int>(s, L.tile_start);
+  T.count = ws<int>(s, L.tile_count);
+  T.rep = ws<int>(s, L.tile_rep);
+  T.rep_tile_off = ws<int>(s, L.rep_tile_off);
+
+  OutDev& O = s->O;
+  O.log_ratio = buf->log_ratio;
+  O.energy = buf->energy;
+  O.accepted = buf->accepted;
+  O.n_committed = buf->n_committed;
+
+  s->Pt = make_pot(cfg->target, L);
+  s->Pd = cfg->mode == LSD_MODE_LSD ? make_pot(cfg->draft, L) : s->Pt;
+  s->state = ST_READY;
+  *out = s;
+  return LSD_OK;
+}
+
+lsd_status lsd_draft_steps(lsd_system* s, int32_t K, lsd_stream stream) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  if (s->state != ST_READY && s->state != ST_COMMITTED)
+    return fail(LSD_ERR_BAD_STATE, "draft_steps needs a committed state (state %d)", s->state);
+  if (K < 1 || K > s->cfg.k_max) return fail(LSD_ERR_INVALID_ARG, "K = %d outside 1..k_max", K);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  s->W.K = K;
+  const bool plain = s->cfg.mode == LSD_MODE_PLAIN;
+  HIP_TRY(launch_window_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, st));
+  HIP_TRY(launch_build_lists(s->S, s->Lst, s->W, false, st));
+  for (int k = 0; k < K; ++k)
+    HIP_TRY(launch_draft(s->S, s->Lst, s->W, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st));
+  s->state = ST_DRAFTED;
+  return LSD_OK;
+}
+
+lsd_status lsd_mark_drafted(lsd_system* s, int32_t K, lsd_stream stream) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  if (s->state != ST_READY && s->state != ST_COMMITTED)
+    return fail(LSD_ERR_BAD_STATE, "mark_drafted needs a committed state (state %d)", s->state);
+  if (K < 1 || K > s->cfg.k_max) return fail(LSD_ERR_INVALID_ARG, "K = %d outside 1..k_max", K);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  s->W.K = K;
+  HIP_TRY(launch_fill_int(s->W.invalid, 0, s->S.R * s->S.kmax, st));
+  HIP_TRY(launch_build_lists(s->S, s->Lst, s->W, true, st));
+  HIP_TRY(launch_frame_validity(s->S, s->W, st));
+  s->state = ST_DRAFTED;
+  return LSD_OK;
+}
+
+lsd_status lsd_verify_window(lsd_system* s, lsd_stream stream) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  if (s->state != ST_DRAFTED) return fail(LSD_ERR_BAD_STATE, "verify_window needs a drafted window");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (s->cfg.mode == LSD_MODE_LSD) {
+    TimingRing& R = s->ring;
+    int slot = -1;
+    if (s->timing) {
+      if (R.used == kTimingRing) LSD_TRY(timing_drain_one(s));
+      slot = (R.head + R.used) % kTimingRing;
+      HIP_TRY(hipEventRecord(R.start[slot], st));
+    }
+    HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, s->fpb, st));
+    if (s->timing) {
+      HIP_TRY(hipEventRecord(R.stop[slot], st));
+      R.used += 1;
+    }
+  }
+  s->state = ST_VERIFIED;
+  return LSD_OK;
+}
+
+lsd_status lsd_accept_rollback(lsd_system* s, int32_t* n_host, lsd_stream stream) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  const bool plain = s->cfg.mode == LSD_MODE_PLAIN;
+  if (!(s->state == ST_VERIFIED || (plain && s->state == ST_DRAFTED)))
+    return fail(LSD_ERR_BAD_STATE, "accept_rollback needs a verified window");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_decide(s->S, s->W, s->T, s->O, plain ? 1 : 0, st));
+  HIP_TRY(launch_commit(s->S, s->W, s->buf.q, s->buf.p, s->buf.img, st));
+  s->state = ST_COMMITTED;
+  if (n_host) {
+    HIP_TRY(hipMemcpyAsync(n_host, s->buf.n_committed, sizeof(int32_t) * s->S.R,
+                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return LSD_OK;
+}
+
+lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stream stream) {
+  if (n_windows < 0) return fail(LSD_ERR_INVALID_ARG, "n_windows < 0");
+  for (int w = 0; w < n_windows; ++w) {
+    LSD_TRY(lsd_draft_steps(s, K, stream));
+    LSD_TRY(lsd_verify_window(s, stream));
+    LSD_TRY(lsd_accept_rollback(s, nullptr, stream));
+  }
+  return LSD_OK;
+}
+
+lsd_status lsd_get_window_layout(const lsd_system* s, lsd_window_layout* out) {
+  if (!s || !out) return fail(LSD_ERR_INVALID_ARG, "null argument");
+  out->q_mid = s->lay.qmid;
+  out->p_draft = s->lay.p;
+  out->f_draft = s->lay.fd;
+  out->f_target = s->lay.ft;
+  out->frame_invalid = s->lay.invalid;
+  out->nbr_target = s->lay.nbr_t;
+  out->cnt_target = s->lay.cnt_t;
+  out->nbr_draft = s->lay.nbr_d;
+  out->cnt_draft = s->lay.cnt_d;
+  out->max_neighbors_target = s->lay.mt;
+  out->max_neighbors_draft = s->lay.md;
+  out->n_atoms = s->S.n;
+  out->k_max = s->S.kmax;
+  return LSD_OK;
+}
+
+lsd_status lsd_get_status(lsd_system* s, int32_t* flags, lsd_stream stream) {
+  if (!s || !flags) return fail(LSD_ERR_INVALID_ARG, "null argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(flags, s->Lst.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return LSD_OK;
+}
+
+lsd_status lsd_set_verify_timing(lsd_system* s, int32_t enable) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  TimingRing& R = s->ring;
+  if (enable && !R.created) {
+    for (int i = 0; i < kTimingRing; ++i) {
+      HIP_TRY(hipEventCreate(&R.start[i]));
+      HIP_TRY(hipEventCreate(&R.stop[i]));
+    }
+    R.created = true;
+  }
+  while (R.used > 0) LSD_TRY(timing_drain_one(s));
+  s->timing = enable != 0;
+  s->t_sum = 0.0;
+  s->t_count = 0;
+  return LSD_OK;
+}
+
+lsd_status lsd_get_verify_timing(lsd_system* s, double* total_ms, int64_t* launches) {
+  if (!s || !total_ms || !launches) return fail(LSD_ERR_INVALID_ARG, "null argument");
+  while (s->ring.used > 0) LSD_TRY(timing_drain_one(s));
+  *total_ms = s->t_sum;
+  *launches = s->t_count;
+  return LSD_OK;
+}
+
+lsd_status lsd_rng_normals(uint64_t seed, int32_t replica, int64_t step, int32_t n, double* out,
+                           lsd_stream stream) {
+  if (!out || n < 0 || replica < 0) return fail(LSD_ERR_INVALID_ARG, "bad rng arguments");
+  HIP_TRY(launch_rng_normals(seed, replica, step, n, out, static_cast<hipStream_t>(stream)));
+  return LSD_OK;
+}
+
+lsd_status lsd_rng_uniforms(uint64_t seed, int32_t replica, int64_t step0, int32_t count,
+                            double* out, lsd_stream stream) {
+  if (!out || count < 0 || replica < 0) return fail(LSD_ERR_INVALID_ARG, "bad rng arguments");
+  HIP_TRY(launch_rng_uniforms(seed, replica, step0, count, out, static_cast<hipStream_t>(stream)));
+  return LSD_OK;
+}
+
+lsd_status lsd_destroy(lsd_system* s) {
+  if (!s) return LSD_OK;
+  if (s->ring.created) {
+    for (int i = 0; i < kTimingRing; ++i) {
+      (void)hipEventDestroy(s->ring.start[i]);
+      (void)hipEventDestroy(s->ring.stop[i]);
+    }
+  }
+  delete s;
+  return LSD_OK;
+}
+
+}  // extern "C"

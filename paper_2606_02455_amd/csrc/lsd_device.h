@@ -1,0 +1,241 @@
+// lsd_device.h -- device-side data structures and inline helpers shared by
+// the HIP kernels of the LSD library (gfx950, wave64).
+//
+// Everything here is written for CDNA4: 64-lane wavefronts, binary64 vector
+// ALU for the transport-map reductions, binary32 for the pair forces.  The
+// translation unit is compiled with -ffp-contract=off so that every product
+// and sum is rounded as written; fused multiply-adds appear only where the
+// code says fma().
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define LSD_MAX_SPECIES 8
+#define LSD_TILE 64           // atoms per verification tile (one wavefront)
+#define LSD_MAX_K 64
+#define LSD_POT_LJ 1
+#define LSD_POT_HARMONIC 2
+
+// status word bits
+#define LSD_STATUS_NBR_TARGET 1
+#define LSD_STATUS_NBR_DRAFT 2
+#define LSD_STATUS_CELL 4
+
+struct PotDev {
+  int kind;
+  float rc2;              // cutoff^2 in binary32
+  float rc2_lo, rc2_hi;   // binary32 band around rc2; inside it the binary64 test decides
+  double rc2_d;           // cutoff^2 in binary64
+  float eps4, eps24, sig2, eshift;  // 4 eps, 24 eps, sigma^2, 4 eps((s/rc)^12 - (s/rc)^6)
+  float kspring;
+  const float* anchor;    // [3][N]
+  const float* offset;    // [3][N] or null
+};
+
+struct SysDev {
+  int n, R, n_tiles, kmax;
+  const int* atom_rep;    // [N] replica of each atom
+  const int* species;     // [N] or null (single species)
+  const int* rep_off;     // [R+1]
+  const double* box;      // [R] box edge (binary32 value held in binary64)
+  double a;               // e^{-gamma dt}
+  double c1fu;            // (1 + a) dt / 2 * force_unit
+  double hdt_m[LSD_MAX_SPECIES];  // (dt / 2) / m_s
+  double sig[LSD_MAX_SPECIES];    // sqrt(m_s kT force_unit (1 - a^2))
+  float half_skin2;       // (skin / 2)^2, slightly reduced
+  uint64_t seed;
+  const double* replay_u;   // [R][kmax] or null
+  const double* replay_xi;  // [kmax][N][3] or null
+  int64_t* step;            // [R] committed step
+};
+
+struct ListDev {
+  const int* rep_nc;        // [R] cells per edge (1 = whole replica, 27 images)
+  const int* rep_cell_off;  // [R] first cell of the replica
+  int* cell_count;          // [C]
+  int* cell_start;          // [C + 1]
+  int* cell_cursor;         // [C]
+  int* cell_atoms;          // [N]
+  int* atom_cell;           // [N]
+  int n_cells;
+  uint32_t* nbr_t; int* cnt_t; int mt;   // target list, ELL [mt][N]
+  uint32_t* nbr_d; int* cnt_d; int md;   // draft list, ELL [md][N]
+  double rl2_t, rl2_d;      // list radii squared (binary64)
+  int* status;
+};
+
+struct WinDev {
+  float4* qmid;       // [kmax][N]
+  float* p;           // [kmax+1][3][N]
+  float* fd;          // [kmax][3][N]
+  float* ft;          // [kmax][3][N]
+  int* invalid;       // [R][kmax]
+  double* partial;    // [kmax][n_tiles][4]: S1, S2, E, unused
+  int* commit_frame;  // [R]
+  int* reflected;     // [R]
+  double* coef;       // [R] 2 S1 / S2 of the rejected frame
+  int K;              // frames in the current window
+};
+
+struct OutDev {
+  double* log_ratio;  // [R][kmax]
+  double* energy;     // [R][kmax]
+  uint8_t* accepted;  // [R][kmax]
+  int32_t* n_committed;  // [R]
+};
+
+struct TileDev {
+  const int* start;   // [T] first atom
+  const int* count;   // [T] atoms (<= 64)
+  const int* rep;     // [T] replica
+  const int* rep_tile_off;  // [R+1]
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the step-keyed stream
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+    uint32_t hi0 = __umulhi(m0, c[0]), lo0 = m0 * c[0];
+    uint32_t hi1 = __umulhi(m1, c[2]), lo1 = m1 * c[2];
+    uint32_t y0 = hi1 ^ c[1] ^ k0;
+    uint32_t y2 = hi0 ^ c[3] ^ k1;
+    c[0] = y0; c[1] = lo1; c[2] = y2; c[3] = lo0;
+  }
+}
+
+#define LSD_TAG_XI 1u
+#define LSD_TAG_U 2u
+
+__device__ __forceinline__ double u53(uint32_t lo, uint32_t hi) {
+  uint64_t x = ((uint64_t)hi << 32) | (uint64_t)lo;
+  return (double)((x >> 11) + 1ull) * (1.0 / 9007199254740992.0);
+}
+
+__device__ __forceinline__ void stream_block(uint64_t seed, uint32_t replica, uint64_t step,
+                                             uint32_t index, uint32_t tag, uint32_t block,
+                                             uint32_t w[4]) {
+  w[0] = index; w[1] = (uint32_t)step; w[2] = (uint32_t)(step >> 32);
+  w[3] = (replica << 8) | (tag << 4) | block;
+  philox4x32_10(w, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+__device__ __forceinline__ double stream_uniform(uint64_t seed, uint32_t replica, uint64_t step) {
+  uint32_t w[4];
+  stream_block(seed, replica, step, 0u, LSD_TAG_U, 0u, w);
+  return u53(w[0], w[1]);
+}
+
+// three normals of local atom `index` at step `step` (Box-Muller, binary64)
+__device__ __forceinline__ void stream_normals3(uint64_t seed, uint32_t replica, uint64_t step,
+                                                uint32_t index, double xi[3]) {
+  const double two_pi = 6.283185307179586476925286766559;
+  uint32_t w[4];
+  stream_block(seed, replica, step, index, LSD_TAG_XI, 0u, w);
+  double r = sqrt(-2.0 * log(u53(w[0], w[1])));
+  double s, c;
+  sincos(two_pi * u53(w[2], w[3]), &s, &c);
+  xi[0] = r * c;
+  xi[1] = r * s;
+  stream_block(seed, replica, step, index, LSD_TAG_XI, 1u, w);
+  r = sqrt(-2.0 * log(u53(w[0], w[1])));
+  xi[2] = r * cos(two_pi * u53(w[2], w[3]));
+}
+
+// ---------------------------------------------------------------------------
+// Integrator pieces (Eq. aboba, Eq. bob)
+// ---------------------------------------------------------------------------
+// (A): x + (dt/2)/m p evaluated in binary64, wrapped into [0, L) and rounded
+// to binary32; the applied image shift is added to *dimg.
+__device__ __forceinline__ float a_half(float x, float p, double hdt_m, double L, int* dimg) {
+  double v = (double)x + hdt_m * (double)p;
+  int s = 0;
+  if (v >= L || v < 0.0) {
+    double f = floor(v / L);
+    v = v - f * L;
+    s = (int)f;
+    if (v >= L) { v -= L; s += 1; }
+    if (v < 0.0) { v += L; s -= 1; }
+  }
+  float r = (float)v;
+  if ((double)r >= L) { r = 0.0f; s += 1; }
+  *dimg += s;
+  return r;
+}
+
+// Mean of the (BOB) Gaussian: e^{-gamma dt} p + (1 + e^{-gamma dt}) dt/2 F.
+__device__ __forceinline__ double bob_mean(double a, double c1fu, float p, float F) {
+  return fma(a, (double)p, c1fu * (double)F);
+}
+
+// image deltas (relative to the committed counters) packed in 3 x 10 bits
+__device__ __forceinline__ float pack_img(int dx, int dy, int dz) {
+  uint32_t v = ((uint32_t)dx & 0x3FFu) | (((uint32_t)dy & 0x3FFu) << 10) |
+               (((uint32_t)dz & 0x3FFu) << 20);
+  return __uint_as_float(v);
+}
+__device__ __forceinline__ void unpack_img(float w, int d[3]) {
+  int v = (int)__float_as_uint(w);
+  d[0] = (v << 22) >> 22;
+  d[1] = (v << 12) >> 22;
+  d[2] = (v << 2) >> 22;
+}
+
+// ---------------------------------------------------------------------------
+// Pair geometry and the Lennard-Jones pair force
+// ---------------------------------------------------------------------------
+// neighbour entry: j << 5 | image code, code = (nx+1) + 3 (ny+1) + 9 (nz+1)
+__device__ __forceinline__ int code_nx(int c) { return c % 3 - 1; }
+__device__ __forceinline__ int code_ny(int c) { return (c / 3) % 3 - 1; }
+__device__ __forceinline__ int code_nz(int c) { return c / 9 - 1; }
+
+// Exact binary64 cutoff predicate: d = (x_j - x_i) + n L, d2 = (dx dx + dy dy)
+// + dz dz, d2 < rc2.  Same expression and rounding as the reference
+// definition of the pair set.
+__device__ __forceinline__ bool inside_exact(float4 xi, float4 xj, int code, double L,
+                                             double rc2) {
+  double dx = ((double)xj.x - (double)xi.x) + (double)code_nx(code) * L;
+  double dy = ((double)xj.y - (double)xi.y) + (double)code_ny(code) * L;
+  double dz = ((double)xj.z - (double)xi.z) + (double)code_nz(code) * L;
+  double d2 = dx * dx + dy * dy + dz * dz;
+  return d2 < rc2;
+}
+
+// Lennard-Jones force on i from image (xj + shift); returns whether the pair
+// is inside the cutoff.  The binary32 distance decides unless it falls in the
+// rounding band around rc^2, where the exact binary64 predicate decides.
+__device__ __forceinline__ bool lj_pair(const PotDev& P, float4 xi, float4 xj, float sx, float sy,
+                                        float sz, int code, double L, float& fx, float& fy,
+                                        float& fz, float& e) {
+  float dx = (xj.x - xi.x) + sx;
+  float dy = (xj.y - xi.y) + sy;
+  float dz = (xj.z - xi.z) + sz;
+  float r2 = dx * dx + dy * dy + dz * dz;
+  if (r2 >= P.rc2_lo) {
+    if (r2 >= P.rc2_hi) return false;
+    if (!inside_exact(xi, xj, code, L, P.rc2_d)) return false;
+  }
+  float inv = __builtin_amdgcn_rcpf(r2);
+  float s2 = P.sig2 * inv;
+  float s6 = s2 * s2 * s2;
+  float fs = P.eps24 * inv * s6 * (2.0f * s6 - 1.0f);
+  fx -= fs * dx;
+  fy -= fs * dy;
+  fz -= fs * dz;
+  e += 0.5f * (P.eps4 * s6 * (s6 - 1.0f) - P.eshift);
+  return true;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}

@@ -1,0 +1,24 @@
+// lsd_launch.h -- host-side launchers of the LSD kernels (lsd_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "lsd_device.h"
+
+hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
+hipError_t launch_window_start(const SysDev& S, const ListDev& L, const WinDev& W, const float* q,
+                               const float* p, hipStream_t st);
+hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W, bool bin_frame0,
+                              hipStream_t st);
+hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P, int k,
+                        int use_target_list, hipStream_t st);
+hipError_t launch_frame_validity(const SysDev& S, const WinDev& W, hipStream_t st);
+hipError_t prepare_verify(int mt);
+hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
+                         const PotDev& P, int fpb, hipStream_t st);
+hipError_t launch_decide(const SysDev& S, const WinDev& W, const TileDev& T, const OutDev& O,
+                         int plain, hipStream_t st);
+hipError_t launch_commit(const SysDev& S, const WinDev& W, float* q, float* p, int* img,
+                         hipStream_t st);
+hipError_t launch_rng_normals(uint64_t seed, int replica, int64_t step, int n, double* out,
+                              hipStream_t st);
+hipError_t launch_rng_uniforms(uint64_t seed, int replica, int64_t step0, int count, double* out,
+                               hipStream_t st);

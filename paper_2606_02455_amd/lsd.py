@@ -1,0 +1,318 @@
+"""Thin ctypes binding of the LSD C ABI (include/lsd.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+kernels of liblsd.so.  PyTorch supplies device memory (all state, output and
+workspace buffers are torch tensors) and the stream.  There is no fallback:
+if liblsd.so is missing, ``load()`` raises.
+"""
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblsd.so")
+
+LSD_OK = 0
+MODE_LSD, MODE_PLAIN = 0, 1
+POT_LJ, POT_HARMONIC = 1, 2
+STATUS_NBR_TARGET, STATUS_NBR_DRAFT, STATUS_CELL = 1, 2, 4
+
+_LIB = None
+
+
+class LSDError(RuntimeError):
+    def __init__(self, status, where, message):
+        super().__init__(f"{where} failed with status {status}: {message}")
+        self.status = status
+
+
+class Potential(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("cutoff", C.c_double), ("epsilon", C.c_double),
+                ("sigma", C.c_double), ("k_spring", C.c_double), ("anchor", C.c_void_p),
+                ("force_offset", C.c_void_p)]
+
+
+class Config(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("n_replicas", C.c_int32),
+                ("atom_offsets", C.POINTER(C.c_int32)), ("box", C.POINTER(C.c_double)),
+                ("species", C.POINTER(C.c_int32)), ("species_mass", C.POINTER(C.c_double)),
+                ("n_species", C.c_int32), ("dt", C.c_double), ("gamma", C.c_double),
+                ("kT", C.c_double), ("force_unit", C.c_double), ("skin", C.c_double),
+                ("k_max", C.c_int32), ("mode", C.c_int32), ("seed", C.c_uint64),
+                ("target", Potential), ("draft", Potential),
+                ("max_neighbors_target", C.c_int32), ("max_neighbors_draft", C.c_int32)]
+
+
+class Buffers(C.Structure):
+    _fields_ = [("q", C.c_void_p), ("p", C.c_void_p), ("img", C.c_void_p), ("step", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("log_ratio", C.c_void_p), ("energy", C.c_void_p), ("accepted", C.c_void_p),
+                ("n_committed", C.c_void_p), ("replay_u", C.c_void_p), ("replay_xi", C.c_void_p)]
+
+
+class WindowLayout(C.Structure):
+    _fields_ = [("q_mid", C.c_size_t), ("p_draft", C.c_size_t), ("f_draft", C.c_size_t),
+                ("f_target", C.c_size_t), ("frame_invalid", C.c_size_t),
+                ("nbr_target", C.c_size_t), ("cnt_target", C.c_size_t),
+                ("nbr_draft", C.c_size_t), ("cnt_draft", C.c_size_t),
+                ("max_neighbors_target", C.c_int32), ("max_neighbors_draft", C.c_int32),
+                ("n_atoms", C.c_int32), ("k_max", C.c_int32)]
+
+
+EXPORTS = {
+    "lsd_workspace_size": ([C.POINTER(Config), C.POINTER(C.c_size_t)], C.c_int),
+    "lsd_init_system": ([C.POINTER(Config), C.POINTER(Buffers), C.c_void_p, C.POINTER(C.c_void_p)],
+                        C.c_int),
+    "lsd_draft_steps": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "lsd_mark_drafted": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int),
+    "lsd_verify_window": ([C.c_void_p, C.c_void_p], C.c_int),
+    "lsd_accept_rollback": ([C.c_void_p, C.POINTER(C.c_int32), C.c_void_p], C.c_int),
+    "lsd_run_windows": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p], C.c_int),
+    "lsd_get_window_layout": ([C.c_void_p, C.POINTER(WindowLayout)], C.c_int),
+    "lsd_get_status": ([C.c_void_p, C.POINTER(C.c_int32), C.c_void_p], C.c_int),
+    "lsd_set_verify_timing": ([C.c_void_p, C.c_int32], C.c_int),
+    "lsd_get_verify_timing": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
+    "lsd_rng_normals": ([C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p],
+                        C.c_int),
+    "lsd_rng_uniforms": ([C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p],
+                         C.c_int),
+    "lsd_destroy": ([C.c_void_p], C.c_int),
+    "lsd_last_error": ([], C.c_char_p),
+}
+
+
+def load():
+    """Load liblsd.so (raises ImportError if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python paper_2606_02455_amd/build.py")
+        lib = C.CDLL(LIB_PATH)
+        for name, (args, res) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = lib
+    return _LIB
+
+
+def _check(status, where):
+    if status != LSD_OK:
+        raise LSDError(status, where, load().lsd_last_error().decode())
+
+
+def _stream(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def rng_normals(seed, replica, step, n):
+    import torch
+    out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    _check(load().lsd_rng_normals(seed, replica, step, n, _ptr(out), _stream(torch)),
+           "lsd_rng_normals")
+    return out
+
+
+def rng_uniforms(seed, replica, step0, count):
+    import torch
+    out = torch.empty((count,), dtype=torch.float64, device="cuda")
+    _check(load().lsd_rng_uniforms(seed, replica, step0, count, _ptr(out), _stream(torch)),
+           "lsd_rng_uniforms")
+    return out
+
+
+class LSDSystem:
+    """One or many replicas with the committed state on the GPU.
+
+    target / draft: dicts ``{"kind": "lj", "rc": 2.5, "eps": 1, "sig": 1}`` or
+    ``{"kind": "harmonic", "k": 2.0, "anchor": array[N, 3]}``, each with an
+    optional ``"offset": array[N, 3]`` constant force field.
+    """
+
+    def __init__(self, workload, mode="lsd", k_max=None, target=None, draft=None, seed=None,
+                 skin=None, replay=False, max_neighbors=(0, 0)):
+        import torch
+        self.torch = torch
+        lib = load()
+        w = workload
+        self.w = w
+        self.N, self.R = w.n_atoms, w.n_replicas
+        self.k_max = int(k_max or w.K)
+        self.mode = MODE_LSD if mode == "lsd" else MODE_PLAIN
+        dev = "cuda"
+        self._keep = []
+        # host tables
+        self._offsets = np.ascontiguousarray(w.atom_offsets, dtype=np.int32)
+        self._box = np.ascontiguousarray(w.box, dtype=np.float64)
+        self._species = np.ascontiguousarray(w.species, dtype=np.int32)
+        self._masses = np.ascontiguousarray(w.species_mass, dtype=np.float64)
+        tgt = dict(target or w.target)
+        dft = dict(draft or w.draft)
+        cfg = Config()
+        cfg.n_atoms, cfg.n_replicas = self.N, self.R
+        cfg.atom_offsets = self._offsets.ctypes.data_as(C.POINTER(C.c_int32))
+        cfg.box = self._box.ctypes.data_as(C.POINTER(C.c_double))
+        cfg.species = self._species.ctypes.data_as(C.POINTER(C.c_int32))
+        cfg.species_mass = self._masses.ctypes.data_as(C.POINTER(C.c_double))
+        cfg.n_species = len(self._masses)
+        cfg.dt, cfg.gamma, cfg.kT, cfg.force_unit = w.dt, w.gamma, w.kT, w.force_unit
+        cfg.skin = float(skin if skin is not None else w.skin)
+        cfg.k_max = self.k_max
+        cfg.mode = self.mode
+        cfg.seed = int(seed if seed is not None else w.seed)
+        cfg.target = self._potential(tgt)
+        cfg.draft = self._potential(dft) if self.mode == MODE_LSD else Potential()
+        cfg.max_neighbors_target, cfg.max_neighbors_draft = max_neighbors
+        self.cfg = cfg
+        nbytes = C.c_size_t()
+        _check(lib.lsd_workspace_size(C.byref(cfg), C.byref(nbytes)), "lsd_workspace_size")
+        t = torch
+        self.q = t.tensor(w.positions.T.copy(), dtype=t.float32, device=dev).contiguous()
+        self.p = t.tensor(w.momenta.T.copy(), dtype=t.float32, device=dev).contiguous()
+        self.img = t.zeros((3, self.N), dtype=t.int32, device=dev)
+        self.step = t.zeros((self.R,), dtype=t.int64, device=dev)
+        self.workspace = t.zeros((nbytes.value,), dtype=t.uint8, device=dev)
+        self.log_ratio = t.zeros((self.R, self.k_max), dtype=t.float64, device=dev)
+        self.energy = t.zeros((self.R, self.k_max), dtype=t.float64, device=dev)
+        self.accepted = t.zeros((self.R, self.k_max), dtype=t.uint8, device=dev)
+        self.n_committed = t.zeros((self.R,), dtype=t.int32, device=dev)
+        self.replay_u = t.zeros((self.R, self.k_max), dtype=t.float64, device=dev) if replay else None
+        self.replay_xi = (t.zeros((self.k_max, self.N, 3), dtype=t.float64, device=dev)
+                          if replay else None)
+        buf = Buffers()
+        buf.q, buf.p, buf.img, buf.step = _ptr(self.q), _ptr(self.p), _ptr(self.img), _ptr(self.step)
+        buf.workspace, buf.workspace_bytes = _ptr(self.workspace), nbytes.value
+        buf.log_ratio, buf.energy = _ptr(self.log_ratio), _ptr(self.energy)
+        buf.accepted, buf.n_committed = _ptr(self.accepted), _ptr(self.n_committed)
+        buf.replay_u, buf.replay_xi = _ptr(self.replay_u), _ptr(self.replay_xi)
+        self.buf = buf
+        handle = C.c_void_p()
+        _check(lib.lsd_init_system(C.byref(cfg), C.byref(buf), _stream(t), C.byref(handle)),
+               "lsd_init_system")
+        self.h = handle
+        lay = WindowLayout()
+        _check(lib.lsd_get_window_layout(self.h, C.byref(lay)), "lsd_get_window_layout")
+        self.layout = lay
+
+    def _potential(self, d):
+        t = self.torch
+        P = Potential()
+        kind = d.get("kind", "lj")
+        if kind == "lj":
+            P.kind, P.cutoff = POT_LJ, float(d["rc"])
+            P.epsilon, P.sigma = float(d.get("eps", 1.0)), float(d.get("sig", 1.0))
+        elif kind == "harmonic":
+            P.kind, P.k_spring = POT_HARMONIC, float(d["k"])
+            anc = t.tensor(np.asarray(d["anchor"], dtype=np.float64).reshape(-1, 3).T.copy(),
+                           dtype=t.float32, device="cuda").contiguous()
+            self._keep.append(anc)
+            P.anchor = anc.data_ptr()
+        else:
+            raise ValueError(f"potential kind {kind!r} is not implemented by the library")
+        if d.get("offset") is not None:
+            off = t.tensor(np.asarray(d["offset"], dtype=np.float64).reshape(-1, 3).T.copy(),
+                           dtype=t.float32, device="cuda").contiguous()
+            self._keep.append(off)
+            P.force_offset = off.data_ptr()
+        return P
+
+    # --- the four calls of the method -----------------------------------------
+    def draft_steps(self, K):
+        _check(load().lsd_draft_steps(self.h, int(K), _stream(self.torch)), "lsd_draft_steps")
+
+    def verify_window(self):
+        _check(load().lsd_verify_window(self.h, _stream(self.torch)), "lsd_verify_window")
+
+    def accept_rollback(self, sync=False):
+        if sync:
+            n = (C.c_int32 * self.R)()
+            _check(load().lsd_accept_rollback(self.h, n, _stream(self.torch)),
+                   "lsd_accept_rollback")
+            return np.array(n[:], dtype=np.int32)
+        _check(load().lsd_accept_rollback(self.h, None, _stream(self.torch)), "lsd_accept_rollback")
+        return None
+
+    def run_windows(self, n_windows, K):
+        _check(load().lsd_run_windows(self.h, int(n_windows), int(K), _stream(self.torch)),
+               "lsd_run_windows")
+
+    def mark_drafted(self, K):
+        _check(load().lsd_mark_drafted(self.h, int(K), _stream(self.torch)), "lsd_mark_drafted")
+
+    # --- inspection -------------------------------------------------------------
+    def window(self) -> Dict[str, "object"]:
+        """Views into the workspace: q_mid [k_max, N, 4] (w = packed image
+        deltas), p_draft [k_max+1, 3, N], f_draft / f_target [k_max, 3, N],
+        frame_invalid [R, k_max]."""
+        t, L, N, K = self.torch, self.layout, self.N, self.k_max
+        ws = self.workspace
+
+        def view(off, count, dtype, shape):
+            nb = count * t.empty((), dtype=dtype).element_size()
+            return ws[off:off + nb].view(dtype).view(*shape)
+
+        return dict(
+            q_mid=view(L.q_mid, K * N * 4, t.float32, (K, N, 4)),
+            p_draft=view(L.p_draft, (K + 1) * 3 * N, t.float32, (K + 1, 3, N)),
+            f_draft=view(L.f_draft, K * 3 * N, t.float32, (K, 3, N)),
+            f_target=view(L.f_target, K * 3 * N, t.float32, (K, 3, N)),
+            frame_invalid=view(L.frame_invalid, self.R * K, t.int32, (self.R, K)),
+        )
+
+    def neighbor_lists(self, which="target"):
+        """(counts [N], entries [width, N] as int64 j << 5 | image code)."""
+        t, L, N = self.torch, self.layout, self.N
+        ws = self.workspace
+        if which == "target":
+            off, coff, m = L.nbr_target, L.cnt_target, L.max_neighbors_target
+        else:
+            off, coff, m = L.nbr_draft, L.cnt_draft, L.max_neighbors_draft
+        cnt = ws[coff:coff + 4 * N].view(t.int32).clone()
+        ent = ws[off:off + 4 * m * N].view(t.int32).view(m, N).clone()
+        return cnt, ent
+
+    def status(self):
+        f = C.c_int32()
+        _check(load().lsd_get_status(self.h, C.byref(f), _stream(self.torch)), "lsd_get_status")
+        return int(f.value)
+
+    def set_verify_timing(self, on=True):
+        _check(load().lsd_set_verify_timing(self.h, 1 if on else 0), "lsd_set_verify_timing")
+
+    def verify_timing(self):
+        ms, n = C.c_double(), C.c_int64()
+        _check(load().lsd_get_verify_timing(self.h, C.byref(ms), C.byref(n)),
+               "lsd_get_verify_timing")
+        return ms.value, n.value
+
+    def state(self):
+        self.torch.cuda.synchronize()
+        return dict(q=self.q.T.double().cpu().numpy(), p=self.p.T.double().cpu().numpy(),
+                    img=self.img.T.cpu().numpy(), step=self.step.cpu().numpy())
+
+    def set_state(self, q, p, img=None, step=None):
+        t = self.torch
+        self.q.copy_(t.tensor(np.asarray(q, dtype=np.float64).T, dtype=t.float32))
+        self.p.copy_(t.tensor(np.asarray(p, dtype=np.float64).T, dtype=t.float32))
+        if img is not None:
+            self.img.copy_(t.tensor(np.asarray(img).T, dtype=t.int32))
+        if step is not None:
+            self.step.copy_(t.tensor(np.asarray(step), dtype=t.int64))
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            load().lsd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

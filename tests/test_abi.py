@@ -1,0 +1,108 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/lsd.h declares, and rejects invalid configurations on the host
+(no device work is started by any call here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lsd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lsd_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2606_02455_amd import lsd
+    return lsd.load()
+
+
+def test_header_declares_the_four_calls():
+    names = _declared()
+    for n in ("lsd_init_system", "lsd_draft_steps", "lsd_verify_window", "lsd_accept_rollback"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2606_02455_amd import lsd
+    assert set(_declared()) == set(lsd.EXPORTS)
+
+
+def _cfg(lsd, w, **over):
+    cfg = lsd.Config()
+    keep = dict(off=np.ascontiguousarray(w.atom_offsets, np.int32),
+                box=np.ascontiguousarray(w.box, np.float64),
+                mass=np.ascontiguousarray(w.species_mass, np.float64))
+    cfg.n_atoms, cfg.n_replicas = w.n_atoms, w.n_replicas
+    cfg.atom_offsets = keep["off"].ctypes.data_as(C.POINTER(C.c_int32))
+    cfg.box = keep["box"].ctypes.data_as(C.POINTER(C.c_double))
+    cfg.species_mass = keep["mass"].ctypes.data_as(C.POINTER(C.c_double))
+    cfg.n_species = 1
+    cfg.dt, cfg.gamma, cfg.kT, cfg.force_unit, cfg.skin = w.dt, w.gamma, w.kT, 1.0, 0.3
+    cfg.k_max, cfg.mode, cfg.seed = w.K, 0, 1
+    cfg.target.kind, cfg.target.cutoff, cfg.target.epsilon, cfg.target.sigma = 1, 2.5, 1.0, 1.0
+    cfg.draft.kind, cfg.draft.cutoff, cfg.draft.epsilon, cfg.draft.sigma = 1, 1.5, 1.0, 1.0
+    for k, v in over.items():
+        setattr(cfg, k, v)
+    return cfg, keep
+
+
+def test_workspace_size_and_validation(lib):
+    from paper_2606_02455_amd import lsd
+    from paper_2606_02455_amd import workloads as W
+    w = W.config("c2")
+    cfg, keep = _cfg(lsd, w)
+    n = C.c_size_t()
+    assert lib.lsd_workspace_size(C.byref(cfg), C.byref(n)) == 0
+    # window + lists dominate: at least K frames of 16 + 12*3 bytes per atom
+    assert n.value > w.K * w.n_atoms * 52
+    for field, bad in (("gamma", 0.0), ("kT", -1.0), ("dt", 0.0), ("skin", 0.0), ("k_max", 65),
+                       ("k_max", 0), ("mode", 7)):
+        c2, _ = _cfg(lsd, w, **{field: bad})
+        assert lib.lsd_workspace_size(C.byref(c2), C.byref(n)) == -1
+        assert lib.lsd_last_error().decode() != ""
+
+
+def test_box_must_be_binary32_and_larger_than_list_radius(lib):
+    from paper_2606_02455_amd import lsd
+    from paper_2606_02455_amd import workloads as W
+    w = W.config("c1")
+    box = np.array([4.3088693618774414 + 1e-12])  # not a binary32 value
+    cfg, keep = _cfg(lsd, w)
+    cfg.box = box.ctypes.data_as(C.POINTER(C.c_double))
+    n = C.c_size_t()
+    assert lib.lsd_workspace_size(C.byref(cfg), C.byref(n)) == -1
+    small = np.array([2.5])
+    cfg.box = small.ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.lsd_workspace_size(C.byref(cfg), C.byref(n)) == -1
+    assert "exceed" in lib.lsd_last_error().decode()
+
+
+def test_init_rejects_null_buffers(lib):
+    from paper_2606_02455_amd import lsd
+    from paper_2606_02455_amd import workloads as W
+    w = W.config("c1")
+    cfg, keep = _cfg(lsd, w)
+    buf = lsd.Buffers()
+    h = C.c_void_p()
+    assert lib.lsd_init_system(C.byref(cfg), C.byref(buf), None, C.byref(h)) == -1
+    assert not h.value
+
+
+def test_calls_on_null_handle_fail_cleanly(lib):
+    assert lib.lsd_draft_steps(None, 4, None) == -1
+    assert lib.lsd_verify_window(None, None) == -1
+    assert lib.lsd_accept_rollback(None, None, None) == -1
+    assert lib.lsd_destroy(None) == 0

@@ -1,0 +1,348 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars:
+  * random stream: Philox words bit-exact, uniforms bit-exact, normals 1e-13;
+  * neighbour lists: exact set equality with the oracle's enumeration;
+  * forces: max |F_gpu - F_oracle| <= 1e-5 max |F_oracle| per frame (binary32
+    pair forces against binary64), energies 1e-5 relative;
+  * log ratios: within a first-order bound propagated from the measured force
+    error; decisions equal except inside the band
+    |log r_oracle - log u| <= max(1e-6 max(|log u|, 1), |log r_gpu - log r_oracle|);
+  * committed momenta / positions: 1e-5 relative (binary32 storage).
+All inputs are seeded and binary32-representable so both sides start from the
+same numbers.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2606_02455_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def lsd(torch):
+    from paper_2606_02455_amd import lsd as L
+    L.load()
+    return L
+
+
+def _ora_system(ora, w, r=0):
+    sl = w.replica_slice(r)
+    return ora.System(sl.stop - sl.start, float(w.box[r]), w.masses()[sl], w.dt, w.gamma, w.kT,
+                      w.force_unit)
+
+
+def _ora_pot(ora, d):
+    if d["kind"] == "lj":
+        return ora.Potential.lj(d["rc"], d.get("eps", 1.0), d.get("sig", 1.0), offset=d.get("offset"))
+    return ora.Potential.harmonic(d["k"], d["anchor"], offset=d.get("offset"))
+
+
+def _inject(sysg, torch, qmid, p_draft, f_draft):
+    """Write caller frames (numpy [K,N,3], [K+1,N,3], [K,N,3]) into the window."""
+    win = sysg.window()
+    K = qmid.shape[0]
+    q4 = np.zeros((K, qmid.shape[1], 4), np.float32)
+    q4[:, :, :3] = qmid
+    win["q_mid"][:K].copy_(torch.tensor(q4))
+    win["p_draft"][:K + 1].copy_(torch.tensor(np.transpose(p_draft, (0, 2, 1)).astype(np.float32)))
+    win["f_draft"][:K].copy_(torch.tensor(np.transpose(f_draft, (0, 2, 1)).astype(np.float32)))
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+def test_rng_matches_oracle(torch, lsd, ora):
+    _say("rng parity")
+    for (seed, rep, step, n) in [(1, 0, 1, 64), (2 ** 40 + 7, 5, 2 ** 33 + 11, 1000)]:
+        g = lsd.rng_normals(seed, rep, step, n).cpu().numpy()
+        o = ora.normals(seed, rep, step, n)
+        assert np.allclose(g, o, rtol=1e-13, atol=1e-13)
+    g = lsd.rng_uniforms(9, 3, 100, 500).cpu().numpy()
+    o = np.array([ora.uniform(9, 3, 100 + k + 1) for k in range(500)])
+    assert np.array_equal(g, o)
+
+
+def _gpu_pairs(sysg, which="target"):
+    cnt, ent = sysg.neighbor_lists(which)
+    cnt, ent = cnt.cpu().numpy(), ent.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    i_idx = np.concatenate([np.full(c, i) for i, c in enumerate(cnt)])
+    e = np.concatenate([ent[:c, i] for i, c in enumerate(cnt)])
+    j = e >> 5
+    code = e & 31
+    nx, ny, nz = code % 3 - 1, (code // 3) % 3 - 1, code // 9 - 1
+    out = np.stack([i_idx, j, nx, ny, nz], axis=1)
+    return out[np.lexsort((out[:, 4], out[:, 3], out[:, 2], out[:, 1], out[:, 0]))]
+
+
+@pytest.mark.parametrize("case", ["c1", "box2000", "c2"])
+def test_neighbor_lists_exact(torch, lsd, ora, case):
+    _say(f"neighbour lists {case}")
+    if case == "box2000":
+        w = W.lj_fluid(10, rho=0.8, seed=11, K=4)
+        w.positions = W.random_box_positions(w.n_atoms, float(w.box[0]), seed=12)
+    else:
+        w = W.config(case)
+    sysg = lsd.LSDSystem(w, mode="lsd", k_max=1)
+    K = 1
+    q = w.positions[None]
+    _inject(sysg, torch, q, np.zeros((2, w.n_atoms, 3)), np.zeros((1, w.n_atoms, 3)))
+    sysg.mark_drafted(K)
+    assert sysg.status() == 0
+    L = float(w.box[0])
+    skin = w.skin
+    for which, rc in (("target", w.target["rc"]), ("draft", w.draft["rc"])):
+        got = _gpu_pairs(sysg, which)
+        method = "cells" if np.floor(L / (rc + skin)) >= 3 else "brute"
+        ref = ora.pairs(w.positions, L, rc + skin, method)
+        assert got.shape == ref.shape and np.array_equal(got, ref), which
+    sysg.destroy()
+
+
+def _perturbed_frames(w, K, seed, amp=0.02):
+    rng = np.random.default_rng(seed)
+    L = float(w.box[0])
+    fr = []
+    for k in range(K):
+        x = w.positions + rng.uniform(-amp, amp, w.positions.shape)
+        fr.append(W.f32(np.mod(x, L)))
+    fr = np.stack(fr)
+    fr[fr >= L] = 0.0
+    return fr
+
+
+@pytest.mark.parametrize("case", ["c1", "c2"])
+def test_target_forces_and_energies(torch, lsd, ora, case):
+    _say(f"target forces {case}")
+    w = W.config(case)
+    K = w.K
+    sysg = lsd.LSDSystem(w, mode="lsd")
+    qm = _perturbed_frames(w, K, seed=3)
+    so = _ora_system(ora, w)
+    T = _ora_pot(ora, w.target)
+    D = _ora_pot(ora, w.draft)
+    fd = np.stack([W.f32(ora.energy_forces(D, qm[k], so.L)[1]) for k in range(K)])
+    rng = np.random.default_rng(4)
+    pd = W.f32(rng.normal(0, 1, (K + 1, w.n_atoms, 3)))
+    _inject(sysg, torch, qm, pd, fd)
+    sysg.mark_drafted(K)
+    sysg.verify_window()
+    sysg.accept_rollback(sync=True)
+    assert sysg.status() == 0
+    ft = sysg.window()["f_target"][:K].cpu().numpy().transpose(0, 2, 1)
+    en = sysg.energy.cpu().numpy()[0]
+    inv = sysg.window()["frame_invalid"].cpu().numpy()[0]
+    assert not inv[:K].any()
+    for k in range(K):
+        E, F = ora.energy_forces(T, qm[k], so.L)
+        err = np.max(np.abs(ft[k] - F))
+        assert err <= 1e-5 * np.max(np.abs(F)), (k, err, np.max(np.abs(F)))
+        assert abs(en[k] - E) <= 1e-5 * abs(E), (k, en[k], E)
+    sysg.destroy()
+
+
+def _oracle_window_rounded(ora, w, xi, u, q0, p0):
+    """Oracle window from (q0, p0), with every stored draft array rounded to
+    binary32 so that both sides can be fed the identical frames."""
+    so = _ora_system(ora, w)
+    T, D = _ora_pot(ora, w.target), _ora_pot(ora, w.draft)
+    q, p = q0.copy(), p0.copy()
+    img = np.zeros(q.shape, np.int32)
+    r = ora.lsd_window(so, T, D, q, p, img, xi, u)
+    return so, T, r
+
+
+@pytest.mark.parametrize("case", ["c1", "lj512"])
+def test_verify_and_commit_on_identical_frames(torch, lsd, ora, case):
+    _say(f"verify parity {case}")
+    w = W.config("c1") if case == "c1" else W.lj_fluid(8, seed=21, K=8)
+    K, N = w.K, w.n_atoms
+    checked_reject = 0
+    for trial in range(6):
+        xi = np.stack([ora.normals(w.seed + trial, 0, s, N) for s in range(1, K + 1)])
+        u = np.array([ora.uniform(w.seed + trial, 0, s) for s in range(1, K + 1)])
+        so, T, r = _oracle_window_rounded(ora, w, xi, u, w.positions, w.momenta)
+        qm, pd, fd = W.f32(r["q_mid"]), W.f32(r["p_draft"]), W.f32(r["F_draft"])
+        if np.any(qm >= so.L):
+            qm[qm >= so.L] = 0.0
+        sysg = lsd.LSDSystem(w, mode="lsd", replay=True)
+        sysg.replay_u.copy_(torch.tensor(u[None, :]))
+        # committed state = frame-0 momenta; positions are not read by verify
+        sysg.set_state(w.positions, pd[0])
+        _inject(sysg, torch, qm, pd, fd)
+        sysg.mark_drafted(K)
+        sysg.verify_window()
+        n = int(sysg.accept_rollback(sync=True)[0])
+        lr = sysg.log_ratio.cpu().numpy()[0]
+        acc = sysg.accepted.cpu().numpy()[0]
+        ft = sysg.window()["f_target"][:K].cpu().numpy().transpose(0, 2, 1)
+        sig = so.sigma()[:, None]
+        c1 = (1 + so.a) * so.dt / 2
+        j_ref = K
+        for k in range(K):
+            v = ora.verify_frame(so, T, qm[k], pd[k], pd[k + 1], fd[k], u[k])
+            dF = np.abs(ft[k] - v["F_target"])
+            assert np.max(dF) <= 1e-5 * np.max(np.abs(v["F_target"]))
+            # first-order bound of |d log r| from the force error
+            mu_t = so.a * pd[k] + c1 * v["F_target"]
+            wt = (pd[k + 1] - mu_t) / sig
+            bound = 2.0 * np.sum(np.abs(wt) * (c1 / sig) * dF) + 1e-9 * max(1.0, abs(v["logr"]))
+            assert abs(lr[k] - v["logr"]) <= bound, (k, lr[k], v["logr"], bound)
+            lu = np.log(u[k])
+            band = abs(v["logr"] - lu) <= max(1e-6 * max(abs(lu), 1.0), abs(lr[k] - v["logr"]))
+            if not band:
+                assert bool(acc[k]) == v["accept"], (k, acc[k], v["accept"])
+            if not v["accept"] and j_ref == K:
+                j_ref = k + 1
+                v_ref = v
+        assert n == j_ref
+        st = sysg.state()
+        if j_ref < K:
+            checked_reject += 1
+            scale = np.max(np.abs(v_ref["p"]))
+            assert np.max(np.abs(st["p"] - v_ref["p"])) <= 1e-5 * scale
+            dq = st["q"] - v_ref["q"]
+            dq -= so.L * np.round(dq / so.L)
+            assert np.max(np.abs(dq)) <= 1e-5 * so.L
+        else:
+            assert np.array_equal(st["p"], pd[K])
+        sysg.destroy()
+    assert checked_reject >= 1
+
+
+def test_draft_steps_match_oracle(torch, lsd, ora):
+    _say("draft parity c1")
+    w = W.config("c1")
+    K, N = w.K, w.n_atoms
+    xi = np.stack([ora.normals(w.seed, 0, s, N) for s in range(1, K + 1)])
+    u = np.ones(K)
+    sysg = lsd.LSDSystem(w, mode="lsd", replay=True)
+    sysg.replay_xi.copy_(torch.tensor(xi))
+    sysg.replay_u.copy_(torch.tensor(u[None, :]))
+    sysg.draft_steps(K)
+    torch.cuda.synchronize()
+    win = sysg.window()
+    qm = win["q_mid"][:K, :, :3].cpu().numpy().astype(np.float64)
+    pd = win["p_draft"][:K + 1].cpu().numpy().transpose(0, 2, 1).astype(np.float64)
+    fd = win["f_draft"][:K].cpu().numpy().transpose(0, 2, 1).astype(np.float64)
+    so, T, r = _oracle_window_rounded(ora, w, xi, u, w.positions, w.momenta)
+    # the first midpoint is the same binary64 expression rounded to binary32
+    assert np.array_equal(qm[0], W.f32(r["q_mid"][0]))
+    for k in range(K):
+        d = qm[k] - r["q_mid"][k]
+        d -= so.L * np.round(d / so.L)
+        assert np.max(np.abs(d)) < 2e-5, k
+        assert np.max(np.abs(fd[k] - r["F_draft"][k])) <= 1e-4 * np.max(np.abs(r["F_draft"][k]))
+        assert np.max(np.abs(pd[k + 1] - r["p_draft"][k + 1])) <= 1e-5 * np.max(np.abs(r["p_draft"][k + 1]))
+    sysg.verify_window()
+    sysg.accept_rollback(sync=True)
+    sysg.destroy()
+
+
+def test_full_size_draft_first_frame(torch, lsd, ora):
+    _say("draft first frame c2")
+    w = W.config("c2")
+    N = w.n_atoms
+    xi = ora.normals(w.seed, 0, 1, N)[None]
+    sysg = lsd.LSDSystem(w, mode="lsd", replay=True, k_max=1)
+    sysg.replay_xi.copy_(torch.tensor(xi))
+    sysg.replay_u.fill_(1.0)
+    sysg.draft_steps(1)
+    torch.cuda.synchronize()
+    win = sysg.window()
+    qm0 = win["q_mid"][0, :, :3].cpu().numpy().astype(np.float64)
+    fd0 = win["f_draft"][0].cpu().numpy().T.astype(np.float64)
+    p1 = win["p_draft"][1].cpu().numpy().T.astype(np.float64)
+    so = _ora_system(ora, w)
+    D = _ora_pot(ora, w.draft)
+    q, p = w.positions.copy(), w.momenta.copy()
+    img = np.zeros((N, 3), np.int32)
+    r = ora.lsd_window(so, _ora_pot(ora, w.target), D, q, p, img, xi, np.ones(1))
+    assert np.array_equal(qm0, W.f32(r["q_mid"][0]))
+    E, F = ora.energy_forces(D, qm0, so.L)
+    assert np.max(np.abs(fd0 - F)) <= 1e-5 * np.max(np.abs(F))
+    assert np.max(np.abs(p1 - r["p_draft"][1])) <= 1e-5 * np.max(np.abs(r["p_draft"][1]))
+    assert sysg.status() == 0
+    sysg.verify_window()
+    sysg.accept_rollback(sync=True)
+    sysg.destroy()
+
+
+def test_draft_equals_target_is_plain_bitwise(torch, lsd):
+    _say("draft == target vs plain")
+    w = W.config("c1")
+    same = dict(w.target)
+    a = lsd.LSDSystem(w, mode="lsd", draft=same)
+    b = lsd.LSDSystem(w, mode="plain")
+    for win in range(25):
+        a.draft_steps(8)
+        a.verify_window()
+        na = a.accept_rollback(sync=True)
+        b.draft_steps(8)
+        nb = b.accept_rollback(sync=True)
+        assert na[0] == nb[0]
+        assert np.all(a.accepted.cpu().numpy()[0][:na[0]] == 1)
+        sa, sb = a.state(), b.state()
+        assert np.array_equal(sa["q"], sb["q"]) and np.array_equal(sa["p"], sb["p"])
+        assert np.array_equal(sa["img"], sb["img"]) and np.array_equal(sa["step"], sb["step"])
+    assert a.state()["step"][0] >= 150
+    a.destroy()
+    b.destroy()
+
+
+def test_run_is_deterministic(torch, lsd):
+    _say("determinism")
+    w = W.config("c1")
+    out = []
+    for rep in range(2):
+        s = lsd.LSDSystem(w, mode="lsd")
+        s.run_windows(40, 8)
+        out.append(s.state())
+        s.destroy()
+    for k in ("q", "p", "img", "step"):
+        assert np.array_equal(out[0][k], out[1][k])
+
+
+def test_window_length_changes_only_rounding(torch, lsd):
+    _say("window length")
+    w = W.config("c1")
+    ref = None
+    for K in (1, 3, 8):
+        s = lsd.LSDSystem(w, mode="lsd", k_max=8)
+        while s.state()["step"][0] < 30:
+            s.draft_steps(min(K, 30 - int(s.state()["step"][0])))
+            s.verify_window()
+            s.accept_rollback(sync=True)
+        st = s.state()
+        s.destroy()
+        if ref is None:
+            ref = st
+        else:
+            assert np.max(np.abs(st["p"] - ref["p"])) < 1e-3
+            assert np.array_equal(st["step"], ref["step"])
+
+
+def test_neighbor_overflow_is_reported(torch, lsd):
+    _say("overflow status")
+    w = W.config("c1")
+    s = lsd.LSDSystem(w, mode="lsd", max_neighbors=(32, 32))
+    s.draft_steps(2)
+    s.verify_window()
+    s.accept_rollback(sync=True)
+    assert s.status() & lsd.STATUS_NBR_TARGET
+    s.destroy()
