@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Benchmark: target-distributed MD steps/s of LSD vs plain target Langevin
+on one MI355X, with the verification kernel's roofline and the FP64 oracle
+timed on the host as the CPU baseline.
+
+A timed "step" is one LSD window over the whole hot path: draft K steps
+(cell + neighbour lists, K draft kernels), verify all K frames in one launch,
+decide, reflect and commit.  ``value`` is committed target-distributed steps
+per second.  Plain Langevin runs the same kernels with the target force
+field and commits every step; it is timed over the same number of windows.
+
+Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--config c2]
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+VERIFY_SOURCES = ["paper_2606_02455_amd/csrc/lsd_kernels.hip",
+                  "paper_2606_02455_amd/csrc/lsd_device.h"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for f in VERIFY_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(config_name):
+    """HBM bytes per verification launch from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_verify_{config_name}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def in_cutoff_pairs(sysg, rc):
+    """Directed pairs within rc at the current list positions (frame 0),
+    counted on the GPU from the neighbour list."""
+    import torch
+    cnt, ent = sysg.neighbor_lists("target")
+    win = sysg.window()
+    x = win["q_mid"][0, :, :3].double()
+    L = float(sysg.w.box[0])
+    m = ent.shape[1]
+    ar = torch.arange(m, device=ent.device)[None, :]
+    valid = ar < cnt[:, None].to(ar.dtype)
+    e = ent.long() & 0xFFFFFFFF
+    j = (e >> 5).clamp(max=sysg.N - 1)
+    code = e & 31
+    n = torch.stack([code % 3 - 1, (code // 3) % 3 - 1, code // 9 - 1], dim=-1).double()
+    d = x[j] + n * L - x[:, None, :]
+    r2 = (d * d).sum(-1)
+    return int(((r2 < rc * rc) & valid).sum().item())
+
+
+def cpu_baseline(w, q, p, seconds):
+    """The FP64 oracle as it stands: LSD windows of K frames from the
+    benchmark's equilibrated state until `seconds` of host time are spent."""
+    import numpy as np
+
+    import oracle
+    so = oracle.System(w.n_atoms, float(w.box[0]), 1.0, w.dt, w.gamma, w.kT)
+    T = oracle.Potential.lj(w.target["rc"])
+    D = oracle.Potential.lj(w.draft["rc"])
+    q, p = q.copy(), p.copy()
+    img = np.zeros(q.shape, np.int32)
+    K, N = w.K, w.n_atoms
+    committed = windows = 0
+    step = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        xi = np.stack([oracle.normals(w.seed, 0, step + k + 1, N) for k in range(K)])
+        u = np.array([oracle.uniform(w.seed, 0, step + k + 1) for k in range(K)])
+        r = oracle.lsd_window(so, T, D, q, p, img, xi, u)
+        committed += r["n_committed"]
+        step += r["n_committed"]
+        windows += 1
+    t_lsd = time.perf_counter() - t0
+    # plain target Langevin on the host for comparison
+    t1 = time.perf_counter()
+    n_plain = 0
+    while time.perf_counter() - t1 < max(2.0, seconds / 4):
+        oracle.plain_run(so, T, q, p, img, w.seed, 0, step + n_plain, 4)
+        n_plain += 4
+    t_plain = time.perf_counter() - t1
+    return dict(value=committed / t_lsd, unit="steps/s", cores=oracle.num_threads(), kind="oracle",
+                sample=(f"{windows} LSD windows (K={K}) of the {N}-atom fluid from the "
+                        f"benchmark state, {committed} committed steps in {t_lsd:.1f} s"),
+                plain_steps_per_s=n_plain / t_plain)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed windows")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed windows")
+    ap.add_argument("--config", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--equilibrate", type=int, default=256, help="plain steps before timing")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only: the batched verification path runs the K frames "
+              f"of a window on a single MI355X (asked for --gpus {args.gpus}, WORLD_SIZE {world}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2606_02455_amd import lsd
+    from paper_2606_02455_amd import workloads as W
+
+    lsd.load()
+    torch.cuda.set_device(0)
+    w = W.config(args.config)
+    K = w.K
+    log(f"workload {w.name}: N={w.n_atoms} K={K} box={w.box[0]:.5f}")
+
+    plain = lsd.LSDSystem(w, mode="plain")
+    eq_windows = max(1, args.equilibrate // K)
+    plain.run_windows(eq_windows, K)
+    torch.cuda.synchronize()
+    lsds = lsd.LSDSystem(w, mode="lsd")
+    lsds.q.copy_(plain.q)
+    lsds.p.copy_(plain.p)
+    lsds.img.copy_(plain.img)
+    lsds.step.copy_(plain.step)
+    st0 = plain.state()
+    log(f"equilibrated {int(st0['step'][0])} plain steps")
+
+    # --- LSD
+    lsds.run_windows(args.warmup, K)
+    lsds.reset_counters()
+    lsds.set_verify_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lsds.run_windows(args.steps, K)
+    torch.cuda.synchronize()
+    t_lsd = time.perf_counter() - t0
+    ver_ms, ver_n = lsds.verify_timing()
+    cn = lsds.counters()[0]
+    lsds.set_verify_timing(False)
+    windows, committed, rejections, frames = (int(v) for v in cn)
+    assert windows == args.steps
+    log(f"LSD: {committed} steps in {t_lsd * 1e3:.1f} ms over {windows} windows; "
+        f"rejections {rejections}; verify {ver_ms / max(ver_n, 1) * 1e3:.1f} us/launch")
+
+    # --- plain target Langevin, same kernels, same number of windows
+    plain.run_windows(args.warmup, K)
+    plain.reset_counters()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plain.run_windows(args.steps, K)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t1
+    pc = plain.counters()[0]
+    plain_steps = int(pc[1])
+    log(f"plain: {plain_steps} steps in {t_plain * 1e3:.1f} ms")
+    status = lsds.status() | plain.status()
+    if status:
+        raise RuntimeError(f"device status {status}: neighbour capacity overflow")
+
+    # --- roofline of the dominant kernel (one verification launch)
+    frames_per_launch = frames / max(ver_n, 1)
+    pairs = in_cutoff_pairs(lsds, w.target["rc"])
+    alg_bytes = frames_per_launch * w.n_atoms * 60.0 + pairs * 4.0
+    avg_s = ver_ms / max(ver_n, 1) * 1e-3
+    achieved = alg_bytes / avg_s / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=read_traffic(args.config),
+                    kernel="k_verify", avg_us=round(avg_s * 1e6, 3),
+                    algorithmic_bytes=int(alg_bytes), frames_per_launch=round(frames_per_launch, 3),
+                    in_cutoff_pairs=pairs)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        st = lsds.state()
+        log("timing the FP64 oracle on the host ...")
+        cpu = cpu_baseline(w, st["q"], st["p"], args.cpu_seconds)
+        log(f"oracle: {cpu['value']:.3f} LSD steps/s, {cpu['plain_steps_per_s']:.3f} plain steps/s "
+            f"on {cpu['cores']} threads")
+
+    value = committed / t_lsd
+    plain_rate = plain_steps / t_plain
+    out = {
+        "metric": "target-distributed MD steps/s (LSD vs plain Langevin, 1 GPU); acceptance rate",
+        "value": round(value, 3),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_lsd / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w.name}: Lennard-Jones fluid, {w.n_atoms} atoms, rho*=0.8, T*=1, "
+                         f"target cutoff {w.target['rc']}, draft cutoff {w.draft['rc']}, "
+                         f"K={K}, dt={w.dt}, gamma={w.gamma}, seed {w.seed}"),
+            "n_atoms": w.n_atoms, "K": K, "skin": w.skin,
+        },
+        "acceptance": round(1.0 - rejections / max(committed, 1), 5),
+        "committed_per_window": round(committed / windows, 4),
+        "plain_steps_per_s": round(plain_rate, 3),
+        "lsd_over_plain": round(value / plain_rate, 5),
+        "tau_per_day_lsd": round(value * w.dt * 86400.0, 2),
+        "tau_per_day_plain": round(plain_rate * w.dt * 86400.0, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

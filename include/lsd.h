@@ -189,9 +189,10 @@ typedef struct {
   size_t f_draft;    /* float [k_max][3][N] */
   size_t f_target;   /* float [k_max][3][N] */
   size_t frame_invalid; /* int32 [R][k_max] */
-  size_t nbr_target; /* uint32 [max_neighbors_target][N]: j << 5 | image code */
+  size_t nbr_target; /* uint32 [N][max_neighbors_target]: j << 5 | image code,
+                        code = (nx+1) + 3 (ny+1) + 9 (nz+1), n = image */
   size_t cnt_target; /* int32 [N] */
-  size_t nbr_draft;  /* uint32 [max_neighbors_draft][N] */
+  size_t nbr_draft;  /* uint32 [N][max_neighbors_draft] */
   size_t cnt_draft;  /* int32 [N] */
   int32_t max_neighbors_target, max_neighbors_draft;
   int32_t n_atoms, k_max;
@@ -201,6 +202,22 @@ LSD_API lsd_status lsd_get_window_layout(const lsd_system *sys, lsd_window_layou
 /* Synchronises `stream` and returns the device status word: bit 0 target
  * list overflow, bit 1 draft list overflow, bit 2 cell overflow. */
 LSD_API lsd_status lsd_get_status(lsd_system *sys, int32_t *flags, lsd_stream stream);
+
+/* Final step count of the run (Alg. 2 stops when that many steps are
+ * verified): frames that would produce a step beyond `limit` are not
+ * verified, so every replica stops exactly at step `limit` (a window may then
+ * commit 0 steps).  Stopping on a step count rather than after a number of
+ * windows keeps the final states target-distributed: window ends follow
+ * rejections, so stopping at a window end would select post-rejection
+ * states.  Default: no limit.  Takes effect from the next window. */
+LSD_API lsd_status lsd_set_step_limit(lsd_system *sys, int64_t limit);
+
+/* Per-replica counters since init or the last reset, copied to host
+ * out[R][4] = {windows, committed steps, rejections (windows ending in a
+ * reflected step), frames verified}.  The empirical rejection rate of the
+ * paper (Sec. 3.3) is rejections / committed.  Synchronises `stream`. */
+LSD_API lsd_status lsd_get_counters(lsd_system *sys, int64_t *out, lsd_stream stream);
+LSD_API lsd_status lsd_reset_counters(lsd_system *sys, lsd_stream stream);
 
 /* Kernel timing of the verification launch with HIP events on `stream`.
  * enable != 0 starts recording; lsd_get_verify_timing synchronises and

@@ -6,6 +6,7 @@
 // with lookahead K, per-step maps of Alg. 2).
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -53,14 +54,14 @@ struct Layout {
   size_t atom_rep, species, rep_off, box, rep_nc, rep_cell_off;
   size_t tile_start, tile_count, tile_rep, rep_tile_off;
   // cells and lists
-  size_t cell_count, cell_start, cell_cursor, cell_atoms, atom_cell;
+  size_t cell_rep, cell_count, cell_start, cell_cursor, cell_unsorted, cell_atoms, atom_cell;
   size_t nbr_t, cnt_t, nbr_d, cnt_d;
   // window
-  size_t qmid, p, fd, ft, invalid, partial, commit_frame, reflected, coef, status;
-  int mt = 0, md = 0, n_cells = 0, n_tiles = 0;
-  double rl_t = 0, rl_d = 0, band_L = 0;
+  size_t qmid, p, fd, ft, invalid, partial, commit_frame, reflected, coef, counters, status;
+  int mt = 0, md = 0, n_cells = 0, n_tiles = 0, cell_cap = 0;
+  double rl_t = 0, rl_d = 0;
   std::vector<int> atom_rep_h, rep_nc_h, rep_cell_off_h, tile_start_h, tile_count_h, tile_rep_h,
-      rep_tile_off_h;
+      rep_tile_off_h, cell_rep_h;
 };
 
 size_t bump(size_t* off, size_t bytes) {
@@ -127,9 +128,10 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   L->tile_start_h.clear();
   L->tile_count_h.clear();
   L->tile_rep_h.clear();
+  L->cell_rep_h.clear();
+  L->cell_cap = 1;
   double rho_max = 0.0;
   long long cells = 0;
-  L->band_L = 0.0;
   for (int r = 0; r < R; ++r) {
     const int a0 = c->atom_offsets[r], a1 = c->atom_offsets[r + 1];
     if (a1 <= a0) return fail(LSD_ERR_INVALID_ARG, "replica %d has no atoms", r);
@@ -138,16 +140,20 @@ lsd_status plan(const lsd_config* c, Layout* L) {
       return fail(LSD_ERR_INVALID_ARG, "box[%d] = %.17g must be > 0 and binary32", r, Lr);
     if (!(Lr > r_cell))
       return fail(LSD_ERR_INVALID_ARG, "box[%d] = %g must exceed cutoff + skin = %g", r, Lr, r_cell);
-    L->band_L = std::max(L->band_L, Lr);
     const int n_r = a1 - a0;
     rho_max = std::max(rho_max, n_r / (Lr * Lr * Lr));
     int nc = (int)std::floor(Lr / (r_cell * (1.0 + 1e-6)));
-    int cap = std::max(1, (int)std::cbrt((double)n_r));
-    nc = std::min(nc, cap);
+    nc = std::min(nc, std::max(1, (int)std::cbrt((double)n_r)));
     if (nc < 3) nc = 1;
     L->rep_nc_h[r] = nc;
     L->rep_cell_off_h[r] = (int)cells;
     cells += (long long)nc * nc * nc;
+    if (cells > (1ll << 30)) return fail(LSD_ERR_INVALID_ARG, "too many cells");
+    L->cell_rep_h.insert(L->cell_rep_h.end(), (size_t)nc * nc * nc, r);
+    // occupancy the list builder covers: the whole replica for a single
+    // cell, else 2.5x the mean occupancy plus 32 (exceeding it is reported)
+    const int cap = nc == 1 ? n_r : (int)std::ceil(2.5 * n_r / ((double)nc * nc * nc) + 32.0);
+    L->cell_cap = std::max(L->cell_cap, cap);
     for (int i = a0; i < a1; ++i) L->atom_rep_h[i] = r;
     L->rep_tile_off_h[r] = (int)L->tile_start_h.size();
     for (int t = a0; t < a1; t += LSD_TILE) {
@@ -157,7 +163,6 @@ lsd_status plan(const lsd_config* c, Layout* L) {
     }
   }
   L->rep_tile_off_h[R] = (int)L->tile_start_h.size();
-  if (cells > (1ll << 30)) return fail(LSD_ERR_INVALID_ARG, "too many cells");
   L->n_cells = (int)cells;
   L->n_tiles = (int)L->tile_start_h.size();
 
@@ -167,7 +172,7 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   };
   L->mt = c->max_neighbors_target > 0 ? c->max_neighbors_target : auto_width(L->rl_t);
   L->md = c->max_neighbors_draft > 0 ? c->max_neighbors_draft : auto_width(L->rl_d);
-  if (L->mt > 640) return fail(LSD_ERR_CAPACITY, "target neighbour width %d > 640", L->mt);
+  if (L->mt > 600) return fail(LSD_ERR_CAPACITY, "target neighbour width %d > 600", L->mt);
   if (L->md > 4096) return fail(LSD_ERR_CAPACITY, "draft neighbour width %d > 4096", L->md);
 
   const size_t n = (size_t)N, K = (size_t)c->k_max, T = (size_t)L->n_tiles;
@@ -182,9 +187,11 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   L->tile_count = bump(&off, T * 4);
   L->tile_rep = bump(&off, T * 4);
   L->rep_tile_off = bump(&off, (R + 1) * 4);
+  L->cell_rep = bump(&off, (size_t)L->n_cells * 4);
   L->cell_count = bump(&off, (size_t)L->n_cells * 4);
   L->cell_start = bump(&off, ((size_t)L->n_cells + 1) * 4);
   L->cell_cursor = bump(&off, (size_t)L->n_cells * 4);
+  L->cell_unsorted = bump(&off, n * 4);
   L->cell_atoms = bump(&off, n * 4);
   L->atom_cell = bump(&off, n * 4);
   L->nbr_t = bump(&off, (size_t)L->mt * n * 4);
@@ -200,6 +207,7 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   L->commit_frame = bump(&off, R * 4);
   L->reflected = bump(&off, R * 4);
   L->coef = bump(&off, R * 8);
+  L->counters = bump(&off, (size_t)R * 4 * 8);
   L->status = bump(&off, 4 * 4);
   L->total = (off + kAlign - 1) / kAlign * kAlign;
   return LSD_OK;
@@ -212,15 +220,14 @@ PotDev make_pot(const lsd_potential& P, const Layout& L) {
   d.offset = P.force_offset;
   if (P.kind == LSD_POT_LJ) {
     const double rc = P.cutoff, rc2 = rc * rc;
-    // bound on |r2_binary32 - r2_exact| near the cutoff for coordinates in
-    // [0, L): |d_binary32 - d| <= u (2 L + r_list) per component, u = 2^-23
-    const double u = std::ldexp(1.0, -23);
-    const double band =
-        4.0 * std::sqrt(3.0) * rc * u * (2.0 * L.band_L + L.rl_t + L.rl_d) + 10.0 * u * rc2;
+    // the binary32 separation has relative error <= 4u per component, so
+    // |r2_binary32 - r2| <= 12u r2 to first order (u = 2^-24); the band
+    // rc2 (1 -+ 32u) hands every closer call to the binary64 predicate
+    const double u = std::ldexp(1.0, -24);
     d.rc2_d = rc2;
     d.rc2 = (float)rc2;
-    d.rc2_lo = (float)(rc2 - band);
-    d.rc2_hi = (float)(rc2 + band);
+    d.rc2_lo = (float)(rc2 * (1.0 - 32.0 * u));
+    d.rc2_hi = (float)(rc2 * (1.0 + 32.0 * u));
     d.eps4 = (float)(4.0 * P.epsilon);
     d.eps24 = (float)(24.0 * P.epsilon);
     d.sig2 = (float)(P.sigma * P.sigma);
@@ -253,7 +260,7 @@ struct lsd_system {
   OutDev O;
   PotDev Pt, Pd;
   int state = ST_READY;
-  int fpb = 8;
+
   bool timing = false;
   TimingRing ring;
   double t_sum = 0.0;
@@ -343,6 +350,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   up(L.tile_count_h, L.tile_count);
   up(L.tile_rep_h, L.tile_rep);
   up(L.rep_tile_off_h, L.rep_tile_off);
+  up(L.cell_rep_h, L.cell_rep);
   if (st_ok != LSD_OK) { delete s; return st_ok; }
   hipError_t e = hipMemcpyAsync(ws<double>(s, L.box), box_h.data(), R * sizeof(double),
                                 hipMemcpyHostToDevice, st);
@@ -351,6 +359,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.status), 0, 4, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.invalid), 0, R * cfg->k_max, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_t), 0, N, st);
+  if (e == hipSuccess) e = launch_zero_i64(ws<long long>(s, L.counters), 4 * R, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_d), 0, N, st);
   if (e == hipSuccess) e = prepare_verify(L.mt);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -383,15 +392,19 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   S.replay_u = buf->replay_u;
   S.replay_xi = buf->replay_xi;
   S.step = buf->step;
+  S.step_limit = INT64_MAX;
 
   ListDev& Ls = s->Lst;
   memset(&Ls, 0, sizeof(Ls));
   Ls.rep_nc = ws<int>(s, L.rep_nc);
   Ls.rep_cell_off = ws<int>(s, L.rep_cell_off);
+  Ls.cell_rep = ws<int>(s, L.cell_rep);
   Ls.cell_count = ws<int>(s, L.cell_count);
   Ls.cell_start = ws<int>(s, L.cell_start);
   Ls.cell_cursor = ws<int>(s, L.cell_cursor);
+  Ls.cell_unsorted = ws<int>(s, L.cell_unsorted);
   Ls.cell_atoms = ws<int>(s, L.cell_atoms);
+  Ls.cell_cap = L.cell_cap;
   Ls.atom_cell = ws<int>(s, L.atom_cell);
   Ls.n_cells = L.n_cells;
   Ls.nbr_t = ws<uint32_t>(s, L.nbr_t);
@@ -415,6 +428,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   W.commit_frame = ws<int>(s, L.commit_frame);
   W.reflected = ws<int>(s, L.reflected);
   W.coef = ws<double>(s, L.coef);
+  W.counters = ws<long long>(s, L.counters);
   W.K = 0;
 
   TileDev& T = s->T;
@@ -478,7 +492,9 @@ lsd_status lsd_verify_window(lsd_system* s, lsd_stream stream) {
       slot = (R.head + R.used) % kTimingRing;
       HIP_TRY(hipEventRecord(R.start[slot], st));
     }
-    HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, s->fpb, st));
+    // frames per wave of the verification kernel: 4 for long windows
+    const int fw = s->W.K >= 8 ? 4 : (s->W.K >= 2 ? 2 : 1);
+    HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st));
     if (s->timing) {
       HIP_TRY(hipEventRecord(R.stop[slot], st));
       R.used += 1;
@@ -538,6 +554,27 @@ lsd_status lsd_get_status(lsd_system* s, int32_t* flags, lsd_stream stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipMemcpyAsync(flags, s->Lst.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  return LSD_OK;
+}
+
+lsd_status lsd_set_step_limit(lsd_system* s, int64_t limit) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  if (limit < 0) return fail(LSD_ERR_INVALID_ARG, "step limit < 0");
+  s->S.step_limit = limit;
+  return LSD_OK;
+}
+
+lsd_status lsd_get_counters(lsd_system* s, int64_t* out, lsd_stream stream) {
+  if (!s || !out) return fail(LSD_ERR_INVALID_ARG, "null argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(out, s->W.counters, sizeof(int64_t) * 4 * s->S.R, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return LSD_OK;
+}
+
+lsd_status lsd_reset_counters(lsd_system* s, lsd_stream stream) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  HIP_TRY(launch_zero_i64(s->W.counters, 4 * s->S.R, static_cast<hipStream_t>(stream)));
   return LSD_OK;
 }
 

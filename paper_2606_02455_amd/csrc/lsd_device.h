@@ -11,7 +11,8 @@
 #include <stdint.h>
 
 #define LSD_MAX_SPECIES 8
-#define LSD_TILE 64           // atoms per verification tile (one wavefront)
+#define LSD_TILE 64           // atoms per verification tile
+#define LSD_LPA 4             // lanes per atom in the force loops
 #define LSD_MAX_K 64
 #define LSD_POT_LJ 1
 #define LSD_POT_HARMONIC 2
@@ -47,19 +48,23 @@ struct SysDev {
   const double* replay_u;   // [R][kmax] or null
   const double* replay_xi;  // [kmax][N][3] or null
   int64_t* step;            // [R] committed step
+  int64_t step_limit;       // frames producing steps beyond this are not verified
 };
 
 struct ListDev {
   const int* rep_nc;        // [R] cells per edge (1 = whole replica, 27 images)
   const int* rep_cell_off;  // [R] first cell of the replica
+  const int* cell_rep;      // [C] replica of each cell
   int* cell_count;          // [C]
   int* cell_start;          // [C + 1]
   int* cell_cursor;         // [C]
-  int* cell_atoms;          // [N]
+  int* cell_unsorted;       // [N] atoms binned by cell, arbitrary order inside a cell
+  int* cell_atoms;          // [N] atoms binned by cell, ascending inside a cell
   int* atom_cell;           // [N]
   int n_cells;
-  uint32_t* nbr_t; int* cnt_t; int mt;   // target list, ELL [mt][N]
-  uint32_t* nbr_d; int* cnt_d; int md;   // draft list, ELL [md][N]
+  int cell_cap;             // largest cell occupancy the list builder covers
+  uint32_t* nbr_t; int* cnt_t; int mt;   // target list, atom-major [N][mt]
+  uint32_t* nbr_d; int* cnt_d; int md;   // draft list, atom-major [N][md]
   double rl2_t, rl2_d;      // list radii squared (binary64)
   int* status;
 };
@@ -74,6 +79,7 @@ struct WinDev {
   int* commit_frame;  // [R]
   int* reflected;     // [R]
   double* coef;       // [R] 2 S1 / S2 of the rejected frame
+  long long* counters;  // [R][4]: windows, committed steps, rejections, frames verified
   int K;              // frames in the current window
 };
 
@@ -204,15 +210,25 @@ __device__ __forceinline__ bool inside_exact(float4 xi, float4 xj, int code, dou
   return d2 < rc2;
 }
 
-// Lennard-Jones force on i from image (xj + shift); returns whether the pair
-// is inside the cutoff.  The binary32 distance decides unless it falls in the
-// rounding band around rc^2, where the exact binary64 predicate decides.
-__device__ __forceinline__ bool lj_pair(const PotDev& P, float4 xi, float4 xj, float sx, float sy,
-                                        float sz, int code, double L, float& fx, float& fy,
+// Separation of the image n of j from i in binary32 without cancellation
+// across the box boundary: the box edge is subtracted from whichever
+// coordinate lies in the far half of the box (that subtraction is exact), so
+// dx = (x_j + min(n,0) L) - (x_i - max(n,0) L) has relative error <= 4u.
+// sj = min(n,0) L and si = max(n,0) L per component.
+__device__ __forceinline__ float sep(float xj, float sj, float xi, float si) {
+  return (xj + sj) - (xi - si);
+}
+
+// Lennard-Jones force on i from image n of j; returns whether the pair is
+// inside the cutoff.  The binary32 distance decides unless it falls in the
+// relative band rc2 (1 -+ 32u) around the cutoff, where the exact binary64
+// predicate decides.
+__device__ __forceinline__ bool lj_pair(const PotDev& P, float4 xi, float4 xj, const float* sj,
+                                        const float* si, int code, double L, float& fx, float& fy,
                                         float& fz, float& e) {
-  float dx = (xj.x - xi.x) + sx;
-  float dy = (xj.y - xi.y) + sy;
-  float dz = (xj.z - xi.z) + sz;
+  float dx = sep(xj.x, sj[0], xi.x, si[0]);
+  float dy = sep(xj.y, sj[1], xi.y, si[1]);
+  float dz = sep(xj.z, sj[2], xi.z, si[2]);
   float r2 = dx * dx + dy * dy + dz * dz;
   if (r2 >= P.rc2_lo) {
     if (r2 >= P.rc2_hi) return false;
@@ -227,6 +243,16 @@ __device__ __forceinline__ bool lj_pair(const PotDev& P, float4 xi, float4 xj, f
   fz -= fs * dz;
   e += 0.5f * (P.eps4 * s6 * (s6 - 1.0f) - P.eshift);
   return true;
+}
+
+// per image code: sj = min(n,0) L, si = max(n,0) L for x, y, z
+__device__ __forceinline__ void image_shifts(int code, float Lf, float sj[3], float si[3]) {
+  const int n[3] = {code_nx(code), code_ny(code), code_nz(code)};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    sj[a] = n[a] < 0 ? -Lf : 0.0f;
+    si[a] = n[a] > 0 ? Lf : 0.0f;
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -29,7 +29,11 @@ __global__ __launch_bounds__(256) void k_window_start(SysDev S, ListDev Lst, Win
                                                       const float* __restrict__ q,
                                                       const float* __restrict__ p) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < S.R * S.kmax) W.invalid[i] = 0;
+  if (i < S.R * S.kmax) {
+    // frames that would produce steps past the step limit are never verified
+    const int rr = i / S.kmax, f = i % S.kmax;
+    W.invalid[i] = (S.step[rr] + f + 1 > S.step_limit) ? 1 : 0;
+  }
   if (i >= S.n) return;
   const int r = S.atom_rep[i];
   const int sp = S.species ? S.species[i] : 0;
@@ -112,94 +116,177 @@ __global__ __launch_bounds__(256) void k_cell_fill(int n, ListDev Lst) {
   if (i >= n) return;
   int c = Lst.atom_cell[i];
   int pos = Lst.cell_start[c] + atomicAdd(&Lst.cell_cursor[c], 1);
-  Lst.cell_atoms[pos] = i;
+  Lst.cell_unsorted[pos] = i;
 }
 
-// ascending atom order inside each cell: the list order then depends only on
-// the positions, not on the order the atomics were served in
-__global__ __launch_bounds__(256) void k_cell_sort(ListDev Lst) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= Lst.n_cells) return;
-  int lo = Lst.cell_start[c], hi = Lst.cell_start[c + 1];
-  for (int a = lo + 1; a < hi; ++a) {
-    int v = Lst.cell_atoms[a];
-    int b = a - 1;
-    while (b >= lo && Lst.cell_atoms[b] > v) {
-      Lst.cell_atoms[b + 1] = Lst.cell_atoms[b];
-      --b;
-    }
-    Lst.cell_atoms[b + 1] = v;
+// ascending atom order inside each cell (rank sort, one block per cell): the
+// list order then depends only on the positions, not on the order in which
+// the binning atomics were served
+__global__ __launch_bounds__(64) void k_cell_sort(ListDev Lst) {
+  const int c = blockIdx.x;
+  const int lo = Lst.cell_start[c], hi = Lst.cell_start[c + 1];
+  for (int e = lo + (int)threadIdx.x; e < hi; e += 64) {
+    const int v = Lst.cell_unsorted[e];
+    int rank = 0;
+    for (int a = lo; a < hi; ++a) rank += Lst.cell_unsorted[a] < v;
+    Lst.cell_atoms[lo + rank] = v;
   }
 }
 
 // Verlet lists at the frame-0 midpoints: every (j, image) with
-// |x_j + n L - x_i| < r_list, scanned over the 27 neighbouring cells.
+// |x_j + n L - x_i| < r_list.  One block per (cell, group of NL_IPB atoms of
+// that cell): the candidates of the 27 neighbouring cells (ascending atom
+// order per cell, fixed cell order) are staged in LDS in chunks; each wave
+// tests one i-atom against 64 candidates at a time with the exact binary64
+// predicate and appends the hits in candidate order by ballot compaction, so
+// list rows are written contiguously (atom-major layout [i][m]).
+#define NL_IPB 32
+#define NL_CH 512
 __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev W) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= S.n) return;
-  const int r = S.atom_rep[i];
-  const double L = S.box[r];
+  __shared__ float4 s_x[NL_CH];
+  __shared__ uint32_t s_e[NL_CH];
+  __shared__ int s_pre[28];
+  __shared__ int s_cstart[27];
+  __shared__ int s_code[27];
+  const int c = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int r = Lst.cell_rep[c];
   const int nc = Lst.rep_nc[r];
   const int coff = Lst.rep_cell_off[r];
-  const float4 xi = W.qmid[i];
-  int c = Lst.atom_cell[i] - coff;
-  const int cx = c % nc, cy = (c / nc) % nc, cz = c / (nc * nc);
-  int nt = 0, nd = 0;
-  for (int oz = -1; oz <= 1; ++oz) {
-    int tz = cz + oz, nz = 0;
+  const int lo = Lst.cell_start[c], hi = Lst.cell_start[c + 1];
+  const int occ = hi - lo;
+  const int ib = blockIdx.y * NL_IPB;
+  if (blockIdx.y == 0 && t == 0 && occ > Lst.cell_cap) atomicOr(Lst.status, LSD_STATUS_CELL);
+  if (ib >= occ) return;
+  const int ie = min(occ, ib + NL_IPB);
+  const double L = S.box[r];
+  if (t < 27) {
+    const int cl = c - coff;
+    const int cx = cl % nc, cy = (cl / nc) % nc, cz = cl / (nc * nc);
+    const int ox = t % 3 - 1, oy = (t / 3) % 3 - 1, oz = t / 9 - 1;
+    int tx = cx + ox, ty = cy + oy, tz = cz + oz, nx = 0, ny = 0, nz = 0;
+    if (tx < 0) { tx += nc; nx = -1; } else if (tx >= nc) { tx -= nc; nx = 1; }
+    if (ty < 0) { ty += nc; ny = -1; } else if (ty >= nc) { ty -= nc; ny = 1; }
     if (tz < 0) { tz += nc; nz = -1; } else if (tz >= nc) { tz -= nc; nz = 1; }
-    for (int oy = -1; oy <= 1; ++oy) {
-      int ty = cy + oy, ny = 0;
-      if (ty < 0) { ty += nc; ny = -1; } else if (ty >= nc) { ty -= nc; ny = 1; }
-      for (int ox = -1; ox <= 1; ++ox) {
-        int tx = cx + ox, nx = 0;
-        if (tx < 0) { tx += nc; nx = -1; } else if (tx >= nc) { tx -= nc; nx = 1; }
-        const int code = (nx + 1) + 3 * (ny + 1) + 9 * (nz + 1);
-        const int cell = coff + tx + nc * (ty + nc * tz);
-        const int lo = Lst.cell_start[cell], hi = Lst.cell_start[cell + 1];
-        for (int a = lo; a < hi; ++a) {
-          const int j = Lst.cell_atoms[a];
-          if (j == i && code == 13) continue;
-          const float4 xj = W.qmid[j];
-          double dx = ((double)xj.x - (double)xi.x) + (double)nx * L;
-          double dy = ((double)xj.y - (double)xi.y) + (double)ny * L;
-          double dz = ((double)xj.z - (double)xi.z) + (double)nz * L;
-          double d2 = dx * dx + dy * dy + dz * dz;
-          const uint32_t e = ((uint32_t)j << 5) | (uint32_t)code;
-          if (d2 < Lst.rl2_t) {
-            if (nt < Lst.mt) Lst.nbr_t[(size_t)nt * S.n + i] = e;
-            ++nt;
-          }
-          if (d2 < Lst.rl2_d) {
-            if (nd < Lst.md) Lst.nbr_d[(size_t)nd * S.n + i] = e;
-            ++nd;
+    const int cell = coff + tx + nc * (ty + nc * tz);
+    s_cstart[t] = Lst.cell_start[cell];
+    s_pre[t + 1] = Lst.cell_start[cell + 1] - Lst.cell_start[cell];
+    s_code[t] = (nx + 1) + 3 * (ny + 1) + 9 * (nz + 1);
+  }
+  __syncthreads();
+  if (t == 0) {
+    s_pre[0] = 0;
+    for (int q = 0; q < 27; ++q) s_pre[q + 1] += s_pre[q];
+  }
+  __syncthreads();
+  const int total = s_pre[27];
+  // this wave's i-atoms: ib + wave, ib + wave + 4, ... (at most NL_IPB / 4)
+  constexpr int PER = NL_IPB / 4;
+  int ia[PER], nt[PER], nd[PER];
+  float4 xi[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = ib + wave + 4 * u;
+    ia[u] = e < ie ? Lst.cell_atoms[lo + e] : -1;
+    xi[u] = ia[u] >= 0 ? W.qmid[ia[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+    nt[u] = 0;
+    nd[u] = 0;
+  }
+  for (int cb = 0; cb < total; cb += NL_CH) {
+    const int cn = min(NL_CH, total - cb);
+    __syncthreads();
+    for (int k = t; k < cn; k += 256) {
+      const int idx = cb + k;
+      int q = 0;
+      while (s_pre[q + 1] <= idx) ++q;
+      const int j = Lst.cell_atoms[s_cstart[q] + (idx - s_pre[q])];
+      s_x[k] = W.qmid[j];
+      s_e[k] = ((uint32_t)j << 5) | (uint32_t)s_code[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      if (ia[u] < 0) continue;  // uniform per wave
+      const int i = ia[u];
+      uint32_t* rowt = Lst.nbr_t + (size_t)i * Lst.mt;
+      uint32_t* rowd = Lst.nbr_d + (size_t)i * Lst.md;
+      for (int k0 = 0; k0 < cn; k0 += 64) {
+        const int k = k0 + lane;
+        bool ht = false, hd = false;
+        uint32_t ent = 0;
+        if (k < cn) {
+          ent = s_e[k];
+          const int j = (int)(ent >> 5), code = (int)(ent & 31u);
+          if (!(j == i && code == 13)) {
+            const float4 xj = s_x[k];
+            double dx = ((double)xj.x - (double)xi[u].x) + (double)code_nx(code) * L;
+            double dy = ((double)xj.y - (double)xi[u].y) + (double)code_ny(code) * L;
+            double dz = ((double)xj.z - (double)xi[u].z) + (double)code_nz(code) * L;
+            double d2 = dx * dx + dy * dy + dz * dz;
+            ht = d2 < Lst.rl2_t;
+            hd = d2 < Lst.rl2_d;
           }
         }
+        const unsigned long long bt = __ballot(ht), bd = __ballot(hd);
+        const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        if (ht) {
+          const int pos = nt[u] + __popcll(bt & below);
+          if (pos < Lst.mt) rowt[pos] = ent;
+        }
+        if (hd) {
+          const int pos = nd[u] + __popcll(bd & below);
+          if (pos < Lst.md) rowd[pos] = ent;
+        }
+        nt[u] += __popcll(bt);
+        nd[u] += __popcll(bd);
       }
     }
   }
-  if (nt > Lst.mt) { atomicOr(Lst.status, LSD_STATUS_NBR_TARGET); nt = Lst.mt; }
-  if (nd > Lst.md) { atomicOr(Lst.status, LSD_STATUS_NBR_DRAFT); nd = Lst.md; }
-  Lst.cnt_t[i] = nt;
-  Lst.cnt_d[i] = nd;
+  if (lane == 0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      if (ia[u] < 0) continue;
+      int a = nt[u], b = nd[u];
+      if (a > Lst.mt) { atomicOr(Lst.status, LSD_STATUS_NBR_TARGET); a = Lst.mt; }
+      if (b > Lst.md) { atomicOr(Lst.status, LSD_STATUS_NBR_DRAFT); b = Lst.md; }
+      Lst.cnt_t[ia[u]] = a;
+      Lst.cnt_d[ia[u]] = b;
+    }
+  }
 }
 
-// Force of potential P on atom i at frame positions X using list (nbr, cnt).
-__device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S, const float4* __restrict__ X,
-                                          const uint32_t* __restrict__ nbr, int cnt, int i, int r,
-                                          float& fx, float& fy, float& fz, float& e) {
+__device__ __forceinline__ float lpa_sum(float v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  return v;
+}
+
+// Force of potential P on atom i at frame positions X.  The LSD_LPA lanes of
+// an atom share the list row: lane `sub` sums the entries m = sub, sub + LPA,
+// ... in order, and the partial sums are combined by the fixed butterfly of
+// lpa_sum, so every kernel that uses this pattern obtains bit-identical
+// forces for identical positions and lists.
+__device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
+                                          const float4* __restrict__ X,
+                                          const uint32_t* __restrict__ row, int cnt, int i, int r,
+                                          int sub, float& fx, float& fy, float& fz, float& e) {
   fx = fy = fz = e = 0.0f;
   const double L = S.box[r];
   const float Lf = (float)L;
   const float4 xi = X[i];
   if (P.kind == LSD_POT_LJ) {
-    for (int m = 0; m < cnt; ++m) {
-      const uint32_t ent = nbr[(size_t)m * S.n + i];
+    for (int m = sub; m < cnt; m += LSD_LPA) {
+      const uint32_t ent = row[m];
       const int j = (int)(ent >> 5), code = (int)(ent & 31u);
       const float4 xj = X[j];
-      lj_pair(P, xi, xj, (float)code_nx(code) * Lf, (float)code_ny(code) * Lf,
-              (float)code_nz(code) * Lf, code, L, fx, fy, fz, e);
+      float sj[3], si[3];
+      image_shifts(code, Lf, sj, si);
+      lj_pair(P, xi, xj, sj, si, code, L, fx, fy, fz, e);
     }
+    fx = lpa_sum(fx);
+    fy = lpa_sum(fy);
+    fz = lpa_sum(fz);
+    e = lpa_sum(e);
   } else if (P.kind == LSD_POT_HARMONIC) {
     float d[3] = {xi.x - P.anchor[i], xi.y - P.anchor[S.n + i], xi.z - P.anchor[2 * S.n + i]};
 #pragma unroll
@@ -219,20 +306,30 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S, cons
 // One draft_step (Alg. 2) for frame k: draft forces at the midpoint, the
 // (BOB) Gaussian draw of Eq. bob, then the two position half steps that end
 // this step and start the next one; flags the next frame invalid when an
-// atom left the skin of the lists.
+// atom left the skin of the lists.  LSD_LPA lanes per atom.
 __global__ __launch_bounds__(256) void k_draft(SysDev S, ListDev Lst, WinDev W, PotDev P, int k,
                                                int use_target_list) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= S.n) return;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i0 = gt / LSD_LPA, sub = gt % LSD_LPA;
+  const bool in = i0 < S.n;
+  const int i = in ? i0 : S.n - 1;
   const int r = S.atom_rep[i];
+  int* inv = W.invalid + (size_t)r * S.kmax;
+  if (inv[k]) {
+    // frames from K_eff on are discarded: no work, and the next frame is
+    // invalid as well (one thread per replica records it)
+    if (in && sub == 0 && i == S.rep_off[r] && k + 1 < W.K) inv[k + 1] = 1;
+    return;
+  }
   const int sp = S.species ? S.species[i] : 0;
   const size_t N = (size_t)S.n;
   const float4* X = W.qmid + (size_t)k * N;
   float F[3], e;
   if (use_target_list)
-    pot_force(P, S, X, Lst.nbr_t, Lst.cnt_t[i], i, r, F[0], F[1], F[2], e);
+    pot_force(P, S, X, Lst.nbr_t + (size_t)i * Lst.mt, Lst.cnt_t[i], i, r, sub, F[0], F[1], F[2], e);
   else
-    pot_force(P, S, X, Lst.nbr_d, Lst.cnt_d[i], i, r, F[0], F[1], F[2], e);
+    pot_force(P, S, X, Lst.nbr_d + (size_t)i * Lst.md, Lst.cnt_d[i], i, r, sub, F[0], F[1], F[2], e);
+  if (!in || sub != 0) return;
 
   double xi[3];
   if (S.replay_xi) {
@@ -277,8 +374,7 @@ __global__ __launch_bounds__(256) void k_draft(SysDev S, ListDev Lst, WinDev W, 
       dd[d] -= Lf * rintf(dd[d] / Lf);
       d2 += dd[d] * dd[d];
     }
-    int* inv = W.invalid + (size_t)r * S.kmax;
-    if (d2 > S.half_skin2 || inv[k] != 0) atomicOr(&inv[k + 1], 1);
+    if (d2 > S.half_skin2 && inv[k + 1] == 0) atomicOr(&inv[k + 1], 1);
   }
 }
 
@@ -290,6 +386,9 @@ __global__ __launch_bounds__(256) void k_frame_validity(SysDev S, WinDev W) {
   const float Lf = (float)S.box[r];
   const float4 x0 = W.qmid[i];
   int* inv = W.invalid + (size_t)r * S.kmax;
+  if (i == S.rep_off[r])
+    for (int k = 0; k < W.K; ++k)
+      if (S.step[r] + k + 1 > S.step_limit) inv[k] = 1;
   for (int k = 1; k < W.K; ++k) {
     const float4 x = W.qmid[(size_t)k * S.n + i];
     float dd[3] = {x.x - x0.x, x.y - x0.y, x.z - x0.z};
@@ -305,93 +404,127 @@ __global__ __launch_bounds__(256) void k_frame_validity(SysDev S, WinDev W) {
   }
 }
 
-// verify_step (Alg. 2) for every valid frame of the window.  Block = one
-// tile of up to 64 atoms of one replica x `fpb` frames; wave w of the block
-// handles frames f0 + w, f0 + w + 4, ...  The tile's neighbour entries are
-// read from HBM once into LDS and reused by all frames of the block.
+// verify_step (Alg. 2) for the valid frames of the window.  Block = one tile
+// of up to 64 atoms of one replica x FW frames.  The tile's neighbour rows
+// are read once into LDS; each atom uses LSD_LPA lanes (same entry split and
+// butterfly as the draft kernel) and each lane advances all FW frames per
+// neighbour entry, so an entry is decoded once and its image shift reused.
 // Epilogue per atom and frame (binary64):
 //   z = (p~_k - <p~_k>) / sigma,  delta = c1 (F~_k - F_k) / sigma
-// summed over the tile with a wavefront butterfly: S1 = delta.z,
-// S2 = delta.delta, plus the potential energy.
+// reduced over the tile in a fixed order: S1 = delta.z, S2 = delta.delta,
+// and the potential energy.
+#define VROW 65  // LDS row stride (words) of the staged neighbour tile
+template <int FW>
 __global__ __launch_bounds__(256) void k_verify(SysDev S, ListDev Lst, WinDev W, TileDev Tl,
-                                                PotDev P, int fpb) {
-  extern __shared__ uint32_t s_nbr[];  // [mt][64]
-  __shared__ float s_shift[27][3];
+                                                PotDev P) {
+  extern __shared__ uint32_t s_nbr[];  // [mt][VROW]
+  __shared__ float s_shift[27][6];
+  __shared__ double s_red[4][FW][3];
   const int tile = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int a = t / LSD_LPA, sub = t % LSD_LPA;
   const int start = Tl.start[tile], count = Tl.count[tile], r = Tl.rep[tile];
+  const int* inv = W.invalid + (size_t)r * S.kmax;
+  const int f0 = blockIdx.y * FW;
+  bool valid[FW];
+  bool any = false;
+#pragma unroll
+  for (int f = 0; f < FW; ++f) {
+    valid[f] = (f0 + f < W.K) && inv[f0 + f] == 0;
+    any = any || valid[f];
+  }
+  if (!any) return;  // uniform over the block
   const double L = S.box[r];
   const float Lf = (float)L;
   const size_t N = (size_t)S.n;
-  const int i = start + lane;
-  const bool active = lane < count;
-  if (threadIdx.x < 27) {
-    int c = threadIdx.x;
-    s_shift[c][0] = (float)code_nx(c) * Lf;
-    s_shift[c][1] = (float)code_ny(c) * Lf;
-    s_shift[c][2] = (float)code_nz(c) * Lf;
+  const bool lj = P.kind == LSD_POT_LJ;
+  if (t < 27) image_shifts(t, Lf, &s_shift[t][0], &s_shift[t][3]);
+  // stage the rows of the tile: wave w copies atoms w, w+4, ...; 64
+  // consecutive entries of one row per instruction
+  if (lj) {
+    for (int aa = wave; aa < count; aa += 4) {
+      const int ci = Lst.cnt_t[start + aa];
+      const uint32_t* row = Lst.nbr_t + (size_t)(start + aa) * Lst.mt;
+      for (int m = lane; m < ci; m += 64) s_nbr[m * VROW + aa] = row[m];
+    }
   }
-  const int cnt = active ? Lst.cnt_t[i] : 0;
-  const int maxcnt = wave_max(cnt);
-  for (int m = wave; m < maxcnt; m += 4)
-    s_nbr[m * 64 + lane] = active ? Lst.nbr_t[(size_t)m * N + i] : 0u;
   __syncthreads();
 
-  const int f0 = blockIdx.y * fpb;
-  const int f1 = min(f0 + fpb, W.K);
-  const int* inv = W.invalid + (size_t)r * S.kmax;
-  const int sp = (active && S.species) ? S.species[i] : 0;
-  for (int f = f0 + wave; f < f1; f += 4) {
-    if (inv[f]) continue;  // frame beyond the valid prefix: not verified
-    const float4* X = W.qmid + (size_t)f * N;
-    float fx = 0.0f, fy = 0.0f, fz = 0.0f, e = 0.0f;
-    if (active) {
-      const float4 xi = X[i];
-      if (P.kind == LSD_POT_LJ) {
-        for (int m = 0; m < cnt; ++m) {
-          const uint32_t ent = s_nbr[m * 64 + lane];
-          const int j = (int)(ent >> 5), code = (int)(ent & 31u);
-          const float4 xj = X[j];
-          lj_pair(P, xi, xj, s_shift[code][0], s_shift[code][1], s_shift[code][2], code, L, fx,
-                  fy, fz, e);
-        }
-        if (P.offset) {
-          fx += P.offset[i];
-          fy += P.offset[N + i];
-          fz += P.offset[2 * N + i];
-        }
-      } else {
-        pot_force(P, S, X, Lst.nbr_t, cnt, i, r, fx, fy, fz, e);
-      }
-    }
-    double s1 = 0.0, s2 = 0.0;
-    if (active) {
-      const float Ft[3] = {fx, fy, fz};
-      const float* pk = W.p + (size_t)f * 3 * N;
-      const float* pk1 = W.p + (size_t)(f + 1) * 3 * N;
-      const float* fdk = W.fd + (size_t)f * 3 * N;
-      float* ftk = W.ft + (size_t)f * 3 * N;
-      const double isg = 1.0 / S.sig[sp];
+  const bool active = a < count;
+  const int i = start + (active ? a : 0);
+  const int cnt = (active && lj) ? Lst.cnt_t[i] : 0;
+  float fx[FW], fy[FW], fz[FW], en[FW];
+  float4 xi[FW];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const float Fd = fdk[d * N + i];
-        ftk[d * N + i] = Ft[d];
-        const double mud = bob_mean(S.a, S.c1fu, pk[d * N + i], Fd);
-        const double z = ((double)pk1[d * N + i] - mud) * isg;
-        const double dl = S.c1fu * ((double)Fd - (double)Ft[d]) * isg;
-        s1 = fma(dl, z, s1);
-        s2 = fma(dl, dl, s2);
+  for (int f = 0; f < FW; ++f) {
+    fx[f] = fy[f] = fz[f] = en[f] = 0.0f;
+    xi[f] = valid[f] ? W.qmid[(size_t)(f0 + f) * N + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  for (int m = sub; m < cnt; m += LSD_LPA) {
+    const uint32_t ent = s_nbr[m * VROW + a];
+    const int j = (int)(ent >> 5), code = (int)(ent & 31u);
+    const float* sh = s_shift[code];
+#pragma unroll
+    for (int f = 0; f < FW; ++f) {
+      if (!valid[f]) continue;
+      const float4 xj = W.qmid[(size_t)(f0 + f) * N + j];
+      lj_pair(P, xi[f], xj, sh, sh + 3, code, L, fx[f], fy[f], fz[f], en[f]);
+    }
+  }
+  const int sp = (active && S.species) ? S.species[i] : 0;
+  const double isg = 1.0 / S.sig[sp];
+#pragma unroll
+  for (int f = 0; f < FW; ++f) {
+    double s1 = 0.0, s2 = 0.0, es = 0.0;
+    if (valid[f]) {
+      float Ft[3], e;
+      if (lj) {
+        Ft[0] = lpa_sum(fx[f]);
+        Ft[1] = lpa_sum(fy[f]);
+        Ft[2] = lpa_sum(fz[f]);
+        e = lpa_sum(en[f]);
+      } else {
+        pot_force(P, S, W.qmid + (size_t)(f0 + f) * N, nullptr, 0, i, r, sub, Ft[0], Ft[1], Ft[2], e);
+      }
+      if (lj && P.offset) {
+        Ft[0] += P.offset[i];
+        Ft[1] += P.offset[N + i];
+        Ft[2] += P.offset[2 * N + i];
+      }
+      if (active && sub == 0) {
+        const int fr = f0 + f;
+        const float* pk = W.p + (size_t)fr * 3 * N;
+        const float* pk1 = W.p + (size_t)(fr + 1) * 3 * N;
+        const float* fdk = W.fd + (size_t)fr * 3 * N;
+        float* ftk = W.ft + (size_t)fr * 3 * N;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const float Fd = fdk[d * N + i];
+          ftk[d * N + i] = Ft[d];
+          const double mud = bob_mean(S.a, S.c1fu, pk[d * N + i], Fd);
+          const double z = ((double)pk1[d * N + i] - mud) * isg;
+          const double dl = S.c1fu * ((double)Fd - (double)Ft[d]) * isg;
+          s1 = fma(dl, z, s1);
+          s2 = fma(dl, dl, s2);
+        }
+        es = (double)e;
       }
     }
     s1 = wave_sum(s1);
     s2 = wave_sum(s2);
-    const double es = wave_sum((double)e);
+    es = wave_sum(es);
     if (lane == 0) {
-      double* out = W.partial + ((size_t)f * S.n_tiles + tile) * 4;
-      out[0] = s1;
-      out[1] = s2;
-      out[2] = es;
+      s_red[wave][f][0] = s1;
+      s_red[wave][f][1] = s2;
+      s_red[wave][f][2] = es;
     }
+  }
+  __syncthreads();
+  if (t < FW && valid[t]) {
+    double* out = W.partial + ((size_t)(f0 + t) * S.n_tiles + tile) * 4;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      out[q] = ((s_red[0][t][q] + s_red[1][t][q]) + s_red[2][t][q]) + s_red[3][t][q];
   }
 }
 
@@ -403,7 +536,7 @@ __global__ __launch_bounds__(64) void k_decide(SysDev S, WinDev W, TileDev Tl, O
   const int K = W.K;
   const int* inv = W.invalid + (size_t)r * S.kmax;
   int keff = K;
-  for (int f = 1; f < K; ++f)
+  for (int f = 0; f < K; ++f)
     if (inv[f]) { keff = f; break; }
   const int t0 = Tl.rep_tile_off[r], t1 = Tl.rep_tile_off[r + 1];
   int j = keff, reflected = 0;
@@ -446,6 +579,11 @@ __global__ __launch_bounds__(64) void k_decide(SysDev S, WinDev W, TileDev Tl, O
     }
   }
   if (lane == 0) {
+    long long* cn = W.counters + (size_t)r * 4;
+    cn[0] += 1;
+    cn[1] += j;
+    cn[2] += reflected;
+    cn[3] += plain ? 0 : keff;
     O.n_committed[r] = j;
     W.commit_frame[r] = j - 1;
     W.reflected[r] = reflected;
@@ -464,6 +602,7 @@ __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __res
   const int sp = S.species ? S.species[i] : 0;
   const size_t N = (size_t)S.n;
   const int f = W.commit_frame[r];
+  if (f < 0) return;  // nothing committed in this window (step limit reached)
   const float4 x = W.qmid[(size_t)f * N + i];
   int dimg[3];
   unpack_img(x.w, dimg);
@@ -516,6 +655,17 @@ __global__ void k_rng_uniforms(uint64_t seed, int replica, int64_t step0, int co
 // ---------------------------------------------------------------------------
 static inline int blocks_for(int n, int b) { return (n + b - 1) / b; }
 
+__global__ void k_zero_i64(long long* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+hipError_t launch_zero_i64(long long* p, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i64, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, v, n);
@@ -535,15 +685,17 @@ hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W
     hipLaunchKernelGGL(k_bin_frame0, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, L, W);
   hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, L);
   hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S.n, L);
-  hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(L.n_cells, 256)), dim3(256), 0, st, L);
-  hipLaunchKernelGGL(k_nl_build, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, L, W);
+  hipLaunchKernelGGL(k_cell_sort, dim3(L.n_cells), dim3(64), 0, st, L);
+  dim3 grid(L.n_cells, (L.cell_cap + NL_IPB - 1) / NL_IPB);
+  hipLaunchKernelGGL(k_nl_build, grid, dim3(256), 0, st, S, L, W);
   return hipGetLastError();
 }
 
 hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P, int k,
                         int use_target_list, hipStream_t st) {
-  hipLaunchKernelGGL(k_draft, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, L, W, P, k,
-                     use_target_list);
+  const long long threads = (long long)S.n * LSD_LPA;
+  hipLaunchKernelGGL(k_draft, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, S, L, W, P,
+                     k, use_target_list);
   return hipGetLastError();
 }
 
@@ -552,17 +704,30 @@ hipError_t launch_frame_validity(const SysDev& S, const WinDev& W, hipStream_t s
   return hipGetLastError();
 }
 
+static size_t verify_lds(int mt) { return (size_t)mt * VROW * sizeof(uint32_t); }
+
 hipError_t prepare_verify(int mt) {
-  size_t lds = (size_t)mt * 64 * sizeof(uint32_t);
-  return hipFuncSetAttribute((const void*)k_verify, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+  const int lds = (int)verify_lds(mt);
+  hipError_t e = hipFuncSetAttribute((const void*)k_verify<1>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_verify<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_verify<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  return e;
 }
 
+// frames per wave: 4 for long windows; fewer when the window is short
 hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
-                         const PotDev& P, int fpb, hipStream_t st) {
-  size_t lds = (size_t)L.mt * 64 * sizeof(uint32_t);
-  dim3 grid(S.n_tiles, (W.K + fpb - 1) / fpb);
-  hipLaunchKernelGGL(k_verify, grid, dim3(256), lds, st, S, L, W, T, P, fpb);
+                         const PotDev& P, int fw, hipStream_t st) {
+  const size_t lds = verify_lds(L.mt);
+  if (fw >= 4) {
+    hipLaunchKernelGGL(k_verify<4>, dim3(S.n_tiles, (W.K + 3) / 4), dim3(256), lds, st, S, L, W, T, P);
+  } else if (fw == 2) {
+    hipLaunchKernelGGL(k_verify<2>, dim3(S.n_tiles, (W.K + 1) / 2), dim3(256), lds, st, S, L, W, T, P);
+  } else {
+    hipLaunchKernelGGL(k_verify<1>, dim3(S.n_tiles, W.K), dim3(256), lds, st, S, L, W, T, P);
+  }
   return hipGetLastError();
 }
 

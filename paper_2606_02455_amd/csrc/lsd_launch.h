@@ -4,6 +4,7 @@
 #include "lsd_device.h"
 
 hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
+hipError_t launch_zero_i64(long long* p, int n, hipStream_t st);
 hipError_t launch_window_start(const SysDev& S, const ListDev& L, const WinDev& W, const float* q,
                                const float* p, hipStream_t st);
 hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W, bool bin_frame0,
@@ -13,7 +14,7 @@ hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, cons
 hipError_t launch_frame_validity(const SysDev& S, const WinDev& W, hipStream_t st);
 hipError_t prepare_verify(int mt);
 hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
-                         const PotDev& P, int fpb, hipStream_t st);
+                         const PotDev& P, int fw, hipStream_t st);
 hipError_t launch_decide(const SysDev& S, const WinDev& W, const TileDev& T, const OutDev& O,
                          int plain, hipStream_t st);
 hipError_t launch_commit(const SysDev& S, const WinDev& W, float* q, float* p, int* img,

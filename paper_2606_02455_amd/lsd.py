@@ -72,6 +72,9 @@ EXPORTS = {
     "lsd_run_windows": ([C.c_void_p, C.c_int32, C.c_int32, C.c_void_p], C.c_int),
     "lsd_get_window_layout": ([C.c_void_p, C.POINTER(WindowLayout)], C.c_int),
     "lsd_get_status": ([C.c_void_p, C.POINTER(C.c_int32), C.c_void_p], C.c_int),
+    "lsd_set_step_limit": ([C.c_void_p, C.c_int64], C.c_int),
+    "lsd_get_counters": ([C.c_void_p, C.POINTER(C.c_int64), C.c_void_p], C.c_int),
+    "lsd_reset_counters": ([C.c_void_p, C.c_void_p], C.c_int),
     "lsd_set_verify_timing": ([C.c_void_p, C.c_int32], C.c_int),
     "lsd_get_verify_timing": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "lsd_rng_normals": ([C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p],
@@ -267,7 +270,7 @@ class LSDSystem:
         )
 
     def neighbor_lists(self, which="target"):
-        """(counts [N], entries [width, N] as int64 j << 5 | image code)."""
+        """(counts [N], entries [N, width] as int32 j << 5 | image code)."""
         t, L, N = self.torch, self.layout, self.N
         ws = self.workspace
         if which == "target":
@@ -275,13 +278,39 @@ class LSDSystem:
         else:
             off, coff, m = L.nbr_draft, L.cnt_draft, L.max_neighbors_draft
         cnt = ws[coff:coff + 4 * N].view(t.int32).clone()
-        ent = ws[off:off + 4 * m * N].view(t.int32).view(m, N).clone()
+        ent = ws[off:off + 4 * m * N].view(t.int32).view(N, m).clone()
         return cnt, ent
 
     def status(self):
         f = C.c_int32()
         _check(load().lsd_get_status(self.h, C.byref(f), _stream(self.torch)), "lsd_get_status")
         return int(f.value)
+
+    def set_step_limit(self, limit):
+        """Stop every replica exactly at step `limit` (None: no limit)."""
+        lim = (1 << 63) - 1 if limit is None else int(limit)
+        _check(load().lsd_set_step_limit(self.h, lim), "lsd_set_step_limit")
+
+    def run_to_step(self, n_steps, K, check_every=16, max_windows=100000):
+        """Windows of K frames until every replica has committed exactly
+        n_steps steps."""
+        self.set_step_limit(n_steps)
+        done = 0
+        while done < max_windows:
+            self.run_windows(check_every, K)
+            done += check_every
+            if int(self.state()["step"].min()) >= n_steps:
+                return done
+        raise RuntimeError("run_to_step did not reach the step count")
+
+    def counters(self):
+        """int64 [R, 4]: windows, committed steps, rejections, frames verified."""
+        out = (C.c_int64 * (4 * self.R))()
+        _check(load().lsd_get_counters(self.h, out, _stream(self.torch)), "lsd_get_counters")
+        return np.array(out[:], dtype=np.int64).reshape(self.R, 4)
+
+    def reset_counters(self):
+        _check(load().lsd_reset_counters(self.h, _stream(self.torch)), "lsd_reset_counters")
 
     def set_verify_timing(self, on=True):
         _check(load().lsd_set_verify_timing(self.h, 1 if on else 0), "lsd_set_verify_timing")

@@ -108,6 +108,36 @@ def lj_fluid(n_side: int, rho: float = 0.8, kT: float = 1.0, jitter: float = 0.0
         draft=dict(kind="lj", rc=rc_draft, eps=1.0, sig=1.0), skin=skin)
 
 
+def lj_replicas(sides, rho: float = 0.8, seed: int = 100, K: int = 8, **kw) -> Workload:
+    """Independent Lennard-Jones systems of side^3 atoms each (one box per
+    replica, same density), concatenated as one batch of replicas."""
+    parts = [lj_fluid(int(n), rho=rho, seed=seed + r, K=K, **kw) for r, n in enumerate(sides)]
+    offs = np.cumsum([0] + [w.n_atoms for w in parts]).astype(np.int32)
+    w0 = parts[0]
+    return Workload(
+        name=f"lj_replicas{len(parts)}", positions=np.concatenate([w.positions for w in parts]),
+        momenta=np.concatenate([w.momenta for w in parts]),
+        species=np.zeros(int(offs[-1]), np.int32), species_mass=np.array([1.0]), atom_offsets=offs,
+        box=np.array([w.box[0] for w in parts]), dt=w0.dt, gamma=w0.gamma, kT=w0.kT,
+        force_unit=1.0, K=K, n_steps=w0.n_steps, seed=seed, target=dict(w0.target),
+        draft=dict(w0.draft), skin=w0.skin)
+
+
+def tether_replicas(n_replicas: int, k: float = 2.0, m: float = 1.0, dt: float = 0.2,
+                    gamma: float = 2.0, kT: float = 1.0, L: float = 1000.0, K: int = 4,
+                    seed: int = 7) -> Workload:
+    """Independent one-atom systems on harmonic tethers at the box centre,
+    starting at rest on their anchors."""
+    n = n_replicas
+    pos = np.full((n, 3), L / 2)
+    return Workload(
+        name=f"tether{n}", positions=pos, momenta=np.zeros((n, 3)), species=np.zeros(n, np.int32),
+        species_mass=np.array([m]), atom_offsets=np.arange(n + 1, dtype=np.int32),
+        box=np.full(n, L), dt=dt, gamma=gamma, kT=kT, force_unit=1.0, K=K, n_steps=100,
+        seed=seed, target=dict(kind="harmonic", k=k, anchor=pos.copy()),
+        draft=dict(kind="harmonic", k=k, anchor=pos.copy()), skin=0.3)
+
+
 # --- triatomic liquid (molecular units: Angstrom, amu, fs, eV) -------------
 TRIATOMIC_MASSES = np.array([1.008, 12.011, 15.999])   # H-like, C-like, O-like
 TRIATOMIC_BONDS = (1.1, 1.2)                            # A-B, B-C in Angstrom

@@ -1,0 +1,127 @@
+"""GPU statistical checks of the committed trajectories (target-distributed
+marginals, Thm. 1; closed-form rejection rate, Eq. rejection_rate).
+
+These run the whole HIP path (draft, one-launch verify, decide, commit) over
+many independent replicas batched in one system and test the resulting
+samples against exact laws or against plain target Langevin on the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+from scipy import special, stats
+
+from paper_2606_02455_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def lsd(torch):
+    from paper_2606_02455_amd import lsd as L
+    L.load()
+    return L
+
+
+def _run_until(sysg, n_steps, K):
+    # stop every replica exactly at n_steps: a fixed number of windows would
+    # stop at window ends, which follow rejections and are not target-distributed
+    sysg.run_to_step(n_steps, K, check_every=8)
+    assert (sysg.state()["step"] == n_steps).all()
+
+
+def test_harmonic_replicas_follow_exact_target_law(torch, lsd):
+    _say("harmonic replicas KS")
+    kT_, kD = 2.0, 1.0
+    w = W.tether_replicas(3000, k=kT_, dt=0.2, gamma=2.0, kT=1.0, K=4, seed=31)
+    anchor = w.positions.copy()
+    draft = dict(kind="harmonic", k=kD, anchor=anchor)
+    g = lsd.LSDSystem(w, mode="lsd", draft=draft)
+    _run_until(g, 60, 4)
+    st = g.state()
+    cn = g.counters()
+    rate = cn[:, 2].sum() / cn[:, 1].sum()
+    assert 0.05 < rate < 0.95
+    dq = (st["q"] - anchor).ravel()
+    var_p = 1.0 * 1.0 / (1.0 - kT_ * 0.2 ** 2 / 4.0)
+    assert stats.kstest(dq / np.sqrt(1.0 / kT_), "norm").pvalue > 0.01
+    assert stats.kstest(st["p"].ravel() / np.sqrt(var_p), "norm").pvalue > 0.01
+    g.destroy()
+    # the draft alone samples a different law: the same test must reject it
+    d = lsd.LSDSystem(w, mode="plain", target=draft)
+    _run_until(d, 60, 4)
+    sd = d.state()
+    assert stats.kstest((sd["q"] - anchor).ravel() / np.sqrt(1.0 / kT_), "norm").pvalue < 1e-4
+    d.destroy()
+
+
+def test_offset_draft_rejection_rate_matches_closed_form(torch, lsd):
+    _say("offset draft acceptance")
+    w = W.config("c1")
+    rng = np.random.default_rng(5)
+    b = rng.normal(size=(w.n_atoms, 3))
+    sig = np.sqrt(1.0 * w.kT * (1 - np.exp(-2 * w.gamma * w.dt)))
+    c1 = (1 + np.exp(-w.gamma * w.dt)) * w.dt / 2
+    b *= 0.9 / np.linalg.norm(c1 * b / sig)        # |delta| = 0.9 at every state
+    b = W.f32(b)
+    dnorm = np.linalg.norm(c1 * b / sig)
+    draft = dict(w.target)
+    draft["offset"] = b
+    g = lsd.LSDSystem(w, mode="lsd", draft=draft)
+    g.run_windows(600, w.K)
+    cn = g.counters()[0]
+    committed, rejections = int(cn[1]), int(cn[2])
+    beta = special.erf(dnorm / np.sqrt(8.0))
+    sd = np.sqrt(beta * (1 - beta) / committed)
+    assert abs(rejections / committed - beta) < 4 * sd, (rejections / committed, beta)
+    assert g.status() == 0
+    g.destroy()
+
+
+def _lj_observables(ora, w, st):
+    Ek, Ep = [], []
+    for r in range(w.n_replicas):
+        sl = w.replica_slice(r)
+        p = st["p"][sl]
+        Ek.append(0.5 * (p ** 2).sum() / (1.5 * p.shape[0]))   # kinetic temperature 2K/(3N)
+        Ep.append(ora.energy_forces(ora.Potential.lj(2.5), st["q"][sl], float(w.box[r]))[0] / p.shape[0])
+    return np.array(Ek), np.array(Ep)
+
+
+def test_lj_lsd_marginals_match_plain_target(torch, lsd, ora):
+    _say("LJ LSD vs plain marginals")
+    R = 192
+    a = W.lj_replicas([4] * R, seed=1000, K=8)
+    b = W.lj_replicas([4] * R, seed=5000, K=8)
+    g = lsd.LSDSystem(a, mode="lsd", seed=11)
+    p = lsd.LSDSystem(b, mode="plain", seed=12)
+    _run_until(g, 400, 8)
+    _run_until(p, 400, 8)
+    assert g.status() == 0 and p.status() == 0
+    Tg, Eg = _lj_observables(ora, a, g.state())
+    Tp, Ep = _lj_observables(ora, b, p.state())
+    assert stats.ks_2samp(Tg, Tp).pvalue > 0.01
+    assert stats.ks_2samp(Eg, Ep).pvalue > 0.01
+    for T in (Tg, Tp):
+        assert abs(T.mean() - 1.0) < 4 * T.std() / np.sqrt(len(T))
+    # the short-cutoff draft alone is a different system: the energy test sees it
+    c = W.lj_replicas([4] * R, seed=9000, K=8)
+    d = lsd.LSDSystem(c, mode="plain", seed=13, target=dict(c.draft))
+    _run_until(d, 400, 8)
+    Td, Ed = _lj_observables(ora, c, d.state())
+    assert stats.ks_2samp(Ed, Ep).pvalue < 1e-3
+    for s in (g, p, d):
+        s.destroy()
