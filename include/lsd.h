@@ -178,13 +178,29 @@ LSD_API lsd_status lsd_verify_window(lsd_system *sys, lsd_stream stream);
 LSD_API lsd_status lsd_accept_rollback(lsd_system *sys, int32_t *n_host,
                                lsd_stream stream);
 
-/* Enqueues n_windows x (draft K, verify, accept) without synchronising. */
+/* Enqueues n_windows x (draft K, verify, accept) without synchronising.
+ * By default each window is one launch of a HIP graph (captured once per K
+ * on a library stream, replayed on `stream`); with verification timing on,
+ * the verification kernel runs between the graph parts that precede and
+ * follow it, bracketed by HIP events.  Results are identical either way. */
 LSD_API lsd_status lsd_run_windows(lsd_system *sys, int32_t n_windows, int32_t K,
                            lsd_stream stream);
 
+/* enable != 0 (default): lsd_run_windows replays captured graphs; 0: it
+ * issues the kernels of every window one by one. */
+LSD_API lsd_status lsd_set_graphs(lsd_system *sys, int32_t enable);
+
 /* Byte offsets into the workspace of the window and list arrays (host). */
+/* Window frames: frame 0 holds the first midpoints wrapped into the box
+ * (the neighbour lists and their image codes are built from them); frames
+ * 1..K-1 are continuous with frame 0 (not wrapped), so an atom near a face
+ * may sit up to skin/2 outside [0, L).  The commit wraps positions and
+ * updates the image counters.  Caller-written frames must follow the same
+ * convention; a frame in which an atom moved more than skin/2 from frame 0
+ * (a wrapped jump included) is not verified. */
 typedef struct {
-  size_t q_mid;      /* float4 [k_max][N]: x, y, z, packed image deltas */
+  size_t q_mid;      /* float4 [k_max][N]: x, y, z, packed image deltas of
+                        frame 0 relative to the committed counters */
   size_t p_draft;    /* float [k_max+1][3][N]: committed p, then p~_1..p~_K */
   size_t f_draft;    /* float [k_max][3][N] */
   size_t f_target;   /* float [k_max][3][N] */

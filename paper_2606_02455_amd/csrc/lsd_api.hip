@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -249,6 +250,12 @@ struct TimingRing {
 
 }  // namespace
 
+// Executable graphs of one window, per window length K: the whole window,
+// or (when the verification launch is timed) the parts before and after it.
+struct WindowGraphs {
+  hipGraphExec_t full = nullptr, pre = nullptr, post = nullptr;
+};
+
 struct lsd_system {
   lsd_config cfg;
   lsd_buffers buf;
@@ -265,6 +272,9 @@ struct lsd_system {
   TimingRing ring;
   double t_sum = 0.0;
   int64_t t_count = 0;
+  bool use_graphs = true;
+  hipStream_t cap_stream = nullptr;
+  std::map<int, WindowGraphs> graphs;
 };
 
 namespace {
@@ -289,6 +299,56 @@ lsd_status timing_drain_one(lsd_system* s) {
   s->t_count += 1;
   R.head = (R.head + 1) % kTimingRing;
   R.used -= 1;
+  return LSD_OK;
+}
+
+void destroy_graphs(lsd_system* s) {
+  for (auto& kv : s->graphs) {
+    if (kv.second.full) (void)hipGraphExecDestroy(kv.second.full);
+    if (kv.second.pre) (void)hipGraphExecDestroy(kv.second.pre);
+    if (kv.second.post) (void)hipGraphExecDestroy(kv.second.post);
+  }
+  s->graphs.clear();
+}
+
+enum Part { PART_FULL = 0, PART_PRE = 1, PART_POST = 2 };
+
+// Enqueues the kernels of one window part on `st` (no state checks).
+hipError_t enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
+  const bool plain = s->cfg.mode == LSD_MODE_PLAIN;
+  hipError_t e = hipSuccess;
+  s->W.K = K;
+  if (part == PART_FULL || part == PART_PRE) {
+    e = launch_window_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, st);
+    if (e == hipSuccess) e = launch_build_lists(s->S, s->Lst, s->W, false, st);
+    for (int k = 0; k < K && e == hipSuccess; ++k)
+      e = launch_draft(s->S, s->Lst, s->W, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st);
+  }
+  if (part == PART_FULL && !plain && e == hipSuccess) {
+    const int fw = K >= 8 ? 4 : (K >= 2 ? 2 : 1);
+    e = launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st);
+  }
+  if ((part == PART_FULL || part == PART_POST) && e == hipSuccess) {
+    e = launch_decide(s->S, s->W, s->T, s->O, plain ? 1 : 0, st);
+    if (e == hipSuccess) e = launch_commit(s->S, s->W, s->buf.q, s->buf.p, s->buf.img, st);
+  }
+  return e;
+}
+
+lsd_status capture(lsd_system* s, int K, int part, hipGraphExec_t* out) {
+  if (!s->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+  hipError_t e = enqueue_part(s, K, part, s->cap_stream);
+  hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(LSD_ERR_HIP, "window capture: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  hipError_t e3 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e3 != hipSuccess) return fail(LSD_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e3));
   return LSD_OK;
 }
 
@@ -522,12 +582,49 @@ lsd_status lsd_accept_rollback(lsd_system* s, int32_t* n_host, lsd_stream stream
 }
 
 lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stream stream) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
   if (n_windows < 0) return fail(LSD_ERR_INVALID_ARG, "n_windows < 0");
-  for (int w = 0; w < n_windows; ++w) {
-    LSD_TRY(lsd_draft_steps(s, K, stream));
-    LSD_TRY(lsd_verify_window(s, stream));
-    LSD_TRY(lsd_accept_rollback(s, nullptr, stream));
+  if (K < 1 || K > s->cfg.k_max) return fail(LSD_ERR_INVALID_ARG, "K = %d outside 1..k_max", K);
+  if (s->state != ST_READY && s->state != ST_COMMITTED)
+    return fail(LSD_ERR_BAD_STATE, "run_windows needs a committed state (state %d)", s->state);
+  if (!s->use_graphs) {
+    for (int w = 0; w < n_windows; ++w) {
+      LSD_TRY(lsd_draft_steps(s, K, stream));
+      LSD_TRY(lsd_verify_window(s, stream));
+      LSD_TRY(lsd_accept_rollback(s, nullptr, stream));
+    }
+    return LSD_OK;
   }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool timed = s->timing && s->cfg.mode == LSD_MODE_LSD;
+  WindowGraphs& G = s->graphs[K];
+  if (!timed && !G.full) LSD_TRY(capture(s, K, PART_FULL, &G.full));
+  if (timed && !G.pre) LSD_TRY(capture(s, K, PART_PRE, &G.pre));
+  if (timed && !G.post) LSD_TRY(capture(s, K, PART_POST, &G.post));
+  s->W.K = K;
+  for (int w = 0; w < n_windows; ++w) {
+    if (!timed) {
+      HIP_TRY(hipGraphLaunch(G.full, st));
+      continue;
+    }
+    HIP_TRY(hipGraphLaunch(G.pre, st));
+    TimingRing& R = s->ring;
+    if (R.used == kTimingRing) LSD_TRY(timing_drain_one(s));
+    const int slot = (R.head + R.used) % kTimingRing;
+    HIP_TRY(hipEventRecord(R.start[slot], st));
+    const int fw = K >= 8 ? 4 : (K >= 2 ? 2 : 1);
+    HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st));
+    HIP_TRY(hipEventRecord(R.stop[slot], st));
+    R.used += 1;
+    HIP_TRY(hipGraphLaunch(G.post, st));
+  }
+  s->state = ST_COMMITTED;
+  return LSD_OK;
+}
+
+lsd_status lsd_set_graphs(lsd_system* s, int32_t enable) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  s->use_graphs = enable != 0;
   return LSD_OK;
 }
 
@@ -561,6 +658,7 @@ lsd_status lsd_set_step_limit(lsd_system* s, int64_t limit) {
   if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
   if (limit < 0) return fail(LSD_ERR_INVALID_ARG, "step limit < 0");
   s->S.step_limit = limit;
+  destroy_graphs(s);  // captured kernels hold the old limit
   return LSD_OK;
 }
 
@@ -619,6 +717,8 @@ lsd_status lsd_rng_uniforms(uint64_t seed, int32_t replica, int64_t step0, int32
 
 lsd_status lsd_destroy(lsd_system* s) {
   if (!s) return LSD_OK;
+  destroy_graphs(s);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->ring.created) {
     for (int i = 0; i < kTimingRing; ++i) {
       (void)hipEventDestroy(s->ring.start[i]);

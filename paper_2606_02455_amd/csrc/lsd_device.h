@@ -172,6 +172,13 @@ __device__ __forceinline__ float a_half(float x, float p, double hdt_m, double L
   return r;
 }
 
+// (A) without wrapping: positions inside a window stay continuous with the
+// wrapped frame-0 positions the neighbour lists (and their image codes) were
+// built from; the commit wraps them.
+__device__ __forceinline__ float a_half_cont(float x, float p, double hdt_m) {
+  return (float)((double)x + hdt_m * (double)p);
+}
+
 // Mean of the (BOB) Gaussian: e^{-gamma dt} p + (1 + e^{-gamma dt}) dt/2 F.
 __device__ __forceinline__ double bob_mean(double a, double c1fu, float p, float F) {
   return fma(a, (double)p, c1fu * (double)F);

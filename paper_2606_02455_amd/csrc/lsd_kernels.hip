@@ -352,28 +352,21 @@ __global__ __launch_bounds__(256) void k_draft(SysDev S, ListDev Lst, WinDev W, 
     pk1[d * N + i] = pn[d];
   }
   if (k + 1 < W.K) {
-    const double L = S.box[r];
     const double hm = S.hdt_m[sp];
     const float4 x = X[i];
-    int dimg[3];
-    unpack_img(x.w, dimg);
-    float xs[3] = {x.x, x.y, x.z}, xn[3];
+    const float xs[3] = {x.x, x.y, x.z};
+    float xn[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      float qend = a_half(xs[d], pn[d], hm, L, &dimg[d]);   // q~_k
-      xn[d] = a_half(qend, pn[d], hm, L, &dimg[d]);         // next midpoint
+      const float qend = a_half_cont(xs[d], pn[d], hm);   // q~_k
+      xn[d] = a_half_cont(qend, pn[d], hm);                // next midpoint
     }
-    W.qmid[(size_t)(k + 1) * N + i] = make_float4(xn[0], xn[1], xn[2], pack_img(dimg[0], dimg[1], dimg[2]));
-    // displacement from the list positions (frame 0), minimum image
+    // frames stay continuous with frame 0, so frame 0's image deltas apply
+    W.qmid[(size_t)(k + 1) * N + i] = make_float4(xn[0], xn[1], xn[2], x.w);
+    // displacement from the list positions (frame 0)
     const float4 x0 = W.qmid[i];
-    const float Lf = (float)L;
-    float dd[3] = {xn[0] - x0.x, xn[1] - x0.y, xn[2] - x0.z};
-    float d2 = 0.0f;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      dd[d] -= Lf * rintf(dd[d] / Lf);
-      d2 += dd[d] * dd[d];
-    }
+    const float dx = xn[0] - x0.x, dy = xn[1] - x0.y, dz = xn[2] - x0.z;
+    const float d2 = dx * dx + dy * dy + dz * dz;
     if (d2 > S.half_skin2 && inv[k + 1] == 0) atomicOr(&inv[k + 1], 1);
   }
 }
@@ -383,20 +376,17 @@ __global__ __launch_bounds__(256) void k_frame_validity(SysDev S, WinDev W) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.n) return;
   const int r = S.atom_rep[i];
-  const float Lf = (float)S.box[r];
   const float4 x0 = W.qmid[i];
   int* inv = W.invalid + (size_t)r * S.kmax;
   if (i == S.rep_off[r])
     for (int k = 0; k < W.K; ++k)
       if (S.step[r] + k + 1 > S.step_limit) inv[k] = 1;
+  // caller frames must be continuous with frame 0 (not wrapped): a frame in
+  // which an atom jumped by a box edge is reported invalid, never verified
   for (int k = 1; k < W.K; ++k) {
     const float4 x = W.qmid[(size_t)k * S.n + i];
-    float dd[3] = {x.x - x0.x, x.y - x0.y, x.z - x0.z};
-    float d2 = 0.0f;
-    for (int d = 0; d < 3; ++d) {
-      dd[d] -= Lf * rintf(dd[d] / Lf);
-      d2 += dd[d] * dd[d];
-    }
+    const float dx = x.x - x0.x, dy = x.y - x0.y, dz = x.z - x0.z;
+    const float d2 = dx * dx + dy * dy + dz * dz;
     if (d2 > S.half_skin2) {
       for (int kk = k; kk < W.K; ++kk) atomicOr(&inv[kk], 1);
       break;

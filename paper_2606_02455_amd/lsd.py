@@ -73,6 +73,7 @@ EXPORTS = {
     "lsd_get_window_layout": ([C.c_void_p, C.POINTER(WindowLayout)], C.c_int),
     "lsd_get_status": ([C.c_void_p, C.POINTER(C.c_int32), C.c_void_p], C.c_int),
     "lsd_set_step_limit": ([C.c_void_p, C.c_int64], C.c_int),
+    "lsd_set_graphs": ([C.c_void_p, C.c_int32], C.c_int),
     "lsd_get_counters": ([C.c_void_p, C.POINTER(C.c_int64), C.c_void_p], C.c_int),
     "lsd_reset_counters": ([C.c_void_p, C.c_void_p], C.c_int),
     "lsd_set_verify_timing": ([C.c_void_p, C.c_int32], C.c_int),
@@ -285,6 +286,10 @@ class LSDSystem:
         f = C.c_int32()
         _check(load().lsd_get_status(self.h, C.byref(f), _stream(self.torch)), "lsd_get_status")
         return int(f.value)
+
+    def set_graphs(self, on=True):
+        """Replay captured HIP graphs in run_windows (default) or not."""
+        _check(load().lsd_set_graphs(self.h, 1 if on else 0), "lsd_set_graphs")
 
     def set_step_limit(self, limit):
         """Stop every replica exactly at step `limit` (None: no limit)."""

@@ -54,10 +54,20 @@ def _ora_pot(ora, d):
     return ora.Potential.harmonic(d["k"], d["anchor"], offset=d.get("offset"))
 
 
+def _continuous(qm, L):
+    """Frames continuous with frame 0 (the window convention): undo wraps."""
+    out = qm.copy()
+    out[1:] -= L * np.round((out[1:] - out[0][None]) / L)
+    return out
+
+
 def _inject(sysg, torch, qmid, p_draft, f_draft):
-    """Write caller frames (numpy [K,N,3], [K+1,N,3], [K,N,3]) into the window."""
+    """Write caller frames (numpy [K,N,3], [K+1,N,3], [K,N,3]) into the window;
+    positions are made continuous with frame 0."""
     win = sysg.window()
     K = qmid.shape[0]
+    L = np.repeat(sysg.w.box, np.diff(sysg.w.atom_offsets))[None, :, None]
+    qmid = _continuous(qmid, L)
     q4 = np.zeros((K, qmid.shape[1], 4), np.float32)
     q4[:, :, :3] = qmid
     win["q_mid"][:K].copy_(torch.tensor(q4))
@@ -425,3 +435,79 @@ def test_uneven_replicas_verify_per_replica(torch, lsd, ora):
         if decided:
             assert n[r] == j, (r, n[r], j)
     g.destroy()
+
+
+def test_graph_replays_equal_eager_launches(torch, lsd):
+    _say("graph vs eager")
+    for mode in ("lsd", "plain"):
+        w = W.config("c1")
+        a = lsd.LSDSystem(w, mode=mode)
+        b = lsd.LSDSystem(w, mode=mode)
+        b.set_graphs(False)
+        for rep in range(6):
+            a.run_windows(3, 8)
+            b.run_windows(3, 8)
+            sa, sb = a.state(), b.state()   # synchronises between replays
+            for k in ("q", "p", "img", "step"):
+                assert np.array_equal(sa[k], sb[k]), (mode, rep, k)
+            assert np.array_equal(a.counters(), b.counters())
+        a.destroy()
+        b.destroy()
+
+
+def _near_faces(w):
+    """The C1 lattice shifted by half a spacing: a layer of atoms sits within
+    the jitter of every box face, so many cross a face within a window."""
+    L = float(w.box[0])
+    a = L / 4
+    x = np.mod(w.positions - 0.5 * a + 0.004, L)
+    x = W.f32(x)
+    x[x >= L] = 0.0
+    return x
+
+
+def test_forces_across_box_faces_inside_a_window(torch, lsd, ora):
+    _say("box-face crossings")
+    w = W.config("c1")
+    w.positions = _near_faces(w)
+    K, N = w.K, w.n_atoms
+    L = float(w.box[0])
+    xi = np.stack([ora.normals(5, 0, s, N) for s in range(1, K + 1)])
+    u = np.ones(K)
+    so, T, r = _oracle_window_rounded(ora, w, xi, u, w.positions, w.momenta)
+    qm, pd, fd = W.f32(r["q_mid"]), W.f32(r["p_draft"]), W.f32(r["F_draft"])
+    qm[qm >= L] = 0.0
+    # the oracle frames do wrap: count atoms that crossed a face after frame 0
+    jumps = np.abs(qm[1:] - qm[0][None]) > L / 2
+    assert jumps.any(axis=(0, 2)).sum() >= 3
+    # identical frames, made continuous by _inject: every target force matches
+    g = lsd.LSDSystem(w, mode="lsd", replay=True)
+    g.replay_u.copy_(torch.tensor(u[None, :]))
+    g.set_state(w.positions, pd[0])
+    _inject(g, torch, qm, pd, fd)
+    g.mark_drafted(K)
+    g.verify_window()
+    g.accept_rollback(sync=True)
+    inv = g.window()["frame_invalid"].cpu().numpy()[0]
+    ft = g.window()["f_target"][:K].cpu().numpy().transpose(0, 2, 1)
+    keff = int(np.argmax(inv[:K])) if inv[:K].any() else K
+    assert keff >= 4
+    for k in range(keff):
+        E, F = ora.energy_forces(T, qm[k], L)
+        assert np.max(np.abs(ft[k] - F)) <= 1e-5 * np.max(np.abs(F)), k
+    g.destroy()
+    # the GPU's own drafting across faces: per-frame draft forces follow the
+    # oracle's trajectory (a lost pair would be an O(1) error)
+    h = lsd.LSDSystem(w, mode="lsd", replay=True)
+    h.replay_xi.copy_(torch.tensor(xi))
+    h.replay_u.fill_(1.0)
+    h.draft_steps(K)
+    torch.cuda.synchronize()
+    fdg = h.window()["f_draft"][:K].cpu().numpy().transpose(0, 2, 1)
+    invh = h.window()["frame_invalid"].cpu().numpy()[0]
+    keff = int(np.argmax(invh[:K])) if invh[:K].any() else K
+    for k in range(keff):
+        assert np.max(np.abs(fdg[k] - r["F_draft"][k])) <= 1e-3 * np.max(np.abs(r["F_draft"][k])), k
+    h.verify_window()
+    h.accept_rollback(sync=True)
+    h.destroy()
