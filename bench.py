@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20  # calibration copy: 256 MiB read + 256 MiB written
 VERIFY_SOURCES = ["paper_2606_02455_amd/csrc/lsd_kernels.hip",
                   "paper_2606_02455_amd/csrc/lsd_device.h"]
 
@@ -186,6 +187,14 @@ def main():
     status = lsds.status() | plain.status()
     if status:
         raise RuntimeError(f"device status {status}: neighbour capacity overflow")
+
+    # --- a plain copy of known size: the reference that scales the
+    # FETCH_SIZE / WRITE_SIZE counters of rocprofv3 (profiles/)
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
     # --- roofline of the dominant kernel (one verification launch)
     frames_per_launch = frames / max(ver_n, 1)

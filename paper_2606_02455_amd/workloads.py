@@ -231,6 +231,44 @@ def triatomic_replicas(n_replicas: int = 256, n_mol_lo: int = 8, n_mol_hi: int =
         target=dict(kind="mpnn", rc=5.0), draft=dict(kind="pair", rc=4.0), skin=kw.get("skin", 0.5))
 
 
+# --- random-init message-passing potential (weights are data) --------------
+MPNN_HIDDEN = 128
+MPNN_RBF = 16
+MPNN_LAYERS = 3
+MPNN_READOUT = 64
+
+
+def mpnn_weight_shapes(n_species: int, H: int = MPNN_HIDDEN, R: int = MPNN_RBF,
+                       T: int = MPNN_LAYERS, RH: int = MPNN_READOUT):
+    """Names and shapes of the flat weight vector, in storage order.  Matrices
+    are stored [out][in]."""
+    shapes = [("W_emb", (n_species, H))]
+    for t in range(T):
+        shapes += [(f"A1_{t}", (H, R)), (f"a1_{t}", (H,)), (f"A2_{t}", (H, H)), (f"a2_{t}", (H,)),
+                   (f"B_{t}", (H, H)), (f"C1_{t}", (H, H)), (f"c1_{t}", (H,)),
+                   (f"C2_{t}", (H, H)), (f"c2_{t}", (H,))]
+    shapes += [("W1", (RH, H)), ("b1", (RH,)), ("w2", (RH,)), ("b2", (1,))]
+    return shapes
+
+
+def mpnn_weights(n_species: int = 3, seed: int = 17) -> np.ndarray:
+    """Seeded random-init weights: U(+-1/sqrt(fan_in)) for every matrix and
+    the readout vector, zero biases, N(0, 1) species embeddings; rounded to
+    binary32 and returned as one flat float64 vector."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shp in mpnn_weight_shapes(n_species):
+        if name == "W_emb":
+            v = rng.standard_normal(shp)
+        elif name.split("_")[0] in ("a1", "a2", "c1", "c2", "b1", "b2"):
+            v = np.zeros(shp)  # biases
+        else:
+            fan_in = shp[-1] if len(shp) == 2 else shp[0]
+            v = rng.uniform(-1.0, 1.0, shp) / np.sqrt(fan_in)
+        parts.append(f32(v).ravel())
+    return np.concatenate(parts)
+
+
 def random_box_positions(n: int, L: float, seed: int) -> np.ndarray:
     """Uniform positions in [0, L)^3 (binary32-representable)."""
     rng = np.random.default_rng(seed)
