@@ -79,8 +79,25 @@ typedef enum { LSD_MODE_LSD = 0, LSD_MODE_PLAIN = 1 } lsd_mode;
 
 typedef enum {
   LSD_POT_LJ = 1,       /* truncated, energy-shifted Lennard-Jones */
-  LSD_POT_HARMONIC = 2  /* tether U = k/2 |q - anchor|^2 (minimum image) */
+  LSD_POT_HARMONIC = 2, /* tether U = k/2 |q - anchor|^2 (minimum image) */
+  LSD_POT_MPNN = 3      /* message-passing network (target only), below */
 } lsd_pot_kind;
+
+/* Message-passing potential (a stand-in for the paper's interatomic
+ * potentials; architecture fixed here): radial basis
+ * e_b(r) = sqrt(2/rc) sin(b pi r/rc)/r (b = 1..16), cutoff
+ * f_c(r) = (cos(pi r/rc) + 1)/2, embedding h_i = W_emb[s_i] (128), three
+ * layers W_ij = f_c(r) (A2 silu(A1 e(r) + a1) + a2),
+ * m_i = sum_j W_ij (.) (B h_j), h_i += C2 silu(C1 m_i + c1) + c2, readout
+ * E = s_E sum_i (w2 . silu(W1 h_i + b1) + b2) with W1 64x128, and forces
+ * F = -dE/dq.  Weights: one flat binary32 device vector, matrices stored
+ * [out][in], in the order W_emb [S][128]; per layer A1 [128][16], a1,
+ * A2 [128][128], a2, B [128][128], C1 [128][128], c1, C2 [128][128], c2;
+ * then W1 [64][128], b1 [64], w2 [64], b2 [1]. */
+#define LSD_MPNN_HIDDEN 128
+#define LSD_MPNN_RBF 16
+#define LSD_MPNN_LAYERS 3
+#define LSD_MPNN_READOUT 64
 
 /* A potential: the target force field of verify_step or the draft force
  * field of draft_step (Alg. 2).  Forces are -dU/dq (Sec. 2.1). */
@@ -92,6 +109,9 @@ typedef struct {
   const float *anchor;       /* tether anchors, device [3][N] (kept by pointer) */
   const float *force_offset; /* optional constant force field added to the
                                 forces, device [3][N] or NULL (test drafts) */
+  const float *weights;      /* MPNN: flat weights (device, kept by pointer) */
+  int32_t n_model_species;   /* MPNN: species rows of W_emb (>= n_species) */
+  double energy_scale;       /* MPNN: s_E */
 } lsd_potential;
 
 typedef struct {

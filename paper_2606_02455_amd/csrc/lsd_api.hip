@@ -17,6 +17,7 @@
 
 #include "lsd.h"
 #include "lsd_launch.h"
+#include "mpnn.h"
 
 namespace {
 
@@ -59,6 +60,8 @@ struct Layout {
   size_t nbr_t, cnt_t, nbr_d, cnt_d;
   // window
   size_t qmid, p, fd, ft, invalid, partial, commit_frame, reflected, coef, counters, status;
+  size_t mpnn = 0, mpnn_bytes = 0, blas = 0, epart = 0;
+  bool has_mpnn = false;
   int mt = 0, md = 0, n_cells = 0, n_tiles = 0, cell_cap = 0;
   double rl_t = 0, rl_d = 0;
   std::vector<int> atom_rep_h, rep_nc_h, rep_cell_off_h, tile_start_h, tile_count_h, tile_rep_h,
@@ -75,7 +78,11 @@ bool is_binary32(double v) { return (double)(float)v == v; }
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-double pot_reach(const lsd_potential& P) { return P.kind == LSD_POT_LJ ? P.cutoff : 0.0; }
+double pot_reach(const lsd_potential& P) {
+  return (P.kind == LSD_POT_LJ || P.kind == LSD_POT_MPNN) ? P.cutoff : 0.0;
+}
+
+constexpr size_t kBlasWorkspace = 64ull << 20;
 
 lsd_status check_potential(const lsd_potential& P, const char* what) {
   if (P.kind == LSD_POT_LJ) {
@@ -84,6 +91,9 @@ lsd_status check_potential(const lsd_potential& P, const char* what) {
   } else if (P.kind == LSD_POT_HARMONIC) {
     if (!P.anchor || !(P.k_spring >= 0.0))
       return fail(LSD_ERR_INVALID_ARG, "%s: tether needs anchors and k >= 0", what);
+  } else if (P.kind == LSD_POT_MPNN) {
+    if (!(P.cutoff > 0.0) || !P.weights || P.n_model_species < 1 || !std::isfinite(P.energy_scale))
+      return fail(LSD_ERR_INVALID_ARG, "%s: network needs cutoff > 0, weights, species", what);
   } else {
     return fail(LSD_ERR_UNSUPPORTED, "%s: potential kind %d not supported", what, P.kind);
   }
@@ -117,6 +127,11 @@ lsd_status plan(const lsd_config* c, Layout* L) {
     return fail(LSD_ERR_INVALID_ARG, "mode %d invalid", c->mode);
   LSD_TRY(check_potential(c->target, "target"));
   if (c->mode == LSD_MODE_LSD) LSD_TRY(check_potential(c->draft, "draft"));
+  if (c->mode == LSD_MODE_LSD && c->draft.kind == LSD_POT_MPNN)
+    return fail(LSD_ERR_UNSUPPORTED, "the message-passing network is supported as target only");
+  if (c->target.kind == LSD_POT_MPNN && c->target.n_model_species < c->n_species)
+    return fail(LSD_ERR_INVALID_ARG, "network embeds %d species, system has %d",
+                c->target.n_model_species, c->n_species);
 
   L->rl_t = pot_reach(c->target) + c->skin;
   L->rl_d = (c->mode == LSD_MODE_LSD ? pot_reach(c->draft) : 0.0) + c->skin;
@@ -210,6 +225,13 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   L->coef = bump(&off, R * 8);
   L->counters = bump(&off, (size_t)R * 4 * 8);
   L->status = bump(&off, 4 * 4);
+  L->has_mpnn = c->target.kind == LSD_POT_MPNN;
+  if (L->has_mpnn) {
+    L->mpnn_bytes = mpnn_buffer_bytes(c->k_max, N, L->mt);
+    L->mpnn = bump(&off, L->mpnn_bytes);
+    L->blas = bump(&off, kBlasWorkspace);
+    L->epart = bump(&off, K * T * 8);
+  }
   L->total = (off + kAlign - 1) / kAlign * kAlign;
   return LSD_OK;
 }
@@ -273,6 +295,8 @@ struct lsd_system {
   double t_sum = 0.0;
   int64_t t_count = 0;
   bool use_graphs = true;
+  MpnnCtx mp;
+  bool has_mpnn = false;
   hipStream_t cap_stream = nullptr;
   std::map<int, WindowGraphs> graphs;
 };
@@ -324,6 +348,7 @@ hipError_t enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
     for (int k = 0; k < K && e == hipSuccess; ++k)
       e = launch_draft(s->S, s->Lst, s->W, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st);
   }
+  if (s->has_mpnn) return hipErrorNotSupported;  // never captured
   if (part == PART_FULL && !plain && e == hipSuccess) {
     const int fw = K >= 8 ? 4 : (K >= 2 ? 2 : 1);
     e = launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st);
@@ -505,6 +530,22 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
 
   s->Pt = make_pot(cfg->target, L);
   s->Pd = cfg->mode == LSD_MODE_LSD ? make_pot(cfg->draft, L) : s->Pt;
+  if (L.has_mpnn) {
+    s->has_mpnn = true;
+    s->use_graphs = false;  // the network pass is issued eagerly
+    MpnnCtx& M = s->mp;
+    mpnn_bind(M, ws<char>(s, L.mpnn), cfg->k_max, N, L.mt, cfg->target.weights,
+              cfg->target.n_model_species);
+    M.rc = (float)cfg->target.cutoff;
+    M.scale = (float)cfg->target.energy_scale;
+    if (rocblas_create_handle(&M.blas) != rocblas_status_success ||
+        rocblas_set_atomics_mode(M.blas, rocblas_atomics_not_allowed) != rocblas_status_success ||
+        rocblas_set_workspace(M.blas, ws<char>(s, L.blas), kBlasWorkspace) != rocblas_status_success) {
+      if (M.blas) rocblas_destroy_handle(M.blas);
+      delete s;
+      return fail(LSD_ERR_HIP, "rocBLAS handle setup failed");
+    }
+  }
   s->state = ST_READY;
   *out = s;
   return LSD_OK;
@@ -520,8 +561,18 @@ lsd_status lsd_draft_steps(lsd_system* s, int32_t K, lsd_stream stream) {
   const bool plain = s->cfg.mode == LSD_MODE_PLAIN;
   HIP_TRY(launch_window_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, st));
   HIP_TRY(launch_build_lists(s->S, s->Lst, s->W, false, st));
-  for (int k = 0; k < K; ++k)
-    HIP_TRY(launch_draft(s->S, s->Lst, s->W, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st));
+  for (int k = 0; k < K; ++k) {
+    if (plain && s->has_mpnn) {
+      // plain stepping with the network: its forces on frame k, then the step
+      char err[256];
+      if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, s->T, k, 1, s->W.fd,
+                     ws<double>(s, s->lay.epart), st, err, sizeof(err)))
+        return fail(LSD_ERR_HIP, "network forces: %s", err);
+      HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->Pt, k, 1, st, 1));
+    } else {
+      HIP_TRY(launch_draft(s->S, s->Lst, s->W, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st));
+    }
+  }
   s->state = ST_DRAFTED;
   return LSD_OK;
 }
@@ -554,7 +605,15 @@ lsd_status lsd_verify_window(lsd_system* s, lsd_stream stream) {
     }
     // frames per wave of the verification kernel: 4 for long windows
     const int fw = s->W.K >= 8 ? 4 : (s->W.K >= 2 ? 2 : 1);
-    HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st));
+    if (s->has_mpnn) {
+      char err[256];
+      if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, s->T, 0, s->W.K, s->W.ft,
+                     ws<double>(s, s->lay.epart), st, err, sizeof(err)))
+        return fail(LSD_ERR_HIP, "network forces: %s", err);
+      HIP_TRY(launch_transport(s->S, s->W, s->T, ws<double>(s, s->lay.epart), st));
+    } else {
+      HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st));
+    }
     if (s->timing) {
       HIP_TRY(hipEventRecord(R.stop[slot], st));
       R.used += 1;
@@ -718,6 +777,7 @@ lsd_status lsd_rng_uniforms(uint64_t seed, int32_t replica, int64_t step0, int32
 lsd_status lsd_destroy(lsd_system* s) {
   if (!s) return LSD_OK;
   destroy_graphs(s);
+  if (s->mp.blas) rocblas_destroy_handle(s->mp.blas);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->ring.created) {
     for (int i = 0; i < kTimingRing; ++i) {

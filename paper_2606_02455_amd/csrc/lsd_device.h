@@ -16,6 +16,7 @@
 #define LSD_MAX_K 64
 #define LSD_POT_LJ 1
 #define LSD_POT_HARMONIC 2
+#define LSD_POT_MPNN 3
 
 // status word bits
 #define LSD_STATUS_NBR_TARGET 1

@@ -308,7 +308,7 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
 // this step and start the next one; flags the next frame invalid when an
 // atom left the skin of the lists.  LSD_LPA lanes per atom.
 __global__ __launch_bounds__(256) void k_draft(SysDev S, ListDev Lst, WinDev W, PotDev P, int k,
-                                               int use_target_list) {
+                                               int use_target_list, int forces_given) {
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int i0 = gt / LSD_LPA, sub = gt % LSD_LPA;
   const bool in = i0 < S.n;
@@ -325,10 +325,17 @@ __global__ __launch_bounds__(256) void k_draft(SysDev S, ListDev Lst, WinDev W, 
   const size_t N = (size_t)S.n;
   const float4* X = W.qmid + (size_t)k * N;
   float F[3], e;
-  if (use_target_list)
+  if (forces_given) {
+    // forces of this frame already in the window (batched network pass)
+    const float* fk0 = W.fd + (size_t)k * 3 * N;
+    F[0] = fk0[i];
+    F[1] = fk0[N + i];
+    F[2] = fk0[2 * N + i];
+  } else if (use_target_list) {
     pot_force(P, S, X, Lst.nbr_t + (size_t)i * Lst.mt, Lst.cnt_t[i], i, r, sub, F[0], F[1], F[2], e);
-  else
+  } else {
     pot_force(P, S, X, Lst.nbr_d + (size_t)i * Lst.md, Lst.cnt_d[i], i, r, sub, F[0], F[1], F[2], e);
+  }
   if (!in || sub != 0) return;
 
   double xi[3];
@@ -518,6 +525,45 @@ __global__ __launch_bounds__(256) void k_verify(SysDev S, ListDev Lst, WinDev W,
   }
 }
 
+// Transport-map sums for frames whose target forces are already in the
+// window (batched network pass): S1, S2 and the energy per (frame, tile), in
+// the same binary64 form as the epilogue of k_verify.
+__global__ __launch_bounds__(64) void k_transport(SysDev S, WinDev W, TileDev Tl,
+                                                  const double* __restrict__ epart) {
+  const int tile = blockIdx.x, f = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int start = Tl.start[tile], count = Tl.count[tile], r = Tl.rep[tile];
+  if (f >= W.K || W.invalid[(size_t)r * S.kmax + f]) return;  // uniform
+  const size_t N = (size_t)S.n;
+  double s1 = 0.0, s2 = 0.0;
+  if (lane < count) {
+    const int i = start + lane;
+    const int sp = S.species ? S.species[i] : 0;
+    const double isg = 1.0 / S.sig[sp];
+    const float* pk = W.p + (size_t)f * 3 * N;
+    const float* pk1 = W.p + (size_t)(f + 1) * 3 * N;
+    const float* fdk = W.fd + (size_t)f * 3 * N;
+    const float* ftk = W.ft + (size_t)f * 3 * N;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float Fd = fdk[d * N + i], Ft = ftk[d * N + i];
+      const double mud = bob_mean(S.a, S.c1fu, pk[d * N + i], Fd);
+      const double z = ((double)pk1[d * N + i] - mud) * isg;
+      const double dl = S.c1fu * ((double)Fd - (double)Ft) * isg;
+      s1 = fma(dl, z, s1);
+      s2 = fma(dl, dl, s2);
+    }
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (lane == 0) {
+    double* out = W.partial + ((size_t)f * S.n_tiles + tile) * 4;
+    out[0] = s1;
+    out[1] = s2;
+    out[2] = epart[(size_t)f * S.n_tiles + tile];
+  }
+}
+
 // Per replica: frame sums over its tiles (fixed order), log ratio, decision
 // with u_{s+k}, first rejection (Alg. 1), outputs and the commit record.
 __global__ __launch_bounds__(64) void k_decide(SysDev S, WinDev W, TileDev Tl, OutDev O, int plain) {
@@ -682,10 +728,16 @@ hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W
 }
 
 hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P, int k,
-                        int use_target_list, hipStream_t st) {
+                        int use_target_list, hipStream_t st, int forces_given) {
   const long long threads = (long long)S.n * LSD_LPA;
   hipLaunchKernelGGL(k_draft, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, S, L, W, P,
-                     k, use_target_list);
+                     k, use_target_list, forces_given);
+  return hipGetLastError();
+}
+
+hipError_t launch_transport(const SysDev& S, const WinDev& W, const TileDev& T, const double* epart,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_transport, dim3(S.n_tiles, W.K), dim3(64), 0, st, S, W, T, epart);
   return hipGetLastError();
 }
 

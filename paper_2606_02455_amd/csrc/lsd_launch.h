@@ -10,7 +10,9 @@ hipError_t launch_window_start(const SysDev& S, const ListDev& L, const WinDev& 
 hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W, bool bin_frame0,
                               hipStream_t st);
 hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P, int k,
-                        int use_target_list, hipStream_t st);
+                        int use_target_list, hipStream_t st, int forces_given = 0);
+hipError_t launch_transport(const SysDev& S, const WinDev& W, const TileDev& T, const double* epart,
+                            hipStream_t st);
 hipError_t launch_frame_validity(const SysDev& S, const WinDev& W, hipStream_t st);
 hipError_t prepare_verify(int mt);
 hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,

@@ -1,0 +1,446 @@
+// mpnn.hip -- the message-passing target evaluated on a batch of frames.
+//
+// Forward (per layer t): filters W_t(r) = f_c(r) (A2 silu(A1 e(r) + a1) + a2)
+// for every slot, X_t = B_t h, m = sum over slots W_t (.) X_t[neighbour],
+// h += C2 silu(C1 m + c1) + c2; readout E = s_E sum (w2 . silu(W1 h + b1) + b2).
+// Reverse pass to the forces F = -dE/dq: gh = dE/dh from the readout, then per
+// layer gM = dE/dm, gX = dE/dX (gathered over each atom's own list, using
+// W_ij = W_ji), and per slot dE/dr accumulated for both directions of the
+// pair; finally F_a = sum over a's slots of dE/dr * (q_b - q_a) / r.
+#include <cstdio>
+
+#include "mpnn.h"
+
+namespace {
+
+constexpr int kSlotsPerBlock = 8;  // 8 slots x 16 basis functions = 128 threads
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
+__device__ __forceinline__ float siluf(float x) { return x * sigmoidf(x); }
+__device__ __forceinline__ float dsiluf(float x) {
+  const float s = sigmoidf(x);
+  return s * (1.0f + x * (1.0f - s));
+}
+
+// Geometry, radial basis and the first filter layer of all three layers:
+// S = silu(A1 e + a1), DS = silu'(A1 e + a1) (.) (A1 de/dr), per slot and
+// channel; f_c, f_c' and the unit vector per slot.  Block: 128 threads
+// (channels), kSlotsPerBlock slots.
+__global__ __launch_bounds__(128) void k_mp_radial(MpnnWeights w, MpnnBuffers b, SysDev S,
+                                                   ListDev L, WinDev W, int f0, int nf, float rc) {
+  __shared__ float s_e[kSlotsPerBlock][MP_R], s_de[kSlotsPerBlock][MP_R];
+  __shared__ float s_r[kSlotsPerBlock];
+  __shared__ int s_on[kSlotsPerBlock];
+  const int c = threadIdx.x;
+  const long N = S.n, mt = L.mt;
+  const long slots = (long)nf * N * mt;
+  const long s0 = (long)blockIdx.x * kSlotsPerBlock;
+  // phase 1: geometry of the block's slots (one thread per slot)
+  if (c < kSlotsPerBlock) {
+    const long slot = s0 + c;
+    int on = 0;
+    float fc = 0.f, dfc = 0.f, ux = 0.f, uy = 0.f, uz = 0.f, r = rc;
+    if (slot < slots) {
+      const long row = slot / mt;
+      const int m = (int)(slot - row * mt);
+      const int fl = (int)(row / N), i = (int)(row - (long)fl * N);
+      if (m < L.cnt_t[i]) {
+        const uint32_t ent = L.nbr_t[(size_t)i * mt + m];
+        const int j = (int)(ent >> 5), code = (int)(ent & 31u);
+        const float Lf = (float)S.box[S.atom_rep[i]];
+        const float4* X = W.qmid + (size_t)(f0 + fl) * N;
+        const float4 xi = X[i], xj = X[j];
+        float sj[3], si[3];
+        image_shifts(code, Lf, sj, si);
+        const float dx = sep(xj.x, sj[0], xi.x, si[0]);
+        const float dy = sep(xj.y, sj[1], xi.y, si[1]);
+        const float dz = sep(xj.z, sj[2], xi.z, si[2]);
+        r = sqrtf(dx * dx + dy * dy + dz * dz);
+        if (r < rc && r > 0.f) {
+          on = 1;
+          const float a = 3.14159265358979f / rc;
+          fc = 0.5f * (cosf(a * r) + 1.0f);
+          dfc = -0.5f * a * sinf(a * r);
+          ux = dx / r;
+          uy = dy / r;
+          uz = dz / r;
+        }
+      }
+      b.fcd[2 * slot] = fc;
+      b.fcd[2 * slot + 1] = dfc;
+      b.uv[4 * slot] = ux;
+      b.uv[4 * slot + 1] = uy;
+      b.uv[4 * slot + 2] = uz;
+      b.uv[4 * slot + 3] = 0.f;
+    }
+    s_on[c] = on;
+    s_r[c] = r;
+  }
+  __syncthreads();
+  // phase 2: radial basis e_b(r) = sqrt(2/rc) sin(b pi r/rc)/r and de_b/dr
+  {
+    const int q = c / MP_R, bb = c % MP_R;  // kSlotsPerBlock * MP_R == blockDim
+    float e = 0.f, de = 0.f;
+    if (s_on[q]) {
+      const float r = s_r[q];
+      const float pre = sqrtf(2.0f / rc);
+      const float k = (float)(bb + 1) * 3.14159265358979f / rc;
+      const float sn = sinf(k * r), cs = cosf(k * r);
+      e = pre * sn / r;
+      de = pre * (k * cs / r - sn / (r * r));
+    }
+    s_e[q][bb] = e;
+    s_de[q][bb] = de;
+  }
+  __syncthreads();
+  // phase 3: first filter layer, channel c of every layer
+  float A[MP_T][MP_R], a1v[MP_T];
+#pragma unroll
+  for (int t = 0; t < MP_T; ++t) {
+#pragma unroll
+    for (int q = 0; q < MP_R; ++q) A[t][q] = w.A1[t][c * MP_R + q];
+    a1v[t] = w.a1[t][c];
+  }
+  for (int q = 0; q < kSlotsPerBlock; ++q) {
+    const long slot = s0 + q;
+    if (slot >= slots) break;
+#pragma unroll
+    for (int t = 0; t < MP_T; ++t) {
+      float z = a1v[t], dz = 0.f;
+#pragma unroll
+      for (int k = 0; k < MP_R; ++k) {
+        z = fmaf(A[t][k], s_e[q][k], z);
+        dz = fmaf(A[t][k], s_de[q][k], dz);
+      }
+      b.S[slot * MP_HT + t * MP_H + c] = siluf(z);
+      b.DS[slot * MP_HT + t * MP_H + c] = dsiluf(z) * dz;
+    }
+  }
+}
+
+// After Z = S A2^T and DZ = DS A2^T: W = f_c (Z + a2) into Z and
+// dW/dr = f_c' (Z + a2) + f_c DZ into DZ.
+__global__ __launch_bounds__(256) void k_mp_filter(MpnnWeights w, MpnnBuffers b, long slots) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= slots * MP_HT) return;
+  const long slot = id / MP_HT;
+  const int col = (int)(id - slot * MP_HT);
+  const int t = col / MP_H, c = col % MP_H;
+  const float fc = b.fcd[2 * slot], dfc = b.fcd[2 * slot + 1];
+  const float zz = b.Z[id] + w.a2[t][c];
+  b.DZ[id] = dfc * zz + fc * b.DZ[id];
+  b.Z[id] = fc * zz;
+}
+
+__global__ __launch_bounds__(128) void k_mp_embed(MpnnWeights w, MpnnBuffers b, SysDev S, long rows) {
+  const long row = blockIdx.x;
+  if (row >= rows) return;
+  const int i = (int)(row % S.n);
+  const int sp = S.species ? S.species[i] : 0;
+  b.H[row * MP_H + threadIdx.x] = w.W_emb[sp * MP_H + threadIdx.x];
+}
+
+// out[row][c] = sum_{m < cnt_i} Wt[slot(row, m)][c] * V[neighbour row][c]
+// (messages with V = X_t; dE/dX with V = gM: W is symmetric in the pair)
+__global__ __launch_bounds__(128) void k_mp_gather(MpnnBuffers b, SysDev S, ListDev L, int t,
+                                                   const float* __restrict__ V,
+                                                   float* __restrict__ out, long rows) {
+  const long row = blockIdx.x;
+  if (row >= rows) return;
+  const int c = threadIdx.x;
+  const long N = S.n, mt = L.mt;
+  const long fl = row / N;
+  const int i = (int)(row - fl * N);
+  const int cnt = L.cnt_t[i];
+  const uint32_t* ent = L.nbr_t + (size_t)i * mt;
+  float acc = 0.f;
+  for (int m = 0; m < cnt; ++m) {
+    const int j = (int)(ent[m] >> 5);
+    const float wv = b.Z[(row * mt + m) * MP_HT + t * MP_H + c];
+    acc = fmaf(wv, V[(fl * N + j) * MP_H + c], acc);
+  }
+  out[row * MP_H + c] = acc;
+}
+
+// U += c1 (kept for the reverse pass); Sn = silu(U)
+__global__ __launch_bounds__(256) void k_mp_act(const float* __restrict__ c1, float* U, float* Sn,
+                                                long n) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  const float u = U[id] + c1[id % MP_H];
+  U[id] = u;
+  Sn[id] = siluf(u);
+}
+
+// Hn += Hp + c2 (residual update)
+__global__ __launch_bounds__(256) void k_mp_residual(const float* __restrict__ c2,
+                                                     const float* __restrict__ Hp, float* Hn, long n) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  Hn[id] = Hn[id] + Hp[id] + c2[id % MP_H];
+}
+
+// Readout of one tile of one frame (64 rows, one lane each): energy summed
+// in binary64 by a wave butterfly; gY = s_E w2 (.) silu'(Y + b1).
+__global__ __launch_bounds__(64) void k_mp_readout(MpnnWeights w, MpnnBuffers b, SysDev S,
+                                                   TileDev T, int f0, float scale, double* epart) {
+  const int tile = blockIdx.x, fl = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int start = T.start[tile], count = T.count[tile];
+  const long row = (long)fl * S.n + start + lane;
+  double e = 0.0;
+  if (lane < count) {
+    float ei = w.b2[0];
+    for (int o = 0; o < MP_RH; ++o) {
+      const float y = b.Y[row * MP_RH + o] + w.b1[o];
+      ei = fmaf(w.w2[o], siluf(y), ei);
+      b.gY[row * MP_RH + o] = scale * w.w2[o] * dsiluf(y);
+    }
+    e = (double)scale * (double)ei;
+  }
+  e = wave_sum(e);
+  if (lane == 0) epart[(size_t)(f0 + fl) * S.n_tiles + tile] = e;
+}
+
+__global__ __launch_bounds__(256) void k_mp_mul_dsilu(const float* __restrict__ U, float* g, long n) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  g[id] *= dsiluf(U[id]);
+}
+
+// dE/dr of one slot, both directions of the pair, layer t:
+// sum_c (gM[a] X[b] + gM[b] X[a])_c dW_c/dr.  One wave per slot.
+__global__ __launch_bounds__(256) void k_mp_dedr(MpnnBuffers b, SysDev S, ListDev L, int t,
+                                                 const float* __restrict__ X, long slots) {
+  const long slot = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (slot >= slots) return;  // uniform per wave
+  const long N = S.n, mt = L.mt;
+  const long row = slot / mt;
+  const int m = (int)(slot - row * mt);
+  const long fl = row / N;
+  const int i = (int)(row - fl * N);
+  if (m >= L.cnt_t[i]) return;  // uniform per wave
+  const int j = (int)(L.nbr_t[(size_t)i * mt + m] >> 5);
+  const long ra = row * MP_H, rb = (fl * N + j) * MP_H;
+  const float* dW = b.DZ + slot * MP_HT + t * MP_H;
+  float acc = 0.f;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = lane + 64 * h;
+    const float g = b.gM[ra + c] * X[rb + c] + b.gM[rb + c] * X[ra + c];
+    acc = fmaf(g, dW[c], acc);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) b.gr[slot] += acc;
+}
+
+// F_a = sum over a's slots of dE/dr (q_b - q_a)/r, frame-major [f][3][N]
+__global__ __launch_bounds__(256) void k_mp_forces(MpnnBuffers b, SysDev S, ListDev L, int f0,
+                                                   float* Fout, long rows) {
+  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= rows) return;
+  const long N = S.n, mt = L.mt;
+  const long fl = row / N;
+  const int i = (int)(row - fl * N);
+  const int cnt = L.cnt_t[i];
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  for (int m = 0; m < cnt; ++m) {
+    const long slot = row * mt + m;
+    const float g = b.gr[slot];
+    fx = fmaf(g, b.uv[4 * slot], fx);
+    fy = fmaf(g, b.uv[4 * slot + 1], fy);
+    fz = fmaf(g, b.uv[4 * slot + 2], fz);
+  }
+  float* F = Fout + (size_t)(f0 + fl) * 3 * N;
+  F[i] = fx;
+  F[N + i] = fy;
+  F[2 * N + i] = fz;
+}
+
+__global__ void k_mp_zero(float* p, long n) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n) p[id] = 0.f;
+}
+
+__global__ void k_mp_copy(const float* __restrict__ a, float* __restrict__ b, long n) {
+  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n) b[id] = a[id];
+}
+
+inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+// row-major C[M][Nc] = A[M][K] . op(B), with op(B) = B^T for B stored
+// [Nc][K] (trans) or op(B) = B for B stored [K][Nc]; column-major view for
+// rocBLAS: C^c = op(B)^c . A^c.
+rocblas_status gemm_rm(rocblas_handle h, const float* A, const float* B, float* C, int M, int Nc,
+                       int K, bool transB, float beta, int lda, int ldc) {
+  const float one = 1.0f;
+  return rocblas_sgemm(h, transB ? rocblas_operation_transpose : rocblas_operation_none,
+                       rocblas_operation_none, Nc, M, K, &one, B, transB ? K : Nc, A, lda, &beta,
+                       C, ldc);
+}
+
+}  // namespace
+
+size_t mpnn_buffer_bytes(int frames, int n, int mt) {
+  const size_t rows = (size_t)frames * n, slots = rows * mt;
+  size_t b = 0;
+  b += 4 * al(slots * MP_HT * 4);            // S, DS, Z, DZ
+  b += al(slots * 2 * 4) + al(slots * 4 * 4) + al(slots * 4);
+  b += al((MP_T + 1) * rows * MP_H * 4) + 2 * al(MP_T * rows * MP_H * 4);
+  b += 2 * al(rows * MP_H * 4) + 2 * al(rows * MP_RH * 4) + 5 * al(rows * MP_H * 4);
+  return b;
+}
+
+void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* weights,
+               int n_model_species) {
+  const size_t rows = (size_t)frames * n, slots = rows * mt;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    float* p = reinterpret_cast<float*>(base + off);
+    off += al(bytes);
+    return p;
+  };
+  MpnnBuffers& b = M.b;
+  b.S = take(slots * MP_HT * 4);
+  b.DS = take(slots * MP_HT * 4);
+  b.Z = take(slots * MP_HT * 4);
+  b.DZ = take(slots * MP_HT * 4);
+  b.fcd = take(slots * 2 * 4);
+  b.uv = take(slots * 4 * 4);
+  b.gr = take(slots * 4);
+  b.H = take((MP_T + 1) * rows * MP_H * 4);
+  b.X = take(MP_T * rows * MP_H * 4);
+  b.U = take(MP_T * rows * MP_H * 4);
+  b.Mm = take(rows * MP_H * 4);
+  b.Sn = take(rows * MP_H * 4);
+  b.Y = take(rows * MP_RH * 4);
+  b.gY = take(rows * MP_RH * 4);
+  b.gH = take(rows * MP_H * 4);
+  b.gP = take(rows * MP_H * 4);
+  b.gS = take(rows * MP_H * 4);
+  b.gM = take(rows * MP_H * 4);
+  b.gX = take(rows * MP_H * 4);
+  M.frames = frames;
+  MpnnWeights& w = M.w;
+  const float* p = weights;
+  w.W_emb = p;
+  p += (size_t)n_model_species * MP_H;
+  w.layer_stride = (long)MP_H * MP_R + MP_H + 4L * MP_H * MP_H + 3L * MP_H;
+  for (int t = 0; t < MP_T; ++t) {
+    w.A1[t] = p; p += MP_H * MP_R;
+    w.a1[t] = p; p += MP_H;
+    w.A2[t] = p; p += MP_H * MP_H;
+    w.a2[t] = p; p += MP_H;
+    w.B[t] = p; p += MP_H * MP_H;
+    w.C1[t] = p; p += MP_H * MP_H;
+    w.c1[t] = p; p += MP_H;
+    w.C2[t] = p; p += MP_H * MP_H;
+    w.c2[t] = p; p += MP_H;
+  }
+  w.W1 = p; p += MP_RH * MP_H;
+  w.b1 = p; p += MP_RH;
+  w.w2 = p; p += MP_RH;
+  w.b2 = p;
+}
+
+#define MP_HIP(x)                                                                       \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess) {                                                             \
+      snprintf(err, errlen, "%s: %s", #x, hipGetErrorString(e_));                       \
+      return false;                                                                     \
+    }                                                                                   \
+  } while (0)
+#define MP_BLAS(x)                                                                      \
+  do {                                                                                  \
+    rocblas_status s_ = (x);                                                            \
+    if (s_ != rocblas_status_success) {                                                 \
+      snprintf(err, errlen, "%s: rocblas status %d", #x, (int)s_);                      \
+      return false;                                                                     \
+    }                                                                                   \
+  } while (0)
+
+bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
+               int f0, int nf, float* Fout, double* epart, hipStream_t st, char* err,
+               size_t errlen) {
+  const MpnnWeights& w = M.w;
+  MpnnBuffers& b = M.b;
+  const long N = S.n, mt = L.mt;
+  const long rows = (long)nf * N, slots = rows * mt;
+  MP_BLAS(rocblas_set_stream(M.blas, st));
+  // filters of all layers
+  hipLaunchKernelGGL(k_mp_radial, dim3(nblk(slots, kSlotsPerBlock)), dim3(128), 0, st, w, b, S, L,
+                     W, f0, nf, M.rc);
+  MP_HIP(hipGetLastError());
+  const float one = 1.0f, zero = 0.0f;
+  // Z_t = S_t A2_t^T and DZ_t = DS_t A2_t^T for the three layers at once
+  MP_BLAS(rocblas_sgemm_strided_batched(M.blas, rocblas_operation_transpose,
+                                        rocblas_operation_none, MP_H, (int)slots, MP_H, &one,
+                                        w.A2[0], MP_H, w.layer_stride, b.S, MP_HT, MP_H, &zero,
+                                        b.Z, MP_HT, MP_H, MP_T));
+  MP_BLAS(rocblas_sgemm_strided_batched(M.blas, rocblas_operation_transpose,
+                                        rocblas_operation_none, MP_H, (int)slots, MP_H, &one,
+                                        w.A2[0], MP_H, w.layer_stride, b.DS, MP_HT, MP_H, &zero,
+                                        b.DZ, MP_HT, MP_H, MP_T));
+  hipLaunchKernelGGL(k_mp_filter, dim3(nblk(slots * MP_HT, 256)), dim3(256), 0, st, w, b, slots);
+  MP_HIP(hipGetLastError());
+  // forward through the layers
+  hipLaunchKernelGGL(k_mp_embed, dim3((unsigned)rows), dim3(MP_H), 0, st, w, b, S, rows);
+  MP_HIP(hipGetLastError());
+  const long rh = rows * MP_H;
+  for (int t = 0; t < MP_T; ++t) {
+    float* Ht = b.H + t * rh;
+    float* Hn = b.H + (t + 1) * rh;
+    float* Xt = b.X + t * rh;
+    float* Ut = b.U + t * rh;
+    MP_BLAS(gemm_rm(M.blas, Ht, w.B[t], Xt, (int)rows, MP_H, MP_H, true, 0.f, MP_H, MP_H));
+    hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, S, L, t, Xt, b.Mm,
+                       rows);
+    MP_HIP(hipGetLastError());
+    MP_BLAS(gemm_rm(M.blas, b.Mm, w.C1[t], Ut, (int)rows, MP_H, MP_H, true, 0.f, MP_H, MP_H));
+    hipLaunchKernelGGL(k_mp_act, dim3(nblk(rh, 256)), dim3(256), 0, st, w.c1[t], Ut, b.Sn, rh);
+    MP_HIP(hipGetLastError());
+    MP_BLAS(gemm_rm(M.blas, b.Sn, w.C2[t], Hn, (int)rows, MP_H, MP_H, true, 0.f, MP_H, MP_H));
+    hipLaunchKernelGGL(k_mp_residual, dim3(nblk(rh, 256)), dim3(256), 0, st, w.c2[t], Ht, Hn, rh);
+    MP_HIP(hipGetLastError());
+  }
+  // readout and its gradient
+  MP_BLAS(gemm_rm(M.blas, b.H + MP_T * rh, w.W1, b.Y, (int)rows, MP_RH, MP_H, true, 0.f, MP_H,
+                  MP_RH));
+  hipLaunchKernelGGL(k_mp_readout, dim3(S.n_tiles, nf), dim3(64), 0, st, w, b, S, T, f0, M.scale,
+                     epart);
+  MP_HIP(hipGetLastError());
+  MP_BLAS(gemm_rm(M.blas, b.gY, w.W1, b.gH, (int)rows, MP_H, MP_RH, false, 0.f, MP_RH, MP_H));
+  hipLaunchKernelGGL(k_mp_zero, dim3(nblk(slots, 256)), dim3(256), 0, st, b.gr, slots);
+  MP_HIP(hipGetLastError());
+  // reverse pass through the layers
+  for (int t = MP_T - 1; t >= 0; --t) {
+    float* Xt = b.X + t * rh;
+    float* Ut = b.U + t * rh;
+    MP_BLAS(gemm_rm(M.blas, b.gH, w.C2[t], b.gS, (int)rows, MP_H, MP_H, false, 0.f, MP_H, MP_H));
+    hipLaunchKernelGGL(k_mp_mul_dsilu, dim3(nblk(rh, 256)), dim3(256), 0, st, Ut, b.gS, rh);
+    MP_HIP(hipGetLastError());
+    MP_BLAS(gemm_rm(M.blas, b.gS, w.C1[t], b.gM, (int)rows, MP_H, MP_H, false, 0.f, MP_H, MP_H));
+    hipLaunchKernelGGL(k_mp_dedr, dim3(nblk(slots, 4)), dim3(256), 0, st, b, S, L, t, Xt, slots);
+    MP_HIP(hipGetLastError());
+    if (t > 0) {
+      hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, S, L, t, b.gM,
+                         b.gX, rows);
+      MP_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_mp_copy, dim3(nblk(rh, 256)), dim3(256), 0, st, b.gH, b.gP, rh);
+      MP_HIP(hipGetLastError());
+      MP_BLAS(gemm_rm(M.blas, b.gX, w.B[t], b.gP, (int)rows, MP_H, MP_H, false, 1.f, MP_H, MP_H));
+      float* tmp = b.gH;
+      b.gH = b.gP;
+      b.gP = tmp;
+    }
+  }
+  hipLaunchKernelGGL(k_mp_forces, dim3(nblk(rows, 256)), dim3(256), 0, st, b, S, L, f0, Fout, rows);
+  MP_HIP(hipGetLastError());
+  return true;
+}

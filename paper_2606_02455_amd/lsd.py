@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblsd.so")
 
 LSD_OK = 0
 MODE_LSD, MODE_PLAIN = 0, 1
-POT_LJ, POT_HARMONIC = 1, 2
+POT_LJ, POT_HARMONIC, POT_MPNN = 1, 2, 3
 STATUS_NBR_TARGET, STATUS_NBR_DRAFT, STATUS_CELL = 1, 2, 4
 
 _LIB = None
@@ -31,7 +31,8 @@ class LSDError(RuntimeError):
 class Potential(C.Structure):
     _fields_ = [("kind", C.c_int32), ("cutoff", C.c_double), ("epsilon", C.c_double),
                 ("sigma", C.c_double), ("k_spring", C.c_double), ("anchor", C.c_void_p),
-                ("force_offset", C.c_void_p)]
+                ("force_offset", C.c_void_p), ("weights", C.c_void_p),
+                ("n_model_species", C.c_int32), ("energy_scale", C.c_double)]
 
 
 class Config(C.Structure):
@@ -218,6 +219,14 @@ class LSDSystem:
                            dtype=t.float32, device="cuda").contiguous()
             self._keep.append(anc)
             P.anchor = anc.data_ptr()
+        elif kind == "mpnn":
+            P.kind, P.cutoff = POT_MPNN, float(d["rc"])
+            wt = t.tensor(np.asarray(d["weights"], dtype=np.float64), dtype=t.float32,
+                          device="cuda").contiguous()
+            self._keep.append(wt)
+            P.weights = wt.data_ptr()
+            P.n_model_species = int(d.get("n_model_species", len(self._masses)))
+            P.energy_scale = float(d.get("scale", 1.0))
         else:
             raise ValueError(f"potential kind {kind!r} is not implemented by the library")
         if d.get("offset") is not None:
