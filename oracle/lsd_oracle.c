@@ -475,24 +475,31 @@ typedef struct {
   /* per frame k = 1..K (stored at k-1) */
   double *logr, *S1, *S2, *E_target;
   int8_t *accept;
-  /* optional frame arrays (NULL to skip): [K][n][3], p_draft [K+1][n][3] */
+  /* optional frame arrays (NULL to skip): [K][n][3], p_draft [K+1][n][3];
+   * F_draft holds the bare draft forces (before any error correction) */
   double *q_mid, *p_draft, *F_draft, *F_target;
   int32_t n_committed; /* frames committed: first rejected index, else K */
   int32_t rejected;    /* 1 if the last committed frame was reflected */
 } ora_window_out;
 
 /* draft_step of Alg. 2: (q, p) = y is advanced in place to y'; the midpoint
- * positions (map f) and the draft forces are returned. */
+ * positions (map f) and the bare draft forces F~ are returned.  With
+ * speculative error correction (App. D, Alg. 3) the mean of the draft
+ * Gaussian is taken from F~ + dF, dF being the cached target-minus-draft force
+ * error of the last committed step, and F_c receives that corrected force;
+ * without it (dF == NULL) F_c = F~. */
 static void draft_step(const ora_sys *S, const ora_pot *D, double *q,
                        double *p, int32_t *img, const double *xi,
-                       double *q_mid, double *F_d) {
+                       double *q_mid, double *F_d, const double *dF,
+                       double *F_c) {
   int m = 3 * S->n;
   double *mu = (double *)malloc(sizeof(double) * m);
   double *sg = (double *)malloc(sizeof(double) * m);
   step_A(S, p, q, img);                           /* q~ <- q~ + dt/2 M^-1 p~ */
   memcpy(q_mid, q, sizeof(double) * m);
   ora_energy_forces(D, S->n, q, S->L, F_d, 1);    /* F~ <- draft forces */
-  bob_mean(S, p, F_d, mu);                        /* <p~> from Eq. bob */
+  for (int c = 0; c < m; ++c) F_c[c] = dF ? F_d[c] + dF[c] : F_d[c];
+  bob_mean(S, p, F_c, mu);                        /* <p~> from Eq. bob */
   bob_sigma(S, sg);
   for (int c = 0; c < m; ++c) p[c] = mu[c] + sg[c] * xi[c]; /* p~ ~ N */
   step_A(S, p, q, img);                           /* q~ <- q~ + dt/2 M^-1 p~ */
@@ -530,14 +537,19 @@ int ora_verify_frame(const ora_sys *S, const ora_pot *T, const double *q_mid,
 /* One synchronous window from the verified state (q, p, img): draft K steps
  * with noise xi[K][n][3], verify all K in parallel with uniforms u[K], keep
  * the prefix up to and including the first rejection (Alg. 1), and advance
- * (q, p, img) to the last kept state. */
+ * (q, p, img) to the last kept state.  dF (NULL: no error correction) is the
+ * error cache of App. D: every draft of the window is corrected by its value
+ * on entry, and on return it holds F - F~ (target minus bare draft force) of
+ * the last committed step, accepted or reflected. */
 int ora_lsd_window(const ora_sys *S, const ora_pot *T, const ora_pot *D,
                    double *q, double *p, int32_t *img, int K,
-                   const double *xi, const double *u, ora_window_out *out) {
+                   const double *xi, const double *u, ora_window_out *out,
+                   double *dF) {
   int n = S->n, m = 3 * n;
   double *qm = (double *)malloc(sizeof(double) * (size_t)K * m);
   double *pd = (double *)malloc(sizeof(double) * (size_t)(K + 1) * m);
   double *Fd = (double *)malloc(sizeof(double) * (size_t)K * m);
+  double *Fc = (double *)malloc(sizeof(double) * (size_t)K * m);
   double *Ft = (double *)malloc(sizeof(double) * (size_t)K * m);
   double *pv = (double *)malloc(sizeof(double) * (size_t)K * m);
   double *qv = (double *)malloc(sizeof(double) * (size_t)K * m);
@@ -559,14 +571,14 @@ int ora_lsd_window(const ora_sys *S, const ora_pot *T, const ora_pot *D,
     memcpy(&imgs[(size_t)(k + 1) * m], &imgs[(size_t)k * m], sizeof(int32_t) * m);
     draft_step(S, D, &qd[(size_t)(k + 1) * m], &pd[(size_t)(k + 1) * m],
                &imgs[(size_t)(k + 1) * m], &xi[(size_t)k * m],
-               &qm[(size_t)k * m], &Fd[(size_t)k * m]);
+               &qm[(size_t)k * m], &Fd[(size_t)k * m], dF, &Fc[(size_t)k * m]);
   }
   /* verification: independent frames, in parallel */
 #pragma omp parallel for schedule(dynamic, 1)
   for (int k = 0; k < K; ++k) {
     acc[k] = (int8_t)ora_verify_frame(
         S, T, &qm[(size_t)k * m], &pd[(size_t)k * m], &pd[(size_t)(k + 1) * m],
-        &Fd[(size_t)k * m], u[k], 0, &Ft[(size_t)k * m], &et[k], &lr[k], &s1[k],
+        &Fc[(size_t)k * m], u[k], 0, &Ft[(size_t)k * m], &et[k], &lr[k], &s1[k],
         &s2[k], &pv[(size_t)k * m], &qv[(size_t)k * m]);
   }
   /* first rejection l; keep steps 1..l (Alg. 1) */
@@ -589,6 +601,9 @@ int ora_lsd_window(const ora_sys *S, const ora_pot *T, const ora_pot *D,
     memcpy(q, &qd[(size_t)K * m], sizeof(double) * m);
     memcpy(img, &imgs[(size_t)K * m], sizeof(int32_t) * m);
   }
+  if (dF) /* new error cache from the EC-uncorrected draft force */
+    for (int c = 0; c < m; ++c)
+      dF[c] = Ft[(size_t)(j - 1) * m + c] - Fd[(size_t)(j - 1) * m + c];
   if (out) {
     if (out->logr) memcpy(out->logr, lr, sizeof(double) * K);
     if (out->S1) memcpy(out->S1, s1, sizeof(double) * K);
@@ -602,7 +617,7 @@ int ora_lsd_window(const ora_sys *S, const ora_pot *T, const ora_pot *D,
     out->n_committed = j;
     out->rejected = rej;
   }
-  free(qm); free(pd); free(Fd); free(Ft); free(pv); free(qv); free(imgs);
+  free(qm); free(pd); free(Fd); free(Fc); free(Ft); free(pv); free(qv); free(imgs);
   free(qd); free(acc); free(lr); free(s1); free(s2); free(et);
   return j;
 }
@@ -623,7 +638,7 @@ typedef struct {
 void ora_lsd_run(const ora_sys *S, const ora_pot *T, const ora_pot *D,
                  double *q, double *p, int32_t *img, uint64_t seed,
                  uint32_t replica, uint64_t step0, int64_t n_steps, int K,
-                 double *traj_q, double *traj_p, ora_run_stats *st) {
+                 double *traj_q, double *traj_p, ora_run_stats *st, double *dF) {
   int n = S->n, m = 3 * n;
   double *xi = (double *)malloc(sizeof(double) * (size_t)K * m);
   double *u = (double *)malloc(sizeof(double) * K);
@@ -646,7 +661,7 @@ void ora_lsd_run(const ora_sys *S, const ora_pot *T, const ora_pot *D,
     o.accept = acc;
     o.q_mid = qm;
     o.p_draft = pd;
-    int j = ora_lsd_window(S, T, D, q, p, img, Kw, xi, u, &o);
+    int j = ora_lsd_window(S, T, D, q, p, img, Kw, xi, u, &o, dF);
     if (traj_q) {
       /* committed states: accepted draft states then the final state */
       double *qt = (double *)malloc(sizeof(double) * m);

@@ -244,3 +244,44 @@ def test_lsd_harmonic_marginals_are_target(ora):
     assert stats.kstest(qs / np.sqrt(kT / kT_), "norm").pvalue > 0.01
     assert stats.kstest(ps / np.sqrt(var_p), "norm").pvalue > 0.01
     assert stats.kstest(qd / np.sqrt(kT / kT_), "norm").pvalue < 1e-4
+
+
+# --- speculative error correction (App. D, Alg. 3) --------------------------
+def test_error_correction_cancels_a_constant_draft_error(ora):
+    # draft F~ = F + b: after the first committed step the cache holds
+    # dF = F - F~_bare = -b, so every later proposal has the target mean and
+    # is accepted; without correction the rejection rate stays erf(|delta|/sqrt 8)
+    n, k = 4, 1.5
+    sysm, T, qref = _tether_system(ora, n, k, dt=0.05, gamma=1.0, kT=1.0)
+    rng = np.random.default_rng(16)
+    b = rng.normal(size=(n, 3))
+    sig = sysm.sigma()[:, None]
+    c1 = (1 + sysm.a) * sysm.dt / 2
+    b *= 1.2 / np.linalg.norm(c1 * b / sig)
+    D = T.with_offset(b)
+    q, p, img = qref.copy(), np.zeros((n, 3)), np.zeros((n, 3), np.int32)
+    ec = np.zeros((n, 3))
+    st, _, _ = ora.lsd_run(sysm, T, D, q, p, img, seed=3, replica=0, step0=0, n_steps=2000, K=4,
+                           ec=ec)
+    assert np.allclose(ec, -b, atol=1e-12)
+    # at most the windows before the first commit can reject
+    assert st["rejections"] <= 1
+    q2, p2, i2 = qref.copy(), np.zeros((n, 3)), np.zeros((n, 3), np.int32)
+    st2, _, _ = ora.lsd_run(sysm, T, D, q2, p2, i2, seed=3, replica=0, step0=0, n_steps=2000, K=4)
+    assert st2["rejections"] > 200
+
+
+def test_error_correction_keeps_target_marginals(ora):
+    kT_, kD, m, dt, kT = 2.0, 1.0, 1.0, 0.2, 1.0
+    qs, ps = [], []
+    for r in range(2000):
+        sysm, T, qref = _tether_system(ora, 1, kT_, m=m, dt=dt, gamma=2.0, kT=kT)
+        D = ora.Potential.harmonic(kD, qref)
+        q, p, img = qref.copy(), np.zeros((1, 3)), np.zeros((1, 3), np.int32)
+        ec = np.zeros((1, 3))
+        ora.lsd_run(sysm, T, D, q, p, img, seed=77, replica=r, step0=0, n_steps=60, K=4, ec=ec)
+        qs.append(q[0] - qref[0])
+        ps.append(p[0])
+    var_p = m * kT / (1.0 - (kT_ / m) * dt * dt / 4.0)
+    assert stats.kstest(np.ravel(qs) / np.sqrt(kT / kT_), "norm").pvalue > 0.01
+    assert stats.kstest(np.ravel(ps) / np.sqrt(var_p), "norm").pvalue > 0.01
