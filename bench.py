@@ -79,9 +79,10 @@ def in_cutoff_pairs(sysg, rc):
     return int(((r2 < rc * rc) & valid).sum().item())
 
 
-def cpu_baseline(w, q, p, seconds):
+def cpu_baseline(w, q, p, seconds, ec_on):
     """The FP64 oracle as it stands: LSD windows of K frames from the
-    benchmark's equilibrated state until `seconds` of host time are spent."""
+    benchmark's equilibrated state until `seconds` of host time are spent
+    (with the same error-correction setting as the GPU run)."""
     import numpy as np
 
     import oracle
@@ -90,6 +91,7 @@ def cpu_baseline(w, q, p, seconds):
     D = oracle.Potential.lj(w.draft["rc"])
     q, p = q.copy(), p.copy()
     img = np.zeros(q.shape, np.int32)
+    ec = np.zeros(q.shape) if ec_on else None
     K, N = w.K, w.n_atoms
     committed = windows = 0
     step = 0
@@ -97,7 +99,7 @@ def cpu_baseline(w, q, p, seconds):
     while time.perf_counter() - t0 < seconds:
         xi = np.stack([oracle.normals(w.seed, 0, step + k + 1, N) for k in range(K)])
         u = np.array([oracle.uniform(w.seed, 0, step + k + 1) for k in range(K)])
-        r = oracle.lsd_window(so, T, D, q, p, img, xi, u)
+        r = oracle.lsd_window(so, T, D, q, p, img, xi, u, ec=ec)
         committed += r["n_committed"]
         step += r["n_committed"]
         windows += 1
@@ -124,6 +126,8 @@ def main():
     ap.add_argument("--equilibrate", type=int, default=256, help="plain steps before timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ec", choices=["on", "off"], default="on",
+                    help="speculative error correction of the draft (App. D)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -148,7 +152,8 @@ def main():
     eq_windows = max(1, args.equilibrate // K)
     plain.run_windows(eq_windows, K)
     torch.cuda.synchronize()
-    lsds = lsd.LSDSystem(w, mode="lsd")
+    ec_on = args.ec == "on"
+    lsds = lsd.LSDSystem(w, mode="lsd", error_correction=ec_on)
     lsds.q.copy_(plain.q)
     lsds.p.copy_(plain.p)
     lsds.img.copy_(plain.img)
@@ -212,7 +217,7 @@ def main():
     if not args.no_cpu_baseline:
         st = lsds.state()
         log("timing the FP64 oracle on the host ...")
-        cpu = cpu_baseline(w, st["q"], st["p"], args.cpu_seconds)
+        cpu = cpu_baseline(w, st["q"], st["p"], args.cpu_seconds, ec_on)
         log(f"oracle: {cpu['value']:.3f} LSD steps/s, {cpu['plain_steps_per_s']:.3f} plain steps/s "
             f"on {cpu['cores']} threads")
 
@@ -234,8 +239,9 @@ def main():
         "config": {
             "workload": (f"{w.name}: Lennard-Jones fluid, {w.n_atoms} atoms, rho*=0.8, T*=1, "
                          f"target cutoff {w.target['rc']}, draft cutoff {w.draft['rc']}, "
-                         f"K={K}, dt={w.dt}, gamma={w.gamma}, seed {w.seed}"),
-            "n_atoms": w.n_atoms, "K": K, "skin": w.skin,
+                         f"K={K}, dt={w.dt}, gamma={w.gamma}, seed {w.seed}, "
+                         f"error correction {args.ec}"),
+            "n_atoms": w.n_atoms, "K": K, "skin": w.skin, "error_correction": ec_on,
         },
         "acceptance": round(1.0 - rejections / max(committed, 1), 5),
         "committed_per_window": round(committed / windows, 4),

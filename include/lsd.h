@@ -132,6 +132,15 @@ typedef struct {
   lsd_potential draft;         /* draft_step force field (ignored in PLAIN) */
   int32_t max_neighbors_target;/* neighbour-list width; 0 = automatic */
   int32_t max_neighbors_draft; /* 0 = automatic */
+  int32_t error_correction;    /* speculative error correction (App. D,
+                                  Alg. 3), LSD mode only: != 0 draws every
+                                  draft of a window from the Gaussian of Eq.
+                                  bob with F~ + dF, dF = F - F~ (target minus
+                                  EC-uncorrected draft force, binary32) of the
+                                  last committed step, cached per atom; the
+                                  cache starts at 0.  Target forces and the
+                                  acceptance rule are unchanged, so the target
+                                  law is preserved. */
 } lsd_config;
 
 typedef struct {
@@ -222,7 +231,9 @@ typedef struct {
   size_t q_mid;      /* float4 [k_max][N]: x, y, z, packed image deltas of
                         frame 0 relative to the committed counters */
   size_t p_draft;    /* float [k_max+1][3][N]: committed p, then p~_1..p~_K */
-  size_t f_draft;    /* float [k_max][3][N] */
+  size_t f_draft;    /* float [k_max][3][N]: bare draft forces F~ (the
+                        error correction is added where the draft mean is
+                        formed, in binary32: F~ + dF) */
   size_t f_target;   /* float [k_max][3][N] */
   size_t frame_invalid; /* int32 [R][k_max] */
   size_t nbr_target; /* uint32 [N][max_neighbors_target]: j << 5 | image code,
@@ -230,6 +241,8 @@ typedef struct {
   size_t cnt_target; /* int32 [N] */
   size_t nbr_draft;  /* uint32 [N][max_neighbors_draft] */
   size_t cnt_draft;  /* int32 [N] */
+  size_t error_cache;/* float [3][N] dF of the error correction; 0 (no
+                        array) when it is off */
   int32_t max_neighbors_target, max_neighbors_draft;
   int32_t n_atoms, k_max;
 } lsd_window_layout;

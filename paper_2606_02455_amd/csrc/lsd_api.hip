@@ -60,6 +60,7 @@ struct Layout {
   size_t nbr_t, cnt_t, nbr_d, cnt_d;
   // window
   size_t qmid, p, fd, ft, invalid, partial, commit_frame, reflected, coef, counters, status;
+  size_t ec = 0;  // error-correction cache (0: off)
   size_t mpnn = 0, mpnn_bytes = 0, blas = 0, epart = 0;
   bool has_mpnn = false;
   int mt = 0, md = 0, n_cells = 0, n_tiles = 0, cell_cap = 0;
@@ -225,6 +226,7 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   L->coef = bump(&off, R * 8);
   L->counters = bump(&off, (size_t)R * 4 * 8);
   L->status = bump(&off, 4 * 4);
+  if (c->error_correction && c->mode == LSD_MODE_LSD) L->ec = bump(&off, 3 * n * 4);
   L->has_mpnn = c->target.kind == LSD_POT_MPNN;
   if (L->has_mpnn) {
     L->mpnn_bytes = mpnn_buffer_bytes(c->k_max, N, L->mt);
@@ -446,6 +448,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_t), 0, N, st);
   if (e == hipSuccess) e = launch_zero_i64(ws<long long>(s, L.counters), 4 * R, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_d), 0, N, st);
+  if (e == hipSuccess && L.ec) e = launch_fill_int(ws<int>(s, L.ec), 0, 3 * N, st);  // +0.0f
   if (e == hipSuccess) e = prepare_verify(L.mt);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
@@ -514,6 +517,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   W.reflected = ws<int>(s, L.reflected);
   W.coef = ws<double>(s, L.coef);
   W.counters = ws<long long>(s, L.counters);
+  W.ec = L.ec ? ws<float>(s, L.ec) : nullptr;
   W.K = 0;
 
   TileDev& T = s->T;
@@ -698,6 +702,7 @@ lsd_status lsd_get_window_layout(const lsd_system* s, lsd_window_layout* out) {
   out->cnt_target = s->lay.cnt_t;
   out->nbr_draft = s->lay.nbr_d;
   out->cnt_draft = s->lay.cnt_d;
+  out->error_cache = s->lay.ec;
   out->max_neighbors_target = s->lay.mt;
   out->max_neighbors_draft = s->lay.md;
   out->n_atoms = s->S.n;

@@ -80,6 +80,7 @@ struct WinDev {
   int* commit_frame;  // [R]
   int* reflected;     // [R]
   double* coef;       // [R] 2 S1 / S2 of the rejected frame
+  float* ec;          // [3][N] error-correction cache dF, or null (off)
   long long* counters;  // [R][4]: windows, committed steps, rejections, frames verified
   int K;              // frames in the current window
 };
@@ -178,6 +179,12 @@ __device__ __forceinline__ float a_half(float x, float p, double hdt_m, double L
 // built from; the commit wraps them.
 __device__ __forceinline__ float a_half_cont(float x, float p, double hdt_m) {
   return (float)((double)x + hdt_m * (double)p);
+}
+
+// Draft force that enters the draft mean: F~ itself, or F~ + dF in binary32
+// with error correction on (App. D).
+__device__ __forceinline__ float draft_mean_force(const float* ec, size_t c, float Fd) {
+  return ec ? Fd + ec[c] : Fd;
 }
 
 // Mean of the (BOB) Gaussian: e^{-gamma dt} p + (1 + e^{-gamma dt}) dt/2 F.

@@ -353,7 +353,8 @@ __global__ __launch_bounds__(256) void k_draft(SysDev S, ListDev Lst, WinDev W, 
   float pn[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    double mu = bob_mean(S.a, S.c1fu, pk[d * N + i], F[d]);
+    const float Fm = draft_mean_force(W.ec, d * N + i, F[d]);
+    double mu = bob_mean(S.a, S.c1fu, pk[d * N + i], Fm);
     pn[d] = (float)fma(sg, xi[d], mu);
     fk[d * N + i] = F[d];
     pk1[d * N + i] = pn[d];
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(256) void k_verify(SysDev S, ListDev Lst, WinDev W,
         float* ftk = W.ft + (size_t)fr * 3 * N;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          const float Fd = fdk[d * N + i];
+          const float Fd = draft_mean_force(W.ec, d * N + i, fdk[d * N + i]);
           ftk[d * N + i] = Ft[d];
           const double mud = bob_mean(S.a, S.c1fu, pk[d * N + i], Fd);
           const double z = ((double)pk1[d * N + i] - mud) * isg;
@@ -546,7 +547,7 @@ __global__ __launch_bounds__(64) void k_transport(SysDev S, WinDev W, TileDev Tl
     const float* ftk = W.ft + (size_t)f * 3 * N;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float Fd = fdk[d * N + i], Ft = ftk[d * N + i];
+      const float Fd = draft_mean_force(W.ec, d * N + i, fdk[d * N + i]), Ft = ftk[d * N + i];
       const double mud = bob_mean(S.a, S.c1fu, pk[d * N + i], Fd);
       const double z = ((double)pk1[d * N + i] - mud) * isg;
       const double dl = S.c1fu * ((double)Fd - (double)Ft) * isg;
@@ -630,6 +631,8 @@ __global__ __launch_bounds__(64) void k_decide(SysDev S, WinDev W, TileDev Tl, O
 
 // Commit: the last kept frame's state; a rejected frame takes the reflected
 // momentum <p> + Sigma^{1/2} (z - (2 delta.z / delta.delta) delta) and map g.
+// With error correction the cache becomes F - F~ of the committed frame,
+// from the EC-uncorrected draft force (App. D).
 __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __restrict__ q,
                                                 float* __restrict__ p, int* __restrict__ img) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -653,9 +656,10 @@ __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __res
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     float pn = pk1[d * N + i];
+    const float Fb = W.fd[(size_t)f * 3 * N + d * N + i];
+    const float Ft = W.ft[(size_t)f * 3 * N + d * N + i];
     if (refl) {
-      const float Fd = W.fd[(size_t)f * 3 * N + d * N + i];
-      const float Ft = W.ft[(size_t)f * 3 * N + d * N + i];
+      const float Fd = draft_mean_force(W.ec, d * N + i, Fb);
       const double mut = bob_mean(S.a, S.c1fu, pk[d * N + i], Ft);
       const double mud = bob_mean(S.a, S.c1fu, pk[d * N + i], Fd);
       const double z = ((double)pn - mud) * isg;
@@ -666,6 +670,7 @@ __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __res
     q[d * N + i] = qn;
     p[d * N + i] = pn;
     img[d * N + i] += dimg[d];
+    if (W.ec) W.ec[d * N + i] = Ft - Fb;
   }
 }
 

@@ -43,7 +43,8 @@ class Config(C.Structure):
                 ("kT", C.c_double), ("force_unit", C.c_double), ("skin", C.c_double),
                 ("k_max", C.c_int32), ("mode", C.c_int32), ("seed", C.c_uint64),
                 ("target", Potential), ("draft", Potential),
-                ("max_neighbors_target", C.c_int32), ("max_neighbors_draft", C.c_int32)]
+                ("max_neighbors_target", C.c_int32), ("max_neighbors_draft", C.c_int32),
+                ("error_correction", C.c_int32)]
 
 
 class Buffers(C.Structure):
@@ -58,6 +59,7 @@ class WindowLayout(C.Structure):
                 ("f_target", C.c_size_t), ("frame_invalid", C.c_size_t),
                 ("nbr_target", C.c_size_t), ("cnt_target", C.c_size_t),
                 ("nbr_draft", C.c_size_t), ("cnt_draft", C.c_size_t),
+                ("error_cache", C.c_size_t),
                 ("max_neighbors_target", C.c_int32), ("max_neighbors_draft", C.c_int32),
                 ("n_atoms", C.c_int32), ("k_max", C.c_int32)]
 
@@ -142,7 +144,7 @@ class LSDSystem:
     """
 
     def __init__(self, workload, mode="lsd", k_max=None, target=None, draft=None, seed=None,
-                 skin=None, replay=False, max_neighbors=(0, 0)):
+                 skin=None, replay=False, max_neighbors=(0, 0), error_correction=False):
         import torch
         self.torch = torch
         lib = load()
@@ -175,6 +177,7 @@ class LSDSystem:
         cfg.target = self._potential(tgt)
         cfg.draft = self._potential(dft) if self.mode == MODE_LSD else Potential()
         cfg.max_neighbors_target, cfg.max_neighbors_draft = max_neighbors
+        cfg.error_correction = int(bool(error_correction))
         self.cfg = cfg
         nbytes = C.c_size_t()
         _check(lib.lsd_workspace_size(C.byref(cfg), C.byref(nbytes)), "lsd_workspace_size")
@@ -263,7 +266,8 @@ class LSDSystem:
     def window(self) -> Dict[str, "object"]:
         """Views into the workspace: q_mid [k_max, N, 4] (w = packed image
         deltas), p_draft [k_max+1, 3, N], f_draft / f_target [k_max, 3, N],
-        frame_invalid [R, k_max]."""
+        frame_invalid [R, k_max]; error_cache [3, N] (None when error
+        correction is off)."""
         t, L, N, K = self.torch, self.layout, self.N, self.k_max
         ws = self.workspace
 
@@ -277,6 +281,7 @@ class LSDSystem:
             f_draft=view(L.f_draft, K * 3 * N, t.float32, (K, 3, N)),
             f_target=view(L.f_target, K * 3 * N, t.float32, (K, 3, N)),
             frame_invalid=view(L.frame_invalid, self.R * K, t.int32, (self.R, K)),
+            error_cache=(view(L.error_cache, 3 * N, t.float32, (3, N)) if L.error_cache else None),
         )
 
     def neighbor_lists(self, which="target"):

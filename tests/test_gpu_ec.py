@@ -1,0 +1,119 @@
+"""GPU checks of speculative error correction (App. D, Alg. 3).
+
+The draft of every frame is drawn with F~ + dF, dF being the target minus
+EC-uncorrected draft force of the last committed step; target forces and the
+acceptance rule are untouched, so the committed states keep the target law.
+Checked against the oracle's EC runs, an exact cancellation case and exact
+stationary laws.
+"""
+import sys
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2606_02455_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no GPU")
+    return T
+
+
+@pytest.fixture(scope="module")
+def lsd(torch):
+    from paper_2606_02455_amd import lsd as L
+    L.load()
+    return L
+
+
+def test_ec_run_matches_oracle_on_tethers(torch, lsd, ora):
+    # draft stiffness differs from the target's, so the force error changes
+    # from step to step and the cache really moves; a large skin keeps every
+    # window at full length, as in the oracle
+    _say("EC run vs oracle (tethers)")
+    R, kT_, kD, n_steps, K = 48, 2.0, 1.0, 40, 4
+    w = W.tether_replicas(R, k=kT_, dt=0.2, gamma=2.0, kT=1.0, K=K, seed=41)
+    anchor = w.positions.copy()
+    draft = dict(kind="harmonic", k=kD, anchor=anchor)
+    g = lsd.LSDSystem(w, mode="lsd", draft=draft, skin=50.0, error_correction=True)
+    g.run_to_step(n_steps, K, check_every=4)
+    st = g.state()
+    cn = g.counters()
+    ec_g = g.window()["error_cache"].cpu().numpy().T.astype(np.float64)
+    assert (st["step"] == n_steps).all()
+    agree, rejections = 0, 0
+    for r in range(R):
+        so = ora.System(1, w.box[r], w.species_mass[0], w.dt, w.gamma, w.kT)
+        T = ora.Potential.harmonic(kT_, anchor[r:r + 1])
+        D = ora.Potential.harmonic(kD, anchor[r:r + 1])
+        q, p = w.positions[r:r + 1].copy(), w.momenta[r:r + 1].copy()
+        img = np.zeros((1, 3), np.int32)
+        ec = np.zeros((1, 3))
+        s, _, _ = ora.lsd_run(so, T, D, q, p, img, seed=w.seed, replica=r, step0=0,
+                              n_steps=n_steps, K=K, ec=ec)
+        rejections += s["rejections"]
+        same = (int(cn[r, 2]) == s["rejections"]
+                and np.max(np.abs(st["q"][r] - q[0])) <= 2e-3
+                and np.max(np.abs(st["p"][r] - p[0])) <= 2e-3
+                and np.max(np.abs(ec_g[r] - ec[0])) <= 1e-2)
+        agree += same
+    # a decision within rounding of log u may flip one replica's path
+    assert agree >= R - 1, (agree, R)
+    assert rejections > 0
+    g.destroy()
+
+
+def test_ec_cancels_a_constant_draft_error(torch, lsd):
+    _say("EC constant offset (C1)")
+    w = W.config("c1")
+    rng = np.random.default_rng(9)
+    b = rng.normal(size=(w.n_atoms, 3))
+    sig = np.sqrt(1.0 * w.kT * (1 - np.exp(-2 * w.gamma * w.dt)))
+    c1 = (1 + np.exp(-w.gamma * w.dt)) * w.dt / 2
+    b = W.f32(b * 2.0 / np.linalg.norm(c1 * b / sig))   # |delta| = 2: erf(2/sqrt 8) = 0.68
+    draft = dict(w.target)
+    draft["offset"] = b
+    g = lsd.LSDSystem(w, mode="lsd", draft=draft, error_correction=True)
+    g.run_windows(200, w.K)
+    cn = g.counters()[0]
+    ec = g.window()["error_cache"].cpu().numpy().T
+    # once a step is committed the cache is F - fl(F + b) = -b up to rounding
+    assert int(cn[2]) <= 1, cn
+    assert np.max(np.abs(ec + b)) <= 1e-5 * (1 + np.max(np.abs(b))), np.max(np.abs(ec + b))
+    assert g.status() == 0
+    g.destroy()
+    # without correction the same draft is rejected at the closed-form rate
+    g = lsd.LSDSystem(w, mode="lsd", draft=draft)
+    g.run_windows(100, w.K)
+    cn = g.counters()[0]
+    assert cn[2] / cn[1] > 0.4
+    assert g.window()["error_cache"] is None
+    g.destroy()
+
+
+def test_ec_keeps_exact_target_law(torch, lsd):
+    _say("EC harmonic replicas KS")
+    kT_, kD = 2.0, 1.0
+    w = W.tether_replicas(3000, k=kT_, dt=0.2, gamma=2.0, kT=1.0, K=4, seed=37)
+    anchor = w.positions.copy()
+    draft = dict(kind="harmonic", k=kD, anchor=anchor)
+    g = lsd.LSDSystem(w, mode="lsd", draft=draft, error_correction=True)
+    g.run_to_step(60, 4, check_every=8)
+    st = g.state()
+    assert (st["step"] == 60).all()
+    dq = (st["q"] - anchor).ravel()
+    var_p = 1.0 / (1.0 - kT_ * 0.2 ** 2 / 4.0)
+    assert stats.kstest(dq / np.sqrt(1.0 / kT_), "norm").pvalue > 0.01
+    assert stats.kstest(st["p"].ravel() / np.sqrt(var_p), "norm").pvalue > 0.01
+    g.destroy()
