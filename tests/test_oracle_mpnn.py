@@ -92,3 +92,76 @@ def test_mpnn_energy_scales_linearly(ora):
     b = MPNN(W.mpnn_weights(3, seed=17), 3, scale=2.5).energy_forces(sp, x, L)
     assert b[0] == pytest.approx(2.5 * a[0], rel=1e-14)
     assert np.allclose(b[1], 2.5 * a[1], rtol=1e-13, atol=0)
+
+
+def _special_weights():
+    """Weights under which one layer and the readout reduce to a short
+    scalar expression: only hidden channels 3, 7 and 9 and basis index 5
+    (b = 6) carry signal, and every matrix used is off-diagonal, so a
+    transposed operand or a shifted basis index changes the result."""
+    parts = {name: np.zeros(shp) for name, shp in W.mpnn_weight_shapes(3)}
+    parts["W_emb"][0, 7], parts["W_emb"][0, 9] = 0.8, -0.3
+    parts["W_emb"][2, 7], parts["W_emb"][2, 9] = 0.5, 1.1
+    parts["W_emb"][1, 7], parts["W_emb"][1, 9] = -0.6, 0.4
+    parts["A1_0"][3, 5] = 1.0            # hidden 3 <- basis b = 6
+    parts["a1_0"][3] = 0.2
+    parts["A2_0"][7, 3], parts["A2_0"][9, 3] = 2.0, -1.5
+    parts["a2_0"][7] = 0.25
+    parts["B_0"][7, 9], parts["B_0"][9, 7] = 1.3, 0.7
+    parts["C1_0"][7, 9], parts["C1_0"][9, 7] = 0.9, 1.2
+    parts["c1_0"][9] = -0.1
+    parts["C2_0"][7, 7], parts["C2_0"][9, 9] = 1.0, -0.8
+    parts["c2_0"][7] = 0.05
+    parts["W1"][0, 7], parts["W1"][1, 9] = 1.0, 1.0
+    parts["b1"][0] = 0.05
+    parts["w2"][0], parts["w2"][1] = 1.0, 0.5
+    parts["b2"][0] = 0.1
+    return np.concatenate([parts[n].ravel() for n, _ in W.mpnn_weight_shapes(3)])
+
+
+def _silu(x):
+    return x / (1.0 + np.exp(-x))
+
+
+def _special_energy(sp, x, rc, scale):
+    # scalar form of the network under _special_weights (no periodic images)
+    emb = {0: (0.8, -0.3), 1: (-0.6, 0.4), 2: (0.5, 1.1)}
+    E = 0.0
+    for i in range(len(x)):
+        h7, h9 = emb[int(sp[i])]
+        m7 = m9 = 0.0
+        for j in range(len(x)):
+            r = np.linalg.norm(x[j] - x[i])
+            if j == i or r >= rc:
+                continue
+            e6 = np.sqrt(2.0 / rc) * np.sin(6 * np.pi * r / rc) / r
+            s = _silu(e6 + 0.2)
+            fc = 0.5 * (np.cos(np.pi * r / rc) + 1.0)
+            g7, g9 = emb[int(sp[j])]
+            m7 += fc * (2.0 * s + 0.25) * (1.3 * g9)
+            m9 += fc * (-1.5 * s) * (0.7 * g7)
+        n7 = h7 + 1.0 * _silu(0.9 * m9) + 0.05
+        n9 = h9 - 0.8 * _silu(1.2 * m7 - 0.1)
+        E += _silu(n7 + 0.05) + 0.5 * _silu(n9) + 0.1
+    return scale * E
+
+
+def test_mpnn_special_weights_reduce_to_scalar_form(ora):
+    from oracle.mpnn import MPNN
+    net = MPNN(_special_weights(), 3, rc=5.0, scale=1.7)
+    L = 40.0
+    sp = np.array([0, 2, 1, 0], np.int32)
+    rng = np.random.default_rng(11)
+    for trial in range(5):
+        # four atoms within a few Angstrom: some pairs inside, some outside rc
+        x = 10.0 + rng.uniform(0.0, 6.0, size=(4, 3))
+        E, F = net.energy_forces(sp, x, L)
+        assert E == pytest.approx(_special_energy(sp, x, 5.0, 1.7), rel=1e-12, abs=1e-12)
+        h = 1e-6
+        for i in range(4):
+            for a in range(3):
+                xp, xm = x.copy(), x.copy()
+                xp[i, a] += h
+                xm[i, a] -= h
+                fd = -(_special_energy(sp, xp, 5.0, 1.7) - _special_energy(sp, xm, 5.0, 1.7)) / (2 * h)
+                assert F[i, a] == pytest.approx(fd, rel=1e-5, abs=1e-7)
