@@ -173,7 +173,7 @@ def main():
     ver_ms, ver_n = lsds.verify_timing()
     cn = lsds.counters()[0]
     lsds.set_verify_timing(False)
-    windows, committed, rejections, frames = (int(v) for v in cn)
+    windows, committed, rejections, frames, builds = (int(v) for v in cn)
     assert windows == args.steps
     log(f"LSD: {committed} steps in {t_lsd * 1e3:.1f} ms over {windows} windows; "
         f"rejections {rejections}; verify {ver_ms / max(ver_n, 1) * 1e3:.1f} us/launch")
@@ -245,6 +245,7 @@ def main():
         },
         "acceptance": round(1.0 - rejections / max(committed, 1), 5),
         "committed_per_window": round(committed / windows, 4),
+        "list_builds_per_window": round(builds / windows, 4),
         "plain_steps_per_s": round(plain_rate, 3),
         "lsd_over_plain": round(value / plain_rate, 5),
         "tau_per_day_lsd": round(value * w.dt * 86400.0, 2),

@@ -80,8 +80,20 @@ typedef enum { LSD_MODE_LSD = 0, LSD_MODE_PLAIN = 1 } lsd_mode;
 typedef enum {
   LSD_POT_LJ = 1,       /* truncated, energy-shifted Lennard-Jones */
   LSD_POT_HARMONIC = 2, /* tether U = k/2 |q - anchor|^2 (minimum image) */
-  LSD_POT_MPNN = 3      /* message-passing network (target only), below */
+  LSD_POT_MPNN = 3,     /* message-passing network (target only), below */
+  LSD_POT_PAIR = 4      /* force-matched pair draft (draft only), below */
 } lsd_pot_kind;
+
+/* Pair-force draft (the fallback of a learned draft: a potential lighter
+ * than the target, fitted to its forces; LSD admits any draft, Sec. 3).
+ * Central force per unordered species pair t = {s_i, s_j}:
+ *   F_i = - sum_(j, image) f_t(r) d / r,  d = q_j + n L - q_i, r = |d| < rc,
+ *   f_t(r) = (cos(pi r/rc) + 1)/2 * sum_{b=1..B} w[t][b-1] sin(b pi r/rc) / r,
+ * with types ordered (0,0), (0,1), .., (0,S-1), (1,1), .. (S = n_model_species,
+ * S(S+1)/2 types).  Weights: device binary32 [S(S+1)/2][B], kept by pointer.
+ * Forces only: the draft energy is never needed.  The weights come from
+ * force matching: lsd_fit_pair_accumulate / lsd_fit_pair_solve. */
+#define LSD_PAIR_MAX_BASIS 32
 
 /* Message-passing potential (a stand-in for the paper's interatomic
  * potentials; architecture fixed here): radial basis
@@ -109,9 +121,10 @@ typedef struct {
   const float *anchor;       /* tether anchors, device [3][N] (kept by pointer) */
   const float *force_offset; /* optional constant force field added to the
                                 forces, device [3][N] or NULL (test drafts) */
-  const float *weights;      /* MPNN: flat weights (device, kept by pointer) */
-  int32_t n_model_species;   /* MPNN: species rows of W_emb (>= n_species) */
+  const float *weights;      /* MPNN / PAIR: flat weights (device, kept by pointer) */
+  int32_t n_model_species;   /* MPNN: species rows of W_emb; PAIR: S (>= n_species) */
   double energy_scale;       /* MPNN: s_E */
+  int32_t n_basis;           /* PAIR: B, 1 .. LSD_PAIR_MAX_BASIS */
 } lsd_potential;
 
 typedef struct {
@@ -141,6 +154,12 @@ typedef struct {
                                   cache starts at 0.  Target forces and the
                                   acceptance rule are unchanged, so the target
                                   law is preserved. */
+  int32_t no_list_reuse;       /* 0 (default): the neighbour lists of a
+                                  replica are kept across windows until one of
+                                  its atoms has moved more than skin/4 from
+                                  the positions they were built at; != 0:
+                                  rebuilt at every window.  Committed results
+                                  differ only in summation order. */
 } lsd_config;
 
 typedef struct {
@@ -220,13 +239,16 @@ LSD_API lsd_status lsd_run_windows(lsd_system *sys, int32_t n_windows, int32_t K
 LSD_API lsd_status lsd_set_graphs(lsd_system *sys, int32_t enable);
 
 /* Byte offsets into the workspace of the window and list arrays (host). */
-/* Window frames: frame 0 holds the first midpoints wrapped into the box
- * (the neighbour lists and their image codes are built from them); frames
- * 1..K-1 are continuous with frame 0 (not wrapped), so an atom near a face
- * may sit up to skin/2 outside [0, L).  The commit wraps positions and
- * updates the image counters.  Caller-written frames must follow the same
- * convention; a frame in which an atom moved more than skin/2 from frame 0
- * (a wrapped jump included) is not verified. */
+/* Window frames are continuous with the positions the neighbour lists (and
+ * their image codes) were built at: those are the wrapped first midpoints of
+ * the window in which the lists were last rebuilt.  Frame 0 is the first
+ * midpoint, shifted by whole box edges to lie next to those positions, and
+ * frames 1..K-1 follow it without wrapping, so an atom near a face may sit up
+ * to skin/2 outside [0, L).  The commit wraps positions and updates the image
+ * counters.  lsd_mark_drafted rebuilds the lists from the caller's frame 0,
+ * which must be wrapped into [0, L); the caller's later frames must be
+ * continuous with it.  A frame in which an atom moved more than skin/2 from
+ * the list positions (a wrapped jump included) is not verified. */
 typedef struct {
   size_t q_mid;      /* float4 [k_max][N]: x, y, z, packed image deltas of
                         frame 0 relative to the committed counters */
@@ -262,9 +284,11 @@ LSD_API lsd_status lsd_get_status(lsd_system *sys, int32_t *flags, lsd_stream st
 LSD_API lsd_status lsd_set_step_limit(lsd_system *sys, int64_t limit);
 
 /* Per-replica counters since init or the last reset, copied to host
- * out[R][4] = {windows, committed steps, rejections (windows ending in a
- * reflected step), frames verified}.  The empirical rejection rate of the
- * paper (Sec. 3.3) is rejections / committed.  Synchronises `stream`. */
+ * out[R][LSD_NUM_COUNTERS] = {windows, committed steps, rejections (windows
+ * ending in a reflected step), frames verified, neighbour-list builds}.  The
+ * empirical rejection rate of the paper (Sec. 3.3) is rejections /
+ * committed.  Synchronises `stream`. */
+#define LSD_NUM_COUNTERS 5
 LSD_API lsd_status lsd_get_counters(lsd_system *sys, int64_t *out, lsd_stream stream);
 LSD_API lsd_status lsd_reset_counters(lsd_system *sys, lsd_stream stream);
 
@@ -282,6 +306,34 @@ LSD_API lsd_status lsd_rng_normals(uint64_t seed, int32_t replica, int64_t step,
                            int32_t n, double *out, lsd_stream stream);
 LSD_API lsd_status lsd_rng_uniforms(uint64_t seed, int32_t replica, int64_t step0,
                             int32_t count, double *out, lsd_stream stream);
+
+/* Force matching of the pair draft (fallback of the learned draft: fitted
+ * to forces the target itself produced).  With P = S(S+1)/2 * n_basis
+ * weights (S = n_species) in the order of the pair-draft weights, the
+ * extended normal equations G = [A | y]^T [A | y] are accumulated, where the
+ * rows of A are the pair-draft forces per unit weight of every atom and
+ * component of the valid frames (0 .. K_eff-1) of the current window at
+ * their midpoints q_mid, and y the forces of those frames: f_target
+ * (use_target_forces != 0: LSD mode, a verified window) or f_draft (the
+ * stepping forces; in PLAIN mode these are the target's).  Pairs are taken
+ * within `cutoff` (<= the target cutoff; the target list is used).
+ *   gram: device binary64 [(P+1)][(P+1)] row-major, accumulated (+=) in a
+ *         fixed order; zero it before the first call.  Column P = A^T y.
+ *   scratch: device memory of lsd_fit_pair_scratch_size bytes.
+ * Needs S * n_basis <= 64.  Asynchronous on `stream`.  Errors: INVALID_ARG,
+ * BAD_STATE (no drafted window, or no target forces), CAPACITY, HIP. */
+LSD_API lsd_status lsd_fit_pair_scratch_size(const lsd_system *sys, int32_t n_basis,
+                                             size_t *bytes);
+LSD_API lsd_status lsd_fit_pair_accumulate(lsd_system *sys, int32_t n_basis, double cutoff,
+                                           int32_t use_target_forces, void *scratch,
+                                           size_t scratch_bytes, double *gram,
+                                           lsd_stream stream);
+/* Host: weights (host binary64 [P]) minimising |A w - y|^2 + lambda |w|^2
+ * from the normal equations `gram` (host copy, layout above), with
+ * lambda = ridge * trace(A^T A) / P, by Cholesky factorisation.
+ * INVALID_ARG if the system is not positive definite (raise the ridge). */
+LSD_API lsd_status lsd_fit_pair_solve(const double *gram, int32_t n_params, double ridge,
+                                      double *weights);
 
 /* Releases the handle and its HIP events (no device memory is freed). */
 LSD_API lsd_status lsd_destroy(lsd_system *sys);

@@ -96,6 +96,9 @@ def _declare(L):
     if hasattr(L, "ora_mpnn_energy_forces"):
         from . import mpnn as _m
         _m.declare(L)
+    if hasattr(L, "ora_pair_forces"):
+        from . import pair as _p
+        _p.declare(L)
 
 
 def _d(a):

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "lsd.h"
+#include "fit.h"
 #include "lsd_launch.h"
 #include "mpnn.h"
 
@@ -57,7 +58,7 @@ struct Layout {
   size_t tile_start, tile_count, tile_rep, rep_tile_off;
   // cells and lists
   size_t cell_rep, cell_count, cell_start, cell_cursor, cell_unsorted, cell_atoms, atom_cell;
-  size_t nbr_t, cnt_t, nbr_d, cnt_d;
+  size_t nbr_t, cnt_t, nbr_d, cnt_d, qref, qwrap, rebuild;
   // window
   size_t qmid, p, fd, ft, invalid, partial, commit_frame, reflected, coef, counters, status;
   size_t ec = 0;  // error-correction cache (0: off)
@@ -80,7 +81,8 @@ bool is_binary32(double v) { return (double)(float)v == v; }
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 double pot_reach(const lsd_potential& P) {
-  return (P.kind == LSD_POT_LJ || P.kind == LSD_POT_MPNN) ? P.cutoff : 0.0;
+  return (P.kind == LSD_POT_LJ || P.kind == LSD_POT_MPNN || P.kind == LSD_POT_PAIR) ? P.cutoff
+                                                                                    : 0.0;
 }
 
 constexpr size_t kBlasWorkspace = 64ull << 20;
@@ -95,6 +97,11 @@ lsd_status check_potential(const lsd_potential& P, const char* what) {
   } else if (P.kind == LSD_POT_MPNN) {
     if (!(P.cutoff > 0.0) || !P.weights || P.n_model_species < 1 || !std::isfinite(P.energy_scale))
       return fail(LSD_ERR_INVALID_ARG, "%s: network needs cutoff > 0, weights, species", what);
+  } else if (P.kind == LSD_POT_PAIR) {
+    if (!(P.cutoff > 0.0) || !P.weights || P.n_model_species < 1 ||
+        P.n_model_species > LSD_MAX_SPECIES || P.n_basis < 1 || P.n_basis > LSD_PAIR_MAX_BASIS)
+      return fail(LSD_ERR_INVALID_ARG, "%s: pair draft needs cutoff > 0, weights, 1..%d species "
+                  "and 1..%d basis functions", what, LSD_MAX_SPECIES, LSD_PAIR_MAX_BASIS);
   } else {
     return fail(LSD_ERR_UNSUPPORTED, "%s: potential kind %d not supported", what, P.kind);
   }
@@ -130,6 +137,12 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   if (c->mode == LSD_MODE_LSD) LSD_TRY(check_potential(c->draft, "draft"));
   if (c->mode == LSD_MODE_LSD && c->draft.kind == LSD_POT_MPNN)
     return fail(LSD_ERR_UNSUPPORTED, "the message-passing network is supported as target only");
+  if (c->target.kind == LSD_POT_PAIR)
+    return fail(LSD_ERR_UNSUPPORTED, "the pair draft is supported as draft only");
+  if (c->mode == LSD_MODE_LSD && c->draft.kind == LSD_POT_PAIR &&
+      c->draft.n_model_species < c->n_species)
+    return fail(LSD_ERR_INVALID_ARG, "pair draft has %d species, system has %d",
+                c->draft.n_model_species, c->n_species);
   if (c->target.kind == LSD_POT_MPNN && c->target.n_model_species < c->n_species)
     return fail(LSD_ERR_INVALID_ARG, "network embeds %d species, system has %d",
                 c->target.n_model_species, c->n_species);
@@ -215,6 +228,9 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   L->cnt_t = bump(&off, n * 4);
   L->nbr_d = bump(&off, (size_t)L->md * n * 4);
   L->cnt_d = bump(&off, n * 4);
+  L->qref = bump(&off, n * 16);
+  L->qwrap = bump(&off, n * 16);
+  L->rebuild = bump(&off, (size_t)R * 4);
   L->qmid = bump(&off, K * n * 16);
   L->p = bump(&off, (K + 1) * 3 * n * 4);
   L->fd = bump(&off, K * 3 * n * 4);
@@ -224,7 +240,7 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   L->commit_frame = bump(&off, R * 4);
   L->reflected = bump(&off, R * 4);
   L->coef = bump(&off, R * 8);
-  L->counters = bump(&off, (size_t)R * 4 * 8);
+  L->counters = bump(&off, (size_t)R * LSD_NCOUNT * 8);
   L->status = bump(&off, 4 * 4);
   if (c->error_correction && c->mode == LSD_MODE_LSD) L->ec = bump(&off, 3 * n * 4);
   L->has_mpnn = c->target.kind == LSD_POT_MPNN;
@@ -262,6 +278,12 @@ PotDev make_pot(const lsd_potential& P, const Layout& L) {
   } else if (P.kind == LSD_POT_HARMONIC) {
     d.kspring = (float)P.k_spring;
     d.anchor = P.anchor;
+  } else if (P.kind == LSD_POT_PAIR) {
+    d.rc2 = (float)(P.cutoff * P.cutoff);
+    d.pi_rc = (float)(M_PI / P.cutoff);
+    d.nb = P.n_basis;
+    d.ns = P.n_model_species;
+    d.w = P.weights;
   }
   return d;
 }
@@ -356,7 +378,7 @@ hipError_t enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
     e = launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st);
   }
   if ((part == PART_FULL || part == PART_POST) && e == hipSuccess) {
-    e = launch_decide(s->S, s->W, s->T, s->O, plain ? 1 : 0, st);
+    e = launch_decide(s->S, s->Lst, s->W, s->T, s->O, plain ? 1 : 0, st);
     if (e == hipSuccess) e = launch_commit(s->S, s->W, s->buf.q, s->buf.p, s->buf.img, st);
   }
   return e;
@@ -446,9 +468,10 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.status), 0, 4, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.invalid), 0, R * cfg->k_max, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_t), 0, N, st);
-  if (e == hipSuccess) e = launch_zero_i64(ws<long long>(s, L.counters), 4 * R, st);
+  if (e == hipSuccess) e = launch_zero_i64(ws<long long>(s, L.counters), LSD_NCOUNT * R, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_d), 0, N, st);
   if (e == hipSuccess && L.ec) e = launch_fill_int(ws<int>(s, L.ec), 0, 3 * N, st);  // +0.0f
+  if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.rebuild), 1, R, st);  // first window builds
   if (e == hipSuccess) e = prepare_verify(L.mt);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
@@ -504,6 +527,12 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   Ls.rl2_t = L.rl_t * L.rl_t;
   Ls.rl2_d = L.rl_d * L.rl_d;
   Ls.status = ws<int>(s, L.status);
+  Ls.qref = ws<float4>(s, L.qref);
+  Ls.qwrap = ws<float4>(s, L.qwrap);
+  Ls.rebuild = ws<int>(s, L.rebuild);
+  const double qs = 0.25 * cfg->skin * (1.0 - 1e-4);
+  Ls.reuse2 = (float)(qs * qs);
+  Ls.always_rebuild = cfg->no_list_reuse ? 1 : 0;
 
   WinDev& W = s->W;
   memset(&W, 0, sizeof(W));
@@ -589,8 +618,9 @@ lsd_status lsd_mark_drafted(lsd_system* s, int32_t K, lsd_stream stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   s->W.K = K;
   HIP_TRY(launch_fill_int(s->W.invalid, 0, s->S.R * s->S.kmax, st));
+  HIP_TRY(launch_fill_int(s->Lst.rebuild, 1, s->S.R, st));  // lists from the caller's frame 0
   HIP_TRY(launch_build_lists(s->S, s->Lst, s->W, true, st));
-  HIP_TRY(launch_frame_validity(s->S, s->W, st));
+  HIP_TRY(launch_frame_validity(s->S, s->Lst, s->W, st));
   s->state = ST_DRAFTED;
   return LSD_OK;
 }
@@ -633,7 +663,7 @@ lsd_status lsd_accept_rollback(lsd_system* s, int32_t* n_host, lsd_stream stream
   if (!(s->state == ST_VERIFIED || (plain && s->state == ST_DRAFTED)))
     return fail(LSD_ERR_BAD_STATE, "accept_rollback needs a verified window");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIP_TRY(launch_decide(s->S, s->W, s->T, s->O, plain ? 1 : 0, st));
+  HIP_TRY(launch_decide(s->S, s->Lst, s->W, s->T, s->O, plain ? 1 : 0, st));
   HIP_TRY(launch_commit(s->S, s->W, s->buf.q, s->buf.p, s->buf.img, st));
   s->state = ST_COMMITTED;
   if (n_host) {
@@ -729,14 +759,15 @@ lsd_status lsd_set_step_limit(lsd_system* s, int64_t limit) {
 lsd_status lsd_get_counters(lsd_system* s, int64_t* out, lsd_stream stream) {
   if (!s || !out) return fail(LSD_ERR_INVALID_ARG, "null argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIP_TRY(hipMemcpyAsync(out, s->W.counters, sizeof(int64_t) * 4 * s->S.R, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(out, s->W.counters, sizeof(int64_t) * LSD_NCOUNT * s->S.R,
+                          hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return LSD_OK;
 }
 
 lsd_status lsd_reset_counters(lsd_system* s, lsd_stream stream) {
   if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
-  HIP_TRY(launch_zero_i64(s->W.counters, 4 * s->S.R, static_cast<hipStream_t>(stream)));
+  HIP_TRY(launch_zero_i64(s->W.counters, LSD_NCOUNT * s->S.R, static_cast<hipStream_t>(stream)));
   return LSD_OK;
 }
 
@@ -776,6 +807,90 @@ lsd_status lsd_rng_uniforms(uint64_t seed, int32_t replica, int64_t step0, int32
                             double* out, lsd_stream stream) {
   if (!out || count < 0 || replica < 0) return fail(LSD_ERR_INVALID_ARG, "bad rng arguments");
   HIP_TRY(launch_rng_uniforms(seed, replica, step0, count, out, static_cast<hipStream_t>(stream)));
+  return LSD_OK;
+}
+
+lsd_status lsd_fit_pair_scratch_size(const lsd_system* s, int32_t n_basis, size_t* bytes) {
+  if (!s || !bytes) return fail(LSD_ERR_INVALID_ARG, "null argument");
+  if (n_basis < 1 || n_basis > LSD_PAIR_MAX_BASIS)
+    return fail(LSD_ERR_INVALID_ARG, "n_basis %d outside 1..%d", n_basis, LSD_PAIR_MAX_BASIS);
+  FitDev F;
+  F.ns = s->cfg.n_species;
+  F.nb = n_basis;
+  F.LP = F.ns * n_basis;
+  if (F.LP > FIT_MAX_LP)
+    return fail(LSD_ERR_UNSUPPORTED, "species x basis = %d > %d", F.LP, FIT_MAX_LP);
+  *bytes = (size_t)s->S.n_tiles * fit_partial_entries(F) * sizeof(double);
+  return LSD_OK;
+}
+
+lsd_status lsd_fit_pair_accumulate(lsd_system* s, int32_t n_basis, double cutoff,
+                                   int32_t use_target_forces, void* scratch, size_t scratch_bytes,
+                                   double* gram, lsd_stream stream) {
+  if (!s || !scratch || !gram) return fail(LSD_ERR_INVALID_ARG, "null argument");
+  size_t need = 0;
+  LSD_TRY(lsd_fit_pair_scratch_size(s, n_basis, &need));
+  if (scratch_bytes < need)
+    return fail(LSD_ERR_CAPACITY, "fit scratch %zu bytes < required %zu", scratch_bytes, need);
+  if (s->state == ST_READY || s->W.K < 1)
+    return fail(LSD_ERR_BAD_STATE, "fit needs a drafted window");
+  if (use_target_forces &&
+      !(s->cfg.mode == LSD_MODE_LSD && (s->state == ST_VERIFIED || s->state == ST_COMMITTED)))
+    return fail(LSD_ERR_BAD_STATE, "target forces exist only for a verified window (LSD mode)");
+  if (!(cutoff > 0.0) || cutoff > pot_reach(s->cfg.target))
+    return fail(LSD_ERR_INVALID_ARG, "fit cutoff %g must be in (0, target cutoff %g]", cutoff,
+                pot_reach(s->cfg.target));
+  FitDev F;
+  F.rc2 = (float)(cutoff * cutoff);
+  F.pi_rc = (float)(M_PI / cutoff);
+  F.nb = n_basis;
+  F.ns = s->cfg.n_species;
+  F.LP = F.ns * n_basis;
+  HIP_TRY(launch_fit(s->S, s->Lst, s->W, s->T, F, use_target_forces ? 1 : 0,
+                     static_cast<double*>(scratch), gram, static_cast<hipStream_t>(stream)));
+  return LSD_OK;
+}
+
+lsd_status lsd_fit_pair_solve(const double* gram, int32_t n_params, double ridge, double* weights) {
+  if (!gram || !weights || n_params < 1) return fail(LSD_ERR_INVALID_ARG, "bad argument");
+  if (!(ridge >= 0.0)) return fail(LSD_ERR_INVALID_ARG, "ridge must be >= 0");
+  const int P = n_params, Pe = P + 1;
+  double tr = 0.0;
+  for (int c = 0; c < P; ++c) tr += gram[(size_t)c * Pe + c];
+  const double lam = ridge * (tr > 0.0 ? tr / P : 1.0);
+  std::vector<double> A((size_t)P * P), b(P);
+  for (int r = 0; r < P; ++r) {
+    for (int c = 0; c < P; ++c)
+      A[(size_t)r * P + c] = 0.5 * (gram[(size_t)r * Pe + c] + gram[(size_t)c * Pe + r]);
+    A[(size_t)r * P + r] += lam;
+    b[r] = 0.5 * (gram[(size_t)r * Pe + P] + gram[(size_t)P * Pe + r]);
+  }
+  // Cholesky A = L L^T (lower triangle in place), then two triangular solves
+  for (int j = 0; j < P; ++j) {
+    double d = A[(size_t)j * P + j];
+    for (int k = 0; k < j; ++k) d -= A[(size_t)j * P + k] * A[(size_t)j * P + k];
+    if (!(d > 0.0))
+      return fail(LSD_ERR_INVALID_ARG, "normal equations not positive definite (pivot %d); "
+                  "raise the ridge", j);
+    const double ljj = std::sqrt(d);
+    A[(size_t)j * P + j] = ljj;
+    for (int i = j + 1; i < P; ++i) {
+      double v = A[(size_t)i * P + j];
+      for (int k = 0; k < j; ++k) v -= A[(size_t)i * P + k] * A[(size_t)j * P + k];
+      A[(size_t)i * P + j] = v / ljj;
+    }
+  }
+  for (int i = 0; i < P; ++i) {
+    double v = b[i];
+    for (int k = 0; k < i; ++k) v -= A[(size_t)i * P + k] * b[k];
+    b[i] = v / A[(size_t)i * P + i];
+  }
+  for (int i = P - 1; i >= 0; --i) {
+    double v = b[i];
+    for (int k = i + 1; k < P; ++k) v -= A[(size_t)k * P + i] * b[k];
+    b[i] = v / A[(size_t)i * P + i];
+  }
+  for (int i = 0; i < P; ++i) weights[i] = b[i];
   return LSD_OK;
 }
 

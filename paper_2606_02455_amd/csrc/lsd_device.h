@@ -14,9 +14,11 @@
 #define LSD_TILE 64           // atoms per verification tile
 #define LSD_LPA 4             // lanes per atom in the force loops
 #define LSD_MAX_K 64
+#define LSD_NCOUNT 5          // per-replica counters (see WinDev::counters)
 #define LSD_POT_LJ 1
 #define LSD_POT_HARMONIC 2
 #define LSD_POT_MPNN 3
+#define LSD_POT_PAIR 4
 
 // status word bits
 #define LSD_STATUS_NBR_TARGET 1
@@ -32,7 +34,17 @@ struct PotDev {
   float kspring;
   const float* anchor;    // [3][N]
   const float* offset;    // [3][N] or null
+  // pair draft: rc2 above, pi / rc, basis size, species, weights [T][nb]
+  float pi_rc;
+  int nb, ns;
+  const float* w;
 };
+
+// index of the unordered species pair {a, b} among S(S+1)/2 types
+__host__ __device__ __forceinline__ int pair_type(int a, int b, int S) {
+  const int lo = a < b ? a : b, hi = a < b ? b : a;
+  return lo * S - lo * (lo - 1) / 2 + (hi - lo);
+}
 
 struct SysDev {
   int n, R, n_tiles, kmax;
@@ -68,6 +80,15 @@ struct ListDev {
   uint32_t* nbr_d; int* cnt_d; int md;   // draft list, atom-major [N][md]
   double rl2_t, rl2_d;      // list radii squared (binary64)
   int* status;
+  // reuse across windows: the lists hold for positions within skin/2 of the
+  // positions they were built at; window frames are kept continuous with
+  // those positions, and a replica rebuilds when an atom's first midpoint is
+  // more than skin/4 away from them
+  float4* qref;             // [N] list positions (wrapped), image deltas unused
+  float4* qwrap;            // [N] wrapped first midpoints of the current window
+  int* rebuild;             // [R] 1: rebuild this replica's lists in this window
+  float reuse2;             // (skin/4)^2, slightly reduced
+  int always_rebuild;       // 1: rebuild every window
 };
 
 struct WinDev {
@@ -81,7 +102,8 @@ struct WinDev {
   int* reflected;     // [R]
   double* coef;       // [R] 2 S1 / S2 of the rejected frame
   float* ec;          // [3][N] error-correction cache dF, or null (off)
-  long long* counters;  // [R][4]: windows, committed steps, rejections, frames verified
+  long long* counters;  // [R][5]: windows, committed steps, rejections, frames verified,
+                        // neighbour-list builds
   int K;              // frames in the current window
 };
 
@@ -258,6 +280,52 @@ __device__ __forceinline__ bool lj_pair(const PotDev& P, float4 xi, float4 xj, c
   fz -= fs * dz;
   e += 0.5f * (P.eps4 * s6 * (s6 - 1.0f) - P.eshift);
   return true;
+}
+
+// Basis values sin(b pi r / rc), b = 1..nb, by the Chebyshev recurrence
+// sin((b+1) t) = 2 cos(t) sin(b t) - sin((b-1) t); returns cos(pi r / rc).
+__device__ __forceinline__ float pair_basis(float pi_rc, float r, int nb, float* sb) {
+  float s, c;
+  sincosf(pi_rc * r, &s, &c);
+  float prev = 0.0f, cur = s;
+  const float two_c = 2.0f * c;
+  sb[0] = s;
+  for (int b = 1; b < nb; ++b) {
+    const float nx = two_c * cur - prev;
+    prev = cur;
+    cur = nx;
+    sb[b] = cur;
+  }
+  return c;
+}
+
+// Pair-draft force on i from image n of j (species spi, spj):
+// -f_t(r) d / r with f_t(r) = f_c(r) sum_b w[t][b] sin(b pi r / rc) / r.
+__device__ __forceinline__ void pair_draft_force(const PotDev& P, float4 xi, float4 xj,
+                                                 const float* sj, const float* si, int spi,
+                                                 int spj, float& fx, float& fy, float& fz) {
+  const float dx = sep(xj.x, sj[0], xi.x, si[0]);
+  const float dy = sep(xj.y, sj[1], xi.y, si[1]);
+  const float dz = sep(xj.z, sj[2], xi.z, si[2]);
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  if (r2 >= P.rc2) return;
+  const float r = sqrtf(r2);
+  const float inv_r = 1.0f / r;
+  const float* w = P.w + pair_type(spi, spj, P.ns) * P.nb;
+  float s, c;
+  sincosf(P.pi_rc * r, &s, &c);
+  float prev = 0.0f, cur = s, acc = w[0] * s;
+  const float two_c = 2.0f * c;
+  for (int b = 1; b < P.nb; ++b) {
+    const float nx = two_c * cur - prev;
+    prev = cur;
+    cur = nx;
+    acc += w[b] * cur;
+  }
+  const float g = 0.5f * (c + 1.0f) * acc * inv_r * inv_r;  // f_t(r) / r
+  fx -= g * dx;
+  fy -= g * dy;
+  fz -= g * dz;
 }
 
 // per image code: sj = min(n,0) L, si = max(n,0) L for x, y, z

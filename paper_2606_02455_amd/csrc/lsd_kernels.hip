@@ -23,8 +23,24 @@ __global__ void k_fill_int(int* p, int v, int n) {
   if (i < n) p[i] = v;
 }
 
-// Midpoint of the first draft step from the committed state, copy of the
-// committed momenta into the window, and cell binning of the midpoints.
+// Sets flags[r] = 1 for every replica r of a lane with `need`, with one
+// atomic per distinct replica in the wave (lanes that left early take no
+// part).
+__device__ __forceinline__ void flag_replicas(bool need, int r, int* flags) {
+  unsigned long long m = __ballot(need);
+  const int lane = threadIdx.x & 63;
+  while (m) {
+    const int leader = __ffsll((long long)m) - 1;
+    const int rl = __shfl(r, leader, 64);
+    if (lane == leader) atomicOr(&flags[rl], 1);
+    m &= ~__ballot(need && r == rl);
+  }
+}
+
+// Midpoint of the first draft step from the committed state and copy of the
+// committed momenta into the window.  Frame 0 is written continuous with the
+// list positions (so the image codes of the lists stay valid); a replica
+// whose atoms moved too far from them is flagged for a rebuild.
 __global__ __launch_bounds__(256) void k_window_start(SysDev S, ListDev Lst, WinDev W,
                                                       const float* __restrict__ q,
                                                       const float* __restrict__ p) {
@@ -47,29 +63,47 @@ __global__ __launch_bounds__(256) void k_window_start(SysDev S, ListDev Lst, Win
     W.p[d * S.n + i] = pd;
     x[d] = a_half(q[d * S.n + i], pd, hm, L, &dimg[d]);
   }
-  W.qmid[i] = make_float4(x[0], x[1], x[2], pack_img(dimg[0], dimg[1], dimg[2]));
-  // cell of the midpoint
-  const int nc = Lst.rep_nc[r];
-  int c[3];
-  const float inv_w = (float)((double)nc / L);
+  const float4 xw = make_float4(x[0], x[1], x[2], pack_img(dimg[0], dimg[1], dimg[2]));
+  Lst.qwrap[i] = xw;
+  if (Lst.always_rebuild) {
+    W.qmid[i] = xw;
+    return;
+  }
+  // continuous with the list positions: both lie in [0, L), so at most one
+  // box edge separates the nearest images
+  const float4 xr = Lst.qref[i];
+  const float xrs[3] = {xr.x, xr.y, xr.z};
+  const float half = (float)(0.5 * L);
+  float d2 = 0.0f;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    int v = (int)(x[d] * inv_w);
-    c[d] = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
+    const float dd0 = x[d] - xrs[d];
+    const int n = dd0 > half ? 1 : (dd0 < -half ? -1 : 0);
+    if (n != 0) {
+      x[d] = (float)((double)x[d] - (double)n * L);
+      dimg[d] += n;
+    }
+    const float dd = x[d] - xrs[d];
+    d2 += dd * dd;
   }
-  const int cell = Lst.rep_cell_off[r] + c[0] + nc * (c[1] + nc * c[2]);
-  Lst.atom_cell[i] = cell;
-  atomicAdd(&Lst.cell_count[cell], 1);
+  W.qmid[i] = make_float4(x[0], x[1], x[2], pack_img(dimg[0], dimg[1], dimg[2]));
+  flag_replicas(d2 > Lst.reuse2 && Lst.rebuild[r] == 0, r, Lst.rebuild);
 }
 
-// Cell binning only (lists rebuilt from caller-written frame 0).
-__global__ __launch_bounds__(256) void k_bin_frame0(SysDev S, ListDev Lst, WinDev W) {
+// For replicas flagged for a rebuild: frame 0 becomes the wrapped midpoints
+// (or stays the caller's frame 0), the list positions are reset to them, and
+// they are binned into cells.
+__global__ __launch_bounds__(256) void k_rebuild_bin(SysDev S, ListDev Lst, WinDev W,
+                                                     int caller_frame0) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.n) return;
   const int r = S.atom_rep[i];
+  if (!Lst.rebuild[r]) return;
   const double L = S.box[r];
-  float4 xq = W.qmid[i];
-  float x[3] = {xq.x, xq.y, xq.z};
+  const float4 xq = caller_frame0 ? W.qmid[i] : Lst.qwrap[i];
+  W.qmid[i] = xq;
+  Lst.qref[i] = xq;
+  const float x[3] = {xq.x, xq.y, xq.z};
   const int nc = Lst.rep_nc[r];
   const float inv_w = (float)((double)nc / L);
   int c[3];
@@ -111,9 +145,11 @@ __global__ __launch_bounds__(1024) void k_cell_scan(ListDev Lst) {
   if (t == 1023) Lst.cell_start[C] = s[1023];
 }
 
-__global__ __launch_bounds__(256) void k_cell_fill(int n, ListDev Lst) {
+__global__ __launch_bounds__(256) void k_cell_fill(int n, const int* __restrict__ atom_rep,
+                                                   ListDev Lst) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (!Lst.rebuild[atom_rep[i]]) return;
   int c = Lst.atom_cell[i];
   int pos = Lst.cell_start[c] + atomicAdd(&Lst.cell_cursor[c], 1);
   Lst.cell_unsorted[pos] = i;
@@ -124,6 +160,7 @@ __global__ __launch_bounds__(256) void k_cell_fill(int n, ListDev Lst) {
 // the binning atomics were served
 __global__ __launch_bounds__(64) void k_cell_sort(ListDev Lst) {
   const int c = blockIdx.x;
+  if (!Lst.rebuild[Lst.cell_rep[c]]) return;
   const int lo = Lst.cell_start[c], hi = Lst.cell_start[c + 1];
   for (int e = lo + (int)threadIdx.x; e < hi; e += 64) {
     const int v = Lst.cell_unsorted[e];
@@ -151,6 +188,7 @@ __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev 
   const int c = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int r = Lst.cell_rep[c];
+  if (!Lst.rebuild[r]) return;  // uniform over the block
   const int nc = Lst.rep_nc[r];
   const int coff = Lst.rep_cell_off[r];
   const int lo = Lst.cell_start[c], hi = Lst.cell_start[c + 1];
@@ -287,6 +325,19 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
     fy = lpa_sum(fy);
     fz = lpa_sum(fz);
     e = lpa_sum(e);
+  } else if (P.kind == LSD_POT_PAIR) {
+    const int spi = S.species ? S.species[i] : 0;
+    for (int m = sub; m < cnt; m += LSD_LPA) {
+      const uint32_t ent = row[m];
+      const int j = (int)(ent >> 5), code = (int)(ent & 31u);
+      const float4 xj = X[j];
+      float sj[3], si[3];
+      image_shifts(code, Lf, sj, si);
+      pair_draft_force(P, xi, xj, sj, si, spi, S.species ? S.species[j] : 0, fx, fy, fz);
+    }
+    fx = lpa_sum(fx);
+    fy = lpa_sum(fy);
+    fz = lpa_sum(fz);
   } else if (P.kind == LSD_POT_HARMONIC) {
     float d[3] = {xi.x - P.anchor[i], xi.y - P.anchor[S.n + i], xi.z - P.anchor[2 * S.n + i]};
 #pragma unroll
@@ -371,20 +422,21 @@ __global__ __launch_bounds__(256) void k_draft(SysDev S, ListDev Lst, WinDev W, 
     }
     // frames stay continuous with frame 0, so frame 0's image deltas apply
     W.qmid[(size_t)(k + 1) * N + i] = make_float4(xn[0], xn[1], xn[2], x.w);
-    // displacement from the list positions (frame 0)
-    const float4 x0 = W.qmid[i];
+    // displacement from the list positions
+    const float4 x0 = Lst.qref[i];
     const float dx = xn[0] - x0.x, dy = xn[1] - x0.y, dz = xn[2] - x0.z;
     const float d2 = dx * dx + dy * dy + dz * dz;
     if (d2 > S.half_skin2 && inv[k + 1] == 0) atomicOr(&inv[k + 1], 1);
   }
 }
 
+
 // Validity of caller-written frames against the frame-0 lists.
-__global__ __launch_bounds__(256) void k_frame_validity(SysDev S, WinDev W) {
+__global__ __launch_bounds__(256) void k_frame_validity(SysDev S, ListDev Lst, WinDev W) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.n) return;
   const int r = S.atom_rep[i];
-  const float4 x0 = W.qmid[i];
+  const float4 x0 = Lst.qref[i];
   int* inv = W.invalid + (size_t)r * S.kmax;
   if (i == S.rep_off[r])
     for (int k = 0; k < W.K; ++k)
@@ -567,26 +619,30 @@ __global__ __launch_bounds__(64) void k_transport(SysDev S, WinDev W, TileDev Tl
 
 // Per replica: frame sums over its tiles (fixed order), log ratio, decision
 // with u_{s+k}, first rejection (Alg. 1), outputs and the commit record.
-__global__ __launch_bounds__(64) void k_decide(SysDev S, WinDev W, TileDev Tl, OutDev O, int plain) {
+// One block per replica; wave w handles frames w, w + nw, ... (the sum over
+// a frame's tiles is lane-strided plus the wave butterfly, whatever the
+// block size), then one thread scans the decisions for the first rejection.
+__global__ __launch_bounds__(1024) void k_decide(SysDev S, WinDev W, TileDev Tl, OutDev O, int plain,
+                                                 int* __restrict__ rebuild, int always_rebuild) {
+  __shared__ double s_s1[LSD_MAX_K], s_s2[LSD_MAX_K];
+  __shared__ int s_acc[LSD_MAX_K];
   const int r = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int K = W.K;
   const int* inv = W.invalid + (size_t)r * S.kmax;
   int keff = K;
   for (int f = 0; f < K; ++f)
     if (inv[f]) { keff = f; break; }
   const int t0 = Tl.rep_tile_off[r], t1 = Tl.rep_tile_off[r + 1];
-  int j = keff, reflected = 0;
-  double coef = 0.0;
   const uint64_t s0 = (uint64_t)S.step[r];
-  bool rejected = false;
-  for (int f = 0; f < K; ++f) {
+  for (int f = wave; f < K; f += nw) {
     const size_t o = (size_t)r * S.kmax + f;
     if (plain || f >= keff) {
       if (lane == 0) {
         O.accepted[o] = 2;
         O.log_ratio[o] = 0.0;
         O.energy[o] = 0.0;
+        s_acc[f] = 1;
       }
       continue;
     }
@@ -600,32 +656,44 @@ __global__ __launch_bounds__(64) void k_decide(SysDev S, WinDev W, TileDev Tl, O
     s1 = wave_sum(s1);
     s2 = wave_sum(s2);
     es = wave_sum(es);
-    const double logr = -s1 - 0.5 * s2;
-    const double u = S.replay_u ? S.replay_u[o] : stream_uniform(S.seed, (uint32_t)r, s0 + f + 1);
-    const bool acc = log(u) <= logr;
     if (lane == 0) {
+      const double logr = -s1 - 0.5 * s2;
+      const double u = S.replay_u ? S.replay_u[o] : stream_uniform(S.seed, (uint32_t)r, s0 + f + 1);
+      const bool acc = log(u) <= logr;
       O.accepted[o] = acc ? 1 : 0;
       O.log_ratio[o] = logr;
       O.energy[o] = es;
-    }
-    if (!acc && !rejected) {
-      rejected = true;
-      j = f + 1;
-      reflected = 1;
-      coef = 2.0 * s1 / s2;
+      s_acc[f] = acc ? 1 : 0;
+      s_s1[f] = s1;
+      s_s2[f] = s2;
     }
   }
-  if (lane == 0) {
-    long long* cn = W.counters + (size_t)r * 4;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int j = keff, reflected = 0;
+    double coef = 0.0;
+    if (!plain) {
+      for (int f = 0; f < keff; ++f)
+        if (!s_acc[f]) {
+          j = f + 1;
+          reflected = 1;
+          coef = 2.0 * s_s1[f] / s_s2[f];
+          break;
+        }
+    }
+    long long* cn = W.counters + (size_t)r * LSD_NCOUNT;
     cn[0] += 1;
     cn[1] += j;
     cn[2] += reflected;
     cn[3] += plain ? 0 : keff;
+    cn[4] += rebuild[r];
     O.n_committed[r] = j;
     W.commit_frame[r] = j - 1;
     W.reflected[r] = reflected;
     W.coef[r] = coef;
     S.step[r] = (int64_t)(s0 + (uint64_t)j);
+    // the next window decides afresh whether this replica's lists are rebuilt
+    rebuild[r] = always_rebuild;
   }
 }
 
@@ -720,12 +788,12 @@ hipError_t launch_window_start(const SysDev& S, const ListDev& L, const WinDev& 
   return hipGetLastError();
 }
 
-hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W, bool bin_frame0,
+hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W, bool caller_frame0,
                               hipStream_t st) {
-  if (bin_frame0)
-    hipLaunchKernelGGL(k_bin_frame0, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, L, W);
+  hipLaunchKernelGGL(k_rebuild_bin, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, L, W,
+                     caller_frame0 ? 1 : 0);
   hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, L);
-  hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S.n, L);
+  hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S.n, S.atom_rep, L);
   hipLaunchKernelGGL(k_cell_sort, dim3(L.n_cells), dim3(64), 0, st, L);
   dim3 grid(L.n_cells, (L.cell_cap + NL_IPB - 1) / NL_IPB);
   hipLaunchKernelGGL(k_nl_build, grid, dim3(256), 0, st, S, L, W);
@@ -746,8 +814,9 @@ hipError_t launch_transport(const SysDev& S, const WinDev& W, const TileDev& T, 
   return hipGetLastError();
 }
 
-hipError_t launch_frame_validity(const SysDev& S, const WinDev& W, hipStream_t st) {
-  hipLaunchKernelGGL(k_frame_validity, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, W);
+hipError_t launch_frame_validity(const SysDev& S, const ListDev& L, const WinDev& W,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_frame_validity, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, L, W);
   return hipGetLastError();
 }
 
@@ -778,9 +847,12 @@ hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, con
   return hipGetLastError();
 }
 
-hipError_t launch_decide(const SysDev& S, const WinDev& W, const TileDev& T, const OutDev& O,
-                         int plain, hipStream_t st) {
-  hipLaunchKernelGGL(k_decide, dim3(S.R), dim3(64), 0, st, S, W, T, O, plain);
+hipError_t launch_decide(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
+                         const OutDev& O, int plain, hipStream_t st) {
+  // one wave per frame up to 16 waves
+  const int waves = plain ? 1 : (W.K < 16 ? W.K : 16);
+  hipLaunchKernelGGL(k_decide, dim3(S.R), dim3(64 * waves), 0, st, S, W, T, O, plain, L.rebuild,
+                     L.always_rebuild);
   return hipGetLastError();
 }
 

@@ -7,18 +7,21 @@ hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
 hipError_t launch_zero_i64(long long* p, int n, hipStream_t st);
 hipError_t launch_window_start(const SysDev& S, const ListDev& L, const WinDev& W, const float* q,
                                const float* p, hipStream_t st);
-hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W, bool bin_frame0,
+// Rebuilds the cell and neighbour lists of the replicas flagged for it, from
+// the wrapped first midpoints or (caller_frame0) from the caller's frame 0.
+hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W, bool caller_frame0,
                               hipStream_t st);
 hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P, int k,
                         int use_target_list, hipStream_t st, int forces_given = 0);
 hipError_t launch_transport(const SysDev& S, const WinDev& W, const TileDev& T, const double* epart,
                             hipStream_t st);
-hipError_t launch_frame_validity(const SysDev& S, const WinDev& W, hipStream_t st);
+hipError_t launch_frame_validity(const SysDev& S, const ListDev& L, const WinDev& W,
+                                 hipStream_t st);
 hipError_t prepare_verify(int mt);
 hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                          const PotDev& P, int fw, hipStream_t st);
-hipError_t launch_decide(const SysDev& S, const WinDev& W, const TileDev& T, const OutDev& O,
-                         int plain, hipStream_t st);
+hipError_t launch_decide(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
+                         const OutDev& O, int plain, hipStream_t st);
 hipError_t launch_commit(const SysDev& S, const WinDev& W, float* q, float* p, int* img,
                          hipStream_t st);
 hipError_t launch_rng_normals(uint64_t seed, int replica, int64_t step, int n, double* out,

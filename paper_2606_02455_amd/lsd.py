@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblsd.so")
 
 LSD_OK = 0
 MODE_LSD, MODE_PLAIN = 0, 1
-POT_LJ, POT_HARMONIC, POT_MPNN = 1, 2, 3
+POT_LJ, POT_HARMONIC, POT_MPNN, POT_PAIR = 1, 2, 3, 4
 STATUS_NBR_TARGET, STATUS_NBR_DRAFT, STATUS_CELL = 1, 2, 4
 
 _LIB = None
@@ -28,11 +28,15 @@ class LSDError(RuntimeError):
         self.status = status
 
 
+NUM_COUNTERS = 5  # LSD_NUM_COUNTERS
+
+
 class Potential(C.Structure):
     _fields_ = [("kind", C.c_int32), ("cutoff", C.c_double), ("epsilon", C.c_double),
                 ("sigma", C.c_double), ("k_spring", C.c_double), ("anchor", C.c_void_p),
                 ("force_offset", C.c_void_p), ("weights", C.c_void_p),
-                ("n_model_species", C.c_int32), ("energy_scale", C.c_double)]
+                ("n_model_species", C.c_int32), ("energy_scale", C.c_double),
+                ("n_basis", C.c_int32)]
 
 
 class Config(C.Structure):
@@ -44,7 +48,7 @@ class Config(C.Structure):
                 ("k_max", C.c_int32), ("mode", C.c_int32), ("seed", C.c_uint64),
                 ("target", Potential), ("draft", Potential),
                 ("max_neighbors_target", C.c_int32), ("max_neighbors_draft", C.c_int32),
-                ("error_correction", C.c_int32)]
+                ("error_correction", C.c_int32), ("no_list_reuse", C.c_int32)]
 
 
 class Buffers(C.Structure):
@@ -85,6 +89,10 @@ EXPORTS = {
                         C.c_int),
     "lsd_rng_uniforms": ([C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p],
                          C.c_int),
+    "lsd_fit_pair_scratch_size": ([C.c_void_p, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
+    "lsd_fit_pair_accumulate": ([C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_void_p,
+                                 C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
+    "lsd_fit_pair_solve": ([C.c_void_p, C.c_int32, C.c_double, C.c_void_p], C.c_int),
     "lsd_destroy": ([C.c_void_p], C.c_int),
     "lsd_last_error": ([], C.c_char_p),
 }
@@ -119,6 +127,21 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def pair_params(n_species, n_basis):
+    """Number of pair-draft weights: S(S+1)/2 types x n_basis."""
+    return n_species * (n_species + 1) // 2 * n_basis
+
+
+def fit_pair_solve(gram, ridge=1e-8):
+    """Weights [P] from host normal equations [P+1, P+1] (lsd_fit_pair_solve)."""
+    g = np.ascontiguousarray(gram, dtype=np.float64)
+    P = g.shape[0] - 1
+    w = np.zeros(P)
+    _check(load().lsd_fit_pair_solve(g.ctypes.data_as(C.c_void_p), P, float(ridge),
+                                     w.ctypes.data_as(C.c_void_p)), "lsd_fit_pair_solve")
+    return w
+
+
 def rng_normals(seed, replica, step, n):
     import torch
     out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
@@ -144,7 +167,8 @@ class LSDSystem:
     """
 
     def __init__(self, workload, mode="lsd", k_max=None, target=None, draft=None, seed=None,
-                 skin=None, replay=False, max_neighbors=(0, 0), error_correction=False):
+                 skin=None, replay=False, max_neighbors=(0, 0), error_correction=False,
+                 list_reuse=True):
         import torch
         self.torch = torch
         lib = load()
@@ -178,6 +202,7 @@ class LSDSystem:
         cfg.draft = self._potential(dft) if self.mode == MODE_LSD else Potential()
         cfg.max_neighbors_target, cfg.max_neighbors_draft = max_neighbors
         cfg.error_correction = int(bool(error_correction))
+        cfg.no_list_reuse = 0 if list_reuse else 1
         self.cfg = cfg
         nbytes = C.c_size_t()
         _check(lib.lsd_workspace_size(C.byref(cfg), C.byref(nbytes)), "lsd_workspace_size")
@@ -230,6 +255,16 @@ class LSDSystem:
             P.weights = wt.data_ptr()
             P.n_model_species = int(d.get("n_model_species", len(self._masses)))
             P.energy_scale = float(d.get("scale", 1.0))
+        elif kind == "pair":
+            P.kind, P.cutoff = POT_PAIR, float(d["rc"])
+            if d.get("weights") is None:
+                raise ValueError("the pair draft needs fitted weights (fit_pair_draft)")
+            wt = t.tensor(np.asarray(d["weights"], dtype=np.float64).ravel(), dtype=t.float32,
+                          device="cuda").contiguous()
+            self._keep.append(wt)
+            P.weights = wt.data_ptr()
+            P.n_model_species = int(d.get("n_model_species", len(self._masses)))
+            P.n_basis = int(d["n_basis"])
         else:
             raise ValueError(f"potential kind {kind!r} is not implemented by the library")
         if d.get("offset") is not None:
@@ -261,6 +296,23 @@ class LSDSystem:
 
     def mark_drafted(self, K):
         _check(load().lsd_mark_drafted(self.h, int(K), _stream(self.torch)), "lsd_mark_drafted")
+
+    # --- force matching of the pair draft --------------------------------------
+    def fit_pair_accumulate(self, n_basis, cutoff, gram, use_target=False, scratch=None):
+        """Add the normal equations of the current window's valid frames to
+        `gram` (float64 CUDA tensor [P+1, P+1]); returns the scratch tensor
+        (reuse it across calls)."""
+        t = self.torch
+        nb = C.c_size_t()
+        _check(load().lsd_fit_pair_scratch_size(self.h, int(n_basis), C.byref(nb)),
+               "lsd_fit_pair_scratch_size")
+        if scratch is None or scratch.numel() < nb.value:
+            scratch = t.empty((max(nb.value, 8),), dtype=t.uint8, device="cuda")
+        _check(load().lsd_fit_pair_accumulate(self.h, int(n_basis), float(cutoff),
+                                              1 if use_target else 0, _ptr(scratch),
+                                              scratch.numel(), _ptr(gram), _stream(t)),
+               "lsd_fit_pair_accumulate")
+        return scratch
 
     # --- inspection -------------------------------------------------------------
     def window(self) -> Dict[str, "object"]:
@@ -323,10 +375,11 @@ class LSDSystem:
         raise RuntimeError("run_to_step did not reach the step count")
 
     def counters(self):
-        """int64 [R, 4]: windows, committed steps, rejections, frames verified."""
-        out = (C.c_int64 * (4 * self.R))()
+        """int64 [R, 5]: windows, committed steps, rejections, frames verified,
+        neighbour-list builds."""
+        out = (C.c_int64 * (NUM_COUNTERS * self.R))()
         _check(load().lsd_get_counters(self.h, out, _stream(self.torch)), "lsd_get_counters")
-        return np.array(out[:], dtype=np.int64).reshape(self.R, 4)
+        return np.array(out[:], dtype=np.int64).reshape(self.R, NUM_COUNTERS)
 
     def reset_counters(self):
         _check(load().lsd_reset_counters(self.h, _stream(self.torch)), "lsd_reset_counters")

@@ -106,3 +106,26 @@ def test_calls_on_null_handle_fail_cleanly(lib):
     assert lib.lsd_verify_window(None, None) == -1
     assert lib.lsd_accept_rollback(None, None, None) == -1
     assert lib.lsd_destroy(None) == 0
+
+
+def test_fit_pair_solve_matches_least_squares(lib):
+    # host-only: Cholesky solve of extended normal equations [A|y]^T [A|y]
+    from paper_2606_02455_amd import lsd
+    rng = np.random.default_rng(3)
+    A = rng.normal(size=(200, 12))
+    y = rng.normal(size=200)
+    Ae = np.concatenate([A, y[:, None]], axis=1)
+    G = Ae.T @ Ae
+    w = lsd.fit_pair_solve(G, ridge=0.0)
+    ref, *_ = np.linalg.lstsq(A, y, rcond=None)
+    assert np.allclose(w, ref, rtol=1e-10, atol=1e-12)
+    # ridge: (A^T A + lam I) w = A^T y with lam = ridge * trace / P
+    lam = 0.1 * np.trace(A.T @ A) / 12
+    wr = lsd.fit_pair_solve(G, ridge=0.1)
+    assert np.allclose(wr, np.linalg.solve(A.T @ A + lam * np.eye(12), A.T @ y), rtol=1e-10)
+    # an unobserved column makes the system singular without a ridge
+    A[:, 3] = 0.0
+    Ae = np.concatenate([A, y[:, None]], axis=1)
+    with pytest.raises(lsd.LSDError):
+        lsd.fit_pair_solve(Ae.T @ Ae, ridge=0.0)
+    assert np.isfinite(lsd.fit_pair_solve(Ae.T @ Ae, ridge=1e-8)).all()

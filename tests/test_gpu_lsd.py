@@ -511,3 +511,75 @@ def test_forces_across_box_faces_inside_a_window(torch, lsd, ora):
     h.verify_window()
     h.accept_rollback(sync=True)
     h.destroy()
+
+
+@pytest.mark.parametrize("case", ["c1", "lj512"])
+def test_reused_lists_hold_every_pair(torch, lsd, case):
+    # lists kept across windows must contain every pair within the cutoff at
+    # every verified frame: forces and energies on the same frames equal
+    # those from lists built afresh (GPU against GPU; the summation order and
+    # the binary32 shift of frame 0 back into the box differ)
+    _say(f"list reuse {case}")
+    w = W.config("c1") if case == "c1" else W.lj_fluid(8, seed=23, K=8)
+    K, N = w.K, w.n_atoms
+    a = lsd.LSDSystem(w, mode="lsd")
+    a.run_windows(10, K)
+    builds_before = int(a.counters()[0, 4])
+    a.draft_steps(K)
+    a.verify_window()
+    torch.cuda.synchronize()
+    win = a.window()
+    qm = win["q_mid"][:K, :, :3].double().cpu().numpy()
+    pd = win["p_draft"][:K + 1].double().cpu().numpy().transpose(0, 2, 1)
+    fd = win["f_draft"][:K].double().cpu().numpy().transpose(0, 2, 1)
+    ft_a = win["f_target"][:K].double().cpu().numpy().transpose(0, 2, 1)
+    inv_a = win["frame_invalid"].cpu().numpy()[0][:K]
+    a.accept_rollback(sync=True)
+    e_a = a.energy.cpu().numpy()[0][:K]
+    assert int(a.counters()[0, 0]) == 11
+    # the lists were kept for at least one window (else nothing is tested)
+    assert builds_before < 10, builds_before
+    L = float(w.box[0])
+    q0 = qm[0] - L * np.floor(qm[0] / L)
+    q0[q0 >= L] = 0.0
+    frames = np.concatenate([q0[None], qm[1:]])
+    b = lsd.LSDSystem(w, mode="lsd")
+    b.set_state(w.positions, pd[0])
+    _inject(b, torch, frames, pd, fd)
+    b.mark_drafted(K)
+    b.verify_window()
+    torch.cuda.synchronize()
+    winb = b.window()
+    ft_b = winb["f_target"][:K].double().cpu().numpy().transpose(0, 2, 1)
+    inv_b = winb["frame_invalid"].cpu().numpy()[0][:K]
+    b.accept_rollback(sync=True)
+    e_b = b.energy.cpu().numpy()[0][:K]
+    both = (inv_a == 0) & (inv_b == 0)
+    assert both[0]
+    for k in np.nonzero(both)[0]:
+        scale = np.max(np.abs(ft_b[k]))
+        assert np.max(np.abs(ft_a[k] - ft_b[k])) <= 1e-5 * scale, k
+        assert abs(e_a[k] - e_b[k]) <= 1e-5 * abs(e_b[k]), k
+    a.destroy()
+    b.destroy()
+
+
+def test_list_reuse_changes_only_rounding(torch, lsd):
+    _say("list reuse vs rebuild")
+    w = W.config("c1")
+    a = lsd.LSDSystem(w, mode="lsd")
+    b = lsd.LSDSystem(w, mode="lsd", list_reuse=False)
+    a.run_windows(40, w.K)
+    b.run_windows(40, w.K)
+    sa, sb = a.state(), b.state()
+    ca, cb = a.counters()[0], b.counters()[0]
+    assert cb[4] == cb[0] and ca[4] < ca[0]
+    # same decisions, states equal up to rounding (summation order)
+    assert np.array_equal(ca[:3], cb[:3]), (ca, cb)
+    assert np.array_equal(sa["step"], sb["step"])
+    assert np.max(np.abs(sa["p"] - sb["p"])) < 1e-3
+    dq = sa["q"] - sb["q"]
+    dq -= float(w.box[0]) * np.round(dq / float(w.box[0]))
+    assert np.max(np.abs(dq)) < 1e-3
+    a.destroy()
+    b.destroy()

@@ -102,26 +102,36 @@ def _lj_observables(ora, w, st):
 
 
 def test_lj_lsd_marginals_match_plain_target(torch, lsd, ora):
+    # draft: shorter cutoff and eps = 0.85, a law the energy test tells apart
+    # from the target's at this sample size (the rc = 1.5 draft alone is too
+    # close to the target's structure for that); |delta| ~ 1.9 per 64-atom box
     _say("LJ LSD vs plain marginals")
     R = 192
+    draft = dict(kind="lj", rc=1.5, eps=0.85)
     a = W.lj_replicas([4] * R, seed=1000, K=8)
     b = W.lj_replicas([4] * R, seed=5000, K=8)
-    g = lsd.LSDSystem(a, mode="lsd", seed=11)
+    e = W.lj_replicas([4] * R, seed=7000, K=8)
+    g = lsd.LSDSystem(a, mode="lsd", seed=11, draft=draft)
     p = lsd.LSDSystem(b, mode="plain", seed=12)
-    _run_until(g, 400, 8)
-    _run_until(p, 400, 8)
-    assert g.status() == 0 and p.status() == 0
+    ge = lsd.LSDSystem(e, mode="lsd", seed=14, draft=draft, error_correction=True)
+    for s in (g, p, ge):
+        _run_until(s, 400, 8)
+        assert s.status() == 0
     Tg, Eg = _lj_observables(ora, a, g.state())
     Tp, Ep = _lj_observables(ora, b, p.state())
-    assert stats.ks_2samp(Tg, Tp).pvalue > 0.01
-    assert stats.ks_2samp(Eg, Ep).pvalue > 0.01
-    for T in (Tg, Tp):
+    Te, Ee = _lj_observables(ora, e, ge.state())
+    rate = g.counters()[:, 2].sum() / g.counters()[:, 1].sum()
+    assert 0.2 < rate < 0.95, rate
+    for Tx, Ex in ((Tg, Eg), (Te, Ee)):
+        assert stats.ks_2samp(Tx, Tp).pvalue > 0.01
+        assert stats.ks_2samp(Ex, Ep).pvalue > 0.01
+    for T in (Tg, Tp, Te):
         assert abs(T.mean() - 1.0) < 4 * T.std() / np.sqrt(len(T))
-    # the short-cutoff draft alone is a different system: the energy test sees it
+    # the draft alone is a different system: the energy test sees it
     c = W.lj_replicas([4] * R, seed=9000, K=8)
-    d = lsd.LSDSystem(c, mode="plain", seed=13, target=dict(c.draft))
+    d = lsd.LSDSystem(c, mode="plain", seed=13, target=draft)
     _run_until(d, 400, 8)
     Td, Ed = _lj_observables(ora, c, d.state())
     assert stats.ks_2samp(Ed, Ep).pvalue < 1e-3
-    for s in (g, p, d):
+    for s in (g, p, ge, d):
         s.destroy()
