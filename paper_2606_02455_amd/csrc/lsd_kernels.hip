@@ -117,9 +117,12 @@ __global__ __launch_bounds__(256) void k_rebuild_bin(SysDev S, ListDev Lst, WinD
   atomicAdd(&Lst.cell_count[cell], 1);
 }
 
-// Exclusive scan of the cell counts (one block), then clear the counters
-// for the next binning.
-__global__ __launch_bounds__(1024) void k_cell_scan(ListDev Lst) {
+// Cell offsets (one block): an exclusive scan of the cell counts restarted
+// at every replica's first atom, so each replica's cells index its own range
+// [rep_off[r], rep_off[r+1]) of the cell-sorted atom list (replicas that keep
+// their lists have zero counts and keep their entries); then the counters
+// are cleared for the next binning.
+__global__ __launch_bounds__(1024) void k_cell_scan(ListDev Lst, const int* __restrict__ rep_off) {
   __shared__ int s[1024];
   const int C = Lst.n_cells;
   const int t = threadIdx.x;
@@ -135,14 +138,21 @@ __global__ __launch_bounds__(1024) void k_cell_scan(ListDev Lst) {
     s[t] += v;
     __syncthreads();
   }
-  int run = s[t] - sum;  // exclusive prefix of this chunk
+  // global exclusive prefix, held in the cursors for the moment
+  int run = s[t] - sum;
   for (int c = lo; c < hi; ++c) {
-    Lst.cell_start[c] = run;
+    Lst.cell_cursor[c] = run;
     run += Lst.cell_count[c];
     Lst.cell_count[c] = 0;
-    Lst.cell_cursor[c] = 0;
   }
-  if (t == 1023) Lst.cell_start[C] = s[1023];
+  __syncthreads();
+  for (int c = lo; c < hi; ++c) {
+    const int r = Lst.cell_rep[c];
+    Lst.cell_start[c] = rep_off[r] + Lst.cell_cursor[c] - Lst.cell_cursor[Lst.rep_cell_off[r]];
+  }
+  __syncthreads();
+  for (int c = lo; c < hi; ++c) Lst.cell_cursor[c] = 0;
+  if (t == 0) Lst.cell_start[C] = rep_off[Lst.cell_rep[C - 1] + 1];
 }
 
 __global__ __launch_bounds__(256) void k_cell_fill(int n, const int* __restrict__ atom_rep,
@@ -313,13 +323,22 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
   const float Lf = (float)L;
   const float4 xi = X[i];
   if (P.kind == LSD_POT_LJ) {
-    for (int m = sub; m < cnt; m += LSD_LPA) {
-      const uint32_t ent = row[m];
-      const int j = (int)(ent >> 5), code = (int)(ent & 31u);
-      const float4 xj = X[j];
+    // two entries per iteration (gathers issued together), added in order
+    for (int m = sub; m < cnt; m += 2 * LSD_LPA) {
+      const bool two = m + LSD_LPA < cnt;
+      const uint32_t e0 = row[m];
+      const uint32_t e1 = row[two ? m + LSD_LPA : m];
+      const int j0 = (int)(e0 >> 5), c0 = (int)(e0 & 31u);
+      const int j1 = (int)(e1 >> 5), c1 = (int)(e1 & 31u);
+      const float4 x0 = X[j0];
+      const float4 x1 = X[j1];
       float sj[3], si[3];
-      image_shifts(code, Lf, sj, si);
-      lj_pair(P, xi, xj, sj, si, code, L, fx, fy, fz, e);
+      image_shifts(c0, Lf, sj, si);
+      lj_pair(P, xi, x0, sj, si, c0, L, fx, fy, fz, e);
+      if (two) {
+        image_shifts(c1, Lf, sj, si);
+        lj_pair(P, xi, x1, sj, si, c1, L, fx, fy, fz, e);
+      }
     }
     fx = lpa_sum(fx);
     fy = lpa_sum(fy);
@@ -510,15 +529,31 @@ __global__ __launch_bounds__(256) void k_verify(SysDev S, ListDev Lst, WinDev W,
     fx[f] = fy[f] = fz[f] = en[f] = 0.0f;
     xi[f] = valid[f] ? W.qmid[(size_t)(f0 + f) * N + i] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  for (int m = sub; m < cnt; m += LSD_LPA) {
-    const uint32_t ent = s_nbr[m * VROW + a];
-    const int j = (int)(ent >> 5), code = (int)(ent & 31u);
-    const float* sh = s_shift[code];
+  // two entries per iteration (m, m + LSD_LPA): their gathers are issued
+  // together; the terms are added in entry order as in the draft kernel
+  for (int m = sub; m < cnt; m += 2 * LSD_LPA) {
+    const bool two = m + LSD_LPA < cnt;
+    const uint32_t e0 = s_nbr[m * VROW + a];
+    const uint32_t e1 = s_nbr[(two ? m + LSD_LPA : m) * VROW + a];
+    const int j0 = (int)(e0 >> 5), c0 = (int)(e0 & 31u);
+    const int j1 = (int)(e1 >> 5), c1 = (int)(e1 & 31u);
+    float4 x0[FW], x1[FW];
 #pragma unroll
     for (int f = 0; f < FW; ++f) {
-      if (!valid[f]) continue;
-      const float4 xj = W.qmid[(size_t)(f0 + f) * N + j];
-      lj_pair(P, xi[f], xj, sh, sh + 3, code, L, fx[f], fy[f], fz[f], en[f]);
+      // frame f0 exists in every block; an invalid frame's load is unused
+      const size_t fr = (size_t)(valid[f] ? f0 + f : f0) * N;
+      x0[f] = W.qmid[fr + j0];
+      x1[f] = W.qmid[fr + j1];
+    }
+    const float* sh0 = s_shift[c0];
+    const float* sh1 = s_shift[c1];
+#pragma unroll
+    for (int f = 0; f < FW; ++f)
+      if (valid[f]) lj_pair(P, xi[f], x0[f], sh0, sh0 + 3, c0, L, fx[f], fy[f], fz[f], en[f]);
+    if (two) {
+#pragma unroll
+      for (int f = 0; f < FW; ++f)
+        if (valid[f]) lj_pair(P, xi[f], x1[f], sh1, sh1 + 3, c1, L, fx[f], fy[f], fz[f], en[f]);
     }
   }
   const int sp = (active && S.species) ? S.species[i] : 0;
@@ -792,7 +827,7 @@ hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W
                               hipStream_t st) {
   hipLaunchKernelGGL(k_rebuild_bin, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, L, W,
                      caller_frame0 ? 1 : 0);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, L);
+  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, L, S.rep_off);
   hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S.n, S.atom_rep, L);
   hipLaunchKernelGGL(k_cell_sort, dim3(L.n_cells), dim3(64), 0, st, L);
   dim3 grid(L.n_cells, (L.cell_cap + NL_IPB - 1) / NL_IPB);
@@ -833,10 +868,15 @@ hipError_t prepare_verify(int mt) {
   return e;
 }
 
-// frames per wave: 4 for long windows; fewer when the window is short
+// frames per wave: up to LSD_VERIFY_FW_MAX for long windows; fewer when the
+// window is short
+#ifndef LSD_VERIFY_FW_MAX
+#define LSD_VERIFY_FW_MAX 4
+#endif
 hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                          const PotDev& P, int fw, hipStream_t st) {
   const size_t lds = verify_lds(L.mt);
+  if (fw > LSD_VERIFY_FW_MAX) fw = LSD_VERIFY_FW_MAX;
   if (fw >= 4) {
     hipLaunchKernelGGL(k_verify<4>, dim3(S.n_tiles, (W.K + 3) / 4), dim3(256), lds, st, S, L, W, T, P);
   } else if (fw == 2) {
