@@ -526,6 +526,14 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   Ls.md = L.md;
   Ls.rl2_t = L.rl_t * L.rl_t;
   Ls.rl2_d = L.rl_d * L.rl_d;
+  {
+    // outside these bands the binary32 distance decides the list predicate
+    const double u = std::ldexp(1.0, -24);
+    Ls.rl2_t_lo = (float)(Ls.rl2_t * (1.0 - 32.0 * u));
+    Ls.rl2_t_hi = (float)(Ls.rl2_t * (1.0 + 32.0 * u));
+    Ls.rl2_d_lo = (float)(Ls.rl2_d * (1.0 - 32.0 * u));
+    Ls.rl2_d_hi = (float)(Ls.rl2_d * (1.0 + 32.0 * u));
+  }
   Ls.status = ws<int>(s, L.status);
   Ls.qref = ws<float4>(s, L.qref);
   Ls.qwrap = ws<float4>(s, L.qwrap);

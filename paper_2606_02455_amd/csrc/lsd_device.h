@@ -79,6 +79,7 @@ struct ListDev {
   uint32_t* nbr_t; int* cnt_t; int mt;   // target list, atom-major [N][mt]
   uint32_t* nbr_d; int* cnt_d; int md;   // draft list, atom-major [N][md]
   double rl2_t, rl2_d;      // list radii squared (binary64)
+  float rl2_t_lo, rl2_t_hi, rl2_d_lo, rl2_d_hi;  // binary32 bands rl2 (1 -+ 32u)
   int* status;
   // reuse across windows: the lists hold for positions within skin/2 of the
   // positions they were built at; window frames are kept continuous with

@@ -195,6 +195,7 @@ __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev 
   __shared__ int s_pre[28];
   __shared__ int s_cstart[27];
   __shared__ int s_code[27];
+  __shared__ float s_sh[27][6];
   const int c = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int r = Lst.cell_rep[c];
@@ -220,6 +221,7 @@ __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev 
     s_cstart[t] = Lst.cell_start[cell];
     s_pre[t + 1] = Lst.cell_start[cell + 1] - Lst.cell_start[cell];
     s_code[t] = (nx + 1) + 3 * (ny + 1) + 9 * (nz + 1);
+    image_shifts(t, (float)L, &s_sh[t][0], &s_sh[t][3]);  // by image code
   }
   __syncthreads();
   if (t == 0) {
@@ -228,34 +230,33 @@ __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev 
   }
   __syncthreads();
   const int total = s_pre[27];
-  // this wave's i-atoms: ib + wave, ib + wave + 4, ... (at most NL_IPB / 4)
-  constexpr int PER = NL_IPB / 4;
-  int ia[PER], nt[PER], nd[PER];
-  float4 xi[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = ib + wave + 4 * u;
-    ia[u] = e < ie ? Lst.cell_atoms[lo + e] : -1;
-    xi[u] = ia[u] >= 0 ? W.qmid[ia[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
-    nt[u] = 0;
-    nd[u] = 0;
+  // list lengths of the block's i-atoms so far (atom u of the block is
+  // handled by wave u % 4 in every chunk)
+  __shared__ int s_nt[NL_IPB], s_nd[NL_IPB];
+  const int nib = ie - ib;
+  if (t < NL_IPB) {
+    s_nt[t] = 0;
+    s_nd[t] = 0;
   }
   for (int cb = 0; cb < total; cb += NL_CH) {
     const int cn = min(NL_CH, total - cb);
     __syncthreads();
     for (int k = t; k < cn; k += 256) {
       const int idx = cb + k;
+      // neighbour cell of candidate idx: s_pre[q] <= idx < s_pre[q + 1]
       int q = 0;
-      while (s_pre[q + 1] <= idx) ++q;
+#pragma unroll
+      for (int step = 16; step > 0; step >>= 1)
+        if (q + step < 27 && s_pre[q + step] <= idx) q += step;
       const int j = Lst.cell_atoms[s_cstart[q] + (idx - s_pre[q])];
       s_x[k] = W.qmid[j];
       s_e[k] = ((uint32_t)j << 5) | (uint32_t)s_code[q];
     }
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      if (ia[u] < 0) continue;  // uniform per wave
-      const int i = ia[u];
+    for (int u = wave; u < nib; u += 4) {  // uniform per wave
+      const int i = Lst.cell_atoms[lo + ib + u];
+      const float4 xi = W.qmid[i];
+      int nt = s_nt[u], nd = s_nd[u];
       uint32_t* rowt = Lst.nbr_t + (size_t)i * Lst.mt;
       uint32_t* rowd = Lst.nbr_d + (size_t)i * Lst.md;
       for (int k0 = 0; k0 < cn; k0 += 64) {
@@ -266,40 +267,56 @@ __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev 
           ent = s_e[k];
           const int j = (int)(ent >> 5), code = (int)(ent & 31u);
           if (!(j == i && code == 13)) {
+            // binary32 separation (relative error <= 4u per component, as in
+            // the force kernels); the exact binary64 predicate decides inside
+            // the band rl2 (1 -+ 32u) around either list radius
             const float4 xj = s_x[k];
-            double dx = ((double)xj.x - (double)xi[u].x) + (double)code_nx(code) * L;
-            double dy = ((double)xj.y - (double)xi[u].y) + (double)code_ny(code) * L;
-            double dz = ((double)xj.z - (double)xi[u].z) + (double)code_nz(code) * L;
-            double d2 = dx * dx + dy * dy + dz * dz;
-            ht = d2 < Lst.rl2_t;
-            hd = d2 < Lst.rl2_d;
+            const float* sh = s_sh[code];
+            const float fdx = sep(xj.x, sh[0], xi.x, sh[3]);
+            const float fdy = sep(xj.y, sh[1], xi.y, sh[4]);
+            const float fdz = sep(xj.z, sh[2], xi.z, sh[5]);
+            const float r2 = fdx * fdx + fdy * fdy + fdz * fdz;
+            const bool bt = r2 >= Lst.rl2_t_lo && r2 < Lst.rl2_t_hi;
+            const bool bd = r2 >= Lst.rl2_d_lo && r2 < Lst.rl2_d_hi;
+            ht = r2 < Lst.rl2_t_lo;
+            hd = r2 < Lst.rl2_d_lo;
+            if (bt || bd) {
+              double dx = ((double)xj.x - (double)xi.x) + (double)code_nx(code) * L;
+              double dy = ((double)xj.y - (double)xi.y) + (double)code_ny(code) * L;
+              double dz = ((double)xj.z - (double)xi.z) + (double)code_nz(code) * L;
+              double d2 = dx * dx + dy * dy + dz * dz;
+              if (bt) ht = d2 < Lst.rl2_t;
+              if (bd) hd = d2 < Lst.rl2_d;
+            }
           }
         }
         const unsigned long long bt = __ballot(ht), bd = __ballot(hd);
         const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         if (ht) {
-          const int pos = nt[u] + __popcll(bt & below);
+          const int pos = nt + __popcll(bt & below);
           if (pos < Lst.mt) rowt[pos] = ent;
         }
         if (hd) {
-          const int pos = nd[u] + __popcll(bd & below);
+          const int pos = nd + __popcll(bd & below);
           if (pos < Lst.md) rowd[pos] = ent;
         }
-        nt[u] += __popcll(bt);
-        nd[u] += __popcll(bd);
+        nt += __popcll(bt);
+        nd += __popcll(bd);
+      }
+      if (lane == 0) {
+        s_nt[u] = nt;
+        s_nd[u] = nd;
       }
     }
   }
-  if (lane == 0) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      if (ia[u] < 0) continue;
-      int a = nt[u], b = nd[u];
-      if (a > Lst.mt) { atomicOr(Lst.status, LSD_STATUS_NBR_TARGET); a = Lst.mt; }
-      if (b > Lst.md) { atomicOr(Lst.status, LSD_STATUS_NBR_DRAFT); b = Lst.md; }
-      Lst.cnt_t[ia[u]] = a;
-      Lst.cnt_d[ia[u]] = b;
-    }
+  __syncthreads();
+  for (int u = t; u < nib; u += 256) {
+    const int i = Lst.cell_atoms[lo + ib + u];
+    int a = s_nt[u], b = s_nd[u];
+    if (a > Lst.mt) { atomicOr(Lst.status, LSD_STATUS_NBR_TARGET); a = Lst.mt; }
+    if (b > Lst.md) { atomicOr(Lst.status, LSD_STATUS_NBR_DRAFT); b = Lst.md; }
+    Lst.cnt_t[i] = a;
+    Lst.cnt_d[i] = b;
   }
 }
 
