@@ -12,7 +12,11 @@
 
 #define LSD_MAX_SPECIES 8
 #define LSD_TILE 64           // atoms per verification tile
-#define LSD_LPA 4             // lanes per atom in the force loops
+#ifndef LSD_LPA
+#define LSD_LPA 4             // lanes per atom in the force loops (power of 2, <= 64)
+#endif
+#define LSD_VTHREADS (LSD_TILE * LSD_LPA)  // threads of a verification block
+#define LSD_VWAVES (LSD_VTHREADS / 64)
 #define LSD_MAX_K 64
 #define LSD_NCOUNT 5          // per-replica counters (see WinDev::counters)
 #define LSD_POT_LJ 1

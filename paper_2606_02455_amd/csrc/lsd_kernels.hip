@@ -321,8 +321,8 @@ __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev 
 }
 
 __device__ __forceinline__ float lpa_sum(float v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
+#pragma unroll
+  for (int o = 1; o < LSD_LPA; o <<= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
@@ -501,11 +501,11 @@ __global__ __launch_bounds__(256) void k_frame_validity(SysDev S, ListDev Lst, W
 // and the potential energy.
 #define VROW 65  // LDS row stride (words) of the staged neighbour tile
 template <int FW>
-__global__ __launch_bounds__(256) void k_verify(SysDev S, ListDev Lst, WinDev W, TileDev Tl,
-                                                PotDev P) {
+__global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, WinDev W,
+                                                         TileDev Tl, PotDev P) {
   extern __shared__ uint32_t s_nbr[];  // [mt][VROW]
   __shared__ float s_shift[27][6];
-  __shared__ double s_red[4][FW][3];
+  __shared__ double s_red[LSD_VWAVES][FW][3];
   const int tile = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int a = t / LSD_LPA, sub = t % LSD_LPA;
@@ -525,10 +525,10 @@ __global__ __launch_bounds__(256) void k_verify(SysDev S, ListDev Lst, WinDev W,
   const size_t N = (size_t)S.n;
   const bool lj = P.kind == LSD_POT_LJ;
   if (t < 27) image_shifts(t, Lf, &s_shift[t][0], &s_shift[t][3]);
-  // stage the rows of the tile: wave w copies atoms w, w+4, ...; 64
+  // stage the rows of the tile: wave w copies atoms w, w + waves, ...; 64
   // consecutive entries of one row per instruction
   if (lj) {
-    for (int aa = wave; aa < count; aa += 4) {
+    for (int aa = wave; aa < count; aa += LSD_VWAVES) {
       const int ci = Lst.cnt_t[start + aa];
       const uint32_t* row = Lst.nbr_t + (size_t)(start + aa) * Lst.mt;
       for (int m = lane; m < ci; m += 64) s_nbr[m * VROW + aa] = row[m];
@@ -625,8 +625,11 @@ __global__ __launch_bounds__(256) void k_verify(SysDev S, ListDev Lst, WinDev W,
   if (t < FW && valid[t]) {
     double* out = W.partial + ((size_t)(f0 + t) * S.n_tiles + tile) * 4;
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-      out[q] = ((s_red[0][t][q] + s_red[1][t][q]) + s_red[2][t][q]) + s_red[3][t][q];
+    for (int q = 0; q < 3; ++q) {
+      double v = s_red[0][t][q];
+      for (int w = 1; w < LSD_VWAVES; ++w) v += s_red[w][t][q];
+      out[q] = v;
+    }
   }
 }
 
@@ -895,11 +898,11 @@ hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, con
   const size_t lds = verify_lds(L.mt);
   if (fw > LSD_VERIFY_FW_MAX) fw = LSD_VERIFY_FW_MAX;
   if (fw >= 4) {
-    hipLaunchKernelGGL(k_verify<4>, dim3(S.n_tiles, (W.K + 3) / 4), dim3(256), lds, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<4>, dim3(S.n_tiles, (W.K + 3) / 4), dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
   } else if (fw == 2) {
-    hipLaunchKernelGGL(k_verify<2>, dim3(S.n_tiles, (W.K + 1) / 2), dim3(256), lds, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<2>, dim3(S.n_tiles, (W.K + 1) / 2), dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
   } else {
-    hipLaunchKernelGGL(k_verify<1>, dim3(S.n_tiles, W.K), dim3(256), lds, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<1>, dim3(S.n_tiles, W.K), dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
   }
   return hipGetLastError();
 }
