@@ -117,12 +117,126 @@ def cpu_baseline(w, q, p, seconds, ec_on):
                 plain_steps_per_s=n_plain / t_plain)
 
 
+def mpnn_flops_per_frame(undirected_edges, n_atoms, H=128, R=16, T=3, RH=64):
+    """Algorithmic FLOPs of one target evaluation (energy and forces) of the
+    message-passing network: per undirected in-cutoff edge and layer the
+    filter MLP (R -> H -> H) forward and its input-gradient backward; per atom
+    and layer the node MLPs (B, C1, C2: H x H) forward and backward; the
+    readout.  Multiply-add = 2 FLOPs; elementwise work is not counted."""
+    per_edge = T * 2 * (2 * (R * H + H * H))
+    per_atom = T * 2 * (3 * 2 * H * H) + 2 * 2 * (RH * H)
+    return undirected_edges * per_edge + n_atoms * per_atom
+
+
+def run_c3(args, lsd, W, torch):
+    """Learned-draft configuration: 1536-atom triatomic liquid, message-passing
+    target, pair draft fitted by force matching on target frames, K = 8."""
+    import numpy as np
+    w = W.config("c3")
+    K, N = w.K, w.n_atoms
+    nb, rc_d = args.pair_basis, float(w.draft["rc"])
+    target = W.mpnn_target()
+    ec_on = args.ec == "on"
+    log(f"workload {w.name}: N={N} K={K} box={w.box[0]:.4f} A")
+    plain = lsd.LSDSystem(w, mode="plain", target=target)
+    eq_windows = max(1, args.equilibrate // K)
+    t0 = time.perf_counter()
+    plain.run_windows(eq_windows, K)
+    torch.cuda.synchronize()
+    log(f"equilibrated {eq_windows * K} plain steps in {time.perf_counter() - t0:.1f} s")
+    # force matching on frames of the plain target trajectory
+    P = lsd.pair_params(3, nb)
+    gram = torch.zeros((P + 1, P + 1), dtype=torch.float64, device="cuda")
+    scratch = None
+    fit_windows = max(1, (args.fit_frames + K - 1) // K)
+    t0 = time.perf_counter()
+    for _ in range(fit_windows):
+        plain.draft_steps(K)
+        scratch = plain.fit_pair_accumulate(nb, rc_d, gram, scratch=scratch)
+        plain.accept_rollback()
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    G = gram.cpu().numpy()
+    wts = lsd.fit_pair_solve(G, ridge=1e-8)
+    log(f"fitted the pair draft on {fit_windows * K} target frames in {t_fit:.1f} s")
+    if plain.status():
+        raise RuntimeError(f"device status {plain.status()} during plain stepping")
+    draft = dict(kind="pair", rc=rc_d, weights=wts, n_basis=nb, n_model_species=3)
+    g = lsd.LSDSystem(w, mode="lsd", target=target, draft=draft, error_correction=ec_on)
+    for a, b in ((g.q, plain.q), (g.p, plain.p), (g.img, plain.img), (g.step, plain.step)):
+        a.copy_(b)
+    g.run_windows(args.warmup, K)
+    g.reset_counters()
+    g.set_verify_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run_windows(args.steps, K)
+    torch.cuda.synchronize()
+    t_lsd = time.perf_counter() - t0
+    ver_ms, ver_n = g.verify_timing()
+    windows, committed, rejections, frames, builds = (int(v) for v in g.counters()[0])
+    log(f"LSD: {committed} steps in {t_lsd * 1e3:.1f} ms over {windows} windows; rejections "
+        f"{rejections}; verify {ver_ms / max(ver_n, 1) * 1e3:.1f} us/launch")
+    plain.run_windows(args.warmup, K)
+    plain.reset_counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain.run_windows(args.steps, K)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain_steps = int(plain.counters()[0][1])
+    log(f"plain: {plain_steps} steps in {t_plain * 1e3:.1f} ms")
+    status = g.status() | plain.status()
+    if status:
+        raise RuntimeError(f"device status {status}: neighbour capacity overflow")
+    pairs = in_cutoff_pairs(g, float(target["rc"]))
+    frames_per_launch = frames / max(ver_n, 1)
+    flops = mpnn_flops_per_frame(pairs / 2.0, N) * frames_per_launch
+    avg_s = ver_ms / max(ver_n, 1) * 1e-3
+    achieved = flops / avg_s / 1e12
+    peak = 157.3
+    value, plain_rate = committed / t_lsd, plain_steps / t_plain
+    dt_fs = w.dt
+    return {
+        "metric": "target-distributed MD steps/s (LSD vs plain Langevin, 1 GPU); acceptance rate",
+        "value": round(value, 3), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_lsd / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w.name}: triatomic liquid, {N} atoms (512 molecules), 300 K, "
+                         f"dt {dt_fs} fs, gamma {w.gamma}/fs, K={K}; target: seeded "
+                         f"message-passing network (3 layers, hidden 128, 16 Bessel, rc 5 A); "
+                         f"draft: pair forces (rc {rc_d} A, {nb} basis) force-matched on "
+                         f"{fit_windows * K} target frames; error correction {args.ec}"),
+            "n_atoms": N, "K": K, "fit_frames": fit_windows * K,
+            "error_correction": ec_on},
+        "acceptance": round(1.0 - rejections / max(committed, 1), 5),
+        "committed_per_window": round(committed / windows, 4),
+        "plain_steps_per_s": round(plain_rate, 3),
+        "lsd_over_plain": round(value / plain_rate, 5),
+        "ns_per_day_lsd": round(value * dt_fs * 1e-6 * 86400.0, 4),
+        "ns_per_day_plain": round(plain_rate * dt_fs * 1e-6 * 86400.0, 4),
+        "fit_seconds": round(t_fit, 2),
+        "roofline": dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                         frac=round(achieved / peak, 5), traffic=None,
+                         kernel="message-passing target evaluation (all frames of a window)",
+                         avg_us=round(avg_s * 1e6, 2), algorithmic_flops=int(flops),
+                         frames_per_launch=round(frames_per_launch, 3),
+                         in_cutoff_pairs=pairs),
+        "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed windows")
     ap.add_argument("--warmup", type=int, default=20, help="untimed windows")
-    ap.add_argument("--config", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--fit-frames", type=int, default=20000,
+                    help="c3: target frames for force matching of the pair draft")
+    ap.add_argument("--pair-basis", type=int, default=16, help="c3: pair-draft basis size")
     ap.add_argument("--equilibrate", type=int, default=256, help="plain steps before timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -144,6 +258,9 @@ def main():
 
     lsd.load()
     torch.cuda.set_device(0)
+    if args.config == "c3":
+        print(json.dumps(run_c3(args, lsd, W, torch)), flush=True)
+        return
     w = W.config(args.config)
     K = w.K
     log(f"workload {w.name}: N={w.n_atoms} K={K} box={w.box[0]:.5f}")

@@ -1,8 +1,8 @@
 // mpnn.h -- batched evaluation of the message-passing target on K frames.
 //
-// Rows are (frame, atom) pairs, row = f_local * N + i; slots are (row, list
-// entry) pairs, slot = row * mt + m, over the Verlet list of the window (its
-// entries beyond the cutoff get f_c = 0 and contribute nothing).  The dense
+// Rows are (frame, atom) pairs, row = f_local * N + i; edges are the list
+// entries of a row inside the cutoff, compacted row by row in list order
+// (capacity: rows x list width).  The dense
 // contractions (the per-slot filter MLP 128 -> 128 of every layer, and the
 // per-row node MLPs) run as FP32 GEMMs; every gather, activation, reduction
 // and the reverse pass to the forces are kernels in mpnn.hip.
@@ -31,6 +31,9 @@ struct MpnnBuffers {
   float* fcd;              // [slots][2]  f_c, f_c'
   float* uv;               // [slots][4]  unit separation vector
   float* gr;               // [slots]     dE/dr summed over both directions and layers
+  int* off;                // [rows+1]    first edge of every (frame, atom) row
+  int* erow;               // [slots]     row of an edge's atom
+  int* enbr;               // [slots]     row of an edge's neighbour
   float* H;                // [T+1][rows][128]
   float* X;                // [T][rows][128]
   float* U;                // [T][rows][128]

@@ -1,19 +1,22 @@
 // mpnn.hip -- the message-passing target evaluated on a batch of frames.
 //
+// Edges: the in-cutoff entries of every atom's list in every frame, compacted
+// per (frame, atom) row in list order (count, scan, write), so the dense
+// filter contractions run over the pairs that contribute and nothing else.
 // Forward (per layer t): filters W_t(r) = f_c(r) (A2 silu(A1 e(r) + a1) + a2)
-// for every slot, X_t = B_t h, m = sum over slots W_t (.) X_t[neighbour],
+// for every edge, X_t = B_t h, m = sum over edges W_t (.) X_t[neighbour],
 // h += C2 silu(C1 m + c1) + c2; readout E = s_E sum (w2 . silu(W1 h + b1) + b2).
 // Reverse pass to the forces F = -dE/dq: gh = dE/dh from the readout, then per
 // layer gM = dE/dm, gX = dE/dX (gathered over each atom's own list, using
 // W_ij = W_ji), and per slot dE/dr accumulated for both directions of the
-// pair; finally F_a = sum over a's slots of dE/dr * (q_b - q_a) / r.
+// pair; finally F_a = sum over a's edges of dE/dr * (q_b - q_a) / r.
 #include <cstdio>
 
 #include "mpnn.h"
 
 namespace {
 
-constexpr int kSlotsPerBlock = 8;  // 8 slots x 16 basis functions = 128 threads
+constexpr int kSlotsPerBlock = 8;  // 8 edges x 16 basis functions = 128 threads
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
 __device__ __forceinline__ float siluf(float x) { return x * sigmoidf(x); }
@@ -22,67 +25,109 @@ __device__ __forceinline__ float dsiluf(float x) {
   return s * (1.0f + x * (1.0f - s));
 }
 
-// Geometry, radial basis and the first filter layer of all three layers:
-// S = silu(A1 e + a1), DS = silu'(A1 e + a1) (.) (A1 de/dr), per slot and
-// channel; f_c, f_c' and the unit vector per slot.  Block: 128 threads
-// (channels), kSlotsPerBlock slots.
-__global__ __launch_bounds__(128) void k_mp_radial(MpnnWeights w, MpnnBuffers b, SysDev S,
-                                                   ListDev L, WinDev W, int f0, int nf, float rc) {
-  __shared__ float s_e[kSlotsPerBlock][MP_R], s_de[kSlotsPerBlock][MP_R];
-  __shared__ float s_r[kSlotsPerBlock];
-  __shared__ int s_on[kSlotsPerBlock];
-  const int c = threadIdx.x;
-  const long N = S.n, mt = L.mt;
-  const long slots = (long)nf * N * mt;
-  const long s0 = (long)blockIdx.x * kSlotsPerBlock;
-  // phase 1: geometry of the block's slots (one thread per slot)
-  if (c < kSlotsPerBlock) {
-    const long slot = s0 + c;
-    int on = 0;
-    float fc = 0.f, dfc = 0.f, ux = 0.f, uy = 0.f, uz = 0.f, r = rc;
-    if (slot < slots) {
-      const long row = slot / mt;
-      const int m = (int)(slot - row * mt);
-      const int fl = (int)(row / N), i = (int)(row - (long)fl * N);
-      if (m < L.cnt_t[i]) {
-        const uint32_t ent = L.nbr_t[(size_t)i * mt + m];
-        const int j = (int)(ent >> 5), code = (int)(ent & 31u);
-        const float Lf = (float)S.box[S.atom_rep[i]];
-        const float4* X = W.qmid + (size_t)(f0 + fl) * N;
-        const float4 xi = X[i], xj = X[j];
-        float sj[3], si[3];
-        image_shifts(code, Lf, sj, si);
-        const float dx = sep(xj.x, sj[0], xi.x, si[0]);
-        const float dy = sep(xj.y, sj[1], xi.y, si[1]);
-        const float dz = sep(xj.z, sj[2], xi.z, si[2]);
-        r = sqrtf(dx * dx + dy * dy + dz * dz);
-        if (r < rc && r > 0.f) {
-          on = 1;
-          const float a = 3.14159265358979f / rc;
-          fc = 0.5f * (cosf(a * r) + 1.0f);
-          dfc = -0.5f * a * sinf(a * r);
-          ux = dx / r;
-          uy = dy / r;
-          uz = dz / r;
-        }
-      }
-      b.fcd[2 * slot] = fc;
-      b.fcd[2 * slot + 1] = dfc;
-      b.uv[4 * slot] = ux;
-      b.uv[4 * slot + 1] = uy;
-      b.uv[4 * slot + 2] = uz;
-      b.uv[4 * slot + 3] = 0.f;
-    }
-    s_on[c] = on;
-    s_r[c] = r;
+// Separation of list entry m of atom i in local frame fl; true when the pair
+// is inside the cutoff (0 < r < rc).
+__device__ __forceinline__ bool edge_geometry(const SysDev& S, const ListDev& L, const WinDev& W,
+                                              int f0, int fl, int i, int m, float rc, int* j_out,
+                                              float d[3], float* r_out) {
+  const long N = S.n;
+  const uint32_t ent = L.nbr_t[(size_t)i * L.mt + m];
+  const int j = (int)(ent >> 5), code = (int)(ent & 31u);
+  const float Lf = (float)S.box[S.atom_rep[i]];
+  const float4* X = W.qmid + (size_t)(f0 + fl) * N;
+  const float4 xi = X[i], xj = X[j];
+  float sj[3], si[3];
+  image_shifts(code, Lf, sj, si);
+  d[0] = sep(xj.x, sj[0], xi.x, si[0]);
+  d[1] = sep(xj.y, sj[1], xi.y, si[1]);
+  d[2] = sep(xj.z, sj[2], xi.z, si[2]);
+  const float r = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  *j_out = j;
+  *r_out = r;
+  return r < rc && r > 0.f;
+}
+
+// in-cutoff entries per (frame, atom) row
+__global__ __launch_bounds__(256) void k_mp_count(MpnnBuffers b, SysDev S, ListDev L, WinDev W,
+                                                  int f0, long rows, float rc) {
+  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= rows) return;
+  const int fl = (int)(row / S.n), i = (int)(row - (long)fl * S.n);
+  const int cnt = L.cnt_t[i];
+  int n = 0;
+  for (int m = 0; m < cnt; ++m) {
+    int j;
+    float d[3], r;
+    n += edge_geometry(S, L, W, f0, fl, i, m, rc, &j, d, &r) ? 1 : 0;
   }
+  b.off[row] = n;
+}
+
+// exclusive scan of the row counts in place (one block); off[rows] = total
+__global__ __launch_bounds__(1024) void k_mp_scan(MpnnBuffers b, long rows) {
+  __shared__ long s[1024];
+  const int t = threadIdx.x;
+  const long chunk = (rows + 1023) / 1024;
+  const long lo = min(rows, (long)t * chunk), hi = min(rows, lo + chunk);
+  long sum = 0;
+  for (long r = lo; r < hi; ++r) sum += b.off[r];
+  s[t] = sum;
   __syncthreads();
-  // phase 2: radial basis e_b(r) = sqrt(2/rc) sin(b pi r/rc)/r and de_b/dr
+  for (int o = 1; o < 1024; o <<= 1) {
+    const long v = t >= o ? s[t - o] : 0;
+    __syncthreads();
+    s[t] += v;
+    __syncthreads();
+  }
+  long run = s[t] - sum;
+  for (long r = lo; r < hi; ++r) {
+    const long c = b.off[r];
+    b.off[r] = (int)run;
+    run += c;
+  }
+  if (t == 1023) b.off[rows] = (int)s[1023];
+}
+
+// edge records of every row in list order: source row, neighbour row,
+// f_c, f_c', unit vector and distance
+__global__ __launch_bounds__(256) void k_mp_edges(MpnnBuffers b, SysDev S, ListDev L, WinDev W,
+                                                  int f0, long rows, float rc) {
+  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= rows) return;
+  const int fl = (int)(row / S.n), i = (int)(row - (long)fl * S.n);
+  const int cnt = L.cnt_t[i];
+  long e = b.off[row];
+  const float a = 3.14159265358979f / rc;
+  for (int m = 0; m < cnt; ++m) {
+    int j;
+    float d[3], r;
+    if (!edge_geometry(S, L, W, f0, fl, i, m, rc, &j, d, &r)) continue;
+    b.erow[e] = (int)row;
+    b.enbr[e] = (int)((long)fl * S.n + j);
+    b.fcd[2 * e] = 0.5f * (cosf(a * r) + 1.0f);
+    b.fcd[2 * e + 1] = -0.5f * a * sinf(a * r);
+    b.uv[4 * e] = d[0] / r;
+    b.uv[4 * e + 1] = d[1] / r;
+    b.uv[4 * e + 2] = d[2] / r;
+    b.uv[4 * e + 3] = r;
+    ++e;
+  }
+}
+
+// Radial basis and the first filter layer of all three layers per edge:
+// S = silu(A1 e + a1), DS = silu'(A1 e + a1) (.) (A1 de/dr).  Block: 128
+// threads (channels), kSlotsPerBlock edges.
+__global__ __launch_bounds__(128) void k_mp_radial(MpnnWeights w, MpnnBuffers b, long edges,
+                                                   float rc) {
+  __shared__ float s_e[kSlotsPerBlock][MP_R], s_de[kSlotsPerBlock][MP_R];
+  const int c = threadIdx.x;
+  const long e0 = (long)blockIdx.x * kSlotsPerBlock;
+  // radial basis e_b(r) = sqrt(2/rc) sin(b pi r/rc)/r and de_b/dr
   {
     const int q = c / MP_R, bb = c % MP_R;  // kSlotsPerBlock * MP_R == blockDim
     float e = 0.f, de = 0.f;
-    if (s_on[q]) {
-      const float r = s_r[q];
+    if (e0 + q < edges) {
+      const float r = b.uv[4 * (e0 + q) + 3];
       const float pre = sqrtf(2.0f / rc);
       const float k = (float)(bb + 1) * 3.14159265358979f / rc;
       const float sn = sinf(k * r), cs = cosf(k * r);
@@ -93,7 +138,6 @@ __global__ __launch_bounds__(128) void k_mp_radial(MpnnWeights w, MpnnBuffers b,
     s_de[q][bb] = de;
   }
   __syncthreads();
-  // phase 3: first filter layer, channel c of every layer
   float A[MP_T][MP_R], a1v[MP_T];
 #pragma unroll
   for (int t = 0; t < MP_T; ++t) {
@@ -102,8 +146,8 @@ __global__ __launch_bounds__(128) void k_mp_radial(MpnnWeights w, MpnnBuffers b,
     a1v[t] = w.a1[t][c];
   }
   for (int q = 0; q < kSlotsPerBlock; ++q) {
-    const long slot = s0 + q;
-    if (slot >= slots) break;
+    const long e = e0 + q;
+    if (e >= edges) break;
 #pragma unroll
     for (int t = 0; t < MP_T; ++t) {
       float z = a1v[t], dz = 0.f;
@@ -112,21 +156,21 @@ __global__ __launch_bounds__(128) void k_mp_radial(MpnnWeights w, MpnnBuffers b,
         z = fmaf(A[t][k], s_e[q][k], z);
         dz = fmaf(A[t][k], s_de[q][k], dz);
       }
-      b.S[slot * MP_HT + t * MP_H + c] = siluf(z);
-      b.DS[slot * MP_HT + t * MP_H + c] = dsiluf(z) * dz;
+      b.S[e * MP_HT + t * MP_H + c] = siluf(z);
+      b.DS[e * MP_HT + t * MP_H + c] = dsiluf(z) * dz;
     }
   }
 }
 
 // After Z = S A2^T and DZ = DS A2^T: W = f_c (Z + a2) into Z and
 // dW/dr = f_c' (Z + a2) + f_c DZ into DZ.
-__global__ __launch_bounds__(256) void k_mp_filter(MpnnWeights w, MpnnBuffers b, long slots) {
+__global__ __launch_bounds__(256) void k_mp_filter(MpnnWeights w, MpnnBuffers b, long edges) {
   const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= slots * MP_HT) return;
-  const long slot = id / MP_HT;
-  const int col = (int)(id - slot * MP_HT);
+  if (id >= edges * MP_HT) return;
+  const long e = id / MP_HT;
+  const int col = (int)(id - e * MP_HT);
   const int t = col / MP_H, c = col % MP_H;
-  const float fc = b.fcd[2 * slot], dfc = b.fcd[2 * slot + 1];
+  const float fc = b.fcd[2 * e], dfc = b.fcd[2 * e + 1];
   const float zz = b.Z[id] + w.a2[t][c];
   b.DZ[id] = dfc * zz + fc * b.DZ[id];
   b.Z[id] = fc * zz;
@@ -140,25 +184,17 @@ __global__ __launch_bounds__(128) void k_mp_embed(MpnnWeights w, MpnnBuffers b, 
   b.H[row * MP_H + threadIdx.x] = w.W_emb[sp * MP_H + threadIdx.x];
 }
 
-// out[row][c] = sum_{m < cnt_i} Wt[slot(row, m)][c] * V[neighbour row][c]
+// out[row][c] = sum over the row's edges e of Wt[e][c] * V[neighbour row][c]
 // (messages with V = X_t; dE/dX with V = gM: W is symmetric in the pair)
-__global__ __launch_bounds__(128) void k_mp_gather(MpnnBuffers b, SysDev S, ListDev L, int t,
-                                                   const float* __restrict__ V,
+__global__ __launch_bounds__(128) void k_mp_gather(MpnnBuffers b, int t, const float* __restrict__ V,
                                                    float* __restrict__ out, long rows) {
   const long row = blockIdx.x;
   if (row >= rows) return;
   const int c = threadIdx.x;
-  const long N = S.n, mt = L.mt;
-  const long fl = row / N;
-  const int i = (int)(row - fl * N);
-  const int cnt = L.cnt_t[i];
-  const uint32_t* ent = L.nbr_t + (size_t)i * mt;
+  const int e1 = b.off[row + 1];
   float acc = 0.f;
-  for (int m = 0; m < cnt; ++m) {
-    const int j = (int)(ent[m] >> 5);
-    const float wv = b.Z[(row * mt + m) * MP_HT + t * MP_H + c];
-    acc = fmaf(wv, V[(fl * N + j) * MP_H + c], acc);
-  }
+  for (int e = b.off[row]; e < e1; ++e)
+    acc = fmaf(b.Z[(long)e * MP_HT + t * MP_H + c], V[(long)b.enbr[e] * MP_H + c], acc);
   out[row * MP_H + c] = acc;
 }
 
@@ -208,22 +244,15 @@ __global__ __launch_bounds__(256) void k_mp_mul_dsilu(const float* __restrict__ 
   g[id] *= dsiluf(U[id]);
 }
 
-// dE/dr of one slot, both directions of the pair, layer t:
-// sum_c (gM[a] X[b] + gM[b] X[a])_c dW_c/dr.  One wave per slot.
-__global__ __launch_bounds__(256) void k_mp_dedr(MpnnBuffers b, SysDev S, ListDev L, int t,
-                                                 const float* __restrict__ X, long slots) {
-  const long slot = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+// dE/dr of one edge, both directions of the pair, layer t:
+// sum_c (gM[a] X[b] + gM[b] X[a])_c dW_c/dr.  One wave per edge.
+__global__ __launch_bounds__(256) void k_mp_dedr(MpnnBuffers b, int t, const float* __restrict__ X,
+                                                 long edges) {
+  const long e = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (slot >= slots) return;  // uniform per wave
-  const long N = S.n, mt = L.mt;
-  const long row = slot / mt;
-  const int m = (int)(slot - row * mt);
-  const long fl = row / N;
-  const int i = (int)(row - fl * N);
-  if (m >= L.cnt_t[i]) return;  // uniform per wave
-  const int j = (int)(L.nbr_t[(size_t)i * mt + m] >> 5);
-  const long ra = row * MP_H, rb = (fl * N + j) * MP_H;
-  const float* dW = b.DZ + slot * MP_HT + t * MP_H;
+  if (e >= edges) return;  // uniform per wave
+  const long ra = (long)b.erow[e] * MP_H, rb = (long)b.enbr[e] * MP_H;
+  const float* dW = b.DZ + e * MP_HT + t * MP_H;
   float acc = 0.f;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -233,25 +262,24 @@ __global__ __launch_bounds__(256) void k_mp_dedr(MpnnBuffers b, SysDev S, ListDe
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (lane == 0) b.gr[slot] += acc;
+  if (lane == 0) b.gr[e] += acc;
 }
 
-// F_a = sum over a's slots of dE/dr (q_b - q_a)/r, frame-major [f][3][N]
-__global__ __launch_bounds__(256) void k_mp_forces(MpnnBuffers b, SysDev S, ListDev L, int f0,
-                                                   float* Fout, long rows) {
+// F_a = sum over a's edges of dE/dr (q_b - q_a)/r, frame-major [f][3][N]
+__global__ __launch_bounds__(256) void k_mp_forces(MpnnBuffers b, SysDev S, int f0, float* Fout,
+                                                   long rows) {
   const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= rows) return;
-  const long N = S.n, mt = L.mt;
+  const long N = S.n;
   const long fl = row / N;
   const int i = (int)(row - fl * N);
-  const int cnt = L.cnt_t[i];
   float fx = 0.f, fy = 0.f, fz = 0.f;
-  for (int m = 0; m < cnt; ++m) {
-    const long slot = row * mt + m;
-    const float g = b.gr[slot];
-    fx = fmaf(g, b.uv[4 * slot], fx);
-    fy = fmaf(g, b.uv[4 * slot + 1], fy);
-    fz = fmaf(g, b.uv[4 * slot + 2], fz);
+  const int e1 = b.off[row + 1];
+  for (int e = b.off[row]; e < e1; ++e) {
+    const float g = b.gr[e];
+    fx = fmaf(g, b.uv[4 * e], fx);
+    fy = fmaf(g, b.uv[4 * e + 1], fy);
+    fz = fmaf(g, b.uv[4 * e + 2], fz);
   }
   float* F = Fout + (size_t)(f0 + fl) * 3 * N;
   F[i] = fx;
@@ -291,6 +319,7 @@ size_t mpnn_buffer_bytes(int frames, int n, int mt) {
   size_t b = 0;
   b += 4 * al(slots * MP_HT * 4);            // S, DS, Z, DZ
   b += al(slots * 2 * 4) + al(slots * 4 * 4) + al(slots * 4);
+  b += al((rows + 1) * 4) + 2 * al(slots * 4);   // row offsets, edge rows
   b += al((MP_T + 1) * rows * MP_H * 4) + 2 * al(MP_T * rows * MP_H * 4);
   b += 2 * al(rows * MP_H * 4) + 2 * al(rows * MP_RH * 4) + 5 * al(rows * MP_H * 4);
   return b;
@@ -313,6 +342,9 @@ void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* w
   b.fcd = take(slots * 2 * 4);
   b.uv = take(slots * 4 * 4);
   b.gr = take(slots * 4);
+  b.off = reinterpret_cast<int*>(take((rows + 1) * 4));
+  b.erow = reinterpret_cast<int*>(take(slots * 4));
+  b.enbr = reinterpret_cast<int*>(take(slots * 4));
   b.H = take((MP_T + 1) * rows * MP_H * 4);
   b.X = take(MP_T * rows * MP_H * 4);
   b.U = take(MP_T * rows * MP_H * 4);
@@ -371,14 +403,32 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
   const MpnnWeights& w = M.w;
   MpnnBuffers& b = M.b;
   const long N = S.n, mt = L.mt;
-  const long rows = (long)nf * N, slots = rows * mt;
+  const long rows = (long)nf * N;
   MP_BLAS(rocblas_set_stream(M.blas, st));
-  // filters of all layers
-  hipLaunchKernelGGL(k_mp_radial, dim3(nblk(slots, kSlotsPerBlock)), dim3(128), 0, st, w, b, S, L,
-                     W, f0, nf, M.rc);
+  // compact the in-cutoff pairs of every row into edges (list order)
+  hipLaunchKernelGGL(k_mp_count, dim3(nblk(rows, 256)), dim3(256), 0, st, b, S, L, W, f0, rows, M.rc);
   MP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_mp_scan, dim3(1), dim3(1024), 0, st, b, rows);
+  MP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_mp_edges, dim3(nblk(rows, 256)), dim3(256), 0, st, b, S, L, W, f0, rows, M.rc);
+  MP_HIP(hipGetLastError());
+  // the edge count sizes the contractions below
+  int total = 0;
+  MP_HIP(hipMemcpyAsync(&total, b.off + rows, sizeof(int), hipMemcpyDeviceToHost, st));
+  MP_HIP(hipStreamSynchronize(st));
+  const long slots = total;
+  if (slots > rows * mt) {
+    snprintf(err, errlen, "edge count %ld exceeds capacity %ld", slots, rows * mt);
+    return false;
+  }
+  if (slots > 0) {
+    hipLaunchKernelGGL(k_mp_radial, dim3(nblk(slots, kSlotsPerBlock)), dim3(128), 0, st, w, b, slots,
+                       M.rc);
+    MP_HIP(hipGetLastError());
+  }
   const float one = 1.0f, zero = 0.0f;
   // Z_t = S_t A2_t^T and DZ_t = DS_t A2_t^T for the three layers at once
+  if (slots > 0) {
   MP_BLAS(rocblas_sgemm_strided_batched(M.blas, rocblas_operation_transpose,
                                         rocblas_operation_none, MP_H, (int)slots, MP_H, &one,
                                         w.A2[0], MP_H, w.layer_stride, b.S, MP_HT, MP_H, &zero,
@@ -389,6 +439,7 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
                                         b.DZ, MP_HT, MP_H, MP_T));
   hipLaunchKernelGGL(k_mp_filter, dim3(nblk(slots * MP_HT, 256)), dim3(256), 0, st, w, b, slots);
   MP_HIP(hipGetLastError());
+  }
   // forward through the layers
   hipLaunchKernelGGL(k_mp_embed, dim3((unsigned)rows), dim3(MP_H), 0, st, w, b, S, rows);
   MP_HIP(hipGetLastError());
@@ -399,8 +450,7 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
     float* Xt = b.X + t * rh;
     float* Ut = b.U + t * rh;
     MP_BLAS(gemm_rm(M.blas, Ht, w.B[t], Xt, (int)rows, MP_H, MP_H, true, 0.f, MP_H, MP_H));
-    hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, S, L, t, Xt, b.Mm,
-                       rows);
+    hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, t, Xt, b.Mm, rows);
     MP_HIP(hipGetLastError());
     MP_BLAS(gemm_rm(M.blas, b.Mm, w.C1[t], Ut, (int)rows, MP_H, MP_H, true, 0.f, MP_H, MP_H));
     hipLaunchKernelGGL(k_mp_act, dim3(nblk(rh, 256)), dim3(256), 0, st, w.c1[t], Ut, b.Sn, rh);
@@ -416,8 +466,10 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
                      epart);
   MP_HIP(hipGetLastError());
   MP_BLAS(gemm_rm(M.blas, b.gY, w.W1, b.gH, (int)rows, MP_H, MP_RH, false, 0.f, MP_RH, MP_H));
-  hipLaunchKernelGGL(k_mp_zero, dim3(nblk(slots, 256)), dim3(256), 0, st, b.gr, slots);
-  MP_HIP(hipGetLastError());
+  if (slots > 0) {
+    hipLaunchKernelGGL(k_mp_zero, dim3(nblk(slots, 256)), dim3(256), 0, st, b.gr, slots);
+    MP_HIP(hipGetLastError());
+  }
   // reverse pass through the layers
   for (int t = MP_T - 1; t >= 0; --t) {
     float* Xt = b.X + t * rh;
@@ -426,11 +478,13 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
     hipLaunchKernelGGL(k_mp_mul_dsilu, dim3(nblk(rh, 256)), dim3(256), 0, st, Ut, b.gS, rh);
     MP_HIP(hipGetLastError());
     MP_BLAS(gemm_rm(M.blas, b.gS, w.C1[t], b.gM, (int)rows, MP_H, MP_H, false, 0.f, MP_H, MP_H));
-    hipLaunchKernelGGL(k_mp_dedr, dim3(nblk(slots, 4)), dim3(256), 0, st, b, S, L, t, Xt, slots);
-    MP_HIP(hipGetLastError());
+    if (slots > 0) {
+      hipLaunchKernelGGL(k_mp_dedr, dim3(nblk(slots, 4)), dim3(256), 0, st, b, t, Xt, slots);
+      MP_HIP(hipGetLastError());
+    }
     if (t > 0) {
-      hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, S, L, t, b.gM,
-                         b.gX, rows);
+      hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, t, b.gM, b.gX,
+                         rows);
       MP_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_mp_copy, dim3(nblk(rh, 256)), dim3(256), 0, st, b.gH, b.gP, rh);
       MP_HIP(hipGetLastError());
@@ -440,7 +494,7 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
       b.gP = tmp;
     }
   }
-  hipLaunchKernelGGL(k_mp_forces, dim3(nblk(rows, 256)), dim3(256), 0, st, b, S, L, f0, Fout, rows);
+  hipLaunchKernelGGL(k_mp_forces, dim3(nblk(rows, 256)), dim3(256), 0, st, b, S, f0, Fout, rows);
   MP_HIP(hipGetLastError());
   return true;
 }

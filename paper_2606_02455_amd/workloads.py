@@ -251,6 +251,20 @@ def mpnn_weight_shapes(n_species: int, H: int = MPNN_HIDDEN, R: int = MPNN_RBF,
     return shapes
 
 
+# Energy scale s_E of the seeded network (weights mpnn_weights(3, seed=17)):
+# the RMS force component on the seeded 1536-atom liquid of config("c3") is
+# then 1 eV/Angstrom.  Computed once by the FP64 evaluation of the network
+# (tests/golden/make_mpnn_scale.py) and fixed before any draft work.
+MPNN_WEIGHT_SEED = 17
+MPNN_C3_SCALE = 115.52612798524363
+
+
+def mpnn_target(n_species: int = 3, rc: float = 5.0) -> dict:
+    """The message-passing target of the triatomic configurations."""
+    return dict(kind="mpnn", rc=rc, weights=mpnn_weights(n_species, seed=MPNN_WEIGHT_SEED),
+                n_model_species=n_species, scale=MPNN_C3_SCALE)
+
+
 def mpnn_weights(n_species: int = 3, seed: int = 17) -> np.ndarray:
     """Seeded random-init weights: U(+-1/sqrt(fan_in)) for every matrix and
     the readout vector, zero biases, N(0, 1) species embeddings; rounded to

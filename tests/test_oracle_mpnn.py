@@ -165,3 +165,10 @@ def test_mpnn_special_weights_reduce_to_scalar_form(ora):
                 xm[i, a] -= h
                 fd = -(_special_energy(sp, xp, 5.0, 1.7) - _special_energy(sp, xm, 5.0, 1.7)) / (2 * h)
                 assert F[i, a] == pytest.approx(fd, rel=1e-5, abs=1e-7)
+
+
+def test_workload_energy_scale_is_the_golden_value():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "mpnn_c3_scale.txt")
+    val = [float(l.split("=")[1]) for l in open(path) if l.startswith("scale")][0]
+    assert W.MPNN_C3_SCALE == val
