@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+EC_MODES = {"off": 0, "on": 1, "linear": 2}
 COPY_BYTES = 256 << 20  # calibration copy: 256 MiB read + 256 MiB written
 VERIFY_SOURCES = ["paper_2606_02455_amd/csrc/lsd_kernels.hip",
                   "paper_2606_02455_amd/csrc/lsd_device.h"]
@@ -79,7 +80,7 @@ def in_cutoff_pairs(sysg, rc):
     return int(((r2 < rc * rc) & valid).sum().item())
 
 
-def cpu_baseline(w, q, p, seconds, ec_on):
+def cpu_baseline(w, q, p, seconds, ec_mode):
     """The FP64 oracle as it stands: LSD windows of K frames from the
     benchmark's equilibrated state until `seconds` of host time are spent
     (with the same error-correction setting as the GPU run)."""
@@ -91,7 +92,9 @@ def cpu_baseline(w, q, p, seconds, ec_on):
     D = oracle.Potential.lj(w.draft["rc"])
     q, p = q.copy(), p.copy()
     img = np.zeros(q.shape, np.int32)
-    ec = np.zeros(q.shape) if ec_on else None
+    ec = np.zeros(q.shape) if ec_mode >= 1 else None
+    ec_prev = np.zeros(q.shape) if ec_mode == 2 else None
+    samples = np.zeros(1, np.int32)
     K, N = w.K, w.n_atoms
     committed = windows = 0
     step = 0
@@ -99,7 +102,7 @@ def cpu_baseline(w, q, p, seconds, ec_on):
     while time.perf_counter() - t0 < seconds:
         xi = np.stack([oracle.normals(w.seed, 0, step + k + 1, N) for k in range(K)])
         u = np.array([oracle.uniform(w.seed, 0, step + k + 1) for k in range(K)])
-        r = oracle.lsd_window(so, T, D, q, p, img, xi, u, ec=ec)
+        r = oracle.lsd_window(so, T, D, q, p, img, xi, u, ec=ec, ec_prev=ec_prev, samples=samples)
         committed += r["n_committed"]
         step += r["n_committed"]
         windows += 1
@@ -136,7 +139,7 @@ def run_c3(args, lsd, W, torch):
     K, N = w.K, w.n_atoms
     nb, rc_d = args.pair_basis, float(w.draft["rc"])
     target = W.mpnn_target()
-    ec_on = args.ec == "on"
+    ec_on = args.ec != "off"
     log(f"workload {w.name}: N={N} K={K} box={w.box[0]:.4f} A")
     plain = lsd.LSDSystem(w, mode="plain", target=target)
     eq_windows = max(1, args.equilibrate // K)
@@ -162,7 +165,8 @@ def run_c3(args, lsd, W, torch):
     if plain.status():
         raise RuntimeError(f"device status {plain.status()} during plain stepping")
     draft = dict(kind="pair", rc=rc_d, weights=wts, n_basis=nb, n_model_species=3)
-    g = lsd.LSDSystem(w, mode="lsd", target=target, draft=draft, error_correction=ec_on)
+    g = lsd.LSDSystem(w, mode="lsd", target=target, draft=draft,
+                      error_correction=EC_MODES[args.ec])
     for a, b in ((g.q, plain.q), (g.p, plain.p), (g.img, plain.img), (g.step, plain.step)):
         a.copy_(b)
     g.run_windows(args.warmup, K)
@@ -210,7 +214,7 @@ def run_c3(args, lsd, W, torch):
                          f"draft: pair forces (rc {rc_d} A, {nb} basis) force-matched on "
                          f"{fit_windows * K} target frames; error correction {args.ec}"),
             "n_atoms": N, "K": K, "fit_frames": fit_windows * K,
-            "error_correction": ec_on},
+            "error_correction": args.ec},
         "acceptance": round(1.0 - rejections / max(committed, 1), 5),
         "committed_per_window": round(committed / windows, 4),
         "plain_steps_per_s": round(plain_rate, 3),
@@ -240,8 +244,9 @@ def main():
     ap.add_argument("--equilibrate", type=int, default=256, help="plain steps before timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--ec", choices=["on", "off"], default="on",
-                    help="speculative error correction of the draft (App. D)")
+    ap.add_argument("--ec", choices=["on", "off", "linear"], default="on",
+                    help="speculative error correction of the draft (App. D); linear: "
+                         "extrapolated from the last two committed errors")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -269,8 +274,8 @@ def main():
     eq_windows = max(1, args.equilibrate // K)
     plain.run_windows(eq_windows, K)
     torch.cuda.synchronize()
-    ec_on = args.ec == "on"
-    lsds = lsd.LSDSystem(w, mode="lsd", error_correction=ec_on)
+    ec_on = args.ec != "off"
+    lsds = lsd.LSDSystem(w, mode="lsd", error_correction=EC_MODES[args.ec])
     lsds.q.copy_(plain.q)
     lsds.p.copy_(plain.p)
     lsds.img.copy_(plain.img)
@@ -334,7 +339,7 @@ def main():
     if not args.no_cpu_baseline:
         st = lsds.state()
         log("timing the FP64 oracle on the host ...")
-        cpu = cpu_baseline(w, st["q"], st["p"], args.cpu_seconds, ec_on)
+        cpu = cpu_baseline(w, st["q"], st["p"], args.cpu_seconds, EC_MODES[args.ec])
         log(f"oracle: {cpu['value']:.3f} LSD steps/s, {cpu['plain_steps_per_s']:.3f} plain steps/s "
             f"on {cpu['cores']} threads")
 
@@ -358,7 +363,7 @@ def main():
                          f"target cutoff {w.target['rc']}, draft cutoff {w.draft['rc']}, "
                          f"K={K}, dt={w.dt}, gamma={w.gamma}, seed {w.seed}, "
                          f"error correction {args.ec}"),
-            "n_atoms": w.n_atoms, "K": K, "skin": w.skin, "error_correction": ec_on,
+            "n_atoms": w.n_atoms, "K": K, "skin": w.skin, "error_correction": args.ec,
         },
         "acceptance": round(1.0 - rejections / max(committed, 1), 5),
         "committed_per_window": round(committed / windows, 4),

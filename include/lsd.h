@@ -146,14 +146,18 @@ typedef struct {
   int32_t max_neighbors_target;/* neighbour-list width; 0 = automatic */
   int32_t max_neighbors_draft; /* 0 = automatic */
   int32_t error_correction;    /* speculative error correction (App. D,
-                                  Alg. 3), LSD mode only: != 0 draws every
-                                  draft of a window from the Gaussian of Eq.
-                                  bob with F~ + dF, dF = F - F~ (target minus
+                                  Alg. 3), LSD mode only.  1: every draft of a
+                                  window is drawn from the Gaussian of Eq. bob
+                                  with F~ + dF, dF = F - F~ (target minus
                                   EC-uncorrected draft force, binary32) of the
                                   last committed step, cached per atom; the
-                                  cache starts at 0.  Target forces and the
-                                  acceptance rule are unchanged, so the target
-                                  law is preserved. */
+                                  cache starts at 0.  2: as 1, but once two
+                                  committed errors dF (step s) and dF' (step
+                                  s-1) are held, frame k uses the linear
+                                  extrapolation dF + (k+1)(dF - dF').  0: off.
+                                  Target forces and the acceptance rule are
+                                  unchanged, so the target law is preserved
+                                  for any setting. */
   int32_t no_list_reuse;       /* 0 (default): the neighbour lists of a
                                   replica are kept across windows until one of
                                   its atoms has moved more than skin/4 from
@@ -265,6 +269,8 @@ typedef struct {
   size_t cnt_draft;  /* int32 [N] */
   size_t error_cache;/* float [3][N] dF of the error correction; 0 (no
                         array) when it is off */
+  size_t error_cache_prev; /* float [3][N] dF of the committed step before
+                        (linear variant), else 0 */
   int32_t max_neighbors_target, max_neighbors_draft;
   int32_t n_atoms, k_max;
 } lsd_window_layout;

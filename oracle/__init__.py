@@ -85,11 +85,12 @@ def _declare(L):
                                    C.c_double, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.ora_verify_frame.restype = C.c_int
     L.ora_lsd_window.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), C.POINTER(_Pot), _dp,
-                                 _dp, _ip, C.c_int, _dp, _dp, C.POINTER(_WinOut), _dp]
+                                 _dp, _ip, C.c_int, _dp, _dp, C.POINTER(_WinOut), _dp, _dp,
+                                 C.POINTER(C.c_int)]
     L.ora_lsd_window.restype = C.c_int
     L.ora_lsd_run.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), C.POINTER(_Pot), _dp, _dp,
                               _ip, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, C.c_int,
-                              _dp, _dp, C.POINTER(_Stats), _dp]
+                              _dp, _dp, C.POINTER(_Stats), _dp, _dp]
     L.ora_plain_run.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), _dp, _dp, _ip,
                                 C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, _dp, _dp, _dp]
     L.ora_num_threads.restype = C.c_int
@@ -218,9 +219,10 @@ def verify_frame(system, target, q_mid, p_prev, p_new, F_d, u):
                 S2=s2.value, p=po, q=qo)
 
 
-def lsd_window(system, target, draft, q, p, img, xi, u, ec=None):
+def lsd_window(system, target, draft, q, p, img, xi, u, ec=None, ec_prev=None, samples=None):
     """One synchronous LSD window; (q, p, img) advance in place.  ec: the
-    error-correction cache [n, 3] (App. D), updated in place, or None."""
+    error-correction cache [n, 3] (App. D), updated in place, or None;
+    ec_prev and samples (a one-element int32 array): the linear variant."""
     n, K = system.n, len(u)
     xi = _f64(xi).reshape(K, n, 3)
     u = _f64(u)
@@ -231,21 +233,25 @@ def lsd_window(system, target, draft, q, p, img, xi, u, ec=None):
     o = _WinOut(_d(res["logr"]), _d(res["S1"]), _d(res["S2"]), _d(res["E_target"]),
                 acc.ctypes.data_as(C.POINTER(C.c_int8)), _d(qm), _d(pd), _d(Fd), _d(Ft), 0, 0)
     lib().ora_lsd_window(C.byref(system._c), C.byref(target._c), C.byref(draft._c), _d(q), _d(p),
-                         img.ctypes.data_as(_ip), K, _d(xi), _d(u), C.byref(o), _d(ec))
+                         img.ctypes.data_as(_ip), K, _d(xi), _d(u), C.byref(o), _d(ec),
+                         _d(ec_prev),
+                         None if samples is None else samples.ctypes.data_as(C.POINTER(C.c_int)))
     res.update(accept=acc.astype(bool), q_mid=qm, p_draft=pd, F_draft=Fd, F_target=Ft,
                n_committed=o.n_committed, rejected=bool(o.rejected))
     return res
 
 
 def lsd_run(system, target, draft, q, p, img, seed, replica, step0, n_steps, K, record=False,
-            ec=None):
+            ec=None, ec_prev=None):
+    """LSD from committed step step0 until n_steps more are committed; ec
+    (and ec_prev for the linear variant) are the error-correction caches."""
     n = system.n
     tq = np.zeros((n_steps, n, 3)) if record else None
     tp = np.zeros((n_steps, n, 3)) if record else None
     st = _Stats()
     lib().ora_lsd_run(C.byref(system._c), C.byref(target._c), C.byref(draft._c), _d(q), _d(p),
                       img.ctypes.data_as(_ip), seed, replica, step0, n_steps, K, _d(tq), _d(tp),
-                      C.byref(st), _d(ec))
+                      C.byref(st), _d(ec), _d(ec_prev))
     stats = dict(windows=st.windows, rejections=st.rejections, frames=st.frames,
                  committed=st.committed)
     return stats, tq, tp

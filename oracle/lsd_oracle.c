@@ -487,18 +487,25 @@ typedef struct {
  * speculative error correction (App. D, Alg. 3) the mean of the draft
  * Gaussian is taken from F~ + dF, dF being the cached target-minus-draft force
  * error of the last committed step, and F_c receives that corrected force;
- * without it (dF == NULL) F_c = F~. */
+ * without it (dF == NULL) F_c = F~.  Linear variant (dF_prev != NULL, the
+ * error of the committed step before): the error is extrapolated to this
+ * draft, which produces the (lag)-th step after the last committed one:
+ * dF + lag (dF - dF_prev). */
 static void draft_step(const ora_sys *S, const ora_pot *D, double *q,
                        double *p, int32_t *img, const double *xi,
                        double *q_mid, double *F_d, const double *dF,
-                       double *F_c) {
+                       const double *dF_prev, int lag, double *F_c) {
   int m = 3 * S->n;
   double *mu = (double *)malloc(sizeof(double) * m);
   double *sg = (double *)malloc(sizeof(double) * m);
   step_A(S, p, q, img);                           /* q~ <- q~ + dt/2 M^-1 p~ */
   memcpy(q_mid, q, sizeof(double) * m);
   ora_energy_forces(D, S->n, q, S->L, F_d, 1);    /* F~ <- draft forces */
-  for (int c = 0; c < m; ++c) F_c[c] = dF ? F_d[c] + dF[c] : F_d[c];
+  for (int c = 0; c < m; ++c) {
+    double corr = dF ? dF[c] : 0.0;
+    if (dF && dF_prev) corr = dF[c] + (double)lag * (dF[c] - dF_prev[c]);
+    F_c[c] = F_d[c] + corr;
+  }
   bob_mean(S, p, F_c, mu);                        /* <p~> from Eq. bob */
   bob_sigma(S, sg);
   for (int c = 0; c < m; ++c) p[c] = mu[c] + sg[c] * xi[c]; /* p~ ~ N */
@@ -540,11 +547,14 @@ int ora_verify_frame(const ora_sys *S, const ora_pot *T, const double *q_mid,
  * (q, p, img) to the last kept state.  dF (NULL: no error correction) is the
  * error cache of App. D: every draft of the window is corrected by its value
  * on entry, and on return it holds F - F~ (target minus bare draft force) of
- * the last committed step, accepted or reflected. */
+ * the last committed step, accepted or reflected.  Linear variant: dF_prev
+ * holds the error of the committed step before and *samples the number of
+ * committed errors seen (capped at 2); with two samples, draft k of the
+ * window (producing the (k+1)-th new step) uses dF + (k+1) (dF - dF_prev). */
 int ora_lsd_window(const ora_sys *S, const ora_pot *T, const ora_pot *D,
                    double *q, double *p, int32_t *img, int K,
                    const double *xi, const double *u, ora_window_out *out,
-                   double *dF) {
+                   double *dF, double *dF_prev, int *samples) {
   int n = S->n, m = 3 * n;
   double *qm = (double *)malloc(sizeof(double) * (size_t)K * m);
   double *pd = (double *)malloc(sizeof(double) * (size_t)(K + 1) * m);
@@ -571,7 +581,9 @@ int ora_lsd_window(const ora_sys *S, const ora_pot *T, const ora_pot *D,
     memcpy(&imgs[(size_t)(k + 1) * m], &imgs[(size_t)k * m], sizeof(int32_t) * m);
     draft_step(S, D, &qd[(size_t)(k + 1) * m], &pd[(size_t)(k + 1) * m],
                &imgs[(size_t)(k + 1) * m], &xi[(size_t)k * m],
-               &qm[(size_t)k * m], &Fd[(size_t)k * m], dF, &Fc[(size_t)k * m]);
+               &qm[(size_t)k * m], &Fd[(size_t)k * m], dF,
+               (dF_prev && samples && *samples >= 2) ? dF_prev : NULL, k + 1,
+               &Fc[(size_t)k * m]);
   }
   /* verification: independent frames, in parallel */
 #pragma omp parallel for schedule(dynamic, 1)
@@ -601,9 +613,14 @@ int ora_lsd_window(const ora_sys *S, const ora_pot *T, const ora_pot *D,
     memcpy(q, &qd[(size_t)K * m], sizeof(double) * m);
     memcpy(img, &imgs[(size_t)K * m], sizeof(int32_t) * m);
   }
-  if (dF) /* new error cache from the EC-uncorrected draft force */
-    for (int c = 0; c < m; ++c)
+  if (dF) { /* new error caches from the EC-uncorrected draft forces */
+    for (int c = 0; c < m; ++c) {
+      if (dF_prev)
+        dF_prev[c] = j >= 2 ? Ft[(size_t)(j - 2) * m + c] - Fd[(size_t)(j - 2) * m + c] : dF[c];
       dF[c] = Ft[(size_t)(j - 1) * m + c] - Fd[(size_t)(j - 1) * m + c];
+    }
+    if (samples) *samples = (*samples + j) < 2 ? (*samples + j) : 2;
+  }
   if (out) {
     if (out->logr) memcpy(out->logr, lr, sizeof(double) * K);
     if (out->S1) memcpy(out->S1, s1, sizeof(double) * K);
@@ -638,7 +655,9 @@ typedef struct {
 void ora_lsd_run(const ora_sys *S, const ora_pot *T, const ora_pot *D,
                  double *q, double *p, int32_t *img, uint64_t seed,
                  uint32_t replica, uint64_t step0, int64_t n_steps, int K,
-                 double *traj_q, double *traj_p, ora_run_stats *st, double *dF) {
+                 double *traj_q, double *traj_p, ora_run_stats *st, double *dF,
+                 double *dF_prev) {
+  int samples = 0; /* committed errors held by the linear error correction */
   int n = S->n, m = 3 * n;
   double *xi = (double *)malloc(sizeof(double) * (size_t)K * m);
   double *u = (double *)malloc(sizeof(double) * K);
@@ -661,7 +680,7 @@ void ora_lsd_run(const ora_sys *S, const ora_pot *T, const ora_pot *D,
     o.accept = acc;
     o.q_mid = qm;
     o.p_draft = pd;
-    int j = ora_lsd_window(S, T, D, q, p, img, Kw, xi, u, &o, dF);
+    int j = ora_lsd_window(S, T, D, q, p, img, Kw, xi, u, &o, dF, dF_prev, &samples);
     if (traj_q) {
       /* committed states: accepted draft states then the final state */
       double *qt = (double *)malloc(sizeof(double) * m);

@@ -61,7 +61,7 @@ struct Layout {
   size_t nbr_t, cnt_t, nbr_d, cnt_d, qref, qwrap, rebuild;
   // window
   size_t qmid, p, fd, ft, invalid, partial, commit_frame, reflected, coef, counters, status;
-  size_t ec = 0;  // error-correction cache (0: off)
+  size_t ec = 0, ec_prev = 0, ec_samples = 0;  // error-correction caches (0: off)
   size_t mpnn = 0, mpnn_bytes = 0, blas = 0, epart = 0;
   bool has_mpnn = false;
   int mt = 0, md = 0, n_cells = 0, n_tiles = 0, cell_cap = 0;
@@ -133,6 +133,8 @@ lsd_status plan(const lsd_config* c, Layout* L) {
     return fail(LSD_ERR_INVALID_ARG, "k_max %d outside 1..%d", c->k_max, LSD_MAX_K);
   if (c->mode != LSD_MODE_LSD && c->mode != LSD_MODE_PLAIN)
     return fail(LSD_ERR_INVALID_ARG, "mode %d invalid", c->mode);
+  if (c->error_correction < 0 || c->error_correction > 2)
+    return fail(LSD_ERR_INVALID_ARG, "error_correction %d outside 0..2", c->error_correction);
   LSD_TRY(check_potential(c->target, "target"));
   if (c->mode == LSD_MODE_LSD) LSD_TRY(check_potential(c->draft, "draft"));
   if (c->mode == LSD_MODE_LSD && c->draft.kind == LSD_POT_MPNN)
@@ -242,7 +244,11 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   L->coef = bump(&off, R * 8);
   L->counters = bump(&off, (size_t)R * LSD_NCOUNT * 8);
   L->status = bump(&off, 4 * 4);
-  if (c->error_correction && c->mode == LSD_MODE_LSD) L->ec = bump(&off, 3 * n * 4);
+  if (c->error_correction && c->mode == LSD_MODE_LSD) {
+    L->ec = bump(&off, 3 * n * 4);
+    L->ec_samples = bump(&off, (size_t)R * 4);
+    if (c->error_correction == 2) L->ec_prev = bump(&off, 3 * n * 4);
+  }
   L->has_mpnn = c->target.kind == LSD_POT_MPNN;
   if (L->has_mpnn) {
     L->mpnn_bytes = mpnn_buffer_bytes(c->k_max, N, L->mt);
@@ -471,6 +477,8 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   if (e == hipSuccess) e = launch_zero_i64(ws<long long>(s, L.counters), LSD_NCOUNT * R, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_d), 0, N, st);
   if (e == hipSuccess && L.ec) e = launch_fill_int(ws<int>(s, L.ec), 0, 3 * N, st);  // +0.0f
+  if (e == hipSuccess && L.ec) e = launch_fill_int(ws<int>(s, L.ec_samples), 0, R, st);
+  if (e == hipSuccess && L.ec_prev) e = launch_fill_int(ws<int>(s, L.ec_prev), 0, 3 * N, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.rebuild), 1, R, st);  // first window builds
   if (e == hipSuccess) e = prepare_verify(L.mt);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -555,6 +563,8 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   W.coef = ws<double>(s, L.coef);
   W.counters = ws<long long>(s, L.counters);
   W.ec = L.ec ? ws<float>(s, L.ec) : nullptr;
+  W.ec_prev = L.ec_prev ? ws<float>(s, L.ec_prev) : nullptr;
+  W.ec_samples = L.ec ? ws<int>(s, L.ec_samples) : nullptr;
   W.K = 0;
 
   TileDev& T = s->T;
@@ -741,6 +751,7 @@ lsd_status lsd_get_window_layout(const lsd_system* s, lsd_window_layout* out) {
   out->nbr_draft = s->lay.nbr_d;
   out->cnt_draft = s->lay.cnt_d;
   out->error_cache = s->lay.ec;
+  out->error_cache_prev = s->lay.ec_prev;
   out->max_neighbors_target = s->lay.mt;
   out->max_neighbors_draft = s->lay.md;
   out->n_atoms = s->S.n;

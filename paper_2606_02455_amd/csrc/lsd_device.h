@@ -107,6 +107,8 @@ struct WinDev {
   int* reflected;     // [R]
   double* coef;       // [R] 2 S1 / S2 of the rejected frame
   float* ec;          // [3][N] error-correction cache dF, or null (off)
+  float* ec_prev;     // [3][N] dF of the committed step before, or null (constant EC)
+  int* ec_samples;    // [R] committed error samples held (0, 1, 2 = both caches valid)
   long long* counters;  // [R][5]: windows, committed steps, rejections, frames verified,
                         // neighbour-list builds
   int K;              // frames in the current window
@@ -208,10 +210,16 @@ __device__ __forceinline__ float a_half_cont(float x, float p, double hdt_m) {
   return (float)((double)x + hdt_m * (double)p);
 }
 
-// Draft force that enters the draft mean: F~ itself, or F~ + dF in binary32
-// with error correction on (App. D).
-__device__ __forceinline__ float draft_mean_force(const float* ec, size_t c, float Fd) {
-  return ec ? Fd + ec[c] : Fd;
+// Draft force that enters the draft mean of frame k of replica r: F~ itself,
+// or F~ + dF with error correction on (App. D), dF being the error of the
+// last committed step; with the linear variant and two samples held, the
+// error is extrapolated to the frame: dF + (k + 1) (dF - dF_prev).  Binary32,
+// the same expression wherever the draft mean is formed.
+__device__ __forceinline__ float draft_mean_force(const WinDev& W, int r, size_t c, int k, float Fd) {
+  if (!W.ec) return Fd;
+  float corr = W.ec[c];
+  if (W.ec_prev && W.ec_samples[r] >= 2) corr = corr + (float)(k + 1) * (W.ec[c] - W.ec_prev[c]);
+  return Fd + corr;
 }
 
 // Mean of the (BOB) Gaussian: e^{-gamma dt} p + (1 + e^{-gamma dt}) dt/2 F.

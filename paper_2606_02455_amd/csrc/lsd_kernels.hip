@@ -440,7 +440,7 @@ __global__ __launch_bounds__(256) void k_draft(SysDev S, ListDev Lst, WinDev W, 
   float pn[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const float Fm = draft_mean_force(W.ec, d * N + i, F[d]);
+    const float Fm = draft_mean_force(W, r, d * N + i, k, F[d]);
     double mu = bob_mean(S.a, S.c1fu, pk[d * N + i], Fm);
     pn[d] = (float)fma(sg, xi[d], mu);
     fk[d * N + i] = F[d];
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, 
         float* ftk = W.ft + (size_t)fr * 3 * N;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          const float Fd = draft_mean_force(W.ec, d * N + i, fdk[d * N + i]);
+          const float Fd = draft_mean_force(W, r, d * N + i, fr, fdk[d * N + i]);
           ftk[d * N + i] = Ft[d];
           const double mud = bob_mean(S.a, S.c1fu, pk[d * N + i], Fd);
           const double z = ((double)pk1[d * N + i] - mud) * isg;
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(64) void k_transport(SysDev S, WinDev W, TileDev Tl
     const float* ftk = W.ft + (size_t)f * 3 * N;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float Fd = draft_mean_force(W.ec, d * N + i, fdk[d * N + i]), Ft = ftk[d * N + i];
+      const float Fd = draft_mean_force(W, r, d * N + i, f, fdk[d * N + i]), Ft = ftk[d * N + i];
       const double mud = bob_mean(S.a, S.c1fu, pk[d * N + i], Fd);
       const double z = ((double)pk1[d * N + i] - mud) * isg;
       const double dl = S.c1fu * ((double)Fd - (double)Ft) * isg;
@@ -749,6 +749,7 @@ __global__ __launch_bounds__(1024) void k_decide(SysDev S, WinDev W, TileDev Tl,
     S.step[r] = (int64_t)(s0 + (uint64_t)j);
     // the next window decides afresh whether this replica's lists are rebuilt
     rebuild[r] = always_rebuild;
+    if (W.ec_samples) W.ec_samples[r] = min(2, W.ec_samples[r] + j);
   }
 }
 
@@ -782,7 +783,7 @@ __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __res
     const float Fb = W.fd[(size_t)f * 3 * N + d * N + i];
     const float Ft = W.ft[(size_t)f * 3 * N + d * N + i];
     if (refl) {
-      const float Fd = draft_mean_force(W.ec, d * N + i, Fb);
+      const float Fd = draft_mean_force(W, r, d * N + i, f, Fb);
       const double mut = bob_mean(S.a, S.c1fu, pk[d * N + i], Ft);
       const double mud = bob_mean(S.a, S.c1fu, pk[d * N + i], Fd);
       const double z = ((double)pn - mud) * isg;
@@ -793,7 +794,15 @@ __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __res
     q[d * N + i] = qn;
     p[d * N + i] = pn;
     img[d * N + i] += dimg[d];
-    if (W.ec) W.ec[d * N + i] = Ft - Fb;
+    if (W.ec) {
+      // the two last committed errors: frames f-1 and f of this window, or
+      // the previous cache and frame f
+      if (W.ec_prev) {
+        const size_t cp = (size_t)(f - 1) * 3 * N + d * N + i;
+        W.ec_prev[d * N + i] = f >= 1 ? W.ft[cp] - W.fd[cp] : W.ec[d * N + i];
+      }
+      W.ec[d * N + i] = Ft - Fb;
+    }
   }
 }
 

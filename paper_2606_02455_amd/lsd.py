@@ -63,7 +63,7 @@ class WindowLayout(C.Structure):
                 ("f_target", C.c_size_t), ("frame_invalid", C.c_size_t),
                 ("nbr_target", C.c_size_t), ("cnt_target", C.c_size_t),
                 ("nbr_draft", C.c_size_t), ("cnt_draft", C.c_size_t),
-                ("error_cache", C.c_size_t),
+                ("error_cache", C.c_size_t), ("error_cache_prev", C.c_size_t),
                 ("max_neighbors_target", C.c_int32), ("max_neighbors_draft", C.c_int32),
                 ("n_atoms", C.c_int32), ("k_max", C.c_int32)]
 
@@ -201,7 +201,7 @@ class LSDSystem:
         cfg.target = self._potential(tgt)
         cfg.draft = self._potential(dft) if self.mode == MODE_LSD else Potential()
         cfg.max_neighbors_target, cfg.max_neighbors_draft = max_neighbors
-        cfg.error_correction = int(bool(error_correction))
+        cfg.error_correction = int(error_correction)  # 0 off, 1 App. D, 2 linear
         cfg.no_list_reuse = 0 if list_reuse else 1
         self.cfg = cfg
         nbytes = C.c_size_t()
@@ -334,6 +334,8 @@ class LSDSystem:
             f_target=view(L.f_target, K * 3 * N, t.float32, (K, 3, N)),
             frame_invalid=view(L.frame_invalid, self.R * K, t.int32, (self.R, K)),
             error_cache=(view(L.error_cache, 3 * N, t.float32, (3, N)) if L.error_cache else None),
+            error_cache_prev=(view(L.error_cache_prev, 3 * N, t.float32, (3, N))
+                              if L.error_cache_prev else None),
         )
 
     def neighbor_lists(self, which="target"):

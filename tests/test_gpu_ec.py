@@ -37,20 +37,24 @@ def lsd(torch):
     return L
 
 
-def test_ec_run_matches_oracle_on_tethers(torch, lsd, ora):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_ec_run_matches_oracle_on_tethers(torch, lsd, ora, mode):
     # draft stiffness differs from the target's, so the force error changes
     # from step to step and the cache really moves; a large skin keeps every
-    # window at full length, as in the oracle
-    _say("EC run vs oracle (tethers)")
+    # window at full length, as in the oracle.  mode 2: linear extrapolation
+    # of the error from the last two committed steps
+    _say(f"EC run vs oracle (tethers), mode {mode}")
     R, kT_, kD, n_steps, K = 48, 2.0, 1.0, 40, 4
     w = W.tether_replicas(R, k=kT_, dt=0.2, gamma=2.0, kT=1.0, K=K, seed=41)
     anchor = w.positions.copy()
     draft = dict(kind="harmonic", k=kD, anchor=anchor)
-    g = lsd.LSDSystem(w, mode="lsd", draft=draft, skin=50.0, error_correction=True)
+    g = lsd.LSDSystem(w, mode="lsd", draft=draft, skin=50.0, error_correction=mode)
     g.run_to_step(n_steps, K, check_every=4)
     st = g.state()
     cn = g.counters()
     ec_g = g.window()["error_cache"].cpu().numpy().T.astype(np.float64)
+    ecp_g = (g.window()["error_cache_prev"].cpu().numpy().T.astype(np.float64) if mode == 2
+             else None)
     assert (st["step"] == n_steps).all()
     agree, rejections = 0, 0
     for r in range(R):
@@ -60,13 +64,15 @@ def test_ec_run_matches_oracle_on_tethers(torch, lsd, ora):
         q, p = w.positions[r:r + 1].copy(), w.momenta[r:r + 1].copy()
         img = np.zeros((1, 3), np.int32)
         ec = np.zeros((1, 3))
+        ecp = np.zeros((1, 3)) if mode == 2 else None
         s, _, _ = ora.lsd_run(so, T, D, q, p, img, seed=w.seed, replica=r, step0=0,
-                              n_steps=n_steps, K=K, ec=ec)
+                              n_steps=n_steps, K=K, ec=ec, ec_prev=ecp)
         rejections += s["rejections"]
         same = (int(cn[r, 2]) == s["rejections"]
                 and np.max(np.abs(st["q"][r] - q[0])) <= 2e-3
                 and np.max(np.abs(st["p"][r] - p[0])) <= 2e-3
-                and np.max(np.abs(ec_g[r] - ec[0])) <= 1e-2)
+                and np.max(np.abs(ec_g[r] - ec[0])) <= 1e-2
+                and (ecp is None or np.max(np.abs(ecp_g[r] - ecp[0])) <= 1e-2))
         agree += same
     # a decision within rounding of log u may flip one replica's path
     assert agree >= R - 1, (agree, R)
@@ -102,13 +108,14 @@ def test_ec_cancels_a_constant_draft_error(torch, lsd):
     g.destroy()
 
 
-def test_ec_keeps_exact_target_law(torch, lsd):
-    _say("EC harmonic replicas KS")
+@pytest.mark.parametrize("mode", [1, 2])
+def test_ec_keeps_exact_target_law(torch, lsd, mode):
+    _say(f"EC harmonic replicas KS, mode {mode}")
     kT_, kD = 2.0, 1.0
     w = W.tether_replicas(3000, k=kT_, dt=0.2, gamma=2.0, kT=1.0, K=4, seed=37)
     anchor = w.positions.copy()
     draft = dict(kind="harmonic", k=kD, anchor=anchor)
-    g = lsd.LSDSystem(w, mode="lsd", draft=draft, error_correction=True)
+    g = lsd.LSDSystem(w, mode="lsd", draft=draft, error_correction=mode)
     g.run_to_step(60, 4, check_every=8)
     st = g.state()
     assert (st["step"] == 60).all()

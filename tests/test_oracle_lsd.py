@@ -285,3 +285,61 @@ def test_error_correction_keeps_target_marginals(ora):
     var_p = m * kT / (1.0 - (kT_ / m) * dt * dt / 4.0)
     assert stats.kstest(np.ravel(qs) / np.sqrt(kT / kT_), "norm").pvalue > 0.01
     assert stats.kstest(np.ravel(ps) / np.sqrt(var_p), "norm").pvalue > 0.01
+
+
+# --- linear variant of the error correction ---------------------------------
+def _mismatch_run(ora, mode, replicas=4, n_steps=1000):
+    rej = com = 0
+    for r in range(replicas):
+        sysm, T, qref = _tether_system(ora, 4, 20.0, dt=0.05, gamma=0.1, kT=1.0)
+        D = ora.Potential.harmonic(1.0, qref)
+        q, p, img = qref.copy(), np.zeros((4, 3)), np.zeros((4, 3), np.int32)
+        ec = np.zeros((4, 3)) if mode >= 1 else None
+        ecp = np.zeros((4, 3)) if mode == 2 else None
+        st, _, _ = ora.lsd_run(sysm, T, D, q, p, img, seed=5, replica=r, step0=0, n_steps=n_steps,
+                               K=4, ec=ec, ec_prev=ecp)
+        rej += st["rejections"]
+        com += st["committed"]
+    return rej / com
+
+
+def test_linear_error_correction_tracks_a_smoothly_varying_error(ora):
+    # stiff target, soft draft, light friction: the draft error follows the
+    # smooth trajectory, so extrapolating it from the last two committed steps
+    # rejects far less often than holding it constant
+    r0, r1, r2 = (_mismatch_run(ora, m) for m in (0, 1, 2))
+    assert r0 > 0.95
+    assert r2 < 0.75 * r1, (r1, r2)
+
+
+def test_linear_error_correction_cancels_a_constant_error(ora):
+    n = 4
+    sysm, T, qref = _tether_system(ora, n, 1.5, dt=0.05, gamma=1.0, kT=1.0)
+    rng = np.random.default_rng(21)
+    b = rng.normal(size=(n, 3))
+    sig = sysm.sigma()[:, None]
+    c1 = (1 + sysm.a) * sysm.dt / 2
+    b *= 1.2 / np.linalg.norm(c1 * b / sig)
+    D = T.with_offset(b)
+    q, p, img = qref.copy(), np.zeros((n, 3)), np.zeros((n, 3), np.int32)
+    ec, ecp = np.zeros((n, 3)), np.zeros((n, 3))
+    st, _, _ = ora.lsd_run(sysm, T, D, q, p, img, seed=3, replica=0, step0=0, n_steps=2000, K=4,
+                           ec=ec, ec_prev=ecp)
+    assert np.allclose(ec, -b, atol=1e-12) and np.allclose(ecp, -b, atol=1e-12)
+    assert st["rejections"] <= 1
+
+
+def test_linear_error_correction_keeps_target_marginals(ora):
+    kT_, kD, m, dt, kT = 2.0, 1.0, 1.0, 0.2, 1.0
+    qs, ps = [], []
+    for r in range(2000):
+        sysm, T, qref = _tether_system(ora, 1, kT_, m=m, dt=dt, gamma=2.0, kT=kT)
+        D = ora.Potential.harmonic(kD, qref)
+        q, p, img = qref.copy(), np.zeros((1, 3)), np.zeros((1, 3), np.int32)
+        ora.lsd_run(sysm, T, D, q, p, img, seed=79, replica=r, step0=0, n_steps=60, K=4,
+                    ec=np.zeros((1, 3)), ec_prev=np.zeros((1, 3)))
+        qs.append(q[0] - qref[0])
+        ps.append(p[0])
+    var_p = m * kT / (1.0 - (kT_ / m) * dt * dt / 4.0)
+    assert stats.kstest(np.ravel(qs) / np.sqrt(kT / kT_), "norm").pvalue > 0.01
+    assert stats.kstest(np.ravel(ps) / np.sqrt(var_p), "norm").pvalue > 0.01
