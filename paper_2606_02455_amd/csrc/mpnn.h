@@ -27,13 +27,21 @@ struct MpnnWeights {
 };
 
 struct MpnnBuffers {
-  float *S, *DS, *Z, *DZ;  // [slots][384]
-  float* fcd;              // [slots][2]  f_c, f_c'
-  float* uv;               // [slots][4]  unit separation vector
-  float* gr;               // [slots]     dE/dr summed over both directions and layers
+  // per unordered pair (capacity slots / 2 + 1)
+  float *S, *DS, *Z, *DZ;  // [pairs][384]
+  float* fcd;              // [pairs][2]  f_c, f_c'
+  float* uv;               // [pairs][4]  unit vector from the owner row, distance
+  float* gr;               // [pairs]     dE/dr summed over both directions and layers
+  int *ua, *ub;            // [pairs]     owner row, neighbour row
+  // per directed edge (capacity slots = rows x list width)
   int* off;                // [rows+1]    first edge of every (frame, atom) row
   int* erow;               // [slots]     row of an edge's atom
   int* enbr;               // [slots]     row of an edge's neighbour
+  int* ecode;              // [slots]     image code of the edge
+  int* uid;                // [slots]     pair of the edge: p (owner) or ~p (reverse)
+  int* uidx;               // [slots+1]   owner flags, then their exclusive scan
+  float* uvd;              // [slots][4]  unit vector and distance of the edge
+  int* counts;             // [4]         directed edges, pairs, error flag
   float* H;                // [T+1][rows][128]
   float* X;                // [T][rows][128]
   float* U;                // [T][rows][128]

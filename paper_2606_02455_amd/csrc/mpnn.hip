@@ -1,8 +1,12 @@
 // mpnn.hip -- the message-passing target evaluated on a batch of frames.
 //
 // Edges: the in-cutoff entries of every atom's list in every frame, compacted
-// per (frame, atom) row in list order (count, scan, write), so the dense
-// filter contractions run over the pairs that contribute and nothing else.
+// per (frame, atom) row in list order (count, scan, write).  The filters
+// depend only on the distance, so they (and dE/dr) are evaluated once per
+// unordered pair: the directed edge from the lower row (or, for an atom and
+// its own image, the one with the positive image code) owns the pair, and the
+// reverse edge refers to it.  The dense filter contractions thus run over
+// the pairs that contribute, once each.
 // Forward (per layer t): filters W_t(r) = f_c(r) (A2 silu(A1 e(r) + a1) + a2)
 // for every edge, X_t = B_t h, m = sum over edges W_t (.) X_t[neighbour],
 // h += C2 silu(C1 m + c1) + c2; readout E = s_E sum (w2 . silu(W1 h + b1) + b2).
@@ -88,8 +92,8 @@ __global__ __launch_bounds__(1024) void k_mp_scan(MpnnBuffers b, long rows) {
   if (t == 1023) b.off[rows] = (int)s[1023];
 }
 
-// edge records of every row in list order: source row, neighbour row,
-// f_c, f_c', unit vector and distance
+// directed edge records of every row in list order: row, neighbour row,
+// image code, unit vector and distance; flag 1 for the pair's owner
 __global__ __launch_bounds__(256) void k_mp_edges(MpnnBuffers b, SysDev S, ListDev L, WinDev W,
                                                   int f0, long rows, float rc) {
   const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -97,21 +101,84 @@ __global__ __launch_bounds__(256) void k_mp_edges(MpnnBuffers b, SysDev S, ListD
   const int fl = (int)(row / S.n), i = (int)(row - (long)fl * S.n);
   const int cnt = L.cnt_t[i];
   long e = b.off[row];
-  const float a = 3.14159265358979f / rc;
   for (int m = 0; m < cnt; ++m) {
     int j;
     float d[3], r;
     if (!edge_geometry(S, L, W, f0, fl, i, m, rc, &j, d, &r)) continue;
+    const int code = (int)(L.nbr_t[(size_t)i * L.mt + m] & 31u);
     b.erow[e] = (int)row;
     b.enbr[e] = (int)((long)fl * S.n + j);
-    b.fcd[2 * e] = 0.5f * (cosf(a * r) + 1.0f);
-    b.fcd[2 * e + 1] = -0.5f * a * sinf(a * r);
-    b.uv[4 * e] = d[0] / r;
-    b.uv[4 * e + 1] = d[1] / r;
-    b.uv[4 * e + 2] = d[2] / r;
-    b.uv[4 * e + 3] = r;
+    b.ecode[e] = code;
+    b.uidx[e] = (i < j || (i == j && code > 13)) ? 1 : 0;
+    b.uvd[4 * e] = d[0] / r;
+    b.uvd[4 * e + 1] = d[1] / r;
+    b.uvd[4 * e + 2] = d[2] / r;
+    b.uvd[4 * e + 3] = r;
     ++e;
   }
+}
+
+// exclusive scan of the owner flags (one block): pair index of every owner;
+// counts = {directed edges, pairs}
+__global__ __launch_bounds__(1024) void k_mp_scan_pairs(MpnnBuffers b, long rows) {
+  __shared__ long s[1024];
+  const int t = threadIdx.x;
+  const long E = b.off[rows];
+  const long chunk = (E + 1023) / 1024;
+  const long lo = min(E, (long)t * chunk), hi = min(E, lo + chunk);
+  long sum = 0;
+  for (long e = lo; e < hi; ++e) sum += b.uidx[e];
+  s[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const long v = t >= o ? s[t - o] : 0;
+    __syncthreads();
+    s[t] += v;
+    __syncthreads();
+  }
+  long run = s[t] - sum;
+  for (long e = lo; e < hi; ++e) {
+    const long c = b.uidx[e];
+    b.uidx[e] = (int)run;
+    run += c;
+  }
+  if (t == 1023) {
+    b.uidx[E] = (int)s[1023];
+    b.counts[0] = (int)E;
+    b.counts[1] = (int)s[1023];
+    b.counts[2] = 0;  // set by k_mp_pairs if a reverse edge has no owner
+  }
+}
+
+// pair records (owner's rows, f_c, f_c', unit vector and distance) and, for
+// every directed edge, its pair: uid = p for the owner, ~p for the reverse
+__global__ __launch_bounds__(256) void k_mp_pairs(MpnnBuffers b, long rows, long cap, float rc) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cap || e >= b.off[rows]) return;
+  const int p0 = b.uidx[e];
+  if (b.uidx[e + 1] != p0) {  // owner
+    const float r = b.uvd[4 * e + 3];
+    const float a = 3.14159265358979f / rc;
+    b.ua[p0] = b.erow[e];
+    b.ub[p0] = b.enbr[e];
+    b.fcd[2 * p0] = 0.5f * (cosf(a * r) + 1.0f);
+    b.fcd[2 * p0 + 1] = -0.5f * a * sinf(a * r);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b.uv[4 * p0 + q] = b.uvd[4 * e + q];
+    b.uid[e] = p0;
+    return;
+  }
+  // reverse edge: the owner is the neighbour row's edge back to this row with
+  // the opposite image
+  const int rj = b.enbr[e], ri = b.erow[e], back = 26 - b.ecode[e];
+  int found = -1;
+  for (int q = b.off[rj]; q < b.off[rj + 1]; ++q)
+    if (b.enbr[q] == ri && b.ecode[q] == back) { found = b.uidx[q]; break; }
+  if (found < 0) {
+    b.counts[2] = 1;  // the edge sets of the two directions differ (not expected)
+    found = 0;
+  }
+  b.uid[e] = ~found;
 }
 
 // Radial basis and the first filter layer of all three layers per edge:
@@ -162,18 +229,11 @@ __global__ __launch_bounds__(128) void k_mp_radial(MpnnWeights w, MpnnBuffers b,
   }
 }
 
-// After Z = S A2^T and DZ = DS A2^T: W = f_c (Z + a2) into Z and
-// dW/dr = f_c' (Z + a2) + f_c DZ into DZ.
-__global__ __launch_bounds__(256) void k_mp_filter(MpnnWeights w, MpnnBuffers b, long edges) {
-  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= edges * MP_HT) return;
-  const long e = id / MP_HT;
-  const int col = (int)(id - e * MP_HT);
-  const int t = col / MP_H, c = col % MP_H;
-  const float fc = b.fcd[2 * e], dfc = b.fcd[2 * e + 1];
-  const float zz = b.Z[id] + w.a2[t][c];
-  b.DZ[id] = dfc * zz + fc * b.DZ[id];
-  b.Z[id] = fc * zz;
+// Filters from the GEMM outputs of a pair (Z = S A2^T, DZ = DS A2^T):
+// W = f_c (Z + a2) and dW/dr = f_c' (Z + a2) + f_c DZ, formed where used.
+__device__ __forceinline__ float filter_w(const MpnnWeights& w, const MpnnBuffers& b, long p, int t,
+                                          int c) {
+  return b.fcd[2 * p] * (b.Z[p * MP_HT + t * MP_H + c] + w.a2[t][c]);
 }
 
 __global__ __launch_bounds__(128) void k_mp_embed(MpnnWeights w, MpnnBuffers b, SysDev S, long rows) {
@@ -184,17 +244,21 @@ __global__ __launch_bounds__(128) void k_mp_embed(MpnnWeights w, MpnnBuffers b, 
   b.H[row * MP_H + threadIdx.x] = w.W_emb[sp * MP_H + threadIdx.x];
 }
 
-// out[row][c] = sum over the row's edges e of Wt[e][c] * V[neighbour row][c]
+// out[row][c] = sum over the row's edges e of W_t[pair(e)][c] * V[neighbour row][c]
 // (messages with V = X_t; dE/dX with V = gM: W is symmetric in the pair)
-__global__ __launch_bounds__(128) void k_mp_gather(MpnnBuffers b, int t, const float* __restrict__ V,
+__global__ __launch_bounds__(128) void k_mp_gather(MpnnWeights w, MpnnBuffers b, int t,
+                                                   const float* __restrict__ V,
                                                    float* __restrict__ out, long rows) {
   const long row = blockIdx.x;
   if (row >= rows) return;
   const int c = threadIdx.x;
   const int e1 = b.off[row + 1];
   float acc = 0.f;
-  for (int e = b.off[row]; e < e1; ++e)
-    acc = fmaf(b.Z[(long)e * MP_HT + t * MP_H + c], V[(long)b.enbr[e] * MP_H + c], acc);
+  for (int e = b.off[row]; e < e1; ++e) {
+    const int u = b.uid[e];
+    const long p = u >= 0 ? u : ~u;
+    acc = fmaf(filter_w(w, b, p, t, c), V[(long)b.enbr[e] * MP_H + c], acc);
+  }
   out[row * MP_H + c] = acc;
 }
 
@@ -244,25 +308,28 @@ __global__ __launch_bounds__(256) void k_mp_mul_dsilu(const float* __restrict__ 
   g[id] *= dsiluf(U[id]);
 }
 
-// dE/dr of one edge, both directions of the pair, layer t:
-// sum_c (gM[a] X[b] + gM[b] X[a])_c dW_c/dr.  One wave per edge.
-__global__ __launch_bounds__(256) void k_mp_dedr(MpnnBuffers b, int t, const float* __restrict__ X,
-                                                 long edges) {
-  const long e = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+// dE/dr of one pair (both directions), layer t:
+// sum_c (gM[a] X[b] + gM[b] X[a])_c dW_c/dr.  One wave per pair.
+__global__ __launch_bounds__(256) void k_mp_dedr(MpnnWeights w, MpnnBuffers b, int t,
+                                                 const float* __restrict__ X, long pairs) {
+  const long p = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (e >= edges) return;  // uniform per wave
-  const long ra = (long)b.erow[e] * MP_H, rb = (long)b.enbr[e] * MP_H;
-  const float* dW = b.DZ + e * MP_HT + t * MP_H;
+  if (p >= pairs) return;  // uniform per wave
+  const long ra = (long)b.ua[p] * MP_H, rb = (long)b.ub[p] * MP_H;
+  const float fc = b.fcd[2 * p], dfc = b.fcd[2 * p + 1];
+  const float* Z = b.Z + p * MP_HT + t * MP_H;
+  const float* DZ = b.DZ + p * MP_HT + t * MP_H;
   float acc = 0.f;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int c = lane + 64 * h;
     const float g = b.gM[ra + c] * X[rb + c] + b.gM[rb + c] * X[ra + c];
-    acc = fmaf(g, dW[c], acc);
+    const float dW = dfc * (Z[c] + w.a2[t][c]) + fc * DZ[c];
+    acc = fmaf(g, dW, acc);
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (lane == 0) b.gr[e] += acc;
+  if (lane == 0) b.gr[p] += acc;
 }
 
 // F_a = sum over a's edges of dE/dr (q_b - q_a)/r, frame-major [f][3][N]
@@ -276,10 +343,14 @@ __global__ __launch_bounds__(256) void k_mp_forces(MpnnBuffers b, SysDev S, int 
   float fx = 0.f, fy = 0.f, fz = 0.f;
   const int e1 = b.off[row + 1];
   for (int e = b.off[row]; e < e1; ++e) {
-    const float g = b.gr[e];
-    fx = fmaf(g, b.uv[4 * e], fx);
-    fy = fmaf(g, b.uv[4 * e + 1], fy);
-    fz = fmaf(g, b.uv[4 * e + 2], fz);
+    // the pair's unit vector points from its owner row; the reverse edge
+    // sees it negated
+    const int u = b.uid[e];
+    const long p = u >= 0 ? u : ~u;
+    const float g = u >= 0 ? b.gr[p] : -b.gr[p];
+    fx = fmaf(g, b.uv[4 * p], fx);
+    fy = fmaf(g, b.uv[4 * p + 1], fy);
+    fz = fmaf(g, b.uv[4 * p + 2], fz);
   }
   float* F = Fout + (size_t)(f0 + fl) * 3 * N;
   F[i] = fx;
@@ -314,12 +385,14 @@ rocblas_status gemm_rm(rocblas_handle h, const float* A, const float* B, float* 
 
 }  // namespace
 
+// capacities: directed edges <= rows x list width; pairs = half of them
 size_t mpnn_buffer_bytes(int frames, int n, int mt) {
-  const size_t rows = (size_t)frames * n, slots = rows * mt;
+  const size_t rows = (size_t)frames * n, slots = rows * mt, pairs = slots / 2 + 1;
   size_t b = 0;
-  b += 4 * al(slots * MP_HT * 4);            // S, DS, Z, DZ
-  b += al(slots * 2 * 4) + al(slots * 4 * 4) + al(slots * 4);
-  b += al((rows + 1) * 4) + 2 * al(slots * 4);   // row offsets, edge rows
+  b += 4 * al(pairs * MP_HT * 4);            // S, DS, Z, DZ
+  b += al(pairs * 2 * 4) + al(pairs * 4 * 4) + al(pairs * 4) + 2 * al(pairs * 4);
+  b += al((rows + 1) * 4) + 4 * al(slots * 4) + al((slots + 1) * 4) + al(slots * 4 * 4);
+  b += al(4 * 4);
   b += al((MP_T + 1) * rows * MP_H * 4) + 2 * al(MP_T * rows * MP_H * 4);
   b += 2 * al(rows * MP_H * 4) + 2 * al(rows * MP_RH * 4) + 5 * al(rows * MP_H * 4);
   return b;
@@ -327,7 +400,7 @@ size_t mpnn_buffer_bytes(int frames, int n, int mt) {
 
 void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* weights,
                int n_model_species) {
-  const size_t rows = (size_t)frames * n, slots = rows * mt;
+  const size_t rows = (size_t)frames * n, slots = rows * mt, pairs = slots / 2 + 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     float* p = reinterpret_cast<float*>(base + off);
@@ -335,16 +408,23 @@ void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* w
     return p;
   };
   MpnnBuffers& b = M.b;
-  b.S = take(slots * MP_HT * 4);
-  b.DS = take(slots * MP_HT * 4);
-  b.Z = take(slots * MP_HT * 4);
-  b.DZ = take(slots * MP_HT * 4);
-  b.fcd = take(slots * 2 * 4);
-  b.uv = take(slots * 4 * 4);
-  b.gr = take(slots * 4);
+  b.S = take(pairs * MP_HT * 4);
+  b.DS = take(pairs * MP_HT * 4);
+  b.Z = take(pairs * MP_HT * 4);
+  b.DZ = take(pairs * MP_HT * 4);
+  b.fcd = take(pairs * 2 * 4);
+  b.uv = take(pairs * 4 * 4);
+  b.gr = take(pairs * 4);
+  b.ua = reinterpret_cast<int*>(take(pairs * 4));
+  b.ub = reinterpret_cast<int*>(take(pairs * 4));
   b.off = reinterpret_cast<int*>(take((rows + 1) * 4));
   b.erow = reinterpret_cast<int*>(take(slots * 4));
   b.enbr = reinterpret_cast<int*>(take(slots * 4));
+  b.ecode = reinterpret_cast<int*>(take(slots * 4));
+  b.uid = reinterpret_cast<int*>(take(slots * 4));
+  b.uidx = reinterpret_cast<int*>(take((slots + 1) * 4));
+  b.uvd = take(slots * 4 * 4);
+  b.counts = reinterpret_cast<int*>(take(4 * 4));
   b.H = take((MP_T + 1) * rows * MP_H * 4);
   b.X = take(MP_T * rows * MP_H * 4);
   b.U = take(MP_T * rows * MP_H * 4);
@@ -405,20 +485,30 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
   const long N = S.n, mt = L.mt;
   const long rows = (long)nf * N;
   MP_BLAS(rocblas_set_stream(M.blas, st));
-  // compact the in-cutoff pairs of every row into edges (list order)
+  // compact the in-cutoff pairs of every row into edges (list order), then
+  // into unordered pairs
   hipLaunchKernelGGL(k_mp_count, dim3(nblk(rows, 256)), dim3(256), 0, st, b, S, L, W, f0, rows, M.rc);
   MP_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_mp_scan, dim3(1), dim3(1024), 0, st, b, rows);
   MP_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_mp_edges, dim3(nblk(rows, 256)), dim3(256), 0, st, b, S, L, W, f0, rows, M.rc);
   MP_HIP(hipGetLastError());
-  // the edge count sizes the contractions below
-  int total = 0;
-  MP_HIP(hipMemcpyAsync(&total, b.off + rows, sizeof(int), hipMemcpyDeviceToHost, st));
+  hipLaunchKernelGGL(k_mp_scan_pairs, dim3(1), dim3(1024), 0, st, b, rows);
+  MP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_mp_pairs, dim3(nblk(rows * mt, 256)), dim3(256), 0, st, b, rows, rows * mt,
+                     M.rc);
+  MP_HIP(hipGetLastError());
+  // the pair count sizes the contractions below
+  int counts[3] = {0, 0, 0};
+  MP_HIP(hipMemcpyAsync(counts, b.counts, sizeof(counts), hipMemcpyDeviceToHost, st));
   MP_HIP(hipStreamSynchronize(st));
-  const long slots = total;
-  if (slots > rows * mt) {
-    snprintf(err, errlen, "edge count %ld exceeds capacity %ld", slots, rows * mt);
+  if (counts[2]) {
+    snprintf(err, errlen, "edge lists of the two directions of a pair differ");
+    return false;
+  }
+  const long slots = counts[1];  // unordered pairs
+  if (slots > rows * mt / 2 + 1) {
+    snprintf(err, errlen, "pair count %ld exceeds capacity %ld", slots, rows * mt / 2 + 1);
     return false;
   }
   if (slots > 0) {
@@ -437,8 +527,6 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
                                         rocblas_operation_none, MP_H, (int)slots, MP_H, &one,
                                         w.A2[0], MP_H, w.layer_stride, b.DS, MP_HT, MP_H, &zero,
                                         b.DZ, MP_HT, MP_H, MP_T));
-  hipLaunchKernelGGL(k_mp_filter, dim3(nblk(slots * MP_HT, 256)), dim3(256), 0, st, w, b, slots);
-  MP_HIP(hipGetLastError());
   }
   // forward through the layers
   hipLaunchKernelGGL(k_mp_embed, dim3((unsigned)rows), dim3(MP_H), 0, st, w, b, S, rows);
@@ -450,7 +538,8 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
     float* Xt = b.X + t * rh;
     float* Ut = b.U + t * rh;
     MP_BLAS(gemm_rm(M.blas, Ht, w.B[t], Xt, (int)rows, MP_H, MP_H, true, 0.f, MP_H, MP_H));
-    hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, t, Xt, b.Mm, rows);
+    hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, w, b, t, Xt, b.Mm,
+                       rows);
     MP_HIP(hipGetLastError());
     MP_BLAS(gemm_rm(M.blas, b.Mm, w.C1[t], Ut, (int)rows, MP_H, MP_H, true, 0.f, MP_H, MP_H));
     hipLaunchKernelGGL(k_mp_act, dim3(nblk(rh, 256)), dim3(256), 0, st, w.c1[t], Ut, b.Sn, rh);
@@ -479,11 +568,11 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
     MP_HIP(hipGetLastError());
     MP_BLAS(gemm_rm(M.blas, b.gS, w.C1[t], b.gM, (int)rows, MP_H, MP_H, false, 0.f, MP_H, MP_H));
     if (slots > 0) {
-      hipLaunchKernelGGL(k_mp_dedr, dim3(nblk(slots, 4)), dim3(256), 0, st, b, t, Xt, slots);
+      hipLaunchKernelGGL(k_mp_dedr, dim3(nblk(slots, 4)), dim3(256), 0, st, w, b, t, Xt, slots);
       MP_HIP(hipGetLastError());
     }
     if (t > 0) {
-      hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, t, b.gM, b.gX,
+      hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, w, b, t, b.gM, b.gX,
                          rows);
       MP_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_mp_copy, dim3(nblk(rh, 256)), dim3(256), 0, st, b.gH, b.gP, rh);
