@@ -39,8 +39,7 @@ struct MpnnBuffers {
   int* enbr;               // [slots]     row of an edge's neighbour
   int* ecode;              // [slots]     image code of the edge
   int* uid;                // [slots]     pair of the edge: p (owner) or ~p (reverse)
-  int* uidx;               // [slots+1]   owner flags, then their exclusive scan
-  float* uvd;              // [slots][4]  unit vector and distance of the edge
+  int* poff;               // [rows+1]    first pair owned by every row
   int* counts;             // [4]         directed edges, pairs, error flag
   float* H;                // [T+1][rows][128]
   float* X;                // [T][rows][128]

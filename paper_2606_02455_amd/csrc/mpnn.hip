@@ -51,129 +51,147 @@ __device__ __forceinline__ bool edge_geometry(const SysDev& S, const ListDev& L,
   return r < rc && r > 0.f;
 }
 
-// in-cutoff entries per (frame, atom) row
-__global__ __launch_bounds__(256) void k_mp_count(MpnnBuffers b, SysDev S, ListDev L, WinDev W,
-                                                  int f0, long rows, float rc) {
-  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= rows) return;
+// Per (frame, atom) row, one block of kRowThreads threads over the list
+// entries (entry m handled by thread m % kRowThreads in pass m / kRowThreads):
+// in-cutoff flags and, from ballots, each entry's rank among the row's
+// in-cutoff entries and owner entries (list order).
+constexpr int kRowThreads = 128;
+
+struct RowScan {
+  int edges, owners;  // totals of the row
+};
+
+template <bool WRITE>
+__device__ __forceinline__ RowScan row_pass(MpnnBuffers& b, const SysDev& S, const ListDev& L,
+                                            const WinDev& W, int f0, long row, float rc) {
+  __shared__ int s_e[kRowThreads / 64], s_o[kRowThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int fl = (int)(row / S.n), i = (int)(row - (long)fl * S.n);
   const int cnt = L.cnt_t[i];
-  int n = 0;
-  for (int m = 0; m < cnt; ++m) {
-    int j;
-    float d[3], r;
-    n += edge_geometry(S, L, W, f0, fl, i, m, rc, &j, d, &r) ? 1 : 0;
+  int base_e = WRITE ? b.off[row] : 0, base_o = WRITE ? b.poff[row] : 0;
+  int tot_e = 0, tot_o = 0;
+  for (int m0 = 0; m0 < cnt; m0 += kRowThreads) {
+    const int m = m0 + t;
+    int j = 0, code = 0;
+    float d[3] = {0.f, 0.f, 0.f}, r = 0.f;
+    bool in = false, own = false;
+    if (m < cnt) {
+      in = edge_geometry(S, L, W, f0, fl, i, m, rc, &j, d, &r);
+      code = (int)(L.nbr_t[(size_t)i * L.mt + m] & 31u);
+      own = in && (i < j || (i == j && code > 13));
+    }
+    const unsigned long long be = __ballot(in), bo = __ballot(own);
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0) {
+      s_e[wave] = __popcll(be);
+      s_o[wave] = __popcll(bo);
+    }
+    __syncthreads();
+    int pe = 0, po = 0;
+    for (int q = 0; q < wave; ++q) {
+      pe += s_e[q];
+      po += s_o[q];
+    }
+    int ce = 0, co = 0;
+    for (int q = 0; q < kRowThreads / 64; ++q) {
+      ce += s_e[q];
+      co += s_o[q];
+    }
+    if (WRITE && in) {
+      const long e = base_e + tot_e + pe + __popcll(be & below);
+      b.erow[e] = (int)row;
+      b.enbr[e] = (int)((long)fl * S.n + j);
+      b.ecode[e] = code;
+      if (own) {
+        const int pp = base_o + tot_o + po + __popcll(bo & below);
+        const float a = 3.14159265358979f / rc;
+        b.uid[e] = pp;
+        b.ua[pp] = (int)row;
+        b.ub[pp] = (int)((long)fl * S.n + j);
+        b.fcd[2 * pp] = 0.5f * (cosf(a * r) + 1.0f);
+        b.fcd[2 * pp + 1] = -0.5f * a * sinf(a * r);
+        b.uv[4 * pp] = d[0] / r;
+        b.uv[4 * pp + 1] = d[1] / r;
+        b.uv[4 * pp + 2] = d[2] / r;
+        b.uv[4 * pp + 3] = r;
+      } else {
+        b.uid[e] = -1;  // reverse edge: resolved by k_mp_reverse
+      }
+    }
+    tot_e += ce;
+    tot_o += co;
+    __syncthreads();
   }
-  b.off[row] = n;
+  return RowScan{tot_e, tot_o};
 }
 
-// exclusive scan of the row counts in place (one block); off[rows] = total
+// in-cutoff entries and owned pairs per row
+__global__ __launch_bounds__(kRowThreads) void k_mp_count(MpnnBuffers b, SysDev S, ListDev L,
+                                                          WinDev W, int f0, float rc) {
+  const long row = blockIdx.x;
+  const RowScan c = row_pass<false>(b, S, L, W, f0, row, rc);
+  if (threadIdx.x == 0) {
+    b.off[row] = c.edges;
+    b.poff[row] = c.owners;
+  }
+}
+
+// exclusive scans of the row counts of edges and pairs in place (one block);
+// off[rows], poff[rows] = totals, also copied to counts[0..1]
 __global__ __launch_bounds__(1024) void k_mp_scan(MpnnBuffers b, long rows) {
-  __shared__ long s[1024];
+  __shared__ long s[1024], s2[1024];
   const int t = threadIdx.x;
   const long chunk = (rows + 1023) / 1024;
   const long lo = min(rows, (long)t * chunk), hi = min(rows, lo + chunk);
-  long sum = 0;
-  for (long r = lo; r < hi; ++r) sum += b.off[r];
-  s[t] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const long v = t >= o ? s[t - o] : 0;
-    __syncthreads();
-    s[t] += v;
-    __syncthreads();
-  }
-  long run = s[t] - sum;
+  long sum = 0, sum2 = 0;
   for (long r = lo; r < hi; ++r) {
-    const long c = b.off[r];
-    b.off[r] = (int)run;
-    run += c;
+    sum += b.off[r];
+    sum2 += b.poff[r];
   }
-  if (t == 1023) b.off[rows] = (int)s[1023];
-}
-
-// directed edge records of every row in list order: row, neighbour row,
-// image code, unit vector and distance; flag 1 for the pair's owner
-__global__ __launch_bounds__(256) void k_mp_edges(MpnnBuffers b, SysDev S, ListDev L, WinDev W,
-                                                  int f0, long rows, float rc) {
-  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= rows) return;
-  const int fl = (int)(row / S.n), i = (int)(row - (long)fl * S.n);
-  const int cnt = L.cnt_t[i];
-  long e = b.off[row];
-  for (int m = 0; m < cnt; ++m) {
-    int j;
-    float d[3], r;
-    if (!edge_geometry(S, L, W, f0, fl, i, m, rc, &j, d, &r)) continue;
-    const int code = (int)(L.nbr_t[(size_t)i * L.mt + m] & 31u);
-    b.erow[e] = (int)row;
-    b.enbr[e] = (int)((long)fl * S.n + j);
-    b.ecode[e] = code;
-    b.uidx[e] = (i < j || (i == j && code > 13)) ? 1 : 0;
-    b.uvd[4 * e] = d[0] / r;
-    b.uvd[4 * e + 1] = d[1] / r;
-    b.uvd[4 * e + 2] = d[2] / r;
-    b.uvd[4 * e + 3] = r;
-    ++e;
-  }
-}
-
-// exclusive scan of the owner flags (one block): pair index of every owner;
-// counts = {directed edges, pairs}
-__global__ __launch_bounds__(1024) void k_mp_scan_pairs(MpnnBuffers b, long rows) {
-  __shared__ long s[1024];
-  const int t = threadIdx.x;
-  const long E = b.off[rows];
-  const long chunk = (E + 1023) / 1024;
-  const long lo = min(E, (long)t * chunk), hi = min(E, lo + chunk);
-  long sum = 0;
-  for (long e = lo; e < hi; ++e) sum += b.uidx[e];
   s[t] = sum;
+  s2[t] = sum2;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
-    const long v = t >= o ? s[t - o] : 0;
+    const long v = t >= o ? s[t - o] : 0, v2 = t >= o ? s2[t - o] : 0;
     __syncthreads();
     s[t] += v;
+    s2[t] += v2;
     __syncthreads();
   }
-  long run = s[t] - sum;
-  for (long e = lo; e < hi; ++e) {
-    const long c = b.uidx[e];
-    b.uidx[e] = (int)run;
+  long run = s[t] - sum, run2 = s2[t] - sum2;
+  for (long r = lo; r < hi; ++r) {
+    const long c = b.off[r], c2 = b.poff[r];
+    b.off[r] = (int)run;
+    b.poff[r] = (int)run2;
     run += c;
+    run2 += c2;
   }
   if (t == 1023) {
-    b.uidx[E] = (int)s[1023];
-    b.counts[0] = (int)E;
-    b.counts[1] = (int)s[1023];
-    b.counts[2] = 0;  // set by k_mp_pairs if a reverse edge has no owner
+    b.off[rows] = (int)s[1023];
+    b.poff[rows] = (int)s2[1023];
+    b.counts[0] = (int)s[1023];
+    b.counts[1] = (int)s2[1023];
+    b.counts[2] = 0;  // set by k_mp_reverse if a reverse edge has no owner
   }
 }
 
-// pair records (owner's rows, f_c, f_c', unit vector and distance) and, for
-// every directed edge, its pair: uid = p for the owner, ~p for the reverse
-__global__ __launch_bounds__(256) void k_mp_pairs(MpnnBuffers b, long rows, long cap, float rc) {
+// directed edge records of every row in list order, and the pair records of
+// the edges the row owns
+__global__ __launch_bounds__(kRowThreads) void k_mp_edges(MpnnBuffers b, SysDev S, ListDev L,
+                                                          WinDev W, int f0, float rc) {
+  row_pass<true>(b, S, L, W, f0, blockIdx.x, rc);
+}
+
+// every reverse edge refers to its owner: the neighbour row's edge back to
+// this row with the opposite image; uid = ~pair
+__global__ __launch_bounds__(256) void k_mp_reverse(MpnnBuffers b, long rows, long cap) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= cap || e >= b.off[rows]) return;
-  const int p0 = b.uidx[e];
-  if (b.uidx[e + 1] != p0) {  // owner
-    const float r = b.uvd[4 * e + 3];
-    const float a = 3.14159265358979f / rc;
-    b.ua[p0] = b.erow[e];
-    b.ub[p0] = b.enbr[e];
-    b.fcd[2 * p0] = 0.5f * (cosf(a * r) + 1.0f);
-    b.fcd[2 * p0 + 1] = -0.5f * a * sinf(a * r);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) b.uv[4 * p0 + q] = b.uvd[4 * e + q];
-    b.uid[e] = p0;
-    return;
-  }
-  // reverse edge: the owner is the neighbour row's edge back to this row with
-  // the opposite image
+  if (b.uid[e] >= 0) return;
   const int rj = b.enbr[e], ri = b.erow[e], back = 26 - b.ecode[e];
   int found = -1;
   for (int q = b.off[rj]; q < b.off[rj + 1]; ++q)
-    if (b.enbr[q] == ri && b.ecode[q] == back) { found = b.uidx[q]; break; }
+    if (b.enbr[q] == ri && b.ecode[q] == back) { found = b.uid[q]; break; }
   if (found < 0) {
     b.counts[2] = 1;  // the edge sets of the two directions differ (not expected)
     found = 0;
@@ -254,7 +272,21 @@ __global__ __launch_bounds__(128) void k_mp_gather(MpnnWeights w, MpnnBuffers b,
   const int c = threadIdx.x;
   const int e1 = b.off[row + 1];
   float acc = 0.f;
-  for (int e = b.off[row]; e < e1; ++e) {
+  int e = b.off[row];
+  // four edges' loads issued together, terms added in edge order
+  for (; e + 4 <= e1; e += 4) {
+    float wv[4], vv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int u = b.uid[e + q];
+      const long p = u >= 0 ? u : ~u;
+      wv[q] = filter_w(w, b, p, t, c);
+      vv[q] = V[(long)b.enbr[e + q] * MP_H + c];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc = fmaf(wv[q], vv[q], acc);
+  }
+  for (; e < e1; ++e) {
     const int u = b.uid[e];
     const long p = u >= 0 ? u : ~u;
     acc = fmaf(filter_w(w, b, p, t, c), V[(long)b.enbr[e] * MP_H + c], acc);
@@ -391,7 +423,7 @@ size_t mpnn_buffer_bytes(int frames, int n, int mt) {
   size_t b = 0;
   b += 4 * al(pairs * MP_HT * 4);            // S, DS, Z, DZ
   b += al(pairs * 2 * 4) + al(pairs * 4 * 4) + al(pairs * 4) + 2 * al(pairs * 4);
-  b += al((rows + 1) * 4) + 4 * al(slots * 4) + al((slots + 1) * 4) + al(slots * 4 * 4);
+  b += 2 * al((rows + 1) * 4) + 4 * al(slots * 4);
   b += al(4 * 4);
   b += al((MP_T + 1) * rows * MP_H * 4) + 2 * al(MP_T * rows * MP_H * 4);
   b += 2 * al(rows * MP_H * 4) + 2 * al(rows * MP_RH * 4) + 5 * al(rows * MP_H * 4);
@@ -418,12 +450,11 @@ void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* w
   b.ua = reinterpret_cast<int*>(take(pairs * 4));
   b.ub = reinterpret_cast<int*>(take(pairs * 4));
   b.off = reinterpret_cast<int*>(take((rows + 1) * 4));
+  b.poff = reinterpret_cast<int*>(take((rows + 1) * 4));
   b.erow = reinterpret_cast<int*>(take(slots * 4));
   b.enbr = reinterpret_cast<int*>(take(slots * 4));
   b.ecode = reinterpret_cast<int*>(take(slots * 4));
   b.uid = reinterpret_cast<int*>(take(slots * 4));
-  b.uidx = reinterpret_cast<int*>(take((slots + 1) * 4));
-  b.uvd = take(slots * 4 * 4);
   b.counts = reinterpret_cast<int*>(take(4 * 4));
   b.H = take((MP_T + 1) * rows * MP_H * 4);
   b.X = take(MP_T * rows * MP_H * 4);
@@ -487,16 +518,15 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
   MP_BLAS(rocblas_set_stream(M.blas, st));
   // compact the in-cutoff pairs of every row into edges (list order), then
   // into unordered pairs
-  hipLaunchKernelGGL(k_mp_count, dim3(nblk(rows, 256)), dim3(256), 0, st, b, S, L, W, f0, rows, M.rc);
+  hipLaunchKernelGGL(k_mp_count, dim3((unsigned)rows), dim3(kRowThreads), 0, st, b, S, L, W, f0,
+                     M.rc);
   MP_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_mp_scan, dim3(1), dim3(1024), 0, st, b, rows);
   MP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_mp_edges, dim3(nblk(rows, 256)), dim3(256), 0, st, b, S, L, W, f0, rows, M.rc);
-  MP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_mp_scan_pairs, dim3(1), dim3(1024), 0, st, b, rows);
-  MP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_mp_pairs, dim3(nblk(rows * mt, 256)), dim3(256), 0, st, b, rows, rows * mt,
+  hipLaunchKernelGGL(k_mp_edges, dim3((unsigned)rows), dim3(kRowThreads), 0, st, b, S, L, W, f0,
                      M.rc);
+  MP_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_mp_reverse, dim3(nblk(rows * mt, 256)), dim3(256), 0, st, b, rows, rows * mt);
   MP_HIP(hipGetLastError());
   // the pair count sizes the contractions below
   int counts[3] = {0, 0, 0};
