@@ -321,8 +321,12 @@ LSD_API lsd_status lsd_rng_uniforms(uint64_t seed, int32_t replica, int64_t step
  * component of the valid frames (0 .. K_eff-1) of the current window at
  * their midpoints q_mid, and y the forces of those frames: f_target
  * (use_target_forces != 0: LSD mode, a verified window) or f_draft (the
- * stepping forces; in PLAIN mode these are the target's).  Pairs are taken
- * within `cutoff` (<= the target cutoff; the target list is used).
+ * stepping forces; in PLAIN mode these are the target's).  differences != 0:
+ * the rows are instead the differences between consecutive valid frames
+ * (rows of frame k+1 minus rows of frame k, forces likewise), which fits the
+ * draft's response to the motion, the part of its error that error
+ * correction (App. D) leaves.  Pairs are taken within `cutoff` (<= the
+ * target cutoff; the target list is used).
  *   gram: device binary64 [(P+1)][(P+1)] row-major, accumulated (+=) in a
  *         fixed order; zero it before the first call.  Column P = A^T y.
  *   scratch: device memory of lsd_fit_pair_scratch_size bytes.
@@ -331,8 +335,8 @@ LSD_API lsd_status lsd_rng_uniforms(uint64_t seed, int32_t replica, int64_t step
 LSD_API lsd_status lsd_fit_pair_scratch_size(const lsd_system *sys, int32_t n_basis,
                                              size_t *bytes);
 LSD_API lsd_status lsd_fit_pair_accumulate(lsd_system *sys, int32_t n_basis, double cutoff,
-                                           int32_t use_target_forces, void *scratch,
-                                           size_t scratch_bytes, double *gram,
+                                           int32_t use_target_forces, int32_t differences,
+                                           void *scratch, size_t scratch_bytes, double *gram,
                                            lsd_stream stream);
 /* Host: weights (host binary64 [P]) minimising |A w - y|^2 + lambda |w|^2
  * from the normal equations `gram` (host copy, layout above), with

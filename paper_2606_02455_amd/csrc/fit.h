@@ -16,8 +16,9 @@ struct FitDev {
 size_t fit_partial_entries(const FitDev& F);
 
 // Adds the normal equations of the window's valid frames (positions q_mid,
-// forces f_target if use_target else f_draft) to gram[(P+1)][(P+1)].
+// forces f_target if use_target else f_draft) to gram[(P+1)][(P+1)]; with
+// diff, of the differences between consecutive valid frames instead.
 // partial: n_tiles * fit_partial_entries doubles of scratch.
 hipError_t launch_fit(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
-                      const FitDev& F, int use_target, double* partial, double* gram,
+                      const FitDev& F, int use_target, int diff, double* partial, double* gram,
                       hipStream_t st);

@@ -17,7 +17,7 @@
 //   h_s[l]      += sum_{atoms a of species s} sum_d A_a[d][l] F_a[d]
 // in binary64.
 __global__ __launch_bounds__(256) void k_fit_tile(SysDev S, ListDev Lst, WinDev W, TileDev Tl,
-                                                  FitDev F, int use_target,
+                                                  FitDev F, int use_target, int diff,
                                                   double* __restrict__ partial) {
   extern __shared__ float s_a[];  // [64][3][LP]
   const int tile = blockIdx.x, t = threadIdx.x;
@@ -32,12 +32,16 @@ __global__ __launch_bounds__(256) void k_fit_tile(SysDev S, ListDev Lst, WinDev 
 #pragma unroll
   for (int q = 0; q < FIT_EPT; ++q) acc[q] = 0.0;
   for (int f = 0; f < W.K; ++f) {
-    if (inv[f]) break;  // frames from K_eff on; uniform over the block
+    // frames from K_eff on are not valid; a difference needs frame f + 1
+    if (inv[f] || (diff && (f + 1 >= W.K || inv[f + 1]))) break;  // uniform over the block
     for (int k = t; k < 64 * 3 * LP; k += 256) s_a[k] = 0.0f;
     __syncthreads();
-    if (t < count) {
+    // rows of frame f, or of frame f + 1 minus those of frame f
+    for (int side = 0; side < (diff ? 2 : 1) && t < count; ++side) {
+      const int fr = diff ? f + 1 - side : f;
+      const float sgn = side ? -1.0f : 1.0f;
       const int i = start + t;
-      const float4* X = W.qmid + (size_t)f * N;
+      const float4* X = W.qmid + (size_t)fr * N;
       const float4 xi = X[i];
       const int cnt = Lst.cnt_t[i];
       const uint32_t* row = Lst.nbr_t + (size_t)i * Lst.mt;
@@ -67,7 +71,7 @@ __global__ __launch_bounds__(256) void k_fit_tile(SysDev S, ListDev Lst, WinDev 
             prev = cur;
             cur = nx;
           }
-          const float v = g0 * cur;
+          const float v = sgn * (g0 * cur);
           a[col0 + b] -= v * dx;
           a[LP + col0 + b] -= v * dy;
           a[2 * LP + col0 + b] -= v * dz;
@@ -75,7 +79,9 @@ __global__ __launch_bounds__(256) void k_fit_tile(SysDev S, ListDev Lst, WinDev 
       }
     }
     __syncthreads();
-    const float* Ff = (use_target ? W.ft : W.fd) + (size_t)f * 3 * N;
+    const float* Fsrc = use_target ? W.ft : W.fd;
+    const float* Ff = Fsrc + (size_t)f * 3 * N;
+    const float* Fn = Fsrc + (size_t)(diff ? f + 1 : f) * 3 * N;
 #pragma unroll
     for (int q = 0; q < FIT_EPT; ++q) {
       const int e = e0 + t + 256 * q;
@@ -96,7 +102,10 @@ __global__ __launch_bounds__(256) void k_fit_tile(SysDev S, ListDev Lst, WinDev 
           if ((S.species ? S.species[i] : 0) != s) continue;
           const float* a = s_a + aa * 3 * LP;
 #pragma unroll
-          for (int d = 0; d < 3; ++d) sum += (double)a[d * LP + l] * (double)Ff[d * N + i];
+          for (int d = 0; d < 3; ++d) {
+            const double y = diff ? (double)Fn[d * N + i] - (double)Ff[d * N + i] : (double)Ff[d * N + i];
+            sum += (double)a[d * LP + l] * y;
+          }
         }
       }
       acc[q] += sum;
@@ -151,7 +160,7 @@ size_t fit_partial_entries(const FitDev& F) {
 }
 
 hipError_t launch_fit(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
-                      const FitDev& F, int use_target, double* partial, double* gram,
+                      const FitDev& F, int use_target, int diff, double* partial, double* gram,
                       hipStream_t st) {
   const int E = (int)fit_partial_entries(F);
   const size_t lds = (size_t)64 * 3 * F.LP * sizeof(float);
@@ -159,7 +168,8 @@ hipError_t launch_fit(const SysDev& S, const ListDev& L, const WinDev& W, const 
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   dim3 grid(S.n_tiles, (E + 256 * FIT_EPT - 1) / (256 * FIT_EPT));
-  hipLaunchKernelGGL(k_fit_tile, grid, dim3(256), lds, st, S, L, W, T, F, use_target, partial);
+  hipLaunchKernelGGL(k_fit_tile, grid, dim3(256), lds, st, S, L, W, T, F, use_target, diff,
+                     partial);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int P = (F.ns * (F.ns + 1) / 2) * F.nb;

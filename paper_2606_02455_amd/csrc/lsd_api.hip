@@ -844,8 +844,8 @@ lsd_status lsd_fit_pair_scratch_size(const lsd_system* s, int32_t n_basis, size_
 }
 
 lsd_status lsd_fit_pair_accumulate(lsd_system* s, int32_t n_basis, double cutoff,
-                                   int32_t use_target_forces, void* scratch, size_t scratch_bytes,
-                                   double* gram, lsd_stream stream) {
+                                   int32_t use_target_forces, int32_t differences, void* scratch,
+                                   size_t scratch_bytes, double* gram, lsd_stream stream) {
   if (!s || !scratch || !gram) return fail(LSD_ERR_INVALID_ARG, "null argument");
   size_t need = 0;
   LSD_TRY(lsd_fit_pair_scratch_size(s, n_basis, &need));
@@ -865,7 +865,7 @@ lsd_status lsd_fit_pair_accumulate(lsd_system* s, int32_t n_basis, double cutoff
   F.nb = n_basis;
   F.ns = s->cfg.n_species;
   F.LP = F.ns * n_basis;
-  HIP_TRY(launch_fit(s->S, s->Lst, s->W, s->T, F, use_target_forces ? 1 : 0,
+  HIP_TRY(launch_fit(s->S, s->Lst, s->W, s->T, F, use_target_forces ? 1 : 0, differences ? 1 : 0,
                      static_cast<double*>(scratch), gram, static_cast<hipStream_t>(stream)));
   return LSD_OK;
 }

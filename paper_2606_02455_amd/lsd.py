@@ -90,8 +90,8 @@ EXPORTS = {
     "lsd_rng_uniforms": ([C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p],
                          C.c_int),
     "lsd_fit_pair_scratch_size": ([C.c_void_p, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
-    "lsd_fit_pair_accumulate": ([C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_void_p,
-                                 C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
+    "lsd_fit_pair_accumulate": ([C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                 C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
     "lsd_fit_pair_solve": ([C.c_void_p, C.c_int32, C.c_double, C.c_void_p], C.c_int),
     "lsd_destroy": ([C.c_void_p], C.c_int),
     "lsd_last_error": ([], C.c_char_p),
@@ -298,10 +298,11 @@ class LSDSystem:
         _check(load().lsd_mark_drafted(self.h, int(K), _stream(self.torch)), "lsd_mark_drafted")
 
     # --- force matching of the pair draft --------------------------------------
-    def fit_pair_accumulate(self, n_basis, cutoff, gram, use_target=False, scratch=None):
-        """Add the normal equations of the current window's valid frames to
-        `gram` (float64 CUDA tensor [P+1, P+1]); returns the scratch tensor
-        (reuse it across calls)."""
+    def fit_pair_accumulate(self, n_basis, cutoff, gram, use_target=False, scratch=None,
+                            differences=False):
+        """Add the normal equations of the current window's valid frames (or
+        of the differences of consecutive frames) to `gram` (float64 CUDA
+        tensor [P+1, P+1]); returns the scratch tensor (reuse it)."""
         t = self.torch
         nb = C.c_size_t()
         _check(load().lsd_fit_pair_scratch_size(self.h, int(n_basis), C.byref(nb)),
@@ -309,7 +310,8 @@ class LSDSystem:
         if scratch is None or scratch.numel() < nb.value:
             scratch = t.empty((max(nb.value, 8),), dtype=t.uint8, device="cuda")
         _check(load().lsd_fit_pair_accumulate(self.h, int(n_basis), float(cutoff),
-                                              1 if use_target else 0, _ptr(scratch),
+                                              1 if use_target else 0, 1 if differences else 0,
+                                              _ptr(scratch),
                                               scratch.numel(), _ptr(gram), _stream(t)),
                "lsd_fit_pair_accumulate")
         return scratch

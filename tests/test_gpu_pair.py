@@ -129,6 +129,20 @@ def test_fit_normal_equations_match_oracle(torch, lsd, ora):
     g.fit_pair_accumulate(NB, RC, gram)
     torch.cuda.synchronize()
     assert np.allclose(gram.cpu().numpy(), 2 * G, rtol=0, atol=1e-12 * scale)
+    # differences of consecutive frames: rows A(k+1) - A(k), forces likewise
+    gd = torch.zeros((P + 1, P + 1), dtype=torch.float64, device="cuda")
+    g.fit_pair_accumulate(NB, RC, gd, differences=True)
+    torch.cuda.synchronize()
+    Ad = [np.concatenate([ref_draft.design(w.species, frames[k + 1], L)
+                          - ref_draft.design(w.species, frames[k], L),
+                          (forces[k + 1].astype(np.float64) - forces[k]).reshape(-1, 1)], 1)
+          for k in range(K - 1)]
+    Gd_ref = sum(a.T @ a for a in Ad)
+    Gd_ref[P, P] = 0.0
+    Gd = gd.cpu().numpy()
+    sd = np.max(np.abs(Gd_ref))
+    # binary32 design rows lose digits in the difference: 1e-4 of the largest entry
+    assert np.max(np.abs(Gd - Gd_ref)) <= 1e-4 * sd, np.max(np.abs(Gd - Gd_ref)) / sd
     g.destroy()
 
 
