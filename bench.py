@@ -67,7 +67,9 @@ def in_cutoff_pairs(sysg, rc):
     cnt, ent = sysg.neighbor_lists("target")
     win = sysg.window()
     x = win["q_mid"][0, :, :3].double()
-    L = float(sysg.w.box[0])
+    import numpy as np
+    per_atom = np.repeat(np.asarray(sysg.w.box, np.float64), np.diff(sysg.w.atom_offsets))
+    L = torch.tensor(per_atom, dtype=torch.float64, device=x.device)[:, None, None]
     m = ent.shape[1]
     ar = torch.arange(m, device=ent.device)[None, :]
     valid = ar < cnt[:, None].to(ar.dtype)
@@ -132,10 +134,11 @@ def mpnn_flops_per_frame(undirected_edges, n_atoms, H=128, R=16, T=3, RH=64):
 
 
 def run_c3(args, lsd, W, torch):
-    """Learned-draft configuration: 1536-atom triatomic liquid, message-passing
-    target, pair draft fitted by force matching on target frames, K = 8."""
+    """Learned-draft configurations: triatomic liquid (c3: 1536 atoms; c4: 256
+    replicas of 24-192 atoms in one system), message-passing target, pair
+    draft fitted by force matching on target frames, K = 8."""
     import numpy as np
-    w = W.config("c3")
+    w = W.config(args.config)
     K, N = w.K, w.n_atoms
     nb, rc_d = args.pair_basis, float(w.draft["rc"])
     target = W.mpnn_target()
@@ -180,7 +183,9 @@ def run_c3(args, lsd, W, torch):
     torch.cuda.synchronize()
     t_lsd = time.perf_counter() - t0
     ver_ms, ver_n = g.verify_timing()
-    windows, committed, rejections, frames, builds = (int(v) for v in g.counters()[0])
+    cn = g.counters()
+    windows = int(cn[0, 0])
+    committed, rejections, frames = (int(cn[:, c].sum()) for c in (1, 2, 3))
     log(f"LSD: {committed} steps in {t_lsd * 1e3:.1f} ms over {windows} windows; rejections "
         f"{rejections}; verify {ver_ms / max(ver_n, 1) * 1e3:.1f} us/launch")
     plain.run_windows(args.warmup, K)
@@ -190,13 +195,14 @@ def run_c3(args, lsd, W, torch):
     plain.run_windows(args.steps, K)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    plain_steps = int(plain.counters()[0][1])
+    plain_steps = int(plain.counters()[:, 1].sum())
     log(f"plain: {plain_steps} steps in {t_plain * 1e3:.1f} ms")
     status = g.status() | plain.status()
     if status:
         raise RuntimeError(f"device status {status}: neighbour capacity overflow")
     pairs = in_cutoff_pairs(g, float(target["rc"]))
-    frames_per_launch = frames / max(ver_n, 1)
+    # replica-frames per launch, as whole-system frames
+    frames_per_launch = frames / max(ver_n, 1) / w.n_replicas
     flops = mpnn_flops_per_frame(pairs / 2.0, N) * frames_per_launch
     avg_s = ver_ms / max(ver_n, 1) * 1e-3
     achieved = flops / avg_s / 1e12
@@ -210,7 +216,7 @@ def run_c3(args, lsd, W, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"{w.name}: triatomic liquid, {N} atoms (512 molecules), 300 K, "
+            "workload": (f"{w.name}: triatomic liquid, {N} atoms in {w.n_replicas} system(s), 300 K, "
                          f"dt {dt_fs} fs, gamma {w.gamma}/fs, K={K}; target: seeded "
                          f"message-passing network (3 layers, hidden 128, 16 Bessel, rc 5 A); "
                          f"draft: pair forces (rc {rc_d} A, {nb} basis) force-matched "
@@ -240,7 +246,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed windows")
     ap.add_argument("--warmup", type=int, default=20, help="untimed windows")
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--fit-frames", type=int, default=20000,
                     help="c3: target frames for force matching of the pair draft")
     ap.add_argument("--pair-basis", type=int, default=16, help="c3: pair-draft basis size")
@@ -253,7 +259,7 @@ def main():
                          "measured setting of the configuration (c1, c2: on; c3: linear)")
     args = ap.parse_args()
     if args.ec == "auto":
-        args.ec = "linear" if args.config == "c3" else "on"
+        args.ec = "linear" if args.config in ("c3", "c4") else "on"
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only: the batched verification path runs the K frames "
@@ -269,7 +275,7 @@ def main():
 
     lsd.load()
     torch.cuda.set_device(0)
-    if args.config == "c3":
+    if args.config in ("c3", "c4"):
         print(json.dumps(run_c3(args, lsd, W, torch)), flush=True)
         return
     w = W.config(args.config)

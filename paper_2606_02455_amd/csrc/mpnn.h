@@ -27,7 +27,7 @@ struct MpnnWeights {
 };
 
 struct MpnnBuffers {
-  // per unordered pair (capacity slots / 2 + 1)
+  // per unordered pair (capacity slots / 4 + 1)
   float *S, *DS, *Z, *DZ;  // [pairs][384]
   float* fcd;              // [pairs][2]  f_c, f_c'
   float* uv;               // [pairs][4]  unit vector from the owner row, distance

@@ -417,9 +417,13 @@ rocblas_status gemm_rm(rocblas_handle h, const float* A, const float* B, float* 
 
 }  // namespace
 
-// capacities: directed edges <= rows x list width; pairs = half of them
+// capacities: directed edges <= rows x list width; pairs <= a quarter of
+// that (the in-cutoff share of a list with the automatic width is about an
+// eighth; exceeding the capacity is reported by mpnn_eval)
+static size_t pair_capacity(size_t slots) { return slots / 4 + 1; }
+
 size_t mpnn_buffer_bytes(int frames, int n, int mt) {
-  const size_t rows = (size_t)frames * n, slots = rows * mt, pairs = slots / 2 + 1;
+  const size_t rows = (size_t)frames * n, slots = rows * mt, pairs = pair_capacity(slots);
   size_t b = 0;
   b += 4 * al(pairs * MP_HT * 4);            // S, DS, Z, DZ
   b += al(pairs * 2 * 4) + al(pairs * 4 * 4) + al(pairs * 4) + 2 * al(pairs * 4);
@@ -432,7 +436,7 @@ size_t mpnn_buffer_bytes(int frames, int n, int mt) {
 
 void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* weights,
                int n_model_species) {
-  const size_t rows = (size_t)frames * n, slots = rows * mt, pairs = slots / 2 + 1;
+  const size_t rows = (size_t)frames * n, slots = rows * mt, pairs = pair_capacity(slots);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     float* p = reinterpret_cast<float*>(base + off);
@@ -537,8 +541,9 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
     return false;
   }
   const long slots = counts[1];  // unordered pairs
-  if (slots > rows * mt / 2 + 1) {
-    snprintf(err, errlen, "pair count %ld exceeds capacity %ld", slots, rows * mt / 2 + 1);
+  if ((size_t)slots > pair_capacity((size_t)rows * mt)) {
+    snprintf(err, errlen, "pair count %ld exceeds capacity %zu", slots,
+             pair_capacity((size_t)rows * mt));
     return false;
   }
   if (slots > 0) {
