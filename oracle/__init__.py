@@ -94,6 +94,14 @@ def _declare(L):
     L.ora_plain_run.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), _dp, _dp, _ip,
                                 C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, _dp, _dp, _dp]
     L.ora_num_threads.restype = C.c_int
+    L.ora_normals_tag.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int, _dp]
+    L.ora_obabo_step.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), _dp, _dp, _ip, _dp, _dp]
+    L.ora_obabo_step.restype = C.c_double
+    L.ora_obabo_plain_run.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), _dp, _dp, _ip, C.c_uint64,
+                                      C.c_uint32, C.c_uint64, C.c_int64]
+    L.ora_obabo_lsd_run.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), C.POINTER(_Pot), _dp, _dp,
+                                    _ip, C.c_uint64, C.c_uint32, C.c_int64, C.c_int,
+                                    C.POINTER(_Stats)]
     if hasattr(L, "ora_mpnn_energy_forces"):
         from . import mpnn as _m
         _m.declare(L)
@@ -270,3 +278,31 @@ def plain_run(system, target, q, p, img, seed, replica, step0, n_steps, record=F
 
 def num_threads():
     return lib().ora_num_threads()
+
+
+# --- (OBABO) splitting (App. E) ----------------------------------------------
+def normals_tag(seed, replica, step, tag, n):
+    out = np.zeros((n, 3))
+    lib().ora_normals_tag(seed, replica, step, tag, n, _d(out))
+    return out
+
+
+def obabo_step(system, pot, q, p, img, xi1, xi2):
+    return lib().ora_obabo_step(C.byref(system._c), C.byref(pot._c), _d(q), _d(p),
+                                img.ctypes.data_as(_ip), _d(_f64(xi1)), _d(_f64(xi2)))
+
+
+def obabo_plain_run(system, pot, q, p, img, seed, replica, step0, n_steps):
+    lib().ora_obabo_plain_run(C.byref(system._c), C.byref(pot._c), _d(q), _d(p),
+                              img.ctypes.data_as(_ip), seed, replica, step0, n_steps)
+
+
+def obabo_lsd_run(system, target, draft, q, p, img, seed, replica, n_steps, K):
+    """LSD for (OBABO) in the staggered frame: (q, p) = y_0 on entry, the
+    (OBABO) state at step n_steps on return."""
+    st = _Stats()
+    lib().ora_obabo_lsd_run(C.byref(system._c), C.byref(target._c), C.byref(draft._c), _d(q),
+                            _d(p), img.ctypes.data_as(_ip), seed, replica, n_steps, K,
+                            C.byref(st))
+    return dict(windows=st.windows, rejections=st.rejections, frames=st.frames,
+                committed=st.committed)

@@ -734,3 +734,146 @@ int ora_num_threads(void) {
   return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* (OBABO) splitting (App. E)                                                */
+/* ------------------------------------------------------------------------ */
+/* Normals of the stream with an explicit tag (same layout as ora_normals).
+ * Tag 3 draws the extra noise of the (OBABO) outputs: the initial (O) half
+ * step at step 0 and the conditional half-step noise of step n. */
+#define ORA_TAG_OB 3u
+void ora_normals_tag(uint64_t seed, uint32_t replica, uint64_t step, uint32_t tag, int n,
+                     double *xi) {
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int i = 0; i < n; ++i) {
+    for (uint32_t block = 0; block < 2; ++block) {
+      uint32_t w[4];
+      stream_words(seed, replica, step, (uint32_t)i, tag, block, w);
+      double rad = sqrt(-2.0 * log(u53(w[0], w[1])));
+      double th = two_pi * u53(w[2], w[3]);
+      if (block == 0) {
+        xi[3 * i + 0] = rad * cos(th);
+        xi[3 * i + 1] = rad * sin(th);
+      } else {
+        xi[3 * i + 2] = rad * cos(th);
+      }
+    }
+  }
+}
+
+/* sqrt of the half-step (O) covariance Sigma_1/2 = M kT (1 - e^{-gamma dt}) */
+static double half_sigma(const ora_sys *S, int i) {
+  return sqrt(S->mass[i] * S->kT * S->fu * (1.0 - exp(-S->gamma * S->dt)));
+}
+
+/* One plain (OBABO) step (Eq. obabo): O(dt/2) with xi1, B(dt/2), A(dt),
+ * B(dt/2), O(dt/2) with xi2.  Returns U at the new positions. */
+double ora_obabo_step(const ora_sys *S, const ora_pot *P, double *q, double *p, int32_t *img,
+                      const double *xi1, const double *xi2) {
+  int m = 3 * S->n;
+  double *F = (double *)malloc(sizeof(double) * m);
+  double ah = exp(-0.5 * S->gamma * S->dt);
+  for (int c = 0; c < m; ++c) p[c] = ah * p[c] + half_sigma(S, c / 3) * xi1[c];   /* O */
+  ora_energy_forces(P, S->n, q, S->L, F, 1);
+  for (int c = 0; c < m; ++c) p[c] += 0.5 * S->dt * S->fu * F[c];                  /* B */
+  for (int i = 0; i < S->n; ++i)                                                   /* A */
+    for (int a = 0; a < 3; ++a) {
+      q[3 * i + a] += S->dt * p[3 * i + a] / S->mass[i];
+      int s = wrap1(&q[3 * i + a], S->L);
+      if (img) img[3 * i + a] += s;
+    }
+  double E = ora_energy_forces(P, S->n, q, S->L, F, 1);
+  for (int c = 0; c < m; ++c) p[c] += 0.5 * S->dt * S->fu * F[c];                  /* B */
+  for (int c = 0; c < m; ++c) p[c] = ah * p[c] + half_sigma(S, c / 3) * xi2[c];    /* O */
+  free(F);
+  return E;
+}
+
+/* n_steps plain (OBABO) steps; the two noises of step t come from tags 1 and
+ * 3 of the stream at step step0 + t + 1. */
+void ora_obabo_plain_run(const ora_sys *S, const ora_pot *P, double *q, double *p, int32_t *img,
+                         uint64_t seed, uint32_t replica, uint64_t step0, int64_t n_steps) {
+  int m = 3 * S->n;
+  double *x1 = (double *)malloc(sizeof(double) * m);
+  double *x2 = (double *)malloc(sizeof(double) * m);
+  for (int64_t t = 0; t < n_steps; ++t) {
+    uint64_t s = step0 + (uint64_t)t + 1u;
+    ora_normals_tag(seed, replica, s, ORA_TAG_OB, S->n, x1);
+    ora_normals(seed, replica, s, S->n, x2);
+    ora_obabo_step(S, P, q, p, img, x1, x2);
+  }
+  free(x1); free(x2);
+}
+
+/* LSD for (OBABO) in the staggered frame (App. E), from the (OBABO) state
+ * y_0 = (q, p) at step 0 to y_{n_steps}, returned in (q, p, img).
+ * 1. ybar_0 = OB(y_0): an (O) half step with noise from tag 3 at step 0,
+ *    then a (B) half step with the target force at q_0.
+ * 2. The staggered chain ybar_n = BOB(A(ybar_{n-1})), A a full position
+ *    step, is the (ABOBA) chain read at its midpoints, so LSD runs on the
+ *    (ABOBA) state (q_0 + dt/2 pbar_0 / m, pbar_0) with the usual windows.
+ * 3. The output y_n at the last committed step: q_n = its midpoint, and
+ *    p_mid = e^{-gamma dt/2}(pbar_{n-1} + dt/2 F_n) + Sigma_1/2^{1/2} xi1*,
+ *    where xi1* is drawn from the Gaussian conditional on
+ *    w = Sigma_1/2^{-1/2}(pbar_n - e^{-gamma dt} pbar_{n-1}
+ *                         - (1 + e^{-gamma dt}) dt/2 F_n):
+ *    mean e^{-gamma dt/2} w / (1 + e^{-gamma dt}), variance 1 / (1 + e^{-gamma dt}),
+ *    from tag 3 at step n.  (dt/2 F carries the force unit fu.) */
+void ora_obabo_lsd_run(const ora_sys *S, const ora_pot *T, const ora_pot *D, double *q,
+                       double *p, int32_t *img, uint64_t seed, uint32_t replica,
+                       int64_t n_steps, int K, ora_run_stats *st) {
+  int n = S->n, m = 3 * n;
+  double *F = (double *)malloc(sizeof(double) * m);
+  double *xi = (double *)malloc(sizeof(double) * (size_t)K * m);
+  double *u = (double *)malloc(sizeof(double) * K);
+  double *pd = (double *)malloc(sizeof(double) * (size_t)(K + 1) * m);
+  double *pprev = (double *)malloc(sizeof(double) * m);
+  double ah = exp(-0.5 * S->gamma * S->dt), a = exp(-S->gamma * S->dt);
+  /* 1. OB half step */
+  ora_normals_tag(seed, replica, 0u, ORA_TAG_OB, n, xi);
+  ora_energy_forces(T, n, q, S->L, F, 1);
+  for (int c = 0; c < m; ++c)
+    p[c] = ah * p[c] + half_sigma(S, c / 3) * xi[c] + 0.5 * S->dt * S->fu * F[c];
+  /* 2. (ABOBA) state whose next midpoint is q_0 + dt pbar_0 / m */
+  step_A(S, p, q, img);
+  memcpy(pprev, p, sizeof(double) * m);
+  if (st) memset(st, 0, sizeof(*st));
+  int64_t done = 0;
+  while (done < n_steps) {
+    int Kw = (int)((n_steps - done) < K ? (n_steps - done) : K);
+    for (int k = 0; k < Kw; ++k) {
+      ora_normals(seed, replica, (uint64_t)done + (uint64_t)k + 1u, n, &xi[(size_t)k * m]);
+      u[k] = ora_uniform(seed, replica, (uint64_t)done + (uint64_t)k + 1u);
+    }
+    ora_window_out o;
+    memset(&o, 0, sizeof(o));
+    o.p_draft = pd;
+    int j = ora_lsd_window(S, T, D, q, p, img, Kw, xi, u, &o, NULL, NULL, NULL);
+    memcpy(pprev, &pd[(size_t)(j - 1) * m], sizeof(double) * m); /* pbar_{n-1} */
+    done += j;
+    if (st) {
+      st->windows += 1;
+      st->committed += j;
+      st->rejections += o.rejected;
+      st->frames += Kw;
+    }
+  }
+  /* 3. output at the last committed step: back to its midpoint, F_n there */
+  for (int i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) {
+      q[3 * i + d] -= (0.5 * S->dt) * p[3 * i + d] / S->mass[i];
+      int s = wrap1(&q[3 * i + d], S->L);
+      if (img) img[3 * i + d] += s;
+    }
+  ora_energy_forces(T, n, q, S->L, F, 1);
+  ora_normals_tag(seed, replica, (uint64_t)n_steps, ORA_TAG_OB, n, xi);
+  double cw = ah / (1.0 + a), cs = 1.0 / sqrt(1.0 + a);
+  for (int c = 0; c < m; ++c) {
+    double sh = half_sigma(S, c / 3);
+    double half_kick = 0.5 * S->dt * S->fu * F[c];
+    double w = (p[c] - a * pprev[c] - (1.0 + a) * half_kick) / sh;
+    double x1 = cw * w + cs * xi[c];
+    p[c] = ah * (pprev[c] + half_kick) + sh * x1;
+  }
+  free(F); free(xi); free(u); free(pd); free(pprev);
+}

@@ -343,3 +343,51 @@ def test_linear_error_correction_keeps_target_marginals(ora):
     var_p = m * kT / (1.0 - (kT_ / m) * dt * dt / 4.0)
     assert stats.kstest(np.ravel(qs) / np.sqrt(kT / kT_), "norm").pvalue > 0.01
     assert stats.kstest(np.ravel(ps) / np.sqrt(var_p), "norm").pvalue > 0.01
+
+
+# --- (OBABO) splitting (App. E) ---------------------------------------------
+# For a harmonic force the (OBABO) chain samples the momenta exactly,
+# Var p = m kT, and the positions with Var q = kT / (k (1 - w^2 dt^2 / 4))
+# (w^2 = k / m); (ABOBA) has these two the other way round.
+def _obabo_samples(ora, runner, kT_, m, dt, replicas, steps, draft_k=None):
+    qs, ps = [], []
+    for r in range(replicas):
+        sysm, T, qref = _tether_system(ora, 1, kT_, m=m, dt=dt, gamma=1.0, kT=1.0)
+        q, p, img = qref.copy(), np.zeros((1, 3)), np.zeros((1, 3), np.int32)
+        if runner == "plain":
+            ora.obabo_plain_run(sysm, T, q, p, img, 11, r, 0, steps)
+        else:
+            D = ora.Potential.harmonic(draft_k, qref)
+            ora.obabo_lsd_run(sysm, T, D, q, p, img, 13, r, steps, 4)
+        qs.append(q[0] - qref[0])
+        ps.append(p[0])
+    return np.ravel(qs), np.ravel(ps)
+
+
+def test_obabo_plain_harmonic_law(ora):
+    kT_, m, dt = 2.0, 1.0, 0.6
+    qs, ps = _obabo_samples(ora, "plain", kT_, m, dt, 2000, 60)
+    var_q = 1.0 / kT_ / (1.0 - (kT_ / m) * dt * dt / 4.0)
+    assert stats.kstest(qs / np.sqrt(var_q), "norm").pvalue > 0.01
+    assert stats.kstest(ps / np.sqrt(m), "norm").pvalue > 0.01
+    # the (ABOBA) momentum law is rejected
+    assert stats.kstest(ps / np.sqrt(m / (1.0 - (kT_ / m) * dt * dt / 4.0)), "norm").pvalue < 1e-3
+
+
+def test_obabo_lsd_outputs_follow_the_obabo_law(ora):
+    # staggered LSD with a softer draft plus the conditional half-step
+    # recovery gives (OBABO) states with exactly the plain (OBABO) law
+    kT_, m, dt = 2.0, 1.0, 0.6
+    qs, ps = _obabo_samples(ora, "lsd", kT_, m, dt, 2000, 60, draft_k=1.2)
+    var_q = 1.0 / kT_ / (1.0 - (kT_ / m) * dt * dt / 4.0)
+    assert stats.kstest(qs / np.sqrt(var_q), "norm").pvalue > 0.01
+    assert stats.kstest(ps / np.sqrt(m), "norm").pvalue > 0.01
+    assert stats.kstest(ps / np.sqrt(m / (1.0 - (kT_ / m) * dt * dt / 4.0)), "norm").pvalue < 1e-3
+
+
+def test_obabo_lsd_accepts_everything_when_draft_is_target(ora):
+    n = 3
+    sysm, T, qref = _tether_system(ora, n, 2.0, dt=0.3, gamma=1.0, kT=1.0)
+    q, p, img = qref.copy(), np.zeros((n, 3)), np.zeros((n, 3), np.int32)
+    st = ora.obabo_lsd_run(sysm, T, T, q, p, img, 5, 0, 200, 8)
+    assert st["rejections"] == 0 and st["committed"] == 200
