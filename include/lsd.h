@@ -77,6 +77,18 @@ typedef enum {
 
 typedef enum { LSD_MODE_LSD = 0, LSD_MODE_PLAIN = 1 } lsd_mode;
 
+/* Integrator (Sec. 2.1, App. E).  ABOBA: the committed state is (q, p) of
+ * Eq. aboba.  OBABO: LSD runs in the staggered frame of App. E (the ABOBA
+ * chain read at its midpoints, which is the staggered (OBABO) chain); on init
+ * buf.q/buf.p hold the (OBABO) state y_0, the library applies the initial OB
+ * half step (target force at q_0, (O) noise from stream tag 3 at the current
+ * step) and keeps its own staggered state in q/p/img from then on; after
+ * every window the (OBABO) state of the last committed step is written to
+ * buf.obabo_q/obabo_p: its midpoint positions (wrapped) and the momentum
+ * recovered by the conditional half step of Eq. obabo_conditional (noise
+ * from stream tag 3 at that step). */
+typedef enum { LSD_INTEGRATOR_ABOBA = 0, LSD_INTEGRATOR_OBABO = 1 } lsd_integrator;
+
 typedef enum {
   LSD_POT_LJ = 1,       /* truncated, energy-shifted Lennard-Jones */
   LSD_POT_HARMONIC = 2, /* tether U = k/2 |q - anchor|^2 (minimum image) */
@@ -158,6 +170,7 @@ typedef struct {
                                   Target forces and the acceptance rule are
                                   unchanged, so the target law is preserved
                                   for any setting. */
+  int32_t integrator;          /* lsd_integrator (0 = ABOBA) */
   int32_t no_list_reuse;       /* 0 (default): the neighbour lists of a
                                   replica are kept across windows until one of
                                   its atoms has moved more than skin/4 from
@@ -184,6 +197,8 @@ typedef struct {
                               frames of the next window; NULL = Philox */
   const double *replay_xi; /* optional [k_max][N][3] normals, frame-major,
                               atom-major within a frame; NULL = Philox */
+  float *obabo_q;        /* OBABO integrator: out [3][N] positions of y_n */
+  float *obabo_p;        /* OBABO integrator: out [3][N] momenta of y_n */
 } lsd_buffers;
 
 /* Workspace bytes needed for cfg (host only; no GPU access). */

@@ -135,6 +135,8 @@ lsd_status plan(const lsd_config* c, Layout* L) {
     return fail(LSD_ERR_INVALID_ARG, "mode %d invalid", c->mode);
   if (c->error_correction < 0 || c->error_correction > 2)
     return fail(LSD_ERR_INVALID_ARG, "error_correction %d outside 0..2", c->error_correction);
+  if (c->integrator != LSD_INTEGRATOR_ABOBA && c->integrator != LSD_INTEGRATOR_OBABO)
+    return fail(LSD_ERR_INVALID_ARG, "integrator %d invalid", c->integrator);
   LSD_TRY(check_potential(c->target, "target"));
   if (c->mode == LSD_MODE_LSD) LSD_TRY(check_potential(c->draft, "draft"));
   if (c->mode == LSD_MODE_LSD && c->draft.kind == LSD_POT_MPNN)
@@ -385,7 +387,7 @@ hipError_t enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
   }
   if ((part == PART_FULL || part == PART_POST) && e == hipSuccess) {
     e = launch_decide(s->S, s->Lst, s->W, s->T, s->O, plain ? 1 : 0, st);
-    if (e == hipSuccess) e = launch_commit(s->S, s->W, s->buf.q, s->buf.p, s->buf.img, st);
+    if (e == hipSuccess) e = launch_commit(s->S, s->W, s->buf.q, s->buf.p, s->buf.img, plain ? 1 : 0, st);
   }
   return e;
 }
@@ -430,6 +432,8 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   if (!buf->q || !buf->p || !buf->img || !buf->step || !buf->workspace || !buf->log_ratio ||
       !buf->energy || !buf->accepted || !buf->n_committed)
     return fail(LSD_ERR_INVALID_ARG, "all state, output and workspace pointers are required");
+  if (cfg->integrator == LSD_INTEGRATOR_OBABO && (!buf->obabo_q || !buf->obabo_p))
+    return fail(LSD_ERR_INVALID_ARG, "the OBABO integrator needs obabo_q and obabo_p");
   if (reinterpret_cast<uintptr_t>(buf->workspace) % kAlign)
     return fail(LSD_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
   if (buf->workspace_bytes < L.total)
@@ -512,6 +516,20 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   S.replay_xi = buf->replay_xi;
   S.step = buf->step;
   S.step_limit = INT64_MAX;
+  if (cfg->integrator == LSD_INTEGRATOR_OBABO) {
+    const double a = std::exp(-cfg->gamma * cfg->dt);
+    S.obabo = 1;
+    S.ah = std::exp(-0.5 * cfg->gamma * cfg->dt);
+    S.hfu = 0.5 * cfg->dt * cfg->force_unit;
+    S.cw = S.ah / (1.0 + a);
+    S.cs = 1.0 / std::sqrt(1.0 + a);
+    for (int sp = 0; sp < LSD_MAX_SPECIES; ++sp) {
+      const double m = cfg->species_mass[sp < cfg->n_species ? sp : 0];
+      S.sh[sp] = std::sqrt(m * cfg->kT * cfg->force_unit * (1.0 - a));
+    }
+    S.obabo_q = buf->obabo_q;
+    S.obabo_p = buf->obabo_p;
+  }
 
   ListDev& Ls = s->Lst;
   memset(&Ls, 0, sizeof(Ls));
@@ -595,6 +613,28 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
       if (M.blas) rocblas_destroy_handle(M.blas);
       delete s;
       return fail(LSD_ERR_HIP, "rocBLAS handle setup failed");
+    }
+  }
+  if (cfg->integrator == LSD_INTEGRATOR_OBABO) {
+    // initial OB half step (App. E): target force at the given positions
+    hipError_t eo = launch_obabo_begin(S, s->Lst, s->W, s->Pt, false, buf->q, buf->p, buf->img, st, 0);
+    if (eo == hipSuccess) eo = launch_build_lists(S, s->Lst, s->W, true, st);
+    bool given = false;
+    if (eo == hipSuccess && s->has_mpnn) {
+      char err[256];
+      if (!mpnn_eval(s->mp, S, s->Lst, s->W, s->T, 0, 1, s->W.ft, ws<double>(s, L.epart), st, err,
+                     sizeof(err))) {
+        lsd_destroy(s);
+        return fail(LSD_ERR_HIP, "network forces at the initial state: %s", err);
+      }
+      given = true;
+    }
+    if (eo == hipSuccess)
+      eo = launch_obabo_begin(S, s->Lst, s->W, s->Pt, given, buf->q, buf->p, buf->img, st, 1);
+    if (eo == hipSuccess) eo = hipStreamSynchronize(st);
+    if (eo != hipSuccess) {
+      lsd_destroy(s);
+      return fail(LSD_ERR_HIP, "initial OB half step: %s", hipGetErrorString(eo));
     }
   }
   s->state = ST_READY;
@@ -682,7 +722,7 @@ lsd_status lsd_accept_rollback(lsd_system* s, int32_t* n_host, lsd_stream stream
     return fail(LSD_ERR_BAD_STATE, "accept_rollback needs a verified window");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(launch_decide(s->S, s->Lst, s->W, s->T, s->O, plain ? 1 : 0, st));
-  HIP_TRY(launch_commit(s->S, s->W, s->buf.q, s->buf.p, s->buf.img, st));
+  HIP_TRY(launch_commit(s->S, s->W, s->buf.q, s->buf.p, s->buf.img, plain ? 1 : 0, st));
   s->state = ST_COMMITTED;
   if (n_host) {
     HIP_TRY(hipMemcpyAsync(n_host, s->buf.n_committed, sizeof(int32_t) * s->S.R,

@@ -66,6 +66,12 @@ struct SysDev {
   const double* replay_xi;  // [kmax][N][3] or null
   int64_t* step;            // [R] committed step
   int64_t step_limit;       // frames producing steps beyond this are not verified
+  // (OBABO) outputs (App. E): half-step friction and noise, recovery weights
+  int obabo;
+  double ah, hfu, cw, cs;   // e^{-gamma dt/2}, dt/2 force_unit, ah/(1+a), (1+a)^{-1/2}
+  double sh[LSD_MAX_SPECIES];  // sqrt(m_s kT force_unit (1 - e^{-gamma dt}))
+  float* obabo_q;           // [3][N]
+  float* obabo_p;           // [3][N]
 };
 
 struct ListDev {
@@ -146,6 +152,7 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 
 #define LSD_TAG_XI 1u
 #define LSD_TAG_U 2u
+#define LSD_TAG_OB 3u  // (OBABO) output noise
 
 __device__ __forceinline__ double u53(uint32_t lo, uint32_t hi) {
   uint64_t x = ((uint64_t)hi << 32) | (uint64_t)lo;
@@ -168,16 +175,17 @@ __device__ __forceinline__ double stream_uniform(uint64_t seed, uint32_t replica
 
 // three normals of local atom `index` at step `step` (Box-Muller, binary64)
 __device__ __forceinline__ void stream_normals3(uint64_t seed, uint32_t replica, uint64_t step,
-                                                uint32_t index, double xi[3]) {
+                                                uint32_t index, double xi[3],
+                                                uint32_t tag = LSD_TAG_XI) {
   const double two_pi = 6.283185307179586476925286766559;
   uint32_t w[4];
-  stream_block(seed, replica, step, index, LSD_TAG_XI, 0u, w);
+  stream_block(seed, replica, step, index, tag, 0u, w);
   double r = sqrt(-2.0 * log(u53(w[0], w[1])));
   double s, c;
   sincos(two_pi * u53(w[2], w[3]), &s, &c);
   xi[0] = r * c;
   xi[1] = r * s;
-  stream_block(seed, replica, step, index, LSD_TAG_XI, 1u, w);
+  stream_block(seed, replica, step, index, tag, 1u, w);
   r = sqrt(-2.0 * log(u53(w[0], w[1])));
   xi[2] = r * cos(two_pi * u53(w[2], w[3]));
 }

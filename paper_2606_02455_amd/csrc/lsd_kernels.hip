@@ -758,7 +758,8 @@ __global__ __launch_bounds__(1024) void k_decide(SysDev S, WinDev W, TileDev Tl,
 // With error correction the cache becomes F - F~ of the committed frame,
 // from the EC-uncorrected draft force (App. D).
 __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __restrict__ q,
-                                                float* __restrict__ p, int* __restrict__ img) {
+                                                float* __restrict__ p, int* __restrict__ img,
+                                                int plain) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.n) return;
   const int r = S.atom_rep[i];
@@ -790,6 +791,23 @@ __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __res
       const double dl = S.c1fu * ((double)Fd - (double)Ft) * isg;
       pn = (float)fma(sg, z - coef * dl, mut);
     }
+    if (S.obabo) {
+      // (OBABO) state of this step (App. E): the midpoint, and the momentum
+      // after the first (O) half step drawn from its conditional given
+      // pbar_{n-1} = pk, pbar_n = pn and the target force F_n there
+      const double Fn = (double)(plain ? Fb : Ft);
+      const double pprev = (double)pk[d * N + i];
+      const double kick = S.hfu * Fn;
+      const double shs = S.sh[sp];
+      const double w = ((double)pn - S.a * pprev - (1.0 + S.a) * kick) / shs;
+      double eta[3];
+      stream_normals3(S.seed, (uint32_t)r, (uint64_t)S.step[r], (uint32_t)(i - S.rep_off[r]), eta,
+                      LSD_TAG_OB);
+      const double x1 = S.cw * w + S.cs * eta[d];
+      S.obabo_p[d * N + i] = (float)(S.ah * (pprev + kick) + shs * x1);
+      int dz = 0;
+      S.obabo_q[d * N + i] = a_half(xs[d], 0.0f, 0.0, L, &dz);  // the midpoint, wrapped
+    }
     const float qn = a_half(xs[d], pn, hm, L, &dimg[d]);
     q[d * N + i] = qn;
     p[d * N + i] = pn;
@@ -804,6 +822,74 @@ __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __res
       W.ec[d * N + i] = Ft - Fb;
     }
   }
+}
+
+// (OBABO) start (App. E): frame 0 = the given positions q_0 (wrapped), for
+// the lists and the target force at q_0.
+__global__ __launch_bounds__(256) void k_obabo_frame0(SysDev S, WinDev W, const float* __restrict__ q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  const size_t N = (size_t)S.n;
+  W.qmid[i] = make_float4(q[i], q[N + i], q[2 * N + i], pack_img(0, 0, 0));
+}
+
+// target forces of frame 0 into f_target (pair potentials and the tether)
+__global__ __launch_bounds__(256) void k_frame0_forces(SysDev S, ListDev Lst, WinDev W, PotDev P) {
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i0 = gt / LSD_LPA, sub = gt % LSD_LPA;
+  const bool in = i0 < S.n;
+  const int i = in ? i0 : S.n - 1;
+  float F[3], e;
+  pot_force(P, S, W.qmid, Lst.nbr_t + (size_t)i * Lst.mt, Lst.cnt_t[i], i, S.atom_rep[i], sub,
+            F[0], F[1], F[2], e);
+  if (!in || sub != 0) return;
+  const size_t N = (size_t)S.n;
+  W.ft[i] = F[0];
+  W.ft[N + i] = F[1];
+  W.ft[2 * N + i] = F[2];
+}
+
+// The initial OB half step: pbar_0 = e^{-gamma dt/2} p_0 + Sigma_1/2^{1/2} xi
+// + dt/2 F(q_0) (xi from tag 3 at the current step); the staggered state is
+// kept as the (ABOBA) state whose next midpoint is q_0 + dt pbar_0 / m.
+__global__ __launch_bounds__(256) void k_obabo_begin(SysDev S, WinDev W, float* __restrict__ q,
+                                                     float* __restrict__ p, int* __restrict__ img) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.n) return;
+  const int r = S.atom_rep[i];
+  const int sp = S.species ? S.species[i] : 0;
+  const size_t N = (size_t)S.n;
+  const double L = S.box[r];
+  double xi[3];
+  stream_normals3(S.seed, (uint32_t)r, (uint64_t)S.step[r], (uint32_t)(i - S.rep_off[r]), xi,
+                  LSD_TAG_OB);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float q0 = q[d * N + i], p0 = p[d * N + i];
+    S.obabo_q[d * N + i] = q0;
+    S.obabo_p[d * N + i] = p0;
+    const float pb = (float)(S.ah * (double)p0 + S.sh[sp] * xi[d] + S.hfu * (double)W.ft[d * N + i]);
+    int dimg = 0;
+    q[d * N + i] = a_half(q0, pb, S.hdt_m[sp], L, &dimg);
+    p[d * N + i] = pb;
+    img[d * N + i] += dimg;
+  }
+}
+
+hipError_t launch_obabo_begin(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P,
+                              bool forces_given, float* q, float* p, int* img, hipStream_t st,
+                              int stage) {
+  if (stage == 0) {
+    hipLaunchKernelGGL(k_obabo_frame0, dim3((S.n + 255) / 256), dim3(256), 0, st, S, W, q);
+    return hipGetLastError();
+  }
+  if (!forces_given) {
+    const long long threads = (long long)S.n * LSD_LPA;
+    hipLaunchKernelGGL(k_frame0_forces, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st,
+                       S, L, W, P);
+  }
+  hipLaunchKernelGGL(k_obabo_begin, dim3((S.n + 255) / 256), dim3(256), 0, st, S, W, q, p, img);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -926,8 +1012,9 @@ hipError_t launch_decide(const SysDev& S, const ListDev& L, const WinDev& W, con
 }
 
 hipError_t launch_commit(const SysDev& S, const WinDev& W, float* q, float* p, int* img,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_commit, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, W, q, p, img);
+                         int plain, hipStream_t st) {
+  hipLaunchKernelGGL(k_commit, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, W, q, p, img,
+                     plain);
   return hipGetLastError();
 }
 

@@ -23,7 +23,14 @@ hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, con
 hipError_t launch_decide(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                          const OutDev& O, int plain, hipStream_t st);
 hipError_t launch_commit(const SysDev& S, const WinDev& W, float* q, float* p, int* img,
-                         hipStream_t st);
+                         int plain, hipStream_t st);
+// (OBABO) start: stage 0 writes the given positions as frame 0; stage 1
+// (after the lists are built and, for the network, its forces are in
+// f_target) computes the target forces there unless given and applies the
+// initial OB half step to (q, p, img).
+hipError_t launch_obabo_begin(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P,
+                              bool forces_given, float* q, float* p, int* img, hipStream_t st,
+                              int stage);
 hipError_t launch_rng_normals(uint64_t seed, int replica, int64_t step, int n, double* out,
                               hipStream_t st);
 hipError_t launch_rng_uniforms(uint64_t seed, int replica, int64_t step0, int count, double* out,

@@ -48,14 +48,16 @@ class Config(C.Structure):
                 ("k_max", C.c_int32), ("mode", C.c_int32), ("seed", C.c_uint64),
                 ("target", Potential), ("draft", Potential),
                 ("max_neighbors_target", C.c_int32), ("max_neighbors_draft", C.c_int32),
-                ("error_correction", C.c_int32), ("no_list_reuse", C.c_int32)]
+                ("error_correction", C.c_int32), ("integrator", C.c_int32),
+                ("no_list_reuse", C.c_int32)]
 
 
 class Buffers(C.Structure):
     _fields_ = [("q", C.c_void_p), ("p", C.c_void_p), ("img", C.c_void_p), ("step", C.c_void_p),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("log_ratio", C.c_void_p), ("energy", C.c_void_p), ("accepted", C.c_void_p),
-                ("n_committed", C.c_void_p), ("replay_u", C.c_void_p), ("replay_xi", C.c_void_p)]
+                ("n_committed", C.c_void_p), ("replay_u", C.c_void_p), ("replay_xi", C.c_void_p),
+                ("obabo_q", C.c_void_p), ("obabo_p", C.c_void_p)]
 
 
 class WindowLayout(C.Structure):
@@ -168,7 +170,7 @@ class LSDSystem:
 
     def __init__(self, workload, mode="lsd", k_max=None, target=None, draft=None, seed=None,
                  skin=None, replay=False, max_neighbors=(0, 0), error_correction=False,
-                 list_reuse=True):
+                 list_reuse=True, integrator="aboba"):
         import torch
         self.torch = torch
         lib = load()
@@ -203,6 +205,10 @@ class LSDSystem:
         cfg.max_neighbors_target, cfg.max_neighbors_draft = max_neighbors
         cfg.error_correction = int(error_correction)  # 0 off, 1 App. D, 2 linear
         cfg.no_list_reuse = 0 if list_reuse else 1
+        if integrator not in ("aboba", "obabo"):
+            raise ValueError(f"integrator {integrator!r}")
+        self.obabo = integrator == "obabo"
+        cfg.integrator = 1 if self.obabo else 0
         self.cfg = cfg
         nbytes = C.c_size_t()
         _check(lib.lsd_workspace_size(C.byref(cfg), C.byref(nbytes)), "lsd_workspace_size")
@@ -225,6 +231,9 @@ class LSDSystem:
         buf.log_ratio, buf.energy = _ptr(self.log_ratio), _ptr(self.energy)
         buf.accepted, buf.n_committed = _ptr(self.accepted), _ptr(self.n_committed)
         buf.replay_u, buf.replay_xi = _ptr(self.replay_u), _ptr(self.replay_xi)
+        self.obabo_q = t.zeros((3, self.N), dtype=t.float32, device=dev) if self.obabo else None
+        self.obabo_p = t.zeros((3, self.N), dtype=t.float32, device=dev) if self.obabo else None
+        buf.obabo_q, buf.obabo_p = _ptr(self.obabo_q), _ptr(self.obabo_p)
         self.buf = buf
         handle = C.c_void_p()
         _check(lib.lsd_init_system(C.byref(cfg), C.byref(buf), _stream(t), C.byref(handle)),
@@ -398,7 +407,14 @@ class LSDSystem:
         return ms.value, n.value
 
     def state(self):
+        """Committed state; with the (OBABO) integrator q and p are the
+        (OBABO) state of the last committed step (the library's own state is
+        the staggered one) and img is not meaningful for them."""
         self.torch.cuda.synchronize()
+        if self.obabo:
+            return dict(q=self.obabo_q.T.double().cpu().numpy(),
+                        p=self.obabo_p.T.double().cpu().numpy(),
+                        img=self.img.T.cpu().numpy(), step=self.step.cpu().numpy())
         return dict(q=self.q.T.double().cpu().numpy(), p=self.p.T.double().cpu().numpy(),
                     img=self.img.T.cpu().numpy(), step=self.step.cpu().numpy())
 
