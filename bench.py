@@ -295,6 +295,13 @@ def main():
     st0 = plain.state()
     log(f"equilibrated {int(st0['step'][0])} plain steps")
 
+    # --- verification kernel variant, tuned on this system (one window)
+    chosen_fw, fw_us = lsds.autotune_verify(K, repeats=5)
+    lsds.verify_window()
+    lsds.accept_rollback()
+    log(f"autotuned verification: {chosen_fw} frames per wave "
+        f"({', '.join(f'{k}: {v:.1f} us' for k, v in fw_us.items())})")
+
     # --- LSD
     lsds.run_windows(args.warmup, K)
     lsds.reset_counters()
@@ -343,7 +350,8 @@ def main():
     achieved = alg_bytes / avg_s / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=read_traffic(args.config),
-                    kernel="k_verify", avg_us=round(avg_s * 1e6, 3),
+                    kernel=f"k_verify<{chosen_fw}>", avg_us=round(avg_s * 1e6, 3),
+                    autotune_us={str(k): round(v, 2) for k, v in fw_us.items()},
                     algorithmic_bytes=int(alg_bytes), frames_per_launch=round(frames_per_launch, 3),
                     in_cutoff_pairs=pairs)
 

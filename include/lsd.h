@@ -253,6 +253,17 @@ LSD_API lsd_status lsd_accept_rollback(lsd_system *sys, int32_t *n_host,
 LSD_API lsd_status lsd_run_windows(lsd_system *sys, int32_t n_windows, int32_t K,
                            lsd_stream stream);
 
+/* Autotuner of the verification kernel (LSD mode, pair targets): drafts a
+ * window of K frames from the committed state (as lsd_draft_steps; the state
+ * is left DRAFTED, so the caller continues with lsd_verify_window), times
+ * the kernel with 1, 2 and 4 frames per wave on those frames (one untimed
+ * and `repeats` timed launches each, HIP events on `stream`) and keeps the
+ * fastest for windows of K frames.  Outputs: chosen (host, frames per wave)
+ * and us (host [3], mean microseconds per launch of each candidate), each
+ * optional.  Captured window graphs are dropped.  Synchronises `stream`. */
+LSD_API lsd_status lsd_autotune_verify(lsd_system *sys, int32_t K, int32_t repeats,
+                                       int32_t *chosen, double *us, lsd_stream stream);
+
 /* enable != 0 (default): lsd_run_windows replays captured graphs; 0: it
  * issues the kernels of every window one by one. */
 LSD_API lsd_status lsd_set_graphs(lsd_system *sys, int32_t enable);

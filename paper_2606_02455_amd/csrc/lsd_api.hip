@@ -331,9 +331,18 @@ struct lsd_system {
   bool has_mpnn = false;
   hipStream_t cap_stream = nullptr;
   std::map<int, WindowGraphs> graphs;
+  std::map<int, int> tuned_fw;  // frames per wave of the verification kernel, by K
 };
 
 namespace {
+
+// frames per wave of the verification kernel for windows of K frames: the
+// autotuned choice if any, else 4 for long windows and fewer for short ones
+int verify_fw(const lsd_system* s, int K) {
+  auto it = s->tuned_fw.find(K);
+  if (it != s->tuned_fw.end()) return it->second;
+  return K >= 8 ? 4 : (K >= 2 ? 2 : 1);
+}
 
 template <typename T>
 T* ws(const lsd_system* s, size_t off) {
@@ -382,7 +391,7 @@ hipError_t enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
   }
   if (s->has_mpnn) return hipErrorNotSupported;  // never captured
   if (part == PART_FULL && !plain && e == hipSuccess) {
-    const int fw = K >= 8 ? 4 : (K >= 2 ? 2 : 1);
+    const int fw = verify_fw(s, K);
     e = launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st);
   }
   if ((part == PART_FULL || part == PART_POST) && e == hipSuccess) {
@@ -696,7 +705,7 @@ lsd_status lsd_verify_window(lsd_system* s, lsd_stream stream) {
       HIP_TRY(hipEventRecord(R.start[slot], st));
     }
     // frames per wave of the verification kernel: 4 for long windows
-    const int fw = s->W.K >= 8 ? 4 : (s->W.K >= 2 ? 2 : 1);
+    const int fw = verify_fw(s, s->W.K);
     if (s->has_mpnn) {
       char err[256];
       if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, s->T, 0, s->W.K, s->W.ft,
@@ -763,13 +772,59 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
     if (R.used == kTimingRing) LSD_TRY(timing_drain_one(s));
     const int slot = (R.head + R.used) % kTimingRing;
     HIP_TRY(hipEventRecord(R.start[slot], st));
-    const int fw = K >= 8 ? 4 : (K >= 2 ? 2 : 1);
+    const int fw = verify_fw(s, K);
     HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st));
     HIP_TRY(hipEventRecord(R.stop[slot], st));
     R.used += 1;
     HIP_TRY(hipGraphLaunch(G.post, st));
   }
   s->state = ST_COMMITTED;
+  return LSD_OK;
+}
+
+lsd_status lsd_autotune_verify(lsd_system* s, int32_t K, int32_t repeats, int32_t* chosen,
+                               double* us, lsd_stream stream) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  if (K < 1 || K > s->cfg.k_max) return fail(LSD_ERR_INVALID_ARG, "K = %d outside 1..k_max", K);
+  if (repeats < 1) return fail(LSD_ERR_INVALID_ARG, "repeats must be >= 1");
+  if (s->cfg.mode != LSD_MODE_LSD || s->has_mpnn)
+    return fail(LSD_ERR_UNSUPPORTED, "the verification kernel is tuned in LSD mode with a pair target");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  LSD_TRY(lsd_draft_steps(s, K, stream));  // leaves the window drafted
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  static const int kCandidates[3] = {1, 2, 4};
+  int best = verify_fw(s, K);
+  float best_ms = 0.0f;
+  for (int c = 0; c < 3; ++c) {
+    const int fw = kCandidates[c];
+    // one untimed launch, then `repeats` timed ones on the same drafted frames
+    // (verification only writes f_target and the per-tile sums: repeatable)
+    hipError_t e = launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int r = 0; r < repeats && e == hipSuccess; ++r)
+      e = launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return fail(LSD_ERR_HIP, "autotune: %s", hipGetErrorString(e));
+    }
+    if (us) us[c] = 1e3 * ms / repeats;
+    if (c == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = fw;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->tuned_fw[K] = best;
+  destroy_graphs(s);  // captured windows used the previous choice
+  if (chosen) *chosen = best;
   return LSD_OK;
 }
 

@@ -95,6 +95,8 @@ EXPORTS = {
     "lsd_fit_pair_accumulate": ([C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_int32,
                                  C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
     "lsd_fit_pair_solve": ([C.c_void_p, C.c_int32, C.c_double, C.c_void_p], C.c_int),
+    "lsd_autotune_verify": ([C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                             C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "lsd_destroy": ([C.c_void_p], C.c_int),
     "lsd_last_error": ([], C.c_char_p),
 }
@@ -365,6 +367,16 @@ class LSDSystem:
         f = C.c_int32()
         _check(load().lsd_get_status(self.h, C.byref(f), _stream(self.torch)), "lsd_get_status")
         return int(f.value)
+
+    def autotune_verify(self, K, repeats=10):
+        """Pick the fastest frames-per-wave variant of the verification
+        kernel for windows of K frames; drafts one window (left drafted).
+        Returns (chosen, {fw: microseconds})."""
+        ch = C.c_int32()
+        us = (C.c_double * 3)()
+        _check(load().lsd_autotune_verify(self.h, int(K), int(repeats), C.byref(ch), us,
+                                          _stream(self.torch)), "lsd_autotune_verify")
+        return int(ch.value), {1: us[0], 2: us[1], 4: us[2]}
 
     def set_graphs(self, on=True):
         """Replay captured HIP graphs in run_windows (default) or not."""

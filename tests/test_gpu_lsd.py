@@ -583,3 +583,27 @@ def test_list_reuse_changes_only_rounding(torch, lsd):
     assert np.max(np.abs(dq)) < 1e-3
     a.destroy()
     b.destroy()
+
+
+def test_autotuned_verification_gives_identical_results(torch, lsd):
+    # every frames-per-wave variant reduces a frame's sums in the same order,
+    # so the tuned choice changes only the time taken
+    _say("verification autotuner")
+    w = W.lj_fluid(8, seed=29, K=8)
+    a = lsd.LSDSystem(w, mode="lsd")
+    b = lsd.LSDSystem(w, mode="lsd")
+    chosen, us = a.autotune_verify(8, repeats=3)
+    assert chosen in (1, 2, 4) and all(v > 0 for v in us.values())
+    a.verify_window()
+    a.accept_rollback()
+    b.draft_steps(8)
+    b.verify_window()
+    b.accept_rollback()
+    a.run_windows(10, 8)
+    b.run_windows(10, 8)
+    sa, sb = a.state(), b.state()
+    for k in ("q", "p", "img", "step"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert np.array_equal(a.log_ratio.cpu().numpy(), b.log_ratio.cpu().numpy())
+    a.destroy()
+    b.destroy()
