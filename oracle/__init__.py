@@ -10,6 +10,9 @@ Paper: "Speculative Sampling For Faster Molecular Dynamics" (arXiv 2606.02455).
   * Eq. reflectionVerify (Sec. 3.1): reflection-maximal coupling.
   * Alg. 1 (App. C): synchronous speculative window; Alg. 2 draft_step /
     verify_step per-step maps.
+  * Drafts (Sec. 3, Sec. 4): pair.py, the force-matched pair draft; net.py,
+    the learned one-layer direct-force draft and its training (loss
+    gradient, Adam).
 """
 import ctypes as C
 import os
@@ -108,6 +111,9 @@ def _declare(L):
     if hasattr(L, "ora_pair_forces"):
         from . import pair as _p
         _p.declare(L)
+    if hasattr(L, "ora_net_forward"):
+        from . import net as _n
+        _n.declare(L)
 
 
 def _d(a):

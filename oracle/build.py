@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["lsd_oracle.c", "mpnn_oracle.c", "pair_oracle.c"]
+SOURCES = ["lsd_oracle.c", "mpnn_oracle.c", "pair_oracle.c", "net_oracle.c"]
 OUT = os.path.join(HERE, "liboracle.so")
 
 
