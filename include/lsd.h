@@ -93,7 +93,8 @@ typedef enum {
   LSD_POT_LJ = 1,       /* truncated, energy-shifted Lennard-Jones */
   LSD_POT_HARMONIC = 2, /* tether U = k/2 |q - anchor|^2 (minimum image) */
   LSD_POT_MPNN = 3,     /* message-passing network (target only), below */
-  LSD_POT_PAIR = 4      /* force-matched pair draft (draft only), below */
+  LSD_POT_PAIR = 4,     /* force-matched pair draft (draft only), below */
+  LSD_POT_NET = 5       /* learned many-body draft (draft only), below */
 } lsd_pot_kind;
 
 /* Pair-force draft (the fallback of a learned draft: a potential lighter
@@ -106,6 +107,31 @@ typedef enum {
  * Forces only: the draft energy is never needed.  The weights come from
  * force matching: lsd_fit_pair_accumulate / lsd_fit_pair_solve. */
 #define LSD_PAIR_MAX_BASIS 32
+
+/* Learned many-body draft (Sec. 3, Sec. 4: the drafts are small learned
+ * potentials fitted to the target's forces that predict forces directly; a
+ * non-conservative draft is admissible because verification corrects its
+ * samples).  A one-layer direct-force network over a species-resolved radial
+ * descriptor, H = LSD_NET_HIDDEN hidden units, S species, B radial functions:
+ *   e_b(r) = (cos(pi r/rc) + 1)/2 sin(b pi r/rc) / r,  b = 1..B, r < rc
+ *   D_i    = sum_(j, image) e(r_ij) placed in the block of species s_j (S B)
+ *   h_i    = silu(W1 D_i + b1[s_i]),   v_i = W2 h_i   (B edge coefficients)
+ *   f_ij   = sum_b e_b(r_ij) (c[t(s_i, s_j)][b] + v_i[b] + v_j[b])
+ *   F_i    = - sum_(j, image) f_ij d / r,  d = q_j + n L - q_i
+ * f_ij is symmetric, so the forces obey Newton's third law; with W2 = 0 the
+ * draft is the pair draft above with weights c.  Parameters: one flat device
+ * binary32 vector kept by pointer (training may update it between windows),
+ * matrices [out][in]: W1 [H][S B], b1 [S][H], W2 [B][H], c [S(S+1)/2][B];
+ * lsd_net_param_count gives its length.  S = n_model_species (<= 4), B =
+ * n_basis (1 .. LSD_NET_MAX_BASIS), S B <= LSD_NET_MAX_DESC.  precision:
+ * LSD_PREC_FP32 evaluates the two dense layers in binary32 on the vector
+ * ALUs; LSD_PREC_BF16 on the matrix cores with D, h, W1 and W2 rounded to
+ * bfloat16 and binary32 accumulation (pair terms are binary32 either way). */
+#define LSD_NET_HIDDEN 32
+#define LSD_NET_MAX_BASIS 16
+#define LSD_NET_MAX_DESC 32
+#define LSD_NET_MAX_SPECIES 4
+typedef enum { LSD_PREC_FP32 = 0, LSD_PREC_BF16 = 1 } lsd_precision;
 
 /* Message-passing potential (a stand-in for the paper's interatomic
  * potentials; architecture fixed here): radial basis
@@ -133,10 +159,11 @@ typedef struct {
   const float *anchor;       /* tether anchors, device [3][N] (kept by pointer) */
   const float *force_offset; /* optional constant force field added to the
                                 forces, device [3][N] or NULL (test drafts) */
-  const float *weights;      /* MPNN / PAIR: flat weights (device, kept by pointer) */
-  int32_t n_model_species;   /* MPNN: species rows of W_emb; PAIR: S (>= n_species) */
+  const float *weights;      /* MPNN / PAIR / NET: flat weights (device, kept by pointer) */
+  int32_t n_model_species;   /* MPNN: species rows of W_emb; PAIR, NET: S (>= n_species) */
   double energy_scale;       /* MPNN: s_E */
-  int32_t n_basis;           /* PAIR: B, 1 .. LSD_PAIR_MAX_BASIS */
+  int32_t n_basis;           /* PAIR: B, 1 .. LSD_PAIR_MAX_BASIS; NET: B */
+  int32_t precision;         /* NET: lsd_precision */
 } lsd_potential;
 
 typedef struct {
@@ -370,6 +397,40 @@ LSD_API lsd_status lsd_fit_pair_accumulate(lsd_system *sys, int32_t n_basis, dou
  * INVALID_ARG if the system is not positive definite (raise the ridge). */
 LSD_API lsd_status lsd_fit_pair_solve(const double *gram, int32_t n_params, double ridge,
                                       double *weights);
+
+/* Training of the learned draft by force matching (host-side count, then
+ * device calls).  lsd_net_param_count: length of the parameter vector for S
+ * species and B radial functions (0 if out of range).
+ *
+ * lsd_net_train_accumulate adds, for the valid frames (0 .. K_eff-1) of the
+ * current window, the gradient of the summed squared force error
+ * sum |F_net(q_mid) - y|^2 (all atoms and components; y = f_target if
+ * use_target_forces != 0, else f_draft, the stepping forces, which are the
+ * target's in PLAIN mode) in the parameters of `net` (kind LSD_POT_NET, its
+ * cutoff <= the target cutoff: the target list is used), evaluated in
+ * binary32 (whatever net->precision says) and reduced in binary64 in a fixed
+ * order:  grad[0..P) += gradient, grad[P] += the squared error, grad[P+1] +=
+ * the number of atom frames.  grad: device binary64 [P+2], zeroed by the
+ * caller before the first call.  scratch: device memory of
+ * lsd_net_train_scratch_size bytes.  Asynchronous.  Errors: INVALID_ARG,
+ * BAD_STATE (no drafted window), CAPACITY, HIP.
+ *
+ * lsd_net_adam_step: one Adam step (Kingma and Ba, 2015) on the mean
+ * squared force component error: g = grad[0..P) / (3 grad[P+1]);
+ * m = beta1 m + (1-beta1) g, v = beta2 v + (1-beta2) g^2 (m, v device
+ * binary64 [P], zero before step 1), params -= lr m^/(sqrt(v^) + eps) with
+ * m^ = m/(1-beta1^t), v^ = v/(1-beta2^t), computed in binary64 and rounded
+ * to the binary32 params; then grad[0..P+2) is zeroed.  t >= 1.  Nothing
+ * changes if grad[P+1] is 0.  Asynchronous; one work-group. */
+LSD_API int32_t lsd_net_param_count(int32_t n_species, int32_t n_basis);
+LSD_API lsd_status lsd_net_train_scratch_size(const lsd_system *sys, size_t *bytes);
+LSD_API lsd_status lsd_net_train_accumulate(lsd_system *sys, const lsd_potential *net,
+                                            int32_t use_target_forces, void *scratch,
+                                            size_t scratch_bytes, double *grad,
+                                            lsd_stream stream);
+LSD_API lsd_status lsd_net_adam_step(float *params, double *m, double *v, double *grad,
+                                     int32_t n_params, double lr, double beta1, double beta2,
+                                     double eps, int64_t t, lsd_stream stream);
 
 /* Releases the handle and its HIP events (no device memory is freed). */
 LSD_API lsd_status lsd_destroy(lsd_system *sys);

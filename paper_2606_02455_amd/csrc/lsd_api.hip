@@ -19,6 +19,7 @@
 #include "fit.h"
 #include "lsd_launch.h"
 #include "mpnn.h"
+#include "net.h"
 
 namespace {
 
@@ -63,6 +64,7 @@ struct Layout {
   size_t qmid, p, fd, ft, invalid, partial, commit_frame, reflected, coef, counters, status;
   size_t ec = 0, ec_prev = 0, ec_samples = 0;  // error-correction caches (0: off)
   size_t mpnn = 0, mpnn_bytes = 0, blas = 0, epart = 0;
+  size_t net_v = 0;  // learned draft: edge coefficients [N][LSD_NET_MAX_BASIS]
   bool has_mpnn = false;
   int mt = 0, md = 0, n_cells = 0, n_tiles = 0, cell_cap = 0;
   double rl_t = 0, rl_d = 0;
@@ -81,8 +83,10 @@ bool is_binary32(double v) { return (double)(float)v == v; }
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 double pot_reach(const lsd_potential& P) {
-  return (P.kind == LSD_POT_LJ || P.kind == LSD_POT_MPNN || P.kind == LSD_POT_PAIR) ? P.cutoff
-                                                                                    : 0.0;
+  return (P.kind == LSD_POT_LJ || P.kind == LSD_POT_MPNN || P.kind == LSD_POT_PAIR ||
+          P.kind == LSD_POT_NET)
+             ? P.cutoff
+             : 0.0;
 }
 
 constexpr size_t kBlasWorkspace = 64ull << 20;
@@ -102,6 +106,15 @@ lsd_status check_potential(const lsd_potential& P, const char* what) {
         P.n_model_species > LSD_MAX_SPECIES || P.n_basis < 1 || P.n_basis > LSD_PAIR_MAX_BASIS)
       return fail(LSD_ERR_INVALID_ARG, "%s: pair draft needs cutoff > 0, weights, 1..%d species "
                   "and 1..%d basis functions", what, LSD_MAX_SPECIES, LSD_PAIR_MAX_BASIS);
+  } else if (P.kind == LSD_POT_NET) {
+    if (!(P.cutoff > 0.0) || !P.weights || P.n_model_species < 1 ||
+        P.n_model_species > LSD_NET_MAX_SPECIES || P.n_basis < 1 ||
+        P.n_basis > LSD_NET_MAX_BASIS || P.n_model_species * P.n_basis > LSD_NET_MAX_DESC)
+      return fail(LSD_ERR_INVALID_ARG, "%s: learned draft needs cutoff > 0, weights, 1..%d "
+                  "species, 1..%d radial functions and species x functions <= %d", what,
+                  LSD_NET_MAX_SPECIES, LSD_NET_MAX_BASIS, LSD_NET_MAX_DESC);
+    if (P.precision != LSD_PREC_FP32 && P.precision != LSD_PREC_BF16)
+      return fail(LSD_ERR_INVALID_ARG, "%s: precision %d invalid", what, P.precision);
   } else {
     return fail(LSD_ERR_UNSUPPORTED, "%s: potential kind %d not supported", what, P.kind);
   }
@@ -141,8 +154,12 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   if (c->mode == LSD_MODE_LSD) LSD_TRY(check_potential(c->draft, "draft"));
   if (c->mode == LSD_MODE_LSD && c->draft.kind == LSD_POT_MPNN)
     return fail(LSD_ERR_UNSUPPORTED, "the message-passing network is supported as target only");
-  if (c->target.kind == LSD_POT_PAIR)
-    return fail(LSD_ERR_UNSUPPORTED, "the pair draft is supported as draft only");
+  if (c->target.kind == LSD_POT_PAIR || c->target.kind == LSD_POT_NET)
+    return fail(LSD_ERR_UNSUPPORTED, "the pair and learned drafts are supported as drafts only");
+  if (c->mode == LSD_MODE_LSD && c->draft.kind == LSD_POT_NET &&
+      c->draft.n_model_species < c->n_species)
+    return fail(LSD_ERR_INVALID_ARG, "learned draft has %d species, system has %d",
+                c->draft.n_model_species, c->n_species);
   if (c->mode == LSD_MODE_LSD && c->draft.kind == LSD_POT_PAIR &&
       c->draft.n_model_species < c->n_species)
     return fail(LSD_ERR_INVALID_ARG, "pair draft has %d species, system has %d",
@@ -251,6 +268,8 @@ lsd_status plan(const lsd_config* c, Layout* L) {
     L->ec_samples = bump(&off, (size_t)R * 4);
     if (c->error_correction == 2) L->ec_prev = bump(&off, 3 * n * 4);
   }
+  if (c->mode == LSD_MODE_LSD && c->draft.kind == LSD_POT_NET)
+    L->net_v = bump(&off, n * LSD_NET_MAX_BASIS * 4);
   L->has_mpnn = c->target.kind == LSD_POT_MPNN;
   if (L->has_mpnn) {
     L->mpnn_bytes = mpnn_buffer_bytes(c->k_max, N, L->mt);
@@ -286,12 +305,13 @@ PotDev make_pot(const lsd_potential& P, const Layout& L) {
   } else if (P.kind == LSD_POT_HARMONIC) {
     d.kspring = (float)P.k_spring;
     d.anchor = P.anchor;
-  } else if (P.kind == LSD_POT_PAIR) {
+  } else if (P.kind == LSD_POT_PAIR || P.kind == LSD_POT_NET) {
     d.rc2 = (float)(P.cutoff * P.cutoff);
     d.pi_rc = (float)(M_PI / P.cutoff);
     d.nb = P.n_basis;
     d.ns = P.n_model_species;
     d.w = P.weights;
+    d.prec = P.kind == LSD_POT_NET ? P.precision : 0;
   }
   return d;
 }
@@ -386,8 +406,11 @@ hipError_t enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
   if (part == PART_FULL || part == PART_PRE) {
     e = launch_window_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, st);
     if (e == hipSuccess) e = launch_build_lists(s->S, s->Lst, s->W, false, st);
-    for (int k = 0; k < K && e == hipSuccess; ++k)
-      e = launch_draft(s->S, s->Lst, s->W, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st);
+    for (int k = 0; k < K && e == hipSuccess; ++k) {
+      if (!plain && s->Pd.kind == LSD_POT_NET) e = launch_net_nodes(s->S, s->Lst, s->W, s->Pd, k, st);
+      if (e == hipSuccess)
+        e = launch_draft(s->S, s->Lst, s->W, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st);
+    }
   }
   if (s->has_mpnn) return hipErrorNotSupported;  // never captured
   if (part == PART_FULL && !plain && e == hipSuccess) {
@@ -608,6 +631,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
 
   s->Pt = make_pot(cfg->target, L);
   s->Pd = cfg->mode == LSD_MODE_LSD ? make_pot(cfg->draft, L) : s->Pt;
+  if (L.net_v) s->Pd.v = ws<float>(s, L.net_v);
   if (L.has_mpnn) {
     s->has_mpnn = true;
     s->use_graphs = false;  // the network pass is issued eagerly
@@ -670,6 +694,8 @@ lsd_status lsd_draft_steps(lsd_system* s, int32_t K, lsd_stream stream) {
         return fail(LSD_ERR_HIP, "network forces: %s", err);
       HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->Pt, k, 1, st, 1));
     } else {
+      if (!plain && s->Pd.kind == LSD_POT_NET)
+        HIP_TRY(launch_net_nodes(s->S, s->Lst, s->W, s->Pd, k, st));
       HIP_TRY(launch_draft(s->S, s->Lst, s->W, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st));
     }
   }
@@ -962,6 +988,61 @@ lsd_status lsd_fit_pair_accumulate(lsd_system* s, int32_t n_basis, double cutoff
   F.LP = F.ns * n_basis;
   HIP_TRY(launch_fit(s->S, s->Lst, s->W, s->T, F, use_target_forces ? 1 : 0, differences ? 1 : 0,
                      static_cast<double*>(scratch), gram, static_cast<hipStream_t>(stream)));
+  return LSD_OK;
+}
+
+int32_t lsd_net_param_count(int32_t n_species, int32_t n_basis) {
+  if (n_species < 1 || n_species > LSD_NET_MAX_SPECIES || n_basis < 1 ||
+      n_basis > LSD_NET_MAX_BASIS || n_species * n_basis > LSD_NET_MAX_DESC)
+    return 0;
+  return net_params(n_species, n_basis);
+}
+
+lsd_status lsd_net_train_scratch_size(const lsd_system* s, size_t* bytes) {
+  if (!s || !bytes) return fail(LSD_ERR_INVALID_ARG, "null argument");
+  *bytes = net_train_bytes(s->cfg.k_max, s->cfg.n_atoms);
+  return LSD_OK;
+}
+
+lsd_status lsd_net_train_accumulate(lsd_system* s, const lsd_potential* net,
+                                    int32_t use_target_forces, void* scratch, size_t scratch_bytes,
+                                    double* grad, lsd_stream stream) {
+  if (!s || !net || !scratch || !grad) return fail(LSD_ERR_INVALID_ARG, "null argument");
+  if (net->kind != LSD_POT_NET) return fail(LSD_ERR_INVALID_ARG, "not a learned draft");
+  LSD_TRY(check_potential(*net, "learned draft"));
+  if (net->n_model_species < s->cfg.n_species)
+    return fail(LSD_ERR_INVALID_ARG, "learned draft has %d species, system has %d",
+                net->n_model_species, s->cfg.n_species);
+  if (net->cutoff > pot_reach(s->cfg.target))
+    return fail(LSD_ERR_INVALID_ARG, "learned draft cutoff %g exceeds the target cutoff %g",
+                net->cutoff, pot_reach(s->cfg.target));
+  const size_t need = net_train_bytes(s->cfg.k_max, s->cfg.n_atoms);
+  if (scratch_bytes < need)
+    return fail(LSD_ERR_CAPACITY, "training scratch %zu bytes < required %zu", scratch_bytes, need);
+  if (s->state == ST_READY || s->W.K < 1)
+    return fail(LSD_ERR_BAD_STATE, "training needs a drafted window");
+  if (use_target_forces &&
+      !(s->cfg.mode == LSD_MODE_LSD && (s->state == ST_VERIFIED || s->state == ST_COMMITTED)))
+    return fail(LSD_ERR_BAD_STATE, "target forces exist only for a verified window (LSD mode)");
+  lsd_potential copy = *net;
+  copy.precision = LSD_PREC_FP32;
+  PotDev P = make_pot(copy, s->lay);
+  const NetTrainDev T = net_train_bind(static_cast<char*>(scratch), s->cfg.k_max, s->cfg.n_atoms);
+  HIP_TRY(launch_net_train(s->S, s->Lst, s->W, P, T, use_target_forces ? 1 : 0, grad,
+                           static_cast<hipStream_t>(stream)));
+  return LSD_OK;
+}
+
+lsd_status lsd_net_adam_step(float* params, double* m, double* v, double* grad, int32_t n_params,
+                             double lr, double beta1, double beta2, double eps, int64_t t,
+                             lsd_stream stream) {
+  if (!params || !m || !v || !grad) return fail(LSD_ERR_INVALID_ARG, "null argument");
+  if (n_params < 1 || t < 1) return fail(LSD_ERR_INVALID_ARG, "n_params and t must be >= 1");
+  if (!(lr >= 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+      !(eps > 0.0))
+    return fail(LSD_ERR_INVALID_ARG, "Adam needs lr >= 0, beta1, beta2 in [0, 1), eps > 0");
+  HIP_TRY(launch_net_adam(params, m, v, grad, n_params, lr, beta1, beta2, eps, (long long)t,
+                          static_cast<hipStream_t>(stream)));
   return LSD_OK;
 }
 

@@ -23,6 +23,11 @@
 #define LSD_POT_HARMONIC 2
 #define LSD_POT_MPNN 3
 #define LSD_POT_PAIR 4
+#define LSD_POT_NET 5
+#define LSD_NET_HIDDEN 32     // hidden units of the learned draft
+#define LSD_NET_MAX_BASIS 16  // radial functions (edge coefficients per atom, v stride)
+#define LSD_NET_MAX_DESC 32   // species x radial functions of the descriptor
+#define LSD_NET_MAX_SPECIES 4
 
 // status word bits
 #define LSD_STATUS_NBR_TARGET 1
@@ -39,10 +44,27 @@ struct PotDev {
   const float* anchor;    // [3][N]
   const float* offset;    // [3][N] or null
   // pair draft: rc2 above, pi / rc, basis size, species, weights [T][nb]
+  // learned draft: the same, w = flat parameters, and the edge coefficients
+  // v [N][LSD_NET_MAX_BASIS] of the frame being drafted
   float pi_rc;
   int nb, ns;
   const float* w;
+  float* v;
+  int prec;
 };
+
+// offsets of the learned draft's parameter blocks W1 [H][S B], b1 [S][H],
+// W2 [B][H], c [T][B]
+__host__ __device__ __forceinline__ int net_off_b1(int S, int B) { return LSD_NET_HIDDEN * S * B; }
+__host__ __device__ __forceinline__ int net_off_w2(int S, int B) {
+  return net_off_b1(S, B) + S * LSD_NET_HIDDEN;
+}
+__host__ __device__ __forceinline__ int net_off_c(int S, int B) {
+  return net_off_w2(S, B) + B * LSD_NET_HIDDEN;
+}
+__host__ __device__ __forceinline__ int net_params(int S, int B) {
+  return net_off_c(S, B) + S * (S + 1) / 2 * B;
+}
 
 // index of the unordered species pair {a, b} among S(S+1)/2 types
 __host__ __device__ __forceinline__ int pair_type(int a, int b, int S) {
@@ -349,6 +371,57 @@ __device__ __forceinline__ void pair_draft_force(const PotDev& P, float4 xi, flo
   fz -= g * dz;
 }
 
+// Radial functions of the learned draft, e_b(r) = f_c(r) sin(b pi r/rc)/r
+// for b = 1..B, by the same recurrence; entries from B on are 0.
+__device__ __forceinline__ void net_radial(float pi_rc, float r, float inv_r, int B,
+                                           float e[LSD_NET_MAX_BASIS]) {
+  float s, c;
+  sincosf(pi_rc * r, &s, &c);
+  const float g0 = 0.5f * (c + 1.0f) * inv_r;
+  float prev = 0.0f, cur = s;
+  const float two_c = 2.0f * c;
+#pragma unroll
+  for (int b = 0; b < LSD_NET_MAX_BASIS; ++b) {
+    if (b < B) {
+      if (b > 0) {
+        const float nx = two_c * cur - prev;
+        prev = cur;
+        cur = nx;
+      }
+      e[b] = g0 * cur;
+    } else {
+      e[b] = 0.0f;
+    }
+  }
+}
+
+// Edge coefficients of one atom (first B of its LSD_NET_MAX_BASIS slots).
+__device__ __forceinline__ void net_load_v(const float* __restrict__ v, int B,
+                                           float out[LSD_NET_MAX_BASIS]) {
+  const float4* v4 = reinterpret_cast<const float4*>(v);
+#pragma unroll
+  for (int q = 0; q < LSD_NET_MAX_BASIS / 4; ++q) {
+    float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (4 * q < B) t = v4[q];
+    out[4 * q] = t.x;
+    out[4 * q + 1] = t.y;
+    out[4 * q + 2] = t.z;
+    out[4 * q + 3] = t.w;
+  }
+}
+
+// Learned-draft pair coefficient f_ij = sum_b e_b (c_t[b] + v_i[b] + v_j[b]).
+__device__ __forceinline__ float net_pair_coef(const float e[LSD_NET_MAX_BASIS],
+                                               const float* __restrict__ ct,
+                                               const float vi[LSD_NET_MAX_BASIS],
+                                               const float vj[LSD_NET_MAX_BASIS], int B) {
+  float f = 0.0f;
+#pragma unroll
+  for (int b = 0; b < LSD_NET_MAX_BASIS; ++b)
+    if (b < B) f += e[b] * ((ct[b] + vi[b]) + vj[b]);
+  return f;
+}
+
 // per image code: sj = min(n,0) L, si = max(n,0) L for x, y, z
 __device__ __forceinline__ void image_shifts(int code, float Lf, float sj[3], float si[3]) {
   const int n[3] = {code_nx(code), code_ny(code), code_nz(code)};
@@ -357,6 +430,56 @@ __device__ __forceinline__ void image_shifts(int code, float Lf, float sj[3], fl
     sj[a] = n[a] < 0 ? -Lf : 0.0f;
     si[a] = n[a] > 0 ? Lf : 0.0f;
   }
+}
+
+// sum over the LSD_LPA lanes of an atom by a fixed butterfly
+__device__ __forceinline__ float lpa_sum(float v) {
+#pragma unroll
+  for (int o = 1; o < LSD_LPA; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Learned-draft force on atom i (replica r) at frame positions X from its
+// list row: F_i = - sum_j f_ij d / r with the edge coefficients P.v of this
+// frame; the LSD_LPA lanes of the atom split the row as in every force loop
+// and the result is their fixed butterfly sum.
+__device__ __forceinline__ void net_force(const PotDev& P, const SysDev& S,
+                                          const float4* __restrict__ X,
+                                          const uint32_t* __restrict__ row, int cnt, int i, int r,
+                                          int sub, float& fx, float& fy, float& fz) {
+  fx = fy = fz = 0.0f;
+  const float Lf = (float)S.box[r];
+  const float4 xi = X[i];
+  const int spi = S.species ? S.species[i] : 0;
+  const int B = P.nb;
+  float vi[LSD_NET_MAX_BASIS];
+  net_load_v(P.v + (size_t)i * LSD_NET_MAX_BASIS, B, vi);
+  const float* cw = P.w + net_off_c(P.ns, B);
+  for (int m = sub; m < cnt; m += LSD_LPA) {
+    const uint32_t ent = row[m];
+    const int j = (int)(ent >> 5), code = (int)(ent & 31u);
+    const float4 xj = X[j];
+    float sj[3], si[3];
+    image_shifts(code, Lf, sj, si);
+    const float dx = sep(xj.x, sj[0], xi.x, si[0]);
+    const float dy = sep(xj.y, sj[1], xi.y, si[1]);
+    const float dz = sep(xj.z, sj[2], xi.z, si[2]);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 >= P.rc2) continue;
+    const float rr = sqrtf(r2);
+    const float inv_r = 1.0f / rr;
+    float eb[LSD_NET_MAX_BASIS], vj[LSD_NET_MAX_BASIS];
+    net_radial(P.pi_rc, rr, inv_r, B, eb);
+    net_load_v(P.v + (size_t)j * LSD_NET_MAX_BASIS, B, vj);
+    const float* ct = cw + pair_type(spi, S.species ? S.species[j] : 0, P.ns) * B;
+    const float g = net_pair_coef(eb, ct, vi, vj, B) * inv_r;
+    fx -= g * dx;
+    fy -= g * dy;
+    fz -= g * dz;
+  }
+  fx = lpa_sum(fx);
+  fy = lpa_sum(fy);
+  fz = lpa_sum(fz);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -320,12 +320,6 @@ __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev 
   }
 }
 
-__device__ __forceinline__ float lpa_sum(float v) {
-#pragma unroll
-  for (int o = 1; o < LSD_LPA; o <<= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // Force of potential P on atom i at frame positions X.  The LSD_LPA lanes of
 // an atom share the list row: lane `sub` sums the entries m = sub, sub + LPA,
 // ... in order, and the partial sums are combined by the fixed butterfly of
@@ -374,6 +368,8 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
     fx = lpa_sum(fx);
     fy = lpa_sum(fy);
     fz = lpa_sum(fz);
+  } else if (P.kind == LSD_POT_NET) {
+    net_force(P, S, X, row, cnt, i, r, sub, fx, fy, fz);
   } else if (P.kind == LSD_POT_HARMONIC) {
     float d[3] = {xi.x - P.anchor[i], xi.y - P.anchor[S.n + i], xi.z - P.anchor[2 * S.n + i]};
 #pragma unroll

@@ -16,7 +16,9 @@ LIB_PATH = os.path.join(HERE, "liblsd.so")
 
 LSD_OK = 0
 MODE_LSD, MODE_PLAIN = 0, 1
-POT_LJ, POT_HARMONIC, POT_MPNN, POT_PAIR = 1, 2, 3, 4
+POT_LJ, POT_HARMONIC, POT_MPNN, POT_PAIR, POT_NET = 1, 2, 3, 4, 5
+PREC_FP32, PREC_BF16 = 0, 1
+NET_HIDDEN = 32
 STATUS_NBR_TARGET, STATUS_NBR_DRAFT, STATUS_CELL = 1, 2, 4
 
 _LIB = None
@@ -36,7 +38,7 @@ class Potential(C.Structure):
                 ("sigma", C.c_double), ("k_spring", C.c_double), ("anchor", C.c_void_p),
                 ("force_offset", C.c_void_p), ("weights", C.c_void_p),
                 ("n_model_species", C.c_int32), ("energy_scale", C.c_double),
-                ("n_basis", C.c_int32)]
+                ("n_basis", C.c_int32), ("precision", C.c_int32)]
 
 
 class Config(C.Structure):
@@ -97,6 +99,12 @@ EXPORTS = {
     "lsd_fit_pair_solve": ([C.c_void_p, C.c_int32, C.c_double, C.c_void_p], C.c_int),
     "lsd_autotune_verify": ([C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                              C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "lsd_net_param_count": ([C.c_int32, C.c_int32], C.c_int32),
+    "lsd_net_train_scratch_size": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
+    "lsd_net_train_accumulate": ([C.c_void_p, C.POINTER(Potential), C.c_int32, C.c_void_p,
+                                  C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
+    "lsd_net_adam_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
+                           C.c_double, C.c_double, C.c_double, C.c_int64, C.c_void_p], C.c_int),
     "lsd_destroy": ([C.c_void_p], C.c_int),
     "lsd_last_error": ([], C.c_char_p),
 }
@@ -129,6 +137,37 @@ def _stream(torch):
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def net_param_count(n_species, n_basis):
+    """Length of the learned draft's parameter vector (0 if out of range)."""
+    return int(load().lsd_net_param_count(int(n_species), int(n_basis)))
+
+
+def net_init_params(n_species, n_basis, pair_weights=None, seed=0, gain=1.0):
+    """Initial parameters of the learned draft (float32 numpy): W1 with
+    N(0, gain^2 / (S B)) entries, b1 = 0, W2 = 0 and c = the pair-draft
+    weights (or 0), so the draft starts as that pair draft."""
+    S, B, H = int(n_species), int(n_basis), NET_HIDDEN
+    P = net_param_count(S, B)
+    if P == 0:
+        raise ValueError("learned draft size out of range")
+    rng = np.random.default_rng(seed)
+    p = np.zeros(P, np.float64)
+    p[:H * S * B] = rng.normal(scale=gain / np.sqrt(S * B), size=H * S * B)
+    if pair_weights is not None:
+        p[P - S * (S + 1) // 2 * B:] = np.asarray(pair_weights, dtype=np.float64).ravel()
+    return p.astype(np.float32)
+
+
+def net_adam_step(torch, params, m, v, grad, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step of lsd_net_adam_step on CUDA tensors: params float32
+    [P], m and v float64 [P], grad float64 [P+2] (cleared by the step)."""
+    P = params.numel()
+    assert m.numel() == P and v.numel() == P and grad.numel() >= P + 2
+    _check(load().lsd_net_adam_step(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), P, float(lr),
+                                    float(beta1), float(beta2), float(eps), int(t),
+                                    _stream(torch)), "lsd_net_adam_step")
 
 
 def pair_params(n_species, n_basis):
@@ -276,6 +315,16 @@ class LSDSystem:
             P.weights = wt.data_ptr()
             P.n_model_species = int(d.get("n_model_species", len(self._masses)))
             P.n_basis = int(d["n_basis"])
+        elif kind == "net":
+            wt = d.get("weights")
+            if wt is None:
+                raise ValueError("the learned draft needs parameters (net_init_params)")
+            if not (hasattr(wt, "is_cuda") and wt.is_cuda):
+                wt = t.tensor(np.asarray(wt, dtype=np.float64).ravel(), dtype=t.float32,
+                              device="cuda").contiguous()
+            # a CUDA float32 tensor is used in place: training may update it
+            self._keep.append(wt)
+            self._net_fields(P, d, wt)
         else:
             raise ValueError(f"potential kind {kind!r} is not implemented by the library")
         if d.get("offset") is not None:
@@ -325,6 +374,36 @@ class LSDSystem:
                                               _ptr(scratch),
                                               scratch.numel(), _ptr(gram), _stream(t)),
                "lsd_fit_pair_accumulate")
+        return scratch
+
+    def _net_fields(self, P, d, wt):
+        t = self.torch
+        if wt.dtype != t.float32 or not wt.is_contiguous() or not wt.is_cuda:
+            raise ValueError("learned-draft parameters must be a contiguous float32 CUDA tensor")
+        P.kind, P.cutoff = POT_NET, float(d["rc"])
+        P.weights = wt.data_ptr()
+        P.n_model_species = int(d.get("n_model_species", len(self._masses)))
+        P.n_basis = int(d["n_basis"])
+        P.precision = {"fp32": PREC_FP32, "bf16": PREC_BF16}[d.get("precision", "bf16")]
+
+    # --- training of the learned draft -------------------------------------------
+    def net_train_accumulate(self, net, grad, use_target=False, scratch=None):
+        """Add the gradient of the summed squared force error of the learned
+        draft `net` (a potential dict of kind "net") over the current
+        window's valid frames to `grad` (float64 CUDA [P+2]: gradient,
+        squared error, atom frames); net["weights"] must be the float32 CUDA
+        parameter tensor.  Returns the scratch tensor (reuse it)."""
+        t = self.torch
+        nb = C.c_size_t()
+        _check(load().lsd_net_train_scratch_size(self.h, C.byref(nb)),
+               "lsd_net_train_scratch_size")
+        if scratch is None or scratch.numel() < nb.value:
+            scratch = t.empty((max(nb.value, 8),), dtype=t.uint8, device="cuda")
+        P = Potential()
+        self._net_fields(P, net, net["weights"])   # the caller owns the CUDA parameters
+        _check(load().lsd_net_train_accumulate(self.h, C.byref(P), 1 if use_target else 0,
+                                               _ptr(scratch), scratch.numel(), _ptr(grad),
+                                               _stream(t)), "lsd_net_train_accumulate")
         return scratch
 
     # --- inspection -------------------------------------------------------------

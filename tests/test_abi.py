@@ -129,3 +129,20 @@ def test_fit_pair_solve_matches_least_squares(lib):
     with pytest.raises(lsd.LSDError):
         lsd.fit_pair_solve(Ae.T @ Ae, ridge=0.0)
     assert np.isfinite(lsd.fit_pair_solve(Ae.T @ Ae, ridge=1e-8)).all()
+
+
+def test_net_parameter_layout(lib, ora):
+    # host-only: the parameter count agrees with the oracle's layout, sizes
+    # outside the supported range give 0, and the initial parameters are the
+    # pair draft (W2 = 0, c = pair weights)
+    from oracle.net import NetDraft
+    from paper_2606_02455_amd import lsd
+    for S, B in ((1, 1), (3, 8), (2, 16), (4, 8)):
+        assert lsd.net_param_count(S, B) == NetDraft.count(S, B)
+    for S, B in ((0, 8), (5, 4), (3, 16), (1, 17)):
+        assert lsd.net_param_count(S, B) == 0
+    pw = np.arange(6 * 8, dtype=np.float64)
+    p = lsd.net_init_params(3, 8, pair_weights=pw, seed=2)
+    W1, b1, W2, c = NetDraft(3, 8, 4.0, p.astype(np.float64)).split()
+    assert np.all(W2 == 0) and np.all(b1 == 0) and np.array_equal(c.ravel(), pw)
+    assert np.std(W1) > 0.1
