@@ -15,6 +15,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -170,6 +171,38 @@ def run_c3(args, lsd, W, torch):
     if plain.status():
         raise RuntimeError(f"device status {plain.status()} during plain stepping")
     draft = dict(kind="pair", rc=rc_d, weights=wts, n_basis=nb, n_model_species=3)
+    train = None
+    if args.draft == "net":
+        # the learned draft: starts as the fitted pair draft (edge weights 0)
+        # and is trained with Adam on the force changes between consecutive
+        # frames of the plain target trajectory, one step per window
+        Pn = lsd.net_param_count(3, nb)
+        pt = torch.tensor(lsd.net_init_params(3, nb, pair_weights=wts, seed=w.seed),
+                          dtype=torch.float32, device="cuda")
+        net = dict(kind="net", rc=rc_d, weights=pt, n_basis=nb, n_model_species=3,
+                   precision=args.net_precision)
+        grad = torch.zeros(Pn + 2, dtype=torch.float64, device="cuda")
+        m1 = torch.zeros(Pn, dtype=torch.float64, device="cuda")
+        m2 = torch.zeros(Pn, dtype=torch.float64, device="cuda")
+        scratch_t, mse = None, []
+        t0 = time.perf_counter()
+        n_train = args.net_train_windows
+        for step in range(1, n_train + 1):
+            plain.draft_steps(K)
+            scratch_t = plain.net_train_accumulate(net, grad, scratch=scratch_t, differences=True)
+            plain.accept_rollback()
+            if step == 1 or step == n_train:
+                torch.cuda.synchronize()
+                mse.append(grad[Pn].item() / (3.0 * max(grad[Pn + 1].item(), 1.0)))
+            lr = args.net_lr * 0.5 * (1.0 + math.cos(math.pi * step / n_train))
+            lsd.net_adam_step(torch, pt, m1, m2, grad, lr, step)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        log(f"trained the learned draft ({Pn} parameters) on {n_train * K} target frames in "
+            f"{t_train:.1f} s; force-change MSE {mse[0]:.3g} -> {mse[-1]:.3g} (eV/A)^2")
+        draft = net
+        train = dict(windows=n_train, frames=n_train * K, seconds=round(t_train, 2),
+                     mse_first=mse[0], mse_last=mse[-1], parameters=Pn)
     g = lsd.LSDSystem(w, mode="lsd", target=target, draft=draft,
                       error_correction=EC_MODES[args.ec])
     for a, b in ((g.q, plain.q), (g.p, plain.p), (g.img, plain.img), (g.step, plain.step)):
@@ -219,11 +252,15 @@ def run_c3(args, lsd, W, torch):
             "workload": (f"{w.name}: triatomic liquid, {N} atoms in {w.n_replicas} system(s), 300 K, "
                          f"dt {dt_fs} fs, gamma {w.gamma}/fs, K={K}; target: seeded "
                          f"message-passing network (3 layers, hidden 128, 16 Bessel, rc 5 A); "
-                         f"draft: pair forces (rc {rc_d} A, {nb} basis) force-matched "
+                         + (f"draft: learned one-layer direct-force network (hidden 32, rc {rc_d} A, "
+                            f"{nb} radial functions, {args.net_precision} node pass) initialised "
+                            f"from the pair draft and trained on {train['frames'] if train else 0} "
+                            f"target frames; " if args.draft == "net" else "")
+                         + f"pair draft: pair forces (rc {rc_d} A, {nb} basis) force-matched "
                          f"(frame-to-frame differences) on {fit_windows * K} target frames; "
                          f"error correction {args.ec}"),
             "n_atoms": N, "K": K, "fit_frames": fit_windows * K,
-            "error_correction": args.ec},
+            "draft": args.draft, "error_correction": args.ec},
         "acceptance": round(1.0 - rejections / max(committed, 1), 5),
         "committed_per_window": round(committed / windows, 4),
         "plain_steps_per_s": round(plain_rate, 3),
@@ -231,6 +268,7 @@ def run_c3(args, lsd, W, torch):
         "ns_per_day_lsd": round(value * dt_fs * 1e-6 * 86400.0, 4),
         "ns_per_day_plain": round(plain_rate * dt_fs * 1e-6 * 86400.0, 4),
         "fit_seconds": round(t_fit, 2),
+        "draft_training": train,
         "roofline": dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                          frac=round(achieved / peak, 5), traffic=None,
                          kernel="message-passing target evaluation (all frames of a window)",
@@ -247,9 +285,18 @@ def main():
     ap.add_argument("--steps", type=int, default=200, help="timed windows")
     ap.add_argument("--warmup", type=int, default=20, help="untimed windows")
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
-    ap.add_argument("--fit-frames", type=int, default=20000,
-                    help="c3: target frames for force matching of the pair draft")
-    ap.add_argument("--pair-basis", type=int, default=16, help="c3: pair-draft basis size")
+    ap.add_argument("--fit-frames", type=int, default=None,
+                    help="c3/c4: target frames for force matching of the pair draft "
+                         "(default 20000 for c3, 2000 whole-system frames of 256 replicas for c4)")
+    ap.add_argument("--pair-basis", type=int, default=16,
+                    help="c3/c4: radial functions of the pair and learned drafts")
+    ap.add_argument("--draft", choices=["net", "pair"], default="net",
+                    help="c3/c4: the learned draft (trained from the pair draft) or the pair draft")
+    ap.add_argument("--net-precision", choices=["bf16", "fp32"], default="bf16")
+    ap.add_argument("--net-train-windows", type=int, default=None,
+                    help="c3/c4: Adam steps, one window of K target frames each "
+                         "(default 2000 for c3, 500 for c4)")
+    ap.add_argument("--net-lr", type=float, default=3e-3)
     ap.add_argument("--equilibrate", type=int, default=256, help="plain steps before timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -258,6 +305,10 @@ def main():
                          "extrapolated from the last two committed errors; auto: the better "
                          "measured setting of the configuration (c1, c2: on; c3: linear)")
     args = ap.parse_args()
+    if args.fit_frames is None:
+        args.fit_frames = 2000 if args.config == "c4" else 20000
+    if args.net_train_windows is None:
+        args.net_train_windows = 500 if args.config == "c4" else 2000
     if args.ec == "auto":
         args.ec = "linear" if args.config in ("c3", "c4") else "on"
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -129,7 +129,7 @@ typedef enum {
  * bfloat16 and binary32 accumulation (pair terms are binary32 either way). */
 #define LSD_NET_HIDDEN 32
 #define LSD_NET_MAX_BASIS 16
-#define LSD_NET_MAX_DESC 32
+#define LSD_NET_MAX_DESC 64
 #define LSD_NET_MAX_SPECIES 4
 typedef enum { LSD_PREC_FP32 = 0, LSD_PREC_BF16 = 1 } lsd_precision;
 
@@ -410,7 +410,11 @@ LSD_API lsd_status lsd_fit_pair_solve(const double *gram, int32_t n_params, doub
  * cutoff <= the target cutoff: the target list is used), evaluated in
  * binary32 (whatever net->precision says) and reduced in binary64 in a fixed
  * order:  grad[0..P) += gradient, grad[P] += the squared error, grad[P+1] +=
- * the number of atom frames.  grad: device binary64 [P+2], zeroed by the
+ * the number of atom frames.  differences != 0: the loss is instead the
+ * squared error of the force changes between consecutive valid frames,
+ * sum_k |(F_k+1 - F_k) - (y_k+1 - y_k)|^2, the part of the draft's error
+ * that error correction (App. D) leaves, and grad[P+1] counts atom
+ * differences.  grad: device binary64 [P+2], zeroed by the
  * caller before the first call.  scratch: device memory of
  * lsd_net_train_scratch_size bytes.  Asynchronous.  Errors: INVALID_ARG,
  * BAD_STATE (no drafted window), CAPACITY, HIP.
@@ -425,7 +429,8 @@ LSD_API lsd_status lsd_fit_pair_solve(const double *gram, int32_t n_params, doub
 LSD_API int32_t lsd_net_param_count(int32_t n_species, int32_t n_basis);
 LSD_API lsd_status lsd_net_train_scratch_size(const lsd_system *sys, size_t *bytes);
 LSD_API lsd_status lsd_net_train_accumulate(lsd_system *sys, const lsd_potential *net,
-                                            int32_t use_target_forces, void *scratch,
+                                            int32_t use_target_forces, int32_t differences,
+                                            void *scratch,
                                             size_t scratch_bytes, double *grad,
                                             lsd_stream stream);
 LSD_API lsd_status lsd_net_adam_step(float *params, double *m, double *v, double *grad,

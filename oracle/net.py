@@ -19,6 +19,8 @@ def declare(L):
     L.ora_net_sse_grad.argtypes = [C.c_int, _dp, C.c_double, _ip, C.c_int, C.c_int, C.c_double,
                                    _dp, _dp, _dp]
     L.ora_net_sse_grad.restype = C.c_double
+    L.ora_net_backward.argtypes = [C.c_int, _dp, C.c_double, _ip, C.c_int, C.c_int, C.c_double,
+                                   _dp, _dp, _dp]
     L.ora_net_adam.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
                                C.c_double, C.c_long]
 
@@ -82,6 +84,33 @@ class NetDraft:
         g = np.zeros(self.P) if grad is None else grad
         sse = self.lib.ora_net_sse_grad(len(x), _p(x), float(L), sp.ctypes.data_as(_ip), self.S,
                                         self.B, self.rc, _p(self.params), _p(Y), _p(g))
+        return sse, g
+
+
+    def backward(self, species, x, L, G, grad):
+        """grad += sum_i G_i . dF_i/dparams (G [n, 3] = dLoss/dF)."""
+        x, sp = self._args(species, x)
+        G = np.ascontiguousarray(G, dtype=np.float64).reshape(-1, 3)
+        self.lib.ora_net_backward(len(x), _p(x), float(L), sp.ctypes.data_as(_ip), self.S, self.B,
+                                  self.rc, _p(self.params), _p(G), _p(grad))
+        return grad
+
+    def diff_sse_grad(self, species, frames, L, Ys, grad=None):
+        """Squared error of the force changes between consecutive frames,
+        sum_k |(F_{k+1} - F_k) - (Y_{k+1} - Y_k)|^2, and its gradient (added
+        to `grad` when given)."""
+        g = np.zeros(self.P) if grad is None else grad
+        F = [self.forces(species, x, L) for x in frames]
+        Y = [np.asarray(y, dtype=np.float64).reshape(-1, 3) for y in Ys]
+        d = [(F[k + 1] - F[k]) - (Y[k + 1] - Y[k]) for k in range(len(F) - 1)]
+        sse = float(sum(np.sum(dk * dk) for dk in d))
+        for k, x in enumerate(frames):
+            G = np.zeros_like(F[k])
+            if k >= 1:
+                G += 2.0 * d[k - 1]
+            if k + 1 < len(F):
+                G -= 2.0 * d[k]
+            self.backward(species, x, L, G, g)
         return sse, g
 
 

@@ -28,8 +28,9 @@
  * Force matching minimises the squared error of all force components against
  * reference forces Y; ora_net_sse_grad returns sum |F - Y|^2 over one frame
  * and adds its gradient in the parameters, by the chain rule through the
- * forward pass above, term by term.  ora_net_adam is one step of Adam
- * (Kingma and Ba, 2015) with bias-corrected moments.
+ * forward pass above, term by term (ora_net_backward: the same chain rule
+ * for any loss whose derivative in the forces is given).  ora_net_adam is
+ * one step of Adam (Kingma and Ba, 2015) with bias-corrected moments.
  */
 #include <math.h>
 #include <stdint.h>
@@ -144,41 +145,15 @@ void ora_net_forward(int n, const double *x, double L, const int32_t *sp, int S,
   free(rec);
 }
 
-/* returns sum_i |F_i - Y_i|^2 and adds its gradient to grad[P] */
-double ora_net_sse_grad(int n, const double *x, double L, const int32_t *sp, int S, int B,
-                        double rc, const double *params, const double *Y, double *grad) {
+/* adds sum_i G_i . dF_i/dtheta to grad[P] (G [n][3] = dLoss/dF) */
+static void backprop(int n, const double *x, double L, const int32_t *sp, int S, int B, double rc,
+                     Params w, const int32_t *rec, long np, const double *D, const double *z,
+                     const double *G, double *grad) {
   const int Din = S * B;
-  Params w = unpack(params, S, B);
   double *gW1 = grad, *gb1 = gW1 + NET_H * Din, *gW2 = gb1 + S * NET_H, *gc = gW2 + B * NET_H;
-  int32_t *rec;
-  long np = records(n, x, L, rc, &rec);
-  double *D = (double *)malloc(sizeof(double) * (size_t)n * Din + 8);
-  double *z = (double *)malloc(sizeof(double) * (size_t)n * NET_H + 8);
-  double *v = (double *)malloc(sizeof(double) * (size_t)n * B + 8);
-  double *F = (double *)calloc(3 * (size_t)n + 1, sizeof(double));
-  double *G = (double *)malloc(sizeof(double) * (3 * (size_t)n + 1));
   double *dv = (double *)calloc((size_t)n * B + 1, sizeof(double));
-  nodes(n, x, L, sp, S, B, rc, w, rec, np, D, z, v);
   double e[64];
-  /* forward forces */
-  for (long p = 0; p < np; ++p) {
-    const int32_t *q = &rec[5 * p];
-    double d[3], r;
-    geometry(x, L, q, d, &r);
-    radial(r, rc, B, e);
-    const double *ct = w.c + (size_t)ora_pair_type(sp[q[0]], sp[q[1]], S) * B;
-    double f = 0.0;
-    for (int b = 0; b < B; ++b) f += e[b] * (ct[b] + v[(size_t)q[0] * B + b] + v[(size_t)q[1] * B + b]);
-    for (int a = 0; a < 3; ++a) F[3 * q[0] + a] -= f * d[a] / r;
-  }
-  /* loss and dSSE/dF */
-  double sse = 0.0;
-  for (size_t k = 0; k < 3 * (size_t)n; ++k) {
-    double res = F[k] - Y[k];
-    sse += res * res;
-    G[k] = 2.0 * res;
-  }
-  /* each pair term -f d / r of F_i: dSSE/df = -G_i . d / r, and f depends
+  /* each pair term -f d / r of F_i: dLoss/df = -G_i . d / r, and f depends
    * on c[t], v_i and v_j with coefficient e_b */
   for (long p = 0; p < np; ++p) {
     const int32_t *q = &rec[5 * p];
@@ -211,13 +186,42 @@ double ora_net_sse_grad(int n, const double *x, double L, const int32_t *sp, int
       for (int k = 0; k < Din; ++k) gW1[h * Din + k] += dz * D[(size_t)i * Din + k];
     }
   }
+  free(dv);
+}
+
+/* adds sum_i G_i . dF_i/dtheta (G [n][3]) to grad[P]: the gradient of any
+ * loss of the forces whose derivative in F is G */
+void ora_net_backward(int n, const double *x, double L, const int32_t *sp, int S, int B, double rc,
+                      const double *params, const double *G, double *grad) {
+  Params w = unpack(params, S, B);
+  int32_t *rec;
+  long np = records(n, x, L, rc, &rec);
+  double *D = (double *)malloc(sizeof(double) * (size_t)n * S * B + 8);
+  double *z = (double *)malloc(sizeof(double) * (size_t)n * NET_H + 8);
+  double *v = (double *)malloc(sizeof(double) * (size_t)n * B + 8);
+  nodes(n, x, L, sp, S, B, rc, w, rec, np, D, z, v);
+  backprop(n, x, L, sp, S, B, rc, w, rec, np, D, z, G, grad);
   free(D);
   free(z);
   free(v);
+  free(rec);
+}
+
+/* returns sum_i |F_i - Y_i|^2 and adds its gradient to grad[P] */
+double ora_net_sse_grad(int n, const double *x, double L, const int32_t *sp, int S, int B,
+                        double rc, const double *params, const double *Y, double *grad) {
+  double *F = (double *)malloc(sizeof(double) * (3 * (size_t)n + 1));
+  double *G = (double *)malloc(sizeof(double) * (3 * (size_t)n + 1));
+  ora_net_forward(n, x, L, sp, S, B, rc, params, NULL, NULL, NULL, F);
+  double sse = 0.0;
+  for (size_t k = 0; k < 3 * (size_t)n; ++k) {
+    double res = F[k] - Y[k];
+    sse += res * res;
+    G[k] = 2.0 * res;
+  }
+  ora_net_backward(n, x, L, sp, S, B, rc, params, G, grad);
   free(F);
   free(G);
-  free(dv);
-  free(rec);
   return sse;
 }
 

@@ -1005,8 +1005,8 @@ lsd_status lsd_net_train_scratch_size(const lsd_system* s, size_t* bytes) {
 }
 
 lsd_status lsd_net_train_accumulate(lsd_system* s, const lsd_potential* net,
-                                    int32_t use_target_forces, void* scratch, size_t scratch_bytes,
-                                    double* grad, lsd_stream stream) {
+                                    int32_t use_target_forces, int32_t differences, void* scratch,
+                                    size_t scratch_bytes, double* grad, lsd_stream stream) {
   if (!s || !net || !scratch || !grad) return fail(LSD_ERR_INVALID_ARG, "null argument");
   if (net->kind != LSD_POT_NET) return fail(LSD_ERR_INVALID_ARG, "not a learned draft");
   LSD_TRY(check_potential(*net, "learned draft"));
@@ -1028,8 +1028,8 @@ lsd_status lsd_net_train_accumulate(lsd_system* s, const lsd_potential* net,
   copy.precision = LSD_PREC_FP32;
   PotDev P = make_pot(copy, s->lay);
   const NetTrainDev T = net_train_bind(static_cast<char*>(scratch), s->cfg.k_max, s->cfg.n_atoms);
-  HIP_TRY(launch_net_train(s->S, s->Lst, s->W, P, T, use_target_forces ? 1 : 0, grad,
-                           static_cast<hipStream_t>(stream)));
+  HIP_TRY(launch_net_train(s->S, s->Lst, s->W, P, T, use_target_forces ? 1 : 0,
+                           differences ? 1 : 0, grad, static_cast<hipStream_t>(stream)));
   return LSD_OK;
 }
 

@@ -26,7 +26,7 @@
 #define LSD_POT_NET 5
 #define LSD_NET_HIDDEN 32     // hidden units of the learned draft
 #define LSD_NET_MAX_BASIS 16  // radial functions (edge coefficients per atom, v stride)
-#define LSD_NET_MAX_DESC 32   // species x radial functions of the descriptor
+#define LSD_NET_MAX_DESC 64   // species x radial functions of the descriptor
 #define LSD_NET_MAX_SPECIES 4
 
 // status word bits
@@ -432,6 +432,35 @@ __device__ __forceinline__ void image_shifts(int code, float Lf, float sj[3], fl
   }
 }
 
+// List entries of one lane whose loads are issued together in the draft-side
+// force loops: the row entries, then the neighbour positions and species,
+// so that the gathers of several entries are in flight at once.  Entries are
+// still added in the lane's order.
+#define LSD_GATHER 4
+struct Gathered {
+  float4 x[LSD_GATHER];
+  int code[LSD_GATHER], j[LSD_GATHER], sp[LSD_GATHER];
+  bool ok[LSD_GATHER];
+};
+__device__ __forceinline__ void gather_entries(const uint32_t* __restrict__ row, int cnt, int m0,
+                                               const float4* __restrict__ X,
+                                               const int* __restrict__ species, Gathered& g) {
+  uint32_t ent[LSD_GATHER];
+#pragma unroll
+  for (int u = 0; u < LSD_GATHER; ++u) {
+    const int m = m0 + u * LSD_LPA;
+    g.ok[u] = m < cnt;
+    ent[u] = row[g.ok[u] ? m : m0];
+  }
+#pragma unroll
+  for (int u = 0; u < LSD_GATHER; ++u) {
+    g.j[u] = (int)(ent[u] >> 5);
+    g.code[u] = (int)(ent[u] & 31u);
+    g.x[u] = X[g.j[u]];
+    g.sp[u] = species ? species[g.j[u]] : 0;
+  }
+}
+
 // sum over the LSD_LPA lanes of an atom by a fixed butterfly
 __device__ __forceinline__ float lpa_sum(float v) {
 #pragma unroll
@@ -455,27 +484,30 @@ __device__ __forceinline__ void net_force(const PotDev& P, const SysDev& S,
   float vi[LSD_NET_MAX_BASIS];
   net_load_v(P.v + (size_t)i * LSD_NET_MAX_BASIS, B, vi);
   const float* cw = P.w + net_off_c(P.ns, B);
-  for (int m = sub; m < cnt; m += LSD_LPA) {
-    const uint32_t ent = row[m];
-    const int j = (int)(ent >> 5), code = (int)(ent & 31u);
-    const float4 xj = X[j];
-    float sj[3], si[3];
-    image_shifts(code, Lf, sj, si);
-    const float dx = sep(xj.x, sj[0], xi.x, si[0]);
-    const float dy = sep(xj.y, sj[1], xi.y, si[1]);
-    const float dz = sep(xj.z, sj[2], xi.z, si[2]);
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 >= P.rc2) continue;
-    const float rr = sqrtf(r2);
-    const float inv_r = 1.0f / rr;
-    float eb[LSD_NET_MAX_BASIS], vj[LSD_NET_MAX_BASIS];
-    net_radial(P.pi_rc, rr, inv_r, B, eb);
-    net_load_v(P.v + (size_t)j * LSD_NET_MAX_BASIS, B, vj);
-    const float* ct = cw + pair_type(spi, S.species ? S.species[j] : 0, P.ns) * B;
-    const float g = net_pair_coef(eb, ct, vi, vj, B) * inv_r;
-    fx -= g * dx;
-    fy -= g * dy;
-    fz -= g * dz;
+  for (int m0 = sub; m0 < cnt; m0 += LSD_GATHER * LSD_LPA) {
+    Gathered gt;
+    gather_entries(row, cnt, m0, X, S.species, gt);
+#pragma unroll
+    for (int u = 0; u < LSD_GATHER; ++u) {
+      if (!gt.ok[u]) break;
+      float sj[3], si[3];
+      image_shifts(gt.code[u], Lf, sj, si);
+      const float dx = sep(gt.x[u].x, sj[0], xi.x, si[0]);
+      const float dy = sep(gt.x[u].y, sj[1], xi.y, si[1]);
+      const float dz = sep(gt.x[u].z, sj[2], xi.z, si[2]);
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 >= P.rc2) continue;
+      const float rr = sqrtf(r2);
+      const float inv_r = 1.0f / rr;
+      float eb[LSD_NET_MAX_BASIS], vj[LSD_NET_MAX_BASIS];
+      net_radial(P.pi_rc, rr, inv_r, B, eb);
+      net_load_v(P.v + (size_t)gt.j[u] * LSD_NET_MAX_BASIS, B, vj);
+      const float* ct = cw + pair_type(spi, gt.sp[u], P.ns) * B;
+      const float g = net_pair_coef(eb, ct, vi, vj, B) * inv_r;
+      fx -= g * dx;
+      fy -= g * dy;
+      fz -= g * dz;
+    }
   }
   fx = lpa_sum(fx);
   fy = lpa_sum(fy);

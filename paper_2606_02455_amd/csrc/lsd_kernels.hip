@@ -357,13 +357,16 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
     e = lpa_sum(e);
   } else if (P.kind == LSD_POT_PAIR) {
     const int spi = S.species ? S.species[i] : 0;
-    for (int m = sub; m < cnt; m += LSD_LPA) {
-      const uint32_t ent = row[m];
-      const int j = (int)(ent >> 5), code = (int)(ent & 31u);
-      const float4 xj = X[j];
-      float sj[3], si[3];
-      image_shifts(code, Lf, sj, si);
-      pair_draft_force(P, xi, xj, sj, si, spi, S.species ? S.species[j] : 0, fx, fy, fz);
+    for (int m0 = sub; m0 < cnt; m0 += LSD_GATHER * LSD_LPA) {
+      Gathered gt;
+      gather_entries(row, cnt, m0, X, S.species, gt);
+#pragma unroll
+      for (int u = 0; u < LSD_GATHER; ++u) {
+        if (!gt.ok[u]) break;
+        float sj[3], si[3];
+        image_shifts(gt.code[u], Lf, sj, si);
+        pair_draft_force(P, xi, gt.x[u], sj, si, spi, gt.sp[u], fx, fy, fz);
+      }
     }
     fx = lpa_sum(fx);
     fy = lpa_sum(fy);

@@ -19,6 +19,7 @@ struct NetTrainDev {
   float* z;         // [K][N][LSD_NET_HIDDEN] pre-activations
   float* v;         // [K][N][LSD_NET_MAX_BASIS] edge coefficients
   float* G;         // [K][3][N] dSSE/dF
+  float* F;         // [K][3][N] forces (loss of force changes)
   double* partial;  // [K][nblk][NET_PROW]
   int nblk;
 };
@@ -31,9 +32,11 @@ hipError_t launch_net_nodes(const SysDev& S, const ListDev& L, const WinDev& W, 
                             int k, hipStream_t st);
 
 // grad[0..P) += d/dtheta sum |F - y|^2 over the window's valid frames,
-// grad[P] += the squared error, grad[P+1] += atom frames (target list).
+// grad[P] += the squared error, grad[P+1] += atom frames (target list);
+// diff: the loss of the changes between consecutive valid frames.
 hipError_t launch_net_train(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P,
-                            const NetTrainDev& T, int use_target, double* grad, hipStream_t st);
+                            const NetTrainDev& T, int use_target, int diff, double* grad,
+                            hipStream_t st);
 
 hipError_t launch_net_adam(float* params, double* m, double* v, double* grad, int n_params,
                            double lr, double beta1, double beta2, double eps, long long t,

@@ -5,15 +5,18 @@
 //   node pass: D_i = species-resolved radial descriptor over the draft list,
 //              h_i = silu(W1 D_i + b1[s_i]), v_i = W2 h_i;
 //   force:     F_i = - sum_j sum_b e_b(r) (c_t[b] + v_i[b] + v_j[b]) d / r.
-// The two dense layers are a [64 atoms x S B] x [S B x 32] and a
-// [64 x 32] x [32 x B] product per block: in bfloat16 they run on the
-// matrix cores (v_mfma_f32_16x16x16_bf16, one wave per 16 atoms, binary32
-// accumulation), in binary32 on the vector ALUs.
+// The two dense layers are a [16 atoms x S B] x [S B x 32] and a
+// [16 x 32] x [32 x B] product per block: in bfloat16 they run on the
+// matrix cores (v_mfma_f32_16x16x16_bf16, binary32 accumulation), in
+// binary32 on the vector ALUs.
 //
 // Training (force matching) runs in binary32 with binary64 reductions in a
 // fixed order, so gradients are deterministic:
 //   k_nt_nodes  descriptor, pre-activations z and v of every atom frame;
 //   k_nt_resid  forces and G = dSSE/dF = 2 (F - y), squared error per block;
+//               for the loss of force changes the forces are kept and
+//   k_nt_diff   forms delta_k = (F_k+1 - F_k) - (y_k+1 - y_k) and
+//               G_k = 2 (delta_k-1 - delta_k);
 //   k_nt_back   gamma_ij = (G_j - G_i) . d / r per list entry, the
 //               species-resolved sums Pc_i[s][b] = sum_{j in s} gamma_ij e_b,
 //               dv_i = sum_s Pc_i[s], dz_i = (W2^T dv_i) silu'(z_i), and per
@@ -27,6 +30,8 @@ static_assert(LSD_LPA >= 4 && LSD_NET_HIDDEN % LSD_LPA == 0,
 #define NET_THREADS (NET_ROWS * LSD_LPA)
 #define NET_HPL (LSD_NET_HIDDEN / LSD_LPA)   // hidden units per lane
 #define NET_DPL (LSD_NET_MAX_DESC / LSD_LPA) // descriptor slots per lane
+#define NET_IROWS 16                         // atoms per block of the drafting node pass
+#define NET_ITHREADS (NET_IROWS * LSD_LPA)
 
 namespace {
 
@@ -53,19 +58,19 @@ struct NetLds {
   float b1[LSD_NET_MAX_SPECIES][LSD_NET_HIDDEN];
 };
 
-__device__ __forceinline__ void load_weights(const PotDev& P, NetLds& L, int t) {
+__device__ __forceinline__ void load_weights(const PotDev& P, NetLds& L, int t, int nt) {
   const int S = P.ns, B = P.nb, Din = S * B;
   const float* w2 = P.w + net_off_w2(S, B);
   const float* b1 = P.w + net_off_b1(S, B);
-  for (int idx = t; idx < LSD_NET_HIDDEN * LSD_NET_MAX_DESC; idx += NET_THREADS) {
+  for (int idx = t; idx < LSD_NET_HIDDEN * LSD_NET_MAX_DESC; idx += nt) {
     const int h = idx / LSD_NET_MAX_DESC, d = idx % LSD_NET_MAX_DESC;
     L.W1[h][d] = d < Din ? P.w[h * Din + d] : 0.0f;
   }
-  for (int idx = t; idx < LSD_NET_MAX_BASIS * LSD_NET_HIDDEN; idx += NET_THREADS) {
+  for (int idx = t; idx < LSD_NET_MAX_BASIS * LSD_NET_HIDDEN; idx += nt) {
     const int b = idx / LSD_NET_HIDDEN, h = idx % LSD_NET_HIDDEN;
     L.W2[b][h] = b < B ? w2[b * LSD_NET_HIDDEN + h] : 0.0f;
   }
-  for (int idx = t; idx < LSD_NET_MAX_SPECIES * LSD_NET_HIDDEN; idx += NET_THREADS) {
+  for (int idx = t; idx < LSD_NET_MAX_SPECIES * LSD_NET_HIDDEN; idx += nt) {
     const int s = idx / LSD_NET_HIDDEN, h = idx % LSD_NET_HIDDEN;
     L.b1[s][h] = s < S ? b1[s * LSD_NET_HIDDEN + h] : 0.0f;
   }
@@ -85,25 +90,28 @@ __device__ __forceinline__ void net_descriptor(const PotDev& P, const SysDev& S,
   const float Lf = (float)S.box[r];
   const float4 xi = X[i];
   const int B = P.nb;
-  for (int m = sub; m < cnt; m += LSD_LPA) {
-    const uint32_t ent = row[m];
-    const int j = (int)(ent >> 5), code = (int)(ent & 31u);
-    const float4 xj = X[j];
-    float sj[3], si[3];
-    image_shifts(code, Lf, sj, si);
-    const float dx = sep(xj.x, sj[0], xi.x, si[0]);
-    const float dy = sep(xj.y, sj[1], xi.y, si[1]);
-    const float dz = sep(xj.z, sj[2], xi.z, si[2]);
-    const float r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 >= P.rc2) continue;
-    const float rr = sqrtf(r2);
-    float e[LSD_NET_MAX_BASIS];
-    net_radial(P.pi_rc, rr, 1.0f / rr, B, e);
-    const int spj = S.species ? S.species[j] : 0;
+  for (int m0 = sub; m0 < cnt; m0 += LSD_GATHER * LSD_LPA) {
+    Gathered gt;
+    gather_entries(row, cnt, m0, X, S.species, gt);
 #pragma unroll
-    for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s)
+    for (int u = 0; u < LSD_GATHER; ++u) {
+      if (!gt.ok[u]) break;
+      float sj[3], si[3];
+      image_shifts(gt.code[u], Lf, sj, si);
+      const float dx = sep(gt.x[u].x, sj[0], xi.x, si[0]);
+      const float dy = sep(gt.x[u].y, sj[1], xi.y, si[1]);
+      const float dz = sep(gt.x[u].z, sj[2], xi.z, si[2]);
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 >= P.rc2) continue;
+      const float rr = sqrtf(r2);
+      float e[LSD_NET_MAX_BASIS];
+      net_radial(P.pi_rc, rr, 1.0f / rr, B, e);
+      const int spj = gt.sp[u];
 #pragma unroll
-      for (int b = 0; b < LSD_NET_MAX_BASIS; ++b) D[s][b] += s == spj ? e[b] : 0.0f;
+      for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s)
+#pragma unroll
+        for (int b = 0; b < LSD_NET_MAX_BASIS; ++b) D[s][b] += s == spj ? e[b] : 0.0f;
+    }
   }
 #pragma unroll
   for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s)
@@ -142,111 +150,140 @@ __device__ __forceinline__ void store_v(float* __restrict__ dst, const float v[L
 }
 
 // Node pass of frame k for drafting: P.v[i] for every atom of a valid frame.
-template <int PREC>
-__global__ __launch_bounds__(NET_THREADS) void k_net_nodes(SysDev S, ListDev Lst, WinDev W,
-                                                           PotDev P, int k) {
+// Small blocks (NET_IROWS atoms, one wave) spread a frame of a small system
+// over many compute units; the pass is latency bound.
+__global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_f32(SysDev S, ListDev Lst, WinDev W,
+                                                                PotDev P, int k) {
   __shared__ NetLds L;
-  __shared__ float s_D[NET_ROWS][LSD_NET_MAX_DESC + 1];
-  __shared__ unsigned short s_Db[NET_ROWS][LSD_NET_MAX_DESC];
-  __shared__ unsigned short s_hb[NET_ROWS][LSD_NET_HIDDEN];
-  __shared__ unsigned short s_W1b[LSD_NET_HIDDEN][LSD_NET_MAX_DESC];
-  __shared__ unsigned short s_W2b[LSD_NET_MAX_BASIS][LSD_NET_HIDDEN];
-  __shared__ int s_sp[NET_ROWS], s_ok[NET_ROWS];
+  __shared__ float s_D[NET_IROWS][LSD_NET_MAX_DESC + 1];
   const int t = threadIdx.x, a = t / LSD_LPA, sub = t % LSD_LPA;
-  const int i0 = blockIdx.x * NET_ROWS + a;
+  const int i0 = blockIdx.x * NET_IROWS + a;
   const bool in = i0 < S.n;
   const int i = in ? i0 : S.n - 1;
   const int r = S.atom_rep[i];
   const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0;
   const int B = P.nb, Din = P.ns * B;
   const size_t N = (size_t)S.n;
-  load_weights(P, L, t);
-  if (PREC == 1) {
-    const float* w2 = P.w + net_off_w2(P.ns, B);
-    for (int idx = t; idx < LSD_NET_HIDDEN * LSD_NET_MAX_DESC; idx += NET_THREADS) {
-      const int h = idx / LSD_NET_MAX_DESC, d = idx % LSD_NET_MAX_DESC;
-      s_W1b[h][d] = to_bf16(d < Din ? P.w[h * Din + d] : 0.0f);
-    }
-    for (int idx = t; idx < LSD_NET_MAX_BASIS * LSD_NET_HIDDEN; idx += NET_THREADS) {
-      const int b = idx / LSD_NET_HIDDEN, h = idx % LSD_NET_HIDDEN;
-      s_W2b[b][h] = to_bf16(b < B ? w2[b * LSD_NET_HIDDEN + h] : 0.0f);
-    }
-  }
+  load_weights(P, L, t, NET_ITHREADS);
   float D[LSD_NET_MAX_SPECIES][LSD_NET_MAX_BASIS];
   net_descriptor(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md,
                  ok ? Lst.cnt_d[i] : 0, i, r, sub, D);
   const int sp = S.species ? S.species[i] : 0;
   if (sub == 0) {
-    s_sp[a] = sp;
+#pragma unroll
+    for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s)
+#pragma unroll
+      for (int b = 0; b < LSD_NET_MAX_BASIS; ++b)
+        if (s < P.ns && b < B) s_D[a][s * B + b] = D[s][b];
+    for (int d = Din; d < LSD_NET_MAX_DESC; ++d) s_D[a][d] = 0.0f;
+  }
+  __syncthreads();
+  float z[NET_HPL], vp[LSD_NET_MAX_BASIS];
+  mlp_fp32(L, s_D[a], sp, sub, z, vp);
+#pragma unroll
+  for (int b = 0; b < LSD_NET_MAX_BASIS; ++b)
+    if (b < B) vp[b] = lpa_sum(vp[b]);
+  if (sub == 0 && ok) store_v(P.v + (size_t)i * LSD_NET_MAX_BASIS, vp, B);
+}
+
+// bfloat16 on the matrix cores: the first wave multiplies the block's 16
+// descriptors by W1 and the hidden activations by W2 with
+// v_mfma_f32_16x16x16_bf16.  16x16x16 operands: lane l holds
+// A[l % 16][4 (l / 16) + 0..3] and B[4 (l / 16) + 0..3][l % 16]; the result
+// D[4 (l / 16) + 0..3][l % 16].  Each lane loads its own B fragments of W1
+// and W2 from the parameters before the descriptor loop.
+__global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_bf16(SysDev S, ListDev Lst, WinDev W,
+                                                                 PotDev P, int k) {
+  __shared__ float s_b1[LSD_NET_MAX_SPECIES][LSD_NET_HIDDEN];
+  __shared__ unsigned short s_Db[NET_IROWS][LSD_NET_MAX_DESC];
+  __shared__ unsigned short s_hb[NET_IROWS][LSD_NET_HIDDEN];
+  __shared__ int s_sp[NET_IROWS], s_ok[NET_IROWS];
+  const int t = threadIdx.x, a = t / LSD_LPA, sub = t % LSD_LPA;
+  const int i0 = blockIdx.x * NET_IROWS + a;
+  const bool in = i0 < S.n;
+  const int i = in ? i0 : S.n - 1;
+  const int r = S.atom_rep[i];
+  const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0;
+  const int B = P.nb, Din = P.ns * B;
+  const size_t N = (size_t)S.n;
+  const int li = t % 16, kq = (t % 64) / 16;
+  const bool mw = t < 64;  // the wave on the matrix cores
+  constexpr int KS1 = LSD_NET_MAX_DESC / 16, KS2 = LSD_NET_HIDDEN / 16;
+  const int ks1 = (Din + 15) / 16;
+  bf16x4 bw1[2][KS1], bw2[KS2];
+  if (mw) {
+    const float* w2 = P.w + net_off_w2(P.ns, B);
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int ks = 0; ks < KS1; ++ks)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int d = 16 * ks + 4 * kq + q, h = 16 * nt + li;
+          bw1[nt][ks][q] = (short)to_bf16(d < Din ? P.w[h * Din + d] : 0.0f);
+        }
+#pragma unroll
+    for (int ks = 0; ks < KS2; ++ks)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        bw2[ks][q] = (short)to_bf16(li < B ? w2[li * LSD_NET_HIDDEN + 16 * ks + 4 * kq + q] : 0.0f);
+  }
+  {
+    const float* b1 = P.w + net_off_b1(P.ns, B);
+    for (int idx = t; idx < LSD_NET_MAX_SPECIES * LSD_NET_HIDDEN; idx += NET_ITHREADS) {
+      const int s = idx / LSD_NET_HIDDEN, h = idx % LSD_NET_HIDDEN;
+      s_b1[s][h] = s < P.ns ? b1[s * LSD_NET_HIDDEN + h] : 0.0f;
+    }
+  }
+  float D[LSD_NET_MAX_SPECIES][LSD_NET_MAX_BASIS];
+  net_descriptor(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md,
+                 ok ? Lst.cnt_d[i] : 0, i, r, sub, D);
+  if (sub == 0) {
+    s_sp[a] = S.species ? S.species[i] : 0;
     s_ok[a] = ok ? 1 : 0;
 #pragma unroll
     for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s)
 #pragma unroll
       for (int b = 0; b < LSD_NET_MAX_BASIS; ++b)
-        if (s < P.ns && b < B) {
-          if (PREC == 1) s_Db[a][s * B + b] = to_bf16(D[s][b]);
-          else s_D[a][s * B + b] = D[s][b];
-        }
-    for (int d = Din; d < LSD_NET_MAX_DESC; ++d) {
-      if (PREC == 1) s_Db[a][d] = 0;
-      else s_D[a][d] = 0.0f;
-    }
+        if (s < P.ns && b < B) s_Db[a][s * B + b] = to_bf16(D[s][b]);
+    for (int d = Din; d < LSD_NET_MAX_DESC; ++d) s_Db[a][d] = 0;
   }
   __syncthreads();
-  if (PREC == 0) {
-    float z[NET_HPL], vp[LSD_NET_MAX_BASIS];
-    mlp_fp32(L, s_D[a], sp, sub, z, vp);
-#pragma unroll
-    for (int b = 0; b < LSD_NET_MAX_BASIS; ++b)
-      if (b < B) vp[b] = lpa_sum(vp[b]);
-    if (sub == 0 && ok) store_v(P.v + (size_t)i * LSD_NET_MAX_BASIS, vp, B);
-    return;
-  }
-  // bfloat16 on the matrix cores: wave w computes atoms 16 w .. 16 w + 15.
-  // 16x16x16 operands: lane l holds A[l % 16][4 (l / 16) + 0..3] and
-  // B[4 (l / 16) + 0..3][l % 16]; the result D[4 (l / 16) + 0..3][l % 16].
-  const int wv = t / 64, lane = t % 64, li = lane % 16, kq = lane / 16;
-  const bool mw = wv < NET_ROWS / 16;  // waves beyond 4 (LSD_LPA > 4) idle here
   if (mw) {
     f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int ks = 0; ks < LSD_NET_MAX_DESC / 16; ++ks) {
-      bf16x4 av, bv0, bv1;
+    for (int ks = 0; ks < KS1; ++ks) {
+      if (ks >= ks1) break;  // zero descriptor slots
+      bf16x4 av;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        av[q] = (short)s_Db[16 * wv + li][16 * ks + 4 * kq + q];
-        bv0[q] = (short)s_W1b[li][16 * ks + 4 * kq + q];
-        bv1[q] = (short)s_W1b[16 + li][16 * ks + 4 * kq + q];
-      }
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv1, acc1, 0, 0, 0);
+      for (int q = 0; q < 4; ++q) av[q] = (short)s_Db[li][16 * ks + 4 * kq + q];
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bw1[0][ks], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bw1[1][ks], acc1, 0, 0, 0);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int ar = 16 * wv + 4 * kq + q;
+      const int ar = 4 * kq + q;
       const int spa = s_sp[ar];
-      s_hb[ar][li] = to_bf16(silu(acc0[q] + L.b1[spa][li]));
-      s_hb[ar][16 + li] = to_bf16(silu(acc1[q] + L.b1[spa][16 + li]));
+      s_hb[ar][li] = to_bf16(silu(acc0[q] + s_b1[spa][li]));
+      s_hb[ar][16 + li] = to_bf16(silu(acc1[q] + s_b1[spa][16 + li]));
     }
   }
   __syncthreads();
-  if (!mw) return;
-  f32x4 acc2 = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (mw) {
+    f32x4 acc2 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int ks = 0; ks < LSD_NET_HIDDEN / 16; ++ks) {
-    bf16x4 av, bv;
+    for (int ks = 0; ks < KS2; ++ks) {
+      bf16x4 av;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) av[q] = (short)s_hb[li][16 * ks + 4 * kq + q];
+      acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bw2[ks], acc2, 0, 0, 0);
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      av[q] = (short)s_hb[16 * wv + li][16 * ks + 4 * kq + q];
-      bv[q] = (short)s_W2b[li][16 * ks + 4 * kq + q];
+      const int ar = 4 * kq + q;
+      const int ia = blockIdx.x * NET_IROWS + ar;
+      if (ia < S.n && s_ok[ar]) P.v[(size_t)ia * LSD_NET_MAX_BASIS + li] = li < B ? acc2[q] : 0.0f;
     }
-    acc2 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc2, 0, 0, 0);
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int ar = 16 * wv + 4 * kq + q;
-    const int ia = blockIdx.x * NET_ROWS + ar;
-    if (ia < S.n && s_ok[ar]) P.v[(size_t)ia * LSD_NET_MAX_BASIS + li] = li < B ? acc2[q] : 0.0f;
   }
 }
 
@@ -265,7 +302,7 @@ __global__ __launch_bounds__(NET_THREADS) void k_nt_nodes(SysDev S, ListDev Lst,
   const bool ok = in && W.invalid[(size_t)r * S.kmax + f] == 0;
   const int B = P.nb, Din = P.ns * B;
   const size_t N = (size_t)S.n, fi = (size_t)f * N + i;
-  load_weights(P, L, t);
+  load_weights(P, L, t, NET_THREADS);
   float D[LSD_NET_MAX_SPECIES][LSD_NET_MAX_BASIS];
   net_descriptor(P, S, W.qmid + (size_t)f * N, Lst.nbr_t + (size_t)i * Lst.mt,
                  ok ? Lst.cnt_t[i] : 0, i, r, sub, D);
@@ -298,7 +335,7 @@ __global__ __launch_bounds__(NET_THREADS) void k_nt_nodes(SysDev S, ListDev Lst,
 
 __global__ __launch_bounds__(NET_THREADS) void k_nt_resid(SysDev S, ListDev Lst, WinDev W,
                                                           PotDev P, NetTrainDev T,
-                                                          int use_target) {
+                                                          int use_target, int diff) {
   __shared__ double s_e[NET_ROWS];
   __shared__ int s_c[NET_ROWS];
   const int t = threadIdx.x, a = t / LSD_LPA, sub = t % LSD_LPA, f = blockIdx.y;
@@ -313,6 +350,13 @@ __global__ __launch_bounds__(NET_THREADS) void k_nt_resid(SysDev S, ListDev Lst,
   float F[3];
   net_force(Q, S, W.qmid + (size_t)f * N, Lst.nbr_t + (size_t)i * Lst.mt, ok ? Lst.cnt_t[i] : 0,
             i, r, sub, F[0], F[1], F[2]);
+  if (diff) {
+    if (sub == 0 && in) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) T.F[((size_t)f * 3 + d) * N + i] = ok ? F[d] : 0.0f;
+    }
+    return;
+  }
   if (sub == 0) {
     const float* Y = (use_target ? W.ft : W.fd) + (size_t)f * 3 * N;
     double e = 0.0;
@@ -327,6 +371,54 @@ __global__ __launch_bounds__(NET_THREADS) void k_nt_resid(SysDev S, ListDev Lst,
   }
   __syncthreads();
   if (t == 0) {
+    double se = 0.0;
+    int c = 0;
+    for (int q = 0; q < NET_ROWS; ++q) {
+      se += s_e[q];
+      c += s_c[q];
+    }
+    double* row = T.partial + ((size_t)f * T.nblk + blockIdx.x) * NET_PROW;
+    row[NET_PMAX] = se;
+    row[NET_PMAX + 1] = (double)c;
+  }
+}
+
+// Loss of force changes: one thread per atom of frame f.  Frames are valid
+// up to K_eff, so a valid frame f + 1 implies a valid frame f.
+__global__ __launch_bounds__(NET_ROWS) void k_nt_diff(SysDev S, WinDev W, NetTrainDev T,
+                                                      int use_target) {
+  __shared__ double s_e[NET_ROWS];
+  __shared__ int s_c[NET_ROWS];
+  const int a = threadIdx.x, f = blockIdx.y;
+  const int i0 = blockIdx.x * NET_ROWS + a;
+  const bool in = i0 < S.n;
+  const int i = in ? i0 : S.n - 1;
+  const int* inv = W.invalid + (size_t)S.atom_rep[i] * S.kmax;
+  const size_t N = (size_t)S.n;
+  const float* Y = use_target ? W.ft : W.fd;
+  // delta_k of this atom, for k = f - 1 (before) and k = f (after)
+  const bool has_before = in && f >= 1 && inv[f] == 0;
+  const bool has_after = in && f + 1 < W.K && inv[f + 1] == 0;
+  double e = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const size_t c0 = ((size_t)f * 3 + d) * N + i;
+    float before = 0.0f, after = 0.0f;
+    if (has_before) {
+      const size_t cm = c0 - 3 * N;
+      before = (T.F[c0] - T.F[cm]) - (Y[c0] - Y[cm]);
+    }
+    if (has_after) {
+      const size_t cp = c0 + 3 * N;
+      after = (T.F[cp] - T.F[c0]) - (Y[cp] - Y[c0]);
+      e += (double)after * (double)after;
+    }
+    if (in) T.G[c0] = 2.0f * before - 2.0f * after;
+  }
+  s_e[a] = e;
+  s_c[a] = has_after ? 1 : 0;
+  __syncthreads();
+  if (a == 0) {
     double se = 0.0;
     int c = 0;
     for (int q = 0; q < NET_ROWS; ++q) {
@@ -507,7 +599,7 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 size_t net_train_bytes(int K, int N) {
   const size_t kn = (size_t)K * N, nblk = ((size_t)N + NET_ROWS - 1) / NET_ROWS;
   return align256(kn * LSD_NET_MAX_DESC * 4) + align256(kn * LSD_NET_HIDDEN * 4) +
-         align256(kn * LSD_NET_MAX_BASIS * 4) + align256(kn * 3 * 4) +
+         align256(kn * LSD_NET_MAX_BASIS * 4) + 2 * align256(kn * 3 * 4) +
          align256((size_t)K * nblk * NET_PROW * 8);
 }
 
@@ -524,27 +616,35 @@ NetTrainDev net_train_bind(char* base, int K, int N) {
   off += align256(kn * LSD_NET_MAX_BASIS * 4);
   T.G = reinterpret_cast<float*>(base + off);
   off += align256(kn * 3 * 4);
+  T.F = reinterpret_cast<float*>(base + off);
+  off += align256(kn * 3 * 4);
   T.partial = reinterpret_cast<double*>(base + off);
   return T;
 }
 
 hipError_t launch_net_nodes(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P,
                             int k, hipStream_t st) {
-  const dim3 grid((S.n + NET_ROWS - 1) / NET_ROWS), block(NET_THREADS);
-  if (P.prec == 1) hipLaunchKernelGGL(k_net_nodes<1>, grid, block, 0, st, S, L, W, P, k);
-  else hipLaunchKernelGGL(k_net_nodes<0>, grid, block, 0, st, S, L, W, P, k);
+  const dim3 grid((S.n + NET_IROWS - 1) / NET_IROWS), block(NET_ITHREADS);
+  if (P.prec == 1) hipLaunchKernelGGL(k_net_nodes_bf16, grid, block, 0, st, S, L, W, P, k);
+  else hipLaunchKernelGGL(k_net_nodes_f32, grid, block, 0, st, S, L, W, P, k);
   return hipGetLastError();
 }
 
 hipError_t launch_net_train(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P,
-                            const NetTrainDev& T, int use_target, double* grad, hipStream_t st) {
+                            const NetTrainDev& T, int use_target, int diff, double* grad,
+                            hipStream_t st) {
   const dim3 grid(T.nblk, W.K), block(NET_THREADS);
   hipLaunchKernelGGL(k_nt_nodes, grid, block, 0, st, S, L, W, P, T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_nt_resid, grid, block, 0, st, S, L, W, P, T, use_target);
+  hipLaunchKernelGGL(k_nt_resid, grid, block, 0, st, S, L, W, P, T, use_target, diff);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (diff) {
+    hipLaunchKernelGGL(k_nt_diff, grid, dim3(NET_ROWS), 0, st, S, W, T, use_target);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_nt_back, grid, block, 0, st, S, L, W, P, T);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -101,8 +101,8 @@ EXPORTS = {
                              C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "lsd_net_param_count": ([C.c_int32, C.c_int32], C.c_int32),
     "lsd_net_train_scratch_size": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
-    "lsd_net_train_accumulate": ([C.c_void_p, C.POINTER(Potential), C.c_int32, C.c_void_p,
-                                  C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
+    "lsd_net_train_accumulate": ([C.c_void_p, C.POINTER(Potential), C.c_int32, C.c_int32,
+                                  C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
     "lsd_net_adam_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
                            C.c_double, C.c_double, C.c_double, C.c_int64, C.c_void_p], C.c_int),
     "lsd_destroy": ([C.c_void_p], C.c_int),
@@ -387,12 +387,13 @@ class LSDSystem:
         P.precision = {"fp32": PREC_FP32, "bf16": PREC_BF16}[d.get("precision", "bf16")]
 
     # --- training of the learned draft -------------------------------------------
-    def net_train_accumulate(self, net, grad, use_target=False, scratch=None):
+    def net_train_accumulate(self, net, grad, use_target=False, scratch=None, differences=False):
         """Add the gradient of the summed squared force error of the learned
         draft `net` (a potential dict of kind "net") over the current
         window's valid frames to `grad` (float64 CUDA [P+2]: gradient,
         squared error, atom frames); net["weights"] must be the float32 CUDA
-        parameter tensor.  Returns the scratch tensor (reuse it)."""
+        parameter tensor.  differences: the loss of the force changes between
+        consecutive frames.  Returns the scratch tensor (reuse it)."""
         t = self.torch
         nb = C.c_size_t()
         _check(load().lsd_net_train_scratch_size(self.h, C.byref(nb)),
@@ -402,7 +403,7 @@ class LSDSystem:
         P = Potential()
         self._net_fields(P, net, net["weights"])   # the caller owns the CUDA parameters
         _check(load().lsd_net_train_accumulate(self.h, C.byref(P), 1 if use_target else 0,
-                                               _ptr(scratch), scratch.numel(), _ptr(grad),
+                                               1 if differences else 0, _ptr(scratch), scratch.numel(), _ptr(grad),
                                                _stream(t)), "lsd_net_train_accumulate")
         return scratch
 

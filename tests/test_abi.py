@@ -137,9 +137,9 @@ def test_net_parameter_layout(lib, ora):
     # pair draft (W2 = 0, c = pair weights)
     from oracle.net import NetDraft
     from paper_2606_02455_amd import lsd
-    for S, B in ((1, 1), (3, 8), (2, 16), (4, 8)):
+    for S, B in ((1, 1), (3, 8), (3, 16), (4, 16)):
         assert lsd.net_param_count(S, B) == NetDraft.count(S, B)
-    for S, B in ((0, 8), (5, 4), (3, 16), (1, 17)):
+    for S, B in ((0, 8), (5, 4), (1, 17), (2, 0)):
         assert lsd.net_param_count(S, B) == 0
     pw = np.arange(6 * 8, dtype=np.float64)
     p = lsd.net_init_params(3, 8, pair_weights=pw, seed=2)

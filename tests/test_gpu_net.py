@@ -213,6 +213,17 @@ def test_net_training_gradient_matches_oracle(torch, lsd, ora):
     assert gg[P] == pytest.approx(sse, rel=1e-4)
     assert np.max(np.abs(gg[:P] - gr)) <= 1e-4 * np.max(np.abs(gr)), \
         np.max(np.abs(gg[:P] - gr)) / np.max(np.abs(gr))
+    # the loss of force changes between consecutive frames
+    gd = torch.zeros(P + 2, dtype=torch.float64, device="cuda")
+    g.net_train_accumulate(net, gd, scratch=scratch, differences=True)
+    torch.cuda.synchronize()
+    gdd = gd.cpu().numpy()
+    sd, grd = ref.diff_sse_grad(w.species, frames, L, ys)
+    assert gdd[P + 1] == (K - 1) * w.n_atoms
+    assert gdd[P] == pytest.approx(sd, rel=1e-4)
+    # differences of binary32 forces lose digits: 1e-3 of the largest entry
+    assert np.max(np.abs(gdd[:P] - grd)) <= 1e-3 * np.max(np.abs(grd)), \
+        np.max(np.abs(gdd[:P] - grd)) / np.max(np.abs(grd))
     # a second call accumulates; an Adam step consumes and clears the buffer
     g.net_train_accumulate(net, grad, scratch=scratch)
     torch.cuda.synchronize()

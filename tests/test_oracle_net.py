@@ -148,6 +148,38 @@ def test_gradient_matches_finite_differences(net):
     assert np.max(np.abs(g2 - 2 * g)) <= 1e-12 * np.max(np.abs(g))
 
 
+def test_difference_loss_gradient_matches_finite_differences(net):
+    # the loss of the force changes between consecutive frames, with its
+    # gradient assembled from per-frame backward passes
+    w = W.triatomic_liquid(12, seed=25)
+    S, B, rc, L = 3, 4, 4.0, float(w.box[0])
+    p = _random_params(net, S, B, seed=9, w2=0.5)
+    d = net.NetDraft(S, B, rc, p)
+    rng = np.random.default_rng(10)
+    frames = [np.mod(w.positions + rng.normal(scale=0.03, size=w.positions.shape), L)
+              for _ in range(3)]
+    Ys = [rng.normal(size=(w.n_atoms, 3)) for _ in frames]
+    sse, g = d.diff_sse_grad(w.species, frames, L, Ys)
+    F = [d.forces(w.species, x, L) for x in frames]
+    want = sum(np.sum(((F[k + 1] - F[k]) - (Ys[k + 1] - Ys[k])) ** 2) for k in range(2))
+    assert sse == pytest.approx(want, rel=1e-13)
+    h = 1e-5
+    for k in np.random.default_rng(11).choice(p.size, 60, replace=False):
+        old = p[k]
+        p[k] = old + h
+        d.params = p
+        up, _ = d.diff_sse_grad(w.species, frames, L, Ys)
+        p[k] = old - h
+        d.params = p
+        dn, _ = d.diff_sse_grad(w.species, frames, L, Ys)
+        p[k] = old
+        d.params = p
+        assert (up - dn) / (2 * h) == pytest.approx(g[k], abs=1e-6 * np.max(np.abs(g))), k
+    # with one frame there is no difference and no gradient
+    s0, g0 = d.diff_sse_grad(w.species, frames[:1], L, Ys[:1])
+    assert s0 == 0.0 and not g0.any()
+
+
 def test_adam_closed_forms(net):
     lr, eps = 0.01, 1e-8
     p0 = np.array([1.0, -2.0, 0.5, 3.0])
