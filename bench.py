@@ -135,9 +135,10 @@ def mpnn_flops_per_frame(undirected_edges, n_atoms, H=128, R=16, T=3, RH=64):
 
 
 def run_c3(args, lsd, W, torch):
-    """Learned-draft configurations: triatomic liquid (c3: 1536 atoms; c4: 256
-    replicas of 24-192 atoms in one system), message-passing target, pair
-    draft fitted by force matching on target frames, K = 8."""
+    """Network-target configurations: triatomic liquid (c3: 1536 atoms, K = 8;
+    c4: 256 replicas of 24-192 atoms in one system, K = 8; c5: 24 576 atoms,
+    K = 32), message-passing target, pair draft fitted by force matching on
+    target frames and the learned draft trained from it."""
     import numpy as np
     w = W.config(args.config)
     K, N = w.K, w.n_atoms
@@ -156,6 +157,7 @@ def run_c3(args, lsd, W, torch):
     gram = torch.zeros((P + 1, P + 1), dtype=torch.float64, device="cuda")
     scratch = None
     fit_windows = max(1, (args.fit_frames + K - 1) // K)
+    committed0 = int(plain.counters()[:, 1].sum())
     t0 = time.perf_counter()
     for _ in range(fit_windows):
         plain.draft_steps(K)
@@ -165,9 +167,12 @@ def run_c3(args, lsd, W, torch):
         plain.accept_rollback()
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t0
+    # frames actually stepped (a window ends early once an atom leaves the
+    # skin), as whole-system frames
+    fit_frames = (int(plain.counters()[:, 1].sum()) - committed0) // w.n_replicas
     G = gram.cpu().numpy()
     wts = lsd.fit_pair_solve(G, ridge=1e-8)
-    log(f"fitted the pair draft on {fit_windows * K} target frames in {t_fit:.1f} s")
+    log(f"fitted the pair draft on {fit_frames} target frames in {t_fit:.1f} s")
     if plain.status():
         raise RuntimeError(f"device status {plain.status()} during plain stepping")
     draft = dict(kind="pair", rc=rc_d, weights=wts, n_basis=nb, n_model_species=3)
@@ -185,6 +190,7 @@ def run_c3(args, lsd, W, torch):
         m1 = torch.zeros(Pn, dtype=torch.float64, device="cuda")
         m2 = torch.zeros(Pn, dtype=torch.float64, device="cuda")
         scratch_t, mse = None, []
+        committed0 = int(plain.counters()[:, 1].sum())
         t0 = time.perf_counter()
         n_train = args.net_train_windows
         for step in range(1, n_train + 1):
@@ -198,11 +204,23 @@ def run_c3(args, lsd, W, torch):
             lsd.net_adam_step(torch, pt, m1, m2, grad, lr, step)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
-        log(f"trained the learned draft ({Pn} parameters) on {n_train * K} target frames in "
+        train_frames = (int(plain.counters()[:, 1].sum()) - committed0) // w.n_replicas
+        log(f"trained the learned draft ({Pn} parameters) on {train_frames} target frames in "
             f"{t_train:.1f} s; force-change MSE {mse[0]:.3g} -> {mse[-1]:.3g} (eV/A)^2")
-        draft = net
-        train = dict(windows=n_train, frames=n_train * K, seconds=round(t_train, 2),
+        train = dict(windows=n_train, frames=train_frames, seconds=round(t_train, 2),
                      mse_first=mse[0], mse_last=mse[-1], parameters=Pn)
+        if args.net_precision == "fp8":
+            # static per-tensor activation scales: the largest |D| and |h| over
+            # 16 windows of target frames, with a 20% margin
+            amax = np.zeros(2)
+            for _ in range(16):
+                plain.draft_steps(K)
+                amax = np.maximum(amax, plain.net_activation_amax(net, scratch=scratch_t))
+                plain.accept_rollback()
+            net["act_amax"] = tuple(1.2 * amax)
+            train["fp8_act_amax"] = [float(a) for a in net["act_amax"]]
+            log(f"FP8 activation scales from max |D| = {amax[0]:.4g}, max |h| = {amax[1]:.4g}")
+        draft = net
     g = lsd.LSDSystem(w, mode="lsd", target=target, draft=draft,
                       error_correction=EC_MODES[args.ec])
     for a, b in ((g.q, plain.q), (g.p, plain.p), (g.img, plain.img), (g.step, plain.step)):
@@ -257,9 +275,9 @@ def run_c3(args, lsd, W, torch):
                             f"from the pair draft and trained on {train['frames'] if train else 0} "
                             f"target frames; " if args.draft == "net" else "")
                          + f"pair draft: pair forces (rc {rc_d} A, {nb} basis) force-matched "
-                         f"(frame-to-frame differences) on {fit_windows * K} target frames; "
+                         f"(frame-to-frame differences) on {fit_frames} target frames; "
                          f"error correction {args.ec}"),
-            "n_atoms": N, "K": K, "fit_frames": fit_windows * K,
+            "n_atoms": N, "K": K, "fit_frames": fit_frames,
             "draft": args.draft, "error_correction": args.ec},
         "acceptance": round(1.0 - rejections / max(committed, 1), 5),
         "committed_per_window": round(committed / windows, 4),
@@ -284,7 +302,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed windows")
     ap.add_argument("--warmup", type=int, default=20, help="untimed windows")
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--fit-frames", type=int, default=None,
                     help="c3/c4: target frames for force matching of the pair draft "
                          "(default 20000 for c3, 2000 whole-system frames of 256 replicas for c4)")
@@ -292,7 +310,7 @@ def main():
                     help="c3/c4: radial functions of the pair and learned drafts")
     ap.add_argument("--draft", choices=["net", "pair"], default="net",
                     help="c3/c4: the learned draft (trained from the pair draft) or the pair draft")
-    ap.add_argument("--net-precision", choices=["bf16", "fp32"], default="bf16")
+    ap.add_argument("--net-precision", choices=["bf16", "fp32", "fp8"], default="bf16")
     ap.add_argument("--net-train-windows", type=int, default=None,
                     help="c3/c4: Adam steps, one window of K target frames each "
                          "(default 2000 for c3, 500 for c4)")
@@ -306,11 +324,11 @@ def main():
                          "measured setting of the configuration (c1, c2: on; c3: linear)")
     args = ap.parse_args()
     if args.fit_frames is None:
-        args.fit_frames = 2000 if args.config == "c4" else 20000
+        args.fit_frames = 2000 if args.config in ("c4", "c5") else 20000
     if args.net_train_windows is None:
-        args.net_train_windows = 500 if args.config == "c4" else 2000
+        args.net_train_windows = {"c4": 500, "c5": 100}.get(args.config, 2000)
     if args.ec == "auto":
-        args.ec = "linear" if args.config in ("c3", "c4") else "on"
+        args.ec = "linear" if args.config in ("c3", "c4", "c5") else "on"
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only: the batched verification path runs the K frames "
@@ -326,7 +344,7 @@ def main():
 
     lsd.load()
     torch.cuda.set_device(0)
-    if args.config in ("c3", "c4"):
+    if args.config in ("c3", "c4", "c5"):
         print(json.dumps(run_c3(args, lsd, W, torch)), flush=True)
         return
     w = W.config(args.config)

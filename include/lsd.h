@@ -126,12 +126,17 @@ typedef enum {
  * n_basis (1 .. LSD_NET_MAX_BASIS), S B <= LSD_NET_MAX_DESC.  precision:
  * LSD_PREC_FP32 evaluates the two dense layers in binary32 on the vector
  * ALUs; LSD_PREC_BF16 on the matrix cores with D, h, W1 and W2 rounded to
- * bfloat16 and binary32 accumulation (pair terms are binary32 either way). */
+ * bfloat16 and binary32 accumulation; LSD_PREC_FP8 on the matrix cores in
+ * OCP e4m3 with one scale per tensor and binary32 accumulation: W1 and W2
+ * are divided by max|W| / 448 (computed from the parameters), D and h by
+ * act_amax[0] / 448 and act_amax[1] / 448 (static scales calibrated by
+ * lsd_net_activation_amax; larger values saturate at +-448), and the
+ * products are scaled back.  Pair terms are binary32 in every mode. */
 #define LSD_NET_HIDDEN 32
 #define LSD_NET_MAX_BASIS 16
 #define LSD_NET_MAX_DESC 64
 #define LSD_NET_MAX_SPECIES 4
-typedef enum { LSD_PREC_FP32 = 0, LSD_PREC_BF16 = 1 } lsd_precision;
+typedef enum { LSD_PREC_FP32 = 0, LSD_PREC_BF16 = 1, LSD_PREC_FP8 = 2 } lsd_precision;
 
 /* Message-passing potential (a stand-in for the paper's interatomic
  * potentials; architecture fixed here): radial basis
@@ -164,6 +169,7 @@ typedef struct {
   double energy_scale;       /* MPNN: s_E */
   int32_t n_basis;           /* PAIR: B, 1 .. LSD_PAIR_MAX_BASIS; NET: B */
   int32_t precision;         /* NET: lsd_precision */
+  double act_amax[2];        /* NET, LSD_PREC_FP8: calibrated max |D| and max |h| (> 0) */
 } lsd_potential;
 
 typedef struct {
@@ -433,6 +439,16 @@ LSD_API lsd_status lsd_net_train_accumulate(lsd_system *sys, const lsd_potential
                                             void *scratch,
                                             size_t scratch_bytes, double *grad,
                                             lsd_stream stream);
+/* Calibration of the FP8 activation scales: max |D| over the descriptor
+ * entries and max |h| over the hidden activations of the learned draft
+ * `net` on the valid frames of the current window (binary32 node pass over
+ * the target list, as in training; the maximum is order-independent, so
+ * the result is exact for those values).  amax: device binary64 [2],
+ * overwritten.  scratch as for training.  Asynchronous.  Errors as for
+ * lsd_net_train_accumulate. */
+LSD_API lsd_status lsd_net_activation_amax(lsd_system *sys, const lsd_potential *net,
+                                           void *scratch, size_t scratch_bytes, double *amax,
+                                           lsd_stream stream);
 LSD_API lsd_status lsd_net_adam_step(float *params, double *m, double *v, double *grad,
                                      int32_t n_params, double lr, double beta1, double beta2,
                                      double eps, int64_t t, lsd_stream stream);

@@ -113,8 +113,13 @@ lsd_status check_potential(const lsd_potential& P, const char* what) {
       return fail(LSD_ERR_INVALID_ARG, "%s: learned draft needs cutoff > 0, weights, 1..%d "
                   "species, 1..%d radial functions and species x functions <= %d", what,
                   LSD_NET_MAX_SPECIES, LSD_NET_MAX_BASIS, LSD_NET_MAX_DESC);
-    if (P.precision != LSD_PREC_FP32 && P.precision != LSD_PREC_BF16)
+    if (P.precision != LSD_PREC_FP32 && P.precision != LSD_PREC_BF16 &&
+        P.precision != LSD_PREC_FP8)
       return fail(LSD_ERR_INVALID_ARG, "%s: precision %d invalid", what, P.precision);
+    if (P.precision == LSD_PREC_FP8 &&
+        !(P.act_amax[0] > 0.0 && P.act_amax[1] > 0.0 && std::isfinite(P.act_amax[0]) &&
+          std::isfinite(P.act_amax[1])))
+      return fail(LSD_ERR_INVALID_ARG, "%s: FP8 needs calibrated activation maxima > 0", what);
   } else {
     return fail(LSD_ERR_UNSUPPORTED, "%s: potential kind %d not supported", what, P.kind);
   }
@@ -312,6 +317,10 @@ PotDev make_pot(const lsd_potential& P, const Layout& L) {
     d.ns = P.n_model_species;
     d.w = P.weights;
     d.prec = P.kind == LSD_POT_NET ? P.precision : 0;
+    if (P.kind == LSD_POT_NET && P.precision == LSD_PREC_FP8) {
+      d.fp8_sD = (float)(P.act_amax[0] / 448.0);
+      d.fp8_sh = (float)(P.act_amax[1] / 448.0);
+    }
   }
   return d;
 }
@@ -1009,7 +1018,9 @@ lsd_status lsd_net_train_accumulate(lsd_system* s, const lsd_potential* net,
                                     size_t scratch_bytes, double* grad, lsd_stream stream) {
   if (!s || !net || !scratch || !grad) return fail(LSD_ERR_INVALID_ARG, "null argument");
   if (net->kind != LSD_POT_NET) return fail(LSD_ERR_INVALID_ARG, "not a learned draft");
-  LSD_TRY(check_potential(*net, "learned draft"));
+  lsd_potential copy = *net;
+  copy.precision = LSD_PREC_FP32;  // training evaluates in binary32
+  LSD_TRY(check_potential(copy, "learned draft"));
   if (net->n_model_species < s->cfg.n_species)
     return fail(LSD_ERR_INVALID_ARG, "learned draft has %d species, system has %d",
                 net->n_model_species, s->cfg.n_species);
@@ -1024,12 +1035,34 @@ lsd_status lsd_net_train_accumulate(lsd_system* s, const lsd_potential* net,
   if (use_target_forces &&
       !(s->cfg.mode == LSD_MODE_LSD && (s->state == ST_VERIFIED || s->state == ST_COMMITTED)))
     return fail(LSD_ERR_BAD_STATE, "target forces exist only for a verified window (LSD mode)");
-  lsd_potential copy = *net;
-  copy.precision = LSD_PREC_FP32;
   PotDev P = make_pot(copy, s->lay);
   const NetTrainDev T = net_train_bind(static_cast<char*>(scratch), s->cfg.k_max, s->cfg.n_atoms);
   HIP_TRY(launch_net_train(s->S, s->Lst, s->W, P, T, use_target_forces ? 1 : 0,
                            differences ? 1 : 0, grad, static_cast<hipStream_t>(stream)));
+  return LSD_OK;
+}
+
+lsd_status lsd_net_activation_amax(lsd_system* s, const lsd_potential* net, void* scratch,
+                                   size_t scratch_bytes, double* amax, lsd_stream stream) {
+  if (!s || !net || !scratch || !amax) return fail(LSD_ERR_INVALID_ARG, "null argument");
+  if (net->kind != LSD_POT_NET) return fail(LSD_ERR_INVALID_ARG, "not a learned draft");
+  lsd_potential copy = *net;
+  copy.precision = LSD_PREC_FP32;
+  LSD_TRY(check_potential(copy, "learned draft"));
+  if (copy.n_model_species < s->cfg.n_species)
+    return fail(LSD_ERR_INVALID_ARG, "learned draft has %d species, system has %d",
+                copy.n_model_species, s->cfg.n_species);
+  if (copy.cutoff > pot_reach(s->cfg.target))
+    return fail(LSD_ERR_INVALID_ARG, "learned draft cutoff %g exceeds the target cutoff %g",
+                copy.cutoff, pot_reach(s->cfg.target));
+  const size_t need = net_train_bytes(s->cfg.k_max, s->cfg.n_atoms);
+  if (scratch_bytes < need)
+    return fail(LSD_ERR_CAPACITY, "scratch %zu bytes < required %zu", scratch_bytes, need);
+  if (s->state == ST_READY || s->W.K < 1)
+    return fail(LSD_ERR_BAD_STATE, "calibration needs a drafted window");
+  PotDev P = make_pot(copy, s->lay);
+  const NetTrainDev T = net_train_bind(static_cast<char*>(scratch), s->cfg.k_max, s->cfg.n_atoms);
+  HIP_TRY(launch_net_amax(s->S, s->Lst, s->W, P, T, amax, static_cast<hipStream_t>(stream)));
   return LSD_OK;
 }
 

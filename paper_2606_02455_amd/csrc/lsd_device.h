@@ -51,6 +51,7 @@ struct PotDev {
   const float* w;
   float* v;
   int prec;
+  float fp8_sD, fp8_sh;  // FP8 node pass: static scales max|D| / 448, max|h| / 448
 };
 
 // offsets of the learned draft's parameter blocks W1 [H][S B], b1 [S][H],

@@ -38,6 +38,10 @@ hipError_t launch_net_train(const SysDev& S, const ListDev& L, const WinDev& W, 
                             const NetTrainDev& T, int use_target, int diff, double* grad,
                             hipStream_t st);
 
+// amax[0] = max |D|, amax[1] = max |silu(z)| over the window's valid frames.
+hipError_t launch_net_amax(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P,
+                           const NetTrainDev& T, double* amax, hipStream_t st);
+
 hipError_t launch_net_adam(float* params, double* m, double* v, double* grad, int n_params,
                            double lr, double beta1, double beta2, double eps, long long t,
                            hipStream_t st);

@@ -287,6 +287,142 @@ __global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_bf16(SysDev S, ListD
   }
 }
 
+// OCP e4m3 (largest finite 448), 8 values of x / s packed for one operand
+// of v_mfma_f32_16x16x32_fp8_fp8 (element e in byte e), round to nearest
+// even after saturation to +-448.
+__device__ __forceinline__ long pack_fp8(const float x[8], float inv_s) {
+  float y[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) y[e] = fminf(fmaxf(x[e] * inv_s, -448.0f), 448.0f);
+  int w0 = __builtin_amdgcn_cvt_pk_fp8_f32(y[0], y[1], 0, false);
+  w0 = __builtin_amdgcn_cvt_pk_fp8_f32(y[2], y[3], w0, true);
+  int w1 = __builtin_amdgcn_cvt_pk_fp8_f32(y[4], y[5], 0, false);
+  w1 = __builtin_amdgcn_cvt_pk_fp8_f32(y[6], y[7], w1, true);
+  return (long)(((unsigned long)(unsigned)w1 << 32) | (unsigned)w0);
+}
+
+__device__ __forceinline__ unsigned char to_fp8(float x, float inv_s) {
+  const float y = fminf(fmaxf(x * inv_s, -448.0f), 448.0f);
+  return (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(y, 0.0f, 0, false) & 0xFF);
+}
+
+__device__ __forceinline__ float wave_absmax(float v) {
+  v = fabsf(v);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// FP8 (OCP e4m3) on the matrix cores, one scale per tensor: W1, W2 by their
+// max |.| / 448 (every block reduces the same values, so all blocks agree),
+// D and h by the calibrated static scales.  16x16x32 operands: lane l holds
+// A[l % 16][8 (l / 16) + 0..7] and B[8 (l / 16) + 0..7][l % 16]; the result
+// D[4 (l / 16) + 0..3][l % 16].
+__global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_fp8(SysDev S, ListDev Lst, WinDev W,
+                                                                PotDev P, int k) {
+  __shared__ float s_b1[LSD_NET_MAX_SPECIES][LSD_NET_HIDDEN];
+  __shared__ __align__(8) unsigned char s_Dq[NET_IROWS][LSD_NET_MAX_DESC];
+  __shared__ __align__(8) unsigned char s_hq[NET_IROWS][LSD_NET_HIDDEN];
+  __shared__ int s_sp[NET_IROWS], s_ok[NET_IROWS];
+  const int t = threadIdx.x, a = t / LSD_LPA, sub = t % LSD_LPA;
+  const int i0 = blockIdx.x * NET_IROWS + a;
+  const bool in = i0 < S.n;
+  const int i = in ? i0 : S.n - 1;
+  const int r = S.atom_rep[i];
+  const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0;
+  const int B = P.nb, Din = P.ns * B;
+  const size_t N = (size_t)S.n;
+  const int li = t % 16, kq = (t % 64) / 16;
+  const bool mw = t < 64;
+  constexpr int KS1 = LSD_NET_MAX_DESC / 32;
+  const int ks1 = (Din + 31) / 32;
+  long bw1[2][KS1], bw2 = 0;
+  float s_w1 = 1.0f, s_w2 = 1.0f;
+  if (mw) {
+    const float* w2 = P.w + net_off_w2(P.ns, B);
+    float f1[2][KS1][8], f2[8];
+    float m1 = 0.0f, m2 = 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int ks = 0; ks < KS1; ++ks)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int d = 32 * ks + 8 * kq + e, h = 16 * nt + li;
+          f1[nt][ks][e] = d < Din ? P.w[h * Din + d] : 0.0f;
+          m1 = fmaxf(m1, fabsf(f1[nt][ks][e]));
+        }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      f2[e] = li < B ? w2[li * LSD_NET_HIDDEN + 8 * kq + e] : 0.0f;
+      m2 = fmaxf(m2, fabsf(f2[e]));
+    }
+    m1 = wave_absmax(m1);
+    m2 = wave_absmax(m2);
+    s_w1 = m1 > 0.0f ? m1 / 448.0f : 1.0f;
+    s_w2 = m2 > 0.0f ? m2 / 448.0f : 1.0f;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int ks = 0; ks < KS1; ++ks) bw1[nt][ks] = pack_fp8(f1[nt][ks], 1.0f / s_w1);
+    bw2 = pack_fp8(f2, 1.0f / s_w2);
+  }
+  {
+    const float* b1 = P.w + net_off_b1(P.ns, B);
+    for (int idx = t; idx < LSD_NET_MAX_SPECIES * LSD_NET_HIDDEN; idx += NET_ITHREADS) {
+      const int s = idx / LSD_NET_HIDDEN, h = idx % LSD_NET_HIDDEN;
+      s_b1[s][h] = s < P.ns ? b1[s * LSD_NET_HIDDEN + h] : 0.0f;
+    }
+  }
+  float D[LSD_NET_MAX_SPECIES][LSD_NET_MAX_BASIS];
+  net_descriptor(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md,
+                 ok ? Lst.cnt_d[i] : 0, i, r, sub, D);
+  const float inv_sD = 1.0f / P.fp8_sD, inv_sh = 1.0f / P.fp8_sh;
+  if (sub == 0) {
+    s_sp[a] = S.species ? S.species[i] : 0;
+    s_ok[a] = ok ? 1 : 0;
+#pragma unroll
+    for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s)
+#pragma unroll
+      for (int b = 0; b < LSD_NET_MAX_BASIS; ++b)
+        if (s < P.ns && b < B) s_Dq[a][s * B + b] = to_fp8(D[s][b], inv_sD);
+    for (int d = Din; d < LSD_NET_MAX_DESC; ++d) s_Dq[a][d] = 0;
+  }
+  __syncthreads();
+  if (mw) {
+    f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < KS1; ++ks) {
+      if (ks >= ks1) break;  // zero descriptor slots
+      const long av = *reinterpret_cast<const long*>(&s_Dq[li][32 * ks + 8 * kq]);
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bw1[0][ks], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bw1[1][ks], acc1, 0, 0, 0);
+    }
+    const float sc1 = P.fp8_sD * s_w1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ar = 4 * kq + q;
+      const int spa = s_sp[ar];
+      s_hq[ar][li] = to_fp8(silu(acc0[q] * sc1 + s_b1[spa][li]), inv_sh);
+      s_hq[ar][16 + li] = to_fp8(silu(acc1[q] * sc1 + s_b1[spa][16 + li]), inv_sh);
+    }
+  }
+  __syncthreads();
+  if (mw) {
+    f32x4 acc2 = {0.0f, 0.0f, 0.0f, 0.0f};
+    const long av = *reinterpret_cast<const long*>(&s_hq[li][8 * kq]);
+    acc2 = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bw2, acc2, 0, 0, 0);
+    const float sc2 = P.fp8_sh * s_w2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ar = 4 * kq + q;
+      const int ia = blockIdx.x * NET_IROWS + ar;
+      if (ia < S.n && s_ok[ar])
+        P.v[(size_t)ia * LSD_NET_MAX_BASIS + li] = li < B ? acc2[q] * sc2 : 0.0f;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Training: block (atom tile, frame f)
 // ---------------------------------------------------------------------------
@@ -557,6 +693,51 @@ __global__ __launch_bounds__(NET_THREADS) void k_nt_back(SysDev S, ListDev Lst, 
   }
 }
 
+// Calibration of the FP8 activation scales: per block the largest |D| and
+// |silu(z)| of its valid atom frames, then one block takes the maximum.
+__global__ __launch_bounds__(NET_ROWS) void k_nt_amax(SysDev S, WinDev W, NetTrainDev T, int Din) {
+  __shared__ float s_m[2][NET_ROWS];
+  const int a = threadIdx.x, f = blockIdx.y;
+  const int i0 = blockIdx.x * NET_ROWS + a;
+  const bool in = i0 < S.n;
+  const int i = in ? i0 : S.n - 1;
+  const bool ok = in && W.invalid[(size_t)S.atom_rep[i] * S.kmax + f] == 0;
+  const size_t fi = (size_t)f * S.n + i;
+  float mD = 0.0f, mh = 0.0f;
+  if (ok) {
+    for (int d = 0; d < Din; ++d) mD = fmaxf(mD, fabsf(T.D[fi * LSD_NET_MAX_DESC + d]));
+    for (int h = 0; h < LSD_NET_HIDDEN; ++h)
+      mh = fmaxf(mh, fabsf(silu(T.z[fi * LSD_NET_HIDDEN + h])));
+  }
+  s_m[0][a] = mD;
+  s_m[1][a] = mh;
+  __syncthreads();
+  if (a < 2) {
+    float m = 0.0f;
+    for (int q = 0; q < NET_ROWS; ++q) m = fmaxf(m, s_m[a][q]);
+    T.partial[((size_t)f * T.nblk + blockIdx.x) * 2 + a] = (double)m;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_nt_amax_final(const double* __restrict__ part, int rows,
+                                                       double* __restrict__ out) {
+  __shared__ double s_m[2][256];
+  const int t = threadIdx.x;
+  double m0 = 0.0, m1 = 0.0;
+  for (int b = t; b < rows; b += 256) {
+    m0 = fmax(m0, part[(size_t)b * 2]);
+    m1 = fmax(m1, part[(size_t)b * 2 + 1]);
+  }
+  s_m[0][t] = m0;
+  s_m[1][t] = m1;
+  __syncthreads();
+  if (t < 2) {
+    double m = 0.0;
+    for (int q = 0; q < 256; ++q) m = fmax(m, s_m[t][q]);
+    out[t] = m;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_nt_reduce(const double* __restrict__ partial, int rows,
                                                    int np, double* __restrict__ grad) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -625,7 +806,8 @@ NetTrainDev net_train_bind(char* base, int K, int N) {
 hipError_t launch_net_nodes(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P,
                             int k, hipStream_t st) {
   const dim3 grid((S.n + NET_IROWS - 1) / NET_IROWS), block(NET_ITHREADS);
-  if (P.prec == 1) hipLaunchKernelGGL(k_net_nodes_bf16, grid, block, 0, st, S, L, W, P, k);
+  if (P.prec == 2) hipLaunchKernelGGL(k_net_nodes_fp8, grid, block, 0, st, S, L, W, P, k);
+  else if (P.prec == 1) hipLaunchKernelGGL(k_net_nodes_bf16, grid, block, 0, st, S, L, W, P, k);
   else hipLaunchKernelGGL(k_net_nodes_f32, grid, block, 0, st, S, L, W, P, k);
   return hipGetLastError();
 }
@@ -651,6 +833,18 @@ hipError_t launch_net_train(const SysDev& S, const ListDev& L, const WinDev& W, 
   const int np = net_params(P.ns, P.nb);
   hipLaunchKernelGGL(k_nt_reduce, dim3((np + 2 + 255) / 256), dim3(256), 0, st, T.partial,
                      W.K * T.nblk, np, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_net_amax(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P,
+                           const NetTrainDev& T, double* amax, hipStream_t st) {
+  hipLaunchKernelGGL(k_nt_nodes, dim3(T.nblk, W.K), dim3(NET_THREADS), 0, st, S, L, W, P, T);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_nt_amax, dim3(T.nblk, W.K), dim3(NET_ROWS), 0, st, S, W, T, P.ns * P.nb);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_nt_amax_final, dim3(1), dim3(256), 0, st, T.partial, W.K * T.nblk, amax);
   return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "liblsd.so")
 LSD_OK = 0
 MODE_LSD, MODE_PLAIN = 0, 1
 POT_LJ, POT_HARMONIC, POT_MPNN, POT_PAIR, POT_NET = 1, 2, 3, 4, 5
-PREC_FP32, PREC_BF16 = 0, 1
+PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
 NET_HIDDEN = 32
 STATUS_NBR_TARGET, STATUS_NBR_DRAFT, STATUS_CELL = 1, 2, 4
 
@@ -38,7 +38,8 @@ class Potential(C.Structure):
                 ("sigma", C.c_double), ("k_spring", C.c_double), ("anchor", C.c_void_p),
                 ("force_offset", C.c_void_p), ("weights", C.c_void_p),
                 ("n_model_species", C.c_int32), ("energy_scale", C.c_double),
-                ("n_basis", C.c_int32), ("precision", C.c_int32)]
+                ("n_basis", C.c_int32), ("precision", C.c_int32),
+                ("act_amax", C.c_double * 2)]
 
 
 class Config(C.Structure):
@@ -103,6 +104,8 @@ EXPORTS = {
     "lsd_net_train_scratch_size": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
     "lsd_net_train_accumulate": ([C.c_void_p, C.POINTER(Potential), C.c_int32, C.c_int32,
                                   C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p], C.c_int),
+    "lsd_net_activation_amax": ([C.c_void_p, C.POINTER(Potential), C.c_void_p, C.c_size_t,
+                                 C.c_void_p, C.c_void_p], C.c_int),
     "lsd_net_adam_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
                            C.c_double, C.c_double, C.c_double, C.c_int64, C.c_void_p], C.c_int),
     "lsd_destroy": ([C.c_void_p], C.c_int),
@@ -384,7 +387,10 @@ class LSDSystem:
         P.weights = wt.data_ptr()
         P.n_model_species = int(d.get("n_model_species", len(self._masses)))
         P.n_basis = int(d["n_basis"])
-        P.precision = {"fp32": PREC_FP32, "bf16": PREC_BF16}[d.get("precision", "bf16")]
+        P.precision = {"fp32": PREC_FP32, "bf16": PREC_BF16,
+                       "fp8": PREC_FP8}[d.get("precision", "bf16")]
+        if d.get("act_amax") is not None:
+            P.act_amax[0], P.act_amax[1] = (float(v) for v in d["act_amax"])
 
     # --- training of the learned draft -------------------------------------------
     def net_train_accumulate(self, net, grad, use_target=False, scratch=None, differences=False):
@@ -406,6 +412,22 @@ class LSDSystem:
                                                1 if differences else 0, _ptr(scratch), scratch.numel(), _ptr(grad),
                                                _stream(t)), "lsd_net_train_accumulate")
         return scratch
+
+    def net_activation_amax(self, net, scratch=None):
+        """(max |D|, max |h|) of the learned draft on the current window's
+        valid frames, the FP8 calibration (synchronises)."""
+        t = self.torch
+        nb = C.c_size_t()
+        _check(load().lsd_net_train_scratch_size(self.h, C.byref(nb)),
+               "lsd_net_train_scratch_size")
+        if scratch is None or scratch.numel() < nb.value:
+            scratch = t.empty((max(nb.value, 8),), dtype=t.uint8, device="cuda")
+        P = Potential()
+        self._net_fields(P, dict(net, precision="fp32"), net["weights"])
+        out = t.zeros(2, dtype=t.float64, device="cuda")
+        _check(load().lsd_net_activation_amax(self.h, C.byref(P), _ptr(scratch), scratch.numel(),
+                                              _ptr(out), _stream(t)), "lsd_net_activation_amax")
+        return out.cpu().numpy()
 
     # --- inspection -------------------------------------------------------------
     def window(self) -> Dict[str, "object"]:

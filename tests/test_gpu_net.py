@@ -12,6 +12,11 @@ Tolerances:
     sum over the atom's pairs of sum_b |e_b| (|dv_i| + |dv_j|).  The test
     evaluates this bound from the oracle's intermediates and allows 1.5x it
     plus the binary32 tolerance.
+  * FP8 node pass (OCP e4m3, 3 mantissa bits, u = 2^-4, one scale s per
+    tensor): each quantised operand errs by at most u |x| + 2^-10 s (half
+    the subnormal spacing); the same propagation through the two layers
+    bounds the force error, again with 1.5x the bound plus the binary32
+    tolerance.
   * training gradient: binary32 forward and backward passes reduced in
     binary64; 1e-4 of the largest gradient entry.
   * Adam: moments from identical binary64 inputs are bitwise equal; the
@@ -82,13 +87,18 @@ def _midpoints(w):
 
 def _bf16_bound(ora_net, species, x, L, D, z, v):
     """Force error bound of the bfloat16 node pass (module docstring)."""
-    from oracle import pairs
     u = 2.0 ** -8
     W1, b1, W2, c = ora_net.split()
     h = z / (1.0 + np.exp(-z))
     dz = 2.01 * u * (np.abs(D) @ np.abs(W1).T)
     dh = 1.1 * dz + 1.01 * u * np.abs(h)
     dv = (dh + 1.01 * u * np.abs(h)) @ np.abs(W2).T
+    return _pair_sum(x, L, species, dv)
+
+
+def _pair_sum(x, L, species, dv):
+    """Per atom, sum over its pairs of sum_b |e_b| (dv_i[b] + dv_j[b])."""
+    from oracle import pairs
     rec = pairs(x, L, RC, method="cells")
     i, j = rec[:, 0], rec[:, 1]
     d = x[j] + L * rec[:, 2:5] - x[i]
@@ -135,6 +145,60 @@ def test_net_draft_forces_match_oracle(torch, lsd, ora, precision):
         bound = _bf16_bound(ref_net, w.species, xm, L, D, z, v)
         assert np.all(err <= 1.5 * bound + tol32), np.max(err / (1.5 * bound + tol32))
         assert np.max(err) > tol32  # the bfloat16 path really ran
+    assert g.status() == 0
+    g.destroy()
+
+
+def _fp8_bound(ora_net, species, x, L, D, z, amax):
+    """Force error bound of the FP8 node pass (module docstring)."""
+    u, a = 2.0 ** -4, 2.0 ** -10
+    W1, b1, W2, c = ora_net.split()
+    sD, sh = amax[0] / 448.0, amax[1] / 448.0
+    sW1, sW2 = np.abs(W1).max() / 448.0, np.abs(W2).max() / 448.0
+    eD = u * np.abs(D) + a * sD
+    eW1 = u * np.abs(W1) + a * sW1
+    dz = eD @ np.abs(W1).T + np.abs(D) @ eW1.T + eD @ eW1.T
+    h = z / (1.0 + np.exp(-z))
+    dh = 1.1 * dz
+    dh = dh + u * (np.abs(h) + dh) + a * sh
+    eW2 = u * np.abs(W2) + a * sW2
+    dv = dh @ np.abs(W2).T + np.abs(h) @ eW2.T + dh @ eW2.T
+    return _pair_sum(x, L, species, dv)
+
+
+def test_net_draft_fp8_within_rounding_bound(torch, lsd, ora):
+    _say("learned draft forces (fp8) and activation calibration")
+    from oracle.net import NetDraft
+    w = W.triatomic_liquid(64, seed=31, K=2)
+    L = float(w.box[0])
+    p = _params(lsd, 3)
+    xm = _midpoints(w)
+    ref_net = NetDraft(S_, B_, RC, p.astype(np.float64))
+    ref, D, z, v = ref_net.forward(w.species, xm, L, intermediates=True)
+    h = z / (1.0 + np.exp(-z))
+    amax = (np.abs(D).max() * 1.0001, np.abs(h).max() * 1.0001)
+    pt = torch.tensor(p, dtype=torch.float32, device="cuda")
+    draft = dict(kind="net", rc=RC, weights=pt, n_basis=B_, n_model_species=S_,
+                 precision="fp8", act_amax=amax)
+    target = dict(kind="mpnn", rc=5.0, weights=W.mpnn_weights(3, seed=17), n_model_species=3,
+                  scale=1.0)
+    g = lsd.LSDSystem(w, mode="lsd", target=target, draft=draft)
+    g.draft_steps(1)
+    torch.cuda.synchronize()
+    win = g.window()
+    assert np.array_equal(win["q_mid"][0, :, :3].double().cpu().numpy(), xm)
+    fd = win["f_draft"][0].double().cpu().numpy().T
+    scale = np.max(np.abs(ref))
+    err = np.abs(fd - ref)
+    bound = 1.5 * _fp8_bound(ref_net, w.species, xm, L, D, z, amax) + 2e-5 * scale
+    assert np.all(err <= bound), np.max(err / bound)
+    # FP8 rounds far more than bfloat16: the error is visible but bounded
+    assert np.max(err) > 1e-3 * scale
+    # the calibration pass returns the maxima of the valid frame exactly up
+    # to binary32 evaluation
+    got = g.net_activation_amax(dict(draft, weights=pt))
+    assert got[0] == pytest.approx(amax[0] / 1.0001, rel=1e-5)
+    assert got[1] == pytest.approx(amax[1] / 1.0001, rel=1e-5)
     assert g.status() == 0
     g.destroy()
 
