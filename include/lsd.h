@@ -289,10 +289,10 @@ LSD_API lsd_status lsd_run_windows(lsd_system *sys, int32_t n_windows, int32_t K
 /* Autotuner of the verification kernel (LSD mode, pair targets): drafts a
  * window of K frames from the committed state (as lsd_draft_steps; the state
  * is left DRAFTED, so the caller continues with lsd_verify_window), times
- * the kernel with 1, 2 and 4 frames per wave on those frames (one untimed
+ * the kernel with 1, 2, 4 and 8 frames per wave on those frames (one untimed
  * and `repeats` timed launches each, HIP events on `stream`) and keeps the
  * fastest for windows of K frames.  Outputs: chosen (host, frames per wave)
- * and us (host [3], mean microseconds per launch of each candidate), each
+ * and us (host [4], mean microseconds per launch of each candidate), each
  * optional.  Captured window graphs are dropped.  Synchronises `stream`. */
 LSD_API lsd_status lsd_autotune_verify(lsd_system *sys, int32_t K, int32_t repeats,
                                        int32_t *chosen, double *us, lsd_stream stream);

@@ -829,10 +829,10 @@ lsd_status lsd_autotune_verify(lsd_system* s, int32_t K, int32_t repeats, int32_
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  static const int kCandidates[3] = {1, 2, 4};
+  static const int kCandidates[4] = {1, 2, 4, 8};
   int best = verify_fw(s, K);
   float best_ms = 0.0f;
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < 4; ++c) {
     const int fw = kCandidates[c];
     // one untimed launch, then `repeats` timed ones on the same drafted frames
     // (verification only writes f_target and the per-tile sums: repeatable)

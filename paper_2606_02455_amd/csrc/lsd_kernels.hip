@@ -320,6 +320,18 @@ __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev 
   }
 }
 
+// Tether force and energy of atom i at position xi (minimum image).
+__device__ __forceinline__ void tether_force(const PotDev& P, const SysDev& S, float4 xi, int i,
+                                             float Lf, float& fx, float& fy, float& fz, float& e) {
+  float d[3] = {xi.x - P.anchor[i], xi.y - P.anchor[S.n + i], xi.z - P.anchor[2 * S.n + i]};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) d[a] -= Lf * rintf(d[a] / Lf);
+  fx = -P.kspring * d[0];
+  fy = -P.kspring * d[1];
+  fz = -P.kspring * d[2];
+  e = 0.5f * P.kspring * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+}
+
 // Force of potential P on atom i at frame positions X.  The LSD_LPA lanes of
 // an atom share the list row: lane `sub` sums the entries m = sub, sub + LPA,
 // ... in order, and the partial sums are combined by the fixed butterfly of
@@ -374,13 +386,7 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
   } else if (P.kind == LSD_POT_NET) {
     net_force(P, S, X, row, cnt, i, r, sub, fx, fy, fz);
   } else if (P.kind == LSD_POT_HARMONIC) {
-    float d[3] = {xi.x - P.anchor[i], xi.y - P.anchor[S.n + i], xi.z - P.anchor[2 * S.n + i]};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) d[a] -= Lf * rintf(d[a] / Lf);
-    fx = -P.kspring * d[0];
-    fy = -P.kspring * d[1];
-    fz = -P.kspring * d[2];
-    e = 0.5f * P.kspring * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    tether_force(P, S, xi, i, Lf, fx, fy, fz, e);
   }
   if (P.offset) {
     fx += P.offset[i];
@@ -585,9 +591,11 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, 
         Ft[2] = lpa_sum(fz[f]);
         e = lpa_sum(en[f]);
       } else {
-        pot_force(P, S, W.qmid + (size_t)(f0 + f) * N, nullptr, 0, i, r, sub, Ft[0], Ft[1], Ft[2], e);
+        // the other target kind here is the tether (network targets take
+        // the batched path; the drafts are never targets)
+        tether_force(P, S, xi[f], i, Lf, Ft[0], Ft[1], Ft[2], e);
       }
-      if (lj && P.offset) {
+      if (P.offset) {
         Ft[0] += P.offset[i];
         Ft[1] += P.offset[N + i];
         Ft[2] += P.offset[2 * N + i];
@@ -971,6 +979,12 @@ hipError_t launch_frame_validity(const SysDev& S, const ListDev& L, const WinDev
 
 static size_t verify_lds(int mt) { return (size_t)mt * VROW * sizeof(uint32_t); }
 
+// frames per wave: up to LSD_VERIFY_FW_MAX (chosen per window length by the
+// caller or the autotuner)
+#ifndef LSD_VERIFY_FW_MAX
+#define LSD_VERIFY_FW_MAX 8
+#endif
+
 hipError_t prepare_verify(int mt) {
   const int lds = (int)verify_lds(mt);
   hipError_t e = hipFuncSetAttribute((const void*)k_verify<1>,
@@ -979,24 +993,25 @@ hipError_t prepare_verify(int mt) {
     e = hipFuncSetAttribute((const void*)k_verify<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_verify<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_verify<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   return e;
 }
 
-// frames per wave: up to LSD_VERIFY_FW_MAX for long windows; fewer when the
-// window is short
-#ifndef LSD_VERIFY_FW_MAX
-#define LSD_VERIFY_FW_MAX 4
-#endif
 hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                          const PotDev& P, int fw, hipStream_t st) {
   const size_t lds = verify_lds(L.mt);
   if (fw > LSD_VERIFY_FW_MAX) fw = LSD_VERIFY_FW_MAX;
-  if (fw >= 4) {
-    hipLaunchKernelGGL(k_verify<4>, dim3(S.n_tiles, (W.K + 3) / 4), dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
+  fw = fw >= 8 ? 8 : (fw >= 4 ? 4 : (fw == 2 ? 2 : 1));
+  const dim3 grid(S.n_tiles, (W.K + fw - 1) / fw);
+  if (fw == 8) {
+    hipLaunchKernelGGL(k_verify<8>, grid, dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
+  } else if (fw == 4) {
+    hipLaunchKernelGGL(k_verify<4>, grid, dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
   } else if (fw == 2) {
-    hipLaunchKernelGGL(k_verify<2>, dim3(S.n_tiles, (W.K + 1) / 2), dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<2>, grid, dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
   } else {
-    hipLaunchKernelGGL(k_verify<1>, dim3(S.n_tiles, W.K), dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<1>, grid, dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
   }
   return hipGetLastError();
 }

@@ -475,10 +475,10 @@ class LSDSystem:
         kernel for windows of K frames; drafts one window (left drafted).
         Returns (chosen, {fw: microseconds})."""
         ch = C.c_int32()
-        us = (C.c_double * 3)()
+        us = (C.c_double * 4)()
         _check(load().lsd_autotune_verify(self.h, int(K), int(repeats), C.byref(ch), us,
                                           _stream(self.torch)), "lsd_autotune_verify")
-        return int(ch.value), {1: us[0], 2: us[1], 4: us[2]}
+        return int(ch.value), {1: us[0], 2: us[1], 4: us[2], 8: us[3]}
 
     def set_graphs(self, on=True):
         """Replay captured HIP graphs in run_windows (default) or not."""

@@ -593,7 +593,7 @@ def test_autotuned_verification_gives_identical_results(torch, lsd):
     a = lsd.LSDSystem(w, mode="lsd")
     b = lsd.LSDSystem(w, mode="lsd")
     chosen, us = a.autotune_verify(8, repeats=3)
-    assert chosen in (1, 2, 4) and all(v > 0 for v in us.values())
+    assert chosen in (1, 2, 4, 8) and all(v > 0 for v in us.values())
     a.verify_window()
     a.accept_rollback()
     b.draft_steps(8)
