@@ -354,3 +354,91 @@ def test_net_training_reduces_the_force_error(torch, lsd):
         lsd.net_adam_step(torch, pt, m, v, grad, 1e-2, t)
     assert losses[1] < 0.2 * losses[0], losses
     g.destroy()
+
+
+def _replica_frames(w, K, seed):
+    """K frames per replica: the wrapped start and small perturbations of it,
+    each replica in its own box."""
+    rng = np.random.default_rng(seed)
+    frames = np.zeros((K, w.n_atoms, 3))
+    for r in range(w.n_replicas):
+        sl = w.replica_slice(r)
+        L = float(w.box[r])
+        base = W.f32(np.mod(w.positions[sl], L))
+        base[base >= L] = 0.0
+        frames[0, sl] = base
+        for k in range(1, K):
+            frames[k, sl] = W.f32(np.clip(base + rng.normal(scale=0.02, size=base.shape), 0,
+                                          L * (1 - 1e-6)))
+    return frames
+
+
+def test_net_on_ragged_replicas(torch, lsd, ora):
+    # replicas of 21..39 atoms: the 16-atom node blocks and 64-atom training
+    # blocks straddle replicas, each box is small enough for 27 images
+    _say("learned draft on ragged replicas")
+    from oracle.net import NetDraft
+    w = W.triatomic_replicas(3, n_mol_lo=7, n_mol_hi=13, seed=35, K=3)
+    assert w.n_atoms % 16 != 0
+    p = _params(lsd, 8)
+    ref_net = NetDraft(S_, B_, RC, p.astype(np.float64))
+    # drafting forces at the first midpoints, replica by replica
+    g = lsd.LSDSystem(w, mode="lsd", target=dict(kind="harmonic", k=1.0, anchor=w.positions),
+                      draft=dict(kind="net", rc=RC, weights=p, n_basis=B_, n_model_species=S_,
+                                 precision="fp32"))
+    g.draft_steps(1)
+    torch.cuda.synchronize()
+    x0 = g.window()["q_mid"][0, :, :3].double().cpu().numpy()
+    fd = g.window()["f_draft"][0].double().cpu().numpy().T
+    for r in range(w.n_replicas):
+        sl = w.replica_slice(r)
+        L = float(w.box[r])
+        ref = ref_net.forces(w.species[sl], np.mod(x0[sl], L), L)
+        assert np.max(np.abs(fd[sl] - ref)) <= 2e-5 * np.max(np.abs(ref)), r
+    g.destroy()
+    # training gradient over caller frames of every replica
+    K = w.K
+    frames = _replica_frames(w, K, seed=36)
+    teacher = NetDraft(S_, B_, RC, _params(lsd, 9).astype(np.float64))
+    ys = np.zeros_like(frames)
+    for r in range(w.n_replicas):
+        sl = w.replica_slice(r)
+        for k in range(K):
+            ys[k, sl] = teacher.forces(w.species[sl], frames[k, sl], float(w.box[r]))
+    ys = W.f32(ys)
+    target = dict(kind="mpnn", rc=5.0, weights=W.mpnn_weights(3, seed=17), n_model_species=3,
+                  scale=1.0)
+    g = lsd.LSDSystem(w, mode="lsd", target=target,
+                      draft=dict(kind="harmonic", k=0.0, anchor=w.positions))
+    g.set_state(w.positions, np.zeros_like(w.positions))
+    win = g.window()
+    q4 = np.zeros((K, w.n_atoms, 4), np.float32)
+    q4[:, :, :3] = frames
+    win["q_mid"][:K].copy_(torch.tensor(q4))
+    win["p_draft"][:K + 1].zero_()
+    win["f_draft"][:K].copy_(torch.tensor(np.transpose(ys, (0, 2, 1)).copy(), dtype=torch.float32))
+    torch.cuda.synchronize()
+    g.mark_drafted(K)
+    pt = torch.tensor(p, dtype=torch.float32, device="cuda")
+    net = dict(kind="net", rc=RC, weights=pt, n_basis=B_, n_model_species=S_)
+    P = p.size
+    for diff in (False, True):
+        grad = torch.zeros(P + 2, dtype=torch.float64, device="cuda")
+        g.net_train_accumulate(net, grad, differences=diff)
+        torch.cuda.synchronize()
+        assert int(win["frame_invalid"][:, :K].sum()) == 0
+        gg = grad.cpu().numpy()
+        gr, sse = np.zeros(P), 0.0
+        for r in range(w.n_replicas):
+            sl = w.replica_slice(r)
+            L = float(w.box[r])
+            if diff:
+                sse += ref_net.diff_sse_grad(w.species[sl], frames[:, sl], L, ys[:, sl], grad=gr)[0]
+            else:
+                for k in range(K):
+                    sse += ref_net.sse_grad(w.species[sl], frames[k, sl], L, ys[k, sl], grad=gr)[0]
+        assert gg[P + 1] == (K - 1 if diff else K) * w.n_atoms
+        assert gg[P] == pytest.approx(sse, rel=1e-4)
+        tol = (1e-3 if diff else 1e-4) * np.max(np.abs(gr))
+        assert np.max(np.abs(gg[:P] - gr)) <= tol, (diff, np.max(np.abs(gg[:P] - gr)) / tol)
+    g.destroy()
