@@ -453,6 +453,39 @@ LSD_API lsd_status lsd_net_adam_step(float *params, double *m, double *v, double
                                      int32_t n_params, double lr, double beta1, double beta2,
                                      double eps, int64_t t, lsd_stream stream);
 
+/* Verifier state of pipelined LSD (Alg. 2, App. C): host-only bookkeeping
+ * for callers that submit every draft step for verification as soon as it
+ * is drafted and receive target results in any order (a pool of target
+ * workers).  Steps are identified by ids 1, 2, ... in submission order; id
+ * 0 is the initial state, verified from the start.  The caller keeps the
+ * draft and target states by id.
+ *   lsd_pipeline_submit: registers the next draft step as eligible pending
+ *     and returns its id.
+ *   lsd_pipeline_return: a target result for `id` arrived, accepted != 0
+ *     if the coupled target state equals the draft state.  If the step was
+ *     flushed by an earlier rejection (or already returned), *ignored = 1
+ *     and nothing changes.  Otherwise it becomes conditionally verified; if
+ *     rejected, every later step is flushed and *rollback = 1: the caller
+ *     continues drafting from this step's target state.  Then every
+ *     conditionally verified step that precedes all pending ones is
+ *     appended to the verified sequence, in id order.
+ *   lsd_pipeline_take_verified: copies up to `cap` ids appended to the
+ *     verified sequence since the last call (host array) and their count.
+ *   lsd_pipeline_counts: out[3] = {pending, conditionally verified,
+ *     verified (including id 0)}.
+ * Every verified sequence satisfies the paper's recursive correctness
+ * condition: each state is a target sample conditioned on its predecessor.
+ * No GPU work; not thread-safe for one handle. */
+typedef struct lsd_pipeline lsd_pipeline;
+LSD_API lsd_status lsd_pipeline_create(lsd_pipeline **out);
+LSD_API lsd_status lsd_pipeline_destroy(lsd_pipeline *pipe);
+LSD_API lsd_status lsd_pipeline_submit(lsd_pipeline *pipe, int64_t *id);
+LSD_API lsd_status lsd_pipeline_return(lsd_pipeline *pipe, int64_t id, int32_t accepted,
+                                       int32_t *ignored, int32_t *rollback);
+LSD_API lsd_status lsd_pipeline_take_verified(lsd_pipeline *pipe, int64_t *ids, int32_t cap,
+                                              int32_t *n);
+LSD_API lsd_status lsd_pipeline_counts(const lsd_pipeline *pipe, int64_t *out);
+
 /* Releases the handle and its HIP events (no device memory is freed). */
 LSD_API lsd_status lsd_destroy(lsd_system *sys);
 

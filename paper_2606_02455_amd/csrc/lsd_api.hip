@@ -333,6 +333,9 @@ struct TimingRing {
 
 }  // namespace
 
+// Error text for the host-only parts of the library in other files.
+lsd_status lsd_record_error(lsd_status s, const char* msg) { return fail(s, "%s", msg); }
+
 // Executable graphs of one window, per window length K: the whole window,
 // or (when the verification launch is timed) the parts before and after it.
 struct WindowGraphs {

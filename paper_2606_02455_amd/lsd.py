@@ -108,6 +108,14 @@ EXPORTS = {
                                  C.c_void_p, C.c_void_p], C.c_int),
     "lsd_net_adam_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
                            C.c_double, C.c_double, C.c_double, C.c_int64, C.c_void_p], C.c_int),
+    "lsd_pipeline_create": ([C.POINTER(C.c_void_p)], C.c_int),
+    "lsd_pipeline_destroy": ([C.c_void_p], C.c_int),
+    "lsd_pipeline_submit": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
+    "lsd_pipeline_return": ([C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int32)], C.c_int),
+    "lsd_pipeline_take_verified": ([C.c_void_p, C.POINTER(C.c_int64), C.c_int32,
+                                    C.POINTER(C.c_int32)], C.c_int),
+    "lsd_pipeline_counts": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "lsd_destroy": ([C.c_void_p], C.c_int),
     "lsd_last_error": ([], C.c_char_p),
 }
@@ -551,3 +559,41 @@ class LSDSystem:
             self.destroy()
         except Exception:
             pass
+
+
+class Pipeline:
+    """Verifier state of pipelined LSD (lsd_pipeline_*): host bookkeeping of
+    eligible-pending, conditionally verified and verified step ids."""
+
+    def __init__(self):
+        self.h = C.c_void_p()
+        _check(load().lsd_pipeline_create(C.byref(self.h)), "lsd_pipeline_create")
+
+    def submit(self):
+        i = C.c_int64()
+        _check(load().lsd_pipeline_submit(self.h, C.byref(i)), "lsd_pipeline_submit")
+        return int(i.value)
+
+    def returned(self, step_id, accepted):
+        """(ignored, rollback) for a target result of step `step_id`."""
+        ig, rb = C.c_int32(), C.c_int32()
+        _check(load().lsd_pipeline_return(self.h, int(step_id), 1 if accepted else 0,
+                                          C.byref(ig), C.byref(rb)), "lsd_pipeline_return")
+        return bool(ig.value), bool(rb.value)
+
+    def take_verified(self, cap=4096):
+        ids = (C.c_int64 * cap)()
+        n = C.c_int32()
+        _check(load().lsd_pipeline_take_verified(self.h, ids, cap, C.byref(n)),
+               "lsd_pipeline_take_verified")
+        return [int(v) for v in ids[:n.value]]
+
+    def counts(self):
+        out = (C.c_int64 * 3)()
+        _check(load().lsd_pipeline_counts(self.h, out), "lsd_pipeline_counts")
+        return tuple(int(v) for v in out)
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().lsd_pipeline_destroy(self.h)
+            self.h = C.c_void_p()
