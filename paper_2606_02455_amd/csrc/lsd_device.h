@@ -437,7 +437,9 @@ __device__ __forceinline__ void image_shifts(int code, float Lf, float sj[3], fl
 // force loops: the row entries, then the neighbour positions and species,
 // so that the gathers of several entries are in flight at once.  Entries are
 // still added in the lane's order.
+#ifndef LSD_GATHER
 #define LSD_GATHER 4
+#endif
 struct Gathered {
   float4 x[LSD_GATHER];
   int code[LSD_GATHER], j[LSD_GATHER], sp[LSD_GATHER];

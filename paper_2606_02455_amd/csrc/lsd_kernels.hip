@@ -346,21 +346,17 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
   const float Lf = (float)L;
   const float4 xi = X[i];
   if (P.kind == LSD_POT_LJ) {
-    // two entries per iteration (gathers issued together), added in order
-    for (int m = sub; m < cnt; m += 2 * LSD_LPA) {
-      const bool two = m + LSD_LPA < cnt;
-      const uint32_t e0 = row[m];
-      const uint32_t e1 = row[two ? m + LSD_LPA : m];
-      const int j0 = (int)(e0 >> 5), c0 = (int)(e0 & 31u);
-      const int j1 = (int)(e1 >> 5), c1 = (int)(e1 & 31u);
-      const float4 x0 = X[j0];
-      const float4 x1 = X[j1];
-      float sj[3], si[3];
-      image_shifts(c0, Lf, sj, si);
-      lj_pair(P, xi, x0, sj, si, c0, L, fx, fy, fz, e);
-      if (two) {
-        image_shifts(c1, Lf, sj, si);
-        lj_pair(P, xi, x1, sj, si, c1, L, fx, fy, fz, e);
+    // LSD_GATHER entries per iteration (gathers issued together), added in
+    // order
+    for (int m0 = sub; m0 < cnt; m0 += LSD_GATHER * LSD_LPA) {
+      Gathered gt;
+      gather_entries(row, cnt, m0, X, nullptr, gt);
+#pragma unroll
+      for (int u = 0; u < LSD_GATHER; ++u) {
+        if (!gt.ok[u]) break;
+        float sj[3], si[3];
+        image_shifts(gt.code[u], Lf, sj, si);
+        lj_pair(P, xi, gt.x[u], sj, si, gt.code[u], L, fx, fy, fz, e);
       }
     }
     fx = lpa_sum(fx);
