@@ -339,7 +339,11 @@ lsd_status lsd_record_error(lsd_status s, const char* msg) { return fail(s, "%s"
 // Executable graphs of one window, per window length K: the whole window,
 // or (when the verification launch is timed) the parts before and after it.
 struct WindowGraphs {
-  hipGraphExec_t full = nullptr, pre = nullptr, post = nullptr;
+  // full: a whole window; with verification timing, the kernels before the
+  // verification (pre), after it (post), and post of one window followed
+  // by pre of the next (mid), so that one graph launch sits between two
+  // timed verifications
+  hipGraphExec_t full = nullptr, pre = nullptr, post = nullptr, mid = nullptr;
 };
 
 struct lsd_system {
@@ -404,17 +408,22 @@ void destroy_graphs(lsd_system* s) {
     if (kv.second.full) (void)hipGraphExecDestroy(kv.second.full);
     if (kv.second.pre) (void)hipGraphExecDestroy(kv.second.pre);
     if (kv.second.post) (void)hipGraphExecDestroy(kv.second.post);
+    if (kv.second.mid) (void)hipGraphExecDestroy(kv.second.mid);
   }
   s->graphs.clear();
 }
 
-enum Part { PART_FULL = 0, PART_PRE = 1, PART_POST = 2 };
+enum Part { PART_FULL = 0, PART_PRE = 1, PART_POST = 2, PART_MID = 3 };
 
 // Enqueues the kernels of one window part on `st` (no state checks).
 hipError_t enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
   const bool plain = s->cfg.mode == LSD_MODE_PLAIN;
   hipError_t e = hipSuccess;
   s->W.K = K;
+  if (part == PART_MID) {
+    e = enqueue_part(s, K, PART_POST, st);
+    return e == hipSuccess ? enqueue_part(s, K, PART_PRE, st) : e;
+  }
   if (part == PART_FULL || part == PART_PRE) {
     e = launch_window_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, st);
     if (e == hipSuccess) e = launch_build_lists(s->S, s->Lst, s->W, false, st);
@@ -799,13 +808,14 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
   if (!timed && !G.full) LSD_TRY(capture(s, K, PART_FULL, &G.full));
   if (timed && !G.pre) LSD_TRY(capture(s, K, PART_PRE, &G.pre));
   if (timed && !G.post) LSD_TRY(capture(s, K, PART_POST, &G.post));
+  if (timed && !G.mid) LSD_TRY(capture(s, K, PART_MID, &G.mid));
   s->W.K = K;
   for (int w = 0; w < n_windows; ++w) {
     if (!timed) {
       HIP_TRY(hipGraphLaunch(G.full, st));
       continue;
     }
-    HIP_TRY(hipGraphLaunch(G.pre, st));
+    if (w == 0) HIP_TRY(hipGraphLaunch(G.pre, st));
     TimingRing& R = s->ring;
     if (R.used == kTimingRing) LSD_TRY(timing_drain_one(s));
     const int slot = (R.head + R.used) % kTimingRing;
@@ -814,7 +824,7 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
     HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st));
     HIP_TRY(hipEventRecord(R.stop[slot], st));
     R.used += 1;
-    HIP_TRY(hipGraphLaunch(G.post, st));
+    HIP_TRY(hipGraphLaunch(w + 1 < n_windows ? G.mid : G.post, st));
   }
   s->state = ST_COMMITTED;
   return LSD_OK;

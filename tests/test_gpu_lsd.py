@@ -607,3 +607,25 @@ def test_autotuned_verification_gives_identical_results(torch, lsd):
     assert np.array_equal(a.log_ratio.cpu().numpy(), b.log_ratio.cpu().numpy())
     a.destroy()
     b.destroy()
+
+
+def test_timed_windows_equal_untimed_windows(torch, lsd):
+    # with verification timing the windows run as graph parts around an
+    # event-bracketed verification launch; the trajectory is unchanged and
+    # every launch is timed
+    _say("timed vs untimed windows")
+    w = W.config("c1")
+    a = lsd.LSDSystem(w, mode="lsd")
+    b = lsd.LSDSystem(w, mode="lsd")
+    b.set_verify_timing(True)
+    for n in (1, 7, 50):
+        a.run_windows(n, 8)
+        b.run_windows(n, 8)
+    sa, sb = a.state(), b.state()
+    for k in ("q", "p", "img", "step"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert np.array_equal(a.counters(), b.counters())
+    ms, n = b.verify_timing()
+    assert n == 58 and 0.0 < ms / n < 5.0, (ms, n)
+    a.destroy()
+    b.destroy()
