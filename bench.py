@@ -310,7 +310,8 @@ def main():
                     help="c3/c4: radial functions of the pair and learned drafts")
     ap.add_argument("--draft", choices=["net", "pair"], default="net",
                     help="c3/c4: the learned draft (trained from the pair draft) or the pair draft")
-    ap.add_argument("--net-precision", choices=["bf16", "fp32", "fp8"], default="bf16")
+    ap.add_argument("--net-precision", choices=["bf16", "fp32", "fp8"], default=None,
+                    help="node pass of the learned draft (default: fp8 for c5, else bf16)")
     ap.add_argument("--net-train-windows", type=int, default=None,
                     help="c3/c4: Adam steps, one window of K target frames each "
                          "(default 2000 for c3, 500 for c4)")
@@ -323,6 +324,8 @@ def main():
                          "extrapolated from the last two committed errors; auto: the better "
                          "measured setting of the configuration (c1, c2: on; c3: linear)")
     args = ap.parse_args()
+    if args.net_precision is None:
+        args.net_precision = "fp8" if args.config == "c5" else "bf16"
     if args.fit_frames is None:
         args.fit_frames = 2000 if args.config in ("c4", "c5") else 20000
     if args.net_train_windows is None:
