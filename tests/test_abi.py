@@ -146,3 +146,47 @@ def test_net_parameter_layout(lib, ora):
     W1, b1, W2, c = NetDraft(3, 8, 4.0, p.astype(np.float64)).split()
     assert np.all(W2 == 0) and np.all(b1 == 0) and np.array_equal(c.ravel(), pw)
     assert np.std(W1) > 0.1
+
+
+def test_learned_draft_configuration_is_validated(lib):
+    # host-only: the workspace query validates the draft like init does
+    from paper_2606_02455_amd import lsd
+    from paper_2606_02455_amd import workloads as W
+    w = W.triatomic_liquid(64, seed=3)
+    weights = np.zeros(lsd.net_param_count(3, 16), np.float32)
+
+    def cfg_with(**net):
+        cfg, keep = _cfg(lsd, w, n_species=3)
+        d = cfg.draft
+        d.kind, d.cutoff, d.weights = lsd.POT_NET, 4.0, weights.ctypes.data
+        d.n_model_species, d.n_basis, d.precision = 3, 16, lsd.PREC_BF16
+        for k, v in net.items():
+            setattr(d, k, v)
+        return cfg, keep
+
+    n = C.c_size_t()
+    cfg, keep = cfg_with()
+    assert lib.lsd_workspace_size(C.byref(cfg), C.byref(n)) == 0, lib.lsd_last_error()
+    bad = [dict(n_basis=17), dict(n_basis=0), dict(n_model_species=5),
+           dict(n_model_species=2),   # fewer than the system's species
+           dict(precision=3), dict(precision=lsd.PREC_FP8),   # FP8 without calibration
+           dict(cutoff=0.0), dict(weights=None)]
+    for b in bad:
+        cfg, keep = cfg_with(**b)
+        assert lib.lsd_workspace_size(C.byref(cfg), C.byref(n)) == -1, b
+        assert lib.lsd_last_error().decode() != ""
+    cfg, keep = cfg_with(precision=lsd.PREC_FP8)
+    cfg.draft.act_amax[0], cfg.draft.act_amax[1] = 2.0, 1.5
+    assert lib.lsd_workspace_size(C.byref(cfg), C.byref(n)) == 0, lib.lsd_last_error()
+    # drafts are never targets
+    cfg, keep = cfg_with()
+    cfg.target = cfg.draft
+    assert lib.lsd_workspace_size(C.byref(cfg), C.byref(n)) == -5
+
+
+def test_autotune_and_net_calls_on_null_handle_fail_cleanly(lib):
+    ch = C.c_int32()
+    assert lib.lsd_autotune_verify(None, 8, 1, C.byref(ch), None, None) == -1
+    assert lib.lsd_net_train_accumulate(None, None, 0, 0, None, 0, None, None) == -1
+    assert lib.lsd_net_adam_step(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None) == -1
+    assert lib.lsd_pipeline_submit(None, None) == -1
