@@ -135,3 +135,67 @@ def test_lj_lsd_marginals_match_plain_target(torch, lsd, ora):
     assert stats.ks_2samp(Ed, Ep).pvalue < 1e-3
     for s in (g, p, ge, d):
         s.destroy()
+
+
+def _nearest_neighbour_distances(w, q):
+    out = []
+    for r in range(w.n_replicas):
+        x = q[w.replica_slice(r)]
+        L = float(w.box[r])
+        d = x[:, None, :] - x[None, :, :]
+        d -= L * np.round(d / L)
+        r2 = np.einsum("ijk,ijk->ij", d, d)
+        np.fill_diagonal(r2, np.inf)
+        out.append(np.sqrt(r2.min(axis=1)))
+    return np.concatenate(out)
+
+
+def test_learned_draft_with_network_target_keeps_the_target_law(torch, lsd):
+    # LSD with the learned draft (bfloat16 node pass, linear error
+    # correction) against plain target Langevin on independent random
+    # streams, both from the same start and stopped at the same step: the
+    # laws of the momenta and of the nearest-neighbour distances agree
+    _say("network target + learned draft: LSD vs plain marginals")
+    import dataclasses
+    base = W.triatomic_replicas(96, n_mol_lo=8, n_mol_hi=12, seed=51, K=8)
+    target = W.mpnn_target()
+    # a draft worth having: the pair draft fitted on a few plain windows,
+    # as the starting point of the learned draft
+    fit = lsd.LSDSystem(dataclasses.replace(base, seed=60), mode="plain", target=target)
+    P = lsd.pair_params(3, 16)
+    gram = torch.zeros((P + 1, P + 1), dtype=torch.float64, device="cuda")
+    scratch = None
+    for _ in range(12):
+        fit.draft_steps(8)
+        scratch = fit.fit_pair_accumulate(16, 4.0, gram, scratch=scratch, differences=True)
+        fit.accept_rollback()
+    wts = lsd.fit_pair_solve(gram.cpu().numpy(), ridge=1e-8)
+    fit.destroy()
+    p = lsd.net_init_params(3, 16, pair_weights=wts, seed=3)
+    rng = np.random.default_rng(4)
+    o2 = 32 * 48 + 3 * 32
+    p[o2:o2 + 16 * 32] = rng.normal(scale=0.01, size=16 * 32)   # some many-body part
+    draft = dict(kind="net", rc=4.0, weights=p, n_basis=16, n_model_species=3, precision="bf16")
+    n_steps = 48
+    g = lsd.LSDSystem(dataclasses.replace(base, seed=61), mode="lsd", target=target, draft=draft,
+                      error_correction=2)
+    _run_until(g, n_steps, 8)
+    ref = lsd.LSDSystem(dataclasses.replace(base, seed=62), mode="plain", target=target)
+    _run_until(ref, n_steps, 8)
+    cn = g.counters()
+    rate = cn[:, 2].sum() / cn[:, 1].sum()
+    assert 0.05 < rate < 0.95, rate
+    assert g.status() == 0 and ref.status() == 0
+    sg, sr = g.state(), ref.state()
+    m = base.species_mass[base.species][:, None]
+    pg = (sg["p"] / np.sqrt(m * base.kT * base.force_unit)).ravel()
+    pr = (sr["p"] / np.sqrt(m * base.kT * base.force_unit)).ravel()
+    assert stats.ks_2samp(pg, pr).pvalue > 0.01
+    dg = _nearest_neighbour_distances(base, sg["q"])
+    dr = _nearest_neighbour_distances(base, sr["q"])
+    assert stats.ks_2samp(dg, dr).pvalue > 0.01
+    # the test has power: the start state differs from both
+    d0 = _nearest_neighbour_distances(base, base.positions)
+    assert stats.ks_2samp(dg, d0).pvalue < 1e-3
+    g.destroy()
+    ref.destroy()
