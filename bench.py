@@ -42,9 +42,10 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def read_traffic(config_name):
+def read_traffic(config_name, kernel):
     """HBM bytes per verification launch from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary, if it was taken on the current kernel source and on
+    the same kernel variant."""
     path = os.path.join(ROOT, "profiles", f"k_verify_{config_name}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -53,7 +54,7 @@ def read_traffic(config_name):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha") != source_sha():
+    if kv.get("source_sha") != source_sha() or kv.get("kernel") != kernel:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -317,6 +318,8 @@ def main():
                          "(default 2000 for c3, 500 for c4)")
     ap.add_argument("--net-lr", type=float, default=3e-3)
     ap.add_argument("--equilibrate", type=int, default=256, help="plain steps before timing")
+    ap.add_argument("--verify-fw", choices=["auto", "1", "2", "4", "8"], default="auto",
+                    help="frames per wave of the verification kernel (auto: autotune)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ec", choices=["auto", "on", "off", "linear"], default="auto",
@@ -368,11 +371,16 @@ def main():
     log(f"equilibrated {int(st0['step'][0])} plain steps")
 
     # --- verification kernel variant, tuned on this system (one window)
-    chosen_fw, fw_us = lsds.autotune_verify(K, repeats=5)
-    lsds.verify_window()
-    lsds.accept_rollback()
-    log(f"autotuned verification: {chosen_fw} frames per wave "
-        f"({', '.join(f'{k}: {v:.1f} us' for k, v in fw_us.items())})")
+    if args.verify_fw == "auto":
+        chosen_fw, fw_us = lsds.autotune_verify(K, repeats=5)
+        lsds.verify_window()
+        lsds.accept_rollback()
+        log(f"autotuned verification: {chosen_fw} frames per wave "
+            f"({', '.join(f'{k}: {v:.1f} us' for k, v in fw_us.items())})")
+    else:
+        chosen_fw, fw_us = int(args.verify_fw), {}
+        lsds.set_verify_variant(K, chosen_fw)
+        log(f"verification: {chosen_fw} frames per wave (fixed)")
 
     # --- LSD
     lsds.run_windows(args.warmup, K)
@@ -421,7 +429,7 @@ def main():
     avg_s = ver_ms / max(ver_n, 1) * 1e-3
     achieved = alg_bytes / avg_s / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=read_traffic(args.config),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=read_traffic(args.config, f"k_verify<{chosen_fw}>"),
                     kernel=f"k_verify<{chosen_fw}>", avg_us=round(avg_s * 1e6, 3),
                     autotune_us={str(k): round(v, 2) for k, v in fw_us.items()},
                     algorithmic_bytes=int(alg_bytes), frames_per_launch=round(frames_per_launch, 3),

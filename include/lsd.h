@@ -297,6 +297,12 @@ LSD_API lsd_status lsd_run_windows(lsd_system *sys, int32_t n_windows, int32_t K
 LSD_API lsd_status lsd_autotune_verify(lsd_system *sys, int32_t K, int32_t repeats,
                                        int32_t *chosen, double *us, lsd_stream stream);
 
+/* Fixes the verification kernel variant for windows of K frames (1 <= K <=
+ * k_max): frames_per_wave in {1, 2, 4, 8}, as lsd_autotune_verify would
+ * choose it, without timing (for reproducible profiles).  Captured window
+ * graphs are dropped.  LSD_ERR_INVALID_ARG for other values. */
+LSD_API lsd_status lsd_set_verify_variant(lsd_system *sys, int32_t K, int32_t frames_per_wave);
+
 /* enable != 0 (default): lsd_run_windows replays captured graphs; 0: it
  * issues the kernels of every window one by one. */
 LSD_API lsd_status lsd_set_graphs(lsd_system *sys, int32_t enable);

@@ -373,11 +373,11 @@ struct lsd_system {
 namespace {
 
 // frames per wave of the verification kernel for windows of K frames: the
-// autotuned choice if any, else 4 for long windows and fewer for short ones
+// autotuned (or fixed) choice if any, else 2 (1 for single frames)
 int verify_fw(const lsd_system* s, int K) {
   auto it = s->tuned_fw.find(K);
   if (it != s->tuned_fw.end()) return it->second;
-  return K >= 8 ? 4 : (K >= 2 ? 2 : 1);
+  return K >= 2 ? 2 : 1;
 }
 
 template <typename T>
@@ -537,7 +537,6 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   if (e == hipSuccess && L.ec) e = launch_fill_int(ws<int>(s, L.ec_samples), 0, R, st);
   if (e == hipSuccess && L.ec_prev) e = launch_fill_int(ws<int>(s, L.ec_prev), 0, 3 * N, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.rebuild), 1, R, st);  // first window builds
-  if (e == hipSuccess) e = prepare_verify(L.mt);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete s;
@@ -873,6 +872,17 @@ lsd_status lsd_autotune_verify(lsd_system* s, int32_t K, int32_t repeats, int32_
   s->tuned_fw[K] = best;
   destroy_graphs(s);  // captured windows used the previous choice
   if (chosen) *chosen = best;
+  return LSD_OK;
+}
+
+lsd_status lsd_set_verify_variant(lsd_system* s, int32_t K, int32_t frames_per_wave) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  if (K < 1 || K > s->cfg.k_max) return fail(LSD_ERR_INVALID_ARG, "K = %d outside 1..k_max", K);
+  const int fw = frames_per_wave;
+  if (fw != 1 && fw != 2 && fw != 4 && fw != 8)
+    return fail(LSD_ERR_INVALID_ARG, "frames per wave %d not in {1, 2, 4, 8}", fw);
+  s->tuned_fw[K] = fw;
+  destroy_graphs(s);
   return LSD_OK;
 }
 

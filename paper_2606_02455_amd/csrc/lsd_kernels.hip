@@ -492,19 +492,23 @@ __global__ __launch_bounds__(256) void k_frame_validity(SysDev S, ListDev Lst, W
 }
 
 // verify_step (Alg. 2) for the valid frames of the window.  Block = one tile
-// of up to 64 atoms of one replica x FW frames.  The tile's neighbour rows
-// are read once into LDS; each atom uses LSD_LPA lanes (same entry split and
-// butterfly as the draft kernel) and each lane advances all FW frames per
-// neighbour entry, so an entry is decoded once and its image shift reused.
+// of up to 64 atoms of one replica x FW frames.  Each atom uses LSD_LPA lanes
+// (same entry split and butterfly as the draft kernel), which read their
+// neighbour entries straight from the list (the lanes of an atom read
+// consecutive words; the rows stay in L1 over the loop), and each lane
+// advances all FW frames per neighbour entry, so an entry is decoded once and
+// its image shift reused.  No LDS staging: occupancy is set by the registers
+// alone (staging the rows, in full or in chunks, measured 1.4-1.9x slower).
 // Epilogue per atom and frame (binary64):
 //   z = (p~_k - <p~_k>) / sigma,  delta = c1 (F~_k - F_k) / sigma
 // reduced over the tile in a fixed order: S1 = delta.z, S2 = delta.delta,
 // and the potential energy.
-#define VROW 65  // LDS row stride (words) of the staged neighbour tile
+#ifndef LSD_VGATHER
+#define LSD_VGATHER 2  // neighbour entries per lane per iteration of k_verify
+#endif
 template <int FW>
 __global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, WinDev W,
                                                          TileDev Tl, PotDev P) {
-  extern __shared__ uint32_t s_nbr[];  // [mt][VROW]
   __shared__ float s_shift[27][6];
   __shared__ double s_red[LSD_VWAVES][FW][3];
   const int tile = blockIdx.x;
@@ -526,15 +530,6 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, 
   const size_t N = (size_t)S.n;
   const bool lj = P.kind == LSD_POT_LJ;
   if (t < 27) image_shifts(t, Lf, &s_shift[t][0], &s_shift[t][3]);
-  // stage the rows of the tile: wave w copies atoms w, w + waves, ...; 64
-  // consecutive entries of one row per instruction
-  if (lj) {
-    for (int aa = wave; aa < count; aa += LSD_VWAVES) {
-      const int ci = Lst.cnt_t[start + aa];
-      const uint32_t* row = Lst.nbr_t + (size_t)(start + aa) * Lst.mt;
-      for (int m = lane; m < ci; m += 64) s_nbr[m * VROW + aa] = row[m];
-    }
-  }
   __syncthreads();
 
   const bool active = a < count;
@@ -547,31 +542,35 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, 
     fx[f] = fy[f] = fz[f] = en[f] = 0.0f;
     xi[f] = valid[f] ? W.qmid[(size_t)(f0 + f) * N + i] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  // two entries per iteration (m, m + LSD_LPA): their gathers are issued
-  // together; the terms are added in entry order as in the draft kernel
-  for (int m = sub; m < cnt; m += 2 * LSD_LPA) {
-    const bool two = m + LSD_LPA < cnt;
-    const uint32_t e0 = s_nbr[m * VROW + a];
-    const uint32_t e1 = s_nbr[(two ? m + LSD_LPA : m) * VROW + a];
-    const int j0 = (int)(e0 >> 5), c0 = (int)(e0 & 31u);
-    const int j1 = (int)(e1 >> 5), c1 = (int)(e1 & 31u);
-    float4 x0[FW], x1[FW];
+  const uint32_t* row = Lst.nbr_t + (size_t)i * Lst.mt;
+  // LSD_VGATHER entries per iteration (m, m + LSD_LPA, ...): their gathers
+  // are issued together; the terms are added in entry order as in the draft
+  // kernel
+  for (int m0 = sub; m0 < cnt; m0 += LSD_VGATHER * LSD_LPA) {
+    int jj[LSD_VGATHER], cc[LSD_VGATHER];
 #pragma unroll
-    for (int f = 0; f < FW; ++f) {
-      // frame f0 exists in every block; an invalid frame's load is unused
-      const size_t fr = (size_t)(valid[f] ? f0 + f : f0) * N;
-      x0[f] = W.qmid[fr + j0];
-      x1[f] = W.qmid[fr + j1];
+    for (int u = 0; u < LSD_VGATHER; ++u) {
+      const int m = m0 + u * LSD_LPA;
+      const uint32_t e = row[m < cnt ? m : m0];
+      jj[u] = (int)(e >> 5);
+      cc[u] = (int)(e & 31u);
     }
-    const float* sh0 = s_shift[c0];
-    const float* sh1 = s_shift[c1];
+    float4 xj[LSD_VGATHER][FW];
 #pragma unroll
-    for (int f = 0; f < FW; ++f)
-      if (valid[f]) lj_pair(P, xi[f], x0[f], sh0, sh0 + 3, c0, L, fx[f], fy[f], fz[f], en[f]);
-    if (two) {
+    for (int u = 0; u < LSD_VGATHER; ++u)
+#pragma unroll
+      for (int f = 0; f < FW; ++f) {
+        // frame f0 exists in every block; an invalid frame's load is unused
+        const size_t fr = (size_t)(valid[f] ? f0 + f : f0) * N;
+        xj[u][f] = W.qmid[fr + jj[u]];
+      }
+#pragma unroll
+    for (int u = 0; u < LSD_VGATHER; ++u) {
+      if (m0 + u * LSD_LPA >= cnt) break;
+      const float* sh = s_shift[cc[u]];
 #pragma unroll
       for (int f = 0; f < FW; ++f)
-        if (valid[f]) lj_pair(P, xi[f], x1[f], sh1, sh1 + 3, c1, L, fx[f], fy[f], fz[f], en[f]);
+        if (valid[f]) lj_pair(P, xi[f], xj[u][f], sh, sh + 3, cc[u], L, fx[f], fy[f], fz[f], en[f]);
     }
   }
   const int sp = (active && S.species) ? S.species[i] : 0;
@@ -973,41 +972,25 @@ hipError_t launch_frame_validity(const SysDev& S, const ListDev& L, const WinDev
   return hipGetLastError();
 }
 
-static size_t verify_lds(int mt) { return (size_t)mt * VROW * sizeof(uint32_t); }
-
 // frames per wave: up to LSD_VERIFY_FW_MAX (chosen per window length by the
 // caller or the autotuner)
 #ifndef LSD_VERIFY_FW_MAX
 #define LSD_VERIFY_FW_MAX 8
 #endif
 
-hipError_t prepare_verify(int mt) {
-  const int lds = (int)verify_lds(mt);
-  hipError_t e = hipFuncSetAttribute((const void*)k_verify<1>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_verify<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_verify<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_verify<8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  return e;
-}
-
 hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                          const PotDev& P, int fw, hipStream_t st) {
-  const size_t lds = verify_lds(L.mt);
   if (fw > LSD_VERIFY_FW_MAX) fw = LSD_VERIFY_FW_MAX;
   fw = fw >= 8 ? 8 : (fw >= 4 ? 4 : (fw == 2 ? 2 : 1));
   const dim3 grid(S.n_tiles, (W.K + fw - 1) / fw);
   if (fw == 8) {
-    hipLaunchKernelGGL(k_verify<8>, grid, dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<8>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P);
   } else if (fw == 4) {
-    hipLaunchKernelGGL(k_verify<4>, grid, dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<4>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P);
   } else if (fw == 2) {
-    hipLaunchKernelGGL(k_verify<2>, grid, dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<2>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P);
   } else {
-    hipLaunchKernelGGL(k_verify<1>, grid, dim3(LSD_VTHREADS), lds, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<1>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P);
   }
   return hipGetLastError();
 }

@@ -17,7 +17,6 @@ hipError_t launch_transport(const SysDev& S, const WinDev& W, const TileDev& T, 
                             hipStream_t st);
 hipError_t launch_frame_validity(const SysDev& S, const ListDev& L, const WinDev& W,
                                  hipStream_t st);
-hipError_t prepare_verify(int mt);
 hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                          const PotDev& P, int fw, hipStream_t st);
 hipError_t launch_decide(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,

@@ -100,6 +100,7 @@ EXPORTS = {
     "lsd_fit_pair_solve": ([C.c_void_p, C.c_int32, C.c_double, C.c_void_p], C.c_int),
     "lsd_autotune_verify": ([C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                              C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "lsd_set_verify_variant": ([C.c_void_p, C.c_int32, C.c_int32], C.c_int),
     "lsd_net_param_count": ([C.c_int32, C.c_int32], C.c_int32),
     "lsd_net_train_scratch_size": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
     "lsd_net_train_accumulate": ([C.c_void_p, C.POINTER(Potential), C.c_int32, C.c_int32,
@@ -487,6 +488,12 @@ class LSDSystem:
         _check(load().lsd_autotune_verify(self.h, int(K), int(repeats), C.byref(ch), us,
                                           _stream(self.torch)), "lsd_autotune_verify")
         return int(ch.value), {1: us[0], 2: us[1], 4: us[2], 8: us[3]}
+
+    def set_verify_variant(self, K, frames_per_wave):
+        """Fix the verification kernel variant (1, 2, 4 or 8 frames per
+        wave) for windows of K frames, without timing."""
+        _check(load().lsd_set_verify_variant(self.h, int(K), int(frames_per_wave)),
+               "lsd_set_verify_variant")
 
     def set_graphs(self, on=True):
         """Replay captured HIP graphs in run_windows (default) or not."""

@@ -187,6 +187,7 @@ def test_learned_draft_configuration_is_validated(lib):
 def test_autotune_and_net_calls_on_null_handle_fail_cleanly(lib):
     ch = C.c_int32()
     assert lib.lsd_autotune_verify(None, 8, 1, C.byref(ch), None, None) == -1
+    assert lib.lsd_set_verify_variant(None, 8, 2) == -1
     assert lib.lsd_net_train_accumulate(None, None, 0, 0, None, 0, None, None) == -1
     assert lib.lsd_net_adam_step(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None) == -1
     assert lib.lsd_pipeline_submit(None, None) == -1

@@ -609,6 +609,31 @@ def test_autotuned_verification_gives_identical_results(torch, lsd):
     b.destroy()
 
 
+def test_every_fixed_verification_variant_gives_identical_results(torch, lsd):
+    # 512 atoms (8 tiles), windows of 12 frames: frame groups of 1, 2, 4 and
+    # 8 frames, the last one ragged, over windows that the skin may truncate
+    _say("fixed verification variants")
+    w = W.lj_fluid(8, seed=31, K=12)
+    runs = []
+    for fw in (1, 2, 4, 8):
+        g = lsd.LSDSystem(w, mode="lsd", error_correction=1)
+        g.set_verify_variant(12, fw)
+        g.run_windows(12, 12)
+        st = g.state()
+        runs.append((st, g.log_ratio.cpu().numpy(), g.counters()))
+        with pytest.raises(lsd.LSDError):
+            g.set_verify_variant(12, 3)
+        with pytest.raises(lsd.LSDError):
+            g.set_verify_variant(13, 2)
+        g.destroy()
+    for st, lr, cn in runs[1:]:
+        for k in ("q", "p", "img", "step"):
+            assert np.array_equal(st[k], runs[0][0][k]), k
+        assert np.array_equal(lr, runs[0][1])
+        assert np.array_equal(cn, runs[0][2])
+    assert runs[0][2][:, 1].sum() > 0
+
+
 def test_timed_windows_equal_untimed_windows(torch, lsd):
     # with verification timing the windows run as graph parts around an
     # event-bracketed verification launch; the trajectory is unchanged and
