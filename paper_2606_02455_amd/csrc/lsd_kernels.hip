@@ -6,11 +6,11 @@
 //   k_cell_scan / k_cell_fill / k_cell_sort
 //                   counting sort of atoms into cells (deterministic order)
 //   k_nl_build      Verlet lists (cutoff + skin) for the target and the draft,
-//                   ELL layout [m][N], exact binary64 predicate
+//                   atom-major rows [N][m], exact binary64 predicate
 //   k_draft         one draft_step of Alg. 2 for every atom (Eq. bob draw)
-//   k_verify        target forces for ALL K frames in one launch with the
-//                   neighbour tile staged in LDS once and reused by every
-//                   frame, fused with the binary64 transport-map sums of
+//   k_verify        target forces for ALL K frames in one launch, each
+//                   neighbour entry decoded once for all frames of a wave,
+//                   fused with the binary64 transport-map sums of
 //                   Eq. reflectionVerify
 //   k_decide        accept / first rejection per replica (Alg. 1)
 //   k_commit        reflection of the rejected momentum and map g (Thm. 1)
