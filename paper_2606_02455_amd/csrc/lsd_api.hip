@@ -367,6 +367,7 @@ struct lsd_system {
   bool has_mpnn = false;
   hipStream_t cap_stream = nullptr;
   std::map<int, WindowGraphs> graphs;
+  hipEvent_t graphs_done = nullptr;  // recorded after the last graph replay
   std::map<int, int> tuned_fw;  // frames per wave of the verification kernel, by K
 };
 
@@ -403,7 +404,9 @@ lsd_status timing_drain_one(lsd_system* s) {
   return LSD_OK;
 }
 
+// Waits for the last replay to finish before the executable graphs go.
 void destroy_graphs(lsd_system* s) {
+  if (s->graphs_done && !s->graphs.empty()) (void)hipEventSynchronize(s->graphs_done);
   for (auto& kv : s->graphs) {
     if (kv.second.full) (void)hipGraphExecDestroy(kv.second.full);
     if (kv.second.pre) (void)hipGraphExecDestroy(kv.second.pre);
@@ -825,6 +828,8 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
     R.used += 1;
     HIP_TRY(hipGraphLaunch(w + 1 < n_windows ? G.mid : G.post, st));
   }
+  if (!s->graphs_done) HIP_TRY(hipEventCreateWithFlags(&s->graphs_done, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(s->graphs_done, st));
   s->state = ST_COMMITTED;
   return LSD_OK;
 }
@@ -1148,6 +1153,7 @@ lsd_status lsd_fit_pair_solve(const double* gram, int32_t n_params, double ridge
 lsd_status lsd_destroy(lsd_system* s) {
   if (!s) return LSD_OK;
   destroy_graphs(s);
+  if (s->graphs_done) (void)hipEventDestroy(s->graphs_done);
   if (s->mp.blas) rocblas_destroy_handle(s->mp.blas);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->ring.created) {
