@@ -418,7 +418,10 @@ void destroy_graphs(lsd_system* s) {
 
 enum Part { PART_FULL = 0, PART_PRE = 1, PART_POST = 2, PART_MID = 3 };
 
-// Enqueues the kernels of one window part on `st` (no state checks).
+// Enqueues the kernels of one window part of lsd_run_windows on `st` (no
+// state checks).  A part begins at the list kernels: the window's start
+// (k_window_start) is fused into the previous window's commit, and the first
+// window of a call is started by a separate launch before the replays.
 hipError_t enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
   const bool plain = s->cfg.mode == LSD_MODE_PLAIN;
   hipError_t e = hipSuccess;
@@ -428,12 +431,11 @@ hipError_t enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
     return e == hipSuccess ? enqueue_part(s, K, PART_PRE, st) : e;
   }
   if (part == PART_FULL || part == PART_PRE) {
-    e = launch_window_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, st);
-    if (e == hipSuccess) e = launch_build_lists(s->S, s->Lst, s->W, false, st);
+    e = launch_build_lists(s->S, s->Lst, s->W, false, st);
     for (int k = 0; k < K && e == hipSuccess; ++k) {
       if (!plain && s->Pd.kind == LSD_POT_NET) e = launch_net_nodes(s->S, s->Lst, s->W, s->Pd, k, st);
       if (e == hipSuccess)
-        e = launch_draft(s->S, s->Lst, s->W, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st);
+        e = launch_draft(s->S, s->Lst, s->W, s->T, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st);
     }
   }
   if (s->has_mpnn) return hipErrorNotSupported;  // never captured
@@ -443,7 +445,9 @@ hipError_t enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
   }
   if ((part == PART_FULL || part == PART_POST) && e == hipSuccess) {
     e = launch_decide(s->S, s->Lst, s->W, s->T, s->O, plain ? 1 : 0, st);
-    if (e == hipSuccess) e = launch_commit(s->S, s->W, s->buf.q, s->buf.p, s->buf.img, plain ? 1 : 0, st);
+    if (e == hipSuccess)
+      e = launch_commit_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, s->buf.img, plain ? 1 : 0,
+                              st);
   }
   return e;
 }
@@ -715,11 +719,11 @@ lsd_status lsd_draft_steps(lsd_system* s, int32_t K, lsd_stream stream) {
       if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, s->T, k, 1, s->W.fd,
                      ws<double>(s, s->lay.epart), st, err, sizeof(err)))
         return fail(LSD_ERR_HIP, "network forces: %s", err);
-      HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->Pt, k, 1, st, 1));
+      HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, s->Pt, k, 1, st, 1));
     } else {
       if (!plain && s->Pd.kind == LSD_POT_NET)
         HIP_TRY(launch_net_nodes(s->S, s->Lst, s->W, s->Pd, k, st));
-      HIP_TRY(launch_draft(s->S, s->Lst, s->W, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st));
+      HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st));
     }
   }
   s->state = ST_DRAFTED;
@@ -812,6 +816,9 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
   if (timed && !G.post) LSD_TRY(capture(s, K, PART_POST, &G.post));
   if (timed && !G.mid) LSD_TRY(capture(s, K, PART_MID, &G.mid));
   s->W.K = K;
+  // the first window's start; every later one is fused into a commit (the
+  // start that the last commit leaves behind is redone by the next call)
+  if (n_windows > 0) HIP_TRY(launch_window_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, st));
   for (int w = 0; w < n_windows; ++w) {
     if (!timed) {
       HIP_TRY(hipGraphLaunch(G.full, st));

@@ -41,10 +41,10 @@ __device__ __forceinline__ void flag_replicas(bool need, int r, int* flags) {
 // committed momenta into the window.  Frame 0 is written continuous with the
 // list positions (so the image codes of the lists stay valid); a replica
 // whose atoms moved too far from them is flagged for a rebuild.
-__global__ __launch_bounds__(256) void k_window_start(SysDev S, ListDev Lst, WinDev W,
-                                                      const float* __restrict__ q,
-                                                      const float* __restrict__ p) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Item i: the validity flag i (i < R kmax) and atom i (i < N).
+__device__ __forceinline__ void window_start_item(const SysDev& S, const ListDev& Lst,
+                                                  const WinDev& W, const float* q, const float* p,
+                                                  int i) {
   if (i < S.R * S.kmax) {
     // frames that would produce steps past the step limit are never verified
     const int rr = i / S.kmax, f = i % S.kmax;
@@ -88,6 +88,12 @@ __global__ __launch_bounds__(256) void k_window_start(SysDev S, ListDev Lst, Win
   }
   W.qmid[i] = make_float4(x[0], x[1], x[2], pack_img(dimg[0], dimg[1], dimg[2]));
   flag_replicas(d2 > Lst.reuse2 && Lst.rebuild[r] == 0, r, Lst.rebuild);
+}
+
+__global__ __launch_bounds__(256) void k_window_start(SysDev S, ListDev Lst, WinDev W,
+                                                      const float* __restrict__ q,
+                                                      const float* __restrict__ p) {
+  window_start_item(S, Lst, W, q, p, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // For replicas flagged for a rebuild: frame 0 becomes the wrapped midpoints
@@ -394,21 +400,24 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
 // One draft_step (Alg. 2) for frame k: draft forces at the midpoint, the
 // (BOB) Gaussian draw of Eq. bob, then the two position half steps that end
 // this step and start the next one; flags the next frame invalid when an
-// atom left the skin of the lists.  LSD_LPA lanes per atom.
-__global__ __launch_bounds__(256) void k_draft(SysDev S, ListDev Lst, WinDev W, PotDev P, int k,
-                                               int use_target_list, int forces_given) {
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i0 = gt / LSD_LPA, sub = gt % LSD_LPA;
-  const bool in = i0 < S.n;
-  const int i = in ? i0 : S.n - 1;
-  const int r = S.atom_rep[i];
+// atom left the skin of the lists.  Block = one tile of up to 64 atoms of
+// one replica (LSD_LPA lanes per atom), so the validity test of the frame is
+// uniform over the block.
+__global__ __launch_bounds__(LSD_VTHREADS) void k_draft(SysDev S, ListDev Lst, WinDev W,
+                                                        TileDev Tl, PotDev P, int k,
+                                                        int use_target_list, int forces_given) {
+  const int tile = blockIdx.x;
+  const int r = Tl.rep[tile];
   int* inv = W.invalid + (size_t)r * S.kmax;
   if (inv[k]) {
     // frames from K_eff on are discarded: no work, and the next frame is
     // invalid as well (one thread per replica records it)
-    if (in && sub == 0 && i == S.rep_off[r] && k + 1 < W.K) inv[k + 1] = 1;
+    if (threadIdx.x == 0 && tile == Tl.rep_tile_off[r] && k + 1 < W.K) inv[k + 1] = 1;
     return;
   }
+  const int a = threadIdx.x / LSD_LPA, sub = threadIdx.x % LSD_LPA;
+  const bool in = a < Tl.count[tile];
+  const int i = Tl.start[tile] + (in ? a : 0);
   const int sp = S.species ? S.species[i] : 0;
   const size_t N = (size_t)S.n;
   const float4* X = W.qmid + (size_t)k * N;
@@ -759,10 +768,8 @@ __global__ __launch_bounds__(1024) void k_decide(SysDev S, WinDev W, TileDev Tl,
 // momentum <p> + Sigma^{1/2} (z - (2 delta.z / delta.delta) delta) and map g.
 // With error correction the cache becomes F - F~ of the committed frame,
 // from the EC-uncorrected draft force (App. D).
-__global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __restrict__ q,
-                                                float* __restrict__ p, int* __restrict__ img,
-                                                int plain) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void commit_atom(const SysDev& S, const WinDev& W, float* q, float* p,
+                                            int* img, int plain, int i) {
   if (i >= S.n) return;
   const int r = S.atom_rep[i];
   const int sp = S.species ? S.species[i] : 0;
@@ -824,6 +831,22 @@ __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __res
       W.ec[d * N + i] = Ft - Fb;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __restrict__ q,
+                                                float* __restrict__ p, int* __restrict__ img,
+                                                int plain) {
+  commit_atom(S, W, q, p, img, plain, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Commit of one window fused with the start of the next (graph-replayed
+// windows): both are per atom, and the start reads only what the same
+// thread has just committed.
+__global__ __launch_bounds__(256) void k_commit_start(SysDev S, ListDev Lst, WinDev W, float* q,
+                                                      float* p, int* img, int plain) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  commit_atom(S, W, q, p, img, plain, i);
+  window_start_item(S, Lst, W, q, p, i);
 }
 
 // (OBABO) start (App. E): frame 0 = the given positions q_0 (wrapped), for
@@ -952,11 +975,11 @@ hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W
   return hipGetLastError();
 }
 
-hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P, int k,
-                        int use_target_list, hipStream_t st, int forces_given) {
-  const long long threads = (long long)S.n * LSD_LPA;
-  hipLaunchKernelGGL(k_draft, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, S, L, W, P,
-                     k, use_target_list, forces_given);
+hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
+                        const PotDev& P, int k, int use_target_list, hipStream_t st,
+                        int forces_given) {
+  hipLaunchKernelGGL(k_draft, dim3(S.n_tiles), dim3(LSD_VTHREADS), 0, st, S, L, W, T, P, k,
+                     use_target_list, forces_given);
   return hipGetLastError();
 }
 
@@ -1001,6 +1024,14 @@ hipError_t launch_decide(const SysDev& S, const ListDev& L, const WinDev& W, con
   const int waves = plain ? 1 : (W.K < 16 ? W.K : 16);
   hipLaunchKernelGGL(k_decide, dim3(S.R), dim3(64 * waves), 0, st, S, W, T, O, plain, L.rebuild,
                      L.always_rebuild);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit_start(const SysDev& S, const ListDev& L, const WinDev& W, float* q,
+                               float* p, int* img, int plain, hipStream_t st) {
+  const int n = S.n > S.R * S.kmax ? S.n : S.R * S.kmax;
+  hipLaunchKernelGGL(k_commit_start, dim3(blocks_for(n, 256)), dim3(256), 0, st, S, L, W, q, p,
+                     img, plain);
   return hipGetLastError();
 }
 

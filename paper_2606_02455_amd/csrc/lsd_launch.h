@@ -11,8 +11,9 @@ hipError_t launch_window_start(const SysDev& S, const ListDev& L, const WinDev& 
 // the wrapped first midpoints or (caller_frame0) from the caller's frame 0.
 hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W, bool caller_frame0,
                               hipStream_t st);
-hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P, int k,
-                        int use_target_list, hipStream_t st, int forces_given = 0);
+hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
+                        const PotDev& P, int k, int use_target_list, hipStream_t st,
+                        int forces_given = 0);
 hipError_t launch_transport(const SysDev& S, const WinDev& W, const TileDev& T, const double* epart,
                             hipStream_t st);
 hipError_t launch_frame_validity(const SysDev& S, const ListDev& L, const WinDev& W,
@@ -21,6 +22,9 @@ hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, con
                          const PotDev& P, int fw, hipStream_t st);
 hipError_t launch_decide(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                          const OutDev& O, int plain, hipStream_t st);
+// commit of the window and start of the next one in one launch
+hipError_t launch_commit_start(const SysDev& S, const ListDev& L, const WinDev& W, float* q,
+                               float* p, int* img, int plain, hipStream_t st);
 hipError_t launch_commit(const SysDev& S, const WinDev& W, float* q, float* p, int* img,
                          int plain, hipStream_t st);
 // (OBABO) start: stage 0 writes the given positions as frame 0; stage 1
