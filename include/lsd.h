@@ -282,7 +282,12 @@ LSD_API lsd_status lsd_accept_rollback(lsd_system *sys, int32_t *n_host,
  * By default each window is one launch of a HIP graph (captured once per K
  * on a library stream, replayed on `stream`); with verification timing on,
  * the verification kernel runs between the graph parts that precede and
- * follow it, bracketed by HIP events.  Results are identical either way. */
+ * follow it, bracketed by HIP events.  Results are identical either way.
+ * In the replayed windows each commit also starts the next window; a call
+ * first starts its own first window, so a state the caller writes between
+ * calls is taken up (a list rebuild that the previous call's last commit
+ * flagged then still happens, which is valid and changes only the order of
+ * the list entries). */
 LSD_API lsd_status lsd_run_windows(lsd_system *sys, int32_t n_windows, int32_t K,
                            lsd_stream stream);
 
