@@ -42,22 +42,25 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def read_traffic(config_name, kernel):
+def read_traffic(config_name, kernel, skin):
     """HBM bytes per verification launch from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source and on
-    the same kernel variant."""
+    counter summary, if it was taken on the current kernel source, with the
+    same list skin, and holds a section for this kernel variant."""
     path = os.path.join(ROOT, "profiles", f"k_verify_{config_name}_traffic.txt")
     if not os.path.exists(path):
         return None
-    kv = {}
+    head, sections, cur = {}, {}, None
     for line in open(path):
-        if "=" in line and not line.startswith("#"):
+        line = line.strip()
+        if line.startswith("[") and line.endswith("]"):
+            cur = sections.setdefault(line[1:-1], {})
+        elif "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("source_sha") != source_sha() or kv.get("kernel") != kernel:
+            (cur if cur is not None else head)[k.strip()] = v.strip()
+    if head.get("source_sha") != source_sha() or head.get("lsd_skin") != repr(float(skin)):
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(sections[kernel]["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -318,6 +321,10 @@ def main():
                          "(default 2000 for c3, 500 for c4)")
     ap.add_argument("--net-lr", type=float, default=3e-3)
     ap.add_argument("--equilibrate", type=int, default=256, help="plain steps before timing")
+    ap.add_argument("--skin", type=float, default=None,
+                    help="list skin of the LSD run (default: the tuned one of the config)")
+    ap.add_argument("--plain-skin", type=float, default=None,
+                    help="list skin of the plain run (default: the tuned one of the config)")
     ap.add_argument("--verify-fw", choices=["auto", "1", "2", "4", "8"], default="auto",
                     help="frames per wave of the verification kernel (auto: autotune)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -357,12 +364,18 @@ def main():
     K = w.K
     log(f"workload {w.name}: N={w.n_atoms} K={K} box={w.box[0]:.5f}")
 
-    plain = lsd.LSDSystem(w, mode="plain")
+    lsd_skin, plain_skin = W.BENCH_SKINS.get(args.config, (w.skin, w.skin))
+    if args.skin is not None:
+        lsd_skin = args.skin
+    if args.plain_skin is not None:
+        plain_skin = args.plain_skin
+    log(f"list skins: LSD {lsd_skin}, plain {plain_skin}")
+    plain = lsd.LSDSystem(w, mode="plain", skin=plain_skin)
     eq_windows = max(1, args.equilibrate // K)
     plain.run_windows(eq_windows, K)
     torch.cuda.synchronize()
     ec_on = args.ec != "off"
-    lsds = lsd.LSDSystem(w, mode="lsd", error_correction=EC_MODES[args.ec])
+    lsds = lsd.LSDSystem(w, mode="lsd", error_correction=EC_MODES[args.ec], skin=lsd_skin)
     lsds.q.copy_(plain.q)
     lsds.p.copy_(plain.p)
     lsds.img.copy_(plain.img)
@@ -429,7 +442,7 @@ def main():
     avg_s = ver_ms / max(ver_n, 1) * 1e-3
     achieved = alg_bytes / avg_s / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=read_traffic(args.config, f"k_verify<{chosen_fw}>"),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=read_traffic(args.config, f"k_verify<{chosen_fw}>", lsd_skin),
                     kernel=f"k_verify<{chosen_fw}>", avg_us=round(avg_s * 1e6, 3),
                     autotune_us={str(k): round(v, 2) for k, v in fw_us.items()},
                     algorithmic_bytes=int(alg_bytes), frames_per_launch=round(frames_per_launch, 3),
@@ -463,7 +476,8 @@ def main():
                          f"target cutoff {w.target['rc']}, draft cutoff {w.draft['rc']}, "
                          f"K={K}, dt={w.dt}, gamma={w.gamma}, seed {w.seed}, "
                          f"error correction {args.ec}"),
-            "n_atoms": w.n_atoms, "K": K, "skin": w.skin, "error_correction": args.ec,
+            "n_atoms": w.n_atoms, "K": K, "skin": lsd_skin, "plain_skin": plain_skin,
+            "error_correction": args.ec,
         },
         "acceptance": round(1.0 - rejections / max(committed, 1), 5),
         "committed_per_window": round(committed / windows, 4),

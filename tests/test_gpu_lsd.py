@@ -100,14 +100,25 @@ def _gpu_pairs(sysg, which="target"):
     return out[np.lexsort((out[:, 4], out[:, 3], out[:, 2], out[:, 1], out[:, 0]))]
 
 
-@pytest.mark.parametrize("case", ["c1", "box2000", "c2"])
+def _config(case):
+    """A configuration; "<name>_bench" with the list skin of the benchmark's
+    LSD run."""
+    if case.endswith("_bench"):
+        name = case[:-len("_bench")]
+        w = W.config(name)
+        w.skin = W.BENCH_SKINS[name][0]
+        return w
+    return W.config(case)
+
+
+@pytest.mark.parametrize("case", ["c1", "box2000", "c2", "c2_bench"])
 def test_neighbor_lists_exact(torch, lsd, ora, case):
     _say(f"neighbour lists {case}")
     if case == "box2000":
         w = W.lj_fluid(10, rho=0.8, seed=11, K=4)
         w.positions = W.random_box_positions(w.n_atoms, float(w.box[0]), seed=12)
     else:
-        w = W.config(case)
+        w = _config(case)
     sysg = lsd.LSDSystem(w, mode="lsd", k_max=1)
     K = 1
     q = w.positions[None]
@@ -136,13 +147,14 @@ def _perturbed_frames(w, K, seed, amp=0.02):
     return fr
 
 
-@pytest.mark.parametrize("case", ["c1", "c2"])
+@pytest.mark.parametrize("case", ["c1", "c2", "c2_bench"])
 def test_target_forces_and_energies(torch, lsd, ora, case):
     _say(f"target forces {case}")
-    w = W.config(case)
+    w = _config(case)
     K = w.K
     sysg = lsd.LSDSystem(w, mode="lsd")
-    qm = _perturbed_frames(w, K, seed=3)
+    # frames differ pairwise by at most 2 sqrt(3) amp, inside half the skin
+    qm = _perturbed_frames(w, K, seed=3, amp=min(0.02, 0.1 * w.skin))
     so = _ora_system(ora, w)
     T = _ora_pot(ora, w.target)
     D = _ora_pot(ora, w.draft)
