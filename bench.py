@@ -150,7 +150,13 @@ def run_c3(args, lsd, W, torch):
     target = W.mpnn_target()
     ec_on = args.ec != "off"
     log(f"workload {w.name}: N={N} K={K} box={w.box[0]:.4f} A")
-    plain = lsd.LSDSystem(w, mode="plain", target=target)
+    lsd_skin, plain_skin = W.BENCH_SKINS.get(args.config, (w.skin, w.skin))
+    if args.skin is not None:
+        lsd_skin = args.skin
+    if args.plain_skin is not None:
+        plain_skin = args.plain_skin
+    log(f"list skins: LSD {lsd_skin}, plain {plain_skin}")
+    plain = lsd.LSDSystem(w, mode="plain", target=target, skin=plain_skin)
     eq_windows = max(1, args.equilibrate // K)
     t0 = time.perf_counter()
     plain.run_windows(eq_windows, K)
@@ -226,7 +232,7 @@ def run_c3(args, lsd, W, torch):
             log(f"FP8 activation scales from max |D| = {amax[0]:.4g}, max |h| = {amax[1]:.4g}")
         draft = net
     g = lsd.LSDSystem(w, mode="lsd", target=target, draft=draft,
-                      error_correction=EC_MODES[args.ec])
+                      error_correction=EC_MODES[args.ec], skin=lsd_skin)
     for a, b in ((g.q, plain.q), (g.p, plain.p), (g.img, plain.img), (g.step, plain.step)):
         a.copy_(b)
     g.run_windows(args.warmup, K)
@@ -282,7 +288,8 @@ def run_c3(args, lsd, W, torch):
                          f"(frame-to-frame differences) on {fit_frames} target frames; "
                          f"error correction {args.ec}"),
             "n_atoms": N, "K": K, "fit_frames": fit_frames,
-            "draft": args.draft, "error_correction": args.ec},
+            "draft": args.draft, "error_correction": args.ec,
+            "skin": lsd_skin, "plain_skin": plain_skin},
         "acceptance": round(1.0 - rejections / max(committed, 1), 5),
         "committed_per_window": round(committed / windows, 4),
         "plain_steps_per_s": round(plain_rate, 3),
