@@ -332,6 +332,8 @@ def main():
                     help="list skin of the LSD run (default: the tuned one of the config)")
     ap.add_argument("--plain-skin", type=float, default=None,
                     help="list skin of the plain run (default: the tuned one of the config)")
+    ap.add_argument("--time-every", type=int, default=8,
+                    help="time every n-th verification launch with HIP events (c1, c2)")
     ap.add_argument("--verify-fw", choices=["auto", "1", "2", "4", "8"], default="auto",
                     help="frames per wave of the verification kernel (auto: autotune)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -405,7 +407,7 @@ def main():
     # --- LSD
     lsds.run_windows(args.warmup, K)
     lsds.reset_counters()
-    lsds.set_verify_timing(True)
+    lsds.set_verify_timing(True, every=args.time_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lsds.run_windows(args.steps, K)
@@ -451,6 +453,7 @@ def main():
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=read_traffic(args.config, f"k_verify<{chosen_fw}>", lsd_skin),
                     kernel=f"k_verify<{chosen_fw}>", avg_us=round(avg_s * 1e6, 3),
+                    timed_launches=int(ver_n), timed_every=args.time_every,
                     autotune_us={str(k): round(v, 2) for k, v in fw_us.items()},
                     algorithmic_bytes=int(alg_bytes), frames_per_launch=round(frames_per_launch, 3),
                     in_cutoff_pairs=pairs)

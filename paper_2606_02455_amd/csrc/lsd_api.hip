@@ -359,6 +359,8 @@ struct lsd_system {
   int state = ST_READY;
 
   bool timing = false;
+  int timing_every = 1;      // time every n-th verification launch
+  int64_t timing_seq = 0;    // verification launches since timing was set
   TimingRing ring;
   double t_sum = 0.0;
   int64_t t_count = 0;
@@ -752,7 +754,8 @@ lsd_status lsd_verify_window(lsd_system* s, lsd_stream stream) {
   if (s->cfg.mode == LSD_MODE_LSD) {
     TimingRing& R = s->ring;
     int slot = -1;
-    if (s->timing) {
+    const bool timed = s->timing && (s->timing_seq++ % s->timing_every) == 0;
+    if (timed) {
       if (R.used == kTimingRing) LSD_TRY(timing_drain_one(s));
       slot = (R.head + R.used) % kTimingRing;
       HIP_TRY(hipEventRecord(R.start[slot], st));
@@ -768,7 +771,7 @@ lsd_status lsd_verify_window(lsd_system* s, lsd_stream stream) {
     } else {
       HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st));
     }
-    if (s->timing) {
+    if (timed) {
       HIP_TRY(hipEventRecord(R.stop[slot], st));
       R.used += 1;
     }
@@ -811,7 +814,7 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool timed = s->timing && s->cfg.mode == LSD_MODE_LSD;
   WindowGraphs& G = s->graphs[K];
-  if (!timed && !G.full) LSD_TRY(capture(s, K, PART_FULL, &G.full));
+  if ((!timed || s->timing_every > 1) && !G.full) LSD_TRY(capture(s, K, PART_FULL, &G.full));
   if (timed && !G.pre) LSD_TRY(capture(s, K, PART_PRE, &G.pre));
   if (timed && !G.post) LSD_TRY(capture(s, K, PART_POST, &G.post));
   if (timed && !G.mid) LSD_TRY(capture(s, K, PART_MID, &G.mid));
@@ -819,12 +822,19 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
   // the first window's start; every later one is fused into a commit (the
   // start that the last commit leaves behind is redone by the next call)
   if (n_windows > 0) HIP_TRY(launch_window_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, st));
+  // a timed window runs as pre, the event-bracketed verification, and post
+  // (merged with the next window's pre into mid when that one is timed
+  // too); an untimed window is one launch of the whole-window graph
+  bool open = false;  // a timed window's post is still to be launched
   for (int w = 0; w < n_windows; ++w) {
-    if (!timed) {
+    const bool t = timed && (s->timing_seq++ % s->timing_every) == 0;
+    if (!t) {
+      if (open) HIP_TRY(hipGraphLaunch(G.post, st));
+      open = false;
       HIP_TRY(hipGraphLaunch(G.full, st));
       continue;
     }
-    if (w == 0) HIP_TRY(hipGraphLaunch(G.pre, st));
+    HIP_TRY(hipGraphLaunch(open ? G.mid : G.pre, st));
     TimingRing& R = s->ring;
     if (R.used == kTimingRing) LSD_TRY(timing_drain_one(s));
     const int slot = (R.head + R.used) % kTimingRing;
@@ -833,8 +843,9 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
     HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st));
     HIP_TRY(hipEventRecord(R.stop[slot], st));
     R.used += 1;
-    HIP_TRY(hipGraphLaunch(w + 1 < n_windows ? G.mid : G.post, st));
+    open = true;
   }
+  if (open) HIP_TRY(hipGraphLaunch(G.post, st));
   if (!s->graphs_done) HIP_TRY(hipEventCreateWithFlags(&s->graphs_done, hipEventDisableTiming));
   HIP_TRY(hipEventRecord(s->graphs_done, st));
   s->state = ST_COMMITTED;
@@ -957,6 +968,7 @@ lsd_status lsd_reset_counters(lsd_system* s, lsd_stream stream) {
 
 lsd_status lsd_set_verify_timing(lsd_system* s, int32_t enable) {
   if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  if (enable < 0) return fail(LSD_ERR_INVALID_ARG, "timing period %d < 0", enable);
   TimingRing& R = s->ring;
   if (enable && !R.created) {
     for (int i = 0; i < kTimingRing; ++i) {
@@ -967,6 +979,8 @@ lsd_status lsd_set_verify_timing(lsd_system* s, int32_t enable) {
   }
   while (R.used > 0) LSD_TRY(timing_drain_one(s));
   s->timing = enable != 0;
+  s->timing_every = enable > 1 ? enable : 1;
+  s->timing_seq = 0;
   s->t_sum = 0.0;
   s->t_count = 0;
   return LSD_OK;

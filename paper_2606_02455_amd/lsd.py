@@ -526,8 +526,10 @@ class LSDSystem:
     def reset_counters(self):
         _check(load().lsd_reset_counters(self.h, _stream(self.torch)), "lsd_reset_counters")
 
-    def set_verify_timing(self, on=True):
-        _check(load().lsd_set_verify_timing(self.h, 1 if on else 0), "lsd_set_verify_timing")
+    def set_verify_timing(self, on=True, every=1):
+        """Time every `every`-th verification launch with HIP events."""
+        _check(load().lsd_set_verify_timing(self.h, int(every) if on else 0),
+               "lsd_set_verify_timing")
 
     def verify_timing(self):
         ms, n = C.c_double(), C.c_int64()

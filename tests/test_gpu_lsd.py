@@ -666,3 +666,34 @@ def test_timed_windows_equal_untimed_windows(torch, lsd):
     assert n == 58 and 0.0 < ms / n < 5.0, (ms, n)
     a.destroy()
     b.destroy()
+
+
+@pytest.mark.parametrize("every", [2, 3])
+def test_sampled_timing_windows_equal_untimed_windows(torch, lsd, every):
+    # every n-th window timed: timed and untimed windows interleave (whole
+    # window graphs between the timed parts), with an eager window and an
+    # eager verification between the calls; trajectory and counters are
+    # those of the untimed run, and exactly every n-th launch is timed
+    _say(f"sampled timing every {every}")
+    w = W.config("c1")
+    a = lsd.LSDSystem(w, mode="lsd")
+    b = lsd.LSDSystem(w, mode="lsd")
+    b.set_verify_timing(True, every=every)
+    launches = 0
+    for n in (1, 7, 50):
+        for g in (a, b):
+            g.run_windows(n, 8)
+            g.draft_steps(8)
+            g.verify_window()
+            g.accept_rollback()
+        launches += n + 1
+    sa, sb = a.state(), b.state()
+    for k in ("q", "p", "img", "step"):
+        assert np.array_equal(sa[k], sb[k]), k
+    assert np.array_equal(a.counters(), b.counters())
+    ms, n = b.verify_timing()
+    assert n == (launches + every - 1) // every and 0.0 < ms / n < 5.0, (ms, n, launches)
+    with pytest.raises(lsd.LSDError):
+        b.set_verify_timing(True, every=-1)
+    a.destroy()
+    b.destroy()
