@@ -262,8 +262,9 @@ def run_c3(args, lsd, W, torch):
     if status:
         raise RuntimeError(f"device status {status}: neighbour capacity overflow")
     pairs = in_cutoff_pairs(g, float(target["rc"]))
-    # replica-frames per launch, as whole-system frames
-    frames_per_launch = frames / max(ver_n, 1) / w.n_replicas
+    # replica-frames per launch (one launch per window), as whole-system
+    # frames
+    frames_per_launch = frames / max(windows, 1) / w.n_replicas
     flops = mpnn_flops_per_frame(pairs / 2.0, N) * frames_per_launch
     avg_s = ver_ms / max(ver_n, 1) * 1e-3
     achieved = flops / avg_s / 1e12
@@ -445,7 +446,7 @@ def main():
     del src, dst
 
     # --- roofline of the dominant kernel (one verification launch)
-    frames_per_launch = frames / max(ver_n, 1)
+    frames_per_launch = frames / max(windows, 1)  # one verification launch per window
     pairs = in_cutoff_pairs(lsds, w.target["rc"])
     alg_bytes = frames_per_launch * w.n_atoms * 60.0 + pairs * 4.0
     avg_s = ver_ms / max(ver_n, 1) * 1e-3
