@@ -467,6 +467,42 @@ def test_graph_replays_equal_eager_launches(torch, lsd):
         b.destroy()
 
 
+@pytest.mark.parametrize("case", ["ec_constant", "ec_linear", "obabo", "replicas_short_skin"])
+def test_graph_replays_equal_eager_launches_variants(torch, lsd, case):
+    # the replayed windows fuse each commit with the next window's start;
+    # with error correction (constant and linear caches), the (OBABO)
+    # integrator, and ragged replicas with a short skin (many list rebuilds
+    # and truncated windows) they must equal the eager calls bit for bit
+    _say(f"graph vs eager {case}")
+    kw = {}
+    if case == "replicas_short_skin":
+        w = W.lj_replicas([3, 4, 5, 6], seed=310, K=8)
+        kw["skin"] = 0.1
+    else:
+        w = W.config("c1")
+    if case == "ec_constant":
+        kw["error_correction"] = 1
+    elif case == "ec_linear":
+        kw["error_correction"] = 2
+    elif case == "obabo":
+        kw["integrator"] = "obabo"
+    a = lsd.LSDSystem(w, mode="lsd", **kw)
+    b = lsd.LSDSystem(w, mode="lsd", **kw)
+    b.set_graphs(False)
+    for rep in range(5):
+        a.run_windows(4, 8)
+        b.run_windows(4, 8)
+        sa, sb = a.state(), b.state()
+        for k in ("q", "p", "img", "step"):
+            assert np.array_equal(sa[k], sb[k]), (case, rep, k)
+        assert np.array_equal(a.counters(), b.counters()), case
+    assert a.counters()[:, 1].sum() > 0
+    if case == "replicas_short_skin":
+        assert a.counters()[:, 4].sum() > 5      # lists rebuilt many times
+    a.destroy()
+    b.destroy()
+
+
 def _near_faces(w):
     """The C1 lattice shifted by half a spacing: a layer of atoms sits within
     the jitter of every box face, so many cross a face within a window."""
