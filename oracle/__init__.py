@@ -105,6 +105,10 @@ def _declare(L):
     L.ora_obabo_lsd_run.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), C.POINTER(_Pot), _dp, _dp,
                                     _ip, C.c_uint64, C.c_uint32, C.c_int64, C.c_int,
                                     C.POINTER(_Stats)]
+    L.ora_obabo_begin.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), _dp, _dp, _ip, C.c_uint64,
+                                  C.c_uint32, C.c_uint64]
+    L.ora_obabo_recover.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), _dp, _dp, _dp, C.c_uint64,
+                                    C.c_uint32, C.c_uint64, _dp, _dp, _ip]
     if hasattr(L, "ora_mpnn_energy_forces"):
         from . import mpnn as _m
         _m.declare(L)
@@ -312,3 +316,21 @@ def obabo_lsd_run(system, target, draft, q, p, img, seed, replica, n_steps, K):
                             C.byref(st))
     return dict(windows=st.windows, rejections=st.rejections, frames=st.frames,
                 committed=st.committed)
+
+
+def obabo_begin(system, target, q, p, img, seed, replica, step=0):
+    """In place: (OBABO) state y = (q, p) -> the staggered (ABOBA) state of
+    LSD for (OBABO) (the OB half step with tag-3 noise at `step`)."""
+    lib().ora_obabo_begin(C.byref(system._c), C.byref(target._c), _d(q), _d(p),
+                          img.ctypes.data_as(_ip), seed, replica, step)
+
+
+def obabo_recover(system, target, q, p, p_prev, seed, replica, step):
+    """(q_n, p_n) of the (OBABO) state at committed step `step` from the
+    staggered state (q, p) and the staggered momentum of the step before."""
+    n = system.n
+    q, p, pp = (_f64(v).reshape(n, 3) for v in (q, p, p_prev))
+    qo, po = np.zeros((n, 3)), np.zeros((n, 3))
+    lib().ora_obabo_recover(C.byref(system._c), C.byref(target._c), _d(q), _d(p), _d(pp), seed,
+                            replica, step, _d(qo), _d(po), None)
+    return qo, po

@@ -805,37 +805,77 @@ void ora_obabo_plain_run(const ora_sys *S, const ora_pot *P, double *q, double *
   free(x1); free(x2);
 }
 
+/* Start of LSD for (OBABO) in the staggered frame (App. E): from the (OBABO)
+ * state y_0 = (q, p), ybar_0 = OB(y_0) is an (O) half step with noise from
+ * tag 3 at step `step`, then a (B) half step with the target force at q_0;
+ * (q, p, img) become the (ABOBA) state whose next midpoint is
+ * q_0 + dt pbar_0 / m (the staggered chain ybar_n = BOB(A(ybar_{n-1})) is the
+ * (ABOBA) chain read at its midpoints). */
+void ora_obabo_begin(const ora_sys *S, const ora_pot *T, double *q, double *p, int32_t *img,
+                     uint64_t seed, uint32_t replica, uint64_t step) {
+  int n = S->n, m = 3 * n;
+  double *F = (double *)malloc(sizeof(double) * m);
+  double *xi = (double *)malloc(sizeof(double) * m);
+  double ah = exp(-0.5 * S->gamma * S->dt);
+  ora_normals_tag(seed, replica, step, ORA_TAG_OB, n, xi);
+  ora_energy_forces(T, n, q, S->L, F, 1);
+  for (int c = 0; c < m; ++c)
+    p[c] = ah * p[c] + half_sigma(S, c / 3) * xi[c] + 0.5 * S->dt * S->fu * F[c];
+  step_A(S, p, q, img);
+  free(F); free(xi);
+}
+
+/* The (OBABO) state y_n of committed step n from the staggered (ABOBA) state
+ * (q, p) = (q_n + dt/2 pbar_n / m, pbar_n) and pbar_{n-1} = pprev:
+ *   q_n  = the midpoint (back by a half step, wrapped),
+ *   p_n  = e^{-gamma dt/2}(pbar_{n-1} + dt/2 F_n) + Sigma_1/2^{1/2} xi1*,
+ * xi1* drawn from the Gaussian conditional on
+ *   w = Sigma_1/2^{-1/2}(pbar_n - e^{-gamma dt} pbar_{n-1} - (1 + e^{-gamma dt}) dt/2 F_n):
+ * mean e^{-gamma dt/2} w / (1 + e^{-gamma dt}), variance 1 / (1 + e^{-gamma dt}),
+ * with noise from tag 3 at step n (Eq. obabo_conditional).  Writes
+ * (q_out, p_out); img (may be NULL) receives the wrap of q_n. */
+void ora_obabo_recover(const ora_sys *S, const ora_pot *T, const double *q, const double *p,
+                       const double *pprev, uint64_t seed, uint32_t replica, uint64_t step,
+                       double *q_out, double *p_out, int32_t *img) {
+  int n = S->n, m = 3 * n;
+  double *F = (double *)malloc(sizeof(double) * m);
+  double *xi = (double *)malloc(sizeof(double) * m);
+  double ah = exp(-0.5 * S->gamma * S->dt), a = exp(-S->gamma * S->dt);
+  for (int i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) {
+      q_out[3 * i + d] = q[3 * i + d] - (0.5 * S->dt) * p[3 * i + d] / S->mass[i];
+      int s = wrap1(&q_out[3 * i + d], S->L);
+      if (img) img[3 * i + d] += s;
+    }
+  ora_energy_forces(T, n, q_out, S->L, F, 1);
+  ora_normals_tag(seed, replica, step, ORA_TAG_OB, n, xi);
+  double cw = ah / (1.0 + a), cs = 1.0 / sqrt(1.0 + a);
+  for (int c = 0; c < m; ++c) {
+    double sh = half_sigma(S, c / 3);
+    double half_kick = 0.5 * S->dt * S->fu * F[c];
+    double w = (p[c] - a * pprev[c] - (1.0 + a) * half_kick) / sh;
+    double x1 = cw * w + cs * xi[c];
+    p_out[c] = ah * (pprev[c] + half_kick) + sh * x1;
+  }
+  free(F); free(xi);
+}
+
 /* LSD for (OBABO) in the staggered frame (App. E), from the (OBABO) state
- * y_0 = (q, p) at step 0 to y_{n_steps}, returned in (q, p, img).
- * 1. ybar_0 = OB(y_0): an (O) half step with noise from tag 3 at step 0,
- *    then a (B) half step with the target force at q_0.
- * 2. The staggered chain ybar_n = BOB(A(ybar_{n-1})), A a full position
- *    step, is the (ABOBA) chain read at its midpoints, so LSD runs on the
- *    (ABOBA) state (q_0 + dt/2 pbar_0 / m, pbar_0) with the usual windows.
- * 3. The output y_n at the last committed step: q_n = its midpoint, and
- *    p_mid = e^{-gamma dt/2}(pbar_{n-1} + dt/2 F_n) + Sigma_1/2^{1/2} xi1*,
- *    where xi1* is drawn from the Gaussian conditional on
- *    w = Sigma_1/2^{-1/2}(pbar_n - e^{-gamma dt} pbar_{n-1}
- *                         - (1 + e^{-gamma dt}) dt/2 F_n):
- *    mean e^{-gamma dt/2} w / (1 + e^{-gamma dt}), variance 1 / (1 + e^{-gamma dt}),
- *    from tag 3 at step n.  (dt/2 F carries the force unit fu.) */
+ * y_0 = (q, p) at step 0 to y_{n_steps}, returned in (q, p, img): the start
+ * ybar_0 = OB(y_0) (ora_obabo_begin), (ABOBA) LSD windows on the staggered
+ * state, and the recovery of y_n at the last committed step
+ * (ora_obabo_recover). */
 void ora_obabo_lsd_run(const ora_sys *S, const ora_pot *T, const ora_pot *D, double *q,
                        double *p, int32_t *img, uint64_t seed, uint32_t replica,
                        int64_t n_steps, int K, ora_run_stats *st) {
   int n = S->n, m = 3 * n;
-  double *F = (double *)malloc(sizeof(double) * m);
   double *xi = (double *)malloc(sizeof(double) * (size_t)K * m);
   double *u = (double *)malloc(sizeof(double) * K);
   double *pd = (double *)malloc(sizeof(double) * (size_t)(K + 1) * m);
   double *pprev = (double *)malloc(sizeof(double) * m);
-  double ah = exp(-0.5 * S->gamma * S->dt), a = exp(-S->gamma * S->dt);
-  /* 1. OB half step */
-  ora_normals_tag(seed, replica, 0u, ORA_TAG_OB, n, xi);
-  ora_energy_forces(T, n, q, S->L, F, 1);
-  for (int c = 0; c < m; ++c)
-    p[c] = ah * p[c] + half_sigma(S, c / 3) * xi[c] + 0.5 * S->dt * S->fu * F[c];
-  /* 2. (ABOBA) state whose next midpoint is q_0 + dt pbar_0 / m */
-  step_A(S, p, q, img);
+  double *qs = (double *)malloc(sizeof(double) * m);
+  double *ps = (double *)malloc(sizeof(double) * m);
+  ora_obabo_begin(S, T, q, p, img, seed, replica, 0u);
   memcpy(pprev, p, sizeof(double) * m);
   if (st) memset(st, 0, sizeof(*st));
   int64_t done = 0;
@@ -858,22 +898,8 @@ void ora_obabo_lsd_run(const ora_sys *S, const ora_pot *T, const ora_pot *D, dou
       st->frames += Kw;
     }
   }
-  /* 3. output at the last committed step: back to its midpoint, F_n there */
-  for (int i = 0; i < n; ++i)
-    for (int d = 0; d < 3; ++d) {
-      q[3 * i + d] -= (0.5 * S->dt) * p[3 * i + d] / S->mass[i];
-      int s = wrap1(&q[3 * i + d], S->L);
-      if (img) img[3 * i + d] += s;
-    }
-  ora_energy_forces(T, n, q, S->L, F, 1);
-  ora_normals_tag(seed, replica, (uint64_t)n_steps, ORA_TAG_OB, n, xi);
-  double cw = ah / (1.0 + a), cs = 1.0 / sqrt(1.0 + a);
-  for (int c = 0; c < m; ++c) {
-    double sh = half_sigma(S, c / 3);
-    double half_kick = 0.5 * S->dt * S->fu * F[c];
-    double w = (p[c] - a * pprev[c] - (1.0 + a) * half_kick) / sh;
-    double x1 = cw * w + cs * xi[c];
-    p[c] = ah * (pprev[c] + half_kick) + sh * x1;
-  }
-  free(F); free(xi); free(u); free(pd); free(pprev);
+  memcpy(qs, q, sizeof(double) * m);
+  memcpy(ps, p, sizeof(double) * m);
+  ora_obabo_recover(S, T, qs, ps, pprev, seed, replica, (uint64_t)n_steps, q, p, img);
+  free(xi); free(u); free(pd); free(pprev); free(qs); free(ps);
 }

@@ -135,8 +135,23 @@ static void filter(const ora_mpnn *M, const mpnn_view *v, int t, const double *e
   free(w); free(s); free(z);
 }
 
+/* Filters of layer t for the pairs [k0, k1) into W[k - k0][H] (and dW): each
+ * pair's filter is a function of its own distance only, so they are formed
+ * side by side (in parallel) before the serial sums that use them. */
+#define ORA_FILTER_CHUNK 16384
+static void filter_chunk(const ora_mpnn *M, const mpnn_view *v, int t, long k0, long k1,
+                         const double *e, const double *de, const double *fc,
+                         const double *dfc, double *W, double *dW) {
+  const int H = M->H, R = M->R;
+#pragma omp parallel for schedule(static)
+  for (long k = k0; k < k1; ++k)
+    filter(M, v, t, &e[(size_t)k * R], &de[(size_t)k * R], fc[k], dfc[k],
+           &W[(size_t)(k - k0) * H], dW ? &dW[(size_t)(k - k0) * H] : NULL);
+}
+
 /* Energy and forces (F may be NULL).  x [n][3] positions in a cubic box of
- * edge L; species [n]. */
+ * edge L; species [n].  Every sum runs serially in the order written; only
+ * independent per-pair and per-atom products run in parallel. */
 double ora_mpnn_energy_forces(const ora_mpnn *M, int n, const int32_t *species, const double *x,
                               double L, double *F) {
   mpnn_view v;
@@ -161,45 +176,65 @@ double ora_mpnn_energy_forces(const ora_mpnn *M, int n, const int32_t *species, 
     r[k] = sqrt(d[3 * k] * d[3 * k] + d[3 * k + 1] * d[3 * k + 1] + d[3 * k + 2] * d[3 * k + 2]);
     radial(M, r[k], &e[(size_t)k * R], &de[(size_t)k * R], &fc[k], &dfc[k]);
   }
+  const long chunk = ORA_FILTER_CHUNK;
+  double *Wc = (double *)malloc(sizeof(double) * (size_t)chunk * H);
+  double *dWc = (double *)malloc(sizeof(double) * (size_t)chunk * H);
   /* forward, keeping what the backward pass needs */
   double *h = (double *)malloc(sizeof(double) * (size_t)(T + 1) * n * H); /* h^0..h^T */
   double *xb = (double *)malloc(sizeof(double) * (size_t)T * n * H);     /* B h^{t-1} */
   double *u = (double *)malloc(sizeof(double) * (size_t)T * n * H);      /* C1 m + c1 */
   double *m = (double *)malloc(sizeof(double) * (size_t)n * H);
-  double *tmp = (double *)malloc(sizeof(double) * H);
-  double *Wf = (double *)malloc(sizeof(double) * H);
   for (int i = 0; i < n; ++i)
     memcpy(&h[(size_t)i * H], &v.W_emb[(size_t)species[i] * H], sizeof(double) * H);
   for (int t = 0; t < T; ++t) {
     const double *hp = &h[(size_t)t * n * H];
     double *hn = &h[(size_t)(t + 1) * n * H];
     double *xt = &xb[(size_t)t * n * H];
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) matvec(v.B[t], NULL, &hp[(size_t)i * H], H, H, &xt[(size_t)i * H]);
     memset(m, 0, sizeof(double) * (size_t)n * H);
-    for (long k = 0; k < np; ++k) {
-      int i = P[5 * k], j = P[5 * k + 1];
-      filter(M, &v, t, &e[(size_t)k * R], &de[(size_t)k * R], fc[k], dfc[k], Wf, NULL);
-      for (int c = 0; c < H; ++c) m[(size_t)i * H + c] += Wf[c] * xt[(size_t)j * H + c];
+    for (long k0 = 0; k0 < np; k0 += chunk) {
+      long k1 = k0 + chunk < np ? k0 + chunk : np;
+      filter_chunk(M, &v, t, k0, k1, e, de, fc, dfc, Wc, NULL);
+      for (long k = k0; k < k1; ++k) {
+        int i = P[5 * k], j = P[5 * k + 1];
+        const double *Wf = &Wc[(size_t)(k - k0) * H];
+        for (int c = 0; c < H; ++c) m[(size_t)i * H + c] += Wf[c] * xt[(size_t)j * H + c];
+      }
     }
-    for (int i = 0; i < n; ++i) {
-      double *ui = &u[((size_t)t * n + i) * H];
-      matvec(v.C1[t], v.c1[t], &m[(size_t)i * H], H, H, ui);
-      for (int c = 0; c < H; ++c) tmp[c] = silu(ui[c]);
-      matvec(v.C2[t], v.c2[t], tmp, H, H, &hn[(size_t)i * H]);
-      for (int c = 0; c < H; ++c) hn[(size_t)i * H + c] += hp[(size_t)i * H + c];
+#pragma omp parallel
+    {
+      double *tmp = (double *)malloc(sizeof(double) * H);
+#pragma omp for schedule(static)
+      for (int i = 0; i < n; ++i) {
+        double *ui = &u[((size_t)t * n + i) * H];
+        matvec(v.C1[t], v.c1[t], &m[(size_t)i * H], H, H, ui);
+        for (int c = 0; c < H; ++c) tmp[c] = silu(ui[c]);
+        matvec(v.C2[t], v.c2[t], tmp, H, H, &hn[(size_t)i * H]);
+        for (int c = 0; c < H; ++c) hn[(size_t)i * H + c] += hp[(size_t)i * H + c];
+      }
+      free(tmp);
     }
   }
-  /* readout */
+  /* readout: per-atom energies side by side, then their sum in atom order */
   double E = 0.0;
-  double *y = (double *)malloc(sizeof(double) * RH);
   const double *hT = &h[(size_t)T * n * H];
-  for (int i = 0; i < n; ++i) {
-    matvec(v.W1, v.b1, &hT[(size_t)i * H], RH, H, y);
-    double ei = v.b2[0];
-    for (int o = 0; o < RH; ++o) ei += v.w2[o] * silu(y[o]);
-    E += ei;
+  double *ea = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel
+  {
+    double *y = (double *)malloc(sizeof(double) * RH);
+#pragma omp for schedule(static)
+    for (int i = 0; i < n; ++i) {
+      matvec(v.W1, v.b1, &hT[(size_t)i * H], RH, H, y);
+      double ei = v.b2[0];
+      for (int o = 0; o < RH; ++o) ei += v.w2[o] * silu(y[o]);
+      ea[i] = ei;
+    }
+    free(y);
   }
+  for (int i = 0; i < n; ++i) E += ea[i];
   E *= M->scale;
+  free(ea);
 
   if (F) {
     /* backward: gh = dE/dh^t, per atom */
@@ -208,40 +243,55 @@ double ora_mpnn_energy_forces(const ora_mpnn *M, int n, const int32_t *species, 
     double *gm = (double *)malloc(sizeof(double) * (size_t)n * H);
     double *gx = (double *)malloc(sizeof(double) * (size_t)n * H);
     double *gr = (double *)calloc((size_t)(np > 0 ? np : 1), sizeof(double));
-    double *dWf = (double *)malloc(sizeof(double) * H);
-    double *g = (double *)malloc(sizeof(double) * RH);
-    double *gs = (double *)malloc(sizeof(double) * H);
-    for (int i = 0; i < n; ++i) {
-      matvec(v.W1, v.b1, &hT[(size_t)i * H], RH, H, y);
-      for (int o = 0; o < RH; ++o) g[o] = M->scale * v.w2[o] * dsilu(y[o]);
-      matvec_t_acc(v.W1, g, RH, H, &gh[(size_t)i * H]);
+#pragma omp parallel
+    {
+      double *y = (double *)malloc(sizeof(double) * RH);
+      double *g = (double *)malloc(sizeof(double) * RH);
+#pragma omp for schedule(static)
+      for (int i = 0; i < n; ++i) {
+        matvec(v.W1, v.b1, &hT[(size_t)i * H], RH, H, y);
+        for (int o = 0; o < RH; ++o) g[o] = M->scale * v.w2[o] * dsilu(y[o]);
+        matvec_t_acc(v.W1, g, RH, H, &gh[(size_t)i * H]);
+      }
+      free(y); free(g);
     }
     for (int t = T - 1; t >= 0; --t) {
       const double *xt = &xb[(size_t)t * n * H];
       /* through h^{t+1} = h^t + C2 silu(u) + c2 and u = C1 m + c1 */
       memcpy(gp, gh, sizeof(double) * (size_t)n * H); /* residual */
       memset(gm, 0, sizeof(double) * (size_t)n * H);
-      for (int i = 0; i < n; ++i) {
-        const double *ui = &u[((size_t)t * n + i) * H];
-        memset(gs, 0, sizeof(double) * H);
-        matvec_t_acc(v.C2[t], &gh[(size_t)i * H], H, H, gs);
-        for (int c = 0; c < H; ++c) gs[c] *= dsilu(ui[c]);
-        matvec_t_acc(v.C1[t], gs, H, H, &gm[(size_t)i * H]);
+#pragma omp parallel
+      {
+        double *gs = (double *)malloc(sizeof(double) * H);
+#pragma omp for schedule(static)
+        for (int i = 0; i < n; ++i) {
+          const double *ui = &u[((size_t)t * n + i) * H];
+          memset(gs, 0, sizeof(double) * H);
+          matvec_t_acc(v.C2[t], &gh[(size_t)i * H], H, H, gs);
+          for (int c = 0; c < H; ++c) gs[c] *= dsilu(ui[c]);
+          matvec_t_acc(v.C1[t], gs, H, H, &gm[(size_t)i * H]);
+        }
+        free(gs);
       }
       /* through m_i = sum_j W_ij (.) x_j */
       memset(gx, 0, sizeof(double) * (size_t)n * H);
-      for (long k = 0; k < np; ++k) {
-        int i = P[5 * k], j = P[5 * k + 1];
-        filter(M, &v, t, &e[(size_t)k * R], &de[(size_t)k * R], fc[k], dfc[k], Wf, dWf);
-        double s = 0.0;
-        for (int c = 0; c < H; ++c) {
-          double gw = gm[(size_t)i * H + c] * xt[(size_t)j * H + c];
-          s += gw * dWf[c];
-          gx[(size_t)j * H + c] += Wf[c] * gm[(size_t)i * H + c];
+      for (long k0 = 0; k0 < np; k0 += chunk) {
+        long k1 = k0 + chunk < np ? k0 + chunk : np;
+        filter_chunk(M, &v, t, k0, k1, e, de, fc, dfc, Wc, dWc);
+        for (long k = k0; k < k1; ++k) {
+          int i = P[5 * k], j = P[5 * k + 1];
+          const double *Wf = &Wc[(size_t)(k - k0) * H], *dWf = &dWc[(size_t)(k - k0) * H];
+          double s = 0.0;
+          for (int c = 0; c < H; ++c) {
+            double gw = gm[(size_t)i * H + c] * xt[(size_t)j * H + c];
+            s += gw * dWf[c];
+            gx[(size_t)j * H + c] += Wf[c] * gm[(size_t)i * H + c];
+          }
+          gr[k] += s;
         }
-        gr[k] += s;
       }
       /* through x_j = B h_j */
+#pragma omp parallel for schedule(static)
       for (int j = 0; j < n; ++j) matvec_t_acc(v.B[t], &gx[(size_t)j * H], H, H, &gp[(size_t)j * H]);
       memcpy(gh, gp, sizeof(double) * (size_t)n * H);
     }
@@ -255,9 +305,9 @@ double ora_mpnn_energy_forces(const ora_mpnn *M, int n, const int32_t *species, 
         F[3 * j + a] -= dq;
       }
     }
-    free(gh); free(gp); free(gm); free(gx); free(gr); free(dWf); free(g); free(gs);
+    free(gh); free(gp); free(gm); free(gx); free(gr);
   }
   free(P); free(d); free(r); free(e); free(de); free(fc); free(dfc);
-  free(h); free(xb); free(u); free(m); free(tmp); free(Wf); free(y);
+  free(h); free(xb); free(u); free(m); free(Wc); free(dWc);
   return E;
 }

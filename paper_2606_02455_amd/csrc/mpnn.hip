@@ -63,7 +63,8 @@ struct RowScan {
 
 template <bool WRITE>
 __device__ __forceinline__ RowScan row_pass(MpnnBuffers& b, const SysDev& S, const ListDev& L,
-                                            const WinDev& W, int f0, long row, float rc) {
+                                            const WinDev& W, int f0, long row, float rc,
+                                            long pair_cap) {
   __shared__ int s_e[kRowThreads / 64], s_o[kRowThreads / 64];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int fl = (int)(row / S.n), i = (int)(row - (long)fl * S.n);
@@ -106,14 +107,18 @@ __device__ __forceinline__ RowScan row_pass(MpnnBuffers& b, const SysDev& S, con
         const int pp = base_o + tot_o + po + __popcll(bo & below);
         const float a = 3.14159265358979f / rc;
         b.uid[e] = pp;
-        b.ua[pp] = (int)row;
-        b.ub[pp] = (int)((long)fl * S.n + j);
-        b.fcd[2 * pp] = 0.5f * (cosf(a * r) + 1.0f);
-        b.fcd[2 * pp + 1] = -0.5f * a * sinf(a * r);
-        b.uv[4 * pp] = d[0] / r;
-        b.uv[4 * pp + 1] = d[1] / r;
-        b.uv[4 * pp + 2] = d[2] / r;
-        b.uv[4 * pp + 3] = r;
+        if (pp < pair_cap) {
+          b.ua[pp] = (int)row;
+          b.ub[pp] = (int)((long)fl * S.n + j);
+          b.fcd[2 * pp] = 0.5f * (cosf(a * r) + 1.0f);
+          b.fcd[2 * pp + 1] = -0.5f * a * sinf(a * r);
+          b.uv[4 * pp] = d[0] / r;
+          b.uv[4 * pp + 1] = d[1] / r;
+          b.uv[4 * pp + 2] = d[2] / r;
+          b.uv[4 * pp + 3] = r;
+        } else {
+          b.counts[3] = 1;  // more pairs than the buffers hold: reported, not written
+        }
       } else {
         b.uid[e] = -1;  // reverse edge: resolved by k_mp_reverse
       }
@@ -129,7 +134,7 @@ __device__ __forceinline__ RowScan row_pass(MpnnBuffers& b, const SysDev& S, con
 __global__ __launch_bounds__(kRowThreads) void k_mp_count(MpnnBuffers b, SysDev S, ListDev L,
                                                           WinDev W, int f0, float rc) {
   const long row = blockIdx.x;
-  const RowScan c = row_pass<false>(b, S, L, W, f0, row, rc);
+  const RowScan c = row_pass<false>(b, S, L, W, f0, row, rc, 0);
   if (threadIdx.x == 0) {
     b.off[row] = c.edges;
     b.poff[row] = c.owners;
@@ -172,14 +177,16 @@ __global__ __launch_bounds__(1024) void k_mp_scan(MpnnBuffers b, long rows) {
     b.counts[0] = (int)s[1023];
     b.counts[1] = (int)s2[1023];
     b.counts[2] = 0;  // set by k_mp_reverse if a reverse edge has no owner
+    b.counts[3] = 0;  // set by k_mp_edges if the pairs exceed the capacity
   }
 }
 
 // directed edge records of every row in list order, and the pair records of
 // the edges the row owns
 __global__ __launch_bounds__(kRowThreads) void k_mp_edges(MpnnBuffers b, SysDev S, ListDev L,
-                                                          WinDev W, int f0, float rc) {
-  row_pass<true>(b, S, L, W, f0, blockIdx.x, rc);
+                                                          WinDev W, int f0, float rc,
+                                                          long pair_cap) {
+  row_pass<true>(b, S, L, W, f0, blockIdx.x, rc, pair_cap);
 }
 
 // every reverse edge refers to its owner: the neighbour row's edge back to
@@ -417,9 +424,12 @@ rocblas_status gemm_rm(rocblas_handle h, const float* A, const float* B, float* 
 
 }  // namespace
 
-// capacities: directed edges <= rows x list width; pairs <= a quarter of
-// that (the in-cutoff share of a list with the automatic width is about an
-// eighth; exceeding the capacity is reported by mpnn_eval)
+// capacities: directed edges <= rows x list width; unordered pairs <= a
+// quarter of that.  A pair is about half of the row's in-cutoff entries,
+// and with the automatic list width (1.3 x the expected entries within
+// cutoff + skin, plus 32, rounded up to 32) that is 0.17 of the width on the
+// 1536-atom liquid; a narrower caller-set width can exceed a quarter, which
+// k_mp_edges reports (counts[3]) instead of writing past the buffers
 static size_t pair_capacity(size_t slots) { return slots / 4 + 1; }
 
 size_t mpnn_buffer_bytes(int frames, int n, int mt) {
@@ -528,14 +538,18 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
   hipLaunchKernelGGL(k_mp_scan, dim3(1), dim3(1024), 0, st, b, rows);
   MP_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_mp_edges, dim3((unsigned)rows), dim3(kRowThreads), 0, st, b, S, L, W, f0,
-                     M.rc);
+                     M.rc, (long)pair_capacity((size_t)rows * mt));
   MP_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_mp_reverse, dim3(nblk(rows * mt, 256)), dim3(256), 0, st, b, rows, rows * mt);
   MP_HIP(hipGetLastError());
   // the pair count sizes the contractions below
-  int counts[3] = {0, 0, 0};
+  int counts[4] = {0, 0, 0, 0};
   MP_HIP(hipMemcpyAsync(counts, b.counts, sizeof(counts), hipMemcpyDeviceToHost, st));
   MP_HIP(hipStreamSynchronize(st));
+  if (counts[3]) {
+    snprintf(err, errlen, "pair count exceeds the capacity %zu", pair_capacity((size_t)rows * mt));
+    return false;
+  }
   if (counts[2]) {
     snprintf(err, errlen, "edge lists of the two directions of a pair differ");
     return false;

@@ -186,15 +186,32 @@ def _oracle_window_rounded(ora, w, xi, u, q0, p0):
     q, p = q0.copy(), p0.copy()
     img = np.zeros(q.shape, np.int32)
     r = ora.lsd_window(so, T, D, q, p, img, xi, u)
+    r["img"] = img
     return so, T, r
 
 
-@pytest.mark.parametrize("case", ["c1", "lj512"])
+def _first_midpoint_wraps(so, q0, p0):
+    """Image shifts of the oracle's first half step (A of Eq. aboba) from
+    (q0, p0): the wrap of q0 + dt/2 p0 / m into [0, L), as the oracle applies
+    it."""
+    x = q0 + (0.5 * so.dt) * p0 / so.masses[:, None]
+    s = np.floor(x / so.L)
+    x = x - s * so.L
+    s = s + (x >= so.L) - (x < 0.0)
+    return s.astype(np.int32)
+
+
+@pytest.mark.parametrize("case", ["c1", "lj512", "c1_faces"])
 def test_verify_and_commit_on_identical_frames(torch, lsd, ora, case):
     _say(f"verify parity {case}")
-    w = W.config("c1") if case == "c1" else W.lj_fluid(8, seed=21, K=8)
+    w = W.lj_fluid(8, seed=21, K=8) if case == "lj512" else W.config("c1")
+    if case == "c1_faces":
+        # a layer of atoms within the jitter of every face: image counters
+        # change inside the window and in the committed (reflected) step
+        w.positions = _near_faces(w)
     K, N = w.K, w.n_atoms
     checked_reject = 0
+    img_moves = 0
     for trial in range(6):
         xi = np.stack([ora.normals(w.seed + trial, 0, s, N) for s in range(1, K + 1)])
         u = np.array([ora.uniform(w.seed + trial, 0, s) for s in range(1, K + 1)])
@@ -248,6 +265,13 @@ def test_verify_and_commit_on_identical_frames(torch, lsd, ora, case):
             continue
         assert n == j_ref, (trial, n, j_ref)
         st = sysg.state()
+        if r["n_committed"] == n:
+            # image counters: the GPU counts from the wrapped first midpoint
+            # (its committed counters were 0 and the injected frame-0 deltas
+            # are 0), the oracle from q0 through that midpoint
+            img_ref = r["img"] - _first_midpoint_wraps(so, w.positions, w.momenta)
+            assert np.array_equal(st["img"], img_ref), (trial, np.argwhere(st["img"] != img_ref))
+            img_moves += int(np.count_nonzero(img_ref))
         if v_ref is not None:
             checked_reject += 1
             # reflected momentum: binary32 rounding plus the first-order effect
@@ -268,6 +292,8 @@ def test_verify_and_commit_on_identical_frames(torch, lsd, ora, case):
             assert np.array_equal(st["p"], pd[j_ref])
         sysg.destroy()
     assert checked_reject >= 1
+    if case == "c1_faces":
+        assert img_moves >= 3, img_moves
 
 
 def test_draft_steps_match_oracle(torch, lsd, ora):
@@ -733,3 +759,36 @@ def test_sampled_timing_windows_equal_untimed_windows(torch, lsd, every):
         b.set_verify_timing(True, every=-1)
     a.destroy()
     b.destroy()
+
+
+def test_plain_lj_matches_oracle_pathwise(torch, lsd, ora):
+    # plain target Langevin through graph-replayed windows (Philox stream
+    # keyed by step) against the oracle's plain ABOBA steps from the same
+    # binary32 start: unwrapped positions and momenta after 48 steps within
+    # the binary32 error of the forces and of the stored state, grown over
+    # the steps
+    _say("plain LJ pathwise c1")
+    w = W.config("c1")
+    n_steps, K = 48, w.K
+    g = lsd.LSDSystem(w, mode="plain")
+    g.run_to_step(n_steps, K, check_every=2)
+    st = g.state()
+    assert int(st["step"][0]) == n_steps and g.status() == 0
+    g.destroy()
+    so = _ora_system(ora, w)
+    T = _ora_pot(ora, w.target)
+    q, p = w.positions.copy(), W.f32(w.momenta)
+    img = np.zeros(q.shape, np.int32)
+    ora.plain_run(so, T, q, p, img, w.seed, 0, 0, n_steps)
+    L = float(w.box[0])
+    dq = (st["q"] + st["img"] * L) - (q + img * L)
+    dp = st["p"] - p
+    _say(f"  max |dq| {np.abs(dq).max():.2e}, max |dp| {np.abs(dp).max():.2e}")
+    # per step: binary32 forces (1e-5 of max |F|) enter p through c1, and
+    # p and q are stored in binary32; 48 steps with a growth factor of 4
+    c1 = (1 + so.a) * so.dt / 2
+    _, F0 = ora.energy_forces(T, w.positions, L)
+    per_step = c1 * 1e-5 * np.abs(F0).max() + 2 ** -23 * (1 + np.abs(p).max())
+    tol_p = 4 * n_steps * per_step
+    assert np.abs(dp).max() <= tol_p, (np.abs(dp).max(), tol_p)
+    assert np.abs(dq).max() <= so.dt * n_steps * tol_p + 4 * n_steps * 2 ** -24 * L

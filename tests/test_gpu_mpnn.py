@@ -56,18 +56,23 @@ def _zero_draft(w):
     return dict(kind="harmonic", k=0.0, anchor=w.positions)
 
 
+def _atom_box(w):
+    """Box edge of every atom's replica, [N, 1]."""
+    return np.repeat(np.asarray(w.box, np.float64), np.diff(w.atom_offsets))[:, None]
+
+
 def _frames(w, K, seed, amp=0.05):
     rng = np.random.default_rng(seed)
-    L = float(w.box[0])
+    L = _atom_box(w)
     fr = W.f32(np.mod(w.positions[None] + rng.uniform(-amp, amp, (K,) + w.positions.shape), L))
-    fr[fr >= L] = 0.0
+    fr = np.where(fr >= L[None], 0.0, fr)
     return fr
 
 
 def _inject(g, torch, qm, pd, fd):
     win = g.window()
     K, N = qm.shape[:2]
-    L = float(g.w.box[0])
+    L = _atom_box(g.w)[None]
     qc = qm.copy()
     qc[1:] -= L * np.round((qc[1:] - qc[0][None]) / L)
     q4 = np.zeros((K, N, 4), np.float32)
@@ -109,6 +114,45 @@ def _check_frames(torch, lsd, ora, w, K, scale, seed):
     g.destroy()
 
 
+def _check_replica_frames(torch, lsd, ora, w, K, scale, seed, amp=0.05):
+    """Per replica and frame: forces and energies of the batched evaluation
+    against the oracle's evaluation of that replica alone."""
+    from oracle.mpnn import MPNN
+    net = MPNN(W.mpnn_weights(3, seed=17), 3, rc=5.0, scale=scale)
+    g = lsd.LSDSystem(w, mode="lsd", target=_target(scale), draft=_zero_draft(w), k_max=K)
+    qm = _frames(w, K, seed, amp)
+    rng = np.random.default_rng(seed + 1)
+    sig = np.sqrt(w.masses() * w.kT * w.force_unit)[:, None]
+    pd = W.f32(rng.normal(size=(K + 1,) + w.positions.shape) * sig)
+    _inject(g, torch, qm, pd, np.zeros_like(qm))
+    g.mark_drafted(K)
+    g.verify_window()
+    g.accept_rollback(sync=True)
+    assert g.status() == 0
+    ft = g.window()["f_target"][:K].cpu().numpy().transpose(0, 2, 1).astype(np.float64)
+    en = g.energy.cpu().numpy()
+    inv = g.window()["frame_invalid"].cpu().numpy()
+    assert not inv[:, :K].any()
+    jobs = [(r, k) for r in range(w.n_replicas) for k in range(K)]
+
+    def ref(job):
+        r, k = job
+        sl = w.replica_slice(r)
+        return net.energy_forces(w.species[sl], qm[k, sl], float(w.box[r]))
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        refs = list(ex.map(ref, jobs))
+    worst = 0.0
+    for (r, k), (E, F) in zip(jobs, refs):
+        sl = w.replica_slice(r)
+        err = np.abs(ft[k, sl] - F).max() / np.abs(F).max()
+        worst = max(worst, err)
+        assert err <= FORCE_TOL, (r, k, err)
+        assert abs(en[r, k] - E) <= ENERGY_TOL * abs(E), (r, k, en[r, k], E)
+    _say(f"  {len(jobs)} replica frames, worst force error / max|F| = {worst:.2e}")
+    g.destroy()
+
+
 def test_mpnn_target_small_system(torch, lsd, ora):
     _say("mpnn 96 atoms")
     w = W.triatomic_liquid(32, seed=8, K=4)
@@ -141,3 +185,21 @@ def test_mpnn_plain_stepping(torch, lsd, ora):
     st = g.state()
     assert np.isfinite(st["p"]).all() and int(st["step"][0]) >= 3
     g.destroy()
+
+
+def test_mpnn_target_ragged_replicas_with_images(torch, lsd, ora):
+    # the batched-replica regime: boxes of 8-20 molecules (7.3-9.9 A edges,
+    # under 2 rc), so every replica is one cell with 27 images, edges reach
+    # periodic copies of the neighbours and of the atom itself, and tiles and
+    # edge blocks straddle replicas of uneven size
+    _say("mpnn ragged replicas (multi-image)")
+    w = W.triatomic_replicas(24, n_mol_lo=8, n_mol_hi=20, seed=44, K=3)
+    assert (np.asarray(w.box) < 10.0).all()
+    _check_replica_frames(torch, lsd, ora, w, 3, c3_scale(), seed=5, amp=0.04)
+
+
+def test_mpnn_target_full_size_c5_frames(torch, lsd, ora):
+    # the precision-at-scale system (24 576 atoms), two frames
+    _say("mpnn c5 size, 2 frames")
+    w = W.config("c5")
+    _check_frames(torch, lsd, ora, w, 2, c3_scale(), seed=6)

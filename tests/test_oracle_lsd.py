@@ -391,3 +391,53 @@ def test_obabo_lsd_accepts_everything_when_draft_is_target(ora):
     q, p, img = qref.copy(), np.zeros((n, 3)), np.zeros((n, 3), np.int32)
     st = ora.obabo_lsd_run(sysm, T, T, q, p, img, 5, 0, 200, 8)
     assert st["rejections"] == 0 and st["committed"] == 200
+
+
+# --- image counters of committed states (map g after a reflection) ----------
+def test_image_counters_unwrap_to_the_unbounded_trajectory(ora):
+    # Forces that do not depend on the positions (a zero-stiffness tether plus
+    # constant offsets; draft and target offsets differ, so windows end in
+    # reflected steps) make the momenta, decisions and unwrapped positions
+    # independent of the box.  Windows in a small periodic box, where atoms
+    # cross faces in every half step, must therefore give q + img L equal to
+    # the positions of the same windows in a box too large to wrap.  This
+    # pins the counters of every committed state, including the reflected
+    # step's midpoint and map g (Eq. reflectionVerify, Thm. 1).
+    n, K, L, big = 200, 6, 2.0, 1024.0
+    rng = np.random.default_rng(91)
+    q0 = rng.uniform(0.0, L, (n, 3))
+    p0 = rng.normal(size=(n, 3))
+    b_t = rng.normal(size=(n, 3))
+    sm = ora.System(n, L, 1.0, 0.1, 1.0, 1.0)
+    sb = ora.System(n, big, 1.0, 0.1, 1.0, 1.0)
+    sig = sm.sigma()[:, None]
+    c1 = (1 + sm.a) * sm.dt / 2
+    db = rng.normal(size=(n, 3))
+    db *= 1.0 / np.linalg.norm(c1 * db / sig)   # |delta| = 1: rejection rate ~0.34
+    pots = {}
+    for name, s in (("small", sm), ("big", sb)):
+        anc = np.zeros((n, 3))
+        pots[name] = (ora.Potential.harmonic(0.0, anc, offset=b_t),
+                      ora.Potential.harmonic(0.0, anc, offset=b_t + db))
+    qs, ps, imgs = q0.copy(), p0.copy(), np.zeros((n, 3), np.int32)
+    qb, pb, imgb = q0 + big / 2, p0.copy(), np.zeros((n, 3), np.int32)
+    step, reflected, crossed = 0, 0, 0
+    for _ in range(40):
+        xi = np.stack([ora.normals(7, 0, step + k + 1, n) for k in range(K)])
+        u = np.array([ora.uniform(7, 0, step + k + 1) for k in range(K)])
+        img_before = imgs.copy()
+        rs = ora.lsd_window(sm, *pots["small"], qs, ps, imgs, xi, u)
+        rb = ora.lsd_window(sb, *pots["big"], qb, pb, imgb, xi, u)
+        assert rs["n_committed"] == rb["n_committed"]
+        assert np.array_equal(rs["accept"], rb["accept"])
+        assert np.array_equal(ps, pb)
+        assert not imgb.any()
+        unwrapped = qs + imgs * L - q0
+        assert np.max(np.abs(unwrapped - (qb - big / 2 - q0))) < 1e-9
+        assert (qs >= 0).all() and (qs < L).all()
+        reflected += rs["rejected"]
+        if rs["rejected"]:
+            crossed += int(np.count_nonzero(imgs != img_before))
+        step += rs["n_committed"]
+    assert reflected >= 10 and crossed >= 50, (reflected, crossed)
+
