@@ -467,6 +467,38 @@ LSD_API lsd_status lsd_net_adam_step(float *params, double *m, double *v, double
                                      int32_t n_params, double lr, double beta1, double beta2,
                                      double eps, int64_t t, lsd_stream stream);
 
+/* Kinetic energy per replica in binary64, the thermostat observable of
+ * Sec. 4.3 (Tab. heating; the kinetic temperature of replica r is
+ * T_kin = 2 ke[r] / (3 N_r k_B): the paper prints it without the 3 of the
+ * three axes):
+ *   ke[r] = sum over atoms i of replica r and axes d of p[d][i]^2 / (2 m_i).
+ * Stateless; works on any momenta in the library's layout (e.g. the
+ * committed state of a system, or frames of a window).
+ *   p: device binary32 [3][n_atoms] (SoA); species: device int32 [n_atoms],
+ *      or NULL (every atom has species 0); species_mass: host binary64
+ *      [n_species], 1 <= n_species <= 8, all > 0 (read during the call);
+ *   atom_offsets: device int32 [n_replicas + 1] (replica r = atoms
+ *      [atom_offsets[r], atom_offsets[r+1])); max_replica_atoms: host, at
+ *      least the largest replica (a replica with more atoms gets NaN);
+ *   ke: device binary64 [n_replicas], overwritten.
+ * Each square is exact in binary64; the products with 1/(2m) and all sums
+ * are binary64 in a fixed order (chunks of 2048 atoms, lane-strided, wave
+ * butterfly, chunks in order), so results repeat bit for bit.  All terms
+ * are positive, so the relative error against the exact value of the
+ * binary32 momenta is at most about (3 N_r + 2) 2^-53.
+ *   scratch: device memory of at least lsd_kinetic_energy_scratch_size()
+ *      bytes (partial sums; its contents on entry do not matter).
+ * Asynchronous on `stream`, no host synchronisation, graph-capturable.
+ * Errors: INVALID_ARG (null pointer, bad count or mass), CAPACITY (scratch
+ * too small), HIP. */
+LSD_API lsd_status lsd_kinetic_energy_scratch_size(int32_t n_replicas,
+                                                   int32_t max_replica_atoms, size_t *bytes);
+LSD_API lsd_status lsd_kinetic_energy(const float *p, int32_t n_atoms, const int32_t *species,
+                                      const double *species_mass, int32_t n_species,
+                                      const int32_t *atom_offsets, int32_t n_replicas,
+                                      int32_t max_replica_atoms, double *ke, void *scratch,
+                                      size_t scratch_bytes, lsd_stream stream);
+
 /* Verifier state of pipelined LSD (Alg. 2, App. C): host-only bookkeeping
  * for callers that submit every draft step for verification as soon as it
  * is drafted and receive target results in any order (a pool of target

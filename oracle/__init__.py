@@ -97,6 +97,8 @@ def _declare(L):
     L.ora_plain_run.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), _dp, _dp, _ip,
                                 C.c_uint64, C.c_uint32, C.c_uint64, C.c_int64, _dp, _dp, _dp]
     L.ora_num_threads.restype = C.c_int
+    L.ora_kinetic_energy.argtypes = [C.c_int, _dp, _dp]
+    L.ora_kinetic_energy.restype = C.c_double
     L.ora_normals_tag.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_int, _dp]
     L.ora_obabo_step.argtypes = [C.POINTER(_Sys), C.POINTER(_Pot), _dp, _dp, _ip, _dp, _dp]
     L.ora_obabo_step.restype = C.c_double
@@ -288,6 +290,23 @@ def plain_run(system, target, q, p, img, seed, replica, step0, n_steps, record=F
 
 def num_threads():
     return lib().ora_num_threads()
+
+
+def kinetic_energy(p, mass):
+    """K = sum_i |p_i|^2 / (2 m_i) in binary64 (p: [n, 3]; mass: scalar or
+    per atom [n]); the kinetic temperature of Sec. 4.3 is 2 K / (3 n k_B)."""
+    p = _f64(p).reshape(-1, 3)
+    n = p.shape[0]
+    m = np.ascontiguousarray(np.broadcast_to(np.asarray(mass, np.float64), (n,)))
+    return lib().ora_kinetic_energy(n, _d(p), _d(m))
+
+
+def kinetic_temperature(p, mass, k_B=1.0):
+    """T_kin = 2 K / (3 n k_B): no constraints, no removal of the centre of
+    mass motion.  The paper's formula (Sec. 4.3) lacks the 3 of the three
+    axes; with it, equipartition gives <T_kin> = T."""
+    p = _f64(p).reshape(-1, 3)
+    return 2.0 * kinetic_energy(p, mass) / (3.0 * p.shape[0] * k_B)
 
 
 # --- (OBABO) splitting (App. E) ----------------------------------------------

@@ -727,6 +727,18 @@ void ora_plain_run(const ora_sys *S, const ora_pot *T, double *q, double *p,
   free(xi);
 }
 
+/* Kinetic energy of one system in binary64: the sum over atoms i and axes
+ * d of p_id^2 / (2 m_i), with p row-major [n][3] and m per atom.  This is
+ * the observable behind the kinetic temperature of Sec. 4.3 (Tab. heating),
+ * T_kin = 2 K / (3 n k_B) (the paper prints the formula without the 3; see
+ * the reading in the Python wrapper).  Summed serially in atom order. */
+double ora_kinetic_energy(int n, const double *p, const double *mass) {
+  double k = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) k += p[3 * i + d] * p[3 * i + d] / (2.0 * mass[i]);
+  return k;
+}
+
 int ora_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -109,6 +109,10 @@ EXPORTS = {
                                  C.c_void_p, C.c_void_p], C.c_int),
     "lsd_net_adam_step": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
                            C.c_double, C.c_double, C.c_double, C.c_int64, C.c_void_p], C.c_int),
+    "lsd_kinetic_energy_scratch_size": ([C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
+    "lsd_kinetic_energy": ([C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double), C.c_int32,
+                            C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                            C.c_size_t, C.c_void_p], C.c_int),
     "lsd_pipeline_create": ([C.POINTER(C.c_void_p)], C.c_int),
     "lsd_pipeline_destroy": ([C.c_void_p], C.c_int),
     "lsd_pipeline_submit": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
@@ -195,6 +199,33 @@ def fit_pair_solve(gram, ridge=1e-8):
     _check(load().lsd_fit_pair_solve(g.ctypes.data_as(C.c_void_p), P, float(ridge),
                                      w.ctypes.data_as(C.c_void_p)), "lsd_fit_pair_solve")
     return w
+
+
+def kinetic_energy_scratch_size(n_replicas, max_replica_atoms):
+    n = C.c_size_t()
+    _check(load().lsd_kinetic_energy_scratch_size(int(n_replicas), int(max_replica_atoms),
+                                                  C.byref(n)), "lsd_kinetic_energy_scratch_size")
+    return n.value
+
+
+def kinetic_energy(p, species, species_mass, atom_offsets, max_replica_atoms, out=None,
+                   scratch=None):
+    """Per-replica kinetic energy (binary64) of device momenta p [3][N]
+    (float32); species: int32 device [N] or None; species_mass: host
+    sequence; atom_offsets: int32 device [R+1]."""
+    import torch
+    R = atom_offsets.shape[0] - 1
+    if out is None:
+        out = torch.empty((R,), dtype=torch.float64, device=p.device)
+    if scratch is None:
+        scratch = torch.empty((kinetic_energy_scratch_size(R, max_replica_atoms),),
+                              dtype=torch.uint8, device=p.device)
+    m = (C.c_double * len(species_mass))(*[float(v) for v in species_mass])
+    _check(load().lsd_kinetic_energy(_ptr(p), int(p.shape[1]), _ptr(species), m,
+                                     len(species_mass), _ptr(atom_offsets), R,
+                                     int(max_replica_atoms), _ptr(out), _ptr(scratch),
+                                     scratch.numel(), _stream(torch)), "lsd_kinetic_energy")
+    return out
 
 
 def rng_normals(seed, replica, step, n):
@@ -536,6 +567,21 @@ class LSDSystem:
         _check(load().lsd_get_verify_timing(self.h, C.byref(ms), C.byref(n)),
                "lsd_get_verify_timing")
         return ms.value, n.value
+
+    def kinetic_energy(self, p=None):
+        """Per-replica kinetic energy (binary64, device [R]) of the committed
+        momenta, or of the given device momenta [3][N]."""
+        t = self.torch
+        if getattr(self, "_ke_tables", None) is None:
+            off = t.tensor(self._offsets, dtype=t.int32, device="cuda")
+            spc = t.tensor(self._species, dtype=t.int32, device="cuda")
+            nmax = int(np.diff(self._offsets).max())
+            scr = t.empty((kinetic_energy_scratch_size(self.R, nmax),), dtype=t.uint8,
+                          device="cuda")
+            self._ke_tables = (off, spc, nmax, scr)
+        off, spc, nmax, scr = self._ke_tables
+        return kinetic_energy(self.p if p is None else p, spc, list(self._masses), off, nmax,
+                              scratch=scr)
 
     def state(self):
         """Committed state; with the (OBABO) integrator q and p are the
