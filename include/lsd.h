@@ -499,6 +499,27 @@ LSD_API lsd_status lsd_kinetic_energy(const float *p, int32_t n_atoms, const int
                                       int32_t max_replica_atoms, double *ke, void *scratch,
                                       size_t scratch_bytes, lsd_stream stream);
 
+/* lsd_kinetic_energy without a scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, kernels, summation
+ * order and results (bit for bit) as lsd_kinetic_energy; the partial sums go
+ * to a static device array of the library instead of caller scratch.
+ *   Limit: n_replicas * ceil(max_replica_atoms / 2048) <= 65536 partial sums
+ *   (512 KiB, held on every GPU the library runs on until the process
+ *   ends); larger requests fail with CAPACITY.
+ * The array is shared by every call on a GPU: calls that overlap on one GPU
+ * (different streams, or threads) race and must be serialised by the caller.
+ * Nothing from an earlier call is read.  Calls no hipMalloc, hipFree or
+ * allocating library routine; the first call on a device looks up the
+ * array's device address (hipGetSymbolAddress) with that device current.
+ * Errors: INVALID_ARG, CAPACITY, UNSUPPORTED (device index above 63), HIP. */
+LSD_API lsd_status lsd_kinetic_energy_noalloc(const float *p, int32_t n_atoms,
+                                              const int32_t *species,
+                                              const double *species_mass, int32_t n_species,
+                                              const int32_t *atom_offsets, int32_t n_replicas,
+                                              int32_t max_replica_atoms, double *ke,
+                                              lsd_stream stream);
+
 /* Verifier state of pipelined LSD (Alg. 2, App. C): host-only bookkeeping
  * for callers that submit every draft step for verification as soon as it
  * is drafted and receive target results in any order (a pool of target

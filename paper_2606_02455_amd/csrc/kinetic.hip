@@ -15,11 +15,20 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "lsd.h"
 #include "lsd_device.h"
 
 lsd_status lsd_record_error(lsd_status s, const char* msg);  // lsd_api.hip
+
+// Partial sums of lsd_kinetic_energy_noalloc: a static array, one copy per
+// GPU, shared by every call on that GPU (calls that overlap on one GPU race).
+// Host code never passes the array's name to a kernel (in host code it is a
+// stand-in, not a device address): it uses the address hipGetSymbolAddress
+// returns for the current device.
+#define LSD_KE_NOALLOC_PARTIALS 65536  // replicas x chunks (512 KiB)
+static __device__ __align__(256) double scratch[LSD_KE_NOALLOC_PARTIALS];
 
 namespace {
 
@@ -112,6 +121,31 @@ lsd_status ke_launch(const float* p, int n_atoms, const int* species, const KeMa
   return LSD_OK;
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+lsd_status noalloc_scratch(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return lsd_record_error(LSD_ERR_HIP, hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return lsd_record_error(LSD_ERR_UNSUPPORTED, "kinetic energy: device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return lsd_record_error(LSD_ERR_HIP, e != hipSuccess ? hipGetErrorString(e)
+                                                           : "kinetic energy: null scratch address");
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return LSD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -140,6 +174,28 @@ lsd_status lsd_kinetic_energy(const float* p, int32_t n_atoms, const int32_t* sp
                                               "lsd_kinetic_energy_scratch_size");
   return ke_launch(p, n_atoms, species, M, atom_offsets, n_replicas, chunks, ke,
                    static_cast<double*>(scratch), static_cast<hipStream_t>(stream));
+}
+
+lsd_status lsd_kinetic_energy_noalloc(const float* p, int32_t n_atoms, const int32_t* species,
+                                      const double* species_mass, int32_t n_species,
+                                      const int32_t* atom_offsets, int32_t n_replicas,
+                                      int32_t max_replica_atoms, double* ke, lsd_stream stream) {
+  KeMass M;
+  lsd_status s = ke_check(p, n_atoms, species_mass, n_species, atom_offsets, n_replicas,
+                          max_replica_atoms, ke, &M);
+  if (s != LSD_OK) return s;
+  const int chunks = ke_chunks(max_replica_atoms);
+  if ((long)n_replicas * (long)chunks > LSD_KE_NOALLOC_PARTIALS)
+    return lsd_record_error(LSD_ERR_CAPACITY,
+                            "kinetic energy (no allocation): n_replicas x ceil(max_replica_atoms"
+                            " / 2048) exceeds 65536");
+  double* part = nullptr;
+  s = noalloc_scratch(&part);
+  if (s != LSD_OK) return s;
+  // pass 1 writes every partial it covers (zero past a replica's end), so
+  // nothing left by an earlier call is read
+  return ke_launch(p, n_atoms, species, M, atom_offsets, n_replicas, chunks, ke, part,
+                   static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

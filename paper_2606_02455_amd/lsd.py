@@ -113,6 +113,9 @@ EXPORTS = {
     "lsd_kinetic_energy": ([C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double), C.c_int32,
                             C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                             C.c_size_t, C.c_void_p], C.c_int),
+    "lsd_kinetic_energy_noalloc": ([C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double),
+                                    C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                    C.c_void_p], C.c_int),
     "lsd_pipeline_create": ([C.POINTER(C.c_void_p)], C.c_int),
     "lsd_pipeline_destroy": ([C.c_void_p], C.c_int),
     "lsd_pipeline_submit": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
@@ -225,6 +228,19 @@ def kinetic_energy(p, species, species_mass, atom_offsets, max_replica_atoms, ou
                                      len(species_mass), _ptr(atom_offsets), R,
                                      int(max_replica_atoms), _ptr(out), _ptr(scratch),
                                      scratch.numel(), _stream(torch)), "lsd_kinetic_energy")
+    return out
+
+
+def kinetic_energy_noalloc(p, species, species_mass, atom_offsets, max_replica_atoms, out):
+    """kinetic_energy without caller scratch (the library's static device
+    array); `out` is the caller's binary64 device tensor [R]."""
+    import torch
+    R = atom_offsets.shape[0] - 1
+    m = (C.c_double * len(species_mass))(*[float(v) for v in species_mass])
+    _check(load().lsd_kinetic_energy_noalloc(_ptr(p), int(p.shape[1]), _ptr(species), m,
+                                             len(species_mass), _ptr(atom_offsets), R,
+                                             int(max_replica_atoms), _ptr(out), _stream(torch)),
+           "lsd_kinetic_energy_noalloc")
     return out
 
 
