@@ -61,7 +61,7 @@ struct Layout {
   size_t cell_rep, cell_count, cell_start, cell_cursor, cell_unsorted, cell_atoms, atom_cell;
   size_t nbr_t, cnt_t, nbr_d, cnt_d, qref, qwrap, rebuild;
   // window
-  size_t qmid, p, fd, ft, invalid, partial, commit_frame, reflected, coef, counters, status;
+  size_t qmid, p, fd, ft, invalid, nvalid, partial, commit_frame, reflected, coef, counters, status;
   size_t ec = 0, ec_prev = 0, ec_samples = 0;  // error-correction caches (0: off)
   size_t mpnn = 0, mpnn_bytes = 0, blas = 0, epart = 0;
   size_t net_v = 0;  // learned draft: edge coefficients [N][LSD_NET_MAX_BASIS]
@@ -262,6 +262,7 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   L->fd = bump(&off, K * 3 * n * 4);
   L->ft = bump(&off, K * 3 * n * 4);
   L->invalid = bump(&off, (size_t)R * K * 4);
+  L->nvalid = bump(&off, 4);
   L->partial = bump(&off, K * T * 4 * 8);
   L->commit_frame = bump(&off, R * 4);
   L->reflected = bump(&off, R * 4);
@@ -539,6 +540,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cell_cursor), 0, L.n_cells, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.status), 0, 4, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.invalid), 0, R * cfg->k_max, st);
+  if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.nvalid), 0, 1, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_t), 0, N, st);
   if (e == hipSuccess) e = launch_zero_i64(ws<long long>(s, L.counters), LSD_NCOUNT * R, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_d), 0, N, st);
@@ -636,6 +638,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   W.fd = ws<float>(s, L.fd);
   W.ft = ws<float>(s, L.ft);
   W.invalid = ws<int>(s, L.invalid);
+  W.nvalid = ws<int>(s, L.nvalid);
   W.partial = ws<double>(s, L.partial);
   W.commit_frame = ws<int>(s, L.commit_frame);
   W.reflected = ws<int>(s, L.reflected);
@@ -740,6 +743,7 @@ lsd_status lsd_mark_drafted(lsd_system* s, int32_t K, lsd_stream stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   s->W.K = K;
   HIP_TRY(launch_fill_int(s->W.invalid, 0, s->S.R * s->S.kmax, st));
+  HIP_TRY(launch_fill_int(s->W.nvalid, K, 1, st));  // bound: every frame
   HIP_TRY(launch_fill_int(s->Lst.rebuild, 1, s->S.R, st));  // lists from the caller's frame 0
   HIP_TRY(launch_build_lists(s->S, s->Lst, s->W, true, st));
   HIP_TRY(launch_frame_validity(s->S, s->Lst, s->W, st));

@@ -131,6 +131,7 @@ struct WinDev {
   float* fd;          // [kmax][3][N]
   float* ft;          // [kmax][3][N]
   int* invalid;       // [R][kmax]
+  int* nvalid;        // [1]: bound on the valid frames of any replica in this window
   double* partial;    // [kmax][n_tiles][4]: S1, S2, E, unused
   int* commit_frame;  // [R]
   int* reflected;     // [R]

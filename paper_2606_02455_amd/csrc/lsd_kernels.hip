@@ -50,6 +50,7 @@ __device__ __forceinline__ void window_start_item(const SysDev& S, const ListDev
     const int rr = i / S.kmax, f = i % S.kmax;
     W.invalid[i] = (S.step[rr] + f + 1 > S.step_limit) ? 1 : 0;
   }
+  if (i == 0) W.nvalid[0] = 0;  // raised by the drafting of each valid frame
   if (i >= S.n) return;
   const int r = S.atom_rep[i];
   const int sp = S.species ? S.species[i] : 0;
@@ -415,6 +416,8 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_draft(SysDev S, ListDev Lst, W
     if (threadIdx.x == 0 && tile == Tl.rep_tile_off[r] && k + 1 < W.K) inv[k + 1] = 1;
     return;
   }
+  // frame k is valid for this replica: the verification covers it
+  if (threadIdx.x == 0 && tile == Tl.rep_tile_off[r]) atomicMax(W.nvalid, k + 1);
   const int a = threadIdx.x / LSD_LPA, sub = threadIdx.x % LSD_LPA;
   const bool in = a < Tl.count[tile];
   const int i = Tl.start[tile] + (in ? a : 0);
@@ -500,32 +503,34 @@ __global__ __launch_bounds__(256) void k_frame_validity(SysDev S, ListDev Lst, W
   }
 }
 
-// verify_step (Alg. 2) for the valid frames of the window.  Block = one tile
-// of up to 64 atoms of one replica x FW frames.  Each atom uses LSD_LPA lanes
-// (same entry split and butterfly as the draft kernel), which read their
-// neighbour entries straight from the list (the lanes of an atom read
-// consecutive words; the rows stay in L1 over the loop), and each lane
-// advances all FW frames per neighbour entry, so an entry is decoded once and
-// its image shift reused.  No LDS staging: occupancy is set by the registers
-// alone (staging the rows, in full or in chunks, measured 1.4-1.9x slower).
+// verify_step (Alg. 2) for the valid frames of the window.  Work item = one
+// tile of up to 64 atoms of one replica x FW frames; the items of the frame
+// groups that can hold a valid frame (W.nvalid, raised by the drafting of
+// every valid frame) are taken by a fixed grid in order, frame group by
+// frame group, so no block is launched for the frames a window never
+// reaches.  Each atom uses LSD_LPA lanes (same entry split and butterfly as
+// the draft kernel), which read their neighbour entries straight from the
+// list (the lanes of an atom read consecutive words; the rows stay in L1 over
+// the loop), and each lane advances all FW frames per neighbour entry, so an
+// entry is decoded once and its image shift reused.  No LDS staging:
+// occupancy is set by the registers alone (staging the rows, in full or in
+// chunks, measured 1.4-1.9x slower).
 // Epilogue per atom and frame (binary64):
 //   z = (p~_k - <p~_k>) / sigma,  delta = c1 (F~_k - F_k) / sigma
 // reduced over the tile in a fixed order: S1 = delta.z, S2 = delta.delta,
-// and the potential energy.
+// and the potential energy.  Which block takes an item does not change any
+// result.
 #ifndef LSD_VGATHER
 #define LSD_VGATHER 2  // neighbour entries per lane per iteration of k_verify
 #endif
 template <int FW>
-__global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, WinDev W,
-                                                         TileDev Tl, PotDev P) {
-  __shared__ float s_shift[27][6];
-  __shared__ double s_red[LSD_VWAVES][FW][3];
-  const int tile = blockIdx.x;
+__device__ __forceinline__ void verify_item(const SysDev& S, const ListDev& Lst, const WinDev& W,
+                                            const TileDev& Tl, const PotDev& P, int tile, int f0,
+                                            float (*s_shift)[6], double (*s_red)[FW][3]) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int a = t / LSD_LPA, sub = t % LSD_LPA;
   const int start = Tl.start[tile], count = Tl.count[tile], r = Tl.rep[tile];
   const int* inv = W.invalid + (size_t)r * S.kmax;
-  const int f0 = blockIdx.y * FW;
   bool valid[FW];
   bool any = false;
 #pragma unroll
@@ -569,7 +574,7 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, 
     for (int u = 0; u < LSD_VGATHER; ++u)
 #pragma unroll
       for (int f = 0; f < FW; ++f) {
-        // frame f0 exists in every block; an invalid frame's load is unused
+        // frame f0 exists in every item; an invalid frame's load is unused
         const size_t fr = (size_t)(valid[f] ? f0 + f : f0) * N;
         xj[u][f] = W.qmid[fr + jj[u]];
       }
@@ -641,6 +646,20 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, 
       for (int w = 1; w < LSD_VWAVES; ++w) v += s_red[w][t][q];
       out[q] = v;
     }
+  }
+  __syncthreads();  // the next item rewrites s_shift and s_red
+}
+
+template <int FW>
+__global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, WinDev W,
+                                                         TileDev Tl, PotDev P) {
+  __shared__ float s_shift[27][6];
+  __shared__ double s_red[LSD_VWAVES][FW][3];
+  const int nv = min(W.nvalid[0], W.K);
+  const int items = (nv + FW - 1) / FW * S.n_tiles;
+  for (int v = blockIdx.x; v < items; v += gridDim.x) {
+    const int g = v / S.n_tiles;
+    verify_item<FW>(S, Lst, W, Tl, P, v - g * S.n_tiles, g * FW, s_shift, s_red);
   }
 }
 
@@ -1001,11 +1020,21 @@ hipError_t launch_frame_validity(const SysDev& S, const ListDev& L, const WinDev
 #define LSD_VERIFY_FW_MAX 8
 #endif
 
+// Blocks of the verification grid: every item of a window whose frames are
+// all valid, up to about the blocks the GPU holds at once at full occupancy
+// (256 CUs x 8 blocks of four waves); beyond that the blocks loop over the
+// items.  Items past the window's valid frames launch no block of their own.
+#ifndef LSD_VERIFY_MAX_BLOCKS
+#define LSD_VERIFY_MAX_BLOCKS 2048
+#endif
+
 hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                          const PotDev& P, int fw, hipStream_t st) {
   if (fw > LSD_VERIFY_FW_MAX) fw = LSD_VERIFY_FW_MAX;
   fw = fw >= 8 ? 8 : (fw >= 4 ? 4 : (fw == 2 ? 2 : 1));
-  const dim3 grid(S.n_tiles, (W.K + fw - 1) / fw);
+  const long all_items = (long)S.n_tiles * ((W.K + fw - 1) / fw);
+  const long cap = LSD_VERIFY_MAX_BLOCKS > S.n_tiles ? LSD_VERIFY_MAX_BLOCKS : S.n_tiles;
+  const dim3 grid((unsigned)(all_items < cap ? all_items : cap));
   if (fw == 8) {
     hipLaunchKernelGGL(k_verify<8>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P);
   } else if (fw == 4) {
