@@ -347,7 +347,10 @@ typedef struct {
 LSD_API lsd_status lsd_get_window_layout(const lsd_system *sys, lsd_window_layout *out);
 
 /* Synchronises `stream` and returns the device status word: bit 0 target
- * list overflow, bit 1 draft list overflow, bit 2 cell overflow. */
+ * list overflow, bit 1 draft list overflow, bit 2 cell overflow, bit 3 more
+ * in-cutoff pairs of the message-passing target than its buffers hold (a
+ * quarter of rows x list width), bit 4 inconsistent pair lists of that
+ * target.  Any set bit means the results since it was set are not valid. */
 LSD_API lsd_status lsd_get_status(lsd_system *sys, int32_t *flags, lsd_stream stream);
 
 /* Final step count of the run (Alg. 2 stops when that many steps are

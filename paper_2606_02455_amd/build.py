@@ -43,8 +43,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for p, c in procs:
         if p.wait() != 0:
             raise RuntimeError("compile failed: " + " ".join(c))
-    link = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", OUT + ".tmp"] + objs + [
-        "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+    link = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", OUT + ".tmp"] + objs
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)

@@ -63,7 +63,7 @@ struct Layout {
   // window
   size_t qmid, p, fd, ft, invalid, nvalid, partial, commit_frame, reflected, coef, counters, status;
   size_t ec = 0, ec_prev = 0, ec_samples = 0;  // error-correction caches (0: off)
-  size_t mpnn = 0, mpnn_bytes = 0, blas = 0, epart = 0;
+  size_t mpnn = 0, mpnn_bytes = 0, epart = 0;
   size_t net_v = 0;  // learned draft: edge coefficients [N][LSD_NET_MAX_BASIS]
   bool has_mpnn = false;
   int mt = 0, md = 0, n_cells = 0, n_tiles = 0, cell_cap = 0;
@@ -89,7 +89,6 @@ double pot_reach(const lsd_potential& P) {
              : 0.0;
 }
 
-constexpr size_t kBlasWorkspace = 64ull << 20;
 
 lsd_status check_potential(const lsd_potential& P, const char* what) {
   if (P.kind == LSD_POT_LJ) {
@@ -280,7 +279,6 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   if (L->has_mpnn) {
     L->mpnn_bytes = mpnn_buffer_bytes(c->k_max, N, L->mt);
     L->mpnn = bump(&off, L->mpnn_bytes);
-    L->blas = bump(&off, kBlasWorkspace);
     L->epart = bump(&off, K * T * 8);
   }
   L->total = (off + kAlign - 1) / kAlign * kAlign;
@@ -421,50 +419,76 @@ void destroy_graphs(lsd_system* s) {
 
 enum Part { PART_FULL = 0, PART_PRE = 1, PART_POST = 2, PART_MID = 3 };
 
+// Network-target forces of frame k of a plain window into the draft force
+// slot (k_draft then steps with them).
+lsd_status enqueue_plain_mpnn(lsd_system* s, int k, hipStream_t st) {
+  char err[256];
+  if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, s->T, k, 1, nullptr, s->W.fd,
+                 ws<double>(s, s->lay.epart), st, err, sizeof(err)))
+    return fail(LSD_ERR_HIP, "network forces: %s", err);
+  return LSD_OK;
+}
+
+// The verification launch(es) of a drafted window: the pair kernel with its
+// fused transport-map epilogue, or the batched network evaluation of the
+// window's valid frames followed by the transport-map sums.
+lsd_status enqueue_verify(lsd_system* s, int K, hipStream_t st) {
+  if (s->has_mpnn) {
+    char err[256];
+    if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, s->T, 0, K, s->W.nvalid, s->W.ft,
+                   ws<double>(s, s->lay.epart), st, err, sizeof(err)))
+      return fail(LSD_ERR_HIP, "network forces: %s", err);
+    HIP_TRY(launch_transport(s->S, s->W, s->T, ws<double>(s, s->lay.epart), st));
+  } else {
+    HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, verify_fw(s, K), st));
+  }
+  return LSD_OK;
+}
+
 // Enqueues the kernels of one window part of lsd_run_windows on `st` (no
 // state checks).  A part begins at the list kernels: the window's start
 // (k_window_start) is fused into the previous window's commit, and the first
 // window of a call is started by a separate launch before the replays.
-hipError_t enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
+lsd_status enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
   const bool plain = s->cfg.mode == LSD_MODE_PLAIN;
-  hipError_t e = hipSuccess;
   s->W.K = K;
   if (part == PART_MID) {
-    e = enqueue_part(s, K, PART_POST, st);
-    return e == hipSuccess ? enqueue_part(s, K, PART_PRE, st) : e;
+    LSD_TRY(enqueue_part(s, K, PART_POST, st));
+    return enqueue_part(s, K, PART_PRE, st);
   }
   if (part == PART_FULL || part == PART_PRE) {
-    e = launch_build_lists(s->S, s->Lst, s->W, false, st);
-    for (int k = 0; k < K && e == hipSuccess; ++k) {
-      if (!plain && s->Pd.kind == LSD_POT_NET) e = launch_net_nodes(s->S, s->Lst, s->W, s->Pd, k, st);
-      if (e == hipSuccess)
-        e = launch_draft(s->S, s->Lst, s->W, s->T, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st);
+    HIP_TRY(launch_build_lists(s->S, s->Lst, s->W, false, st));
+    for (int k = 0; k < K; ++k) {
+      if (plain && s->has_mpnn) {
+        LSD_TRY(enqueue_plain_mpnn(s, k, st));
+        HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, s->Pt, k, 1, st, 1));
+        continue;
+      }
+      if (!plain && s->Pd.kind == LSD_POT_NET)
+        HIP_TRY(launch_net_nodes(s->S, s->Lst, s->W, s->Pd, k, st));
+      HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st));
     }
   }
-  if (s->has_mpnn) return hipErrorNotSupported;  // never captured
-  if (part == PART_FULL && !plain && e == hipSuccess) {
-    const int fw = verify_fw(s, K);
-    e = launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st);
+  if (part == PART_FULL && !plain) LSD_TRY(enqueue_verify(s, K, st));
+  if (part == PART_FULL || part == PART_POST) {
+    HIP_TRY(launch_decide(s->S, s->Lst, s->W, s->T, s->O, plain ? 1 : 0, st));
+    HIP_TRY(launch_commit_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, s->buf.img, plain ? 1 : 0,
+                                st));
   }
-  if ((part == PART_FULL || part == PART_POST) && e == hipSuccess) {
-    e = launch_decide(s->S, s->Lst, s->W, s->T, s->O, plain ? 1 : 0, st);
-    if (e == hipSuccess)
-      e = launch_commit_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, s->buf.img, plain ? 1 : 0,
-                              st);
-  }
-  return e;
+  return LSD_OK;
 }
 
 lsd_status capture(lsd_system* s, int K, int part, hipGraphExec_t* out) {
   if (!s->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
   hipGraph_t g = nullptr;
   HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
-  hipError_t e = enqueue_part(s, K, part, s->cap_stream);
+  const lsd_status e = enqueue_part(s, K, part, s->cap_stream);
+  const std::string enqueue_err = e != LSD_OK ? g_err : std::string();
   hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
-  if (e != hipSuccess || e2 != hipSuccess) {
+  if (e != LSD_OK || e2 != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
-    return fail(LSD_ERR_HIP, "window capture: %s",
-                hipGetErrorString(e != hipSuccess ? e : e2));
+    if (e != LSD_OK) return fail(e, "window capture: %s", enqueue_err.c_str());
+    return fail(LSD_ERR_HIP, "window capture: %s", hipGetErrorString(e2));
   }
   hipError_t e3 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -666,18 +690,15 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   if (L.net_v) s->Pd.v = ws<float>(s, L.net_v);
   if (L.has_mpnn) {
     s->has_mpnn = true;
-    s->use_graphs = false;  // the network pass is issued eagerly
     MpnnCtx& M = s->mp;
     mpnn_bind(M, ws<char>(s, L.mpnn), cfg->k_max, N, L.mt, cfg->target.weights,
               cfg->target.n_model_species);
     M.rc = (float)cfg->target.cutoff;
     M.scale = (float)cfg->target.energy_scale;
-    if (rocblas_create_handle(&M.blas) != rocblas_status_success ||
-        rocblas_set_atomics_mode(M.blas, rocblas_atomics_not_allowed) != rocblas_status_success ||
-        rocblas_set_workspace(M.blas, ws<char>(s, L.blas), kBlasWorkspace) != rocblas_status_success) {
-      if (M.blas) rocblas_destroy_handle(M.blas);
+    char err[256];
+    if (!mpnn_prepare(M, st, err, sizeof(err))) {
       delete s;
-      return fail(LSD_ERR_HIP, "rocBLAS handle setup failed");
+      return fail(LSD_ERR_HIP, "network weight fragments: %s", err);
     }
   }
   if (cfg->integrator == LSD_INTEGRATOR_OBABO) {
@@ -687,8 +708,8 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
     bool given = false;
     if (eo == hipSuccess && s->has_mpnn) {
       char err[256];
-      if (!mpnn_eval(s->mp, S, s->Lst, s->W, s->T, 0, 1, s->W.ft, ws<double>(s, L.epart), st, err,
-                     sizeof(err))) {
+      if (!mpnn_eval(s->mp, S, s->Lst, s->W, s->T, 0, 1, nullptr, s->W.ft, ws<double>(s, L.epart),
+                     st, err, sizeof(err))) {
         lsd_destroy(s);
         return fail(LSD_ERR_HIP, "network forces at the initial state: %s", err);
       }
@@ -720,10 +741,7 @@ lsd_status lsd_draft_steps(lsd_system* s, int32_t K, lsd_stream stream) {
   for (int k = 0; k < K; ++k) {
     if (plain && s->has_mpnn) {
       // plain stepping with the network: its forces on frame k, then the step
-      char err[256];
-      if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, s->T, k, 1, s->W.fd,
-                     ws<double>(s, s->lay.epart), st, err, sizeof(err)))
-        return fail(LSD_ERR_HIP, "network forces: %s", err);
+      LSD_TRY(enqueue_plain_mpnn(s, k, st));
       HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, s->Pt, k, 1, st, 1));
     } else {
       if (!plain && s->Pd.kind == LSD_POT_NET)
@@ -764,17 +782,7 @@ lsd_status lsd_verify_window(lsd_system* s, lsd_stream stream) {
       slot = (R.head + R.used) % kTimingRing;
       HIP_TRY(hipEventRecord(R.start[slot], st));
     }
-    // frames per wave of the verification kernel: 4 for long windows
-    const int fw = verify_fw(s, s->W.K);
-    if (s->has_mpnn) {
-      char err[256];
-      if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, s->T, 0, s->W.K, s->W.ft,
-                     ws<double>(s, s->lay.epart), st, err, sizeof(err)))
-        return fail(LSD_ERR_HIP, "network forces: %s", err);
-      HIP_TRY(launch_transport(s->S, s->W, s->T, ws<double>(s, s->lay.epart), st));
-    } else {
-      HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st));
-    }
+    LSD_TRY(enqueue_verify(s, s->W.K, st));
     if (timed) {
       HIP_TRY(hipEventRecord(R.stop[slot], st));
       R.used += 1;
@@ -843,8 +851,7 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
     if (R.used == kTimingRing) LSD_TRY(timing_drain_one(s));
     const int slot = (R.head + R.used) % kTimingRing;
     HIP_TRY(hipEventRecord(R.start[slot], st));
-    const int fw = verify_fw(s, K);
-    HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st));
+    LSD_TRY(enqueue_verify(s, K, st));
     HIP_TRY(hipEventRecord(R.stop[slot], st));
     R.used += 1;
     open = true;
@@ -1179,7 +1186,6 @@ lsd_status lsd_destroy(lsd_system* s) {
   if (!s) return LSD_OK;
   destroy_graphs(s);
   if (s->graphs_done) (void)hipEventDestroy(s->graphs_done);
-  if (s->mp.blas) rocblas_destroy_handle(s->mp.blas);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->ring.created) {
     for (int i = 0; i < kTimingRing; ++i) {

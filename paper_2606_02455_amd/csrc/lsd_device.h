@@ -33,6 +33,8 @@
 #define LSD_STATUS_NBR_TARGET 1
 #define LSD_STATUS_NBR_DRAFT 2
 #define LSD_STATUS_CELL 4
+#define LSD_STATUS_PAIRS 8    // network target: more pairs than its buffers hold
+#define LSD_STATUS_EDGES 16   // network target: the two directions of a pair differ
 
 struct PotDev {
   int kind;

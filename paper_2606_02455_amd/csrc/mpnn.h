@@ -2,13 +2,15 @@
 //
 // Rows are (frame, atom) pairs, row = f_local * N + i; edges are the list
 // entries of a row inside the cutoff, compacted row by row in list order
-// (capacity: rows x list width).  The dense
-// contractions (the per-slot filter MLP 128 -> 128 of every layer, and the
-// per-row node MLPs) run as FP32 GEMMs; every gather, activation, reduction
-// and the reverse pass to the forces are kernels in mpnn.hip.
+// (capacity: rows x list width).  The dense contractions (the per-pair filter
+// MLP 128 -> 128 of every layer and its r-derivative, and the per-row node
+// MLPs) run on the matrix cores as bfloat16 hi/lo splits with binary32
+// accumulation; every gather, activation, reduction and the reverse pass to
+// the forces are kernels in mpnn.hip.  The counts of edges and pairs stay on
+// the device: an evaluation has no host synchronisation and can be captured
+// in a graph.
 #pragma once
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include "lsd_device.h"
 
@@ -18,18 +20,18 @@
 #define MP_RH 64
 #define MP_HT (MP_H * MP_T)  // filter channels of all layers side by side
 
-struct MpnnWeights {
-  const float* W_emb;
-  const float *A1[MP_T], *a1[MP_T], *A2[MP_T], *a2[MP_T], *B[MP_T], *C1[MP_T], *c1[MP_T];
-  const float *C2[MP_T], *c2[MP_T];
-  const float *W1, *b1, *w2, *b2;
-  long layer_stride;  // floats between consecutive layers' blocks
+
+// bfloat16 hi/lo fragments of a weight matrix, laid out for the operands of
+// v_mfma_f32_16x16x32_bf16 (8 values per lane, 16 bytes): element
+// [tile][k-step][lane] of hi and of lo
+struct MpnnFrag {
+  const uint4* hi;
+  const uint4* lo;
 };
 
 struct MpnnBuffers {
-  // per unordered pair (capacity slots / 4 + 1)
-  float *S, *DS, *Z, *DZ;  // [pairs][384]
-  float* fcd;              // [pairs][2]  f_c, f_c'
+  // per unordered pair (capacity: slots / 4 + 1)
+  float *Wf, *Vf;          // [pairs][T][128]  filter W and dW/dr of every layer
   float* uv;               // [pairs][4]  unit vector from the owner row, distance
   float* gr;               // [pairs]     dE/dr summed over both directions and layers
   int *ua, *ub;            // [pairs]     owner row, neighbour row
@@ -40,13 +42,30 @@ struct MpnnBuffers {
   int* ecode;              // [slots]     image code of the edge
   int* uid;                // [slots]     pair of the edge: p (owner) or ~p (reverse)
   int* poff;               // [rows+1]    first pair owned by every row
-  int* counts;             // [4]         directed edges, pairs, error flag
+  int* counts;             // [4]         directed edges, pairs, error flags
   float* H;                // [T+1][rows][128]
   float* X;                // [T][rows][128]
   float* U;                // [T][rows][128]
   float *Mm, *Sn;          // [rows][128]
   float *Y, *gY;           // [rows][64]
   float *gH, *gP, *gS, *gM, *gX;  // [rows][128]
+  // weight fragments (written once by mpnn_prepare)
+  uint4* frag;             // all fragment arrays below, contiguous
+};
+
+struct MpnnWeights {
+  const float* W_emb;
+  const float *A1[MP_T], *a1[MP_T], *A2[MP_T], *a2[MP_T], *B[MP_T], *C1[MP_T], *c1[MP_T];
+  const float *C2[MP_T], *c2[MP_T];
+  const float *W1, *b1, *w2, *b2;
+  long layer_stride;  // floats between consecutive layers' blocks
+  // A2 of each layer as the first operand of the filter product (channels x
+  // inputs); the node matrices as the second operand, forward (W^T) and
+  // reverse (W): out[row][n] = sum_k in[row][k] op[k][n]
+  MpnnFrag A2f[MP_T];
+  MpnnFrag Bf[MP_T], C1f[MP_T], C2f[MP_T];   // forward: B^T, C1^T, C2^T
+  MpnnFrag Bb[MP_T], C1b[MP_T], C2b[MP_T];   // reverse: B, C1, C2
+  MpnnFrag W1f, W1b;                          // W1^T (128 -> 64), W1 (64 -> 128)
 };
 
 struct MpnnCtx {
@@ -54,7 +73,7 @@ struct MpnnCtx {
   MpnnBuffers b;
   float rc, scale;
   int frames;  // frames per evaluation (buffer capacity)
-  rocblas_handle blas = nullptr;
+  long pair_cap;
 };
 
 // Bytes of the buffers for `frames` frames of N atoms with list width mt.
@@ -62,9 +81,17 @@ size_t mpnn_buffer_bytes(int frames, int n, int mt);
 // Carves the buffers out of `base` (256-byte aligned) and sets weight views.
 void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* weights,
                int n_model_species);
+// Writes the weight fragments (once, after mpnn_bind).
+bool mpnn_prepare(MpnnCtx& M, hipStream_t st, char* err, size_t errlen);
 // Energies (per frame and tile, binary64, into epart[(f0+f) * n_tiles + tile])
 // and forces (frame-major [f0+f][3][N] into Fout) of frames f0 .. f0+nf-1.
-// Returns false and a message in err on a HIP or rocBLAS failure.
+// Asynchronous on `st`, no host synchronisation; a pair count above the
+// capacity or inconsistent edge lists are latched in the status word
+// (LSD_STATUS_PAIRS, LSD_STATUS_EDGES).  Returns false and a message in err
+// on a launch failure.
+// Frames past the device bound nvalid (a window's valid frames; nullptr: all
+// nf) and frames flagged invalid are not evaluated (no edges; their forces
+// and energies are left as they were).
 bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
-               int f0, int nf, float* Fout, double* epart, hipStream_t st, char* err,
-               size_t errlen);
+               int f0, int nf, const int* nvalid, float* Fout, double* epart, hipStream_t st,
+               char* err, size_t errlen);
