@@ -127,6 +127,78 @@ def cpu_baseline(w, q, p, seconds, ec_mode):
                 plain_steps_per_s=n_plain / t_plain)
 
 
+def cpu_baseline_mpnn(w, state, target, draft, ec_mode, seconds):
+    """The FP64 oracle as it stands on a network-target configuration: LSD
+    windows of K frames (message-passing target, the same draft with the
+    same parameters, the same error-correction setting) from the benchmark's
+    state, replica after replica, until `seconds` of host time are spent (at
+    least one window); then plain target steps for a quarter of that."""
+    import numpy as np
+
+    import oracle
+    from oracle.mpnn import MPNN
+    from oracle.net import NetDraft
+    from oracle.pair import PairDraft
+    net = MPNN(np.asarray(target["weights"], np.float64), 3, rc=target["rc"],
+               scale=target["scale"])
+    if draft["kind"] == "net":
+        dparams = draft["weights"].detach().cpu().numpy().astype(np.float64)
+        dmodel = NetDraft(3, draft["n_basis"], draft["rc"], dparams)
+    else:
+        dmodel = PairDraft(3, draft["n_basis"], draft["rc"], w=np.asarray(draft["weights"]))
+    K = w.K
+    off = np.asarray(w.atom_offsets)
+    q_all = np.asarray(state["q"], np.float64).reshape(-1, 3)
+    p_all = np.asarray(state["p"], np.float64).reshape(-1, 3)
+    steps = np.asarray(state["step"]).reshape(-1)
+    reps = []
+    for r in range(w.n_replicas):
+        a, b = int(off[r]), int(off[r + 1])
+        sp = w.species[a:b]
+        so = oracle.System(b - a, float(w.box[r]), w.masses()[a:b], w.dt, w.gamma, w.kT,
+                           w.force_unit)
+        T = oracle.Potential.mpnn(net, sp)
+        D = (oracle.Potential.net_draft(dmodel, sp) if draft["kind"] == "net"
+             else oracle.Potential.pair_draft(dmodel, sp))
+        n = b - a
+        reps.append(dict(so=so, T=T, D=D, q=q_all[a:b].copy(), p=p_all[a:b].copy(),
+                         img=np.zeros((n, 3), np.int32), step=int(steps[r]),
+                         ec=np.zeros((n, 3)) if ec_mode >= 1 else None,
+                         ec_prev=np.zeros((n, 3)) if ec_mode == 2 else None,
+                         samples=np.zeros(1, np.int32), n=n))
+    committed = windows = 0
+    t0 = time.perf_counter()
+    r = 0
+    while windows == 0 or time.perf_counter() - t0 < seconds:
+        R = reps[r % len(reps)]
+        xi = np.stack([oracle.normals(w.seed, r % len(reps), R["step"] + k + 1, R["n"])
+                       for k in range(K)])
+        u = np.array([oracle.uniform(w.seed, r % len(reps), R["step"] + k + 1) for k in range(K)])
+        res = oracle.lsd_window(R["so"], R["T"], R["D"], R["q"], R["p"], R["img"], xi, u,
+                                ec=R["ec"], ec_prev=R["ec_prev"], samples=R["samples"])
+        committed += res["n_committed"]
+        R["step"] += res["n_committed"]
+        windows += 1
+        r += 1
+    t_lsd = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    n_plain = 0
+    r = 0
+    while n_plain == 0 or time.perf_counter() - t1 < max(2.0, seconds / 4):
+        R = reps[r % len(reps)]
+        oracle.plain_run(R["so"], R["T"], R["q"], R["p"], R["img"], w.seed, r % len(reps),
+                         R["step"] + n_plain, 1)
+        n_plain += 1
+        r += 1
+    t_plain = time.perf_counter() - t1
+    return dict(value=committed / t_lsd, unit="steps/s", cores=oracle.num_threads(), kind="oracle",
+                sample=(f"{windows} LSD windows (K={K}) over {min(windows, len(reps))} of "
+                        f"{len(reps)} system(s) of the {w.n_atoms}-atom liquid from the benchmark "
+                        f"state (FP64 message-passing target, {draft['kind']} draft), "
+                        f"{committed} committed steps in {t_lsd:.1f} s"),
+                plain_steps_per_s=n_plain / t_plain)
+
+
 def mpnn_flops_per_frame(undirected_edges, n_atoms, H=128, R=16, T=3, RH=64):
     """Algorithmic FLOPs of one target evaluation (energy and forces) of the
     message-passing network: per undirected in-cutoff edge and layer the
@@ -271,6 +343,12 @@ def run_c3(args, lsd, W, torch):
     peak = 157.3
     value, plain_rate = committed / t_lsd, plain_steps / t_plain
     dt_fs = w.dt
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host ...")
+        cpu = cpu_baseline_mpnn(w, g.state(), target, draft, EC_MODES[args.ec], args.cpu_seconds)
+        log(f"oracle: {cpu['value']:.4f} LSD steps/s, {cpu['plain_steps_per_s']:.4f} plain "
+            f"steps/s on {cpu['cores']} threads")
     return {
         "metric": "target-distributed MD steps/s (LSD vs plain Langevin, 1 GPU); acceptance rate",
         "value": round(value, 3), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
@@ -305,7 +383,7 @@ def run_c3(args, lsd, W, torch):
                          avg_us=round(avg_s * 1e6, 2), algorithmic_flops=int(flops),
                          frames_per_launch=round(frames_per_launch, 3),
                          in_cutoff_pairs=pairs),
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
 
 

@@ -22,7 +22,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-POT_NONE, POT_LJ, POT_HARMONIC = 0, 1, 2
+POT_NONE, POT_LJ, POT_HARMONIC, POT_EXT = 0, 1, 2, 3
 
 
 def lib():
@@ -46,7 +46,18 @@ class _Sys(C.Structure):
 class _Pot(C.Structure):
     _fields_ = [("kind", C.c_int), ("rc", C.c_double), ("eps", C.c_double),
                 ("sig", C.c_double), ("k", C.c_double),
-                ("qref", C.POINTER(C.c_double)), ("offset", C.POINTER(C.c_double))]
+                ("qref", C.POINTER(C.c_double)), ("offset", C.POINTER(C.c_double)),
+                ("ext", C.c_void_p), ("ext_ctx", C.c_void_p)]
+
+
+# contexts of the force fields of the other oracle files (kind POT_EXT)
+class _MpnnCtx(C.Structure):
+    _fields_ = [("m", C.c_void_p), ("species", C.c_void_p)]
+
+
+class _DraftCtx(C.Structure):
+    _fields_ = [("S", C.c_int), ("B", C.c_int), ("rc", C.c_double), ("w", C.c_void_p),
+                ("species", C.c_void_p)]
 
 
 class _WinOut(C.Structure):
@@ -169,7 +180,40 @@ class Potential:
         return Potential(POT_HARMONIC, k=k, qref=qref, offset=offset)
 
     def with_offset(self, offset):
+        if self.kind == POT_EXT:
+            raise ValueError("offsets of external force fields are not supported")
         return Potential(self.kind, self.rc, self.eps, self.sig, self.k, self.qref, offset)
+
+    @staticmethod
+    def _external(fn_name, ctx, keep):
+        pot = Potential(POT_EXT)
+        pot._keep = keep + [ctx]
+        pot._c.ext = C.cast(getattr(lib(), fn_name), C.c_void_p)
+        pot._c.ext_ctx = C.cast(C.pointer(ctx), C.c_void_p)
+        return pot
+
+    @staticmethod
+    def mpnn(net, species):
+        """The message-passing network (oracle.mpnn.MPNN) as a force field of
+        the integrator and window functions, for atoms of the given species."""
+        sp = np.ascontiguousarray(species, dtype=np.int32)
+        ctx = _MpnnCtx(C.cast(C.pointer(net._c), C.c_void_p), sp.ctypes.data)
+        return Potential._external("ora_mpnn_ext", ctx, [net, sp])
+
+    @staticmethod
+    def net_draft(draft, species):
+        """The learned draft (oracle.net.NetDraft) as a force field."""
+        sp = np.ascontiguousarray(species, dtype=np.int32)
+        ctx = _DraftCtx(draft.S, draft.B, draft.rc, draft.params.ctypes.data, sp.ctypes.data)
+        return Potential._external("ora_net_ext", ctx, [draft, sp])
+
+    @staticmethod
+    def pair_draft(draft, species):
+        """The pair draft (oracle.pair.PairDraft, weights fitted) as a force field."""
+        sp = np.ascontiguousarray(species, dtype=np.int32)
+        w = np.ascontiguousarray(draft.w, dtype=np.float64)
+        ctx = _DraftCtx(draft.S, draft.B, draft.rc, w.ctypes.data, sp.ctypes.data)
+        return Potential._external("ora_pair_ext", ctx, [draft, sp, w])
 
 
 # ----------------------------------------------------------------------------

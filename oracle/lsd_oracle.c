@@ -129,7 +129,11 @@ typedef struct {
   double dt, gamma, kT, fu;
 } ora_sys;
 
-enum { ORA_POT_NONE = 0, ORA_POT_LJ = 1, ORA_POT_HARMONIC = 2 };
+enum { ORA_POT_NONE = 0, ORA_POT_LJ = 1, ORA_POT_HARMONIC = 2, ORA_POT_EXT = 3 };
+
+/* A force field defined in another oracle file (the message-passing target,
+ * the pair and learned drafts): energy returned, forces written to F[n][3]. */
+typedef double (*ora_ext_fn)(const void *ctx, int n, const double *x, double L, double *F);
 
 typedef struct {
   int kind;
@@ -138,6 +142,8 @@ typedef struct {
   double k;              /* harmonic tether stiffness */
   const double *qref;    /* tether anchors [n][3] */
   const double *offset;  /* optional additive force field b [n][3] (test drafts) */
+  ora_ext_fn ext;        /* ORA_POT_EXT: the force field and its context */
+  const void *ext_ctx;
 } ora_pot;
 
 /* wrap one coordinate into [0, L); returns the image shift applied */
@@ -351,6 +357,12 @@ static double tether_atom(int i, const double *x, double L, const ora_pot *P,
  * sums are independent of the thread count. */
 double ora_energy_forces(const ora_pot *P, int n, const double *x, double L,
                          double *F, int parallel) {
+  if (P->kind == ORA_POT_EXT) {
+    double E = P->ext(P->ext_ctx, n, x, L, F);
+    if (P->offset)
+      for (int c = 0; c < 3 * n; ++c) F[c] += P->offset[c];
+    return E;
+  }
   cells_t cells, *cp = NULL;
   if (P->kind == ORA_POT_LJ && cells_build(&cells, n, x, L, P->rc)) cp = &cells;
   double *e_atom = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));

@@ -311,3 +311,16 @@ double ora_mpnn_energy_forces(const ora_mpnn *M, int n, const int32_t *species, 
   free(h); free(xb); free(u); free(m); free(Wc); free(dWc);
   return E;
 }
+
+/* The network as a force field of the integrator and window code
+ * (lsd_oracle.c, kind ORA_POT_EXT): context = the network and the species of
+ * the atoms. */
+typedef struct {
+  const ora_mpnn *m;
+  const int32_t *species;
+} ora_mpnn_ctx;
+
+double ora_mpnn_ext(const void *ctx, int n, const double *x, double L, double *F) {
+  const ora_mpnn_ctx *c = (const ora_mpnn_ctx *)ctx;
+  return ora_mpnn_energy_forces(c->m, n, c->species, x, L, F);
+}

@@ -236,3 +236,19 @@ void ora_net_adam(int P, double *params, double *m, double *v, const double *g, 
     params[k] -= lr * mh / (sqrt(vh) + eps);
   }
 }
+
+/* The learned draft as a force field of the integrator and window code
+ * (lsd_oracle.c, kind ORA_POT_EXT).  A direct-force draft has no energy; 0
+ * is returned. */
+typedef struct {
+  int S, B;
+  double rc;
+  const double *params;
+  const int32_t *species;
+} ora_net_ctx;
+
+double ora_net_ext(const void *ctx, int n, const double *x, double L, double *F) {
+  const ora_net_ctx *c = (const ora_net_ctx *)ctx;
+  ora_net_forward(n, x, L, c->species, c->S, c->B, c->rc, c->params, NULL, NULL, NULL, F);
+  return 0.0;
+}

@@ -99,3 +99,18 @@ void ora_pair_design(int n, const double *x, double L, const int32_t *sp, int S,
   }
   free(rec);
 }
+
+/* The pair draft as a force field of the integrator and window code
+ * (lsd_oracle.c, kind ORA_POT_EXT); its energy is never needed (0). */
+typedef struct {
+  int S, B;
+  double rc;
+  const double *w;
+  const int32_t *species;
+} ora_pair_ctx;
+
+double ora_pair_ext(const void *ctx, int n, const double *x, double L, double *F) {
+  const ora_pair_ctx *c = (const ora_pair_ctx *)ctx;
+  ora_pair_forces(n, x, L, c->species, c->S, c->B, c->rc, c->w, F);
+  return 0.0;
+}
