@@ -26,6 +26,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 EC_MODES = {"off": 0, "on": 1, "linear": 2}
 COPY_BYTES = 256 << 20  # calibration copy: 256 MiB read + 256 MiB written
+ACCEPT_SAMPLE_WINDOWS = 400  # untimed windows behind the reported acceptance (c1, c2)
+# binary32 vector peak without packed instructions: 256 CUs x 2.4 GHz x 64
+# lanes x 2 (a fused multiply-add counts two)
+VALU_PEAK_TFLOPS = 256 * 2.4e9 * 64 * 2 / 1e12
+LJ_PAIR_FLOPS = 31  # per directed in-cutoff pair and frame (separation, r^2, r^-6 terms, force, energy)
 VERIFY_SOURCES = ["paper_2606_02455_amd/csrc/lsd_kernels.hip",
                   "paper_2606_02455_amd/csrc/lsd_device.h"]
 
@@ -63,6 +68,30 @@ def read_traffic(config_name, kernel, skin):
         return float(sections[kernel]["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def read_profile_avg_us(config_name, kernel, skin):
+    """Average duration of the kernel in the committed rocprofv3 kernel trace
+    of this configuration, if that trace was taken on the current kernel
+    source and list skin."""
+    path = os.path.join(ROOT, "profiles", f"k_verify_{config_name}_kernel_trace.txt")
+    if not os.path.exists(path):
+        return None
+    head, avg = {}, None
+    for line in open(path):
+        t = line.strip()
+        if t.startswith("#") and "=" in t:
+            k, v = t[1:].split("=", 1)
+            head[k.strip()] = v.strip()
+        elif t.startswith(kernel + " ") or t.startswith(f"void {kernel}("):
+            parts = t.replace(kernel, "", 1).split()
+            try:
+                avg = float(parts[1])
+            except (IndexError, ValueError):
+                pass
+    if head.get("source_sha") != source_sha() or head.get("lsd_skin") != repr(float(skin)):
+        return None
+    return avg
 
 
 def in_cutoff_pairs(sysg, rc):
@@ -234,29 +263,40 @@ def run_c3(args, lsd, W, torch):
     plain.run_windows(eq_windows, K)
     torch.cuda.synchronize()
     log(f"equilibrated {eq_windows * K} plain steps in {time.perf_counter() - t0:.1f} s")
+    # the drafts are trained on target frames of this system, or of the
+    # 1536-atom liquid of the same recipe (a local model transfers)
+    trainer, wt = plain, w
+    if args.draft_source != args.config:
+        wt = W.config(args.draft_source)
+        tskin = W.BENCH_SKINS.get(args.draft_source, (wt.skin, wt.skin))[1]
+        trainer = lsd.LSDSystem(wt, mode="plain", target=target, skin=tskin)
+        trainer.run_windows(max(1, args.equilibrate // wt.K), wt.K)
+        torch.cuda.synchronize()
+        log(f"drafts trained on {wt.name} ({wt.n_atoms} atoms)")
+    Kt = wt.K
     # force matching on frames of the plain target trajectory
     P = lsd.pair_params(3, nb)
     gram = torch.zeros((P + 1, P + 1), dtype=torch.float64, device="cuda")
     scratch = None
-    fit_windows = max(1, (args.fit_frames + K - 1) // K)
-    committed0 = int(plain.counters()[:, 1].sum())
+    fit_windows = max(1, (args.fit_frames + Kt - 1) // Kt)
+    committed0 = int(trainer.counters()[:, 1].sum())
     t0 = time.perf_counter()
     for _ in range(fit_windows):
-        plain.draft_steps(K)
+        trainer.draft_steps(Kt)
         # differences of consecutive frames: the draft's response to the
         # motion, which the error correction does not remove
-        scratch = plain.fit_pair_accumulate(nb, rc_d, gram, scratch=scratch, differences=True)
-        plain.accept_rollback()
+        scratch = trainer.fit_pair_accumulate(nb, rc_d, gram, scratch=scratch, differences=True)
+        trainer.accept_rollback()
     torch.cuda.synchronize()
     t_fit = time.perf_counter() - t0
     # frames actually stepped (a window ends early once an atom leaves the
     # skin), as whole-system frames
-    fit_frames = (int(plain.counters()[:, 1].sum()) - committed0) // w.n_replicas
+    fit_frames = (int(trainer.counters()[:, 1].sum()) - committed0) // wt.n_replicas
     G = gram.cpu().numpy()
     wts = lsd.fit_pair_solve(G, ridge=1e-8)
     log(f"fitted the pair draft on {fit_frames} target frames in {t_fit:.1f} s")
-    if plain.status():
-        raise RuntimeError(f"device status {plain.status()} during plain stepping")
+    if trainer.status():
+        raise RuntimeError(f"device status {trainer.status()} during plain stepping")
     draft = dict(kind="pair", rc=rc_d, weights=wts, n_basis=nb, n_model_species=3)
     train = None
     if args.draft == "net":
@@ -272,13 +312,13 @@ def run_c3(args, lsd, W, torch):
         m1 = torch.zeros(Pn, dtype=torch.float64, device="cuda")
         m2 = torch.zeros(Pn, dtype=torch.float64, device="cuda")
         scratch_t, mse = None, []
-        committed0 = int(plain.counters()[:, 1].sum())
+        committed0 = int(trainer.counters()[:, 1].sum())
         t0 = time.perf_counter()
         n_train = args.net_train_windows
         for step in range(1, n_train + 1):
-            plain.draft_steps(K)
-            scratch_t = plain.net_train_accumulate(net, grad, scratch=scratch_t, differences=True)
-            plain.accept_rollback()
+            trainer.draft_steps(Kt)
+            scratch_t = trainer.net_train_accumulate(net, grad, scratch=scratch_t, differences=True)
+            trainer.accept_rollback()
             if step == 1 or step == n_train:
                 torch.cuda.synchronize()
                 mse.append(grad[Pn].item() / (3.0 * max(grad[Pn + 1].item(), 1.0)))
@@ -286,41 +326,66 @@ def run_c3(args, lsd, W, torch):
             lsd.net_adam_step(torch, pt, m1, m2, grad, lr, step)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
-        train_frames = (int(plain.counters()[:, 1].sum()) - committed0) // w.n_replicas
+        train_frames = (int(trainer.counters()[:, 1].sum()) - committed0) // wt.n_replicas
         log(f"trained the learned draft ({Pn} parameters) on {train_frames} target frames in "
             f"{t_train:.1f} s; force-change MSE {mse[0]:.3g} -> {mse[-1]:.3g} (eV/A)^2")
         train = dict(windows=n_train, frames=train_frames, seconds=round(t_train, 2),
-                     mse_first=mse[0], mse_last=mse[-1], parameters=Pn)
-        if args.net_precision == "fp8":
+                     mse_first=mse[0], mse_last=mse[-1], parameters=Pn, system=wt.name)
+        if args.net_precision == "fp8" or args.compare_precision:
             # static per-tensor activation scales: the largest |D| and |h| over
-            # 16 windows of target frames, with a 20% margin
+            # 16 windows of target frames of the measured system, with a 20%
+            # margin
             amax = np.zeros(2)
             for _ in range(16):
                 plain.draft_steps(K)
-                amax = np.maximum(amax, plain.net_activation_amax(net, scratch=scratch_t))
+                amax = np.maximum(amax, plain.net_activation_amax(net))
                 plain.accept_rollback()
             net["act_amax"] = tuple(1.2 * amax)
             train["fp8_act_amax"] = [float(a) for a in net["act_amax"]]
             log(f"FP8 activation scales from max |D| = {amax[0]:.4g}, max |h| = {amax[1]:.4g}")
         draft = net
-    g = lsd.LSDSystem(w, mode="lsd", target=target, draft=draft,
-                      error_correction=EC_MODES[args.ec], skin=lsd_skin)
-    for a, b in ((g.q, plain.q), (g.p, plain.p), (g.img, plain.img), (g.step, plain.step)):
-        a.copy_(b)
-    g.run_windows(args.warmup, K)
-    g.reset_counters()
-    g.set_verify_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g.run_windows(args.steps, K)
-    torch.cuda.synchronize()
-    t_lsd = time.perf_counter() - t0
+    start = [t.clone() for t in (plain.q, plain.p, plain.img, plain.step)]
+
+    def lsd_run(dr):
+        """Autotuned, warmed-up LSD windows from the benchmark state; the
+        timed windows with their verification timed by HIP events."""
+        g = lsd.LSDSystem(w, mode="lsd", target=target, draft=dr,
+                          error_correction=EC_MODES[args.ec], skin=lsd_skin)
+        for a, b in zip((g.q, g.p, g.img, g.step), start):
+            a.copy_(b)
+        shape, shape_us = g.autotune_verify(K, repeats=3)
+        g.verify_window()
+        g.accept_rollback()
+        if args.pipeline:
+            g.set_pipeline(args.pipeline)
+        g.run_windows(args.warmup, K)
+        g.reset_counters()
+        g.set_verify_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.run_windows(args.steps, K)
+        torch.cuda.synchronize()
+        return g, time.perf_counter() - t0, shape, shape_us
+
+    g, t_lsd, shape, shape_us = lsd_run(draft)
     ver_ms, ver_n = g.verify_timing()
     cn = g.counters()
     windows = int(cn[0, 0])
     committed, rejections, frames = (int(cn[:, c].sum()) for c in (1, 2, 3))
     log(f"LSD: {committed} steps in {t_lsd * 1e3:.1f} ms over {windows} windows; rejections "
-        f"{rejections}; verify {ver_ms / max(ver_n, 1) * 1e3:.1f} us/launch")
+        f"{rejections}; verify {ver_ms / max(ver_n, 1) * 1e3:.1f} us/launch; launch shape "
+        f"{lsd.LSDSystem.NET_SHAPES[shape]}")
+    other = None
+    if args.compare_precision and args.draft == "net":
+        prec = "bf16" if args.net_precision == "fp8" else "fp8"
+        g2, t2, _, _ = lsd_run(dict(draft, precision=prec))
+        c2 = g2.counters()
+        n2, r2 = int(c2[:, 1].sum()), int(c2[:, 2].sum())
+        other = dict(precision=prec, steps_per_s=round(n2 / t2, 3),
+                     acceptance=round(1.0 - r2 / max(n2, 1), 5),
+                     committed_per_window=round(n2 / max(int(c2[0, 0]), 1), 4))
+        log(f"LSD with the {prec} node pass: {n2} steps in {t2 * 1e3:.1f} ms, rejections {r2}")
+        g2.destroy()
     plain.run_windows(args.warmup, K)
     plain.reset_counters()
     torch.cuda.synchronize()
@@ -362,10 +427,10 @@ def run_c3(args, lsd, W, torch):
                          + (f"draft: learned one-layer direct-force network (hidden 32, rc {rc_d} A, "
                             f"{nb} radial functions, {args.net_precision} node pass) initialised "
                             f"from the pair draft and trained on {train['frames'] if train else 0} "
-                            f"target frames; " if args.draft == "net" else "")
+                            f"target frames of {wt.name}; " if args.draft == "net" else "")
                          + f"pair draft: pair forces (rc {rc_d} A, {nb} basis) force-matched "
-                         f"(frame-to-frame differences) on {fit_frames} target frames; "
-                         f"error correction {args.ec}"),
+                         f"(frame-to-frame differences) on {fit_frames} target frames of "
+                         f"{wt.name}; error correction {args.ec}"),
             "n_atoms": N, "K": K, "fit_frames": fit_frames,
             "draft": args.draft, "error_correction": args.ec,
             "skin": lsd_skin, "plain_skin": plain_skin},
@@ -377,9 +442,14 @@ def run_c3(args, lsd, W, torch):
         "ns_per_day_plain": round(plain_rate * dt_fs * 1e-6 * 86400.0, 4),
         "fit_seconds": round(t_fit, 2),
         "draft_training": train,
+        "net_precision": args.net_precision if args.draft == "net" else None,
+        "other_precision": other,
         "roofline": dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
                          frac=round(achieved / peak, 5), traffic=None,
                          kernel="message-passing target evaluation (all frames of a window)",
+                         launch_shape=dict(zip(("filter_blocks", "chain_rows"),
+                                               lsd.LSDSystem.NET_SHAPES[shape])),
+                         autotune_us={f"{a}x{b}": round(v, 1) for (a, b), v in shape_us.items()},
                          avg_us=round(avg_s * 1e6, 2), algorithmic_flops=int(flops),
                          frames_per_launch=round(frames_per_launch, 3),
                          in_cutoff_pairs=pairs),
@@ -406,6 +476,12 @@ def main():
                     help="c3/c4: Adam steps, one window of K target frames each "
                          "(default 2000 for c3, 500 for c4)")
     ap.add_argument("--net-lr", type=float, default=3e-3)
+    ap.add_argument("--draft-source", choices=["c3", "c4", "c5"], default=None,
+                    help="c3/c4/c5: system whose target frames train the drafts (default: c3 for "
+                         "c5, else the measured system)")
+    ap.add_argument("--compare-precision", action="store_true",
+                    help="c3/c4/c5: also time LSD with the other node-pass precision of the "
+                         "learned draft (bf16 vs fp8) and report both acceptances")
     ap.add_argument("--equilibrate", type=int, default=256, help="plain steps before timing")
     ap.add_argument("--skin", type=float, default=None,
                     help="list skin of the LSD run (default: the tuned one of the config)")
@@ -415,6 +491,9 @@ def main():
                     help="time every n-th verification launch with HIP events (c1, c2)")
     ap.add_argument("--verify-fw", choices=["auto", "1", "2", "4", "8"], default="auto",
                     help="frames per wave of the verification kernel (auto: autotune)")
+    ap.add_argument("--pipeline", type=int, default=0,
+                    help="pipelined LSD windows: verify every group of this many drafted frames on "
+                         "a second stream while drafting continues (0: synchronous windows)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ec", choices=["auto", "on", "off", "linear"], default="auto",
@@ -424,10 +503,12 @@ def main():
     args = ap.parse_args()
     if args.net_precision is None:
         args.net_precision = "fp8" if args.config == "c5" else "bf16"
-    if args.fit_frames is None:
-        args.fit_frames = 2000 if args.config in ("c4", "c5") else 20000
+    if args.draft_source is None:
+        args.draft_source = "c3" if args.config == "c5" else args.config
     if args.net_train_windows is None:
-        args.net_train_windows = {"c4": 500, "c5": 100}.get(args.config, 2000)
+        args.net_train_windows = 2000 if args.draft_source == "c3" else 500
+    if args.fit_frames is None:
+        args.fit_frames = 2000 if args.draft_source in ("c4", "c5") else 20000
     if args.ec == "auto":
         args.ec = "linear" if args.config in ("c3", "c4", "c5") else "on"
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -484,6 +565,8 @@ def main():
         log(f"verification: {chosen_fw} frames per wave (fixed)")
 
     # --- LSD
+    if args.pipeline:
+        lsds.set_pipeline(args.pipeline)
     lsds.run_windows(args.warmup, K)
     lsds.reset_counters()
     lsds.set_verify_timing(True, every=args.time_every)
@@ -499,6 +582,15 @@ def main():
     assert windows == args.steps
     log(f"LSD: {committed} steps in {t_lsd * 1e3:.1f} ms over {windows} windows; "
         f"rejections {rejections}; verify {ver_ms / max(ver_n, 1) * 1e3:.1f} us/launch")
+
+    # --- acceptance over a fixed sample of windows (untimed), so that the
+    # reported rate does not depend on --steps
+    lsds.reset_counters()
+    lsds.run_windows(ACCEPT_SAMPLE_WINDOWS, K)
+    an = lsds.counters()[0]
+    acc_committed, acc_rejections, acc_frames = int(an[1]), int(an[2]), int(an[3])
+    log(f"acceptance sample: {ACCEPT_SAMPLE_WINDOWS} windows, {acc_committed} steps, "
+        f"{acc_rejections} rejections")
 
     # --- plain target Langevin, same kernels, same number of windows
     plain.run_windows(args.warmup, K)
@@ -529,13 +621,24 @@ def main():
     alg_bytes = frames_per_launch * w.n_atoms * 60.0 + pairs * 4.0
     avg_s = ver_ms / max(ver_n, 1) * 1e-3
     achieved = alg_bytes / avg_s / 1e9
+    valu_flops = frames_per_launch * pairs * LJ_PAIR_FLOPS
+    prof_us = read_profile_avg_us(args.config, f"k_verify<{chosen_fw}>", lsd_skin)
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=read_traffic(args.config, f"k_verify<{chosen_fw}>", lsd_skin),
                     kernel=f"k_verify<{chosen_fw}>", avg_us=round(avg_s * 1e6, 3),
+                    timing=("HIP events around each timed launch on its stream: the kernel "
+                            "plus its dispatch and end-of-kernel latency"),
+                    profile_avg_us=prof_us,
+                    frac_at_profile_us=(round(alg_bytes / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+                                        if prof_us else None),
                     timed_launches=int(ver_n), timed_every=args.time_every,
                     autotune_us={str(k): round(v, 2) for k, v in fw_us.items()},
                     algorithmic_bytes=int(alg_bytes), frames_per_launch=round(frames_per_launch, 3),
-                    in_cutoff_pairs=pairs)
+                    in_cutoff_pairs=pairs,
+                    valu=dict(achieved=round(valu_flops / avg_s / 1e12, 3),
+                              peak=round(VALU_PEAK_TFLOPS, 2), unit="TFLOP/s",
+                              frac=round(valu_flops / avg_s / 1e12 / VALU_PEAK_TFLOPS, 4),
+                              flops_per_pair_frame=LJ_PAIR_FLOPS))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -568,7 +671,13 @@ def main():
             "n_atoms": w.n_atoms, "K": K, "skin": lsd_skin, "plain_skin": plain_skin,
             "error_correction": args.ec,
         },
-        "acceptance": round(1.0 - rejections / max(committed, 1), 5),
+        "acceptance": round(1.0 - acc_rejections / max(acc_committed, 1), 5),
+        "acceptance_sample": {"windows": ACCEPT_SAMPLE_WINDOWS, "committed": acc_committed,
+                              "rejections": acc_rejections,
+                              "K_eff": round(acc_frames / ACCEPT_SAMPLE_WINDOWS, 3)},
+        "acceptance_timed": round(1.0 - rejections / max(committed, 1), 5),
+        "K": K,
+        "K_eff": round(frames / max(windows, 1), 3),
         "committed_per_window": round(committed / windows, 4),
         "list_builds_per_window": round(builds / windows, 4),
         "plain_steps_per_s": round(plain_rate, 3),

@@ -291,22 +291,47 @@ LSD_API lsd_status lsd_accept_rollback(lsd_system *sys, int32_t *n_host,
 LSD_API lsd_status lsd_run_windows(lsd_system *sys, int32_t n_windows, int32_t K,
                            lsd_stream stream);
 
-/* Autotuner of the verification kernel (LSD mode, pair targets): drafts a
- * window of K frames from the committed state (as lsd_draft_steps; the state
- * is left DRAFTED, so the caller continues with lsd_verify_window), times
- * the kernel with 1, 2, 4 and 8 frames per wave on those frames (one untimed
- * and `repeats` timed launches each, HIP events on `stream`) and keeps the
- * fastest for windows of K frames.  Outputs: chosen (host, frames per wave)
- * and us (host [4], mean microseconds per launch of each candidate), each
+/* Autotuner of the verification (LSD mode): drafts a window of K frames
+ * from the committed state (as lsd_draft_steps; the state is left DRAFTED,
+ * so the caller continues with lsd_verify_window), times every candidate on
+ * those frames (one untimed and `repeats` timed verifications each, HIP
+ * events on `stream`) and keeps the fastest.  Every candidate gives the same
+ * results bit for bit.
+ *   Pair targets: the verification kernel with 1, 2, 4 and 8 frames per
+ *   wave, kept for windows of K frames; chosen = frames per wave, us [4].
+ *   Message-passing target: the evaluation's launch shapes, blocks of the
+ *   pair-filter kernel {256, 512, 1024} x rows per row-chain block {16, 32,
+ *   64} (candidate 3 f + c), kept for every K; chosen = candidate index,
+ *   us [9].
+ * chosen and us (mean microseconds per verification) are host outputs, each
  * optional.  Captured window graphs are dropped.  Synchronises `stream`. */
 LSD_API lsd_status lsd_autotune_verify(lsd_system *sys, int32_t K, int32_t repeats,
                                        int32_t *chosen, double *us, lsd_stream stream);
 
-/* Fixes the verification kernel variant for windows of K frames (1 <= K <=
- * k_max): frames_per_wave in {1, 2, 4, 8}, as lsd_autotune_verify would
- * choose it, without timing (for reproducible profiles).  Captured window
- * graphs are dropped.  LSD_ERR_INVALID_ARG for other values. */
+/* Fixes the verification variant for windows of K frames (1 <= K <=
+ * k_max) as lsd_autotune_verify would choose it, without timing (for
+ * reproducible profiles): frames_per_wave in {1, 2, 4, 8} for pair targets,
+ * the launch-shape candidate 0..8 for the message-passing target (every K).
+ * Captured window graphs are dropped.  LSD_ERR_INVALID_ARG for other values. */
 LSD_API lsd_status lsd_set_verify_variant(lsd_system *sys, int32_t K, int32_t frames_per_wave);
+
+/* Pipelined windows: the one-GPU form of pipelined LSD (Alg. 2, App. C).
+ * With group_frames = G >= 1, lsd_run_windows verifies every group of G
+ * drafted frames on a second stream (default priority) as soon as its last
+ * frame is drafted, while the draft chain continues on the caller's stream;
+ * each group's decisions record the first rejected frame on the device, and
+ * the draft and verification launches of later frames of the window then
+ * find nothing to do (the flushed drafts of Alg. 2).  The window ends with
+ * the decision over every kept frame and the commit, as in a synchronous
+ * window: with the step-keyed stream the committed trajectory is the same
+ * bit for bit (frames after the first rejection are never kept).  The
+ * outputs of frames after the first rejection are reported as not verified
+ * (accepted = 2).  Untimed windows run as one two-stream graph; windows
+ * whose verification is timed are issued eagerly, each group's verification
+ * launch bracketed by events.  0 (the default) restores synchronous windows.
+ * LSD mode only (ignored in plain mode); needs graphs on.
+ * Errors: INVALID_ARG (G outside 0..64), UNSUPPORTED (graphs off). */
+LSD_API lsd_status lsd_set_pipeline(lsd_system *sys, int32_t group_frames);
 
 /* enable != 0 (default): lsd_run_windows replays captured graphs; 0: it
  * issues the kernels of every window one by one. */

@@ -61,9 +61,9 @@ struct Layout {
   size_t cell_rep, cell_count, cell_start, cell_cursor, cell_unsorted, cell_atoms, atom_cell;
   size_t nbr_t, cnt_t, nbr_d, cnt_d, qref, qwrap, rebuild;
   // window
-  size_t qmid, p, fd, ft, invalid, nvalid, partial, commit_frame, reflected, coef, counters, status;
+  size_t qmid, p, fd, ft, invalid, nvalid, rej, partial, commit_frame, reflected, coef, counters, status;
   size_t ec = 0, ec_prev = 0, ec_samples = 0;  // error-correction caches (0: off)
-  size_t mpnn = 0, mpnn_bytes = 0, epart = 0;
+  size_t mpnn = 0, mpnn_bytes = 0;
   size_t net_v = 0;  // learned draft: edge coefficients [N][LSD_NET_MAX_BASIS]
   bool has_mpnn = false;
   int mt = 0, md = 0, n_cells = 0, n_tiles = 0, cell_cap = 0;
@@ -262,6 +262,7 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   L->ft = bump(&off, K * 3 * n * 4);
   L->invalid = bump(&off, (size_t)R * K * 4);
   L->nvalid = bump(&off, 4);
+  L->rej = bump(&off, (size_t)R * 4);
   L->partial = bump(&off, K * T * 4 * 8);
   L->commit_frame = bump(&off, R * 4);
   L->reflected = bump(&off, R * 4);
@@ -279,7 +280,6 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   if (L->has_mpnn) {
     L->mpnn_bytes = mpnn_buffer_bytes(c->k_max, N, L->mt);
     L->mpnn = bump(&off, L->mpnn_bytes);
-    L->epart = bump(&off, K * T * 8);
   }
   L->total = (off + kAlign - 1) / kAlign * kAlign;
   return LSD_OK;
@@ -370,6 +370,12 @@ struct lsd_system {
   std::map<int, WindowGraphs> graphs;
   hipEvent_t graphs_done = nullptr;  // recorded after the last graph replay
   std::map<int, int> tuned_fw;  // frames per wave of the verification kernel, by K
+  // pipelined windows: frames per verification group (0: synchronous
+  // windows), the second stream and the fork/join events
+  int pipe_group = 0;
+  hipStream_t side_stream = nullptr;
+  hipEvent_t pipe_ev[LSD_MAX_K + 1] = {};
+  std::map<int, hipGraphExec_t> pipe_graphs;
 };
 
 namespace {
@@ -407,7 +413,8 @@ lsd_status timing_drain_one(lsd_system* s) {
 
 // Waits for the last replay to finish before the executable graphs go.
 void destroy_graphs(lsd_system* s) {
-  if (s->graphs_done && !s->graphs.empty()) (void)hipEventSynchronize(s->graphs_done);
+  if (s->graphs_done && (!s->graphs.empty() || !s->pipe_graphs.empty()))
+    (void)hipEventSynchronize(s->graphs_done);
   for (auto& kv : s->graphs) {
     if (kv.second.full) (void)hipGraphExecDestroy(kv.second.full);
     if (kv.second.pre) (void)hipGraphExecDestroy(kv.second.pre);
@@ -415,6 +422,9 @@ void destroy_graphs(lsd_system* s) {
     if (kv.second.mid) (void)hipGraphExecDestroy(kv.second.mid);
   }
   s->graphs.clear();
+  for (auto& kv : s->pipe_graphs)
+    if (kv.second) (void)hipGraphExecDestroy(kv.second);
+  s->pipe_graphs.clear();
 }
 
 enum Part { PART_FULL = 0, PART_PRE = 1, PART_POST = 2, PART_MID = 3 };
@@ -423,25 +433,96 @@ enum Part { PART_FULL = 0, PART_PRE = 1, PART_POST = 2, PART_MID = 3 };
 // slot (k_draft then steps with them).
 lsd_status enqueue_plain_mpnn(lsd_system* s, int k, hipStream_t st) {
   char err[256];
-  if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, s->T, k, 1, nullptr, s->W.fd,
-                 ws<double>(s, s->lay.epart), st, err, sizeof(err)))
+  if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, k, 1, nullptr, s->W.fd, st, err, sizeof(err)))
     return fail(LSD_ERR_HIP, "network forces: %s", err);
   return LSD_OK;
 }
 
-// The verification launch(es) of a drafted window: the pair kernel with its
-// fused transport-map epilogue, or the batched network evaluation of the
-// window's valid frames followed by the transport-map sums.
-lsd_status enqueue_verify(lsd_system* s, int K, hipStream_t st) {
+// The verification launch(es) of frames [fb, fe) of a drafted window: the
+// pair kernel with its fused transport-map epilogue, or the batched network
+// evaluation of those frames (the valid ones) followed by the transport-map
+// sums.
+lsd_status enqueue_verify_range(lsd_system* s, int K, int fb, int fe, hipStream_t st) {
   if (s->has_mpnn) {
     char err[256];
-    if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, s->T, 0, K, s->W.nvalid, s->W.ft,
-                   ws<double>(s, s->lay.epart), st, err, sizeof(err)))
+    if (!mpnn_eval(s->mp, s->S, s->Lst, s->W, fb, fe - fb, s->W.nvalid, s->W.ft, st, err,
+                   sizeof(err)))
       return fail(LSD_ERR_HIP, "network forces: %s", err);
-    HIP_TRY(launch_transport(s->S, s->W, s->T, ws<double>(s, s->lay.epart), st));
+    HIP_TRY(launch_transport(s->S, s->W, s->T, s->mp.b.Erow, fb, fe, st));
   } else {
-    HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, verify_fw(s, K), st));
+    HIP_TRY(launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, verify_fw(s, K), fb, fe, st));
   }
+  return LSD_OK;
+}
+
+lsd_status enqueue_verify(lsd_system* s, int K, hipStream_t st) {
+  return enqueue_verify_range(s, K, 0, K, st);
+}
+
+// One pipelined window (Alg. 2 on one GPU): the draft chain runs on `a`;
+// each group of pipe_group drafted frames is verified on `b` as soon as its
+// last frame is drafted, and its decisions record the first rejection, after
+// which the remaining draft and verification launches of the window find no
+// frame to work on.  The window ends on `a` with the decision over all kept
+// frames and the commit (fused with the next window's start).  With
+// `timed`, HIP events bracket every verification launch on `b`.
+lsd_status enqueue_pipelined(lsd_system* s, int K, hipStream_t a, hipStream_t b, bool timed) {
+  const int G = s->pipe_group;
+  s->W.K = K;
+  HIP_TRY(launch_build_lists(s->S, s->Lst, s->W, false, a));
+  int fb = 0, g = 0;
+  for (int k = 0; k < K; ++k) {
+    if (s->Pd.kind == LSD_POT_NET) HIP_TRY(launch_net_nodes(s->S, s->Lst, s->W, s->Pd, k, a));
+    HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, s->Pd, k, 0, a));
+    if (k + 1 - fb < G && k + 1 < K) continue;
+    HIP_TRY(hipEventRecord(s->pipe_ev[g], a));
+    HIP_TRY(hipStreamWaitEvent(b, s->pipe_ev[g], 0));
+    int slot = -1;
+    if (timed) {
+      TimingRing& R = s->ring;
+      if (R.used == kTimingRing) LSD_TRY(timing_drain_one(s));
+      slot = (R.head + R.used) % kTimingRing;
+      HIP_TRY(hipEventRecord(R.start[slot], b));
+    }
+    LSD_TRY(enqueue_verify_range(s, K, fb, k + 1, b));
+    if (timed) {
+      HIP_TRY(hipEventRecord(s->ring.stop[slot], b));
+      s->ring.used += 1;
+    }
+    HIP_TRY(launch_decide_group(s->S, s->W, s->T, fb, k + 1, b));
+    fb = k + 1;
+    ++g;
+  }
+  HIP_TRY(hipEventRecord(s->pipe_ev[LSD_MAX_K], b));
+  HIP_TRY(hipStreamWaitEvent(a, s->pipe_ev[LSD_MAX_K], 0));
+  HIP_TRY(launch_decide(s->S, s->Lst, s->W, s->T, s->O, 0, a));
+  HIP_TRY(launch_commit_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, s->buf.img, 0, a));
+  return LSD_OK;
+}
+
+lsd_status pipeline_resources(lsd_system* s) {
+  if (!s->side_stream) HIP_TRY(hipStreamCreateWithFlags(&s->side_stream, hipStreamNonBlocking));
+  for (int i = 0; i <= LSD_MAX_K; ++i)
+    if (!s->pipe_ev[i]) HIP_TRY(hipEventCreateWithFlags(&s->pipe_ev[i], hipEventDisableTiming));
+  return LSD_OK;
+}
+
+lsd_status capture_pipelined(lsd_system* s, int K, hipGraphExec_t* out) {
+  if (!s->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  LSD_TRY(pipeline_resources(s));
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+  const lsd_status e = enqueue_pipelined(s, K, s->cap_stream, s->side_stream, false);
+  const std::string enqueue_err = e != LSD_OK ? g_err : std::string();
+  hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
+  if (e != LSD_OK || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    if (e != LSD_OK) return fail(e, "pipelined window capture: %s", enqueue_err.c_str());
+    return fail(LSD_ERR_HIP, "pipelined window capture: %s", hipGetErrorString(e2));
+  }
+  hipError_t e3 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e3 != hipSuccess) return fail(LSD_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e3));
   return LSD_OK;
 }
 
@@ -565,6 +646,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.status), 0, 4, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.invalid), 0, R * cfg->k_max, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.nvalid), 0, 1, st);
+  if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.rej), LSD_MAX_K, R, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_t), 0, N, st);
   if (e == hipSuccess) e = launch_zero_i64(ws<long long>(s, L.counters), LSD_NCOUNT * R, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_d), 0, N, st);
@@ -663,6 +745,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   W.ft = ws<float>(s, L.ft);
   W.invalid = ws<int>(s, L.invalid);
   W.nvalid = ws<int>(s, L.nvalid);
+  W.rej = ws<int>(s, L.rej);
   W.partial = ws<double>(s, L.partial);
   W.commit_frame = ws<int>(s, L.commit_frame);
   W.reflected = ws<int>(s, L.reflected);
@@ -708,8 +791,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
     bool given = false;
     if (eo == hipSuccess && s->has_mpnn) {
       char err[256];
-      if (!mpnn_eval(s->mp, S, s->Lst, s->W, s->T, 0, 1, nullptr, s->W.ft, ws<double>(s, L.epart),
-                     st, err, sizeof(err))) {
+      if (!mpnn_eval(s->mp, S, s->Lst, s->W, 0, 1, nullptr, s->W.ft, st, err, sizeof(err))) {
         lsd_destroy(s);
         return fail(LSD_ERR_HIP, "network forces at the initial state: %s", err);
       }
@@ -762,6 +844,7 @@ lsd_status lsd_mark_drafted(lsd_system* s, int32_t K, lsd_stream stream) {
   s->W.K = K;
   HIP_TRY(launch_fill_int(s->W.invalid, 0, s->S.R * s->S.kmax, st));
   HIP_TRY(launch_fill_int(s->W.nvalid, K, 1, st));  // bound: every frame
+  HIP_TRY(launch_fill_int(s->W.rej, LSD_MAX_K, s->S.R, st));
   HIP_TRY(launch_fill_int(s->Lst.rebuild, 1, s->S.R, st));  // lists from the caller's frame 0
   HIP_TRY(launch_build_lists(s->S, s->Lst, s->W, true, st));
   HIP_TRY(launch_frame_validity(s->S, s->Lst, s->W, st));
@@ -825,6 +908,28 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   const bool timed = s->timing && s->cfg.mode == LSD_MODE_LSD;
+  if (s->pipe_group > 0 && s->cfg.mode == LSD_MODE_LSD) {
+    // pipelined windows: an untimed window is one launch of its two-stream
+    // graph; a timed one is issued eagerly with its verification launches
+    // bracketed by events
+    LSD_TRY(pipeline_resources(s));
+    hipGraphExec_t& PG = s->pipe_graphs[K];
+    if ((!timed || s->timing_every > 1) && !PG) LSD_TRY(capture_pipelined(s, K, &PG));
+    s->W.K = K;
+    if (n_windows > 0) HIP_TRY(launch_window_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, st));
+    for (int w = 0; w < n_windows; ++w) {
+      const bool t = timed && (s->timing_seq++ % s->timing_every) == 0;
+      if (t) {
+        LSD_TRY(enqueue_pipelined(s, K, st, s->side_stream, true));
+      } else {
+        HIP_TRY(hipGraphLaunch(PG, st));
+      }
+    }
+    if (!s->graphs_done) HIP_TRY(hipEventCreateWithFlags(&s->graphs_done, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(s->graphs_done, st));
+    s->state = ST_COMMITTED;
+    return LSD_OK;
+  }
   WindowGraphs& G = s->graphs[K];
   if ((!timed || s->timing_every > 1) && !G.full) LSD_TRY(capture(s, K, PART_FULL, &G.full));
   if (timed && !G.pre) LSD_TRY(capture(s, K, PART_PRE, &G.pre));
@@ -868,13 +973,49 @@ lsd_status lsd_autotune_verify(lsd_system* s, int32_t K, int32_t repeats, int32_
   if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
   if (K < 1 || K > s->cfg.k_max) return fail(LSD_ERR_INVALID_ARG, "K = %d outside 1..k_max", K);
   if (repeats < 1) return fail(LSD_ERR_INVALID_ARG, "repeats must be >= 1");
-  if (s->cfg.mode != LSD_MODE_LSD || s->has_mpnn)
-    return fail(LSD_ERR_UNSUPPORTED, "the verification kernel is tuned in LSD mode with a pair target");
+  if (s->cfg.mode != LSD_MODE_LSD)
+    return fail(LSD_ERR_UNSUPPORTED, "the verification is tuned in LSD mode");
   hipStream_t st = static_cast<hipStream_t>(stream);
   LSD_TRY(lsd_draft_steps(s, K, stream));  // leaves the window drafted
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
+  if (s->has_mpnn) {
+    // the network evaluation's launch shapes, timed on the drafted frames
+    // (evaluation and transport sums only write the window's target forces,
+    // the per-tile sums and the network's own buffers: repeatable)
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int c = 0; c < MP_TUNE_CANDIDATES; ++c) {
+      mpnn_set_shape(s->mp, c);
+      lsd_status ls = enqueue_verify(s, K, st);
+      hipError_t e = ls == LSD_OK ? hipEventRecord(e0, st) : hipSuccess;
+      for (int r = 0; r < repeats && ls == LSD_OK && e == hipSuccess; ++r)
+        ls = enqueue_verify(s, K, st);
+      if (ls == LSD_OK && e == hipSuccess) e = hipEventRecord(e1, st);
+      if (ls == LSD_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (ls == LSD_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (ls != LSD_OK || e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (ls != LSD_OK) return ls;
+        return fail(LSD_ERR_HIP, "autotune: %s", hipGetErrorString(e));
+      }
+      if (us) us[c] = 1e3 * ms / repeats;
+      if (c == 0 || ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    mpnn_set_shape(s->mp, best);
+    s->tuned_fw[K] = best;
+    destroy_graphs(s);
+    if (chosen) *chosen = best;
+    return LSD_OK;
+  }
   static const int kCandidates[4] = {1, 2, 4, 8};
   int best = verify_fw(s, K);
   float best_ms = 0.0f;
@@ -882,10 +1023,10 @@ lsd_status lsd_autotune_verify(lsd_system* s, int32_t K, int32_t repeats, int32_
     const int fw = kCandidates[c];
     // one untimed launch, then `repeats` timed ones on the same drafted frames
     // (verification only writes f_target and the per-tile sums: repeatable)
-    hipError_t e = launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st);
+    hipError_t e = launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, 0, K, st);
     if (e == hipSuccess) e = hipEventRecord(e0, st);
     for (int r = 0; r < repeats && e == hipSuccess; ++r)
-      e = launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, st);
+      e = launch_verify(s->S, s->Lst, s->W, s->T, s->Pt, fw, 0, K, st);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -913,10 +1054,30 @@ lsd_status lsd_set_verify_variant(lsd_system* s, int32_t K, int32_t frames_per_w
   if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
   if (K < 1 || K > s->cfg.k_max) return fail(LSD_ERR_INVALID_ARG, "K = %d outside 1..k_max", K);
   const int fw = frames_per_wave;
+  if (s->has_mpnn) {
+    if (fw < 0 || fw >= MP_TUNE_CANDIDATES)
+      return fail(LSD_ERR_INVALID_ARG, "network launch shape %d outside 0..%d", fw,
+                  MP_TUNE_CANDIDATES - 1);
+    mpnn_set_shape(s->mp, fw);
+    s->tuned_fw[K] = fw;
+    destroy_graphs(s);
+    return LSD_OK;
+  }
   if (fw != 1 && fw != 2 && fw != 4 && fw != 8)
     return fail(LSD_ERR_INVALID_ARG, "frames per wave %d not in {1, 2, 4, 8}", fw);
   s->tuned_fw[K] = fw;
   destroy_graphs(s);
+  return LSD_OK;
+}
+
+lsd_status lsd_set_pipeline(lsd_system* s, int32_t group_frames) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  if (group_frames < 0 || group_frames > LSD_MAX_K)
+    return fail(LSD_ERR_INVALID_ARG, "group_frames %d outside 0..%d", group_frames, LSD_MAX_K);
+  if (group_frames > 0 && !s->use_graphs)
+    return fail(LSD_ERR_UNSUPPORTED, "pipelined windows run through lsd_run_windows with graphs on");
+  if (s->pipe_group != group_frames) destroy_graphs(s);
+  s->pipe_group = group_frames;
   return LSD_OK;
 }
 
@@ -1187,6 +1348,12 @@ lsd_status lsd_destroy(lsd_system* s) {
   destroy_graphs(s);
   if (s->graphs_done) (void)hipEventDestroy(s->graphs_done);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  if (s->side_stream) {
+    (void)hipStreamSynchronize(s->side_stream);
+    (void)hipStreamDestroy(s->side_stream);
+  }
+  for (int i = 0; i <= LSD_MAX_K; ++i)
+    if (s->pipe_ev[i]) (void)hipEventDestroy(s->pipe_ev[i]);
   if (s->ring.created) {
     for (int i = 0; i < kTimingRing; ++i) {
       (void)hipEventDestroy(s->ring.start[i]);

@@ -134,6 +134,8 @@ struct WinDev {
   float* ft;          // [kmax][3][N]
   int* invalid;       // [R][kmax]
   int* nvalid;        // [1]: bound on the valid frames of any replica in this window
+  int* rej;           // [R]: first rejected frame found while the window is still being
+                      //      drafted (pipelined windows), LSD_MAX_K while none is known
   double* partial;    // [kmax][n_tiles][4]: S1, S2, E, unused
   int* commit_frame;  // [R]
   int* reflected;     // [R]

@@ -51,6 +51,7 @@ __device__ __forceinline__ void window_start_item(const SysDev& S, const ListDev
     W.invalid[i] = (S.step[rr] + f + 1 > S.step_limit) ? 1 : 0;
   }
   if (i == 0) W.nvalid[0] = 0;  // raised by the drafting of each valid frame
+  if (i < S.R) W.rej[i] = LSD_MAX_K;  // no rejection known yet
   if (i >= S.n) return;
   const int r = S.atom_rep[i];
   const int sp = S.species ? S.species[i] : 0;
@@ -410,7 +411,12 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_draft(SysDev S, ListDev Lst, W
   const int tile = blockIdx.x;
   const int r = Tl.rep[tile];
   int* inv = W.invalid + (size_t)r * S.kmax;
-  if (inv[k]) {
+  // a frame after a rejection that the verification of earlier frames has
+  // already found (pipelined windows) is discarded like one past the skin;
+  // a block that sees it marks the frame, so that no part of it is verified
+  const bool after_reject = W.rej[r] < k;
+  if (after_reject && threadIdx.x == 0 && inv[k] == 0) atomicOr(&inv[k], 1);
+  if (after_reject || inv[k]) {
     // frames from K_eff on are discarded: no work, and the next frame is
     // invalid as well (one thread per replica records it)
     if (threadIdx.x == 0 && tile == Tl.rep_tile_off[r] && k + 1 < W.K) inv[k + 1] = 1;
@@ -526,16 +532,19 @@ __global__ __launch_bounds__(256) void k_frame_validity(SysDev S, ListDev Lst, W
 template <int FW>
 __device__ __forceinline__ void verify_item(const SysDev& S, const ListDev& Lst, const WinDev& W,
                                             const TileDev& Tl, const PotDev& P, int tile, int f0,
-                                            float (*s_shift)[6], double (*s_red)[FW][3]) {
+                                            int fend, float (*s_shift)[6],
+                                            double (*s_red)[FW][3]) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int a = t / LSD_LPA, sub = t % LSD_LPA;
   const int start = Tl.start[tile], count = Tl.count[tile], r = Tl.rep[tile];
   const int* inv = W.invalid + (size_t)r * S.kmax;
+  const int rej = W.rej[r];
   bool valid[FW];
   bool any = false;
 #pragma unroll
   for (int f = 0; f < FW; ++f) {
-    valid[f] = (f0 + f < W.K) && inv[f0 + f] == 0;
+    // frames after a rejection found earlier in the window are not needed
+    valid[f] = (f0 + f < fend) && inv[f0 + f] == 0 && f0 + f <= rej;
     any = any || valid[f];
   }
   if (!any) return;  // uniform over the block
@@ -650,31 +659,36 @@ __device__ __forceinline__ void verify_item(const SysDev& S, const ListDev& Lst,
   __syncthreads();  // the next item rewrites s_shift and s_red
 }
 
+// Frames [fbeg, fend) of the window (all of it, or one group of a pipelined
+// window).
 template <int FW>
 __global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, WinDev W,
-                                                         TileDev Tl, PotDev P) {
+                                                         TileDev Tl, PotDev P, int fbeg,
+                                                         int fend) {
   __shared__ float s_shift[27][6];
   __shared__ double s_red[LSD_VWAVES][FW][3];
-  const int nv = min(W.nvalid[0], W.K);
-  const int items = (nv + FW - 1) / FW * S.n_tiles;
+  const int nv = min(min(W.nvalid[0], W.K), fend);
+  const int items = nv > fbeg ? (nv - fbeg + FW - 1) / FW * S.n_tiles : 0;
   for (int v = blockIdx.x; v < items; v += gridDim.x) {
     const int g = v / S.n_tiles;
-    verify_item<FW>(S, Lst, W, Tl, P, v - g * S.n_tiles, g * FW, s_shift, s_red);
+    verify_item<FW>(S, Lst, W, Tl, P, v - g * S.n_tiles, fbeg + g * FW, fend, s_shift, s_red);
   }
 }
 
 // Transport-map sums for frames whose target forces are already in the
 // window (batched network pass): S1, S2 and the energy per (frame, tile), in
-// the same binary64 form as the epilogue of k_verify.
+// the same binary64 form as the epilogue of k_verify; the energies of the
+// tile's rows come from the network pass (e_rows, frames counted from fbeg).
 __global__ __launch_bounds__(64) void k_transport(SysDev S, WinDev W, TileDev Tl,
-                                                  const double* __restrict__ epart) {
-  const int tile = blockIdx.x, f = blockIdx.y;
+                                                  const double* __restrict__ e_rows, int fbeg) {
+  const int tile = blockIdx.x, f = fbeg + blockIdx.y;
   const int lane = threadIdx.x;
   const int start = Tl.start[tile], count = Tl.count[tile], r = Tl.rep[tile];
-  if (f >= W.K || W.invalid[(size_t)r * S.kmax + f]) return;  // uniform
+  if (f >= W.K || W.invalid[(size_t)r * S.kmax + f] || f > W.rej[r]) return;  // uniform
   const size_t N = (size_t)S.n;
-  double s1 = 0.0, s2 = 0.0;
+  double s1 = 0.0, s2 = 0.0, es = 0.0;
   if (lane < count) {
+    es = e_rows[(size_t)(f - fbeg) * N + start + lane];
     const int i = start + lane;
     const int sp = S.species ? S.species[i] : 0;
     const double isg = 1.0 / S.sig[sp];
@@ -694,11 +708,12 @@ __global__ __launch_bounds__(64) void k_transport(SysDev S, WinDev W, TileDev Tl
   }
   s1 = wave_sum(s1);
   s2 = wave_sum(s2);
+  es = wave_sum(es);
   if (lane == 0) {
     double* out = W.partial + ((size_t)f * S.n_tiles + tile) * 4;
     out[0] = s1;
     out[1] = s2;
-    out[2] = epart[(size_t)f * S.n_tiles + tile];
+    out[2] = es;
   }
 }
 
@@ -707,6 +722,69 @@ __global__ __launch_bounds__(64) void k_transport(SysDev S, WinDev W, TileDev Tl
 // One block per replica; wave w handles frames w, w + nw, ... (the sum over
 // a frame's tiles is lane-strided plus the wave butterfly, whatever the
 // block size), then one thread scans the decisions for the first rejection.
+// Frames after a rejection already found while the window was drafted
+// (pipelined windows) are not verified.
+
+// S1, S2 and the energy of frame f of replica r from the per-tile partials,
+// in a fixed order (lane-strided over the tiles, then the wave butterfly),
+// and the decision log u_{s+f+1} <= log r (Eq. reflectionVerify).
+__device__ __forceinline__ bool frame_decision(const SysDev& S, const WinDev& W, const TileDev& Tl,
+                                               int r, int f, int lane, double* s1o, double* s2o,
+                                               double* eso, double* logro) {
+  const int t0 = Tl.rep_tile_off[r], t1 = Tl.rep_tile_off[r + 1];
+  double s1 = 0.0, s2 = 0.0, es = 0.0;
+  for (int t = t0 + lane; t < t1; t += 64) {
+    const double* pp = W.partial + ((size_t)f * S.n_tiles + t) * 4;
+    s1 += pp[0];
+    s2 += pp[1];
+    es += pp[2];
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  es = wave_sum(es);
+  const double logr = -s1 - 0.5 * s2;
+  const size_t o = (size_t)r * S.kmax + f;
+  const double u = S.replay_u ? S.replay_u[o]
+                              : stream_uniform(S.seed, (uint32_t)r, (uint64_t)S.step[r] + f + 1);
+  *s1o = s1;
+  *s2o = s2;
+  *eso = es;
+  *logro = logr;
+  return log(u) <= logr;
+}
+
+// Decisions of the frames [fbeg, fend) of a pipelined window as soon as they
+// are verified: the first rejected frame is recorded (W.rej), so that the
+// drafting and verification of later frames stop.  One block per replica,
+// one wave per frame of the group.  k_decide later repeats the same
+// arithmetic for every kept frame.
+__global__ __launch_bounds__(1024) void k_decide_group(SysDev S, WinDev W, TileDev Tl, int fbeg,
+                                                       int fend) {
+  __shared__ int s_acc[LSD_MAX_K];
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int* inv = W.invalid + (size_t)r * S.kmax;
+  const int rej = W.rej[r];
+  for (int f = fbeg + wave; f < fend; f += nw) {
+    int acc = 1;
+    if (f <= rej && !inv[f]) {
+      double s1, s2, es, logr;
+      acc = frame_decision(S, W, Tl, r, f, lane, &s1, &s2, &es, &logr) ? 1 : 0;
+    }
+    if (lane == 0) s_acc[f] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && rej >= fend) {
+    for (int f = fbeg; f < fend; ++f) {
+      if (inv[f]) break;
+      if (!s_acc[f]) {
+        W.rej[r] = f;
+        break;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_decide(SysDev S, WinDev W, TileDev Tl, OutDev O, int plain,
                                                  int* __restrict__ rebuild, int always_rebuild) {
   __shared__ double s_s1[LSD_MAX_K], s_s2[LSD_MAX_K];
@@ -718,7 +796,8 @@ __global__ __launch_bounds__(1024) void k_decide(SysDev S, WinDev W, TileDev Tl,
   int keff = K;
   for (int f = 0; f < K; ++f)
     if (inv[f]) { keff = f; break; }
-  const int t0 = Tl.rep_tile_off[r], t1 = Tl.rep_tile_off[r + 1];
+  // a rejection found while the window was drafted ends the verified frames
+  if (!plain && W.rej[r] + 1 < keff) keff = W.rej[r] + 1;
   const uint64_t s0 = (uint64_t)S.step[r];
   for (int f = wave; f < K; f += nw) {
     const size_t o = (size_t)r * S.kmax + f;
@@ -731,20 +810,9 @@ __global__ __launch_bounds__(1024) void k_decide(SysDev S, WinDev W, TileDev Tl,
       }
       continue;
     }
-    double s1 = 0.0, s2 = 0.0, es = 0.0;
-    for (int t = t0 + lane; t < t1; t += 64) {
-      const double* pp = W.partial + ((size_t)f * S.n_tiles + t) * 4;
-      s1 += pp[0];
-      s2 += pp[1];
-      es += pp[2];
-    }
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    es = wave_sum(es);
+    double s1, s2, es, logr;
+    const bool acc = frame_decision(S, W, Tl, r, f, lane, &s1, &s2, &es, &logr);
     if (lane == 0) {
-      const double logr = -s1 - 0.5 * s2;
-      const double u = S.replay_u ? S.replay_u[o] : stream_uniform(S.seed, (uint32_t)r, s0 + f + 1);
-      const bool acc = log(u) <= logr;
       O.accepted[o] = acc ? 1 : 0;
       O.log_ratio[o] = logr;
       O.energy[o] = es;
@@ -1002,9 +1070,20 @@ hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, cons
   return hipGetLastError();
 }
 
-hipError_t launch_transport(const SysDev& S, const WinDev& W, const TileDev& T, const double* epart,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(k_transport, dim3(S.n_tiles, W.K), dim3(64), 0, st, S, W, T, epart);
+hipError_t launch_transport(const SysDev& S, const WinDev& W, const TileDev& T, const double* e_rows,
+                            int fbeg, int fend, hipStream_t st) {
+  if (fend <= fbeg) return hipSuccess;
+  hipLaunchKernelGGL(k_transport, dim3(S.n_tiles, fend - fbeg), dim3(64), 0, st, S, W, T, e_rows,
+                     fbeg);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide_group(const SysDev& S, const WinDev& W, const TileDev& T, int fbeg,
+                               int fend, hipStream_t st) {
+  const int n = fend - fbeg;
+  if (n <= 0) return hipSuccess;
+  const int waves = n < 16 ? n : 16;
+  hipLaunchKernelGGL(k_decide_group, dim3(S.R), dim3(64 * waves), 0, st, S, W, T, fbeg, fend);
   return hipGetLastError();
 }
 
@@ -1029,20 +1108,21 @@ hipError_t launch_frame_validity(const SysDev& S, const ListDev& L, const WinDev
 #endif
 
 hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
-                         const PotDev& P, int fw, hipStream_t st) {
+                         const PotDev& P, int fw, int fbeg, int fend, hipStream_t st) {
+  if (fend <= fbeg) return hipSuccess;
   if (fw > LSD_VERIFY_FW_MAX) fw = LSD_VERIFY_FW_MAX;
   fw = fw >= 8 ? 8 : (fw >= 4 ? 4 : (fw == 2 ? 2 : 1));
-  const long all_items = (long)S.n_tiles * ((W.K + fw - 1) / fw);
+  const long all_items = (long)S.n_tiles * ((fend - fbeg + fw - 1) / fw);
   const long cap = LSD_VERIFY_MAX_BLOCKS > S.n_tiles ? LSD_VERIFY_MAX_BLOCKS : S.n_tiles;
   const dim3 grid((unsigned)(all_items < cap ? all_items : cap));
   if (fw == 8) {
-    hipLaunchKernelGGL(k_verify<8>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<8>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P, fbeg, fend);
   } else if (fw == 4) {
-    hipLaunchKernelGGL(k_verify<4>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<4>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P, fbeg, fend);
   } else if (fw == 2) {
-    hipLaunchKernelGGL(k_verify<2>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<2>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P, fbeg, fend);
   } else {
-    hipLaunchKernelGGL(k_verify<1>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P);
+    hipLaunchKernelGGL(k_verify<1>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T, P, fbeg, fend);
   }
   return hipGetLastError();
 }

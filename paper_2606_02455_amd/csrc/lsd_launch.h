@@ -14,12 +14,18 @@ hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W
 hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                         const PotDev& P, int k, int use_target_list, hipStream_t st,
                         int forces_given = 0);
-hipError_t launch_transport(const SysDev& S, const WinDev& W, const TileDev& T, const double* epart,
-                            hipStream_t st);
+// transport-map sums of frames [fbeg, fend) whose target forces are in the
+// window; e_rows: energy per row of those frames, [f - fbeg][N]
+hipError_t launch_transport(const SysDev& S, const WinDev& W, const TileDev& T, const double* e_rows,
+                            int fbeg, int fend, hipStream_t st);
 hipError_t launch_frame_validity(const SysDev& S, const ListDev& L, const WinDev& W,
                                  hipStream_t st);
+// verification of frames [fbeg, fend) with fw frames per wave
 hipError_t launch_verify(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
-                         const PotDev& P, int fw, hipStream_t st);
+                         const PotDev& P, int fw, int fbeg, int fend, hipStream_t st);
+// decisions of frames [fbeg, fend) of a pipelined window; records the first rejection
+hipError_t launch_decide_group(const SysDev& S, const WinDev& W, const TileDev& T, int fbeg,
+                               int fend, hipStream_t st);
 hipError_t launch_decide(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                          const OutDev& O, int plain, hipStream_t st);
 // commit of the window and start of the next one in one launch

@@ -46,9 +46,9 @@ struct MpnnBuffers {
   float* H;                // [T+1][rows][128]
   float* X;                // [T][rows][128]
   float* U;                // [T][rows][128]
-  float *Mm, *Sn;          // [rows][128]
-  float *Y, *gY;           // [rows][64]
-  float *gH, *gP, *gS, *gM, *gX;  // [rows][128]
+  float* Mm;               // [rows][128]  messages of the current layer
+  double* Erow;            // [rows]       energy of every row (s_E times its readout)
+  float *gH, *gP, *gM, *gX;  // [rows][128]
   // weight fragments (written once by mpnn_prepare)
   uint4* frag;             // all fragment arrays below, contiguous
 };
@@ -62,11 +62,16 @@ struct MpnnWeights {
   // A2 of each layer as the first operand of the filter product (channels x
   // inputs); the node matrices as the second operand, forward (W^T) and
   // reverse (W): out[row][n] = sum_k in[row][k] op[k][n]
+  MpnnFrag A1f[MP_T];  // A1 [128][16] as the first operand, contraction padded to 32
   MpnnFrag A2f[MP_T];
   MpnnFrag Bf[MP_T], C1f[MP_T], C2f[MP_T];   // forward: B^T, C1^T, C2^T
   MpnnFrag Bb[MP_T], C1b[MP_T], C2b[MP_T];   // reverse: B, C1, C2
   MpnnFrag W1f, W1b;                          // W1^T (128 -> 64), W1 (64 -> 128)
 };
+
+// Launch shapes of an evaluation (they change no result: every pair and row
+// is computed the same way whichever block takes it)
+#define MP_TUNE_CANDIDATES 9  // filter blocks {256, 512, 1024} x chain rows {16, 32, 64}
 
 struct MpnnCtx {
   MpnnWeights w;
@@ -74,7 +79,12 @@ struct MpnnCtx {
   float rc, scale;
   int frames;  // frames per evaluation (buffer capacity)
   long pair_cap;
+  unsigned filt_blocks = 512;  // blocks of the filter kernel (two per compute unit)
+  int chain_nt = 0;            // row tiles of 16 per chain block; 0: from the row count
 };
+
+// Candidate c of the evaluation's launch shapes (0 <= c < MP_TUNE_CANDIDATES).
+void mpnn_set_shape(MpnnCtx& M, int c);
 
 // Bytes of the buffers for `frames` frames of N atoms with list width mt.
 size_t mpnn_buffer_bytes(int frames, int n, int mt);
@@ -83,8 +93,8 @@ void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* w
                int n_model_species);
 // Writes the weight fragments (once, after mpnn_bind).
 bool mpnn_prepare(MpnnCtx& M, hipStream_t st, char* err, size_t errlen);
-// Energies (per frame and tile, binary64, into epart[(f0+f) * n_tiles + tile])
-// and forces (frame-major [f0+f][3][N] into Fout) of frames f0 .. f0+nf-1.
+// Forces (frame-major [f0+f][3][N] into Fout) of frames f0 .. f0+nf-1, and
+// the energy of every row (frame f0+f, atom i) in b.Erow[f N + i] (binary64).
 // Asynchronous on `st`, no host synchronisation; a pair count above the
 // capacity or inconsistent edge lists are latched in the status word
 // (LSD_STATUS_PAIRS, LSD_STATUS_EDGES).  Returns false and a message in err
@@ -92,6 +102,5 @@ bool mpnn_prepare(MpnnCtx& M, hipStream_t st, char* err, size_t errlen);
 // Frames past the device bound nvalid (a window's valid frames; nullptr: all
 // nf) and frames flagged invalid are not evaluated (no edges; their forces
 // and energies are left as they were).
-bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
-               int f0, int nf, const int* nvalid, float* Fout, double* epart, hipStream_t st,
-               char* err, size_t errlen);
+bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, int f0, int nf,
+               const int* nvalid, float* Fout, hipStream_t st, char* err, size_t errlen);

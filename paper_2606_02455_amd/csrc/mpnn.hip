@@ -52,7 +52,12 @@ __device__ __forceinline__ int eff_frames(const int* nvalid, int f0, int nf) {
   return v < 0 ? 0 : (v < nf ? v : nf);
 }
 
-__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
+// logistic function from the hardware exponential and reciprocal (each
+// within about one ulp; far below the binary32 rounding of the products
+// around them)
+__device__ __forceinline__ float sigmoidf(float x) {
+  return __builtin_amdgcn_rcpf(1.0f + __expf(-x));
+}
 __device__ __forceinline__ float siluf(float x) { return x * sigmoidf(x); }
 __device__ __forceinline__ float dsiluf(float x) {
   const float s = sigmoidf(x);
@@ -117,9 +122,10 @@ __device__ __forceinline__ RowScan row_pass(MpnnBuffers& b, const SysDev& S, con
   __shared__ int s_e[kRowThreads / 64], s_o[kRowThreads / 64];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int fl = (int)(row / S.n), i = (int)(row - (long)fl * S.n);
-  // frames that are not verified (past the skin, or past the step limit)
-  // contribute no edges
-  const bool live = W.invalid[(size_t)S.atom_rep[i] * S.kmax + f0 + fl] == 0;
+  // frames that are not verified (past the skin or the step limit, or after
+  // a rejection already found in a pipelined window) contribute no edges
+  const int rep = S.atom_rep[i];
+  const bool live = W.invalid[(size_t)rep * S.kmax + f0 + fl] == 0 && f0 + fl <= W.rej[rep];
   const int cnt = live ? L.cnt_t[i] : 0;
   int base_e = WRITE ? b.off[row] : 0, base_o = WRITE ? b.poff[row] : 0;
   int tot_e = 0, tot_o = 0;
@@ -250,21 +256,40 @@ __global__ __launch_bounds__(kRowThreads) void k_mp_edges(MpnnBuffers b, SysDev 
 
 // every reverse edge refers to its owner: the neighbour row's edge back to
 // this row with the opposite image; uid = ~pair (kNoPair if the owner's pair
-// is past the capacity)
+// is past the capacity).  Sixteen lanes per edge test sixteen of the
+// neighbour row's edges at a time; the first match in row order wins.
+constexpr int kRevLanes = 16;
+constexpr unsigned kRevBlocks = 2048;  // fixed grid; edges taken in strides
+
 __global__ __launch_bounds__(256) void k_mp_reverse(MpnnBuffers b, long rows, long cap,
                                                     int* __restrict__ status) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= cap || e >= b.off[rows]) return;
-  if (b.uid[e] >= 0) return;
-  const int rj = b.enbr[e], ri = b.erow[e], back = 26 - b.ecode[e];
-  int found = -1;
-  for (int q = b.off[rj]; q < b.off[rj + 1]; ++q)
-    if (b.enbr[q] == ri && b.ecode[q] == back) { found = b.uid[q]; break; }
-  if (found < 0) {
-    atomicOr(status, LSD_STATUS_EDGES);  // the edge sets of the two directions differ
-    found = kNoPair;
+  const int sub = threadIdx.x % kRevLanes;
+  const int lane = threadIdx.x & 63, g0 = lane & ~(kRevLanes - 1);
+  const long n_edges = min((long)b.off[rows], cap);
+  const long stride = (long)gridDim.x * (blockDim.x / kRevLanes);
+  for (long e = ((long)blockIdx.x * blockDim.x + threadIdx.x) / kRevLanes; e < n_edges;
+       e += stride) {
+    if (b.uid[e] >= 0) continue;  // an owner edge (or a capped one): uniform over the lanes
+    const int rj = b.enbr[e], ri = b.erow[e], back = 26 - b.ecode[e];
+    const int q0 = b.off[rj], q1 = b.off[rj + 1];
+    int found = -1;
+    for (int q = q0; q < q1; q += kRevLanes) {
+      const int qq = q + sub;
+      const bool hit = qq < q1 && b.enbr[qq] == ri && b.ecode[qq] == back;
+      const unsigned long long m = (__ballot(hit) >> g0) & ((1ull << kRevLanes) - 1);
+      if (m) {
+        found = b.uid[q + __ffsll((long long)m) - 1];
+        break;
+      }
+    }
+    if (sub == 0) {
+      if (found < 0) {
+        atomicOr(status, LSD_STATUS_EDGES);  // the edge sets of the two directions differ
+        found = kNoPair;
+      }
+      b.uid[e] = found == kNoPair ? kNoPair : ~found;
+    }
   }
-  b.uid[e] = found == kNoPair ? kNoPair : ~found;
 }
 
 // pairs the buffers hold
@@ -292,7 +317,6 @@ __global__ __launch_bounds__(256) void k_mp_filter(MpnnWeights w, MpnnBuffers b,
   const long np = held_pairs(b, cap);
   const long ntiles = (np + kFiltPairs - 1) / kFiltPairs;
   if ((long)blockIdx.x >= ntiles) return;  // uniform
-  const int c = t & (MP_H - 1), ph = t >> 7;  // channel and pair half of the S stage
   const float pre = sqrtf(2.0f / rc), pi_rc = 3.14159265358979f / rc;
   for (int l = 0; l < MP_T; ++l) {
     bf16x8 ah[2][4], al[2][4];
@@ -304,10 +328,16 @@ __global__ __launch_bounds__(256) void k_mp_filter(MpnnWeights w, MpnnBuffers b,
         ah[mt][ks] = as_bf16x8(w.A2f[l].hi[fi]);
         al[mt][ks] = as_bf16x8(w.A2f[l].lo[fi]);
       }
-    float a1r[MP_R];
+    bf16x8 a1h[2], a1l[2];
+    float a1v[2][4];
 #pragma unroll
-    for (int k = 0; k < MP_R; ++k) a1r[k] = w.A1[l][c * MP_R + k];
-    const float a1c = w.a1[l][c];
+    for (int mt = 0; mt < 2; ++mt) {
+      const long fi = (long)(2 * wave + mt) * 64 + lane;
+      a1h[mt] = as_bf16x8(w.A1f[l].hi[fi]);
+      a1l[mt] = as_bf16x8(w.A1f[l].lo[fi]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a1v[mt][q] = w.a1[l][32 * wave + 16 * mt + 4 * (lane >> 4) + q];
+    }
     float a2v[2][4];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
@@ -334,20 +364,43 @@ __global__ __launch_bounds__(256) void k_mp_filter(MpnnWeights w, MpnnBuffers b,
         }
       }
       __syncthreads();
-      // first layer of the filter MLP (binary32), staged as bfloat16 parts
-      for (int q = 16 * ph; q < 16 * ph + 16; ++q) {
-        float z = a1c, dz = 0.f;
+      // first layer of the filter MLP on the matrix cores (16 inputs padded
+      // to 32): z = A1 e + a1 and A1 de/dr per channel and pair; then
+      // S = silu(z), DS = silu'(z) (A1 de/dr), staged as bfloat16 parts
 #pragma unroll
-        for (int k = 0; k < MP_R; ++k) {
-          z = fmaf(a1r[k], s_e[q][k], z);
-          dz = fmaf(a1r[k], s_de[q][k], dz);
+      for (int nt = 0; nt < 2; ++nt) {
+        const int q = 16 * nt + (lane & 15), kk = 8 * (lane >> 4);
+        float xe[8], xd[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          xe[e] = kk < MP_R ? s_e[q][kk + e] : 0.0f;
+          xd[e] = kk < MP_R ? s_de[q][kk + e] : 0.0f;
         }
-        const float S = siluf(z), DS = dsiluf(z) * dz;
-        const __bf16 sh = (__bf16)S, dh = (__bf16)DS;
-        s_sh[q][c] = sh;
-        s_sl[q][c] = (__bf16)(S - (float)sh);
-        s_dh[q][c] = dh;
-        s_dl[q][c] = (__bf16)(DS - (float)dh);
+        bf16x8 beh, bel, bdh, bdl;
+        split8(xe, beh, bel);
+        split8(xd, bdh, bdl);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+          const f32x4 z = mfma3(a1h[mt], a1l[mt], beh, bel, zero);
+          const f32x4 dz = mfma3(a1h[mt], a1l[mt], bdh, bdl, zero);
+          __bf16 sh[4], sl[4], dh[4], dl[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float zz = z[e] + a1v[mt][e];
+            const float sg = sigmoidf(zz);
+            const float S = zz * sg, DS = sg * (1.0f + zz * (1.0f - sg)) * dz[e];
+            sh[e] = (__bf16)S;
+            sl[e] = (__bf16)(S - (float)sh[e]);
+            dh[e] = (__bf16)DS;
+            dl[e] = (__bf16)(DS - (float)dh[e]);
+          }
+          const int c0 = 32 * wave + 16 * mt + 4 * (lane >> 4);
+          *reinterpret_cast<uint2*>(&s_sh[q][c0]) = __builtin_bit_cast(uint2, sh);
+          *reinterpret_cast<uint2*>(&s_sl[q][c0]) = __builtin_bit_cast(uint2, sl);
+          *reinterpret_cast<uint2*>(&s_dh[q][c0]) = __builtin_bit_cast(uint2, dh);
+          *reinterpret_cast<uint2*>(&s_dl[q][c0]) = __builtin_bit_cast(uint2, dl);
+        }
       }
       __syncthreads();
       // A2 S and A2 DS for 16 pairs at a time
@@ -393,9 +446,6 @@ __global__ __launch_bounds__(256) void k_mp_filter(MpnnWeights w, MpnnBuffers b,
   }
 }
 
-// Dense row products out[row][n] = sum_k in[row][k] op[k][n] (+ epilogue) on
-// the matrix cores, rows in tiles of 16; wave w computes the output channels
-// [w ND/4, (w+1) ND/4) from fragments of op held in registers.
 // rows of an evaluation that are computed: the frames below the device bound
 struct RowSpan {
   const int* nvalid;
@@ -404,24 +454,48 @@ struct RowSpan {
   __device__ __forceinline__ long rows() const { return (long)eff_frames(nvalid, f0, nf) * n; }
 };
 
-enum RowEpilogue {
-  EP_STORE = 0,      // out = x
-  EP_BIAS_SILU = 1,  // out = u = x + bias (kept), out2 = silu(u)
-  EP_RESID = 2,      // out = in2 + x + bias
-  EP_DSILU = 3,      // out = x * silu'(in2)
-  EP_ACCUM = 4,      // out = in2 + x
+// Row chains: the node MLPs between two gathers, fused.  A block owns 16 NT
+// consecutive rows (NT tiles of 16) and runs a fixed sequence of stages on
+// them; each stage is one product out = in . op on the matrix cores (the
+// weights' fragments of the stage in registers, wave w computing the output
+// channels [w ND/4, (w+1) ND/4) of every tile) with its epilogue, the input
+// and output tiles staying in LDS between stages.
+//   CH_EMBED     h0 = W_emb[s]            -> H0; X0 = h0 B0^T         -> X0
+//   CH_FWD(t)    U = m C1^T + c1           -> U_t; Sn = silu(U)
+//                h' = h + Sn C2^T + c2     -> H_{t+1}; X = h' B_{t+1}^T -> X_{t+1}
+//   CH_LAST      the same up to h' = h_T, then the readout and the row part
+//                of the reverse pass of the last layer:
+//                y = h_T W1^T + b1, e = s_E (w2 . silu(y) + b2) -> energy per row,
+//                gY = s_E w2 (.) silu'(y), gH = gY W1                -> gH
+//                gS = (gH C2) (.) silu'(U_t), gM = gS C1              -> gM
+//   CH_BWD(t)    gH' = gH + gX B_{t+1}     -> gH (other buffer)
+//                gS = (gH' C2_t) (.) silu'(U_t), gM = gS C1_t          -> gM
+enum ChainMode { CH_EMBED = 0, CH_FWD = 1, CH_LAST = 2, CH_BWD = 3 };
+
+constexpr int kChainLd = MP_H + 4;        // fp32 row stride of the LDS tiles
+
+struct ChainArgs {
+  int t;                                  // layer
+  const float* in;                        // m (CH_FWD, CH_LAST) or gX (CH_BWD), [rows][128]
+  const float* h;                         // h_t (CH_FWD, CH_LAST)
+  float* u_out;                           // U_t (CH_FWD, CH_LAST)
+  float* h_out;                           // h_{t+1} (CH_EMBED: h0; CH_FWD)
+  float* x_out;                           // X_{t+1} (CH_EMBED: X0; CH_FWD)
+  const float* gh;                        // gH (CH_BWD)
+  float* gh_out;                          // gH' (CH_BWD) or gH (CH_LAST)
+  const float* u_in;                      // U_t (CH_BWD)
+  float* gm_out;                          // gM (CH_LAST, CH_BWD)
+  double* e_row;                          // energy of every row (CH_LAST)
+  float scale;
 };
 
-template <int KD, int ND, int EP>
-__global__ __launch_bounds__(256) void k_mp_rows(MpnnFrag op, const float* __restrict__ in,
-                                                 RowSpan span, float* __restrict__ out,
-                                                 float* __restrict__ out2,
-                                                 const float* __restrict__ in2,
-                                                 const float* __restrict__ bias) {
+// out = tile . op for the 64 rows staged in `in` (LDS); the epilogue gets
+// (row in block, channel c0, four values) for four consecutive channels.
+template <int NT, int KD, int ND, typename Epi>
+__device__ __forceinline__ void chain_stage(const MpnnFrag& op, const float (*in)[kChainLd],
+                                            Epi epi) {
   constexpr int KS = KD / 32, MT = ND / 64;
-  const long rows = span.rows();
-  if ((long)blockIdx.x * 16 >= rows) return;  // uniform
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   bf16x8 ah[MT][KS], al[MT][KS];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
@@ -431,67 +505,180 @@ __global__ __launch_bounds__(256) void k_mp_rows(MpnnFrag op, const float* __res
       ah[mt][ks] = as_bf16x8(op.hi[fi]);
       al[mt][ks] = as_bf16x8(op.lo[fi]);
     }
-  const long ntiles = (rows + 15) / 16;
   const int kk = 8 * (lane >> 4);
-  for (long rt = blockIdx.x; rt < ntiles; rt += gridDim.x) {
-    const long row = rt * 16 + (lane & 15);
-    const bool ok = row < rows;
+#pragma unroll 1
+  for (int nt = 0; nt < NT; ++nt) {
+    const int rr = 16 * nt + (lane & 15);
     f32x4 acc[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) acc[mt] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      float x[8];
-      if (ok) {
-        const float4 u0 = *reinterpret_cast<const float4*>(in + row * KD + 32 * ks + kk);
-        const float4 u1 = *reinterpret_cast<const float4*>(in + row * KD + 32 * ks + kk + 4);
-        x[0] = u0.x; x[1] = u0.y; x[2] = u0.z; x[3] = u0.w;
-        x[4] = u1.x; x[5] = u1.y; x[6] = u1.z; x[7] = u1.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = 0.f;
-      }
+      const float4 u0 = *reinterpret_cast<const float4*>(&in[rr][32 * ks + kk]);
+      const float4 u1 = *reinterpret_cast<const float4*>(&in[rr][32 * ks + kk + 4]);
+      const float x[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
       bf16x8 bh, bl;
       split8(x, bh, bl);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma3(ah[mt][ks], al[mt][ks], bh, bl, acc[mt]);
     }
-    if (!ok) continue;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int c0 = (ND / 4) * wave + 16 * mt + 4 * (lane >> 4);
-      const long o = row * ND + c0;
-      float4 y;
-      float* yp = &y.x;
-      if (EP == EP_STORE) {
+    for (int mt = 0; mt < MT; ++mt)
+      epi(rr, (ND / 4) * wave + 16 * mt + 4 * (lane >> 4), acc[mt]);
+  }
+}
+
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void st4(float* p, float4 v) { *reinterpret_cast<float4*>(p) = v; }
+
+// The row part of the reverse pass of layer t from gH (staged in `g`):
+// gS = (gH C2_t) (.) silu'(U_t) into `scratch`, gM = gS C1_t to global.
+template <int NT>
+__device__ __forceinline__ void chain_tail(const MpnnWeights& w, const ChainArgs& a,
+                                           float (*g)[kChainLd], float (*scratch)[kChainLd],
+                                           const float (*su)[kChainLd], long r0, long rows) {
+  const int l = a.t;
+  chain_stage<NT, MP_H, MP_H>(w.C2b[l], g, [&](int rr, int c0, f32x4 v) {
+    const float4 u = ld4(&su[rr][c0]);
+    const float uv[4] = {u.x, u.y, u.z, u.w};
+    float o[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) yp[e] = acc[mt][e];
-      } else if (EP == EP_BIAS_SILU) {
-        float4 s;
-        float* sp = &s.x;
+    for (int e = 0; e < 4; ++e) o[e] = v[e] * dsiluf(uv[e]);
+    st4(&scratch[rr][c0], make_float4(o[0], o[1], o[2], o[3]));
+  });
+  __syncthreads();
+  chain_stage<NT, MP_H, MP_H>(w.C1b[l], scratch, [&](int rr, int c0, f32x4 v) {
+    const long row = r0 + rr;
+    if (row < rows) st4(a.gm_out + row * MP_H + c0, make_float4(v[0], v[1], v[2], v[3]));
+  });
+  __syncthreads();
+}
+
+template <int MODE, int NT>
+__global__ __launch_bounds__(256) void k_mp_chain(MpnnWeights w, MpnnBuffers b, SysDev S,
+                                                  RowSpan span, ChainArgs a) {
+  constexpr int kChainRows = 16 * NT;
+  __shared__ __align__(16) float s_a[kChainRows][kChainLd];
+  __shared__ __align__(16) float s_b[kChainRows][kChainLd];
+  __shared__ __align__(16) float s_u[MODE == CH_EMBED ? 1 : kChainRows][kChainLd];
+  __shared__ float s_e[4][kChainRows];
+  const long rows = span.rows();
+  const int t = threadIdx.x;
+  for (long r0 = (long)blockIdx.x * kChainRows; r0 < rows; r0 += (long)gridDim.x * kChainRows) {
+    // stage the block's input rows (zeros past the end)
+    for (int idx = t; idx < kChainRows * (MP_H / 4); idx += 256) {
+      const int rr = idx / (MP_H / 4), c = 4 * (idx % (MP_H / 4));
+      const long row = r0 + rr;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row < rows) {
+        if constexpr (MODE == CH_EMBED) {
+          const int i = (int)(row % S.n);
+          const int sp = S.species ? S.species[i] : 0;
+          v = ld4(w.W_emb + sp * MP_H + c);
+          st4(a.h_out + row * MP_H + c, v);
+        } else {
+          v = ld4(a.in + row * MP_H + c);
+        }
+      }
+      st4(&s_a[rr][c], v);
+    }
+    __syncthreads();
+    if constexpr (MODE == CH_EMBED) {
+      chain_stage<NT, MP_H, MP_H>(w.Bf[0], s_a, [&](int rr, int c0, f32x4 v) {
+        const long row = r0 + rr;
+        if (row < rows) st4(a.x_out + row * MP_H + c0, make_float4(v[0], v[1], v[2], v[3]));
+      });
+      __syncthreads();
+      continue;
+    }
+    if constexpr (MODE == CH_FWD || MODE == CH_LAST) {
+      const int l = a.t;
+      // U = m C1^T + c1 (kept), Sn = silu(U)
+      chain_stage<NT, MP_H, MP_H>(w.C1f[l], s_a, [&](int rr, int c0, f32x4 v) {
+        const long row = r0 + rr;
+        float u[4], sn[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          yp[e] = acc[mt][e] + bias[c0 + e];
-          sp[e] = siluf(yp[e]);
+          u[e] = v[e] + w.c1[l][c0 + e];
+          sn[e] = siluf(u[e]);
         }
-        *reinterpret_cast<float4*>(out2 + o) = s;
-      } else if (EP == EP_RESID) {
-        const float4 h = *reinterpret_cast<const float4*>(in2 + o);
-        const float* hp = &h.x;
+        st4(&s_u[rr][c0], make_float4(u[0], u[1], u[2], u[3]));
+        st4(&s_b[rr][c0], make_float4(sn[0], sn[1], sn[2], sn[3]));
+        if (row < rows) st4(a.u_out + row * MP_H + c0, make_float4(u[0], u[1], u[2], u[3]));
+      });
+      __syncthreads();
+      // h' = h + Sn C2^T + c2
+      chain_stage<NT, MP_H, MP_H>(w.C2f[l], s_b, [&](int rr, int c0, f32x4 v) {
+        const long row = r0 + rr;
+        float4 hp = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row < rows) hp = ld4(a.h + row * MP_H + c0);
+        const float hv[4] = {hp.x, hp.y, hp.z, hp.w};
+        float o[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) yp[e] = (acc[mt][e] + hp[e]) + bias[c0 + e];
-      } else if (EP == EP_DSILU) {
-        const float4 u = *reinterpret_cast<const float4*>(in2 + o);
-        const float* up = &u.x;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) yp[e] = acc[mt][e] * dsiluf(up[e]);
-      } else {  // EP_ACCUM
-        const float4 h = *reinterpret_cast<const float4*>(in2 + o);
-        const float* hp = &h.x;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) yp[e] = hp[e] + acc[mt][e];
+        for (int e = 0; e < 4; ++e) o[e] = (v[e] + hv[e]) + w.c2[l][c0 + e];
+        const float4 ov = make_float4(o[0], o[1], o[2], o[3]);
+        st4(&s_a[rr][c0], ov);
+        if (MODE == CH_FWD && row < rows) st4(a.h_out + row * MP_H + c0, ov);
+      });
+      __syncthreads();
+      if constexpr (MODE == CH_FWD) {
+        // X_{t+1} = h' B_{t+1}^T
+        chain_stage<NT, MP_H, MP_H>(w.Bf[l + 1], s_a, [&](int rr, int c0, f32x4 v) {
+          const long row = r0 + rr;
+          if (row < rows) st4(a.x_out + row * MP_H + c0, make_float4(v[0], v[1], v[2], v[3]));
+        });
+        __syncthreads();
+        continue;
       }
-      *reinterpret_cast<float4*>(out + o) = y;
+      // readout: y = h_T W1^T + b1; per row e = w2 . silu(y) + b2 and
+      // gY = s_E w2 (.) silu'(y) (into s_b, 64 columns)
+      chain_stage<NT, MP_H, MP_RH>(w.W1f, s_a, [&](int rr, int c0, f32x4 v) {
+        float gy[4], ep = 0.f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float y = v[e] + w.b1[c0 + e];
+          const float sg = sigmoidf(y);
+          ep = fmaf(w.w2[c0 + e], y * sg, ep);
+          gy[e] = a.scale * w.w2[c0 + e] * (sg * (1.0f + y * (1.0f - sg)));
+        }
+        st4(&s_b[rr][c0], make_float4(gy[0], gy[1], gy[2], gy[3]));
+        // the four lane groups of the wave hold consecutive channel quads of
+        // the same row: a fixed butterfly, then one value per wave and row
+        ep += __shfl_xor(ep, 16, 64);
+        ep += __shfl_xor(ep, 32, 64);
+        if ((threadIdx.x & 63) < 16) s_e[threadIdx.x >> 6][rr] = ep;
+      });
+      __syncthreads();
+      if (t < kChainRows && r0 + t < rows) {
+        const float ei = ((s_e[0][t] + s_e[1][t]) + (s_e[2][t] + s_e[3][t])) + w.b2[0];
+        a.e_row[r0 + t] = (double)a.scale * (double)ei;
+      }
+      // gH = gY W1 (into s_a)
+      chain_stage<NT, MP_RH, MP_H>(w.W1b, s_b, [&](int rr, int c0, f32x4 v) {
+        const long row = r0 + rr;
+        const float4 ov = make_float4(v[0], v[1], v[2], v[3]);
+        st4(&s_a[rr][c0], ov);
+        if (row < rows) st4(a.gh_out + row * MP_H + c0, ov);
+      });
+      __syncthreads();
+      chain_tail<NT>(w, a, s_a, s_b, s_u, r0, rows);
+    } else {  // CH_BWD: gH' = gH + gX B_{t+1} (into s_b)
+      chain_stage<NT, MP_H, MP_H>(w.Bb[a.t + 1], s_a, [&](int rr, int c0, f32x4 v) {
+        const long row = r0 + rr;
+        float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (row < rows) g = ld4(a.gh + row * MP_H + c0);
+        const float4 ov = make_float4(g.x + v[0], g.y + v[1], g.z + v[2], g.w + v[3]);
+        st4(&s_b[rr][c0], ov);
+        if (row < rows) st4(a.gh_out + row * MP_H + c0, ov);
+      });
+      // U_t of the block's rows for silu'
+      for (int idx = t; idx < kChainRows * (MP_H / 4); idx += 256) {
+        const int rr = idx / (MP_H / 4), c = 4 * (idx % (MP_H / 4));
+        const long row = r0 + rr;
+        st4(&s_u[rr][c], row < rows ? ld4(a.u_in + row * MP_H + c) : make_float4(0.f, 0.f, 0.f, 0.f));
+      }
+      __syncthreads();
+      chain_tail<NT>(w, a, s_b, s_a, s_u, r0, rows);
     }
   }
 }
@@ -499,9 +686,9 @@ __global__ __launch_bounds__(256) void k_mp_rows(MpnnFrag op, const float* __res
 // Fragments of G(i, k) (i: output channel, k: contraction index) for the A
 // operand: element [(it KS + ks) 64 + lane][e] = G(16 it + lane % 16,
 // 32 ks + 8 (lane / 16) + e), split into bfloat16 hi and lo.  G(i, k) =
-// src[i ld + k], or src[k ld + i] when transposed.
+// src[i ld + k], or src[k ld + i] when transposed; 0 for k >= Ksrc.
 __global__ void k_mp_frag(const float* __restrict__ src, int ld, int trans, int I, int K,
-                          uint4* __restrict__ hi, uint4* __restrict__ lo) {
+                          int Ksrc, uint4* __restrict__ hi, uint4* __restrict__ lo) {
   const int KS = K / 32;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)(I / 16) * KS * 64) return;
@@ -509,21 +696,16 @@ __global__ void k_mp_frag(const float* __restrict__ src, int ld, int trans, int 
   const int i = 16 * it + lane % 16, k0 = 32 * ks + 8 * (lane / 16);
   float x[8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) x[e] = trans ? src[(long)(k0 + e) * ld + i] : src[(long)i * ld + k0 + e];
+  for (int e = 0; e < 8; ++e) {
+    const int k = k0 + e;  // contraction indices from Ksrc on are zero padding
+    x[e] = k >= Ksrc ? 0.0f : (trans ? src[(long)k * ld + i] : src[(long)i * ld + k]);
+  }
   bf16x8 h, l;
   split8(x, h, l);
   hi[idx] = __builtin_bit_cast(uint4, h);
   lo[idx] = __builtin_bit_cast(uint4, l);
 }
 
-__global__ __launch_bounds__(128) void k_mp_embed(MpnnWeights w, MpnnBuffers b, SysDev S,
-                                                  RowSpan span) {
-  const long row = blockIdx.x;
-  if (row >= span.rows()) return;
-  const int i = (int)(row % S.n);
-  const int sp = S.species ? S.species[i] : 0;
-  b.H[row * MP_H + threadIdx.x] = w.W_emb[sp * MP_H + threadIdx.x];
-}
 
 // out[row][c] = sum over the row's edges e of W_t[pair(e)][c] * V[neighbour row][c]
 // (messages with V = X_t; dE/dX with V = gM: W is symmetric in the pair)
@@ -556,31 +738,6 @@ __global__ __launch_bounds__(128) void k_mp_gather(MpnnBuffers b, int t, const f
   out[row * MP_H + c] = acc;
 }
 
-// Readout of one tile of one frame (64 rows, one lane each): energy summed
-// in binary64 by a wave butterfly; gY = s_E w2 (.) silu'(Y + b1).
-__global__ __launch_bounds__(64) void k_mp_readout(MpnnWeights w, MpnnBuffers b, SysDev S,
-                                                   TileDev T, RowSpan span, float scale,
-                                                   double* epart) {
-  const int tile = blockIdx.x, fl = blockIdx.y;
-  const int f0 = span.f0;
-  if (fl >= eff_frames(span.nvalid, f0, span.nf)) return;  // energy not needed
-  const int lane = threadIdx.x;
-  const int start = T.start[tile], count = T.count[tile];
-  const long row = (long)fl * S.n + start + lane;
-  double e = 0.0;
-  if (lane < count) {
-    float ei = w.b2[0];
-    for (int o = 0; o < MP_RH; ++o) {
-      const float y = b.Y[row * MP_RH + o] + w.b1[o];
-      ei = fmaf(w.w2[o], siluf(y), ei);
-      b.gY[row * MP_RH + o] = scale * w.w2[o] * dsiluf(y);
-    }
-    e = (double)scale * (double)ei;
-  }
-  e = wave_sum(e);
-  if (lane == 0) epart[(size_t)(f0 + fl) * S.n_tiles + tile] = e;
-}
-
 // dE/dr of one pair (both directions), layer t:
 // sum_c (gM[a] X[b] + gM[b] X[a])_c dW_c/dr.  One wave per pair, pairs
 // taken by a fixed grid up to the device pair count; the first layer of the
@@ -605,28 +762,43 @@ __global__ __launch_bounds__(256) void k_mp_dedr(MpnnBuffers b, int t, int first
   }
 }
 
-// F_a = sum over a's edges of dE/dr (q_b - q_a)/r, frame-major [f][3][N]
+// F_a = sum over a's edges of dE/dr (q_b - q_a)/r, frame-major [f][3][N].
+// Sixteen lanes per row: lane sub sums the edges sub, sub + 16, ... in
+// order, then a fixed butterfly over the sixteen lanes.
+constexpr int kForceLanes = 16;
+
 __global__ __launch_bounds__(256) void k_mp_forces(MpnnBuffers b, SysDev S, RowSpan span,
                                                    float* Fout) {
-  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= span.rows()) return;
-  const int f0 = span.f0;
+  const long row = ((long)blockIdx.x * blockDim.x + threadIdx.x) / kForceLanes;
+  const int sub = threadIdx.x % kForceLanes;
+  const bool in = row < span.rows();
   const long N = S.n;
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  if (in) {
+    const int e1 = b.off[row + 1];
+    for (int e = b.off[row] + sub; e < e1; e += kForceLanes) {
+      // the pair's unit vector points from its owner row; the reverse edge
+      // sees it negated
+      const int u = b.uid[e];
+      if (u == kNoPair) continue;  // only after a latched capacity overflow
+      const long p = u >= 0 ? u : ~u;
+      const float g = u >= 0 ? b.gr[p] : -b.gr[p];
+      const float4 v = *reinterpret_cast<const float4*>(b.uv + 4 * p);
+      fx = fmaf(g, v.x, fx);
+      fy = fmaf(g, v.y, fy);
+      fz = fmaf(g, v.z, fz);
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < kForceLanes; o <<= 1) {
+    fx += __shfl_xor(fx, o, 64);
+    fy += __shfl_xor(fy, o, 64);
+    fz += __shfl_xor(fz, o, 64);
+  }
+  if (!in || sub != 0) return;
+  const int f0 = span.f0;
   const long fl = row / N;
   const int i = (int)(row - fl * N);
-  float fx = 0.f, fy = 0.f, fz = 0.f;
-  const int e1 = b.off[row + 1];
-  for (int e = b.off[row]; e < e1; ++e) {
-    // the pair's unit vector points from its owner row; the reverse edge
-    // sees it negated
-    const int u = b.uid[e];
-    if (u == kNoPair) continue;  // only after a latched capacity overflow
-    const long p = u >= 0 ? u : ~u;
-    const float g = u >= 0 ? b.gr[p] : -b.gr[p];
-    fx = fmaf(g, b.uv[4 * p], fx);
-    fy = fmaf(g, b.uv[4 * p + 1], fy);
-    fz = fmaf(g, b.uv[4 * p + 2], fz);
-  }
   float* F = Fout + (size_t)(f0 + fl) * 3 * N;
   F[i] = fx;
   F[N + i] = fy;
@@ -643,19 +815,12 @@ size_t frag_elems(int I, int K) { return (size_t)(I / 16) * (K / 32) * 64; }
 // all fragment arrays: per layer A2 and six node matrices (128 x 128), plus
 // W1 forward (64 x 128) and reverse (128 x 64), each hi and lo
 size_t frag_total() {
-  return 2 * ((size_t)MP_T * 7 * frag_elems(MP_H, MP_H) + frag_elems(MP_RH, MP_H) +
-              frag_elems(MP_H, MP_RH));
+  return 2 * ((size_t)MP_T * (7 * frag_elems(MP_H, MP_H) + frag_elems(MP_H, 32)) +
+              frag_elems(MP_RH, MP_H) + frag_elems(MP_H, MP_RH));
 }
 
 // blocks of the fixed grids over pairs: two per compute unit
 constexpr unsigned kPairBlocks = 512;
-// row tiles per block of the dense row products: up to one tile per block
-constexpr unsigned kRowBlocksMax = 1024;
-
-unsigned row_blocks(long rows) {
-  const long tiles = (rows + 15) / 16;
-  return (unsigned)(tiles < (long)kRowBlocksMax ? tiles : (long)kRowBlocksMax);
-}
 
 }  // namespace
 
@@ -676,7 +841,7 @@ size_t mpnn_buffer_bytes(int frames, int n, int mt) {
   b += 2 * al((rows + 1) * 4) + 4 * al(slots * 4);
   b += al(4 * 4);
   b += al((MP_T + 1) * rows * MP_H * 4) + 2 * al(MP_T * rows * MP_H * 4);
-  b += 2 * al(rows * MP_H * 4) + 2 * al(rows * MP_RH * 4) + 5 * al(rows * MP_H * 4);
+  b += al(rows * MP_H * 4) + al(rows * 8) + 4 * al(rows * MP_H * 4);
   b += al(frag_total() * 16);
   return b;
 }
@@ -708,12 +873,9 @@ void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* w
   b.X = take(MP_T * rows * MP_H * 4);
   b.U = take(MP_T * rows * MP_H * 4);
   b.Mm = take(rows * MP_H * 4);
-  b.Sn = take(rows * MP_H * 4);
-  b.Y = take(rows * MP_RH * 4);
-  b.gY = take(rows * MP_RH * 4);
+  b.Erow = reinterpret_cast<double*>(take(rows * 8));
   b.gH = take(rows * MP_H * 4);
   b.gP = take(rows * MP_H * 4);
-  b.gS = take(rows * MP_H * 4);
   b.gM = take(rows * MP_H * 4);
   b.gX = take(rows * MP_H * 4);
   b.frag = reinterpret_cast<uint4*>(take(frag_total() * 16));
@@ -748,6 +910,7 @@ void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* w
     return r;
   };
   for (int t = 0; t < MP_T; ++t) {
+    w.A1f[t] = frag(MP_H, 32);
     w.A2f[t] = frag(MP_H, MP_H);
     w.Bf[t] = frag(MP_H, MP_H);
     w.C1f[t] = frag(MP_H, MP_H);
@@ -769,15 +932,25 @@ void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* w
     }                                                                                   \
   } while (0)
 
+void mpnn_set_shape(MpnnCtx& M, int c) {
+  static const unsigned kFilt[3] = {256, 512, 1024};
+  static const int kNt[3] = {1, 2, 4};
+  M.filt_blocks = kFilt[(c / 3) % 3];
+  M.chain_nt = kNt[c % 3];
+}
+
 bool mpnn_prepare(MpnnCtx& M, hipStream_t st, char* err, size_t errlen) {
   const MpnnWeights& w = M.w;
-  auto launch = [&](const float* src, int ld, int trans, int I, int K, const MpnnFrag& d) {
+  auto launch = [&](const float* src, int ld, int trans, int I, int K, const MpnnFrag& d,
+                    int Ksrc = 0) {
     const long n = (long)frag_elems(I, K);
     hipLaunchKernelGGL(k_mp_frag, dim3(nblk(n, 256)), dim3(256), 0, st, src, ld, trans, I, K,
-                       const_cast<uint4*>(d.hi), const_cast<uint4*>(d.lo));
+                       Ksrc ? Ksrc : K, const_cast<uint4*>(d.hi), const_cast<uint4*>(d.lo));
     return hipGetLastError();
   };
   for (int t = 0; t < MP_T; ++t) {
+    // first filter layer: A1 [128][16], contraction padded to 32
+    MP_HIP(launch(w.A1[t], MP_R, 0, MP_H, 32, w.A1f[t], MP_R));
     // filter: A2 [out][in] as stored; forward node products use W^T, i.e.
     // G(out, in) = W[out][in]; reverse products use W, G(i, k) = W[k][i]
     MP_HIP(launch(w.A2[t], MP_H, 0, MP_H, MP_H, w.A2f[t]));
@@ -793,9 +966,8 @@ bool mpnn_prepare(MpnnCtx& M, hipStream_t st, char* err, size_t errlen) {
   return true;
 }
 
-bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
-               int f0, int nf, const int* nvalid, float* Fout, double* epart, hipStream_t st,
-               char* err, size_t errlen) {
+bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, int f0, int nf,
+               const int* nvalid, float* Fout, hipStream_t st, char* err, size_t errlen) {
   const MpnnWeights& w = M.w;
   MpnnBuffers& b = M.b;
   const long N = S.n, mt = L.mt;
@@ -812,70 +984,86 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, c
   hipLaunchKernelGGL(k_mp_edges, dim3((unsigned)rows), dim3(kRowThreads), 0, st, b, S, L, W, f0,
                      nf, nvalid, M.rc, cap);
   MP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_mp_reverse, dim3(nblk(rows * mt, 256)), dim3(256), 0, st, b, rows,
-                     rows * mt, L.status);
+  {
+    const unsigned need = nblk(rows * mt * kRevLanes, 256);
+    hipLaunchKernelGGL(k_mp_reverse, dim3(need < kRevBlocks ? need : kRevBlocks), dim3(256), 0, st,
+                       b, rows, rows * mt, L.status);
+  }
   MP_HIP(hipGetLastError());
   // filters W and dW/dr of every pair and layer
-  hipLaunchKernelGGL(k_mp_filter, dim3(kPairBlocks), dim3(256), 0, st, w, b, M.rc, cap);
+  hipLaunchKernelGGL(k_mp_filter, dim3(M.filt_blocks), dim3(256), 0, st, w, b, M.rc, cap);
   MP_HIP(hipGetLastError());
-  // forward through the layers
-  hipLaunchKernelGGL(k_mp_embed, dim3((unsigned)rows), dim3(MP_H), 0, st, w, b, S, span);
-  MP_HIP(hipGetLastError());
+  // forward through the layers: gathers and fused row chains
   const long rh = rows * MP_H;
-  const dim3 rg(row_blocks(rows)), rb(256);
+  // rows per chain block: 16, 32 or 64, so that a small evaluation still
+  // spreads over a few hundred blocks
+  const long tiles16 = (rows + 15) / 16;
+  const int nt = M.chain_nt ? M.chain_nt : (tiles16 >= 4L * 512 ? 4 : (tiles16 >= 2L * 256 ? 2 : 1));
+  const dim3 cg((unsigned)((tiles16 + nt - 1) / nt)), cb(256);
+  auto chain = [&](int mode, const ChainArgs& c) {
+#define MP_CHAIN(MODE_)                                                                    \
+  if (nt == 4) hipLaunchKernelGGL((k_mp_chain<MODE_, 4>), cg, cb, 0, st, w, b, S, span, c); \
+  else if (nt == 2) hipLaunchKernelGGL((k_mp_chain<MODE_, 2>), cg, cb, 0, st, w, b, S, span, c); \
+  else hipLaunchKernelGGL((k_mp_chain<MODE_, 1>), cg, cb, 0, st, w, b, S, span, c);
+    if (mode == CH_EMBED) { MP_CHAIN(CH_EMBED) }
+    else if (mode == CH_FWD) { MP_CHAIN(CH_FWD) }
+    else if (mode == CH_LAST) { MP_CHAIN(CH_LAST) }
+    else { MP_CHAIN(CH_BWD) }
+#undef MP_CHAIN
+    return hipGetLastError();
+  };
+  ChainArgs ca{};
+  ca.scale = M.scale;
+  ca.h_out = b.H;
+  ca.x_out = b.X;
+  MP_HIP(chain(CH_EMBED, ca));
   for (int t = 0; t < MP_T; ++t) {
-    float* Ht = b.H + t * rh;
-    float* Hn = b.H + (t + 1) * rh;
     float* Xt = b.X + t * rh;
-    float* Ut = b.U + t * rh;
-    hipLaunchKernelGGL((k_mp_rows<MP_H, MP_H, EP_STORE>), rg, rb, 0, st, w.Bf[t], Ht, span, Xt,
-                       nullptr, nullptr, nullptr);
-    MP_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, t, Xt, b.Mm, span);
     MP_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_mp_rows<MP_H, MP_H, EP_BIAS_SILU>), rg, rb, 0, st, w.C1f[t], b.Mm, span,
-                       Ut, b.Sn, nullptr, w.c1[t]);
-    MP_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_mp_rows<MP_H, MP_H, EP_RESID>), rg, rb, 0, st, w.C2f[t], b.Sn, span, Hn,
-                       nullptr, Ht, w.c2[t]);
+    ChainArgs c{};
+    c.scale = M.scale;
+    c.t = t;
+    c.in = b.Mm;
+    c.h = b.H + t * rh;
+    c.u_out = b.U + t * rh;
+    if (t + 1 < MP_T) {
+      c.h_out = b.H + (t + 1) * rh;
+      c.x_out = b.X + (t + 1) * rh;
+      MP_HIP(chain(CH_FWD, c));
+    } else {
+      // readout, energies per row, and the row part of the last layer's
+      // reverse pass
+      c.gh_out = b.gH;
+      c.gm_out = b.gM;
+      c.e_row = b.Erow;
+      MP_HIP(chain(CH_LAST, c));
+    }
     MP_HIP(hipGetLastError());
   }
-  // readout and its gradient
-  hipLaunchKernelGGL((k_mp_rows<MP_H, MP_RH, EP_STORE>), rg, rb, 0, st, w.W1f, b.H + MP_T * rh,
-                     span, b.Y, nullptr, nullptr, nullptr);
-  MP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_mp_readout, dim3(S.n_tiles, nf), dim3(64), 0, st, w, b, S, T, span, M.scale,
-                     epart);
-  MP_HIP(hipGetLastError());
-  hipLaunchKernelGGL((k_mp_rows<MP_RH, MP_H, EP_STORE>), rg, rb, 0, st, w.W1b, b.gY, span, b.gH,
-                     nullptr, nullptr, nullptr);
-  MP_HIP(hipGetLastError());
   // reverse pass through the layers
   for (int t = MP_T - 1; t >= 0; --t) {
-    float* Xt = b.X + t * rh;
-    float* Ut = b.U + t * rh;
-    hipLaunchKernelGGL((k_mp_rows<MP_H, MP_H, EP_DSILU>), rg, rb, 0, st, w.C2b[t], b.gH, span,
-                       b.gS, nullptr, Ut, nullptr);
-    MP_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_mp_rows<MP_H, MP_H, EP_STORE>), rg, rb, 0, st, w.C1b[t], b.gS, span,
-                       b.gM, nullptr, nullptr, nullptr);
-    MP_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_mp_dedr, dim3(kPairBlocks * 2), dim3(256), 0, st, b, t,
-                       t == MP_T - 1 ? 1 : 0, Xt, cap);
+                       t == MP_T - 1 ? 1 : 0, b.X + t * rh, cap);
     MP_HIP(hipGetLastError());
-    if (t > 0) {
-      hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, t, b.gM, b.gX,
-                         span);
-      MP_HIP(hipGetLastError());
-      hipLaunchKernelGGL((k_mp_rows<MP_H, MP_H, EP_ACCUM>), rg, rb, 0, st, w.Bb[t], b.gX, span,
-                         b.gP, nullptr, b.gH, nullptr);
-      MP_HIP(hipGetLastError());
-      float* tmp = b.gH;
-      b.gH = b.gP;
-      b.gP = tmp;
-    }
+    if (t == 0) break;
+    hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, t, b.gM, b.gX, span);
+    MP_HIP(hipGetLastError());
+    ChainArgs c{};
+    c.scale = M.scale;
+    c.t = t - 1;
+    c.in = b.gX;
+    c.gh = b.gH;
+    c.gh_out = b.gP;
+    c.u_in = b.U + (t - 1) * rh;
+    c.gm_out = b.gM;
+    MP_HIP(chain(CH_BWD, c));
+    float* tmp = b.gH;
+    b.gH = b.gP;
+    b.gP = tmp;
   }
-  hipLaunchKernelGGL(k_mp_forces, dim3(nblk(rows, 256)), dim3(256), 0, st, b, S, span, Fout);
+  hipLaunchKernelGGL(k_mp_forces, dim3(nblk(rows * kForceLanes, 256)), dim3(256), 0, st, b, S,
+                     span, Fout);
   MP_HIP(hipGetLastError());
   return true;
 }

@@ -86,6 +86,7 @@ EXPORTS = {
     "lsd_get_status": ([C.c_void_p, C.POINTER(C.c_int32), C.c_void_p], C.c_int),
     "lsd_set_step_limit": ([C.c_void_p, C.c_int64], C.c_int),
     "lsd_set_graphs": ([C.c_void_p, C.c_int32], C.c_int),
+    "lsd_set_pipeline": ([C.c_void_p, C.c_int32], C.c_int),
     "lsd_get_counters": ([C.c_void_p, C.POINTER(C.c_int64), C.c_void_p], C.c_int),
     "lsd_reset_counters": ([C.c_void_p, C.c_void_p], C.c_int),
     "lsd_set_verify_timing": ([C.c_void_p, C.c_int32], C.c_int),
@@ -288,6 +289,7 @@ class LSDSystem:
         self._masses = np.ascontiguousarray(w.species_mass, dtype=np.float64)
         tgt = dict(target or w.target)
         dft = dict(draft or w.draft)
+        self.network_target = tgt.get("kind") == "mpnn"
         cfg = Config()
         cfg.n_atoms, cfg.n_replicas = self.N, self.R
         cfg.atom_offsets = self._offsets.ctypes.data_as(C.POINTER(C.c_int32))
@@ -526,25 +528,39 @@ class LSDSystem:
         _check(load().lsd_get_status(self.h, C.byref(f), _stream(self.torch)), "lsd_get_status")
         return int(f.value)
 
+    NET_SHAPES = [(f, c) for f in (256, 512, 1024) for c in (16, 32, 64)]
+
     def autotune_verify(self, K, repeats=10):
-        """Pick the fastest frames-per-wave variant of the verification
-        kernel for windows of K frames; drafts one window (left drafted).
-        Returns (chosen, {fw: microseconds})."""
+        """Pick the fastest verification variant; drafts one window (left
+        drafted).  Pair targets: frames per wave of the verification kernel
+        for windows of K frames, returns (chosen, {fw: microseconds}).
+        Network target: the evaluation's launch shape, returns (candidate,
+        {(filter blocks, chain rows): microseconds})."""
         ch = C.c_int32()
-        us = (C.c_double * 4)()
+        us = (C.c_double * 9)()
         _check(load().lsd_autotune_verify(self.h, int(K), int(repeats), C.byref(ch), us,
                                           _stream(self.torch)), "lsd_autotune_verify")
+        if self.network_target:
+            return int(ch.value), {self.NET_SHAPES[c]: us[c] for c in range(9)}
         return int(ch.value), {1: us[0], 2: us[1], 4: us[2], 8: us[3]}
 
     def set_verify_variant(self, K, frames_per_wave):
-        """Fix the verification kernel variant (1, 2, 4 or 8 frames per
-        wave) for windows of K frames, without timing."""
+        """Fix the verification variant without timing: 1, 2, 4 or 8 frames
+        per wave for windows of K frames (pair targets), or the launch-shape
+        candidate 0..8 (network target)."""
         _check(load().lsd_set_verify_variant(self.h, int(K), int(frames_per_wave)),
                "lsd_set_verify_variant")
 
     def set_graphs(self, on=True):
         """Replay captured HIP graphs in run_windows (default) or not."""
         _check(load().lsd_set_graphs(self.h, 1 if on else 0), "lsd_set_graphs")
+
+    def set_pipeline(self, group_frames):
+        """Pipelined windows in run_windows: verify every group of
+        `group_frames` drafted frames on a second stream while drafting
+        continues, stopping the window's drafting at the first rejection
+        (0: synchronous windows)."""
+        _check(load().lsd_set_pipeline(self.h, int(group_frames)), "lsd_set_pipeline")
 
     def set_step_limit(self, limit):
         """Stop every replica exactly at step `limit` (None: no limit)."""

@@ -203,3 +203,60 @@ def test_mpnn_target_full_size_c5_frames(torch, lsd, ora):
     _say("mpnn c5 size, 2 frames")
     w = W.config("c5")
     _check_frames(torch, lsd, ora, w, 2, c3_scale(), seed=6)
+
+
+def test_network_launch_shapes_give_identical_results(torch, lsd):
+    # the autotuner's candidates for the network evaluation (blocks of the
+    # pair-filter kernel x rows per row-chain block) change only which block
+    # computes what: forces and energies are equal bit for bit
+    _say("mpnn launch shapes")
+    w = W.triatomic_replicas(n_replicas=3, n_mol_lo=10, n_mol_hi=20, seed=51, K=4)
+    K = 4
+    scale = c3_scale()
+    qm = _frames(w, K, 52)
+    rng = np.random.default_rng(53)
+    sig = np.sqrt(w.masses() * w.kT * w.force_unit)[:, None]
+    pd = W.f32(rng.normal(size=(K + 1,) + w.positions.shape) * sig)
+    ref = None
+    for c in range(9):
+        g = lsd.LSDSystem(w, mode="lsd", target=_target(scale), draft=_zero_draft(w), k_max=K)
+        g.set_verify_variant(K, c)
+        _inject(g, torch, qm, pd, np.zeros_like(qm))
+        g.mark_drafted(K)
+        g.verify_window()
+        g.accept_rollback(sync=True)
+        assert g.status() == 0
+        out = (g.window()["f_target"][:K].cpu().numpy().copy(), g.energy.cpu().numpy().copy(),
+               g.log_ratio.cpu().numpy().copy())
+        if ref is None:
+            ref = out
+        else:
+            for x, y in zip(out, ref):
+                assert np.array_equal(x, y), c
+        g.destroy()
+
+
+def test_network_autotuned_windows_equal_untuned(torch, lsd):
+    _say("mpnn autotuned vs untuned windows")
+    w = W.triatomic_replicas(n_replicas=3, n_mol_lo=8, n_mol_hi=16, seed=54, K=4)
+    tgt = dict(kind="mpnn", rc=5.0, weights=W.mpnn_weights(3, seed=17), n_model_species=3,
+               scale=0.1 * W.MPNN_C3_SCALE)
+    a = lsd.LSDSystem(w, mode="lsd", target=tgt, draft=_zero_draft(w), error_correction=2)
+    b = lsd.LSDSystem(w, mode="lsd", target=tgt, draft=_zero_draft(w), error_correction=2)
+    chosen, us = b.autotune_verify(4, repeats=2)
+    assert 0 <= chosen < 9 and len(us) == 9 and all(v > 0 for v in us.values())
+    b.verify_window()
+    b.accept_rollback()
+    a.draft_steps(4)
+    a.verify_window()
+    a.accept_rollback()
+    for rep in range(3):
+        a.run_windows(4, 4)
+        b.run_windows(4, 4)
+        sa, sb = a.state(), b.state()
+        for k in ("q", "p", "img", "step"):
+            assert np.array_equal(sa[k], sb[k]), (rep, k)
+        assert np.array_equal(a.counters(), b.counters())
+    assert a.counters()[:, 1].sum() > a.counters()[:, 0].sum()
+    a.destroy()
+    b.destroy()
