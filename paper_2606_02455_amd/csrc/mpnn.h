@@ -43,6 +43,7 @@ struct MpnnBuffers {
   int* uid;                // [slots]     pair of the edge: p (owner) or ~p (reverse)
   int* poff;               // [rows+1]    first pair owned by every row
   int* counts;             // [4]         directed edges, pairs, error flags
+  int* tile_sums;          // [tiles][2]  scan of large evaluations: totals per tile of rows
   float* H;                // [T+1][rows][128]
   float* X;                // [T][rows][128]
   float* U;                // [T][rows][128]

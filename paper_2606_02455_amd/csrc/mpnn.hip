@@ -206,8 +206,15 @@ __global__ __launch_bounds__(kRowThreads) void k_mp_count(MpnnBuffers b, SysDev 
   }
 }
 
-// exclusive scans of the row counts of edges and pairs in place (one block);
-// off[rows], poff[rows] = totals, also copied to counts[0..1]
+// Exclusive scans of the row counts of edges (off) and pairs (poff) in place;
+// off[rows], poff[rows] = totals, also copied to counts[0..1].
+// Small evaluations: one block, thread t scanning the contiguous rows
+// [t chunk, (t+1) chunk).  Large ones: blocks of kScanTile rows scan their
+// tile (coalesced, wave scans) and record its totals, one block scans the
+// totals, and a last pass adds each tile's offset.
+constexpr int kScanTile = 1024;
+constexpr long kScanSingleMax = 4096;  // rows scanned by the single-block form
+
 __global__ __launch_bounds__(1024) void k_mp_scan(MpnnBuffers b, long rows) {
   __shared__ long s[1024], s2[1024];
   const int t = threadIdx.x;
@@ -242,6 +249,87 @@ __global__ __launch_bounds__(1024) void k_mp_scan(MpnnBuffers b, long rows) {
     b.counts[0] = (int)s[1023];
     b.counts[1] = (int)s2[1023];
   }
+}
+
+// inclusive scan of one int over a 1024-thread block (wave scans, then the
+// sixteen wave totals); returns the inclusive prefix, *total the block sum
+__device__ __forceinline__ int block_scan_incl(int v, int* s_w, int* total) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  if (lane == 63) s_w[wave] = v;
+  __syncthreads();
+  if (t < 64) {
+    int w = t < 16 ? s_w[t] : 0;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const int u = __shfl_up(w, o, 64);
+      if (t >= o) w += u;
+    }
+    if (t < 16) s_w[16 + t] = w;  // inclusive prefix of the wave totals
+  }
+  __syncthreads();
+  const int incl = v + (wave > 0 ? s_w[16 + wave - 1] : 0);
+  *total = s_w[16 + 15];
+  __syncthreads();
+  return incl;
+}
+
+// pass 1: each tile's exclusive prefixes and totals
+__global__ __launch_bounds__(1024) void k_mp_scan_tiles(MpnnBuffers b, long rows, int* tile_sums) {
+  __shared__ int s_w[32];
+  const long r = (long)blockIdx.x * kScanTile + threadIdx.x;
+  const int v1 = r < rows ? b.off[r] : 0, v2 = r < rows ? b.poff[r] : 0;
+  int t1, t2;
+  const int i1 = block_scan_incl(v1, s_w, &t1);
+  const int i2 = block_scan_incl(v2, s_w, &t2);
+  if (r < rows) {
+    b.off[r] = i1 - v1;
+    b.poff[r] = i2 - v2;
+  }
+  if (threadIdx.x == 0) {
+    tile_sums[2 * blockIdx.x] = t1;
+    tile_sums[2 * blockIdx.x + 1] = t2;
+  }
+}
+
+// pass 2: exclusive prefixes of the tile totals (one block, up to 1024
+// tiles per round; rounds carried)
+__global__ __launch_bounds__(1024) void k_mp_scan_top(MpnnBuffers b, long rows, int* tile_sums,
+                                                      int tiles) {
+  __shared__ int s_w[32];
+  int carry1 = 0, carry2 = 0;
+  for (int base = 0; base < tiles; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int v1 = i < tiles ? tile_sums[2 * i] : 0, v2 = i < tiles ? tile_sums[2 * i + 1] : 0;
+    int t1, t2;
+    const int i1 = block_scan_incl(v1, s_w, &t1);
+    const int i2 = block_scan_incl(v2, s_w, &t2);
+    if (i < tiles) {
+      tile_sums[2 * i] = carry1 + i1 - v1;
+      tile_sums[2 * i + 1] = carry2 + i2 - v2;
+    }
+    carry1 += t1;
+    carry2 += t2;
+  }
+  if (threadIdx.x == 0) {
+    b.off[rows] = carry1;
+    b.poff[rows] = carry2;
+    b.counts[0] = carry1;
+    b.counts[1] = carry2;
+  }
+}
+
+// pass 3: add each tile's offset
+__global__ __launch_bounds__(1024) void k_mp_scan_add(MpnnBuffers b, long rows,
+                                                      const int* __restrict__ tile_sums) {
+  const long r = (long)blockIdx.x * kScanTile + threadIdx.x;
+  if (r >= rows) return;
+  b.off[r] += tile_sums[2 * blockIdx.x];
+  b.poff[r] += tile_sums[2 * blockIdx.x + 1];
 }
 
 // directed edge records of every row in list order, and the pair records of
@@ -451,7 +539,17 @@ struct RowSpan {
   const int* nvalid;
   int f0, nf;
   long n;
+  const int* atom_rep;   // [N]
+  const int* invalid;    // [R][kmax]
+  const int* rej;        // [R]
+  int kmax;
   __device__ __forceinline__ long rows() const { return (long)eff_frames(nvalid, f0, nf) * n; }
+  // the row's frame is one the window verifies (the same test as the edges')
+  __device__ __forceinline__ bool live(long row) const {
+    const int fl = (int)(row / n), i = (int)(row - (long)fl * n);
+    const int r = atom_rep[i];
+    return invalid[(size_t)r * kmax + f0 + fl] == 0 && f0 + fl <= rej[r];
+  }
 };
 
 // Row chains: the node MLPs between two gathers, fused.  A block owns 16 NT
@@ -565,6 +663,11 @@ __global__ __launch_bounds__(256) void k_mp_chain(MpnnWeights w, MpnnBuffers b, 
   const long rows = span.rows();
   const int t = threadIdx.x;
   for (long r0 = (long)blockIdx.x * kChainRows; r0 < rows; r0 += (long)gridDim.x * kChainRows) {
+    // rows of frames the window does not verify (another replica's
+    // truncated window, past the skin) are skipped block by block: no
+    // gather or force of a verified frame reads them
+    const bool lv = t < kChainRows && r0 + t < rows && span.live(r0 + t);
+    if (!__syncthreads_or(lv ? 1 : 0)) continue;
     // stage the block's input rows (zeros past the end)
     for (int idx = t; idx < kChainRows * (MP_H / 4); idx += 256) {
       const int rr = idx / (MP_H / 4), c = 4 * (idx % (MP_H / 4));
@@ -708,7 +811,11 @@ __global__ void k_mp_frag(const float* __restrict__ src, int ld, int trans, int 
 
 
 // out[row][c] = sum over the row's edges e of W_t[pair(e)][c] * V[neighbour row][c]
-// (messages with V = X_t; dE/dX with V = gM: W is symmetric in the pair)
+// (messages with V = X_t; dE/dX with V = gM: W is symmetric in the pair).
+// One block of 128 threads (channels) per row; eight edges' loads issued
+// together, terms added in edge order.
+constexpr int kGatherDepth = 8;
+
 __device__ __forceinline__ float pair_filter(const MpnnBuffers& b, int u, int t, int c) {
   if (u == kNoPair) return 0.f;  // only after a latched capacity overflow
   const long p = u >= 0 ? u : ~u;
@@ -723,42 +830,44 @@ __global__ __launch_bounds__(128) void k_mp_gather(MpnnBuffers b, int t, const f
   const int e1 = b.off[row + 1];
   float acc = 0.f;
   int e = b.off[row];
-  // four edges' loads issued together, terms added in edge order
-  for (; e + 4 <= e1; e += 4) {
-    float wv[4], vv[4];
+  for (; e + kGatherDepth <= e1; e += kGatherDepth) {
+    float wv[kGatherDepth], vv[kGatherDepth];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kGatherDepth; ++q) {
       wv[q] = pair_filter(b, b.uid[e + q], t, c);
       vv[q] = V[(long)b.enbr[e + q] * MP_H + c];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc = fmaf(wv[q], vv[q], acc);
+    for (int q = 0; q < kGatherDepth; ++q) acc = fmaf(wv[q], vv[q], acc);
   }
   for (; e < e1; ++e) acc = fmaf(pair_filter(b, b.uid[e], t, c), V[(long)b.enbr[e] * MP_H + c], acc);
   out[row * MP_H + c] = acc;
 }
 
 // dE/dr of one pair (both directions), layer t:
-// sum_c (gM[a] X[b] + gM[b] X[a])_c dW_c/dr.  One wave per pair, pairs
-// taken by a fixed grid up to the device pair count; the first layer of the
-// reverse pass stores, the others add.
+// sum_c (gM[a] X[b] + gM[b] X[a])_c dW_c/dr.  Thirty-two lanes per pair (four
+// channels each, 16-byte loads), two pairs per wave, pairs taken by a fixed
+// grid up to the device pair count; a fixed butterfly over the 32 lanes.
+// The first layer of the reverse pass stores, the others add.
 __global__ __launch_bounds__(256) void k_mp_dedr(MpnnBuffers b, int t, int first,
                                                  const float* __restrict__ X, long cap) {
-  const int lane = threadIdx.x & 63;
+  const int l32 = threadIdx.x & 31, c = 4 * l32;
   const long np = held_pairs(b, cap);
-  for (long p = (long)blockIdx.x * 4 + (threadIdx.x >> 6); p < np; p += (long)gridDim.x * 4) {
-    const long ra = (long)b.ua[p] * MP_H, rb = (long)b.ub[p] * MP_H;
-    const float* V = b.Vf + p * MP_HT + t * MP_H;
-    float acc = 0.f;
+  const long stride = (long)gridDim.x * 8;
+  for (long p = (long)blockIdx.x * 8 + (threadIdx.x >> 5); p < np; p += stride) {
+    const long ra = (long)b.ua[p] * MP_H + c, rb = (long)b.ub[p] * MP_H + c;
+    const float4 ga = *reinterpret_cast<const float4*>(b.gM + ra);
+    const float4 gb = *reinterpret_cast<const float4*>(b.gM + rb);
+    const float4 xa = *reinterpret_cast<const float4*>(X + ra);
+    const float4 xb = *reinterpret_cast<const float4*>(X + rb);
+    const float4 v = *reinterpret_cast<const float4*>(b.Vf + p * MP_HT + t * MP_H + c);
+    float acc = (ga.x * xb.x + gb.x * xa.x) * v.x;
+    acc = fmaf(ga.y * xb.y + gb.y * xa.y, v.y, acc);
+    acc = fmaf(ga.z * xb.z + gb.z * xa.z, v.z, acc);
+    acc = fmaf(ga.w * xb.w + gb.w * xa.w, v.w, acc);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int c = lane + 64 * h;
-      const float g = b.gM[ra + c] * X[rb + c] + b.gM[rb + c] * X[ra + c];
-      acc = fmaf(g, V[c], acc);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) b.gr[p] = first ? acc : b.gr[p] + acc;
+    for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+    if (l32 == 0) b.gr[p] = first ? acc : b.gr[p] + acc;
   }
 }
 
@@ -839,7 +948,7 @@ size_t mpnn_buffer_bytes(int frames, int n, int mt) {
   b += 2 * al(pairs * MP_HT * 4);            // Wf, Vf
   b += al(pairs * 4 * 4) + al(pairs * 4) + 2 * al(pairs * 4);
   b += 2 * al((rows + 1) * 4) + 4 * al(slots * 4);
-  b += al(4 * 4);
+  b += al(4 * 4) + al(((rows + kScanTile - 1) / kScanTile) * 2 * 4);
   b += al((MP_T + 1) * rows * MP_H * 4) + 2 * al(MP_T * rows * MP_H * 4);
   b += al(rows * MP_H * 4) + al(rows * 8) + 4 * al(rows * MP_H * 4);
   b += al(frag_total() * 16);
@@ -869,6 +978,7 @@ void mpnn_bind(MpnnCtx& M, char* base, int frames, int n, int mt, const float* w
   b.ecode = reinterpret_cast<int*>(take(slots * 4));
   b.uid = reinterpret_cast<int*>(take(slots * 4));
   b.counts = reinterpret_cast<int*>(take(4 * 4));
+  b.tile_sums = reinterpret_cast<int*>(take(((rows + kScanTile - 1) / kScanTile) * 2 * 4));
   b.H = take((MP_T + 1) * rows * MP_H * 4);
   b.X = take(MP_T * rows * MP_H * 4);
   b.U = take(MP_T * rows * MP_H * 4);
@@ -973,14 +1083,24 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, i
   const long N = S.n, mt = L.mt;
   const long rows = (long)nf * N;
   const long cap = M.pair_cap;
-  const RowSpan span{nvalid, f0, nf, N};
+  const RowSpan span{nvalid, f0, nf, N, S.atom_rep, W.invalid, W.rej, S.kmax};
   // compact the in-cutoff pairs of every row into edges (list order), then
   // into unordered pairs; the totals stay on the device
   hipLaunchKernelGGL(k_mp_count, dim3((unsigned)rows), dim3(kRowThreads), 0, st, b, S, L, W, f0,
                      nf, nvalid, M.rc);
   MP_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_mp_scan, dim3(1), dim3(1024), 0, st, b, rows);
-  MP_HIP(hipGetLastError());
+  if (rows <= kScanSingleMax) {
+    hipLaunchKernelGGL(k_mp_scan, dim3(1), dim3(1024), 0, st, b, rows);
+    MP_HIP(hipGetLastError());
+  } else {
+    const int tiles = (int)((rows + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_mp_scan_tiles, dim3(tiles), dim3(1024), 0, st, b, rows, b.tile_sums);
+    MP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_mp_scan_top, dim3(1), dim3(1024), 0, st, b, rows, b.tile_sums, tiles);
+    MP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_mp_scan_add, dim3(tiles), dim3(1024), 0, st, b, rows, b.tile_sums);
+    MP_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_mp_edges, dim3((unsigned)rows), dim3(kRowThreads), 0, st, b, S, L, W, f0,
                      nf, nvalid, M.rc, cap);
   MP_HIP(hipGetLastError());

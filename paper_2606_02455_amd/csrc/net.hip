@@ -161,7 +161,10 @@ __global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_f32(SysDev S, ListDe
   const bool in = i0 < S.n;
   const int i = in ? i0 : S.n - 1;
   const int r = S.atom_rep[i];
-  const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0;
+  // frames past the skin or after a rejection already found are not
+  // drafted: a block none of whose atoms has a valid frame does nothing
+  const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0 && k <= W.rej[r];
+  if (!__syncthreads_or(ok ? 1 : 0)) return;
   const int B = P.nb, Din = P.ns * B;
   const size_t N = (size_t)S.n;
   load_weights(P, L, t, NET_ITHREADS);
@@ -203,7 +206,10 @@ __global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_bf16(SysDev S, ListD
   const bool in = i0 < S.n;
   const int i = in ? i0 : S.n - 1;
   const int r = S.atom_rep[i];
-  const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0;
+  // frames past the skin or after a rejection already found are not
+  // drafted: a block none of whose atoms has a valid frame does nothing
+  const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0 && k <= W.rej[r];
+  if (!__syncthreads_or(ok ? 1 : 0)) return;
   const int B = P.nb, Din = P.ns * B;
   const size_t N = (size_t)S.n;
   const int li = t % 16, kq = (t % 64) / 16;
@@ -329,7 +335,10 @@ __global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_fp8(SysDev S, ListDe
   const bool in = i0 < S.n;
   const int i = in ? i0 : S.n - 1;
   const int r = S.atom_rep[i];
-  const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0;
+  // frames past the skin or after a rejection already found are not
+  // drafted: a block none of whose atoms has a valid frame does nothing
+  const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0 && k <= W.rej[r];
+  if (!__syncthreads_or(ok ? 1 : 0)) return;
   const int B = P.nb, Din = P.ns * B;
   const size_t N = (size_t)S.n;
   const int li = t % 16, kq = (t % 64) / 16;
