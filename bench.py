@@ -26,22 +26,26 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 EC_MODES = {"off": 0, "on": 1, "linear": 2}
 COPY_BYTES = 256 << 20  # calibration copy: 256 MiB read + 256 MiB written
-ACCEPT_SAMPLE_WINDOWS = 400  # untimed windows behind the reported acceptance (c1, c2)
+ACCEPT_SAMPLE_WINDOWS = 400  # default untimed windows behind the reported acceptance (c1, c2)
 # binary32 vector peak without packed instructions: 256 CUs x 2.4 GHz x 64
 # lanes x 2 (a fused multiply-add counts two)
 VALU_PEAK_TFLOPS = 256 * 2.4e9 * 64 * 2 / 1e12
 LJ_PAIR_FLOPS = 31  # per directed in-cutoff pair and frame (separation, r^2, r^-6 terms, force, energy)
 VERIFY_SOURCES = ["paper_2606_02455_amd/csrc/lsd_kernels.hip",
                   "paper_2606_02455_amd/csrc/lsd_device.h"]
+# sources of the network-target verification (evaluation kernels and the
+# transport reduction)
+MPNN_SOURCES = VERIFY_SOURCES + ["paper_2606_02455_amd/csrc/mpnn.hip",
+                                 "paper_2606_02455_amd/csrc/mpnn.h"]
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def source_sha():
+def source_sha(sources=VERIFY_SOURCES):
     h = hashlib.sha256()
-    for f in VERIFY_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -92,6 +96,25 @@ def read_profile_avg_us(config_name, kernel, skin):
     if head.get("source_sha") != source_sha() or head.get("lsd_skin") != repr(float(skin)):
         return None
     return avg
+
+
+def read_profile_keys(name, sources, skin):
+    """Key = value lines (commented or not) of a committed rocprofv3 summary
+    under profiles/, if it was taken on the current source of the kernels it
+    covers and with the same list skin; else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    keys = {}
+    for line in open(path):
+        t = line.strip().lstrip("#").strip()
+        if "=" in t and not t.startswith("cd "):
+            k, v = t.split("=", 1)
+            if " " not in k.strip():
+                keys[k.strip()] = v.strip()
+    if keys.get("source_sha") != source_sha(sources) or keys.get("lsd_skin") != repr(float(skin)):
+        return None
+    return keys
 
 
 def in_cutoff_pairs(sysg, rc):
@@ -398,6 +421,13 @@ def run_c3(args, lsd, W, torch):
     status = g.status() | plain.status()
     if status:
         raise RuntimeError(f"device status {status}: neighbour capacity overflow")
+    # a plain copy of known size: the reference that scales the FETCH_SIZE /
+    # WRITE_SIZE counters of rocprofv3 (profiles/)
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
     pairs = in_cutoff_pairs(g, float(target["rc"]))
     # replica-frames per launch (one launch per window), as whole-system
     # frames
@@ -406,6 +436,11 @@ def run_c3(args, lsd, W, torch):
     avg_s = ver_ms / max(ver_n, 1) * 1e-3
     achieved = flops / avg_s / 1e12
     peak = 157.3
+    # the committed rocprofv3 summaries of this configuration: kernel time of
+    # the evaluation per window, its matrix-core counters and HBM traffic
+    trace = read_profile_keys(f"mpnn_{args.config}_kernel_trace.txt", MPNN_SOURCES, lsd_skin) or {}
+    traffic = read_profile_keys(f"mpnn_{args.config}_traffic.txt", MPNN_SOURCES, lsd_skin) or {}
+    prof_us = float(trace["verify_kernel_us_per_window"]) if "verify_kernel_us_per_window" in trace else None
     value, plain_rate = committed / t_lsd, plain_steps / t_plain
     dt_fs = w.dt
     cpu = None
@@ -445,8 +480,16 @@ def run_c3(args, lsd, W, torch):
         "net_precision": args.net_precision if args.draft == "net" else None,
         "other_precision": other,
         "roofline": dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                         frac=round(achieved / peak, 5), traffic=None,
+                         frac=round(achieved / peak, 5),
+                         traffic=(float(traffic["hbm_bytes_per_window"])
+                                  if "hbm_bytes_per_window" in traffic else None),
                          kernel="message-passing target evaluation (all frames of a window)",
+                         timing=("HIP events around each window's verification on its stream: "
+                                 "the evaluation kernels and the transport reduction with the "
+                                 "gaps between their launches"),
+                         profile_avg_us=prof_us,
+                         frac_at_profile_us=(round(flops / (prof_us * 1e-6) / 1e12 / peak, 5)
+                                             if prof_us else None),
                          launch_shape=dict(zip(("filter_blocks", "chain_rows"),
                                                lsd.LSDSystem.NET_SHAPES[shape])),
                          autotune_us={f"{a}x{b}": round(v, 1) for (a, b), v in shape_us.items()},
@@ -494,6 +537,8 @@ def main():
     ap.add_argument("--pipeline", type=int, default=0,
                     help="pipelined LSD windows: verify every group of this many drafted frames on "
                          "a second stream while drafting continues (0: synchronous windows)")
+    ap.add_argument("--accept-windows", type=int, default=ACCEPT_SAMPLE_WINDOWS,
+                    help="c1, c2: untimed windows behind the reported acceptance")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ec", choices=["auto", "on", "off", "linear"], default="auto",
@@ -586,10 +631,13 @@ def main():
     # --- acceptance over a fixed sample of windows (untimed), so that the
     # reported rate does not depend on --steps
     lsds.reset_counters()
-    lsds.run_windows(ACCEPT_SAMPLE_WINDOWS, K)
+    for done in range(0, args.accept_windows, 100):
+        lsds.run_windows(min(100, args.accept_windows - done), K)
+        torch.cuda.synchronize()
+        log(f"acceptance sample: {min(done + 100, args.accept_windows)} windows")
     an = lsds.counters()[0]
     acc_committed, acc_rejections, acc_frames = int(an[1]), int(an[2]), int(an[3])
-    log(f"acceptance sample: {ACCEPT_SAMPLE_WINDOWS} windows, {acc_committed} steps, "
+    log(f"acceptance sample: {args.accept_windows} windows, {acc_committed} steps, "
         f"{acc_rejections} rejections")
 
     # --- plain target Langevin, same kernels, same number of windows
@@ -672,9 +720,9 @@ def main():
             "error_correction": args.ec,
         },
         "acceptance": round(1.0 - acc_rejections / max(acc_committed, 1), 5),
-        "acceptance_sample": {"windows": ACCEPT_SAMPLE_WINDOWS, "committed": acc_committed,
+        "acceptance_sample": {"windows": args.accept_windows, "committed": acc_committed,
                               "rejections": acc_rejections,
-                              "K_eff": round(acc_frames / ACCEPT_SAMPLE_WINDOWS, 3)},
+                              "K_eff": round(acc_frames / max(args.accept_windows, 1), 3)},
         "acceptance_timed": round(1.0 - rejections / max(committed, 1), 5),
         "K": K,
         "K_eff": round(frames / max(windows, 1), 3),

@@ -28,6 +28,16 @@
 #define LSD_NET_MAX_BASIS 16  // radial functions (edge coefficients per atom, v stride)
 #define LSD_NET_MAX_DESC 64   // species x radial functions of the descriptor
 #define LSD_NET_MAX_SPECIES 4
+#define LSD_NET_MAX_TYPES (LSD_NET_MAX_SPECIES * (LSD_NET_MAX_SPECIES + 1) / 2)
+// drafting with the learned draft: lanes per atom and blocks per tile of the
+// force loop (a block holds LSD_TILE / LSD_NET_SUB atoms), so that the
+// latency-bound loop of a small system spreads over many compute units
+#ifndef LSD_NET_LPA
+#define LSD_NET_LPA 16
+#endif
+#ifndef LSD_NET_SUB
+#define LSD_NET_SUB 16
+#endif
 
 // status word bits
 #define LSD_STATUS_NBR_TARGET 1
@@ -161,6 +171,29 @@ struct TileDev {
   const int* rep;     // [T] replica
   const int* rep_tile_off;  // [R+1]
 };
+
+// Tile t: first atom, atoms, replica, and whether it is its replica's first
+// tile.  A single system's tiles are consecutive runs of LSD_TILE atoms and
+// need no loads (their table holds the same values).
+struct TileInfo {
+  int start, count, rep;
+  bool first;
+};
+__device__ __forceinline__ TileInfo tile_info(int n, int R, const TileDev& Tl, int t) {
+  TileInfo T;
+  if (R == 1) {
+    T.start = t * LSD_TILE;
+    T.count = min(LSD_TILE, n - T.start);
+    T.rep = 0;
+    T.first = t == 0;
+  } else {
+    T.start = Tl.start[t];
+    T.count = Tl.count[t];
+    T.rep = Tl.rep[t];
+    T.first = t == Tl.rep_tile_off[T.rep];
+  }
+  return T;
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11) and the step-keyed stream
@@ -441,7 +474,8 @@ __device__ __forceinline__ void image_shifts(int code, float Lf, float sj[3], fl
 // List entries of one lane whose loads are issued together in the draft-side
 // force loops: the row entries, then the neighbour positions and species,
 // so that the gathers of several entries are in flight at once.  Entries are
-// still added in the lane's order.
+// still added in the lane's order; NL lanes share a row (lane `sub` takes
+// entries sub, sub + NL, ...).
 #ifndef LSD_GATHER
 #define LSD_GATHER 4
 #endif
@@ -450,40 +484,50 @@ struct Gathered {
   int code[LSD_GATHER], j[LSD_GATHER], sp[LSD_GATHER];
   bool ok[LSD_GATHER];
 };
-__device__ __forceinline__ void gather_entries(const uint32_t* __restrict__ row, int cnt, int m0,
-                                               const float4* __restrict__ X,
+// The entry words are read for every slot below the row width (words past
+// the count are read but not used), so the first group's loads need not wait
+// for the count; an unused slot gathers atom 0.
+template <int NL = LSD_LPA>
+__device__ __forceinline__ void gather_entries(const uint32_t* __restrict__ row, int width,
+                                               int cnt, int m0, const float4* __restrict__ X,
                                                const int* __restrict__ species, Gathered& g) {
   uint32_t ent[LSD_GATHER];
 #pragma unroll
   for (int u = 0; u < LSD_GATHER; ++u) {
-    const int m = m0 + u * LSD_LPA;
+    const int m = m0 + u * NL;
     g.ok[u] = m < cnt;
-    ent[u] = row[g.ok[u] ? m : m0];
+    ent[u] = row[m < width ? m : 0];
   }
 #pragma unroll
   for (int u = 0; u < LSD_GATHER; ++u) {
-    g.j[u] = (int)(ent[u] >> 5);
+    g.j[u] = g.ok[u] ? (int)(ent[u] >> 5) : 0;
     g.code[u] = (int)(ent[u] & 31u);
     g.x[u] = X[g.j[u]];
     g.sp[u] = species ? species[g.j[u]] : 0;
   }
 }
 
-// sum over the LSD_LPA lanes of an atom by a fixed butterfly
-__device__ __forceinline__ float lpa_sum(float v) {
+// sum over the NL lanes of an atom (aligned groups of NL lanes) by a fixed
+// butterfly
+template <int NL>
+__device__ __forceinline__ float lanes_sum(float v) {
 #pragma unroll
-  for (int o = 1; o < LSD_LPA; o <<= 1) v += __shfl_xor(v, o, 64);
+  for (int o = 1; o < NL; o <<= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+__device__ __forceinline__ float lpa_sum(float v) { return lanes_sum<LSD_LPA>(v); }
 
 // Learned-draft force on atom i (replica r) at frame positions X from its
 // list row: F_i = - sum_j f_ij d / r with the edge coefficients P.v of this
-// frame; the LSD_LPA lanes of the atom split the row as in every force loop
-// and the result is their fixed butterfly sum.
+// frame and the pair-type coefficients ctab [T][B] (the parameters' c
+// block, or a copy of it in LDS); the NL lanes of the atom split the row as
+// in every force loop and the result is their fixed butterfly sum.
+template <int NL = LSD_LPA>
 __device__ __forceinline__ void net_force(const PotDev& P, const SysDev& S,
                                           const float4* __restrict__ X,
-                                          const uint32_t* __restrict__ row, int cnt, int i, int r,
-                                          int sub, float& fx, float& fy, float& fz) {
+                                          const uint32_t* __restrict__ row, int width, int cnt,
+                                          int i, int r, int sub, const float* __restrict__ ctab,
+                                          float& fx, float& fy, float& fz) {
   fx = fy = fz = 0.0f;
   const float Lf = (float)S.box[r];
   const float4 xi = X[i];
@@ -491,10 +535,11 @@ __device__ __forceinline__ void net_force(const PotDev& P, const SysDev& S,
   const int B = P.nb;
   float vi[LSD_NET_MAX_BASIS];
   net_load_v(P.v + (size_t)i * LSD_NET_MAX_BASIS, B, vi);
-  const float* cw = P.w + net_off_c(P.ns, B);
-  for (int m0 = sub; m0 < cnt; m0 += LSD_GATHER * LSD_LPA) {
+  // the first group of entries is gathered whatever the count (its loads
+  // overlap those of the count), the rest while entries remain
+  for (int m0 = sub, first = 1; first || m0 < cnt; m0 += LSD_GATHER * NL, first = 0) {
     Gathered gt;
-    gather_entries(row, cnt, m0, X, S.species, gt);
+    gather_entries<NL>(row, width, cnt, m0, X, S.species, gt);
 #pragma unroll
     for (int u = 0; u < LSD_GATHER; ++u) {
       if (!gt.ok[u]) break;
@@ -510,16 +555,16 @@ __device__ __forceinline__ void net_force(const PotDev& P, const SysDev& S,
       float eb[LSD_NET_MAX_BASIS], vj[LSD_NET_MAX_BASIS];
       net_radial(P.pi_rc, rr, inv_r, B, eb);
       net_load_v(P.v + (size_t)gt.j[u] * LSD_NET_MAX_BASIS, B, vj);
-      const float* ct = cw + pair_type(spi, gt.sp[u], P.ns) * B;
+      const float* ct = ctab + pair_type(spi, gt.sp[u], P.ns) * B;
       const float g = net_pair_coef(eb, ct, vi, vj, B) * inv_r;
       fx -= g * dx;
       fy -= g * dy;
       fz -= g * dz;
     }
   }
-  fx = lpa_sum(fx);
-  fy = lpa_sum(fy);
-  fz = lpa_sum(fz);
+  fx = lanes_sum<NL>(fx);
+  fy = lanes_sum<NL>(fy);
+  fz = lanes_sum<NL>(fz);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

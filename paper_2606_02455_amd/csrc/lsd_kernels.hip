@@ -340,15 +340,21 @@ __device__ __forceinline__ void tether_force(const PotDev& P, const SysDev& S, f
   e = 0.5f * P.kspring * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
 }
 
-// Force of potential P on atom i at frame positions X.  The LSD_LPA lanes of
-// an atom share the list row: lane `sub` sums the entries m = sub, sub + LPA,
-// ... in order, and the partial sums are combined by the fixed butterfly of
-// lpa_sum, so every kernel that uses this pattern obtains bit-identical
-// forces for identical positions and lists.
+// Force of potential P on atom i at frame positions X.  The NL lanes of an
+// atom share the list row: lane `sub` sums the entries m = sub, sub + NL, ...
+// in order, and the partial sums are combined by a fixed butterfly, so every
+// kernel that uses this pattern with the same NL obtains bit-identical forces
+// for identical positions and lists.  NL is LSD_LPA everywhere but in the
+// drafting kernel of the learned draft; ctab: that draft's pair-type
+// coefficients (null: read from its parameters).
+// width: the list's row width (the first group of entries is read before
+// the count is known).
+template <int NL = LSD_LPA>
 __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
                                           const float4* __restrict__ X,
-                                          const uint32_t* __restrict__ row, int cnt, int i, int r,
-                                          int sub, float& fx, float& fy, float& fz, float& e) {
+                                          const uint32_t* __restrict__ row, int width, int cnt,
+                                          int i, int r, int sub, float& fx, float& fy, float& fz,
+                                          float& e, const float* __restrict__ ctab = nullptr) {
   fx = fy = fz = e = 0.0f;
   const double L = S.box[r];
   const float Lf = (float)L;
@@ -356,9 +362,9 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
   if (P.kind == LSD_POT_LJ) {
     // LSD_GATHER entries per iteration (gathers issued together), added in
     // order
-    for (int m0 = sub; m0 < cnt; m0 += LSD_GATHER * LSD_LPA) {
+    for (int m0 = sub, first = 1; first || m0 < cnt; m0 += LSD_GATHER * NL, first = 0) {
       Gathered gt;
-      gather_entries(row, cnt, m0, X, nullptr, gt);
+      gather_entries<NL>(row, width, cnt, m0, X, nullptr, gt);
 #pragma unroll
       for (int u = 0; u < LSD_GATHER; ++u) {
         if (!gt.ok[u]) break;
@@ -367,15 +373,15 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
         lj_pair(P, xi, gt.x[u], sj, si, gt.code[u], L, fx, fy, fz, e);
       }
     }
-    fx = lpa_sum(fx);
-    fy = lpa_sum(fy);
-    fz = lpa_sum(fz);
-    e = lpa_sum(e);
+    fx = lanes_sum<NL>(fx);
+    fy = lanes_sum<NL>(fy);
+    fz = lanes_sum<NL>(fz);
+    e = lanes_sum<NL>(e);
   } else if (P.kind == LSD_POT_PAIR) {
     const int spi = S.species ? S.species[i] : 0;
-    for (int m0 = sub; m0 < cnt; m0 += LSD_GATHER * LSD_LPA) {
+    for (int m0 = sub, first = 1; first || m0 < cnt; m0 += LSD_GATHER * NL, first = 0) {
       Gathered gt;
-      gather_entries(row, cnt, m0, X, S.species, gt);
+      gather_entries<NL>(row, width, cnt, m0, X, S.species, gt);
 #pragma unroll
       for (int u = 0; u < LSD_GATHER; ++u) {
         if (!gt.ok[u]) break;
@@ -384,11 +390,12 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
         pair_draft_force(P, xi, gt.x[u], sj, si, spi, gt.sp[u], fx, fy, fz);
       }
     }
-    fx = lpa_sum(fx);
-    fy = lpa_sum(fy);
-    fz = lpa_sum(fz);
+    fx = lanes_sum<NL>(fx);
+    fy = lanes_sum<NL>(fy);
+    fz = lanes_sum<NL>(fz);
   } else if (P.kind == LSD_POT_NET) {
-    net_force(P, S, X, row, cnt, i, r, sub, fx, fy, fz);
+    net_force<NL>(P, S, X, row, width, cnt, i, r, sub,
+                  ctab ? ctab : P.w + net_off_c(P.ns, P.nb), fx, fy, fz);
   } else if (P.kind == LSD_POT_HARMONIC) {
     tether_force(P, S, xi, i, Lf, fx, fy, fz, e);
   }
@@ -402,34 +409,81 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
 // One draft_step (Alg. 2) for frame k: draft forces at the midpoint, the
 // (BOB) Gaussian draw of Eq. bob, then the two position half steps that end
 // this step and start the next one; flags the next frame invalid when an
-// atom left the skin of the lists.  Block = one tile of up to 64 atoms of
-// one replica (LSD_LPA lanes per atom), so the validity test of the frame is
-// uniform over the block.
-__global__ __launch_bounds__(LSD_VTHREADS) void k_draft(SysDev S, ListDev Lst, WinDev W,
-                                                        TileDev Tl, PotDev P, int k,
-                                                        int use_target_list, int forces_given) {
-  const int tile = blockIdx.x;
-  const int r = Tl.rep[tile];
+// atom left the skin of the lists.  SUB blocks share one tile of up to 64
+// atoms of one replica (NL lanes per atom), so the validity test of the
+// frame is uniform over each block.
+static_assert(LSD_TILE % LSD_NET_SUB == 0 && LSD_NET_LPA <= 64 &&
+                  (LSD_NET_LPA & (LSD_NET_LPA - 1)) == 0 &&
+                  LSD_TILE / LSD_NET_SUB * LSD_NET_LPA <= 1024,
+              "learned-draft launch: whole atoms per block, power-of-two lanes per atom");
+template <int NL, int SUB>
+__global__ __launch_bounds__(LSD_TILE / SUB * NL) void k_draft(SysDev S, ListDev Lst, WinDev W,
+                                                               TileDev Tl, PotDev P, int k,
+                                                               int use_target_list,
+                                                               int forces_given) {
+  constexpr int APB = LSD_TILE / SUB;  // atoms per block
+  __shared__ float s_ct[LSD_NET_MAX_TYPES * LSD_NET_MAX_BASIS];
+  const int tile = blockIdx.x / SUB, part = blockIdx.x % SUB;
+  const TileInfo T = tile_info(S.n, S.R, Tl, tile);
+  const int r = T.rep;
   int* inv = W.invalid + (size_t)r * S.kmax;
   // a frame after a rejection that the verification of earlier frames has
   // already found (pipelined windows) is discarded like one past the skin;
   // a block that sees it marks the frame, so that no part of it is verified
   const bool after_reject = W.rej[r] < k;
-  if (after_reject && threadIdx.x == 0 && inv[k] == 0) atomicOr(&inv[k], 1);
-  if (after_reject || inv[k]) {
+  const int inv_k = inv[k];
+  // the atom's list row and position are requested before the test of the
+  // frame, so that their latency overlaps it
+  const int a = part * APB + threadIdx.x / NL, sub = threadIdx.x % NL;
+  const bool in = a < T.count;
+  const int i = T.start + (in ? a : 0);
+  const int width = use_target_list ? Lst.mt : Lst.md;
+  const uint32_t* row = (use_target_list ? Lst.nbr_t : Lst.nbr_d) + (size_t)i * width;
+  const int cnt = forces_given ? 0 : (use_target_list ? Lst.cnt_t[i] : Lst.cnt_d[i]);
+  // the learned draft's pair-type coefficients, read by every entry: staged
+  // in LDS (requested here as well)
+  constexpr int CT_PER = (LSD_NET_MAX_TYPES * LSD_NET_MAX_BASIS + APB * NL - 1) / (APB * NL);
+  const bool net = P.kind == LSD_POT_NET && !forces_given;
+  const int nct = net ? P.ns * (P.ns + 1) / 2 * P.nb : 0;
+  float ctv[CT_PER];
+#pragma unroll
+  for (int q = 0; q < CT_PER; ++q) {
+    const int t = threadIdx.x + q * APB * NL;
+    ctv[q] = t < nct ? P.w[net_off_c(P.ns, P.nb) + t] : 0.0f;
+  }
+  if (after_reject && threadIdx.x == 0 && inv_k == 0) atomicOr(&inv[k], 1);
+  if (after_reject || inv_k) {
     // frames from K_eff on are discarded: no work, and the next frame is
     // invalid as well (one thread per replica records it)
-    if (threadIdx.x == 0 && tile == Tl.rep_tile_off[r] && k + 1 < W.K) inv[k + 1] = 1;
+    if (threadIdx.x == 0 && T.first && part == 0 && k + 1 < W.K) inv[k + 1] = 1;
     return;
   }
   // frame k is valid for this replica: the verification covers it
-  if (threadIdx.x == 0 && tile == Tl.rep_tile_off[r]) atomicMax(W.nvalid, k + 1);
-  const int a = threadIdx.x / LSD_LPA, sub = threadIdx.x % LSD_LPA;
-  const bool in = a < Tl.count[tile];
-  const int i = Tl.start[tile] + (in ? a : 0);
+  if (threadIdx.x == 0 && T.first && part == 0) atomicMax(W.nvalid, k + 1);
+  if (net) {
+#pragma unroll
+    for (int q = 0; q < CT_PER; ++q) {
+      const int t = threadIdx.x + q * APB * NL;
+      if (t < nct) s_ct[t] = ctv[q];
+    }
+    __syncthreads();
+  }
   const int sp = S.species ? S.species[i] : 0;
   const size_t N = (size_t)S.n;
   const float4* X = W.qmid + (size_t)k * N;
+  // inputs of the step after the force, requested before the force loop
+  const bool lead = in && sub == 0;
+  float pk[3] = {0.0f, 0.0f, 0.0f}, fmc[3] = {0.0f, 0.0f, 0.0f};
+  float4 x0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (lead) {
+    const float* pkp = W.p + (size_t)k * 3 * N;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      pk[d] = pkp[d * N + i];
+      fmc[d] = draft_mean_force(W, r, d * N + i, k, 0.0f);  // error-correction term
+    }
+    x0 = Lst.qref[i];
+  }
   float F[3], e;
   if (forces_given) {
     // forces of this frame already in the window (batched network pass)
@@ -437,12 +491,10 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_draft(SysDev S, ListDev Lst, W
     F[0] = fk0[i];
     F[1] = fk0[N + i];
     F[2] = fk0[2 * N + i];
-  } else if (use_target_list) {
-    pot_force(P, S, X, Lst.nbr_t + (size_t)i * Lst.mt, Lst.cnt_t[i], i, r, sub, F[0], F[1], F[2], e);
   } else {
-    pot_force(P, S, X, Lst.nbr_d + (size_t)i * Lst.md, Lst.cnt_d[i], i, r, sub, F[0], F[1], F[2], e);
+    pot_force<NL>(P, S, X, row, width, cnt, i, r, sub, F[0], F[1], F[2], e, s_ct);
   }
-  if (!in || sub != 0) return;
+  if (!lead) return;
 
   double xi[3];
   if (S.replay_xi) {
@@ -452,15 +504,14 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_draft(SysDev S, ListDev Lst, W
     stream_normals3(S.seed, (uint32_t)r, (uint64_t)(S.step[r] + k + 1),
                     (uint32_t)(i - S.rep_off[r]), xi);
   }
-  const float* pk = W.p + (size_t)k * 3 * N;
   float* pk1 = W.p + (size_t)(k + 1) * 3 * N;
   float* fk = W.fd + (size_t)k * 3 * N;
   const double sg = S.sig[sp];
   float pn[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const float Fm = draft_mean_force(W, r, d * N + i, k, F[d]);
-    double mu = bob_mean(S.a, S.c1fu, pk[d * N + i], Fm);
+    const float Fm = W.ec ? F[d] + fmc[d] : F[d];
+    double mu = bob_mean(S.a, S.c1fu, pk[d], Fm);
     pn[d] = (float)fma(sg, xi[d], mu);
     fk[d * N + i] = F[d];
     pk1[d * N + i] = pn[d];
@@ -478,7 +529,6 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_draft(SysDev S, ListDev Lst, W
     // frames stay continuous with frame 0, so frame 0's image deltas apply
     W.qmid[(size_t)(k + 1) * N + i] = make_float4(xn[0], xn[1], xn[2], x.w);
     // displacement from the list positions
-    const float4 x0 = Lst.qref[i];
     const float dx = xn[0] - x0.x, dy = xn[1] - x0.y, dz = xn[2] - x0.z;
     const float d2 = dx * dx + dy * dy + dz * dz;
     if (d2 > S.half_skin2 && inv[k + 1] == 0) atomicOr(&inv[k + 1], 1);
@@ -952,8 +1002,8 @@ __global__ __launch_bounds__(256) void k_frame0_forces(SysDev S, ListDev Lst, Wi
   const bool in = i0 < S.n;
   const int i = in ? i0 : S.n - 1;
   float F[3], e;
-  pot_force(P, S, W.qmid, Lst.nbr_t + (size_t)i * Lst.mt, Lst.cnt_t[i], i, S.atom_rep[i], sub,
-            F[0], F[1], F[2], e);
+  pot_force(P, S, W.qmid, Lst.nbr_t + (size_t)i * Lst.mt, Lst.mt, Lst.cnt_t[i], i,
+            S.atom_rep[i], sub, F[0], F[1], F[2], e);
   if (!in || sub != 0) return;
   const size_t N = (size_t)S.n;
   W.ft[i] = F[0];
@@ -1065,8 +1115,16 @@ hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W
 hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                         const PotDev& P, int k, int use_target_list, hipStream_t st,
                         int forces_given) {
-  hipLaunchKernelGGL(k_draft, dim3(S.n_tiles), dim3(LSD_VTHREADS), 0, st, S, L, W, T, P, k,
-                     use_target_list, forces_given);
+  if (P.kind == LSD_POT_NET && !forces_given) {
+    // the learned draft: a small system's latency-bound loop over more
+    // lanes per atom and more compute units
+    hipLaunchKernelGGL((k_draft<LSD_NET_LPA, LSD_NET_SUB>), dim3(S.n_tiles * LSD_NET_SUB),
+                       dim3(LSD_TILE / LSD_NET_SUB * LSD_NET_LPA), 0, st, S, L, W, T, P, k,
+                       use_target_list, forces_given);
+  } else {
+    hipLaunchKernelGGL((k_draft<LSD_LPA, 1>), dim3(S.n_tiles), dim3(LSD_VTHREADS), 0, st, S, L, W,
+                       T, P, k, use_target_list, forces_given);
+  }
   return hipGetLastError();
 }
 

@@ -32,6 +32,12 @@ static_assert(LSD_LPA >= 4 && LSD_NET_HIDDEN % LSD_LPA == 0,
 #define NET_DPL (LSD_NET_MAX_DESC / LSD_LPA) // descriptor slots per lane
 #define NET_IROWS 16                         // atoms per block of the drafting node pass
 #define NET_ITHREADS (NET_IROWS * LSD_LPA)
+// lanes per atom of the descriptor loop in the matrix-core node passes
+#ifndef NET_NODE_LPA
+#define NET_NODE_LPA 16
+#endif
+static_assert(NET_NODE_LPA >= 4 && NET_NODE_LPA <= 16 && (NET_NODE_LPA & (NET_NODE_LPA - 1)) == 0,
+              "node pass: 16 atoms x a power-of-two number of lanes, at least one wave");
 
 namespace {
 
@@ -77,11 +83,12 @@ __device__ __forceinline__ void load_weights(const PotDev& P, NetLds& L, int t, 
 }
 
 // D[s][b] = sum over the row's entries j of species s within the cutoff of
-// e_b(r_ij), summed over the LSD_LPA lanes of the atom (all lanes hold it).
+// e_b(r_ij), summed over the NL lanes of the atom (all lanes hold it).
+template <int NL = LSD_LPA>
 __device__ __forceinline__ void net_descriptor(const PotDev& P, const SysDev& S,
                                                const float4* __restrict__ X,
-                                               const uint32_t* __restrict__ row, int cnt, int i,
-                                               int r, int sub,
+                                               const uint32_t* __restrict__ row, int width,
+                                               int cnt, int i, int r, int sub,
                                                float D[LSD_NET_MAX_SPECIES][LSD_NET_MAX_BASIS]) {
 #pragma unroll
   for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s)
@@ -90,9 +97,10 @@ __device__ __forceinline__ void net_descriptor(const PotDev& P, const SysDev& S,
   const float Lf = (float)S.box[r];
   const float4 xi = X[i];
   const int B = P.nb;
-  for (int m0 = sub; m0 < cnt; m0 += LSD_GATHER * LSD_LPA) {
+  // the first group of entries is gathered whatever the count
+  for (int m0 = sub, first = 1; first || m0 < cnt; m0 += LSD_GATHER * NL, first = 0) {
     Gathered gt;
-    gather_entries(row, cnt, m0, X, S.species, gt);
+    gather_entries<NL>(row, width, cnt, m0, X, S.species, gt);
 #pragma unroll
     for (int u = 0; u < LSD_GATHER; ++u) {
       if (!gt.ok[u]) break;
@@ -117,7 +125,7 @@ __device__ __forceinline__ void net_descriptor(const PotDev& P, const SysDev& S,
   for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s)
 #pragma unroll
     for (int b = 0; b < LSD_NET_MAX_BASIS; ++b)
-      if (s < P.ns && b < B) D[s][b] = lpa_sum(D[s][b]);
+      if (s < P.ns && b < B) D[s][b] = lanes_sum<NL>(D[s][b]);
 }
 
 // Binary32 dense layers for the hidden units sub*HPL .. of one atom: z of
@@ -160,17 +168,19 @@ __global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_f32(SysDev S, ListDe
   const int i0 = blockIdx.x * NET_IROWS + a;
   const bool in = i0 < S.n;
   const int i = in ? i0 : S.n - 1;
-  const int r = S.atom_rep[i];
+  const int r = S.R == 1 ? 0 : S.atom_rep[i];
   // frames past the skin or after a rejection already found are not
   // drafted: a block none of whose atoms has a valid frame does nothing
+  // (the atom's entry count is requested together with that test)
   const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0 && k <= W.rej[r];
+  const int cnt = Lst.cnt_d[i];
   if (!__syncthreads_or(ok ? 1 : 0)) return;
   const int B = P.nb, Din = P.ns * B;
   const size_t N = (size_t)S.n;
   load_weights(P, L, t, NET_ITHREADS);
   float D[LSD_NET_MAX_SPECIES][LSD_NET_MAX_BASIS];
-  net_descriptor(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md,
-                 ok ? Lst.cnt_d[i] : 0, i, r, sub, D);
+  net_descriptor(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md, Lst.md,
+                 ok ? cnt : 0, i, r, sub, D);
   const int sp = S.species ? S.species[i] : 0;
   if (sub == 0) {
 #pragma unroll
@@ -195,20 +205,23 @@ __global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_f32(SysDev S, ListDe
 // A[l % 16][4 (l / 16) + 0..3] and B[4 (l / 16) + 0..3][l % 16]; the result
 // D[4 (l / 16) + 0..3][l % 16].  Each lane loads its own B fragments of W1
 // and W2 from the parameters before the descriptor loop.
-__global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_bf16(SysDev S, ListDev Lst, WinDev W,
-                                                                 PotDev P, int k) {
+template <int NL>
+__global__ __launch_bounds__(NET_IROWS * NL) void k_net_nodes_bf16(SysDev S, ListDev Lst, WinDev W,
+                                                                  PotDev P, int k) {
   __shared__ float s_b1[LSD_NET_MAX_SPECIES][LSD_NET_HIDDEN];
   __shared__ unsigned short s_Db[NET_IROWS][LSD_NET_MAX_DESC];
   __shared__ unsigned short s_hb[NET_IROWS][LSD_NET_HIDDEN];
   __shared__ int s_sp[NET_IROWS], s_ok[NET_IROWS];
-  const int t = threadIdx.x, a = t / LSD_LPA, sub = t % LSD_LPA;
+  const int t = threadIdx.x, a = t / NL, sub = t % NL;
   const int i0 = blockIdx.x * NET_IROWS + a;
   const bool in = i0 < S.n;
   const int i = in ? i0 : S.n - 1;
-  const int r = S.atom_rep[i];
+  const int r = S.R == 1 ? 0 : S.atom_rep[i];
   // frames past the skin or after a rejection already found are not
   // drafted: a block none of whose atoms has a valid frame does nothing
+  // (the atom's entry count is requested together with that test)
   const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0 && k <= W.rej[r];
+  const int cnt = Lst.cnt_d[i];
   if (!__syncthreads_or(ok ? 1 : 0)) return;
   const int B = P.nb, Din = P.ns * B;
   const size_t N = (size_t)S.n;
@@ -236,14 +249,14 @@ __global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_bf16(SysDev S, ListD
   }
   {
     const float* b1 = P.w + net_off_b1(P.ns, B);
-    for (int idx = t; idx < LSD_NET_MAX_SPECIES * LSD_NET_HIDDEN; idx += NET_ITHREADS) {
+    for (int idx = t; idx < LSD_NET_MAX_SPECIES * LSD_NET_HIDDEN; idx += NET_IROWS * NL) {
       const int s = idx / LSD_NET_HIDDEN, h = idx % LSD_NET_HIDDEN;
       s_b1[s][h] = s < P.ns ? b1[s * LSD_NET_HIDDEN + h] : 0.0f;
     }
   }
   float D[LSD_NET_MAX_SPECIES][LSD_NET_MAX_BASIS];
-  net_descriptor(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md,
-                 ok ? Lst.cnt_d[i] : 0, i, r, sub, D);
+  net_descriptor<NL>(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md, Lst.md,
+                     ok ? cnt : 0, i, r, sub, D);
   if (sub == 0) {
     s_sp[a] = S.species ? S.species[i] : 0;
     s_ok[a] = ok ? 1 : 0;
@@ -324,20 +337,23 @@ __device__ __forceinline__ float wave_absmax(float v) {
 // D and h by the calibrated static scales.  16x16x32 operands: lane l holds
 // A[l % 16][8 (l / 16) + 0..7] and B[8 (l / 16) + 0..7][l % 16]; the result
 // D[4 (l / 16) + 0..3][l % 16].
-__global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_fp8(SysDev S, ListDev Lst, WinDev W,
-                                                                PotDev P, int k) {
+template <int NL>
+__global__ __launch_bounds__(NET_IROWS * NL) void k_net_nodes_fp8(SysDev S, ListDev Lst, WinDev W,
+                                                                 PotDev P, int k) {
   __shared__ float s_b1[LSD_NET_MAX_SPECIES][LSD_NET_HIDDEN];
   __shared__ __align__(8) unsigned char s_Dq[NET_IROWS][LSD_NET_MAX_DESC];
   __shared__ __align__(8) unsigned char s_hq[NET_IROWS][LSD_NET_HIDDEN];
   __shared__ int s_sp[NET_IROWS], s_ok[NET_IROWS];
-  const int t = threadIdx.x, a = t / LSD_LPA, sub = t % LSD_LPA;
+  const int t = threadIdx.x, a = t / NL, sub = t % NL;
   const int i0 = blockIdx.x * NET_IROWS + a;
   const bool in = i0 < S.n;
   const int i = in ? i0 : S.n - 1;
-  const int r = S.atom_rep[i];
+  const int r = S.R == 1 ? 0 : S.atom_rep[i];
   // frames past the skin or after a rejection already found are not
   // drafted: a block none of whose atoms has a valid frame does nothing
+  // (the atom's entry count is requested together with that test)
   const bool ok = in && W.invalid[(size_t)r * S.kmax + k] == 0 && k <= W.rej[r];
+  const int cnt = Lst.cnt_d[i];
   if (!__syncthreads_or(ok ? 1 : 0)) return;
   const int B = P.nb, Din = P.ns * B;
   const size_t N = (size_t)S.n;
@@ -378,14 +394,14 @@ __global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_fp8(SysDev S, ListDe
   }
   {
     const float* b1 = P.w + net_off_b1(P.ns, B);
-    for (int idx = t; idx < LSD_NET_MAX_SPECIES * LSD_NET_HIDDEN; idx += NET_ITHREADS) {
+    for (int idx = t; idx < LSD_NET_MAX_SPECIES * LSD_NET_HIDDEN; idx += NET_IROWS * NL) {
       const int s = idx / LSD_NET_HIDDEN, h = idx % LSD_NET_HIDDEN;
       s_b1[s][h] = s < P.ns ? b1[s * LSD_NET_HIDDEN + h] : 0.0f;
     }
   }
   float D[LSD_NET_MAX_SPECIES][LSD_NET_MAX_BASIS];
-  net_descriptor(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md,
-                 ok ? Lst.cnt_d[i] : 0, i, r, sub, D);
+  net_descriptor<NL>(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md, Lst.md,
+                     ok ? cnt : 0, i, r, sub, D);
   const float inv_sD = 1.0f / P.fp8_sD, inv_sh = 1.0f / P.fp8_sh;
   if (sub == 0) {
     s_sp[a] = S.species ? S.species[i] : 0;
@@ -449,7 +465,7 @@ __global__ __launch_bounds__(NET_THREADS) void k_nt_nodes(SysDev S, ListDev Lst,
   const size_t N = (size_t)S.n, fi = (size_t)f * N + i;
   load_weights(P, L, t, NET_THREADS);
   float D[LSD_NET_MAX_SPECIES][LSD_NET_MAX_BASIS];
-  net_descriptor(P, S, W.qmid + (size_t)f * N, Lst.nbr_t + (size_t)i * Lst.mt,
+  net_descriptor(P, S, W.qmid + (size_t)f * N, Lst.nbr_t + (size_t)i * Lst.mt, Lst.mt,
                  ok ? Lst.cnt_t[i] : 0, i, r, sub, D);
   const int sp = S.species ? S.species[i] : 0;
   if (sub == 0) {
@@ -493,8 +509,8 @@ __global__ __launch_bounds__(NET_THREADS) void k_nt_resid(SysDev S, ListDev Lst,
   PotDev Q = P;
   Q.v = T.v + (size_t)f * N * LSD_NET_MAX_BASIS;
   float F[3];
-  net_force(Q, S, W.qmid + (size_t)f * N, Lst.nbr_t + (size_t)i * Lst.mt, ok ? Lst.cnt_t[i] : 0,
-            i, r, sub, F[0], F[1], F[2]);
+  net_force(Q, S, W.qmid + (size_t)f * N, Lst.nbr_t + (size_t)i * Lst.mt, Lst.mt,
+            ok ? Lst.cnt_t[i] : 0, i, r, sub, P.w + net_off_c(P.ns, P.nb), F[0], F[1], F[2]);
   if (diff) {
     if (sub == 0 && in) {
 #pragma unroll
@@ -814,10 +830,13 @@ NetTrainDev net_train_bind(char* base, int K, int N) {
 
 hipError_t launch_net_nodes(const SysDev& S, const ListDev& L, const WinDev& W, const PotDev& P,
                             int k, hipStream_t st) {
-  const dim3 grid((S.n + NET_IROWS - 1) / NET_IROWS), block(NET_ITHREADS);
-  if (P.prec == 2) hipLaunchKernelGGL(k_net_nodes_fp8, grid, block, 0, st, S, L, W, P, k);
-  else if (P.prec == 1) hipLaunchKernelGGL(k_net_nodes_bf16, grid, block, 0, st, S, L, W, P, k);
-  else hipLaunchKernelGGL(k_net_nodes_f32, grid, block, 0, st, S, L, W, P, k);
+  const dim3 grid((S.n + NET_IROWS - 1) / NET_IROWS), wide(NET_IROWS * NET_NODE_LPA);
+  if (P.prec == 2)
+    hipLaunchKernelGGL(k_net_nodes_fp8<NET_NODE_LPA>, grid, wide, 0, st, S, L, W, P, k);
+  else if (P.prec == 1)
+    hipLaunchKernelGGL(k_net_nodes_bf16<NET_NODE_LPA>, grid, wide, 0, st, S, L, W, P, k);
+  else
+    hipLaunchKernelGGL(k_net_nodes_f32, grid, dim3(NET_ITHREADS), 0, st, S, L, W, P, k);
   return hipGetLastError();
 }
 
