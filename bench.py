@@ -87,8 +87,9 @@ def read_profile_avg_us(config_name, kernel, skin):
         if t.startswith("#") and "=" in t:
             k, v = t[1:].split("=", 1)
             head[k.strip()] = v.strip()
-        elif t.startswith(kernel + " ") or t.startswith(f"void {kernel}("):
-            parts = t.replace(kernel, "", 1).split()
+        elif (t.startswith(kernel + " ") or t.startswith(f"void {kernel} ")
+              or t.startswith(f"void {kernel}(")):
+            parts = t.replace("void ", "", 1).replace(kernel, "", 1).split()
             try:
                 avg = float(parts[1])
             except (IndexError, ValueError):
@@ -483,6 +484,8 @@ def run_c3(args, lsd, W, torch):
                          frac=round(achieved / peak, 5),
                          traffic=(float(traffic["hbm_bytes_per_window"])
                                   if "hbm_bytes_per_window" in traffic else None),
+                         traffic_frames_per_window=(float(traffic["frames_per_window"])
+                                                    if "frames_per_window" in traffic else None),
                          kernel="message-passing target evaluation (all frames of a window)",
                          timing=("HIP events around each window's verification on its stream: "
                                  "the evaluation kernels and the transport reduction with the "
