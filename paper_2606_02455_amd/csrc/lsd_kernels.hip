@@ -586,9 +586,31 @@ __device__ __forceinline__ void verify_item(const SysDev& S, const ListDev& Lst,
                                             double (*s_red)[FW][3]) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int a = t / LSD_LPA, sub = t % LSD_LPA;
-  const int start = Tl.start[tile], count = Tl.count[tile], r = Tl.rep[tile];
+  const TileInfo T = tile_info(S.n, S.R, Tl, tile);
+  const int start = T.start, count = T.count, r = T.rep;
   const int* inv = W.invalid + (size_t)r * S.kmax;
   const int rej = W.rej[r];
+  const double L = S.box[r];
+  const size_t N = (size_t)S.n;
+  const bool lj = P.kind == LSD_POT_LJ;
+  // the atom's positions, entry count and first group of entry words are
+  // requested together with the frame flags (for a frame that is not
+  // verified they go unused; every slot below the row width is in the list,
+  // and a word past the count is not used)
+  const bool active = a < count;
+  const int i = start + (active ? a : 0);
+  const uint32_t* row = Lst.nbr_t + (size_t)i * Lst.mt;
+  const int cnt = (active && lj) ? Lst.cnt_t[i] : 0;
+  uint32_t e0[LSD_VGATHER];
+#pragma unroll
+  for (int u = 0; u < LSD_VGATHER; ++u) {
+    const int m = sub + u * LSD_LPA;
+    e0[u] = row[m < Lst.mt ? m : 0];
+  }
+  float4 xi[FW];
+#pragma unroll
+  for (int f = 0; f < FW; ++f)
+    xi[f] = W.qmid[(size_t)(f0 + f < fend ? f0 + f : f0) * N + i];
   bool valid[FW];
   bool any = false;
 #pragma unroll
@@ -598,34 +620,38 @@ __device__ __forceinline__ void verify_item(const SysDev& S, const ListDev& Lst,
     any = any || valid[f];
   }
   if (!any) return;  // uniform over the block
-  const double L = S.box[r];
   const float Lf = (float)L;
-  const size_t N = (size_t)S.n;
-  const bool lj = P.kind == LSD_POT_LJ;
   if (t < 27) image_shifts(t, Lf, &s_shift[t][0], &s_shift[t][3]);
   __syncthreads();
 
-  const bool active = a < count;
-  const int i = start + (active ? a : 0);
-  const int cnt = (active && lj) ? Lst.cnt_t[i] : 0;
   float fx[FW], fy[FW], fz[FW], en[FW];
-  float4 xi[FW];
 #pragma unroll
-  for (int f = 0; f < FW; ++f) {
-    fx[f] = fy[f] = fz[f] = en[f] = 0.0f;
-    xi[f] = valid[f] ? W.qmid[(size_t)(f0 + f) * N + i] : make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int f = 0; f < FW; ++f) fx[f] = fy[f] = fz[f] = en[f] = 0.0f;
+  // one frame per wave: the epilogue's inputs are requested before the
+  // force loop (error-correction term as in draft_mean_force)
+  float pre_p[3] = {0.f, 0.f, 0.f}, pre_p1[3] = {0.f, 0.f, 0.f};
+  float pre_fd[3] = {0.f, 0.f, 0.f}, pre_ec[3] = {0.f, 0.f, 0.f};
+  if constexpr (FW == 1) {
+    if (active && sub == 0 && valid[0]) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        pre_p[d] = W.p[(size_t)f0 * 3 * N + d * N + i];
+        pre_p1[d] = W.p[(size_t)(f0 + 1) * 3 * N + d * N + i];
+        pre_fd[d] = W.fd[(size_t)f0 * 3 * N + d * N + i];
+        pre_ec[d] = draft_mean_force(W, r, d * N + i, f0, 0.0f);
+      }
+    }
   }
-  const uint32_t* row = Lst.nbr_t + (size_t)i * Lst.mt;
   // LSD_VGATHER entries per iteration (m, m + LSD_LPA, ...): their gathers
   // are issued together; the terms are added in entry order as in the draft
   // kernel
-  for (int m0 = sub; m0 < cnt; m0 += LSD_VGATHER * LSD_LPA) {
+  for (int m0 = sub, first = 1; first || m0 < cnt; m0 += LSD_VGATHER * LSD_LPA, first = 0) {
     int jj[LSD_VGATHER], cc[LSD_VGATHER];
 #pragma unroll
     for (int u = 0; u < LSD_VGATHER; ++u) {
       const int m = m0 + u * LSD_LPA;
-      const uint32_t e = row[m < cnt ? m : m0];
-      jj[u] = (int)(e >> 5);
+      const uint32_t e = first ? e0[u] : row[m < Lst.mt ? m : 0];
+      jj[u] = m < cnt ? (int)(e >> 5) : 0;
       cc[u] = (int)(e & 31u);
     }
     float4 xj[LSD_VGATHER][FW];
@@ -676,10 +702,19 @@ __device__ __forceinline__ void verify_item(const SysDev& S, const ListDev& Lst,
         float* ftk = W.ft + (size_t)fr * 3 * N;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          const float Fd = draft_mean_force(W, r, d * N + i, fr, fdk[d * N + i]);
+          float Fd, pkd, pk1d;
+          if constexpr (FW == 1) {
+            Fd = W.ec ? pre_fd[d] + pre_ec[d] : pre_fd[d];
+            pkd = pre_p[d];
+            pk1d = pre_p1[d];
+          } else {
+            Fd = draft_mean_force(W, r, d * N + i, fr, fdk[d * N + i]);
+            pkd = pk[d * N + i];
+            pk1d = pk1[d * N + i];
+          }
           ftk[d * N + i] = Ft[d];
-          const double mud = bob_mean(S.a, S.c1fu, pk[d * N + i], Fd);
-          const double z = ((double)pk1[d * N + i] - mud) * isg;
+          const double mud = bob_mean(S.a, S.c1fu, pkd, Fd);
+          const double z = ((double)pk1d - mud) * isg;
           const double dl = S.c1fu * ((double)Fd - (double)Ft[d]) * isg;
           s1 = fma(dl, z, s1);
           s2 = fma(dl, dl, s2);
@@ -717,9 +752,19 @@ __global__ __launch_bounds__(LSD_VTHREADS) void k_verify(SysDev S, ListDev Lst, 
                                                          int fend) {
   __shared__ float s_shift[27][6];
   __shared__ double s_red[LSD_VWAVES][FW][3];
-  const int nv = min(min(W.nvalid[0], W.K), fend);
+  // the block's first item needs no count: frames from the window's valid
+  // count on are flagged invalid, which the item tests itself; the count
+  // (requested here) bounds the items the block takes after it
+  const int nvalid = W.nvalid[0];
+  const int all_items = (fend - fbeg + FW - 1) / FW * S.n_tiles;
+  int v = blockIdx.x;
+  if (v < all_items) {
+    const int g = v / S.n_tiles;
+    verify_item<FW>(S, Lst, W, Tl, P, v - g * S.n_tiles, fbeg + g * FW, fend, s_shift, s_red);
+  }
+  const int nv = min(min(nvalid, W.K), fend);
   const int items = nv > fbeg ? (nv - fbeg + FW - 1) / FW * S.n_tiles : 0;
-  for (int v = blockIdx.x; v < items; v += gridDim.x) {
+  for (v += gridDim.x; v < items; v += gridDim.x) {
     const int g = v / S.n_tiles;
     verify_item<FW>(S, Lst, W, Tl, P, v - g * S.n_tiles, fbeg + g * FW, fend, s_shift, s_red);
   }
