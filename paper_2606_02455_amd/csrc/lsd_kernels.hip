@@ -130,10 +130,17 @@ __global__ __launch_bounds__(256) void k_rebuild_bin(SysDev S, ListDev Lst, WinD
 // [rep_off[r], rep_off[r+1]) of the cell-sorted atom list (replicas that keep
 // their lists have zero counts and keep their entries); then the counters
 // are cleared for the next binning.
-__global__ __launch_bounds__(1024) void k_cell_scan(ListDev Lst, const int* __restrict__ rep_off) {
+__global__ __launch_bounds__(1024) void k_cell_scan(ListDev Lst, const int* __restrict__ rep_off,
+                                                    int R) {
   __shared__ int s[1024];
   const int C = Lst.n_cells;
   const int t = threadIdx.x;
+  // nothing to do when no replica rebuilds its lists: the counts are all
+  // zero (only rebuilt replicas are binned), every scan rewrites the cursors
+  // before the next fill, and the offsets of kept lists are not read
+  int any = 0;
+  for (int r = t; r < R; r += 1024) any |= Lst.rebuild[r];
+  if (!__syncthreads_or(any)) return;
   const int chunk = (C + 1023) / 1024;
   const int lo = min(C, t * chunk), hi = min(C, lo + chunk);
   int sum = 0;
@@ -1149,7 +1156,7 @@ hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W
                               hipStream_t st) {
   hipLaunchKernelGGL(k_rebuild_bin, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, L, W,
                      caller_frame0 ? 1 : 0);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, L, S.rep_off);
+  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, L, S.rep_off, S.R);
   hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S.n, S.atom_rep, L);
   hipLaunchKernelGGL(k_cell_sort, dim3(L.n_cells), dim3(64), 0, st, L);
   dim3 grid(L.n_cells, (L.cell_cap + NL_IPB - 1) / NL_IPB);

@@ -32,12 +32,8 @@ static_assert(LSD_LPA >= 4 && LSD_NET_HIDDEN % LSD_LPA == 0,
 #define NET_DPL (LSD_NET_MAX_DESC / LSD_LPA) // descriptor slots per lane
 #define NET_IROWS 16                         // atoms per block of the drafting node pass
 #define NET_ITHREADS (NET_IROWS * LSD_LPA)
-// lanes per atom of the descriptor loop in the matrix-core node passes
-#ifndef NET_NODE_LPA
-#define NET_NODE_LPA 16
-#endif
-static_assert(NET_NODE_LPA >= 4 && NET_NODE_LPA <= 16 && (NET_NODE_LPA & (NET_NODE_LPA - 1)) == 0,
-              "node pass: 16 atoms x a power-of-two number of lanes, at least one wave");
+// lanes per atom of the matrix-core node passes: one per radial function
+#define NET_NODE_LPA LSD_NET_MAX_BASIS
 
 namespace {
 
@@ -199,6 +195,81 @@ __global__ __launch_bounds__(NET_ITHREADS) void k_net_nodes_f32(SysDev S, ListDe
   if (sub == 0 && ok) store_v(P.v + (size_t)i * LSD_NET_MAX_BASIS, vp, B);
 }
 
+// Descriptor of the 16 atoms of a node-pass block with one lane per radial
+// function (16 lanes per atom).  The atom's lanes first stage the distance
+// and species of its list entries in LDS, 64 entries at a time (entry m on
+// lane m mod 16); then lane b sums e_{b+1}(r) = f_c(r) sin((b+1) pi r / r_c) / r
+// over the staged entries of each species, in entry order, so no lanes are
+// summed across.  sin and cos come from the vector unit's own instructions
+// (arguments in turns, at most 8 here): their error is far below the
+// bfloat16 or FP8 rounding of D that follows.  Every thread of the block
+// calls it (it holds barriers); acc[s] is D[s][b] of the lane's atom.
+#define NET_STAGE 64
+struct NetStage {
+  float r[NET_IROWS][NET_STAGE];
+  int sp[NET_IROWS][NET_STAGE];
+  int maxcnt;
+};
+__device__ __forceinline__ void net_descriptor_lanes(const PotDev& P, const SysDev& S,
+                                                     const float4* __restrict__ X,
+                                                     const uint32_t* __restrict__ row,
+                                                     int width, int cnt, int i, int r, int a,
+                                                     int sub, NetStage& st,
+                                                     float acc[LSD_NET_MAX_SPECIES]) {
+#pragma unroll
+  for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s) acc[s] = 0.0f;
+  if (threadIdx.x == 0) st.maxcnt = 0;
+  __syncthreads();
+  if (sub == 0 && cnt > 0) atomicMax(&st.maxcnt, cnt);
+  __syncthreads();
+  const int maxcnt = st.maxcnt;
+  const float Lf = (float)S.box[r];
+  const float4 xi = X[i];
+  const float turn_rc = P.pi_rc * 0.15915494309189535f;  // 1 / (2 r_c): turns per unit r
+  const float kb = (float)(sub + 1) * turn_rc;
+  for (int c0 = 0; c0 < maxcnt; c0 += NET_STAGE) {
+    // stage: four entries per lane
+    uint32_t ent[NET_STAGE / 16];
+#pragma unroll
+    for (int u = 0; u < NET_STAGE / 16; ++u) {
+      const int m = c0 + sub + 16 * u;
+      ent[u] = row[m < width ? m : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < NET_STAGE / 16; ++u) {
+      const int m = c0 + sub + 16 * u;
+      const bool ok = m < cnt;
+      const int j = ok ? (int)(ent[u] >> 5) : 0;
+      const float4 xj = X[j];
+      const int spj = S.species ? S.species[j] : 0;
+      float sj[3], si[3];
+      image_shifts((int)(ent[u] & 31u), Lf, sj, si);
+      const float dx = sep(xj.x, sj[0], xi.x, si[0]);
+      const float dy = sep(xj.y, sj[1], xi.y, si[1]);
+      const float dz = sep(xj.z, sj[2], xi.z, si[2]);
+      const float r2 = dx * dx + dy * dy + dz * dz;
+      st.r[a][sub + 16 * u] = (ok && r2 < P.rc2) ? sqrtf(r2) : -1.0f;
+      st.sp[a][sub + 16 * u] = spj;
+    }
+    __syncthreads();
+    const int n = min(NET_STAGE, cnt - c0);
+    if (sub < P.nb) {
+#pragma unroll 4
+      for (int m = 0; m < n; ++m) {
+        const float rr = st.r[a][m];
+        if (rr > 0.0f) {
+          const int spj = st.sp[a][m];
+          const float fc = 0.5f * (__builtin_amdgcn_cosf(rr * turn_rc) + 1.0f);
+          const float e = fc * __builtin_amdgcn_sinf(rr * kb) * __builtin_amdgcn_rcpf(rr);
+#pragma unroll
+          for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s) acc[s] += s == spj ? e : 0.0f;
+        }
+      }
+    }
+    __syncthreads();  // the next chunk rewrites the stage
+  }
+}
+
 // bfloat16 on the matrix cores: the first wave multiplies the block's 16
 // descriptors by W1 and the hidden activations by W2 with
 // v_mfma_f32_16x16x16_bf16.  16x16x16 operands: lane l holds
@@ -212,6 +283,8 @@ __global__ __launch_bounds__(NET_IROWS * NL) void k_net_nodes_bf16(SysDev S, Lis
   __shared__ unsigned short s_Db[NET_IROWS][LSD_NET_MAX_DESC];
   __shared__ unsigned short s_hb[NET_IROWS][LSD_NET_HIDDEN];
   __shared__ int s_sp[NET_IROWS], s_ok[NET_IROWS];
+  __shared__ NetStage stage;
+  static_assert(NL == LSD_NET_MAX_BASIS, "one lane per radial function");
   const int t = threadIdx.x, a = t / NL, sub = t % NL;
   const int i0 = blockIdx.x * NET_IROWS + a;
   const bool in = i0 < S.n;
@@ -254,19 +327,19 @@ __global__ __launch_bounds__(NET_IROWS * NL) void k_net_nodes_bf16(SysDev S, Lis
       s_b1[s][h] = s < P.ns ? b1[s * LSD_NET_HIDDEN + h] : 0.0f;
     }
   }
-  float D[LSD_NET_MAX_SPECIES][LSD_NET_MAX_BASIS];
-  net_descriptor<NL>(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md, Lst.md,
-                     ok ? cnt : 0, i, r, sub, D);
+  float acc[LSD_NET_MAX_SPECIES];
+  net_descriptor_lanes(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md, Lst.md,
+                       ok ? cnt : 0, i, r, a, sub, stage, acc);
   if (sub == 0) {
     s_sp[a] = S.species ? S.species[i] : 0;
     s_ok[a] = ok ? 1 : 0;
+  }
+  if (sub < B) {
 #pragma unroll
     for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s)
-#pragma unroll
-      for (int b = 0; b < LSD_NET_MAX_BASIS; ++b)
-        if (s < P.ns && b < B) s_Db[a][s * B + b] = to_bf16(D[s][b]);
-    for (int d = Din; d < LSD_NET_MAX_DESC; ++d) s_Db[a][d] = 0;
+      if (s < P.ns) s_Db[a][s * B + sub] = to_bf16(acc[s]);
   }
+  for (int d = Din + sub; d < LSD_NET_MAX_DESC; d += NL) s_Db[a][d] = 0;
   __syncthreads();
   if (mw) {
     f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -344,6 +417,8 @@ __global__ __launch_bounds__(NET_IROWS * NL) void k_net_nodes_fp8(SysDev S, List
   __shared__ __align__(8) unsigned char s_Dq[NET_IROWS][LSD_NET_MAX_DESC];
   __shared__ __align__(8) unsigned char s_hq[NET_IROWS][LSD_NET_HIDDEN];
   __shared__ int s_sp[NET_IROWS], s_ok[NET_IROWS];
+  __shared__ NetStage stage;
+  static_assert(NL == LSD_NET_MAX_BASIS, "one lane per radial function");
   const int t = threadIdx.x, a = t / NL, sub = t % NL;
   const int i0 = blockIdx.x * NET_IROWS + a;
   const bool in = i0 < S.n;
@@ -399,20 +474,20 @@ __global__ __launch_bounds__(NET_IROWS * NL) void k_net_nodes_fp8(SysDev S, List
       s_b1[s][h] = s < P.ns ? b1[s * LSD_NET_HIDDEN + h] : 0.0f;
     }
   }
-  float D[LSD_NET_MAX_SPECIES][LSD_NET_MAX_BASIS];
-  net_descriptor<NL>(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md, Lst.md,
-                     ok ? cnt : 0, i, r, sub, D);
+  float acc[LSD_NET_MAX_SPECIES];
+  net_descriptor_lanes(P, S, W.qmid + (size_t)k * N, Lst.nbr_d + (size_t)i * Lst.md, Lst.md,
+                       ok ? cnt : 0, i, r, a, sub, stage, acc);
   const float inv_sD = 1.0f / P.fp8_sD, inv_sh = 1.0f / P.fp8_sh;
   if (sub == 0) {
     s_sp[a] = S.species ? S.species[i] : 0;
     s_ok[a] = ok ? 1 : 0;
+  }
+  if (sub < B) {
 #pragma unroll
     for (int s = 0; s < LSD_NET_MAX_SPECIES; ++s)
-#pragma unroll
-      for (int b = 0; b < LSD_NET_MAX_BASIS; ++b)
-        if (s < P.ns && b < B) s_Dq[a][s * B + b] = to_fp8(D[s][b], inv_sD);
-    for (int d = Din; d < LSD_NET_MAX_DESC; ++d) s_Dq[a][d] = 0;
+      if (s < P.ns) s_Dq[a][s * B + sub] = to_fp8(acc[s], inv_sD);
   }
+  for (int d = Din + sub; d < LSD_NET_MAX_DESC; d += NL) s_Dq[a][d] = 0;
   __syncthreads();
   if (mw) {
     f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
