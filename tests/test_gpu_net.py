@@ -55,19 +55,19 @@ def lsd(torch):
     return L
 
 
-def _params(lsd, seed, w2=0.05, c=0.3):
+def _params(lsd, seed, w2=0.05, c=0.3, nb=B_):
     """Random learned-draft parameters (float32) whose edge coefficients
     matter next to the pair part."""
-    P = lsd.net_param_count(S_, B_)
+    P = lsd.net_param_count(S_, nb)
     rng = np.random.default_rng(seed)
     p = np.zeros(P)
-    o1 = H * S_ * B_
+    o1 = H * S_ * nb
     o2 = o1 + S_ * H
-    o3 = o2 + B_ * H
-    p[:o1] = rng.normal(scale=1.0 / np.sqrt(S_ * B_), size=o1)
+    o3 = o2 + nb * H
+    p[:o1] = rng.normal(scale=1.0 / np.sqrt(S_ * nb), size=o1)
     p[o1:o2] = rng.normal(scale=0.2, size=o2 - o1)
     p[o2:o3] = rng.normal(scale=w2, size=o3 - o2)
-    p[o3:] = rng.normal(scale=c, size=P - o3) / (1.0 + np.arange(B_))[None, :].repeat(6, 0).ravel()
+    p[o3:] = rng.normal(scale=c, size=P - o3) / (1.0 + np.arange(nb))[None, :].repeat(6, 0).ravel()
     return W.f32(p)
 
 
@@ -85,7 +85,7 @@ def _midpoints(w):
     return x
 
 
-def _bf16_bound(ora_net, species, x, L, D, z, v):
+def _bf16_bound(ora_net, species, x, L, D, z, v, rc=RC, nb=B_):
     """Force error bound of the bfloat16 node pass (module docstring)."""
     u = 2.0 ** -8
     W1, b1, W2, c = ora_net.split()
@@ -93,18 +93,18 @@ def _bf16_bound(ora_net, species, x, L, D, z, v):
     dz = 2.01 * u * (np.abs(D) @ np.abs(W1).T)
     dh = 1.1 * dz + 1.01 * u * np.abs(h)
     dv = (dh + 1.01 * u * np.abs(h)) @ np.abs(W2).T
-    return _pair_sum(x, L, species, dv)
+    return _pair_sum(x, L, species, dv, rc, nb)
 
 
-def _pair_sum(x, L, species, dv):
+def _pair_sum(x, L, species, dv, rc=RC, nb=B_):
     """Per atom, sum over its pairs of sum_b |e_b| (dv_i[b] + dv_j[b])."""
     from oracle import pairs
-    rec = pairs(x, L, RC, method="cells")
+    rec = pairs(x, L, rc, method="cells" if np.floor(L / rc) >= 3 else "brute")
     i, j = rec[:, 0], rec[:, 1]
     d = x[j] + L * rec[:, 2:5] - x[i]
     r = np.linalg.norm(d, axis=1)
-    b = np.arange(1, B_ + 1)
-    e = (0.5 * (np.cos(np.pi * r / RC) + 1.0))[:, None] * np.sin(np.pi * np.outer(r, b) / RC) / r[:, None]
+    b = np.arange(1, nb + 1)
+    e = (0.5 * (np.cos(np.pi * r / rc) + 1.0))[:, None] * np.sin(np.pi * np.outer(r, b) / rc) / r[:, None]
     per = np.sum(np.abs(e) * (dv[i] + dv[j]), axis=1)
     out = np.zeros(len(x))
     np.add.at(out, i, per)
@@ -145,6 +145,38 @@ def test_net_draft_forces_match_oracle(torch, lsd, ora, precision):
         bound = _bf16_bound(ref_net, w.species, xm, L, D, z, v)
         assert np.all(err <= 1.5 * bound + tol32), np.max(err / (1.5 * bound + tol32))
         assert np.max(err) > tol32  # the bfloat16 path really ran
+    assert g.status() == 0
+    g.destroy()
+
+
+@pytest.mark.parametrize("rc,nb", [(6.5, 8), (4.0, 16)])
+def test_net_draft_bf16_long_rows_and_full_basis(torch, lsd, ora, rc, nb):
+    # the bfloat16 node pass stages each atom's list entries 64 at a time
+    # with one lane per radial function: a 6.5 A cutoff gives rows of more
+    # than 64 entries (several stages, the lanes past the basis idle), and
+    # 16 radial functions use every lane
+    _say(f"learned draft, bfloat16, rc {rc}, {nb} radial functions")
+    from oracle.net import NetDraft
+    w = W.triatomic_liquid(64, seed=33, K=2)
+    L = float(w.box[0])
+    p = _params(lsd, 5, nb=nb)
+    draft = dict(kind="net", rc=rc, weights=p, n_basis=nb, n_model_species=S_, precision="bf16")
+    g = lsd.LSDSystem(w, mode="lsd", target=_tether(w), draft=draft)
+    g.draft_steps(1)
+    torch.cuda.synchronize()
+    if rc > 6.0:
+        cnt = g.neighbor_lists("draft")[0]
+        assert int(cnt.max()) > 64, int(cnt.max())
+    win = g.window()
+    fd = win["f_draft"][0].double().cpu().numpy().T
+    xm = _midpoints(w)
+    ref_net = NetDraft(S_, nb, rc, p.astype(np.float64))
+    ref, D, z, v = ref_net.forward(w.species, xm, L, intermediates=True)
+    scale = np.max(np.abs(ref))
+    err = np.abs(fd - ref)
+    tol32 = 2e-5 * scale
+    bound = _bf16_bound(ref_net, w.species, xm, L, D, z, v, rc, nb)
+    assert np.all(err <= 1.5 * bound + tol32), np.max(err / (1.5 * bound + tol32))
     assert g.status() == 0
     g.destroy()
 
