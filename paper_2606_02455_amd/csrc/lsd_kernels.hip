@@ -356,7 +356,9 @@ __device__ __forceinline__ void tether_force(const PotDev& P, const SysDev& S, f
 // coefficients (null: read from its parameters).
 // width: the list's row width (the first group of entries is read before
 // the count is known).
-template <int NL = LSD_LPA>
+// KIND: the potential kind when the launch fixes it (the other kinds' code is
+// then left out of the kernel), 0 to read it from P.
+template <int NL = LSD_LPA, int KIND = 0>
 __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
                                           const float4* __restrict__ X,
                                           const uint32_t* __restrict__ row, int width, int cnt,
@@ -366,7 +368,8 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
   const double L = S.box[r];
   const float Lf = (float)L;
   const float4 xi = X[i];
-  if (P.kind == LSD_POT_LJ) {
+  const int kind = KIND > 0 ? KIND : P.kind;
+  if (kind == LSD_POT_LJ) {
     // LSD_GATHER entries per iteration (gathers issued together), added in
     // order
     for (int m0 = sub, first = 1; first || m0 < cnt; m0 += LSD_GATHER * NL, first = 0) {
@@ -384,7 +387,7 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
     fy = lanes_sum<NL>(fy);
     fz = lanes_sum<NL>(fz);
     e = lanes_sum<NL>(e);
-  } else if (P.kind == LSD_POT_PAIR) {
+  } else if (kind == LSD_POT_PAIR) {
     const int spi = S.species ? S.species[i] : 0;
     for (int m0 = sub, first = 1; first || m0 < cnt; m0 += LSD_GATHER * NL, first = 0) {
       Gathered gt;
@@ -400,10 +403,10 @@ __device__ __forceinline__ void pot_force(const PotDev& P, const SysDev& S,
     fx = lanes_sum<NL>(fx);
     fy = lanes_sum<NL>(fy);
     fz = lanes_sum<NL>(fz);
-  } else if (P.kind == LSD_POT_NET) {
+  } else if (kind == LSD_POT_NET) {
     net_force<NL>(P, S, X, row, width, cnt, i, r, sub,
                   ctab ? ctab : P.w + net_off_c(P.ns, P.nb), fx, fy, fz);
-  } else if (P.kind == LSD_POT_HARMONIC) {
+  } else if (kind == LSD_POT_HARMONIC) {
     tether_force(P, S, xi, i, Lf, fx, fy, fz, e);
   }
   if (P.offset) {
@@ -423,11 +426,14 @@ static_assert(LSD_TILE % LSD_NET_SUB == 0 && LSD_NET_LPA <= 64 &&
                   (LSD_NET_LPA & (LSD_NET_LPA - 1)) == 0 &&
                   LSD_TILE / LSD_NET_SUB * LSD_NET_LPA <= 1024,
               "learned-draft launch: whole atoms per block, power-of-two lanes per atom");
-template <int NL, int SUB>
+// KIND: the draft's potential kind fixed by the launch (0: read from P), or
+// LSD_KIND_GIVEN for forces already in the window.
+#define LSD_KIND_GIVEN (-1)
+template <int NL, int SUB, int KIND>
 __global__ __launch_bounds__(LSD_TILE / SUB * NL) void k_draft(SysDev S, ListDev Lst, WinDev W,
                                                                TileDev Tl, PotDev P, int k,
-                                                               int use_target_list,
-                                                               int forces_given) {
+                                                               int use_target_list) {
+  constexpr bool forces_given = KIND == LSD_KIND_GIVEN;
   constexpr int APB = LSD_TILE / SUB;  // atoms per block
   __shared__ float s_ct[LSD_NET_MAX_TYPES * LSD_NET_MAX_BASIS];
   const int tile = blockIdx.x / SUB, part = blockIdx.x % SUB;
@@ -450,7 +456,7 @@ __global__ __launch_bounds__(LSD_TILE / SUB * NL) void k_draft(SysDev S, ListDev
   // the learned draft's pair-type coefficients, read by every entry: staged
   // in LDS (requested here as well)
   constexpr int CT_PER = (LSD_NET_MAX_TYPES * LSD_NET_MAX_BASIS + APB * NL - 1) / (APB * NL);
-  const bool net = P.kind == LSD_POT_NET && !forces_given;
+  const bool net = !forces_given && (KIND > 0 ? KIND : P.kind) == LSD_POT_NET;
   const int nct = net ? P.ns * (P.ns + 1) / 2 * P.nb : 0;
   float ctv[CT_PER];
 #pragma unroll
@@ -492,14 +498,14 @@ __global__ __launch_bounds__(LSD_TILE / SUB * NL) void k_draft(SysDev S, ListDev
     x0 = Lst.qref[i];
   }
   float F[3], e;
-  if (forces_given) {
+  if constexpr (forces_given) {
     // forces of this frame already in the window (batched network pass)
     const float* fk0 = W.fd + (size_t)k * 3 * N;
     F[0] = fk0[i];
     F[1] = fk0[N + i];
     F[2] = fk0[2 * N + i];
   } else {
-    pot_force<NL>(P, S, X, row, width, cnt, i, r, sub, F[0], F[1], F[2], e, s_ct);
+    pot_force<NL, KIND>(P, S, X, row, width, cnt, i, r, sub, F[0], F[1], F[2], e, s_ct);
   }
   if (!lead) return;
 
@@ -1167,15 +1173,26 @@ hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W
 hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                         const PotDev& P, int k, int use_target_list, hipStream_t st,
                         int forces_given) {
-  if (P.kind == LSD_POT_NET && !forces_given) {
+  // one kernel per draft kind (each holds only its own force loop)
+  const dim3 tiles(S.n_tiles), block(LSD_VTHREADS);
+  if (forces_given) {
+    hipLaunchKernelGGL((k_draft<LSD_LPA, 1, LSD_KIND_GIVEN>), tiles, block, 0, st, S, L, W, T, P,
+                       k, use_target_list);
+  } else if (P.kind == LSD_POT_NET) {
     // the learned draft: a small system's latency-bound loop over more
     // lanes per atom and more compute units
-    hipLaunchKernelGGL((k_draft<LSD_NET_LPA, LSD_NET_SUB>), dim3(S.n_tiles * LSD_NET_SUB),
-                       dim3(LSD_TILE / LSD_NET_SUB * LSD_NET_LPA), 0, st, S, L, W, T, P, k,
-                       use_target_list, forces_given);
+    hipLaunchKernelGGL((k_draft<LSD_NET_LPA, LSD_NET_SUB, LSD_POT_NET>),
+                       dim3(S.n_tiles * LSD_NET_SUB), dim3(LSD_TILE / LSD_NET_SUB * LSD_NET_LPA), 0,
+                       st, S, L, W, T, P, k, use_target_list);
+  } else if (P.kind == LSD_POT_LJ) {
+    hipLaunchKernelGGL((k_draft<LSD_LPA, 1, LSD_POT_LJ>), tiles, block, 0, st, S, L, W, T, P, k,
+                       use_target_list);
+  } else if (P.kind == LSD_POT_PAIR) {
+    hipLaunchKernelGGL((k_draft<LSD_LPA, 1, LSD_POT_PAIR>), tiles, block, 0, st, S, L, W, T, P, k,
+                       use_target_list);
   } else {
-    hipLaunchKernelGGL((k_draft<LSD_LPA, 1>), dim3(S.n_tiles), dim3(LSD_VTHREADS), 0, st, S, L, W,
-                       T, P, k, use_target_list, forces_given);
+    hipLaunchKernelGGL((k_draft<LSD_LPA, 1, 0>), tiles, block, 0, st, S, L, W, T, P, k,
+                       use_target_list);
   }
   return hipGetLastError();
 }
