@@ -42,9 +42,12 @@ __device__ __forceinline__ void flag_replicas(bool need, int r, int* flags) {
 // list positions (so the image codes of the lists stay valid); a replica
 // whose atoms moved too far from them is flagged for a rebuild.
 // Item i: the validity flag i (i < R kmax) and atom i (i < N).
+// qc, pc: the atom's committed position and momentum when the caller holds
+// them (null: read from q and p).
 __device__ __forceinline__ void window_start_item(const SysDev& S, const ListDev& Lst,
                                                   const WinDev& W, const float* q, const float* p,
-                                                  int i) {
+                                                  int i, const float* qc = nullptr,
+                                                  const float* pc = nullptr) {
   if (i < S.R * S.kmax) {
     // frames that would produce steps past the step limit are never verified
     const int rr = i / S.kmax, f = i % S.kmax;
@@ -53,7 +56,7 @@ __device__ __forceinline__ void window_start_item(const SysDev& S, const ListDev
   if (i == 0) W.nvalid[0] = 0;  // raised by the drafting of each valid frame
   if (i < S.R) W.rej[i] = LSD_MAX_K;  // no rejection known yet
   if (i >= S.n) return;
-  const int r = S.atom_rep[i];
+  const int r = S.R == 1 ? 0 : S.atom_rep[i];
   const int sp = S.species ? S.species[i] : 0;
   const double L = S.box[r];
   const double hm = S.hdt_m[sp];
@@ -61,9 +64,9 @@ __device__ __forceinline__ void window_start_item(const SysDev& S, const ListDev
   float x[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    float pd = p[d * S.n + i];
+    float pd = pc ? pc[d] : p[d * S.n + i];
     W.p[d * S.n + i] = pd;
-    x[d] = a_half(q[d * S.n + i], pd, hm, L, &dimg[d]);
+    x[d] = a_half(qc ? qc[d] : q[d * S.n + i], pd, hm, L, &dimg[d]);
   }
   const float4 xw = make_float4(x[0], x[1], x[2], pack_img(dimg[0], dimg[1], dimg[2]));
   Lst.qwrap[i] = xw;
@@ -963,14 +966,17 @@ __global__ __launch_bounds__(1024) void k_decide(SysDev S, WinDev W, TileDev Tl,
 // momentum <p> + Sigma^{1/2} (z - (2 delta.z / delta.delta) delta) and map g.
 // With error correction the cache becomes F - F~ of the committed frame,
 // from the EC-uncorrected draft force (App. D).
-__device__ __forceinline__ void commit_atom(const SysDev& S, const WinDev& W, float* q, float* p,
-                                            int* img, int plain, int i) {
-  if (i >= S.n) return;
-  const int r = S.atom_rep[i];
+// Returns whether the atom was committed; qc, pc (if given) then hold the
+// committed position and momentum.
+__device__ __forceinline__ bool commit_atom(const SysDev& S, const WinDev& W, float* q, float* p,
+                                            int* img, int plain, int i, float* qc = nullptr,
+                                            float* pc = nullptr) {
+  if (i >= S.n) return false;
+  const int r = S.R == 1 ? 0 : S.atom_rep[i];
   const int sp = S.species ? S.species[i] : 0;
   const size_t N = (size_t)S.n;
   const int f = W.commit_frame[r];
-  if (f < 0) return;  // nothing committed in this window (step limit reached)
+  if (f < 0) return false;  // nothing committed in this window (step limit reached)
   const float4 x = W.qmid[(size_t)f * N + i];
   int dimg[3];
   unpack_img(x.w, dimg);
@@ -1015,6 +1021,10 @@ __device__ __forceinline__ void commit_atom(const SysDev& S, const WinDev& W, fl
     const float qn = a_half(xs[d], pn, hm, L, &dimg[d]);
     q[d * N + i] = qn;
     p[d * N + i] = pn;
+    if (qc) {
+      qc[d] = qn;
+      pc[d] = pn;
+    }
     img[d * N + i] += dimg[d];
     if (W.ec) {
       // the two last committed errors: frames f-1 and f of this window, or
@@ -1026,6 +1036,7 @@ __device__ __forceinline__ void commit_atom(const SysDev& S, const WinDev& W, fl
       W.ec[d * N + i] = Ft - Fb;
     }
   }
+  return true;
 }
 
 __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __restrict__ q,
@@ -1040,8 +1051,11 @@ __global__ __launch_bounds__(256) void k_commit(SysDev S, WinDev W, float* __res
 __global__ __launch_bounds__(256) void k_commit_start(SysDev S, ListDev Lst, WinDev W, float* q,
                                                       float* p, int* img, int plain) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  commit_atom(S, W, q, p, img, plain, i);
-  window_start_item(S, Lst, W, q, p, i);
+  float qc[3], pc[3];
+  const bool done = commit_atom(S, W, q, p, img, plain, i, qc, pc);
+  // the next window starts from the values just committed (or, where
+  // nothing was committed, from the state as it stands)
+  window_start_item(S, Lst, W, q, p, i, done ? qc : nullptr, done ? pc : nullptr);
 }
 
 // (OBABO) start (App. E): frame 0 = the given positions q_0 (wrapped), for
