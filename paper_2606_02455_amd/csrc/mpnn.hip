@@ -433,22 +433,30 @@ __global__ __launch_bounds__(256) void k_mp_filter(MpnnWeights w, MpnnBuffers b,
       for (int q = 0; q < 4; ++q) a2v[mt][q] = w.a2[l][32 * wave + 16 * mt + 4 * (lane >> 4) + q];
     for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
       const long p0 = tile * kFiltPairs;
-      // radial basis e_b(r) = sqrt(2/rc) sin(b pi r/rc)/r, de_b/dr, cutoff
+      // radial basis e_b(r) = sqrt(2/rc) sin(b pi r/rc)/r, de_b/dr, cutoff;
+      // eight threads per pair, two functions each: sin and cos of the
+      // first one's angle, the second one's by a rotation by pi r/rc
       {
         const int q = t >> 3, b0 = 2 * (t & 7);
         const long p = p0 + q;
         const float r = p < np ? b.uv[4 * p + 3] : 0.5f * rc;
+        const float inv_r = 1.0f / r;
+        float s1, c1, sn, cs;
+        sincosf(pi_rc * r, &s1, &c1);
+        sincosf((float)(b0 + 1) * pi_rc * r, &sn, &cs);
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           const int bb = b0 + u;
           const float k = (float)(bb + 1) * pi_rc;
-          const float sn = sinf(k * r), cs = cosf(k * r);
-          s_e[q][bb] = pre * sn / r;
-          s_de[q][bb] = pre * (k * cs / r - sn / (r * r));
+          s_e[q][bb] = pre * sn * inv_r;
+          s_de[q][bb] = pre * (k * cs - sn * inv_r) * inv_r;
+          const float sn2 = sn * c1 + cs * s1, cs2 = cs * c1 - sn * s1;
+          sn = sn2;
+          cs = cs2;
         }
         if ((t & 7) == 0) {
-          s_fc[q] = 0.5f * (cosf(pi_rc * r) + 1.0f);
-          s_dfc[q] = -0.5f * pi_rc * sinf(pi_rc * r);
+          s_fc[q] = 0.5f * (c1 + 1.0f);
+          s_dfc[q] = -0.5f * pi_rc * s1;
         }
       }
       __syncthreads();
