@@ -495,8 +495,8 @@ lsd_status enqueue_pipelined(lsd_system* s, int K, hipStream_t a, hipStream_t b,
   }
   HIP_TRY(hipEventRecord(s->pipe_ev[LSD_MAX_K], b));
   HIP_TRY(hipStreamWaitEvent(a, s->pipe_ev[LSD_MAX_K], 0));
-  HIP_TRY(launch_decide(s->S, s->Lst, s->W, s->T, s->O, 0, a));
-  HIP_TRY(launch_commit_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, s->buf.img, 0, a));
+  HIP_TRY(launch_decide_commit_start(s->S, s->Lst, s->W, s->T, s->O, s->buf.q, s->buf.p,
+                                     s->buf.img, 0, a));
   return LSD_OK;
 }
 
@@ -552,9 +552,8 @@ lsd_status enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
   }
   if (part == PART_FULL && !plain) LSD_TRY(enqueue_verify(s, K, st));
   if (part == PART_FULL || part == PART_POST) {
-    HIP_TRY(launch_decide(s->S, s->Lst, s->W, s->T, s->O, plain ? 1 : 0, st));
-    HIP_TRY(launch_commit_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, s->buf.img, plain ? 1 : 0,
-                                st));
+    HIP_TRY(launch_decide_commit_start(s->S, s->Lst, s->W, s->T, s->O, s->buf.q, s->buf.p,
+                                       s->buf.img, plain ? 1 : 0, st));
   }
   return LSD_OK;
 }

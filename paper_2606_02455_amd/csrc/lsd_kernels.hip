@@ -338,6 +338,105 @@ __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev 
   }
 }
 
+// Verlet lists of one small system in one launch, without cells: wave u of
+// block b takes atom i = 4 b + u and tests every candidate (image, j) in a
+// fixed order -- j ascending, each at its nearest image, when the box holds
+// no second image of an atom inside the larger list radius (L > 2 r_list),
+// else all 27 images of every j, image-major -- with the binary32 test and
+// the binary64 band predicate of k_nl_build, appending the hits in candidate
+// order by ballot compaction.  The same wave resets its atom's list position
+// (and frame 0) as k_rebuild_bin does.  Every candidate is read from the
+// positions the lists are built at, which no wave writes here.
+#define NL_SMALL_MAX 2048
+__global__ __launch_bounds__(256) void k_nl_small(SysDev S, ListDev Lst, WinDev W,
+                                                  int caller_frame0) {
+  __shared__ float s_sh[27][6];
+  if (!Lst.rebuild[0]) return;  // uniform over the grid
+  const int t = threadIdx.x, lane = t & 63;
+  const double L = S.box[0];
+  const float Lf = (float)L;
+  if (t < 27) image_shifts(t, Lf, &s_sh[t][0], &s_sh[t][3]);
+  __syncthreads();
+  const int n = S.n;
+  const int i = blockIdx.x * 4 + (t >> 6);
+  if (i >= n) return;  // uniform per wave; no barrier follows
+  const float4* src = caller_frame0 ? W.qmid : Lst.qwrap;
+  const float4 xi = src[i];
+  if (lane == 0) {
+    if (!caller_frame0) W.qmid[i] = xi;
+    Lst.qref[i] = xi;
+  }
+  // one image per atom at most inside the list radius: L^2 > 4 r^2 with a
+  // margin far above the rounding of the binary32 separations below
+  const double rl2 = Lst.rl2_t > Lst.rl2_d ? Lst.rl2_t : Lst.rl2_d;
+  const bool nearest = L * L > 4.0 * rl2 * (1.0 + 1e-5);
+  const int total = nearest ? n : 27 * n;
+  const float half = 0.5f * Lf;
+  uint32_t* rowt = Lst.nbr_t + (size_t)i * Lst.mt;
+  uint32_t* rowd = Lst.nbr_d + (size_t)i * Lst.md;
+  int nt = 0, nd = 0;
+  for (int k0 = 0; k0 < total; k0 += 64) {
+    const int k = k0 + lane;
+    bool ht = false, hd = false;
+    uint32_t ent = 0;
+    if (k < total) {
+      int j, code;
+      if (nearest) {
+        j = k;
+      } else {
+        code = k / n;
+        j = k - code * n;
+      }
+      const float4 xj = src[j];
+      if (nearest) {
+        const float ex = xj.x - xi.x, ey = xj.y - xi.y, ez = xj.z - xi.z;
+        const int nx = ex > half ? -1 : (ex < -half ? 1 : 0);
+        const int ny = ey > half ? -1 : (ey < -half ? 1 : 0);
+        const int nz = ez > half ? -1 : (ez < -half ? 1 : 0);
+        code = (nx + 1) + 3 * (ny + 1) + 9 * (nz + 1);
+      }
+      ent = ((uint32_t)j << 5) | (uint32_t)code;
+      if (!(j == i && code == 13)) {
+        const float* sh = s_sh[code];
+        const float fdx = sep(xj.x, sh[0], xi.x, sh[3]);
+        const float fdy = sep(xj.y, sh[1], xi.y, sh[4]);
+        const float fdz = sep(xj.z, sh[2], xi.z, sh[5]);
+        const float r2 = fdx * fdx + fdy * fdy + fdz * fdz;
+        const bool bt = r2 >= Lst.rl2_t_lo && r2 < Lst.rl2_t_hi;
+        const bool bd = r2 >= Lst.rl2_d_lo && r2 < Lst.rl2_d_hi;
+        ht = r2 < Lst.rl2_t_lo;
+        hd = r2 < Lst.rl2_d_lo;
+        if (bt || bd) {
+          double dx = ((double)xj.x - (double)xi.x) + (double)code_nx(code) * L;
+          double dy = ((double)xj.y - (double)xi.y) + (double)code_ny(code) * L;
+          double dz = ((double)xj.z - (double)xi.z) + (double)code_nz(code) * L;
+          double d2 = dx * dx + dy * dy + dz * dz;
+          if (bt) ht = d2 < Lst.rl2_t;
+          if (bd) hd = d2 < Lst.rl2_d;
+        }
+      }
+    }
+    const unsigned long long bt = __ballot(ht), bd = __ballot(hd);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (ht) {
+      const int pos = nt + __popcll(bt & below);
+      if (pos < Lst.mt) rowt[pos] = ent;
+    }
+    if (hd) {
+      const int pos = nd + __popcll(bd & below);
+      if (pos < Lst.md) rowd[pos] = ent;
+    }
+    nt += __popcll(bt);
+    nd += __popcll(bd);
+  }
+  if (lane == 0) {
+    if (nt > Lst.mt) { atomicOr(Lst.status, LSD_STATUS_NBR_TARGET); nt = Lst.mt; }
+    if (nd > Lst.md) { atomicOr(Lst.status, LSD_STATUS_NBR_DRAFT); nd = Lst.md; }
+    Lst.cnt_t[i] = nt;
+    Lst.cnt_d[i] = nd;
+  }
+}
+
 // Tether force and energy of atom i at position xi (minimum image).
 __device__ __forceinline__ void tether_force(const PotDev& P, const SysDev& S, float4 xi, int i,
                                              float Lf, float& fx, float& fy, float& fz, float& e) {
@@ -896,11 +995,11 @@ __global__ __launch_bounds__(1024) void k_decide_group(SysDev S, WinDev W, TileD
   }
 }
 
-__global__ __launch_bounds__(1024) void k_decide(SysDev S, WinDev W, TileDev Tl, OutDev O, int plain,
-                                                 int* __restrict__ rebuild, int always_rebuild) {
+__device__ __forceinline__ void decide_replica(const SysDev& S, const WinDev& W, const TileDev& Tl,
+                                               const OutDev& O, int plain, int* rebuild,
+                                               int always_rebuild, int r) {
   __shared__ double s_s1[LSD_MAX_K], s_s2[LSD_MAX_K];
   __shared__ int s_acc[LSD_MAX_K];
-  const int r = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int K = W.K;
   const int* inv = W.invalid + (size_t)r * S.kmax;
@@ -960,6 +1059,11 @@ __global__ __launch_bounds__(1024) void k_decide(SysDev S, WinDev W, TileDev Tl,
     rebuild[r] = always_rebuild;
     if (W.ec_samples) W.ec_samples[r] = min(2, W.ec_samples[r] + j);
   }
+}
+
+__global__ __launch_bounds__(1024) void k_decide(SysDev S, WinDev W, TileDev Tl, OutDev O, int plain,
+                                                 int* __restrict__ rebuild, int always_rebuild) {
+  decide_replica(S, W, Tl, O, plain, rebuild, always_rebuild, blockIdx.x);
 }
 
 // Commit: the last kept frame's state; a rejected frame takes the reflected
@@ -1056,6 +1160,25 @@ __global__ __launch_bounds__(256) void k_commit_start(SysDev S, ListDev Lst, Win
   // the next window starts from the values just committed (or, where
   // nothing was committed, from the state as it stands)
   window_start_item(S, Lst, W, q, p, i, done ? qc : nullptr, done ? pc : nullptr);
+}
+
+// One small system: the decision, the commit and the next window's start in
+// one block, since the commit of every atom waits only for the decision of
+// its replica.  The barrier after the decision orders its reads of the
+// window's flags before the start rewrites them, and its writes (committed
+// frame, reflection, step, list flag) before the commit reads them.
+__global__ __launch_bounds__(1024) void k_decide_commit_start(SysDev S, ListDev Lst, WinDev W,
+                                                              TileDev Tl, OutDev O, float* q,
+                                                              float* p, int* img, int plain) {
+  decide_replica(S, W, Tl, O, plain, Lst.rebuild, Lst.always_rebuild, 0);
+  __syncthreads();
+  const int n = S.n > S.kmax ? S.n : S.kmax;
+  for (int base = 0; base < n; base += blockDim.x) {  // uniform trip count
+    const int i = base + threadIdx.x;
+    float qc[3], pc[3];
+    const bool done = commit_atom(S, W, q, p, img, plain, i, qc, pc);
+    window_start_item(S, Lst, W, q, p, i, done ? qc : nullptr, done ? pc : nullptr);
+  }
 }
 
 // (OBABO) start (App. E): frame 0 = the given positions q_0 (wrapped), for
@@ -1174,6 +1297,11 @@ hipError_t launch_window_start(const SysDev& S, const ListDev& L, const WinDev& 
 
 hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W, bool caller_frame0,
                               hipStream_t st) {
+  if (S.R == 1 && S.n <= NL_SMALL_MAX) {
+    hipLaunchKernelGGL(k_nl_small, dim3((S.n + 3) / 4), dim3(256), 0, st, S, L, W,
+                       caller_frame0 ? 1 : 0);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_rebuild_bin, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S, L, W,
                      caller_frame0 ? 1 : 0);
   hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, L, S.rep_off, S.R);
@@ -1275,6 +1403,24 @@ hipError_t launch_decide(const SysDev& S, const ListDev& L, const WinDev& W, con
   hipLaunchKernelGGL(k_decide, dim3(S.R), dim3(64 * waves), 0, st, S, W, T, O, plain, L.rebuild,
                      L.always_rebuild);
   return hipGetLastError();
+}
+
+// Decision, commit and the next window's start: one block for one small
+// system, else one launch per step.
+#ifndef LSD_FUSED_COMMIT_MAX
+#define LSD_FUSED_COMMIT_MAX 1024
+#endif
+hipError_t launch_decide_commit_start(const SysDev& S, const ListDev& L, const WinDev& W,
+                                      const TileDev& T, const OutDev& O, float* q, float* p,
+                                      int* img, int plain, hipStream_t st) {
+  if (S.R == 1 && S.n <= LSD_FUSED_COMMIT_MAX) {
+    hipLaunchKernelGGL(k_decide_commit_start, dim3(1), dim3(1024), 0, st, S, L, W, T, O, q, p, img,
+                       plain);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_decide(S, L, W, T, O, plain, st);
+  if (e != hipSuccess) return e;
+  return launch_commit_start(S, L, W, q, p, img, plain, st);
 }
 
 hipError_t launch_commit_start(const SysDev& S, const ListDev& L, const WinDev& W, float* q,

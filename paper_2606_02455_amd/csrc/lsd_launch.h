@@ -28,6 +28,11 @@ hipError_t launch_decide_group(const SysDev& S, const WinDev& W, const TileDev& 
                                int fend, hipStream_t st);
 hipError_t launch_decide(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
                          const OutDev& O, int plain, hipStream_t st);
+// decision, commit of the window and start of the next one (one launch for a
+// single small system, else launch_decide then launch_commit_start)
+hipError_t launch_decide_commit_start(const SysDev& S, const ListDev& L, const WinDev& W,
+                                      const TileDev& T, const OutDev& O, float* q, float* p,
+                                      int* img, int plain, hipStream_t st);
 // commit of the window and start of the next one in one launch
 hipError_t launch_commit_start(const SysDev& S, const ListDev& L, const WinDev& W, float* q,
                                float* p, int* img, int plain, hipStream_t st);

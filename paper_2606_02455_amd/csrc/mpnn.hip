@@ -208,46 +208,58 @@ __global__ __launch_bounds__(kRowThreads) void k_mp_count(MpnnBuffers b, SysDev 
 
 // Exclusive scans of the row counts of edges (off) and pairs (poff) in place;
 // off[rows], poff[rows] = totals, also copied to counts[0..1].
-// Small evaluations: one block, thread t scanning the contiguous rows
-// [t chunk, (t+1) chunk).  Large ones: blocks of kScanTile rows scan their
-// tile (coalesced, wave scans) and record its totals, one block scans the
-// totals, and a last pass adds each tile's offset.
+// Small evaluations (up to kScanSingleMax rows): one block, thread t scanning
+// the contiguous rows [t chunk, (t+1) chunk) of the rows that can hold edges
+// (the valid-frame prefix); the rows after it get the totals.  Large ones:
+// blocks of kScanTile rows scan their tile (coalesced, wave scans) and record
+// its totals, one block scans the totals, and a last pass adds each tile's
+// offset.
 constexpr int kScanTile = 1024;
-constexpr long kScanSingleMax = 4096;  // rows scanned by the single-block form
+constexpr int kScanChunk = 16;                          // rows per thread of the single-block form
+constexpr long kScanSingleMax = 1024L * kScanChunk;     // rows scanned by the single-block form
 
-__global__ __launch_bounds__(1024) void k_mp_scan(MpnnBuffers b, long rows) {
-  __shared__ long s[1024], s2[1024];
+__device__ __forceinline__ int block_scan_incl(int v, int* s_w, int* total);
+
+__global__ __launch_bounds__(1024) void k_mp_scan(MpnnBuffers b, long rows, long n_atoms, int f0,
+                                                  int nf, const int* nvalid) {
+  __shared__ int s_w[32];
   const int t = threadIdx.x;
-  const long chunk = (rows + 1023) / 1024;
-  const long lo = min(rows, (long)t * chunk), hi = min(rows, lo + chunk);
-  long sum = 0, sum2 = 0;
-  for (long r = lo; r < hi; ++r) {
-    sum += b.off[r];
-    sum2 += b.poff[r];
+  const long live = (long)eff_frames(nvalid, f0, nf) * n_atoms;  // <= rows
+  const long chunk = (live + 1023) / 1024;
+  const long lo = min(live, (long)t * chunk), hi = min(live, lo + chunk);
+  int c1[kScanChunk], c2[kScanChunk];
+  int sum = 0, sum2 = 0;
+#pragma unroll
+  for (int u = 0; u < kScanChunk; ++u) {
+    const long r = lo + u;
+    c1[u] = r < hi ? b.off[r] : 0;
+    c2[u] = r < hi ? b.poff[r] : 0;
   }
-  s[t] = sum;
-  s2[t] = sum2;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const long v = t >= o ? s[t - o] : 0, v2 = t >= o ? s2[t - o] : 0;
-    __syncthreads();
-    s[t] += v;
-    s2[t] += v2;
-    __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kScanChunk; ++u) {
+    sum += c1[u];
+    sum2 += c2[u];
   }
-  long run = s[t] - sum, run2 = s2[t] - sum2;
-  for (long r = lo; r < hi; ++r) {
-    const long c = b.off[r], c2 = b.poff[r];
-    b.off[r] = (int)run;
-    b.poff[r] = (int)run2;
-    run += c;
-    run2 += c2;
+  int tot, tot2;
+  int run = block_scan_incl(sum, s_w, &tot) - sum;
+  int run2 = block_scan_incl(sum2, s_w, &tot2) - sum2;
+#pragma unroll
+  for (int u = 0; u < kScanChunk; ++u) {
+    const long r = lo + u;
+    if (r < hi) {
+      b.off[r] = run;
+      b.poff[r] = run2;
+    }
+    run += c1[u];
+    run2 += c2[u];
   }
-  if (t == 1023) {
-    b.off[rows] = (int)s[1023];
-    b.poff[rows] = (int)s2[1023];
-    b.counts[0] = (int)s[1023];
-    b.counts[1] = (int)s2[1023];
+  for (long r = live + t; r <= rows; r += 1024) {
+    b.off[r] = tot;
+    b.poff[r] = tot2;
+  }
+  if (t == 0) {
+    b.counts[0] = tot;
+    b.counts[1] = tot2;
   }
 }
 
@@ -821,8 +833,21 @@ __global__ void k_mp_frag(const float* __restrict__ src, int ld, int trans, int 
 // out[row][c] = sum over the row's edges e of W_t[pair(e)][c] * V[neighbour row][c]
 // (messages with V = X_t; dE/dX with V = gM: W is symmetric in the pair).
 // One block of 128 threads (channels) per row; eight edges' loads issued
-// together, terms added in edge order.
+// together, terms added in edge order.  Blocks are dealt to the eight XCDs in
+// turn (block b to XCD b mod 8), so the rows are handed out in pieces of G
+// consecutive rows, piece s of XCD x being rows [(8 s + x) G, (8 s + x + 1) G),
+// with G = ceil(rows / 8) up to kGatherPiece: the two rows of a pair (atoms
+// close in the ordering) then read its filters and each other's features
+// through the same L2, and long evaluations (whose later frames hold fewer
+// live rows) still spread every frame over all eight XCDs.
 constexpr int kGatherDepth = 8;
+constexpr long kGatherPiece = 1024;
+
+// grid of the gather: enough blocks for every row count up to rows
+static unsigned gather_grid(long rows) {
+  const long q = rows <= 8 * kGatherPiece ? 8 : 8 * kGatherPiece;
+  return (unsigned)((rows + q - 1) / q * q);
+}
 
 __device__ __forceinline__ float pair_filter(const MpnnBuffers& b, int u, int t, int c) {
   if (u == kNoPair) return 0.f;  // only after a latched capacity overflow
@@ -832,8 +857,12 @@ __device__ __forceinline__ float pair_filter(const MpnnBuffers& b, int u, int t,
 
 __global__ __launch_bounds__(128) void k_mp_gather(MpnnBuffers b, int t, const float* __restrict__ V,
                                                    float* __restrict__ out, RowSpan span) {
-  const long row = blockIdx.x;
-  if (row >= span.rows()) return;
+  const long nrow = span.rows();
+  if (nrow == 0) return;
+  const long cch = (nrow + 7) / 8, G = cch < kGatherPiece ? cch : kGatherPiece;
+  const long l = blockIdx.x / 8;
+  const long row = (l / G) * 8 * G + (long)(blockIdx.x % 8) * G + l % G;
+  if (row >= nrow) return;
   const int c = threadIdx.x;
   const int e1 = b.off[row + 1];
   float acc = 0.f;
@@ -1098,7 +1127,7 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, i
                      nf, nvalid, M.rc);
   MP_HIP(hipGetLastError());
   if (rows <= kScanSingleMax) {
-    hipLaunchKernelGGL(k_mp_scan, dim3(1), dim3(1024), 0, st, b, rows);
+    hipLaunchKernelGGL(k_mp_scan, dim3(1), dim3(1024), 0, st, b, rows, N, f0, nf, nvalid);
     MP_HIP(hipGetLastError());
   } else {
     const int tiles = (int)((rows + kScanTile - 1) / kScanTile);
@@ -1147,7 +1176,8 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, i
   MP_HIP(chain(CH_EMBED, ca));
   for (int t = 0; t < MP_T; ++t) {
     float* Xt = b.X + t * rh;
-    hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, t, Xt, b.Mm, span);
+    hipLaunchKernelGGL(k_mp_gather, dim3(gather_grid(rows)), dim3(MP_H), 0, st, b, t, Xt, b.Mm,
+                       span);
     MP_HIP(hipGetLastError());
     ChainArgs c{};
     c.scale = M.scale;
@@ -1175,7 +1205,8 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, i
                        t == MP_T - 1 ? 1 : 0, b.X + t * rh, cap);
     MP_HIP(hipGetLastError());
     if (t == 0) break;
-    hipLaunchKernelGGL(k_mp_gather, dim3((unsigned)rows), dim3(MP_H), 0, st, b, t, b.gM, b.gX, span);
+    hipLaunchKernelGGL(k_mp_gather, dim3(gather_grid(rows)), dim3(MP_H), 0, st, b, t, b.gM, b.gX,
+                       span);
     MP_HIP(hipGetLastError());
     ChainArgs c{};
     c.scale = M.scale;
