@@ -354,6 +354,24 @@ __global__ __launch_bounds__(kRowThreads) void k_mp_edges(MpnnBuffers b, SysDev 
   row_pass<true>(b, S, L, W, f0, blockIdx.x, rc, pair_cap);
 }
 
+// Fixed grids over a list of n items (edges or pairs, ordered by row): the
+// blocks are dealt to the eight XCDs in turn (block b to XCD b mod 8), so XCD
+// x takes the contiguous eighth [x c, (x + 1) c), c = ceil(n / 8), of the
+// items, its gridDim / 8 blocks striding through it.  The rows an item reads
+// (its own and its neighbour's, close in the ordering) then come through one
+// L2.  The grid is a multiple of eight.
+struct XcdSpan {
+  long base, end, first, stride;
+  __device__ __forceinline__ XcdSpan(long n, int per_block, int local) {
+    const long c = (n + 7) / 8;
+    const int x = blockIdx.x % 8;
+    base = (long)x * c;
+    end = base + c < n ? base + c : n;
+    first = base + (long)(blockIdx.x / 8) * per_block + local;
+    stride = (long)(gridDim.x / 8) * per_block;
+  }
+};
+
 // every reverse edge refers to its owner: the neighbour row's edge back to
 // this row with the opposite image; uid = ~pair (kNoPair if the owner's pair
 // is past the capacity).  Sixteen lanes per edge test sixteen of the
@@ -366,9 +384,8 @@ __global__ __launch_bounds__(256) void k_mp_reverse(MpnnBuffers b, long rows, lo
   const int sub = threadIdx.x % kRevLanes;
   const int lane = threadIdx.x & 63, g0 = lane & ~(kRevLanes - 1);
   const long n_edges = min((long)b.off[rows], cap);
-  const long stride = (long)gridDim.x * (blockDim.x / kRevLanes);
-  for (long e = ((long)blockIdx.x * blockDim.x + threadIdx.x) / kRevLanes; e < n_edges;
-       e += stride) {
+  const XcdSpan xs(n_edges, blockDim.x / kRevLanes, threadIdx.x / kRevLanes);
+  for (long e = xs.first; e < xs.end; e += xs.stride) {
     if (b.uid[e] >= 0) continue;  // an owner edge (or a capped one): uniform over the lanes
     const int rj = b.enbr[e], ri = b.erow[e], back = 26 - b.ecode[e];
     const int q0 = b.off[rj], q1 = b.off[rj + 1];
@@ -884,14 +901,14 @@ __global__ __launch_bounds__(128) void k_mp_gather(MpnnBuffers b, int t, const f
 // dE/dr of one pair (both directions), layer t:
 // sum_c (gM[a] X[b] + gM[b] X[a])_c dW_c/dr.  Thirty-two lanes per pair (four
 // channels each, 16-byte loads), two pairs per wave, pairs taken by a fixed
-// grid up to the device pair count; a fixed butterfly over the 32 lanes.
-// The first layer of the reverse pass stores, the others add.
+// grid up to the device pair count (in XCD pieces); a fixed butterfly over
+// the 32 lanes.  The first layer of the reverse pass stores, the others add.
 __global__ __launch_bounds__(256) void k_mp_dedr(MpnnBuffers b, int t, int first,
                                                  const float* __restrict__ X, long cap) {
   const int l32 = threadIdx.x & 31, c = 4 * l32;
   const long np = held_pairs(b, cap);
-  const long stride = (long)gridDim.x * 8;
-  for (long p = (long)blockIdx.x * 8 + (threadIdx.x >> 5); p < np; p += stride) {
+  const XcdSpan xs(np, 8, threadIdx.x >> 5);
+  for (long p = xs.first; p < xs.end; p += xs.stride) {
     const long ra = (long)b.ua[p] * MP_H + c, rb = (long)b.ub[p] * MP_H + c;
     const float4 ga = *reinterpret_cast<const float4*>(b.gM + ra);
     const float4 gb = *reinterpret_cast<const float4*>(b.gM + rb);
@@ -1143,7 +1160,8 @@ bool mpnn_eval(MpnnCtx& M, const SysDev& S, const ListDev& L, const WinDev& W, i
   MP_HIP(hipGetLastError());
   {
     const unsigned need = nblk(rows * mt * kRevLanes, 256);
-    hipLaunchKernelGGL(k_mp_reverse, dim3(need < kRevBlocks ? need : kRevBlocks), dim3(256), 0, st,
+    const unsigned nb = ((need < kRevBlocks ? need : kRevBlocks) + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_mp_reverse, dim3(nb), dim3(256), 0, st,
                        b, rows, rows * mt, L.status);
   }
   MP_HIP(hipGetLastError());
