@@ -341,14 +341,17 @@ __device__ __forceinline__ float sep(float xj, float sj, float xi, float si) {
 // Lennard-Jones force on i from image n of j; returns whether the pair is
 // inside the cutoff.  The binary32 distance decides unless it falls in the
 // relative band rc2 (1 -+ 32u) around the cutoff, where the exact binary64
-// predicate decides.
+// predicate decides.  The squared distance and the accumulations are fused
+// multiply-adds (one rounding each, so the squared distance stays inside the
+// error the band allows for); the pair energy is added as
+// (eps4/2) s6 (s6 - 1) - eshift/2.
 __device__ __forceinline__ bool lj_pair(const PotDev& P, float4 xi, float4 xj, const float* sj,
                                         const float* si, int code, double L, float& fx, float& fy,
                                         float& fz, float& e) {
   float dx = sep(xj.x, sj[0], xi.x, si[0]);
   float dy = sep(xj.y, sj[1], xi.y, si[1]);
   float dz = sep(xj.z, sj[2], xi.z, si[2]);
-  float r2 = dx * dx + dy * dy + dz * dz;
+  float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
   if (r2 >= P.rc2_lo) {
     if (r2 >= P.rc2_hi) return false;
     if (!inside_exact(xi, xj, code, L, P.rc2_d)) return false;
@@ -357,10 +360,10 @@ __device__ __forceinline__ bool lj_pair(const PotDev& P, float4 xi, float4 xj, c
   float s2 = P.sig2 * inv;
   float s6 = s2 * s2 * s2;
   float fs = P.eps24 * inv * s6 * (2.0f * s6 - 1.0f);
-  fx -= fs * dx;
-  fy -= fs * dy;
-  fz -= fs * dz;
-  e += 0.5f * (P.eps4 * s6 * (s6 - 1.0f) - P.eshift);
+  fx = __builtin_fmaf(-fs, dx, fx);
+  fy = __builtin_fmaf(-fs, dy, fy);
+  fz = __builtin_fmaf(-fs, dz, fz);
+  e = __builtin_fmaf(0.5f * P.eps4 * s6, s6 - 1.0f, e) - 0.5f * P.eshift;
   return true;
 }
 

@@ -111,12 +111,23 @@ def _config(case):
     return W.config(case)
 
 
-@pytest.mark.parametrize("case", ["c1", "box2000", "c2", "c2_bench"])
+@pytest.mark.parametrize("case", ["c1", "box2000", "box_2rl_above", "box_2rl_below", "c2",
+                                  "c2_bench"])
 def test_neighbor_lists_exact(torch, lsd, ora, case):
+    """Lists equal the oracle's pair sets.  A single small system takes the
+    one-launch builder: nearest images when L > 2 r_list (box2000 and a box
+    0.4% above 2 r_list), all 27 images otherwise (c1 and a box 0.4% below
+    2 r_list, where an atom can meet two images of another); c2 takes the
+    cells."""
     _say(f"neighbour lists {case}")
     if case == "box2000":
         w = W.lj_fluid(10, rho=0.8, seed=11, K=4)
         w.positions = W.random_box_positions(w.n_atoms, float(w.box[0]), seed=12)
+    elif case.startswith("box_2rl"):
+        w = W.lj_fluid(6, rho=0.8, seed=13, K=4)
+        L = 2.0 * (w.target["rc"] + w.skin) * (1.004 if case.endswith("above") else 0.996)
+        w.box = np.array([float(W.f32(L))])
+        w.positions = W.random_box_positions(w.n_atoms, float(w.box[0]), seed=14)
     else:
         w = _config(case)
     sysg = lsd.LSDSystem(w, mode="lsd", k_max=1)
