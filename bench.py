@@ -442,6 +442,9 @@ def run_c3(args, lsd, W, torch):
     trace = read_profile_keys(f"mpnn_{args.config}_kernel_trace.txt", MPNN_SOURCES, lsd_skin) or {}
     traffic = read_profile_keys(f"mpnn_{args.config}_traffic.txt", MPNN_SOURCES, lsd_skin) or {}
     prof_us = float(trace["verify_kernel_us_per_window"]) if "verify_kernel_us_per_window" in trace else None
+    # the profiled run verifies its own number of frames per window: its
+    # kernel time is compared per frame
+    prof_frames = float(trace["frames_per_window"]) if "frames_per_window" in trace else None
     value, plain_rate = committed / t_lsd, plain_steps / t_plain
     dt_fs = w.dt
     cpu = None
@@ -491,8 +494,11 @@ def run_c3(args, lsd, W, torch):
                                  "the evaluation kernels and the transport reduction with the "
                                  "gaps between their launches"),
                          profile_avg_us=prof_us,
-                         frac_at_profile_us=(round(flops / (prof_us * 1e-6) / 1e12 / peak, 5)
-                                             if prof_us else None),
+                         profile_frames_per_window=prof_frames,
+                         frac_at_profile_us=(round(flops / frames_per_launch * prof_frames
+                                                   / (prof_us * 1e-6) / 1e12 / peak, 5)
+                                             if prof_us and prof_frames and frames_per_launch
+                                             else None),
                          launch_shape=dict(zip(("filter_blocks", "chain_rows"),
                                                lsd.LSDSystem.NET_SHAPES[shape])),
                          autotune_us={f"{a}x{b}": round(v, 1) for (a, b), v in shape_us.items()},
