@@ -315,5 +315,5 @@ CONFIG_NAMES: List[str] = ["c1", "c2", "c3", "c4", "c5"]
 # the skin admits but commits only a few per window (~1.2 on the
 # 32768-atom fluid, ~1.3-3 on the triatomic liquids), so a short skin
 # pays; a plain window commits every valid frame, so a long one does.
-BENCH_SKINS: Dict[str, tuple] = {"c2": (0.125, 0.6), "c3": (0.15, 0.5), "c4": (0.15, 0.5),
-                                 "c5": (0.15, 0.5)}
+BENCH_SKINS: Dict[str, tuple] = {"c2": (0.125, 0.6), "c3": (0.15, 1.0), "c4": (0.15, 1.0),
+                                 "c5": (0.15, 2.0)}
