@@ -397,8 +397,9 @@ LSD_API lsd_status lsd_get_counters(lsd_system *sys, int64_t *out, lsd_stream st
 LSD_API lsd_status lsd_reset_counters(lsd_system *sys, lsd_stream stream);
 
 /* Kernel timing of the verification launch with HIP events on `stream`.
- * enable = n > 0 starts recording every n-th verification launch (1: every
- * one; a sample keeps the graph of the untimed windows whole), 0 stops,
+ * enable = n > 0 starts recording every n-th verification launch (the n-th,
+ * 2n-th, ... after enabling; 1: every one; a sample keeps the graph of the
+ * untimed windows whole), 0 stops,
  * n < 0 is LSD_ERR_INVALID_ARG.  lsd_get_verify_timing synchronises and
  * returns the summed milliseconds and the count of timed launches since
  * enabling. */

@@ -858,7 +858,7 @@ lsd_status lsd_verify_window(lsd_system* s, lsd_stream stream) {
   if (s->cfg.mode == LSD_MODE_LSD) {
     TimingRing& R = s->ring;
     int slot = -1;
-    const bool timed = s->timing && (s->timing_seq++ % s->timing_every) == 0;
+    const bool timed = s->timing && (s->timing_seq++ % s->timing_every) == s->timing_every - 1;
     if (timed) {
       if (R.used == kTimingRing) LSD_TRY(timing_drain_one(s));
       slot = (R.head + R.used) % kTimingRing;
@@ -917,7 +917,7 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
     s->W.K = K;
     if (n_windows > 0) HIP_TRY(launch_window_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, st));
     for (int w = 0; w < n_windows; ++w) {
-      const bool t = timed && (s->timing_seq++ % s->timing_every) == 0;
+      const bool t = timed && (s->timing_seq++ % s->timing_every) == s->timing_every - 1;
       if (t) {
         LSD_TRY(enqueue_pipelined(s, K, st, s->side_stream, true));
       } else {
@@ -943,7 +943,7 @@ lsd_status lsd_run_windows(lsd_system* s, int32_t n_windows, int32_t K, lsd_stre
   // too); an untimed window is one launch of the whole-window graph
   bool open = false;  // a timed window's post is still to be launched
   for (int w = 0; w < n_windows; ++w) {
-    const bool t = timed && (s->timing_seq++ % s->timing_every) == 0;
+    const bool t = timed && (s->timing_seq++ % s->timing_every) == s->timing_every - 1;
     if (!t) {
       if (open) HIP_TRY(hipGraphLaunch(G.post, st));
       open = false;
