@@ -380,6 +380,8 @@ def run_c3(args, lsd, W, torch):
         shape, shape_us = g.autotune_verify(K, repeats=3)
         g.verify_window()
         g.accept_rollback()
+        if args.draft_tail is not None:
+            g.set_draft_tail(args.draft_tail)
         if args.pipeline:
             g.set_pipeline(args.pipeline)
         # the warmup runs with the timed windows' graphs already in use, so
@@ -547,6 +549,9 @@ def main():
                     help="time every n-th verification launch with HIP events (c1, c2)")
     ap.add_argument("--verify-fw", choices=["auto", "1", "2", "4", "8"], default="auto",
                     help="frames per wave of the verification kernel (auto: autotune)")
+    ap.add_argument("--draft-tail", type=int, default=None,
+                    help="first draft step run in the one-launch draft chain of a short system "
+                         "(0: one launch per step; default: the library's)")
     ap.add_argument("--pipeline", type=int, default=0,
                     help="pipelined LSD windows: verify every group of this many drafted frames on "
                          "a second stream while drafting continues (0: synchronous windows)")
@@ -623,6 +628,8 @@ def main():
         log(f"verification: {chosen_fw} frames per wave (fixed)")
 
     # --- LSD
+    if args.draft_tail is not None:
+        lsds.set_draft_tail(args.draft_tail)
     if args.pipeline:
         lsds.set_pipeline(args.pipeline)
     # the warmup runs with the timed windows' graphs already in use, so the

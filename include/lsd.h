@@ -337,6 +337,17 @@ LSD_API lsd_status lsd_set_pipeline(lsd_system *sys, int32_t group_frames);
  * issues the kernels of every window one by one. */
 LSD_API lsd_status lsd_set_graphs(lsd_system *sys, int32_t enable);
 
+/* Drafting of one short system in fewer launches (Alg. 2, the draft chain
+ * of a window).  With the learned draft and its bfloat16 node pass on a
+ * single system of at most 2048 atoms, in synchronous windows, the draft
+ * steps first_step .. K-1 run in one launch (node and force passes block by
+ * block with a grid barrier after each, ending at the first frame past the
+ * skin) instead of two launches per step; results are bit for bit those of
+ * the per-step launches.  first_step = 0 turns it off; the default is 3.
+ * Other systems ignore the setting.  A grid barrier that times out sets bit
+ * 5 of the status word.  Errors: INVALID_ARG (first_step outside 0..64). */
+LSD_API lsd_status lsd_set_draft_tail(lsd_system *sys, int32_t first_step);
+
 /* Byte offsets into the workspace of the window and list arrays (host). */
 /* Window frames are continuous with the positions the neighbour lists (and
  * their image codes) were built at: those are the wrapped first midpoints of
@@ -375,7 +386,9 @@ LSD_API lsd_status lsd_get_window_layout(const lsd_system *sys, lsd_window_layou
  * list overflow, bit 1 draft list overflow, bit 2 cell overflow, bit 3 more
  * in-cutoff pairs of the message-passing target than its buffers hold (a
  * quarter of rows x list width), bit 4 inconsistent pair lists of that
- * target.  Any set bit means the results since it was set are not valid. */
+ * target, bit 5 a grid barrier of the one-launch draft chain timed out
+ * (lsd_set_draft_tail).  Any set bit means the results since it was set are
+ * not valid. */
 LSD_API lsd_status lsd_get_status(lsd_system *sys, int32_t *flags, lsd_stream stream);
 
 /* Final step count of the run (Alg. 2 stops when that many steps are

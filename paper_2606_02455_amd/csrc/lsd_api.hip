@@ -62,6 +62,7 @@ struct Layout {
   size_t nbr_t, cnt_t, nbr_d, cnt_d, qref, qwrap, rebuild;
   // window
   size_t qmid, p, fd, ft, invalid, nvalid, rej, partial, commit_frame, reflected, coef, counters, status;
+  size_t tail_bar;
   size_t ec = 0, ec_prev = 0, ec_samples = 0;  // error-correction caches (0: off)
   size_t mpnn = 0, mpnn_bytes = 0;
   size_t net_v = 0;  // learned draft: edge coefficients [N][LSD_NET_MAX_BASIS]
@@ -269,6 +270,7 @@ lsd_status plan(const lsd_config* c, Layout* L) {
   L->coef = bump(&off, R * 8);
   L->counters = bump(&off, (size_t)R * LSD_NCOUNT * 8);
   L->status = bump(&off, 4 * 4);
+  L->tail_bar = bump(&off, 4);
   if (c->error_correction && c->mode == LSD_MODE_LSD) {
     L->ec = bump(&off, 3 * n * 4);
     L->ec_samples = bump(&off, (size_t)R * 4);
@@ -373,6 +375,7 @@ struct lsd_system {
   // pipelined windows: frames per verification group (0: synchronous
   // windows), the second stream and the fork/join events
   int pipe_group = 0;
+  int draft_tail = 3;  // first draft step of the one-launch chain (0: one launch per step)
   hipStream_t side_stream = nullptr;
   hipEvent_t pipe_ev[LSD_MAX_K + 1] = {};
   std::map<int, hipGraphExec_t> pipe_graphs;
@@ -526,6 +529,33 @@ lsd_status capture_pipelined(lsd_system* s, int K, hipGraphExec_t* out) {
   return LSD_OK;
 }
 
+// The window's draft steps on `st`: one launch per step (two with the
+// learned draft's node pass), or, where draft_tail_fits and windows are
+// synchronous, steps draft_tail .. K-1 in one launch.
+lsd_status enqueue_drafts(lsd_system* s, int K, hipStream_t st) {
+  const bool plain = s->cfg.mode == LSD_MODE_PLAIN;
+  const int k0 = (!plain && s->draft_tail > 0 && s->pipe_group == 0 &&
+                  draft_tail_fits(s->S, s->Pd))
+                     ? s->draft_tail
+                     : K;
+  for (int k = 0; k < K; ++k) {
+    if (plain && s->has_mpnn) {
+      // plain stepping with the network: its forces on frame k, then the step
+      LSD_TRY(enqueue_plain_mpnn(s, k, st));
+      HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, s->Pt, k, 1, st, 1));
+      continue;
+    }
+    if (k == k0) {
+      HIP_TRY(launch_draft_tail(s->S, s->Lst, s->W, s->T, s->Pd, k0, st));
+      break;
+    }
+    if (!plain && s->Pd.kind == LSD_POT_NET)
+      HIP_TRY(launch_net_nodes(s->S, s->Lst, s->W, s->Pd, k, st));
+    HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st));
+  }
+  return LSD_OK;
+}
+
 // Enqueues the kernels of one window part of lsd_run_windows on `st` (no
 // state checks).  A part begins at the list kernels: the window's start
 // (k_window_start) is fused into the previous window's commit, and the first
@@ -539,16 +569,7 @@ lsd_status enqueue_part(lsd_system* s, int K, int part, hipStream_t st) {
   }
   if (part == PART_FULL || part == PART_PRE) {
     HIP_TRY(launch_build_lists(s->S, s->Lst, s->W, false, st));
-    for (int k = 0; k < K; ++k) {
-      if (plain && s->has_mpnn) {
-        LSD_TRY(enqueue_plain_mpnn(s, k, st));
-        HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, s->Pt, k, 1, st, 1));
-        continue;
-      }
-      if (!plain && s->Pd.kind == LSD_POT_NET)
-        HIP_TRY(launch_net_nodes(s->S, s->Lst, s->W, s->Pd, k, st));
-      HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st));
-    }
+    LSD_TRY(enqueue_drafts(s, K, st));
   }
   if (part == PART_FULL && !plain) LSD_TRY(enqueue_verify(s, K, st));
   if (part == PART_FULL || part == PART_POST) {
@@ -645,6 +666,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.status), 0, 4, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.invalid), 0, R * cfg->k_max, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.nvalid), 0, 1, st);
+  if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.tail_bar), 0, 1, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.rej), LSD_MAX_K, R, st);
   if (e == hipSuccess) e = launch_fill_int(ws<int>(s, L.cnt_t), 0, N, st);
   if (e == hipSuccess) e = launch_zero_i64(ws<long long>(s, L.counters), LSD_NCOUNT * R, st);
@@ -750,6 +772,7 @@ lsd_status lsd_init_system(const lsd_config* cfg, const lsd_buffers* buf, lsd_st
   W.reflected = ws<int>(s, L.reflected);
   W.coef = ws<double>(s, L.coef);
   W.counters = ws<long long>(s, L.counters);
+  W.tail_bar = ws<int>(s, L.tail_bar);
   W.ec = L.ec ? ws<float>(s, L.ec) : nullptr;
   W.ec_prev = L.ec_prev ? ws<float>(s, L.ec_prev) : nullptr;
   W.ec_samples = L.ec ? ws<int>(s, L.ec_samples) : nullptr;
@@ -816,20 +839,9 @@ lsd_status lsd_draft_steps(lsd_system* s, int32_t K, lsd_stream stream) {
   if (K < 1 || K > s->cfg.k_max) return fail(LSD_ERR_INVALID_ARG, "K = %d outside 1..k_max", K);
   hipStream_t st = static_cast<hipStream_t>(stream);
   s->W.K = K;
-  const bool plain = s->cfg.mode == LSD_MODE_PLAIN;
   HIP_TRY(launch_window_start(s->S, s->Lst, s->W, s->buf.q, s->buf.p, st));
   HIP_TRY(launch_build_lists(s->S, s->Lst, s->W, false, st));
-  for (int k = 0; k < K; ++k) {
-    if (plain && s->has_mpnn) {
-      // plain stepping with the network: its forces on frame k, then the step
-      LSD_TRY(enqueue_plain_mpnn(s, k, st));
-      HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, s->Pt, k, 1, st, 1));
-    } else {
-      if (!plain && s->Pd.kind == LSD_POT_NET)
-        HIP_TRY(launch_net_nodes(s->S, s->Lst, s->W, s->Pd, k, st));
-      HIP_TRY(launch_draft(s->S, s->Lst, s->W, s->T, plain ? s->Pt : s->Pd, k, plain ? 1 : 0, st));
-    }
-  }
+  LSD_TRY(enqueue_drafts(s, K, st));
   s->state = ST_DRAFTED;
   return LSD_OK;
 }
@@ -1077,6 +1089,15 @@ lsd_status lsd_set_pipeline(lsd_system* s, int32_t group_frames) {
     return fail(LSD_ERR_UNSUPPORTED, "pipelined windows run through lsd_run_windows with graphs on");
   if (s->pipe_group != group_frames) destroy_graphs(s);
   s->pipe_group = group_frames;
+  return LSD_OK;
+}
+
+lsd_status lsd_set_draft_tail(lsd_system* s, int32_t first_step) {
+  if (!s) return fail(LSD_ERR_INVALID_ARG, "null system");
+  if (first_step < 0 || first_step > LSD_MAX_K)
+    return fail(LSD_ERR_INVALID_ARG, "first_step %d outside 0..%d", first_step, LSD_MAX_K);
+  if (s->draft_tail != first_step) destroy_graphs(s);  // captured windows hold the old choice
+  s->draft_tail = first_step;
   return LSD_OK;
 }
 

@@ -45,6 +45,7 @@
 #define LSD_STATUS_CELL 4
 #define LSD_STATUS_PAIRS 8    // network target: more pairs than its buffers hold
 #define LSD_STATUS_EDGES 16   // network target: the two directions of a pair differ
+#define LSD_STATUS_TAIL 32    // the one-launch draft chain's grid barrier timed out
 
 struct PotDev {
   int kind;
@@ -155,6 +156,8 @@ struct WinDev {
   int* ec_samples;    // [R] committed error samples held (0, 1, 2 = both caches valid)
   long long* counters;  // [R][5]: windows, committed steps, rejections, frames verified,
                         // neighbour-list builds
+  int* tail_bar;      // [1]: arrivals at the grid barriers of the one-launch draft chain,
+                      //      cleared at every window start
   int K;              // frames in the current window
 };
 

@@ -16,6 +16,7 @@
 //   k_commit        reflection of the rejected momentum and map g (Thm. 1)
 #include "lsd_device.h"
 #include "lsd_launch.h"
+#include "net_node.h"
 
 // ---------------------------------------------------------------------------
 __global__ void k_fill_int(int* p, int v, int n) {
@@ -53,7 +54,10 @@ __device__ __forceinline__ void window_start_item(const SysDev& S, const ListDev
     const int rr = i / S.kmax, f = i % S.kmax;
     W.invalid[i] = (S.step[rr] + f + 1 > S.step_limit) ? 1 : 0;
   }
-  if (i == 0) W.nvalid[0] = 0;  // raised by the drafting of each valid frame
+  if (i == 0) {
+    W.nvalid[0] = 0;  // raised by the drafting of each valid frame
+    W.tail_bar[0] = 0;
+  }
   if (i < S.R) W.rej[i] = LSD_MAX_K;  // no rejection known yet
   if (i >= S.n) return;
   const int r = S.R == 1 ? 0 : S.atom_rep[i];
@@ -531,14 +535,16 @@ static_assert(LSD_TILE % LSD_NET_SUB == 0 && LSD_NET_LPA <= 64 &&
 // KIND: the draft's potential kind fixed by the launch (0: read from P), or
 // LSD_KIND_GIVEN for forces already in the window.
 #define LSD_KIND_GIVEN (-1)
-template <int NL, int SUB, int KIND>
-__global__ __launch_bounds__(LSD_TILE / SUB * NL) void k_draft(SysDev S, ListDev Lst, WinDev W,
-                                                               TileDev Tl, PotDev P, int k,
-                                                               int use_target_list) {
+// One block of the draft step (block index blk, thread tid of LSD_TILE / SUB
+// * NL).  STAGE: the block stages the learned draft's pair-type coefficients
+// in s_ct itself (one launch per step); otherwise they are in s_ct already.
+template <int NL, int SUB, int KIND, bool STAGE>
+__device__ __forceinline__ void draft_block(const SysDev& S, const ListDev& Lst, const WinDev& W,
+                                            const TileDev& Tl, const PotDev& P, int k,
+                                            int use_target_list, int blk, int tid, float* s_ct) {
   constexpr bool forces_given = KIND == LSD_KIND_GIVEN;
   constexpr int APB = LSD_TILE / SUB;  // atoms per block
-  __shared__ float s_ct[LSD_NET_MAX_TYPES * LSD_NET_MAX_BASIS];
-  const int tile = blockIdx.x / SUB, part = blockIdx.x % SUB;
+  const int tile = blk / SUB, part = blk % SUB;
   const TileInfo T = tile_info(S.n, S.R, Tl, tile);
   const int r = T.rep;
   int* inv = W.invalid + (size_t)r * S.kmax;
@@ -549,7 +555,7 @@ __global__ __launch_bounds__(LSD_TILE / SUB * NL) void k_draft(SysDev S, ListDev
   const int inv_k = inv[k];
   // the atom's list row and position are requested before the test of the
   // frame, so that their latency overlaps it
-  const int a = part * APB + threadIdx.x / NL, sub = threadIdx.x % NL;
+  const int a = part * APB + tid / NL, sub = tid % NL;
   const bool in = a < T.count;
   const int i = T.start + (in ? a : 0);
   const int width = use_target_list ? Lst.mt : Lst.md;
@@ -563,22 +569,22 @@ __global__ __launch_bounds__(LSD_TILE / SUB * NL) void k_draft(SysDev S, ListDev
   float ctv[CT_PER];
 #pragma unroll
   for (int q = 0; q < CT_PER; ++q) {
-    const int t = threadIdx.x + q * APB * NL;
-    ctv[q] = t < nct ? P.w[net_off_c(P.ns, P.nb) + t] : 0.0f;
+    const int t = tid + q * APB * NL;
+    ctv[q] = (STAGE && t < nct) ? P.w[net_off_c(P.ns, P.nb) + t] : 0.0f;
   }
-  if (after_reject && threadIdx.x == 0 && inv_k == 0) atomicOr(&inv[k], 1);
+  if (after_reject && tid == 0 && inv_k == 0) atomicOr(&inv[k], 1);
   if (after_reject || inv_k) {
     // frames from K_eff on are discarded: no work, and the next frame is
     // invalid as well (one thread per replica records it)
-    if (threadIdx.x == 0 && T.first && part == 0 && k + 1 < W.K) inv[k + 1] = 1;
+    if (tid == 0 && T.first && part == 0 && k + 1 < W.K) inv[k + 1] = 1;
     return;
   }
   // frame k is valid for this replica: the verification covers it
-  if (threadIdx.x == 0 && T.first && part == 0) atomicMax(W.nvalid, k + 1);
-  if (net) {
+  if (tid == 0 && T.first && part == 0) atomicMax(W.nvalid, k + 1);
+  if (STAGE && net) {
 #pragma unroll
     for (int q = 0; q < CT_PER; ++q) {
-      const int t = threadIdx.x + q * APB * NL;
+      const int t = tid + q * APB * NL;
       if (t < nct) s_ct[t] = ctv[q];
     }
     __syncthreads();
@@ -650,6 +656,84 @@ __global__ __launch_bounds__(LSD_TILE / SUB * NL) void k_draft(SysDev S, ListDev
   }
 }
 
+
+template <int NL, int SUB, int KIND>
+__global__ __launch_bounds__(LSD_TILE / SUB * NL) void k_draft(SysDev S, ListDev Lst, WinDev W,
+                                                               TileDev Tl, PotDev P, int k,
+                                                               int use_target_list) {
+  __shared__ float s_ct[LSD_NET_MAX_TYPES * LSD_NET_MAX_BASIS];
+  draft_block<NL, SUB, KIND, true>(S, Lst, W, Tl, P, k, use_target_list, blockIdx.x, threadIdx.x,
+                                   s_ct);
+}
+
+// Draft steps k0 .. K-1 of a window of one small system with the learned
+// draft (bfloat16 node pass) in one launch.  Each step is the node pass and
+// the force pass of the per-step kernels, run block by block over the same
+// blocks (the node pass's 16-atom blocks, then four of the force pass's
+// 64-thread blocks per block, one per wave), with a grid barrier after each
+// pass, so the results are those of the per-step launches bit for bit.  The
+// chain stops at the first frame that is not drafted (past the skin), and
+// flags the later frames as the per-step launches would; launches for those
+// frames are what it saves.  Every block of the grid is resident at once
+// (at most one per compute unit), and every wait at a barrier is bounded: a
+// barrier that times out latches LSD_STATUS_TAIL and ends the chain.
+#define LSD_TAIL_SPIN (1 << 16)
+__device__ __forceinline__ bool tail_barrier(int* bar, int target, int* status, int* s_fail) {
+  // the stores of every wave have completed before the block arrives
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();  // release: this block's writes are visible device-wide
+    atomicAdd(bar, 1);
+    int spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
+           spins < LSD_TAIL_SPIN)
+      ++spins;
+    if (spins >= LSD_TAIL_SPIN) {
+      atomicOr(status, LSD_STATUS_TAIL);
+      *s_fail = 1;
+    }
+    __threadfence();  // acquire: the other blocks' writes are seen from here on
+  }
+  __syncthreads();
+  return *s_fail == 0;
+}
+
+__global__ __launch_bounds__(256) void k_draft_tail_net(SysDev S, ListDev Lst, WinDev W,
+                                                        TileDev Tl, PotDev P, int k0) {
+  __shared__ float s_ct[LSD_NET_MAX_TYPES * LSD_NET_MAX_BASIS];
+  __shared__ int s_fail;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int nct = P.ns * (P.ns + 1) / 2 * P.nb;
+  for (int q = t; q < nct; q += 256) s_ct[q] = P.w[net_off_c(P.ns, P.nb) + q];
+  if (t == 0) s_fail = 0;
+  __syncthreads();
+  const int G = gridDim.x;
+  const int node_blocks = (S.n + NET_IROWS - 1) / NET_IROWS;
+  const int force_blocks = S.n_tiles * LSD_NET_SUB;
+  int target = 0, k = k0;
+  for (; k < W.K; ++k) {
+    // frame k is drafted unless the skin (or a rejection already known)
+    // ended the window before it; every block reads the same flags, at
+    // device scope (the previous pass set them)
+    if (__hip_atomic_load(&W.invalid[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+        W.rej[0] < k)
+      break;
+    for (int b = blockIdx.x; b < node_blocks; b += G)
+      net_nodes_bf16_block<NET_NODE_LPA>(S, Lst, W, P, k, b);
+    target += G;
+    if (!tail_barrier(W.tail_bar, target, Lst.status, &s_fail)) return;
+    for (int b = blockIdx.x * 4 + wave; b < force_blocks; b += G * 4)
+      draft_block<LSD_NET_LPA, LSD_NET_SUB, LSD_POT_NET, false>(S, Lst, W, Tl, P, k, 0, b, lane,
+                                                                s_ct);
+    target += G;
+    if (!tail_barrier(W.tail_bar, target, Lst.status, &s_fail)) return;
+  }
+  // frames after the first one not drafted are flagged, as the per-step
+  // launches flag them one by one
+  if (blockIdx.x == 0 && t == 0)
+    for (int kk = k + 1; kk < W.K; ++kk) W.invalid[kk] = 1;
+}
 
 // Validity of caller-written frames against the frame-0 lists.
 __global__ __launch_bounds__(256) void k_frame_validity(SysDev S, ListDev Lst, WinDev W) {
@@ -1336,6 +1420,20 @@ hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, cons
     hipLaunchKernelGGL((k_draft<LSD_LPA, 1, 0>), tiles, block, 0, st, S, L, W, T, P, k,
                        use_target_list);
   }
+  return hipGetLastError();
+}
+
+// One launch for draft steps k0 .. K-1 (see k_draft_tail_net): a learned
+// draft with the bfloat16 node pass on one system of at most
+// LSD_TAIL_MAX_ATOMS atoms.
+bool draft_tail_fits(const SysDev& S, const PotDev& P) {
+  return S.R == 1 && S.n <= LSD_TAIL_MAX_ATOMS && P.kind == LSD_POT_NET && P.prec == 1;
+}
+
+hipError_t launch_draft_tail(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
+                             const PotDev& P, int k0, hipStream_t st) {
+  const int node_blocks = (S.n + NET_IROWS - 1) / NET_IROWS;
+  hipLaunchKernelGGL(k_draft_tail_net, dim3(node_blocks), dim3(256), 0, st, S, L, W, T, P, k0);
   return hipGetLastError();
 }
 

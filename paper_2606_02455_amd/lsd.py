@@ -90,6 +90,7 @@ EXPORTS = {
     "lsd_get_counters": ([C.c_void_p, C.POINTER(C.c_int64), C.c_void_p], C.c_int),
     "lsd_reset_counters": ([C.c_void_p, C.c_void_p], C.c_int),
     "lsd_set_verify_timing": ([C.c_void_p, C.c_int32], C.c_int),
+    "lsd_set_draft_tail": ([C.c_void_p, C.c_int32], C.c_int),
     "lsd_get_verify_timing": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "lsd_rng_normals": ([C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p],
                         C.c_int),
@@ -588,6 +589,11 @@ class LSDSystem:
 
     def reset_counters(self):
         _check(load().lsd_reset_counters(self.h, _stream(self.torch)), "lsd_reset_counters")
+
+    def set_draft_tail(self, first_step):
+        """Draft steps first_step .. K-1 of a short system's window in one
+        launch (0: one launch per step)."""
+        _check(load().lsd_set_draft_tail(self.h, int(first_step)), "lsd_set_draft_tail")
 
     def set_verify_timing(self, on=True, every=1):
         """Time every `every`-th verification launch with HIP events."""

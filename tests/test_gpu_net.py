@@ -256,6 +256,45 @@ def test_net_draft_graph_replays_equal_eager(torch, lsd):
     b.destroy()
 
 
+@pytest.mark.parametrize("skin", [1.0, 0.05])
+def test_net_draft_tail_equals_per_step_launches(torch, lsd, skin):
+    """Draft steps from first_step on in one launch (node and force passes
+    block by block with grid barriers) give the trajectory and counters of
+    one launch per step: graph and eager windows, three first steps, a skin
+    long enough for whole windows and one that ends windows inside the
+    chain."""
+    _say(f"learned draft: one-launch chain vs per-step launches, skin {skin}")
+    w = W.triatomic_liquid(64, seed=33, K=8)
+    p = torch.tensor(_params(lsd, 4, w2=0.01, c=0.05), dtype=torch.float32, device="cuda")
+    draft = dict(kind="net", rc=RC, weights=p, n_basis=B_, n_model_species=S_, precision="bf16")
+    ref = lsd.LSDSystem(w, mode="lsd", target=_tether(w), draft=draft, skin=skin)
+    ref.set_draft_tail(0)
+    systems = []
+    for first, graphs in ((1, True), (3, True), (5, True), (3, False)):
+        g = lsd.LSDSystem(w, mode="lsd", target=_tether(w), draft=draft, skin=skin)
+        g.set_draft_tail(first)
+        g.set_graphs(graphs)
+        systems.append(g)
+    for rep in range(3):
+        ref.run_windows(4, 8)
+        sr = ref.state()
+        for g in systems:
+            g.run_windows(4, 8)
+            sg = g.state()
+            for k in ("q", "p", "img", "step"):
+                assert np.array_equal(sr[k], sg[k]), (rep, k)
+            assert np.array_equal(ref.counters(), g.counters()), rep
+            assert g.status() == 0
+    cn = ref.counters()[0]
+    frames_per_window = cn[3] / cn[0]
+    if skin == 1.0:
+        assert frames_per_window > 5, frames_per_window  # the chain runs valid steps
+    else:
+        assert frames_per_window < 8, frames_per_window  # windows end inside the chain
+    for g in [ref] + systems:
+        g.destroy()
+
+
 def _training_window(torch, lsd, w, K, net_p):
     """A system whose window holds K caller frames (small perturbations of
     the wrapped start) with forces y of a teacher net, written as the
