@@ -550,7 +550,7 @@ def main():
     ap.add_argument("--verify-fw", choices=["auto", "1", "2", "4", "8"], default="auto",
                     help="frames per wave of the verification kernel (auto: autotune)")
     ap.add_argument("--draft-tail", type=int, default=None,
-                    help="first draft step run in the one-launch draft chain of a short system "
+                    help="LSD: first draft step run in the one-launch draft chain of one system "
                          "(0: one launch per step; default: the library's)")
     ap.add_argument("--pipeline", type=int, default=0,
                     help="pipelined LSD windows: verify every group of this many drafted frames on "

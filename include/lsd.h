@@ -337,15 +337,18 @@ LSD_API lsd_status lsd_set_pipeline(lsd_system *sys, int32_t group_frames);
  * issues the kernels of every window one by one. */
 LSD_API lsd_status lsd_set_graphs(lsd_system *sys, int32_t enable);
 
-/* Drafting of one short system in fewer launches (Alg. 2, the draft chain
- * of a window).  With the learned draft and its bfloat16 node pass on a
- * single system of at most 2048 atoms, in synchronous windows, the draft
- * steps first_step .. K-1 run in one launch (node and force passes block by
- * block with a grid barrier after each, ending at the first frame past the
- * skin) instead of two launches per step; results are bit for bit those of
- * the per-step launches.  first_step = 0 turns it off; the default is 3.
- * Other systems ignore the setting.  A grid barrier that times out sets bit
- * 5 of the status word.  Errors: INVALID_ARG (first_step outside 0..64). */
+/* Drafting of one system in fewer launches (Alg. 2, the draft chain of a
+ * window).  In synchronous windows of a single system with a pair draft
+ * (Lennard-Jones or force-matched pairs), or with the learned draft and its
+ * bfloat16 node pass up to 2048 atoms, the draft steps first_step .. K-1 run
+ * in one launch (the per-step kernels' blocks in turn, a bounded grid
+ * barrier after each pass, ending at the first frame past the skin) instead
+ * of one or two launches per step; results are bit for bit those of the
+ * per-step launches.  Plain stepping with a pair target takes it for a
+ * system of one tile (64 atoms), where no grid barrier is needed.
+ * first_step = 0 turns it off; the default is 3.  Other systems ignore the
+ * setting.  A grid barrier that times out sets bit 5 of the status word.
+ * Errors: INVALID_ARG (first_step outside 0..64). */
 LSD_API lsd_status lsd_set_draft_tail(lsd_system *sys, int32_t first_step);
 
 /* Byte offsets into the workspace of the window and list arrays (host). */

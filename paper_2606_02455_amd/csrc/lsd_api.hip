@@ -531,13 +531,14 @@ lsd_status capture_pipelined(lsd_system* s, int K, hipGraphExec_t* out) {
 
 // The window's draft steps on `st`: one launch per step (two with the
 // learned draft's node pass), or, where draft_tail_fits and windows are
-// synchronous, steps draft_tail .. K-1 in one launch.
+// synchronous, steps draft_tail .. K-1 in one launch.  Plain stepping (every
+// step drafted) takes the one-launch chain only where it needs no grid
+// barrier (one block).
 lsd_status enqueue_drafts(lsd_system* s, int K, hipStream_t st) {
   const bool plain = s->cfg.mode == LSD_MODE_PLAIN;
-  const int k0 = (!plain && s->draft_tail > 0 && s->pipe_group == 0 &&
-                  draft_tail_fits(s->S, s->Pd))
-                     ? s->draft_tail
-                     : K;
+  const bool tail = s->draft_tail > 0 && s->pipe_group == 0 && !(plain && s->has_mpnn) &&
+                    draft_tail_fits(s->S, plain ? s->Pt : s->Pd) && (!plain || s->S.n_tiles == 1);
+  const int k0 = tail ? s->draft_tail : K;
   for (int k = 0; k < K; ++k) {
     if (plain && s->has_mpnn) {
       // plain stepping with the network: its forces on frame k, then the step
@@ -546,7 +547,8 @@ lsd_status enqueue_drafts(lsd_system* s, int K, hipStream_t st) {
       continue;
     }
     if (k == k0) {
-      HIP_TRY(launch_draft_tail(s->S, s->Lst, s->W, s->T, s->Pd, k0, st));
+      HIP_TRY(launch_draft_tail(s->S, s->Lst, s->W, s->T, plain ? s->Pt : s->Pd, k0, plain ? 1 : 0,
+                                st));
       break;
     }
     if (!plain && s->Pd.kind == LSD_POT_NET)

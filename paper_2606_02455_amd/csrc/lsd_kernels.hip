@@ -682,6 +682,7 @@ __device__ __forceinline__ bool tail_barrier(int* bar, int target, int* status, 
   // the stores of every wave have completed before the block arrives
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  if (gridDim.x == 1) return true;  // one block: its waves share the compute unit's caches
   if (threadIdx.x == 0) {
     __threadfence();  // release: this block's writes are visible device-wide
     atomicAdd(bar, 1);
@@ -732,6 +733,35 @@ __global__ __launch_bounds__(256) void k_draft_tail_net(SysDev S, ListDev Lst, W
   // frames after the first one not drafted are flagged, as the per-step
   // launches flag them one by one
   if (blockIdx.x == 0 && t == 0)
+    for (int kk = k + 1; kk < W.K; ++kk) W.invalid[kk] = 1;
+}
+
+// The same for a pair draft (Lennard-Jones or force-matched pair forces), or
+// for plain stepping with such a target (use_target_list), on one system:
+// steps k0 .. K-1 in one launch of at most LSD_TAIL_PAIR_BLOCKS blocks, each
+// running the per-step kernel's 64-atom blocks in turn, one bounded grid
+// barrier per step.
+#define LSD_TAIL_PAIR_BLOCKS 128
+template <int KIND>
+__global__ __launch_bounds__(LSD_VTHREADS) void k_draft_tail_pair(SysDev S, ListDev Lst, WinDev W,
+                                                                  TileDev Tl, PotDev P, int k0,
+                                                                  int use_target_list) {
+  __shared__ int s_fail;
+  if (threadIdx.x == 0) s_fail = 0;
+  __syncthreads();
+  const int G = gridDim.x;
+  int target = 0, k = k0;
+  for (; k < W.K; ++k) {
+    if (__hip_atomic_load(&W.invalid[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+        W.rej[0] < k)
+      break;
+    for (int b = blockIdx.x; b < S.n_tiles; b += G)
+      draft_block<LSD_LPA, 1, KIND, false>(S, Lst, W, Tl, P, k, use_target_list, b, threadIdx.x,
+                                           nullptr);
+    target += G;
+    if (!tail_barrier(W.tail_bar, target, Lst.status, &s_fail)) return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
     for (int kk = k + 1; kk < W.K; ++kk) W.invalid[kk] = 1;
 }
 
@@ -1423,17 +1453,29 @@ hipError_t launch_draft(const SysDev& S, const ListDev& L, const WinDev& W, cons
   return hipGetLastError();
 }
 
-// One launch for draft steps k0 .. K-1 (see k_draft_tail_net): a learned
-// draft with the bfloat16 node pass on one system of at most
-// LSD_TAIL_MAX_ATOMS atoms.
+// One launch for draft steps k0 .. K-1 (k_draft_tail_net, k_draft_tail_pair)
+// on one system: the learned draft with the bfloat16 node pass up to
+// LSD_TAIL_MAX_ATOMS atoms, or a pair draft.
 bool draft_tail_fits(const SysDev& S, const PotDev& P) {
-  return S.R == 1 && S.n <= LSD_TAIL_MAX_ATOMS && P.kind == LSD_POT_NET && P.prec == 1;
+  if (S.R != 1) return false;
+  if (P.kind == LSD_POT_NET) return S.n <= LSD_TAIL_MAX_ATOMS && P.prec == 1;
+  return P.kind == LSD_POT_LJ || P.kind == LSD_POT_PAIR;
 }
 
 hipError_t launch_draft_tail(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
-                             const PotDev& P, int k0, hipStream_t st) {
-  const int node_blocks = (S.n + NET_IROWS - 1) / NET_IROWS;
-  hipLaunchKernelGGL(k_draft_tail_net, dim3(node_blocks), dim3(256), 0, st, S, L, W, T, P, k0);
+                             const PotDev& P, int k0, int use_target_list, hipStream_t st) {
+  if (P.kind == LSD_POT_NET) {
+    const int node_blocks = (S.n + NET_IROWS - 1) / NET_IROWS;
+    hipLaunchKernelGGL(k_draft_tail_net, dim3(node_blocks), dim3(256), 0, st, S, L, W, T, P, k0);
+  } else {
+    const dim3 grid(S.n_tiles < LSD_TAIL_PAIR_BLOCKS ? S.n_tiles : LSD_TAIL_PAIR_BLOCKS);
+    if (P.kind == LSD_POT_LJ)
+      hipLaunchKernelGGL(k_draft_tail_pair<LSD_POT_LJ>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W, T,
+                         P, k0, use_target_list);
+    else
+      hipLaunchKernelGGL(k_draft_tail_pair<LSD_POT_PAIR>, grid, dim3(LSD_VTHREADS), 0, st, S, L, W,
+                         T, P, k0, use_target_list);
+  }
   return hipGetLastError();
 }
 

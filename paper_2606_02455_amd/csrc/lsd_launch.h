@@ -34,12 +34,12 @@ hipError_t launch_decide_commit_start(const SysDev& S, const ListDev& L, const W
                                       const TileDev& T, const OutDev& O, float* q, float* p,
                                       int* img, int plain, hipStream_t st);
 // draft steps k0 .. K-1 in one launch, for the systems draft_tail_fits
-// admits (one system of at most LSD_TAIL_MAX_ATOMS atoms, learned draft with
-// the bfloat16 node pass)
+// admits (one system: the learned draft with the bfloat16 node pass up to
+// LSD_TAIL_MAX_ATOMS atoms, or a pair draft)
 #define LSD_TAIL_MAX_ATOMS 2048
 bool draft_tail_fits(const SysDev& S, const PotDev& P);
 hipError_t launch_draft_tail(const SysDev& S, const ListDev& L, const WinDev& W, const TileDev& T,
-                             const PotDev& P, int k0, hipStream_t st);
+                             const PotDev& P, int k0, int use_target_list, hipStream_t st);
 // commit of the window and start of the next one in one launch
 hipError_t launch_commit_start(const SysDev& S, const ListDev& L, const WinDev& W, float* q,
                                float* p, int* img, int plain, hipStream_t st);

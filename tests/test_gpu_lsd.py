@@ -146,6 +146,45 @@ def test_neighbor_lists_exact(torch, lsd, ora, case):
     sysg.destroy()
 
 
+@pytest.mark.parametrize("case,mode", [("c1", "lsd"), ("c1", "plain"), ("lj4096", "lsd"),
+                                       ("c2_bench", "lsd")])
+def test_pair_draft_tail_equals_per_step_launches(torch, lsd, case, mode):
+    """Draft steps from first_step on in one launch (the per-step kernel's
+    blocks in turn, one bounded grid barrier per step) give the trajectory
+    and counters of one launch per step: one tile (c1, LSD and plain
+    stepping), 64 tiles, 512 tiles over 128 blocks (c2 at the benchmark's
+    skin); graph and eager windows."""
+    _say(f"pair draft: one-launch chain vs per-step launches, {case} {mode}")
+    w = W.lj_fluid(16, rho=0.8, seed=21, K=16) if case == "lj4096" else _config(case)
+    K = w.K
+    kw = dict(error_correction=2) if mode == "lsd" else {}
+    ref = lsd.LSDSystem(w, mode=mode, **kw)
+    ref.set_draft_tail(0)
+    systems = []
+    for first, graphs in ((1, True), (3, True), (3, False)):
+        g = lsd.LSDSystem(w, mode=mode, **kw)
+        g.set_draft_tail(first)
+        g.set_graphs(graphs)
+        systems.append(g)
+    n = 2 if case == "c2_bench" else 4
+    for rep in range(3):
+        ref.run_windows(n, K)
+        sr = ref.state()
+        for g in systems:
+            g.run_windows(n, K)
+            sg = g.state()
+            for k in ("q", "p", "img", "step"):
+                assert np.array_equal(sr[k], sg[k]), (rep, k)
+            assert np.array_equal(ref.counters(), g.counters()), rep
+            assert g.status() == 0
+    cn = ref.counters()[0]
+    # more frames verified (LSD) or steps committed (plain) than windows: the
+    # chain runs drafted steps
+    assert (cn[3] if mode == "lsd" else cn[1]) > cn[0], cn
+    for g in [ref] + systems:
+        g.destroy()
+
+
 def _perturbed_frames(w, K, seed, amp=0.02):
     rng = np.random.default_rng(seed)
     L = float(w.box[0])
