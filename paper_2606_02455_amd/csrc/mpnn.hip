@@ -884,12 +884,30 @@ __global__ __launch_bounds__(128) void k_mp_gather(MpnnBuffers b, int t, const f
   const int e1 = b.off[row + 1];
   float acc = 0.f;
   int e = b.off[row];
+  // the pair and neighbour indices of the next group of edges are requested
+  // while this group's filter and feature values load
+  int un[kGatherDepth], jn[kGatherDepth];
+  if (e + kGatherDepth <= e1) {
+#pragma unroll
+    for (int q = 0; q < kGatherDepth; ++q) {
+      un[q] = b.uid[e + q];
+      jn[q] = b.enbr[e + q];
+    }
+  }
   for (; e + kGatherDepth <= e1; e += kGatherDepth) {
     float wv[kGatherDepth], vv[kGatherDepth];
 #pragma unroll
     for (int q = 0; q < kGatherDepth; ++q) {
-      wv[q] = pair_filter(b, b.uid[e + q], t, c);
-      vv[q] = V[(long)b.enbr[e + q] * MP_H + c];
+      wv[q] = pair_filter(b, un[q], t, c);
+      vv[q] = V[(long)jn[q] * MP_H + c];
+    }
+    const int en = e + kGatherDepth;
+    if (en + kGatherDepth <= e1) {
+#pragma unroll
+      for (int q = 0; q < kGatherDepth; ++q) {
+        un[q] = b.uid[en + q];
+        jn[q] = b.enbr[en + q];
+      }
     }
 #pragma unroll
     for (int q = 0; q < kGatherDepth; ++q) acc = fmaf(wv[q], vv[q], acc);
@@ -908,13 +926,24 @@ __global__ __launch_bounds__(256) void k_mp_dedr(MpnnBuffers b, int t, int first
   const int l32 = threadIdx.x & 31, c = 4 * l32;
   const long np = held_pairs(b, cap);
   const XcdSpan xs(np, 8, threadIdx.x >> 5);
+  // the next pair's row indices are requested while this pair's rows load
+  int ua = 0, ub = 0;
+  if (xs.first < xs.end) {
+    ua = b.ua[xs.first];
+    ub = b.ub[xs.first];
+  }
   for (long p = xs.first; p < xs.end; p += xs.stride) {
-    const long ra = (long)b.ua[p] * MP_H + c, rb = (long)b.ub[p] * MP_H + c;
+    const long ra = (long)ua * MP_H + c, rb = (long)ub * MP_H + c;
     const float4 ga = *reinterpret_cast<const float4*>(b.gM + ra);
     const float4 gb = *reinterpret_cast<const float4*>(b.gM + rb);
     const float4 xa = *reinterpret_cast<const float4*>(X + ra);
     const float4 xb = *reinterpret_cast<const float4*>(X + rb);
     const float4 v = *reinterpret_cast<const float4*>(b.Vf + p * MP_HT + t * MP_H + c);
+    const long pn = p + xs.stride;
+    if (pn < xs.end) {
+      ua = b.ua[pn];
+      ub = b.ub[pn];
+    }
     float acc = (ga.x * xb.x + gb.x * xa.x) * v.x;
     acc = fmaf(ga.y * xb.y + gb.y * xa.y, v.y, acc);
     acc = fmaf(ga.z * xb.z + gb.z * xa.z, v.z, acc);
