@@ -202,6 +202,48 @@ __global__ __launch_bounds__(64) void k_cell_sort(ListDev Lst) {
   }
 }
 
+// One list candidate (j at image code, position xj, image shift sh) of
+// atom i at xi: in the target list (ht) and in the draft list (hd).  The
+// binary32 separation has relative error <= 4u per component, as in the
+// force kernels; the exact binary64 predicate decides inside the band
+// rl2 (1 -+ 32u) around either list radius.
+__device__ __forceinline__ void nl_pair_test(const ListDev& Lst, double L, float4 xi, int i,
+                                             float4 xj, int j, int code, const float* sh,
+                                             bool& ht, bool& hd) {
+  ht = false;
+  hd = false;
+  if (j == i && code == 13) return;
+  const float fdx = sep(xj.x, sh[0], xi.x, sh[3]);
+  const float fdy = sep(xj.y, sh[1], xi.y, sh[4]);
+  const float fdz = sep(xj.z, sh[2], xi.z, sh[5]);
+  const float r2 = fdx * fdx + fdy * fdy + fdz * fdz;
+  const bool bt = r2 >= Lst.rl2_t_lo && r2 < Lst.rl2_t_hi;
+  const bool bd = r2 >= Lst.rl2_d_lo && r2 < Lst.rl2_d_hi;
+  ht = r2 < Lst.rl2_t_lo;
+  hd = r2 < Lst.rl2_d_lo;
+  if (bt || bd) {
+    double dx = ((double)xj.x - (double)xi.x) + (double)code_nx(code) * L;
+    double dy = ((double)xj.y - (double)xi.y) + (double)code_ny(code) * L;
+    double dz = ((double)xj.z - (double)xi.z) + (double)code_nz(code) * L;
+    double d2 = dx * dx + dy * dy + dz * dz;
+    if (bt) ht = d2 < Lst.rl2_t;
+    if (bd) hd = d2 < Lst.rl2_d;
+  }
+}
+
+// Appends the wave's hits in lane (candidate) order to a list row holding n
+// entries so far (ballot compaction; entries past the row's width m are
+// counted, not written).
+__device__ __forceinline__ void nl_append(bool hit, uint32_t ent, unsigned long long below, int& n,
+                                          uint32_t* row, int m) {
+  const unsigned long long b = __ballot(hit);
+  if (hit) {
+    const int pos = n + __popcll(b & below);
+    if (pos < m) row[pos] = ent;
+  }
+  n += __popcll(b);
+}
+
 // Verlet lists at the frame-0 midpoints: every (j, image) with
 // |x_j + n L - x_i| < r_list.  One block per (cell, group of NL_IPB atoms of
 // that cell): the candidates of the 27 neighbouring cells (ascending atom
@@ -210,8 +252,10 @@ __global__ __launch_bounds__(64) void k_cell_sort(ListDev Lst) {
 // predicate and appends the hits in candidate order by ballot compaction, so
 // list rows are written contiguously (atom-major layout [i][m]).
 #define NL_IPB 32
-#define NL_CH 512
-__global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev W) {
+#define NL_CH 1024
+#define NL_NT 256
+__global__ __launch_bounds__(NL_NT) void k_nl_build(SysDev S, ListDev Lst, WinDev W) {
+  constexpr int NT = NL_NT, NW = NT / 64, IPB = NL_IPB;
   __shared__ float4 s_x[NL_CH];
   __shared__ uint32_t s_e[NL_CH];
   __shared__ int s_pre[28];
@@ -226,11 +270,21 @@ __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev 
   const int coff = Lst.rep_cell_off[r];
   const int lo = Lst.cell_start[c], hi = Lst.cell_start[c + 1];
   const int occ = hi - lo;
-  const int ib = blockIdx.y * NL_IPB;
+  const int ib = blockIdx.y * IPB;
   if (blockIdx.y == 0 && t == 0 && occ > Lst.cell_cap) atomicOr(Lst.status, LSD_STATUS_CELL);
   if (ib >= occ) return;
-  const int ie = min(occ, ib + NL_IPB);
+  const int ie = min(occ, ib + IPB);
+  const int nib = ie - ib;
   const double L = S.box[r];
+  // the block's i-atoms and their positions, requested together with the
+  // neighbour cells' offsets so that no wave waits on them per atom
+  __shared__ int s_i[IPB];
+  __shared__ float4 s_xi[IPB];
+  for (int u = t; u < nib; u += NT) {
+    const int i = Lst.cell_atoms[lo + ib + u];
+    s_i[u] = i;
+    s_xi[u] = W.qmid[i];
+  }
   if (t < 27) {
     const int cl = c - coff;
     const int cx = cl % nc, cy = (cl / nc) % nc, cz = cl / (nc * nc);
@@ -253,87 +307,90 @@ __global__ __launch_bounds__(256) void k_nl_build(SysDev S, ListDev Lst, WinDev 
   __syncthreads();
   const int total = s_pre[27];
   // list lengths of the block's i-atoms so far (atom u of the block is
-  // handled by wave u % 4 in every chunk)
-  __shared__ int s_nt[NL_IPB], s_nd[NL_IPB];
-  const int nib = ie - ib;
-  if (t < NL_IPB) {
-    s_nt[t] = 0;
-    s_nd[t] = 0;
+  // handled by wave u % NW in every chunk)
+  __shared__ int s_nt[IPB], s_nd[IPB];
+  for (int u = t; u < nib; u += NT) {
+    s_nt[u] = 0;
+    s_nd[u] = 0;
   }
   for (int cb = 0; cb < total; cb += NL_CH) {
     const int cn = min(NL_CH, total - cb);
     __syncthreads();
-    for (int k = t; k < cn; k += 256) {
-      const int idx = cb + k;
-      // neighbour cell of candidate idx: s_pre[q] <= idx < s_pre[q + 1]
-      int q = 0;
+    // a thread's candidates: all their atom indices are requested before
+    // any position, so the staging costs two dependent loads, not two per
+    // candidate
+    int jv[NL_CH / NT], cv[NL_CH / NT];
 #pragma unroll
-      for (int step = 16; step > 0; step >>= 1)
-        if (q + step < 27 && s_pre[q + step] <= idx) q += step;
-      const int j = Lst.cell_atoms[s_cstart[q] + (idx - s_pre[q])];
-      s_x[k] = W.qmid[j];
-      s_e[k] = ((uint32_t)j << 5) | (uint32_t)s_code[q];
+    for (int a = 0; a < NL_CH / NT; ++a) {
+      const int k = t + NT * a;
+      jv[a] = 0;
+      cv[a] = 0;
+      if (k < cn) {
+        const int idx = cb + k;
+        // neighbour cell of candidate idx: s_pre[q] <= idx < s_pre[q + 1]
+        int q = 0;
+#pragma unroll
+        for (int step = 16; step > 0; step >>= 1)
+          if (q + step < 27 && s_pre[q + step] <= idx) q += step;
+        jv[a] = Lst.cell_atoms[s_cstart[q] + (idx - s_pre[q])];
+        cv[a] = s_code[q];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < NL_CH / NT; ++a) {
+      const int k = t + NT * a;
+      if (k < cn) {
+        s_x[k] = W.qmid[jv[a]];
+        s_e[k] = ((uint32_t)jv[a] << 5) | (uint32_t)cv[a];
+      }
     }
     __syncthreads();
-    for (int u = wave; u < nib; u += 4) {  // uniform per wave
-      const int i = Lst.cell_atoms[lo + ib + u];
-      const float4 xi = W.qmid[i];
-      int nt = s_nt[u], nd = s_nd[u];
-      uint32_t* rowt = Lst.nbr_t + (size_t)i * Lst.mt;
-      uint32_t* rowd = Lst.nbr_d + (size_t)i * Lst.md;
+    // each wave takes its atoms two at a time (u and u + NW), so every
+    // staged candidate it reads serves both
+    for (int u0 = wave; u0 < nib; u0 += 2 * NW) {
+      const int u1 = u0 + NW;
+      const bool two = u1 < nib;  // uniform per wave
+      const int i0 = s_i[u0], i1 = two ? s_i[u1] : -1;
+      const float4 x0 = s_xi[u0], x1 = two ? s_xi[u1] : x0;
+      int nt0 = s_nt[u0], nd0 = s_nd[u0];
+      int nt1 = two ? s_nt[u1] : 0, nd1 = two ? s_nd[u1] : 0;
+      uint32_t* rowt0 = Lst.nbr_t + (size_t)i0 * Lst.mt;
+      uint32_t* rowd0 = Lst.nbr_d + (size_t)i0 * Lst.md;
+      uint32_t* rowt1 = Lst.nbr_t + (size_t)(two ? i1 : i0) * Lst.mt;
+      uint32_t* rowd1 = Lst.nbr_d + (size_t)(two ? i1 : i0) * Lst.md;
       for (int k0 = 0; k0 < cn; k0 += 64) {
         const int k = k0 + lane;
-        bool ht = false, hd = false;
+        bool ht0 = false, hd0 = false, ht1 = false, hd1 = false;
         uint32_t ent = 0;
         if (k < cn) {
           ent = s_e[k];
           const int j = (int)(ent >> 5), code = (int)(ent & 31u);
-          if (!(j == i && code == 13)) {
-            // binary32 separation (relative error <= 4u per component, as in
-            // the force kernels); the exact binary64 predicate decides inside
-            // the band rl2 (1 -+ 32u) around either list radius
-            const float4 xj = s_x[k];
-            const float* sh = s_sh[code];
-            const float fdx = sep(xj.x, sh[0], xi.x, sh[3]);
-            const float fdy = sep(xj.y, sh[1], xi.y, sh[4]);
-            const float fdz = sep(xj.z, sh[2], xi.z, sh[5]);
-            const float r2 = fdx * fdx + fdy * fdy + fdz * fdz;
-            const bool bt = r2 >= Lst.rl2_t_lo && r2 < Lst.rl2_t_hi;
-            const bool bd = r2 >= Lst.rl2_d_lo && r2 < Lst.rl2_d_hi;
-            ht = r2 < Lst.rl2_t_lo;
-            hd = r2 < Lst.rl2_d_lo;
-            if (bt || bd) {
-              double dx = ((double)xj.x - (double)xi.x) + (double)code_nx(code) * L;
-              double dy = ((double)xj.y - (double)xi.y) + (double)code_ny(code) * L;
-              double dz = ((double)xj.z - (double)xi.z) + (double)code_nz(code) * L;
-              double d2 = dx * dx + dy * dy + dz * dz;
-              if (bt) ht = d2 < Lst.rl2_t;
-              if (bd) hd = d2 < Lst.rl2_d;
-            }
-          }
+          const float4 xj = s_x[k];
+          const float* sh = s_sh[code];
+          nl_pair_test(Lst, L, x0, i0, xj, j, code, sh, ht0, hd0);
+          if (two) nl_pair_test(Lst, L, x1, i1, xj, j, code, sh, ht1, hd1);
         }
-        const unsigned long long bt = __ballot(ht), bd = __ballot(hd);
         const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        if (ht) {
-          const int pos = nt + __popcll(bt & below);
-          if (pos < Lst.mt) rowt[pos] = ent;
+        nl_append(ht0, ent, below, nt0, rowt0, Lst.mt);
+        nl_append(hd0, ent, below, nd0, rowd0, Lst.md);
+        if (two) {
+          nl_append(ht1, ent, below, nt1, rowt1, Lst.mt);
+          nl_append(hd1, ent, below, nd1, rowd1, Lst.md);
         }
-        if (hd) {
-          const int pos = nd + __popcll(bd & below);
-          if (pos < Lst.md) rowd[pos] = ent;
-        }
-        nt += __popcll(bt);
-        nd += __popcll(bd);
       }
       if (lane == 0) {
-        s_nt[u] = nt;
-        s_nd[u] = nd;
+        s_nt[u0] = nt0;
+        s_nd[u0] = nd0;
+        if (two) {
+          s_nt[u1] = nt1;
+          s_nd[u1] = nd1;
+        }
       }
     }
   }
   __syncthreads();
-  for (int u = t; u < nib; u += 256) {
-    const int i = Lst.cell_atoms[lo + ib + u];
+  for (int u = t; u < nib; u += NT) {
+    const int i = s_i[u];
     int a = s_nt[u], b = s_nd[u];
     if (a > Lst.mt) { atomicOr(Lst.status, LSD_STATUS_NBR_TARGET); a = Lst.mt; }
     if (b > Lst.md) { atomicOr(Lst.status, LSD_STATUS_NBR_DRAFT); b = Lst.md; }
@@ -1422,7 +1479,7 @@ hipError_t launch_build_lists(const SysDev& S, const ListDev& L, const WinDev& W
   hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(S.n, 256)), dim3(256), 0, st, S.n, S.atom_rep, L);
   hipLaunchKernelGGL(k_cell_sort, dim3(L.n_cells), dim3(64), 0, st, L);
   dim3 grid(L.n_cells, (L.cell_cap + NL_IPB - 1) / NL_IPB);
-  hipLaunchKernelGGL(k_nl_build, grid, dim3(256), 0, st, S, L, W);
+  hipLaunchKernelGGL(k_nl_build, grid, dim3(NL_NT), 0, st, S, L, W);
   return hipGetLastError();
 }
 

@@ -112,13 +112,15 @@ def _config(case):
 
 
 @pytest.mark.parametrize("case", ["c1", "box2000", "box_2rl_above", "box_2rl_below", "c2",
-                                  "c2_bench"])
+                                  "c2_bench", "c2_skin05", "c2_skin1"])
 def test_neighbor_lists_exact(torch, lsd, ora, case):
     """Lists equal the oracle's pair sets.  A single small system takes the
     one-launch builder: nearest images when L > 2 r_list (box2000 and a box
     0.4% above 2 r_list), all 27 images otherwise (c1 and a box 0.4% below
     2 r_list, where an atom can meet two images of another); c2 takes the
-    cells."""
+    cells (c2 at its own skin and at 0.125, 0.5 and 1.0; at 1.0, about 45
+    atoms per cell, a cell's 27 neighbour cells hold more candidates than
+    one staging pass takes and its atoms span more than one block)."""
     _say(f"neighbour lists {case}")
     if case == "box2000":
         w = W.lj_fluid(10, rho=0.8, seed=11, K=4)
@@ -128,6 +130,9 @@ def test_neighbor_lists_exact(torch, lsd, ora, case):
         L = 2.0 * (w.target["rc"] + w.skin) * (1.004 if case.endswith("above") else 0.996)
         w.box = np.array([float(W.f32(L))])
         w.positions = W.random_box_positions(w.n_atoms, float(w.box[0]), seed=14)
+    elif case in ("c2_skin05", "c2_skin1"):
+        w = W.config("c2")
+        w.skin = 0.5 if case == "c2_skin05" else 1.0
     else:
         w = _config(case)
     sysg = lsd.LSDSystem(w, mode="lsd", k_max=1)
